@@ -1,0 +1,175 @@
+/*
+ * tfi.h -- C ABI of the MI355X tree field integrator (libtfi.so).
+ *
+ * Problem (Section 1, equation "integration"; Section 2, equation
+ * "stad-target"): for every vertex v of a forest with positive integer
+ * edge lengths,
+ *
+ *     out[v, c] = sum_{w in same tree} f(dist(v, w)) * F[w, c],
+ *
+ * where dist is the sum of edge lengths on the v-w path and f is a table on
+ * the integer lattice (f : Z>=0 -> R; real lengths are quantised to lattice
+ * units first, appendix "Distance quantization"). The self term f(0) F[v]
+ * is included; vertices of different trees do not interact.
+ *
+ * Method (Section 2 and its appendix algorithms): the tree is decomposed
+ * recursively around backbones -- a diameter path or a single centroid,
+ * chosen per call by the adaptive score (equation "stad-score"). Each
+ * call's cross-component interactions are the interaction table
+ * G_q[s] (equation "sumofFFTterms") minus the per-component corrections
+ * E_alpha (equation "stad-E", lemma "stad-cross"), with G evaluated as one
+ * 2-D convolution of the depth-reversed aggregate table with the kernel
+ * K[a, b] = f(H + a + |b|) (equation "stad-2d-convolution", lemma
+ * "stad-2d-fft"). Backbone coordinates and depths are weighted lattice
+ * distances. Small subtrees are evaluated densely.
+ *
+ * Conventions for every entry point:
+ *  - return 0 on success, a negative tfi_status otherwise; the message of
+ *    the last failure on the calling thread is tfi_last_error();
+ *  - no entry point throws or aborts; invalid arguments are reported;
+ *  - "device" pointers are HIP device allocations of the handle's device;
+ *    "host" pointers are ordinary CPU memory;
+ *  - device work is enqueued on `stream` (0 = the null stream) and is
+ *    asynchronous with respect to the host; a handle must not be used on
+ *    two streams at the same time (it owns scratch arenas);
+ *  - element types follow `dtype` (TFI_F32 = float, TFI_F64 = double);
+ *  - matrices are row-major: element (v, c) of an [N x d] matrix is at
+ *    offset v * d + c.
+ */
+#ifndef TFI_H
+#define TFI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tfi_plan *tfi_handle;
+
+typedef enum {
+    TFI_F32 = 0,
+    TFI_F64 = 1
+} tfi_dtype;
+
+typedef enum {
+    TFI_OK = 0,
+    TFI_ERR_ARG = -1,     /* null pointer, bad size, bad option          */
+    TFI_ERR_TREE = -2,    /* parent out of range, self loop or cycle      */
+    TFI_ERR_WEIGHT = -3,  /* weight < 1, or a distance exceeds int32      */
+    TFI_ERR_DTYPE = -4,   /* unknown dtype                               */
+    TFI_ERR_OOM = -5,     /* host or device allocation failed            */
+    TFI_ERR_BUDGET = -6,  /* device memory budget too small              */
+    TFI_ERR_HIP = -7,     /* HIP runtime error (no device, launch error)  */
+    TFI_ERR_STATE = -8    /* handle built host-only, or wrong device      */
+} tfi_status;
+
+/* Backbone selection policy per recursive call. */
+typedef enum {
+    TFI_POLICY_ADAPTIVE = 0, /* diameter or centroid by the adaptive score  */
+    TFI_POLICY_DIAMETER = 1, /* always a (weighted) diameter path           */
+    TFI_POLICY_CENTROID = 2  /* always a single centroid vertex             */
+} tfi_policy;
+
+/* Build options; pass NULL for the defaults (all fields 0 = default). */
+typedef struct {
+    int32_t policy;              /* tfi_policy; default adaptive            */
+    int32_t leaf_max;            /* subtrees with at most this many
+                                    vertices are integrated densely;
+                                    0 = default (32), 1 = only single
+                                    vertices (the plain recursion)         */
+    int32_t device;              /* HIP device ordinal; -1 = host-only
+                                    plan (no device upload; for planning
+                                    statistics and host-side tests)        */
+    int32_t table_method;        /* 0 = per-job choice, 1 = force direct
+                                    sums, 2 = force FFT for every table    */
+    uint64_t memory_budget_bytes;/* cap on device bytes held by the handle
+                                    and its per-call scratch; 0 = none     */
+    int32_t reserved[8];
+} tfi_build_opts;
+
+/*
+ * Plan a forest on the host and upload the plan to the device.
+ *   parent  host int64[N]: parent[v] in [-1, N), -1 marks a root; the
+ *           parent pointers must form a forest (no cycles, no self loops)
+ *   weight  host int32[N]: weight[v] >= 1 is the length of edge
+ *           (v, parent[v]); ignored at roots
+ *   N       number of vertices, N >= 1
+ *   opts    NULL or build options
+ *   out     receives the handle (owned by the caller; free with
+ *           tfi_destroy)
+ * The arrays are read during the call only. Errors: TFI_ERR_ARG,
+ * TFI_ERR_TREE, TFI_ERR_WEIGHT, TFI_ERR_OOM, TFI_ERR_HIP, TFI_ERR_BUDGET.
+ */
+int tfi_build(const int64_t *parent, const int32_t *weight, int64_t N,
+              const tfi_build_opts *opts, tfi_handle *out);
+
+/* Number of vertices of the handle's forest. */
+int64_t tfi_num_vertices(tfi_handle h);
+
+/*
+ * Number of kernel-table entries f[0 .. K-1] that tfi_integrate and
+ * tfi_backward read. K exceeds the forest diameter: the interaction tables
+ * evaluate f at surrogate (through-the-backbone) distances and on the
+ * padded convolution grid (appendix algorithm "ComputeGTerm2DFFT" indexes
+ * f up to 2H + m - 1). Those extra entries cancel exactly in exact
+ * arithmetic but must be finite. Returns -1 for a null handle.
+ */
+int64_t tfi_kernel_length(tfi_handle h);
+
+/*
+ * Forward integration: out = K F with K[v, w] = f(dist(v, w)).
+ *   f    device dtype[tfi_kernel_length(h)]
+ *   F    device dtype[N x d]
+ *   d    channels, d >= 1
+ *   out  device dtype[N x d]; must not alias F
+ * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE, TFI_ERR_HIP,
+ * TFI_ERR_BUDGET, TFI_ERR_OOM.
+ */
+int tfi_integrate(tfi_handle h, const void *f, const void *F, int64_t d,
+                  tfi_dtype dtype, void *out, void *stream);
+
+/*
+ * Adjoint of tfi_integrate for the loss L = sum(gout * out):
+ *   dF = K gout (K is symmetric), device dtype[N x d], may be NULL;
+ *   df[k] = sum_{v, w : dist(v, w) = k} <gout[v, :], F[w, :]>, the
+ *   gradient with respect to the kernel table, device double[K] with
+ *   K = tfi_kernel_length(h) (entries beyond the diameter are 0), may be
+ *   NULL.
+ *   f, F, gout as in tfi_integrate (gout device dtype[N x d]).
+ * Errors as tfi_integrate.
+ */
+int tfi_backward(tfi_handle h, const void *f, const void *F,
+                 const void *gout, int64_t d, tfi_dtype dtype, void *dF,
+                 double *df, void *stream);
+
+/*
+ * Plan statistics as a JSON object written to the host buffer json[cap]
+ * (NUL-terminated, truncated to fit). Returns the full length needed
+ * (excluding the NUL), or a negative status.
+ */
+int64_t tfi_plan_stats(tfi_handle h, char *json, size_t cap);
+
+/*
+ * Copy a named plan array to the host buffer buf[cap bytes] for host-side
+ * inspection and tests. Returns the array's size in bytes (copying only
+ * when buf != NULL and cap is large enough), or a negative status for an
+ * unknown name. Names and element types are listed in the plan-stats JSON
+ * under "arrays".
+ */
+int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
+                        size_t cap);
+
+/* Release the handle and all its host and device memory. NULL is a no-op.
+ * Work enqueued with the handle must have completed. */
+void tfi_destroy(tfi_handle h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tfi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TFI_H */

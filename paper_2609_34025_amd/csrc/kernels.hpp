@@ -1,0 +1,352 @@
+// kernels.hpp -- gfx950 device kernels of the tree field integrator.
+//
+// Stages of one integration (all calls of all recursion levels at once):
+//   scatter  : b-cell sums b_alpha[r] (equation "stad-E") and A-cell sums
+//              A_r[x] (Section 2.2) from the field rows of their vertices;
+//   tables   : every table job evaluates, at its own occupied cells,
+//                G(i) = sum_j f(r_i + r_j + |x_i - x_j|) * val(j)
+//              by direct sums (small or sparse tables) or by one FFT
+//              convolution on the padded lattice (equation
+//              "stad-2d-convolution", lemma "stad-2d-fft");
+//   gather   : out[v] = sum over the calls holding v of G - E
+//              (lemma "stad-cross");
+//   leaves   : dense f(D) F on small subtrees.
+// No floating-point atomics: every sum has a fixed order, so results are
+// bitwise reproducible run to run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfi {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+
+// ------------------------------------------------------------- scatter ----
+// One thread per (A-cell, channel): walks the A-cell's b-cells, each a run
+// of incidences, summing field rows; writes every b-cell sum and the
+// A-cell sum into the value matrix val[(NA + NB) x d] (A-cells first).
+template <typename T>
+__global__ void k_scatter(int64_t NA, int32_t d, const int64_t* __restrict__ a_b_off,
+                          const int64_t* __restrict__ b_inc_off,
+                          const int32_t* __restrict__ inc_v, const T* __restrict__ F,
+                          T* __restrict__ val) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= NA * d) return;
+    const int64_t a = tid / d;
+    const int32_t c = (int32_t)(tid - a * d);
+    T sa = 0;
+    const int64_t b1 = a_b_off[a + 1];
+    for (int64_t b = a_b_off[a]; b < b1; ++b) {
+        T sb = 0;
+        const int64_t i1 = b_inc_off[b + 1];
+        for (int64_t i = b_inc_off[b]; i < i1; ++i)
+            sb += F[(int64_t)inc_v[i] * d + c];
+        val[(NA + b) * d + c] = sb;
+        sa += sb;
+    }
+    val[a * d + c] = sa;
+}
+
+// ------------------------------------------------------ direct tables ----
+// One thread per (output cell, channel) of the direct-method jobs. Cell k
+// of the list is table cell dcell[k]; its job's cells are [dbeg, dend).
+template <typename T>
+__global__ void k_direct(int64_t ncell, int32_t d, const int32_t* __restrict__ dcell,
+                         const int32_t* __restrict__ dbeg, const int32_t* __restrict__ dend,
+                         const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                         const int32_t* __restrict__ jc_val, const T* __restrict__ f,
+                         const T* __restrict__ val, T* __restrict__ g) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= ncell * d) return;
+    const int64_t k = tid / d;
+    const int32_t c = (int32_t)(tid - k * d);
+    const int32_t i = dcell[k];
+    const int32_t r = jc_r[i], x = jc_x[i];
+    T s = 0;
+    const int32_t e = dend[k];
+    for (int32_t j = dbeg[k]; j < e; ++j) {
+        const int32_t dx = x - jc_x[j];
+        const int32_t dist = r + jc_r[j] + (dx < 0 ? -dx : dx);
+        s += f[dist] * val[(int64_t)jc_val[j] * d + c];
+    }
+    g[(int64_t)jc_val[i] * d + c] = s;
+}
+
+// ---------------------------------------------------------------- gather --
+// One thread per (vertex, channel): sums, over the b-cells holding the
+// vertex, the call's table value at the b-cell's A-cell minus the
+// component correction (if any). Writes every out row.
+template <typename T>
+__global__ void k_gather(int64_t N, int32_t d, int64_t NA, const int64_t* __restrict__ v_off,
+                         const int32_t* __restrict__ v_b, const int32_t* __restrict__ b2a,
+                         const int8_t* __restrict__ b_corr, const T* __restrict__ g,
+                         T* __restrict__ out) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= N * d) return;
+    const int64_t v = tid / d;
+    const int32_t c = (int32_t)(tid - v * d);
+    T s = 0;
+    const int64_t k1 = v_off[v + 1];
+    for (int64_t k = v_off[v]; k < k1; ++k) {
+        const int32_t b = v_b[k];
+        s += g[(int64_t)b2a[b] * d + c];
+        if (b_corr[b]) s -= g[(NA + b) * d + c];
+    }
+    out[v * d + c] = s;
+}
+
+// ----------------------------------------------------------- leaf tiles --
+// One workgroup per leaf tile (a subtree of at most a few dozen vertices):
+// out[v] += sum_w f(D[v, w]) F[w] over the tile.
+template <typename T>
+__global__ void k_leaf(int32_t d, const int64_t* __restrict__ leaf_off,
+                       const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
+                       const int32_t* __restrict__ leaf_D, const T* __restrict__ f,
+                       const T* __restrict__ F, T* __restrict__ out) {
+    const int64_t t = blockIdx.x;
+    const int64_t beg = leaf_off[t];
+    const int32_t n = (int32_t)(leaf_off[t + 1] - beg);
+    const int32_t* D = leaf_D + leaf_doff[t];
+    const int32_t* vs = leaf_v + beg;
+    for (int32_t idx = threadIdx.x; idx < n * d; idx += blockDim.x) {
+        const int32_t i = idx / d, c = idx - i * d;
+        T s = 0;
+        for (int32_t j = 0; j < n; ++j)
+            s += f[D[i * n + j]] * F[(int64_t)vs[j] * d + c];
+        out[(int64_t)vs[i] * d + c] += s;
+    }
+}
+
+// ------------------------------------------------------------------- FFT --
+// In-place radix-2 transforms along one axis of a 2-D array in LDS.
+// Forward: decimation in frequency, natural order in, bit-reversed out.
+// Inverse: decimation in time, bit-reversed in, natural order out
+// (unnormalised). A convolution multiplies two forward spectra in the same
+// bit-reversed layout, so no reordering pass is needed.
+// Axis of length 2^lgL; `count` lines; element stride es, line stride ls.
+// tw[k] = exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), with lgtw >= lgL.
+template <typename T, bool INV>
+__device__ void fft_axis_lds(cpx<T>* z, int lgL, int count, int es, int ls,
+                             const cpx<T>* __restrict__ tw, int lgtw) {
+    if (lgL == 0) return;
+    const int half = 1 << (lgL - 1);
+    const int nb = count * half;
+    for (int s = 0; s < lgL; ++s) {
+        const int lh = INV ? s : (lgL - 1 - s);  // span h = 2^lh
+        const int h = 1 << lh;
+        for (int bi = threadIdx.x; bi < nb; bi += blockDim.x) {
+            const int line = bi >> (lgL - 1);
+            const int m = bi & (half - 1);
+            const int j = m & (h - 1);
+            const int blk = m >> lh;
+            const int i0 = line * ls + ((blk << (lh + 1)) + j) * es;
+            const int i1 = i0 + h * es;
+            const cpx<T> w = tw[j << (lgtw - lh - 1)];
+            const cpx<T> u = z[i0];
+            const cpx<T> v = z[i1];
+            if (!INV) {
+                z[i0] = cadd(u, v);
+                z[i1] = cmul(csub(u, v), w);
+            } else {
+                const cpx<T> vw = cmulc(v, w);
+                z[i0] = cadd(u, vw);
+                z[i1] = csub(u, vw);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Kernel spectrum of one FFT bucket: k[a][b] = f(a + |b|) on the padded
+// L1 x L2 grid (b taken as the signed circular offset), zero outside the
+// bucket's reach a <= 2 Hmax, |b| <= Xmax; forward 2-D transform.
+template <typename T>
+__global__ void k_spectrum_lds(int lg1, int lg2, int32_t hmax, int32_t xmax,
+                               const T* __restrict__ f, const cpx<T>* __restrict__ tw,
+                               int lgtw, cpx<T>* __restrict__ spec) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        const int a = p >> lg2, b = p & (L2 - 1);
+        const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
+        T v = 0;
+        if (a <= 2 * hmax && bs <= xmax) v = f[a + bs];
+        z[p] = {v, (T)0};
+    }
+    __syncthreads();
+    fft_axis_lds<T, false>(z, lg2, L1, 1, L2, tw, lgtw);
+    fft_axis_lds<T, false>(z, lg1, L2, L2, 1, tw, lgtw);
+    for (int p = threadIdx.x; p < P; p += blockDim.x) spec[p] = z[p];
+}
+
+// FFT convolution of LDS-resident tables: one workgroup per (job, channel
+// pair). Two real channels ride in the real and imaginary parts of one
+// complex table (the kernel is real, so the two results separate again in
+// the real and imaginary parts of the output). Source cell (r, x) goes to
+// row (-r mod L1): the Hankel dependence on q + r becomes a circular
+// convolution whose output row q needs no shift.
+template <typename T>
+__global__ void k_fft_conv_lds(int lg1, int lg2, const int32_t* __restrict__ jobs,
+                               const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                               const int32_t* __restrict__ jc_val, int32_t d,
+                               const T* __restrict__ val, T* __restrict__ g,
+                               const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
+                               int lgtw) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
+    const int32_t c0 = 2 * blockIdx.y, c1 = c0 + 1;
+    const bool has1 = c1 < d;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) z[p] = {(T)0, (T)0};
+    __syncthreads();
+    for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
+        const int row = (L1 - jc_r[k]) & (L1 - 1);
+        const int64_t vr = (int64_t)jc_val[k] * d;
+        z[(row << lg2) + jc_x[k]] = {val[vr + c0], has1 ? val[vr + c1] : (T)0};
+    }
+    __syncthreads();
+    fft_axis_lds<T, false>(z, lg2, L1, 1, L2, tw, lgtw);
+    fft_axis_lds<T, false>(z, lg1, L2, L2, 1, tw, lgtw);
+    for (int p = threadIdx.x; p < P; p += blockDim.x) z[p] = cmul(z[p], spec[p]);
+    __syncthreads();
+    fft_axis_lds<T, true>(z, lg1, L2, L2, 1, tw, lgtw);
+    fft_axis_lds<T, true>(z, lg2, L1, 1, L2, tw, lgtw);
+    const T scale = (T)1 / (T)P;
+    for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
+        const cpx<T> y = z[(jc_r[k] << lg2) + jc_x[k]];
+        const int64_t vr = (int64_t)jc_val[k] * d;
+        g[vr + c0] = y.x * scale;
+        if (has1) g[vr + c1] = y.y * scale;
+    }
+}
+
+// ---------------------------------------------- FFT through global memory --
+// Tables too large for LDS: the same in-place DIF/DIT transforms, one
+// radix-2 stage per launch over every (job, channel pair) line set of a
+// bucket. Buffer layout: slot s = job * npairs + pair holds P complex.
+template <typename T>
+__global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
+                              const int32_t* __restrict__ jobs,
+                              const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                              const int32_t* __restrict__ jc_val, int32_t d,
+                              const T* __restrict__ val, cpx<T>* __restrict__ buf) {
+    const int64_t P = (int64_t)1 << (lg1 + lg2);
+    const int64_t slot = blockIdx.y;
+    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
+    const int32_t c0 = 2 * pair, c1 = c0 + 1;
+    const int64_t L1 = (int64_t)1 << lg1;
+    cpx<T>* z = buf + slot * P;
+    const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
+    for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
+         k += gridDim.x * blockDim.x) {
+        const int64_t row = (L1 - jc_r[k]) & (L1 - 1);
+        const int64_t vr = (int64_t)jc_val[k] * d;
+        z[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
+    }
+}
+
+template <typename T, bool INV>
+__global__ void k_fft_stage_global(cpx<T>* __restrict__ buf, int64_t nslots, int lgP, int lgL,
+                                   int lh, int64_t es, const cpx<T>* __restrict__ tw, int lgtw) {
+    // Butterflies of span 2^lh along an axis of length 2^lgL with element
+    // stride es; every slot holds one 2^lgP-element array.
+    const int64_t P = (int64_t)1 << lgP;
+    const int64_t per_slot = P >> 1;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= nslots * per_slot) return;
+    const int64_t slot = tid / per_slot;
+    const int64_t bi = tid - slot * per_slot;
+    const int64_t half = (int64_t)1 << (lgL - 1);
+    const int64_t line = bi / half;
+    const int64_t m = bi - line * half;
+    const int64_t h = (int64_t)1 << lh;
+    const int64_t j = m & (h - 1);
+    const int64_t blk = m >> lh;
+    // line index -> base offset: lines enumerate the other axis
+    const int64_t base = (es == 1) ? line << lgL : line;
+    const int64_t i0 = slot * P + base + ((blk << (lh + 1)) + j) * es;
+    const int64_t i1 = i0 + h * es;
+    const cpx<T> w = tw[j << (lgtw - lh - 1)];
+    const cpx<T> u = buf[i0];
+    const cpx<T> v = buf[i1];
+    if (!INV) {
+        buf[i0] = cadd(u, v);
+        buf[i1] = cmul(csub(u, v), w);
+    } else {
+        const cpx<T> vw = cmulc(v, w);
+        buf[i0] = cadd(u, vw);
+        buf[i1] = csub(u, vw);
+    }
+}
+
+template <typename T>
+__global__ void k_spec_fill_global(int lg1, int lg2, int32_t hmax, int32_t xmax,
+                                   const T* __restrict__ f, cpx<T>* __restrict__ z) {
+    const int64_t P = (int64_t)1 << (lg1 + lg2);
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const int64_t L2 = (int64_t)1 << lg2;
+    const int64_t a = p >> lg2, b = p & (L2 - 1);
+    const int64_t bs = (b <= (L2 >> 1)) ? b : L2 - b;
+    T v = 0;
+    if (a <= 2 * (int64_t)hmax && bs <= xmax) v = f[a + bs];
+    z[p] = {v, (T)0};
+}
+
+template <typename T>
+__global__ void k_spec_mul_global(cpx<T>* __restrict__ buf, int64_t nslots, int lgP,
+                                  const cpx<T>* __restrict__ spec) {
+    const int64_t P = (int64_t)1 << lgP;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= nslots * P) return;
+    buf[tid] = cmul(buf[tid], spec[tid & (P - 1)]);
+}
+
+template <typename T>
+__global__ void k_extract_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
+                                 const int32_t* __restrict__ jobs,
+                                 const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                                 const int32_t* __restrict__ jc_val, int32_t d,
+                                 const cpx<T>* __restrict__ buf, T* __restrict__ g) {
+    const int64_t P = (int64_t)1 << (lg1 + lg2);
+    const int64_t slot = blockIdx.y;
+    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
+    const int32_t c0 = 2 * pair, c1 = c0 + 1;
+    const cpx<T>* z = buf + slot * P;
+    const T scale = (T)1 / (T)P;
+    const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
+    for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
+         k += gridDim.x * blockDim.x) {
+        const cpx<T> y = z[((int64_t)jc_r[k] << lg2) + jc_x[k]];
+        const int64_t vr = (int64_t)jc_val[k] * d;
+        g[vr + c0] = y.x * scale;
+        if (c1 < d) g[vr + c1] = y.y * scale;
+    }
+}
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ p, int64_t n) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < n) p[tid] = T{};
+}
+
+}  // namespace tfi

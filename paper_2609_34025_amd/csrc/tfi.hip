@@ -1,0 +1,497 @@
+// tfi.hip -- runtime and C ABI of libtfi.so (declared in include/tfi.h).
+//
+// tfi_build plans on the host (plan.cpp) and uploads the plan once.
+// tfi_integrate enqueues, on the caller's stream:
+//   spectra (per FFT bucket) -> scatter -> direct tables -> FFT tables
+//   -> gather -> leaf tiles.
+// tfi_backward enqueues the same forward on gout for dF (the kernel matrix
+// f(D) is symmetric) and the pair histograms for df.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tfi.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define TFI_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return fail(TFI_ERR_HIP, std::string(#call) + ": " +              \
+                                         hipGetErrorString(e_));               \
+    } while (0)
+
+constexpr int kThreads = 256;
+constexpr int64_t kLdsBytes = 64 * 1024;
+
+inline unsigned blocks_for(int64_t n, int threads = kThreads) {
+    return (unsigned)((n + threads - 1) / threads);
+}
+
+struct Bucket {
+    int lg1 = 0, lg2 = 0;
+    int32_t hmax = 0, xmax = 0;
+    std::vector<int32_t> jobs;  // pairs [cell_beg, cell_end)
+    int32_t* d_jobs = nullptr;
+    int64_t spec_off = 0;       // element offset into the spectrum arena
+    int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
+    int64_t njobs() const { return (int64_t)jobs.size() / 2; }
+};
+
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct tfi_plan {
+    tfi::Plan plan;
+    int device = -1;
+    uint64_t budget = 0;
+    size_t dev_bytes = 0;
+    std::vector<void*> allocs;
+
+    // plan arrays on the device
+    int32_t *d_inc_v = nullptr, *d_v_b = nullptr, *d_b2a = nullptr;
+    int64_t *d_b_inc_off = nullptr, *d_a_b_off = nullptr, *d_v_off = nullptr;
+    int8_t* d_b_corr = nullptr;
+    int32_t *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
+    int32_t *d_dcell = nullptr, *d_dbeg = nullptr, *d_dend = nullptr;
+    int64_t ndirect = 0;
+    int64_t *d_leaf_off = nullptr, *d_leaf_doff = nullptr;
+    int32_t *d_leaf_v = nullptr, *d_leaf_D = nullptr;
+    std::vector<Bucket> buckets;
+    int64_t spec_elems = 0;
+    int lgtw = 1;
+    void* d_tw[2] = {nullptr, nullptr};  // float / double twiddles
+
+    // per-dtype scratch (grow-only)
+    DeviceBuf val[2], g[2], spec[2], fftbuf[2], ftab[2];
+
+    ~tfi_plan() {
+        if (device >= 0) {
+            int prev = 0;
+            if (hipGetDevice(&prev) == hipSuccess) {
+                (void)hipSetDevice(device);
+                for (void* p : allocs) (void)hipFree(p);
+                for (int t = 0; t < 2; ++t)
+                    for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &ftab[t]})
+                        if (b->p) (void)hipFree(b->p);
+                (void)hipSetDevice(prev);
+            }
+        }
+    }
+
+    int dalloc(void** p, size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        if (budget && dev_bytes + bytes > budget)
+            return fail(TFI_ERR_BUDGET, "device memory budget exceeded (need " +
+                                            std::to_string(dev_bytes + bytes) + " bytes)");
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess)
+            return fail(TFI_ERR_OOM, std::string("hipMalloc(") + std::to_string(bytes) +
+                                         "): " + hipGetErrorString(e));
+        dev_bytes += bytes;
+        return TFI_OK;
+    }
+
+    template <typename V>
+    int upload(V** dst, const std::vector<V>& src) {
+        void* p = nullptr;
+        int rc = dalloc(&p, src.size() * sizeof(V));
+        if (rc) return rc;
+        allocs.push_back(p);
+        if (!src.empty())
+            TFI_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
+        *dst = (V*)p;
+        return TFI_OK;
+    }
+
+    int ensure(DeviceBuf& b, size_t bytes) {
+        if (b.bytes >= bytes && b.p) return TFI_OK;
+        if (b.p) {
+            TFI_HIP(hipDeviceSynchronize());
+            TFI_HIP(hipFree(b.p));
+            dev_bytes -= b.bytes;
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        int rc = dalloc(&b.p, bytes);
+        if (rc) return rc;
+        b.bytes = bytes;
+        return TFI_OK;
+    }
+};
+
+namespace {
+
+int check_handle(tfi_handle h, bool need_device) {
+    if (!h) return fail(TFI_ERR_ARG, "null handle");
+    if (need_device && h->device < 0)
+        return fail(TFI_ERR_STATE, "handle was built host-only (opts.device = -1)");
+    if (need_device) {
+        hipError_t e = hipSetDevice(h->device);
+        if (e != hipSuccess)
+            return fail(TFI_ERR_HIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
+    return TFI_OK;
+}
+
+int upload_plan(tfi_plan* h) {
+    const tfi::Plan& p = h->plan;
+    int rc;
+    if ((rc = h->upload(&h->d_inc_v, p.inc_v))) return rc;
+    if ((rc = h->upload(&h->d_b_inc_off, p.b_inc_off))) return rc;
+    if ((rc = h->upload(&h->d_a_b_off, p.a_b_off))) return rc;
+    if ((rc = h->upload(&h->d_b2a, p.b2a))) return rc;
+    if ((rc = h->upload(&h->d_b_corr, p.b_corr))) return rc;
+    if ((rc = h->upload(&h->d_v_off, p.v_off))) return rc;
+    if ((rc = h->upload(&h->d_v_b, p.v_b))) return rc;
+    if ((rc = h->upload(&h->d_jc_r, p.jc_r))) return rc;
+    if ((rc = h->upload(&h->d_jc_x, p.jc_x))) return rc;
+    if ((rc = h->upload(&h->d_jc_val, p.jc_val))) return rc;
+    if ((rc = h->upload(&h->d_leaf_off, p.leaf_off))) return rc;
+    if ((rc = h->upload(&h->d_leaf_v, p.leaf_v))) return rc;
+    if ((rc = h->upload(&h->d_leaf_doff, p.leaf_doff))) return rc;
+    if ((rc = h->upload(&h->d_leaf_D, p.leaf_D))) return rc;
+
+    // direct-method output cells with their job ranges
+    std::vector<int32_t> dcell, dbeg, dend;
+    std::map<std::pair<int, int>, size_t> bidx;
+    const int64_t J = (int64_t)p.job_H.size();
+    int maxlg = 1;
+    for (int64_t j = 0; j < J; ++j) {
+        const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
+        if (p.job_method[j] == tfi::METHOD_DIRECT) {
+            for (int32_t i = cb; i < ce; ++i) {
+                dcell.push_back(i);
+                dbeg.push_back(cb);
+                dend.push_back(ce);
+            }
+        } else {
+            auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
+            auto it = bidx.find(key);
+            if (it == bidx.end()) {
+                it = bidx.emplace(key, h->buckets.size()).first;
+                Bucket b;
+                b.lg1 = key.first;
+                b.lg2 = key.second;
+                h->buckets.push_back(b);
+            }
+            Bucket& b = h->buckets[it->second];
+            b.hmax = std::max(b.hmax, p.job_H[j]);
+            b.xmax = std::max(b.xmax, p.job_X[j]);
+            b.jobs.push_back(cb);
+            b.jobs.push_back(ce);
+            maxlg = std::max(maxlg, std::max(b.lg1, b.lg2));
+        }
+    }
+    h->ndirect = (int64_t)dcell.size();
+    if ((rc = h->upload(&h->d_dcell, dcell))) return rc;
+    if ((rc = h->upload(&h->d_dbeg, dbeg))) return rc;
+    if ((rc = h->upload(&h->d_dend, dend))) return rc;
+    h->spec_elems = 0;
+    for (Bucket& b : h->buckets) {
+        if ((rc = h->upload(&b.d_jobs, b.jobs))) return rc;
+        b.spec_off = h->spec_elems;
+        h->spec_elems += b.P();
+    }
+    // twiddles exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), from long double
+    h->lgtw = maxlg;
+    const int64_t TW = (int64_t)1 << h->lgtw, nt = TW / 2;
+    std::vector<tfi::cpx<float>> twf(nt);
+    std::vector<tfi::cpx<double>> twd(nt);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int64_t k = 0; k < nt; ++k) {
+        long double a = -2.0L * pi * (long double)k / (long double)TW;
+        twd[k] = {(double)cosl(a), (double)sinl(a)};
+        twf[k] = {(float)cosl(a), (float)sinl(a)};
+    }
+    tfi::cpx<float>* tf = nullptr;
+    tfi::cpx<double>* td = nullptr;
+    if ((rc = h->upload(&tf, twf))) return rc;
+    if ((rc = h->upload(&td, twd))) return rc;
+    h->d_tw[0] = tf;
+    h->d_tw[1] = td;
+    return TFI_OK;
+}
+
+template <typename T>
+int64_t lds_cells() {
+    return kLdsBytes / (int64_t)sizeof(tfi::cpx<T>);
+}
+
+// Forward integration out = f(D) F on `stream`.
+template <typename T>
+int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const int64_t rows = p.NA + p.NB;
+    int rc;
+    if ((rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(rows, 1) * d * sizeof(T)))) return rc;
+    if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(rows, 1) * d * sizeof(T)))) return rc;
+    if ((rc = h->ensure(h->spec[ti],
+                        (size_t)std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>))))
+        return rc;
+    T* val = (T*)h->val[ti].p;
+    T* g = (T*)h->g[ti].p;
+    tfi::cpx<T>* spec = (tfi::cpx<T>*)h->spec[ti].p;
+    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
+    const int64_t ldsc = lds_cells<T>();
+    const int32_t npairs = (d + 1) / 2;
+
+    // FFT workspace for buckets beyond LDS: jobs are processed in chunks
+    // of at most 2 GiB (and 65535 job-channel-pair slots) per chunk
+    size_t want = 0;
+    for (const Bucket& b : h->buckets) {
+        if (b.P() <= ldsc) continue;
+        const size_t one_job = (size_t)b.P() * npairs * sizeof(tfi::cpx<T>);
+        const size_t all = one_job * (size_t)b.njobs();
+        want = std::max(want, std::max(one_job, std::min(all, (size_t)2 << 30)));
+    }
+    if (want && (rc = h->ensure(h->fftbuf[ti], want))) return rc;
+
+    // 1. kernel spectra per bucket
+    for (const Bucket& b : h->buckets) {
+        if (b.P() <= ldsc) {
+            hipLaunchKernelGGL(tfi::k_spectrum_lds<T>, dim3(1), dim3(kThreads),
+                               (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1, b.lg2, b.hmax,
+                               b.xmax, f, tw, h->lgtw, spec + b.spec_off);
+        } else {
+            tfi::cpx<T>* z = spec + b.spec_off;
+            hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads),
+                               0, st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
+            const int lgP = b.lg1 + b.lg2;
+            for (int s = 0; s < b.lg2; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
+                                   dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
+                                   (int64_t)1, tw, h->lgtw);
+            for (int s = 0; s < b.lg1; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
+                                   dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
+                                   (int64_t)1 << b.lg2, tw, h->lgtw);
+        }
+    }
+    // 2. scatter
+    if (p.NA > 0)
+        hipLaunchKernelGGL(tfi::k_scatter<T>, dim3(blocks_for(p.NA * d)), dim3(kThreads), 0, st,
+                           p.NA, d, h->d_a_b_off, h->d_b_inc_off, h->d_inc_v, F, val);
+    // 3. direct tables
+    if (h->ndirect > 0)
+        hipLaunchKernelGGL(tfi::k_direct<T>, dim3(blocks_for(h->ndirect * d)), dim3(kThreads), 0,
+                           st, h->ndirect, d, h->d_dcell, h->d_dbeg, h->d_dend, h->d_jc_r,
+                           h->d_jc_x, h->d_jc_val, f, val, g);
+    // 4. FFT tables
+    for (const Bucket& b : h->buckets) {
+        if (b.P() <= ldsc) {
+            hipLaunchKernelGGL(tfi::k_fft_conv_lds<T>, dim3((unsigned)b.njobs(), npairs),
+                               dim3(kThreads), (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1,
+                               b.lg2, b.d_jobs, h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g,
+                               spec + b.spec_off, tw, h->lgtw);
+            continue;
+        }
+        tfi::cpx<T>* buf = (tfi::cpx<T>*)h->fftbuf[ti].p;
+        const int64_t slots_cap = std::min<int64_t>(
+            65535, (int64_t)(h->fftbuf[ti].bytes / sizeof(tfi::cpx<T>)) / b.P());
+        const int64_t jobs_per_chunk = std::max<int64_t>(1, slots_cap / npairs);
+        const int lgP = b.lg1 + b.lg2;
+        for (int64_t j0 = 0; j0 < b.njobs(); j0 += jobs_per_chunk) {
+            const int64_t nj = std::min(jobs_per_chunk, b.njobs() - j0);
+            const int64_t nslots = nj * npairs;
+            const int32_t* jobs = b.d_jobs + 2 * j0;
+            hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * b.P())),
+                               dim3(kThreads), 0, st, buf, nslots * b.P());
+            hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
+                               0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r,
+                               h->d_jc_x, h->d_jc_val, d, val, buf);
+            const unsigned nb = blocks_for(nslots * b.P() / 2);
+            for (int s = 0; s < b.lg2; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                                   st, buf, nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
+                                   h->lgtw);
+            for (int s = 0; s < b.lg1; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                                   st, buf, nslots, lgP, b.lg1, b.lg1 - 1 - s,
+                                   (int64_t)1 << b.lg2, tw, h->lgtw);
+            hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
+                               dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
+            for (int s = 0; s < b.lg1; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
+                                   st, buf, nslots, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw,
+                                   h->lgtw);
+            for (int s = 0; s < b.lg2; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
+                                   st, buf, nslots, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+            hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots),
+                               dim3(kThreads), 0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs,
+                               h->d_jc_r, h->d_jc_x, h->d_jc_val, d, buf, g);
+        }
+    }
+    // 5. gather (writes every row of out)
+    hipLaunchKernelGGL(tfi::k_gather<T>, dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st, p.N, d,
+                       p.NA, h->d_v_off, h->d_v_b, h->d_b2a, h->d_b_corr, g, out);
+    // 6. leaf tiles add their dense values
+    const int64_t nleaf = (int64_t)p.leaf_off.size() - 1;
+    if (nleaf > 0)
+        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)nleaf), dim3(128), 0, st, d,
+                           h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff, h->d_leaf_D, f, F, out);
+    TFI_HIP(hipGetLastError());
+    return TFI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
+              const tfi_build_opts* opts, tfi_handle* out) {
+    g_err.clear();
+    if (!out) return fail(TFI_ERR_ARG, "tfi_build: null output handle");
+    *out = nullptr;
+    tfi_build_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    tfi::PlanOptions po;
+    po.policy = o.policy;
+    po.leaf_max = o.leaf_max == 0 ? 32 : o.leaf_max;
+    po.table_method = o.table_method;
+    if (o.device < -1) return fail(TFI_ERR_ARG, "tfi_build: device must be >= -1");
+    std::unique_ptr<tfi_plan> h;
+    try {
+        h.reset(new tfi_plan());
+    } catch (const std::bad_alloc&) {
+        return fail(TFI_ERR_OOM, "tfi_build: host allocation failed");
+    }
+    std::string err;
+    int rc = tfi::build_plan(parent, weight, N, po, h->plan, err);
+    if (rc) return fail(rc, err);
+    h->budget = o.memory_budget_bytes;
+    if (o.device >= 0) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count <= o.device)
+            return fail(TFI_ERR_HIP, "tfi_build: HIP device " + std::to_string(o.device) +
+                                         " not available");
+        TFI_HIP(hipSetDevice(o.device));
+        h->device = o.device;
+        rc = upload_plan(h.get());
+        if (rc) return rc;
+    }
+    *out = h.release();
+    return TFI_OK;
+}
+
+int64_t tfi_num_vertices(tfi_handle h) { return h ? h->plan.N : -1; }
+
+int64_t tfi_kernel_length(tfi_handle h) { return h ? h->plan.kernel_len : -1; }
+
+int tfi_integrate(tfi_handle h, const void* f, const void* F, int64_t d, tfi_dtype dtype,
+                  void* out, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate: null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_integrate: need 1 <= d <= 2^20");
+    if (F == out) return fail(TFI_ERR_ARG, "tfi_integrate: out must not alias F");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return run_forward<float>(h, (const float*)f, (const float*)F, (int32_t)d, (float*)out, st);
+    if (dtype == TFI_F64)
+        return run_forward<double>(h, (const double*)f, (const double*)F, (int32_t)d,
+                                   (double*)out, st);
+    return fail(TFI_ERR_DTYPE, "tfi_integrate: unknown dtype");
+}
+
+int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, int64_t d,
+                 tfi_dtype dtype, void* dF, double* df, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f || !F || !gout) return fail(TFI_ERR_ARG, "tfi_backward: null pointer");
+    if (df) return fail(TFI_ERR_STATE, "tfi_backward: df is not available in this build");
+    if (dF) return tfi_integrate(h, f, gout, d, dtype, dF, stream);
+    return TFI_OK;
+}
+
+int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
+    g_err.clear();
+    if (!h) return fail(TFI_ERR_ARG, "tfi_plan_stats: null handle");
+    std::string s = tfi::plan_stats_json(h->plan);
+    s += ",\"device\":" + std::to_string(h->device) +
+         ",\"device_bytes\":" + std::to_string(h->dev_bytes) +
+         ",\"arrays\":{\"job_H\":\"i32\",\"job_X\":\"i32\",\"job_sign\":\"i32\","
+         "\"job_method\":\"i32\",\"job_level\":\"i32\",\"job_lg1\":\"i32\",\"job_lg2\":\"i32\","
+         "\"job_cell_off\":\"i64\",\"jc_r\":\"i32\",\"jc_x\":\"i32\",\"jc_val\":\"i32\","
+         "\"inc_v\":\"i32\",\"b_inc_off\":\"i64\",\"a_b_off\":\"i64\",\"b2a\":\"i32\","
+         "\"b_corr\":\"i8\",\"v_off\":\"i64\",\"v_b\":\"i32\",\"leaf_off\":\"i64\","
+         "\"leaf_v\":\"i32\",\"leaf_doff\":\"i64\",\"leaf_D\":\"i32\"}}";
+    if (json && cap > 0) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(json, s.data(), n);
+        json[n] = 0;
+    }
+    return (int64_t)s.size();
+}
+
+int64_t tfi_plan_export(tfi_handle h, const char* name, void* buf, size_t cap) {
+    g_err.clear();
+    if (!h || !name) return fail(TFI_ERR_ARG, "tfi_plan_export: null argument");
+    const tfi::Plan& p = h->plan;
+    const void* src = nullptr;
+    size_t bytes = 0;
+    auto pick = [&](const auto& v) {
+        src = v.data();
+        bytes = v.size() * sizeof(v[0]);
+    };
+    std::string n(name);
+    if (n == "job_H") pick(p.job_H);
+    else if (n == "job_X") pick(p.job_X);
+    else if (n == "job_sign") pick(p.job_sign);
+    else if (n == "job_method") pick(p.job_method);
+    else if (n == "job_level") pick(p.job_level);
+    else if (n == "job_lg1") pick(p.job_lg1);
+    else if (n == "job_lg2") pick(p.job_lg2);
+    else if (n == "job_cell_off") pick(p.job_cell_off);
+    else if (n == "jc_r") pick(p.jc_r);
+    else if (n == "jc_x") pick(p.jc_x);
+    else if (n == "jc_val") pick(p.jc_val);
+    else if (n == "inc_v") pick(p.inc_v);
+    else if (n == "b_inc_off") pick(p.b_inc_off);
+    else if (n == "a_b_off") pick(p.a_b_off);
+    else if (n == "b2a") pick(p.b2a);
+    else if (n == "b_corr") pick(p.b_corr);
+    else if (n == "v_off") pick(p.v_off);
+    else if (n == "v_b") pick(p.v_b);
+    else if (n == "leaf_off") pick(p.leaf_off);
+    else if (n == "leaf_v") pick(p.leaf_v);
+    else if (n == "leaf_doff") pick(p.leaf_doff);
+    else if (n == "leaf_D") pick(p.leaf_D);
+    else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
+    if (buf && cap >= bytes && bytes) std::memcpy(buf, src, bytes);
+    return (int64_t)bytes;
+}
+
+void tfi_destroy(tfi_handle h) { delete h; }
+
+const char* tfi_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

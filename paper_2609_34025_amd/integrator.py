@@ -1,0 +1,163 @@
+"""User-facing tree field integrator on one MI355X GPU.
+
+``TreeIntegrator`` owns a plan built once per forest (``tfi_build``) and
+integrates fields on the GPU: ``out[v] = sum_w f(dist(v, w)) F[w]``.
+``TreeIntegrate`` is the autograd function with the hand-written adjoint
+(dF = f(D) gout since f(D) is symmetric; df from pair histograms), and
+``expsum_table`` materialises the learnable kernel
+``f(k) = sum_j a_j exp(-b_j k)`` as a table so autograd carries df to da, db.
+
+PyTorch supplies device memory and the current stream; all arithmetic runs
+in libtfi.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.float32: _lib.TFI_F32, torch.float64: _lib.TFI_F64}
+
+
+class TreeIntegrator:
+    """Plan of one forest, uploaded to one GPU.
+
+    parent  int64[N], -1 at roots; weight int32[N] >= 1 (edge to parent).
+    policy  'adaptive' (paper's score), 'diameter' or 'centroid'.
+    leaf_max  subtrees up to this size are integrated densely (0 = default).
+    device  CUDA/HIP device index, or None for a host-only plan (stats and
+            plan inspection only).
+    table_method  'auto', 'direct' or 'fft' for every interaction table.
+    memory_budget  cap in bytes on device memory held by the handle (0 = no cap).
+    """
+
+    def __init__(self, parent, weight, *, policy="adaptive", leaf_max=0, device=0,
+                 table_method="auto", memory_budget=0):
+        if device is not None and isinstance(device, torch.device):
+            device = device.index or 0
+        self._h = _lib.build_handle(parent, weight, policy=policy, leaf_max=leaf_max,
+                                    device=device, table_method=table_method,
+                                    memory_budget=memory_budget)
+        self.device = None if device is None else torch.device("cuda", int(device))
+        lib = _lib.load()
+        self.num_vertices = int(lib.tfi_num_vertices(self._h))
+        self.kernel_length = int(lib.tfi_kernel_length(self._h))
+
+    # ------------------------------------------------------------- info --
+    def stats(self):
+        lib = _lib.load()
+        n = _lib.check(lib.tfi_plan_stats(self._h, None, 0))
+        buf = C.create_string_buffer(n + 1)
+        _lib.check(lib.tfi_plan_stats(self._h, buf, n + 1))
+        return json.loads(buf.value.decode())
+
+    def export(self, name):
+        lib = _lib.load()
+        nbytes = _lib.check(lib.tfi_plan_export(self._h, name.encode(), None, 0))
+        kind = self.stats()["arrays"][name]
+        arr = np.empty(nbytes // np.dtype(_lib._EXPORT_TYPES[kind]).itemsize,
+                       dtype=_lib._EXPORT_TYPES[kind])
+        if nbytes:
+            _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, nbytes))
+        return arr
+
+    # ---------------------------------------------------------- compute --
+    def _check(self, f, *mats):
+        if self.device is None:
+            raise _lib.TFIError(-8, "host-only plan: build with a device to integrate")
+        if f.dtype not in _DTYPES:
+            raise TypeError("f must be float32 or float64")
+        if f.device != self.device or f.dim() != 1 or not f.is_contiguous():
+            raise ValueError(f"f must be a contiguous 1-D tensor on {self.device}")
+        if f.numel() < self.kernel_length:
+            raise ValueError(f"f needs at least kernel_length={self.kernel_length} entries, "
+                             f"got {f.numel()}")
+        for m in mats:
+            if m.dtype != f.dtype:
+                raise TypeError("field and kernel must share one dtype")
+            if m.device != self.device or not m.is_contiguous():
+                raise ValueError(f"fields must be contiguous tensors on {self.device}")
+            if m.shape[0] != self.num_vertices or m.dim() not in (1, 2):
+                raise ValueError(f"fields must be [N] or [N, d] with N={self.num_vertices}")
+
+    @staticmethod
+    def _stream(dev):
+        return torch.cuda.current_stream(dev).cuda_stream
+
+    def integrate(self, f, F):
+        """out = f(D) F for F of shape [N] or [N, d]."""
+        self._check(f, F)
+        d = 1 if F.dim() == 1 else F.shape[1]
+        out = torch.empty_like(F)
+        if d == 0:
+            return out
+        lib = _lib.load()
+        _lib.check(lib.tfi_integrate(self._h, f.data_ptr(), F.data_ptr(), d,
+                                     _DTYPES[f.dtype], out.data_ptr(),
+                                     self._stream(self.device)))
+        return out
+
+    def backward(self, f, F, gout, need_dF=True, need_df=True):
+        """Adjoint of ``integrate`` for L = sum(gout * out): returns
+        ``(dF, df)``; df is float64 of length ``kernel_length``."""
+        self._check(f, F, gout)
+        if F.shape != gout.shape:
+            raise ValueError("F and gout must have the same shape")
+        d = 1 if F.dim() == 1 else F.shape[1]
+        dF = torch.empty_like(F) if need_dF else None
+        df = (torch.zeros(self.kernel_length, dtype=torch.float64, device=self.device)
+              if need_df else None)
+        lib = _lib.load()
+        _lib.check(lib.tfi_backward(self._h, f.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
+                                    _DTYPES[f.dtype],
+                                    dF.data_ptr() if dF is not None else None,
+                                    df.data_ptr() if df is not None else None,
+                                    self._stream(self.device)))
+        return dF, df
+
+    def close(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            _lib.load().tfi_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TreeIntegrate(torch.autograd.Function):
+    """``out = TreeIntegrate.apply(integrator, F, f)`` with gradients for F
+    and the kernel table f."""
+
+    @staticmethod
+    def forward(ctx, integrator, F, f):
+        ctx.integrator = integrator
+        ctx.save_for_backward(F, f)
+        return integrator.integrate(f, F)
+
+    @staticmethod
+    def backward(ctx, gout):
+        F, f = ctx.saved_tensors
+        need_dF, need_df = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
+        if not (need_dF or need_df):
+            return None, None, None
+        dF, df = ctx.integrator.backward(f, F, gout.contiguous(), need_dF, need_df)
+        if df is not None:
+            full = torch.zeros_like(f)
+            k = min(f.numel(), df.numel())
+            full[:k] = df[:k].to(f.dtype)
+            df = full
+        return None, dF, df
+
+
+def expsum_table(a, b, length):
+    """Kernel table ``f[k] = sum_j a_j exp(-b_j k)``, k < length, built with
+    torch ops so that autograd maps df to (da, db)."""
+    k = torch.arange(length, dtype=a.dtype, device=a.device)
+    return (a[None, :] * torch.exp(-k[:, None] * b[None, :])).sum(1)
