@@ -1,0 +1,236 @@
+"""GPU parity: libtfi.so on the device against the CPU FP64 oracle.
+
+Error metric: relative Frobenius norm ||Y - Y*||_F / ||Y*||_F over all
+outputs compared (all rows, or sampled rows at full sizes). Bars: 1e-10 for
+FP64 and 1e-4 for FP32.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_34025_amd import synth as S
+from paper_2609_34025_amd import TreeIntegrator
+from paper_2609_34025_amd._lib import TFIError
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-10, torch.float32: 1e-4}
+DEV = "cuda:0"
+
+
+def relerr(y, ref):
+    y = np.asarray(y, dtype=np.float64)
+    n = np.linalg.norm(ref)
+    return np.linalg.norm(y - ref) / (n if n > 0 else 1.0)
+
+
+def gpu_integrate(p, w, ftab, F, dtype=torch.float64, **opts):
+    t = TreeIntegrator(p, w, device=0, **opts)
+    K = t.kernel_length
+    f = torch.tensor(ftab(K) if callable(ftab) else ftab[:K], dtype=dtype, device=DEV)
+    Ft = torch.tensor(F, dtype=dtype, device=DEV)
+    out = t.integrate(f, Ft)
+    torch.cuda.synchronize()
+    return t, out.cpu().numpy()
+
+
+def check(p, w, ftab_fn, F, dtype=torch.float64, rows=None, **opts):
+    t, y = gpu_integrate(p, w, ftab_fn, F, dtype, **opts)
+    K = t.kernel_length
+    ref = oracle.integrate(p, w, ftab_fn(K), F, rows=rows)
+    y = y if rows is None else y[rows]
+    e = relerr(y, ref)
+    assert e <= TOL[dtype], (e, opts)
+    return e
+
+
+def test_small_config_fp64_and_fp32():
+    W = S.workload("small")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    fn = W["kernels"][0][1]
+    e64 = check(p, w, fn, F, torch.float64)
+    e32 = check(p, w, fn, F, torch.float32)
+    print(f"small N=2000 d=4: fp64 {e64:.2e} fp32 {e32:.2e}", flush=True)
+
+
+def prufer_trees(n):
+    for seq in itertools.product(range(n), repeat=n - 2):
+        deg = [1] * n
+        for x in seq:
+            deg[x] += 1
+        edges = []
+        for x in seq:
+            leaf = min(i for i in range(n) if deg[i] == 1)
+            edges.append((leaf, x))
+            deg[leaf] -= 1
+            deg[x] -= 1
+        u, v = [i for i in range(n) if deg[i] == 1]
+        edges.append((u, v))
+        yield edges
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_all_labelled_trees(n):
+    rng = np.random.default_rng(200 + n)
+    trees = list(prufer_trees(n)) if n > 1 else [[]]
+    for edges in trees:
+        wt = rng.integers(1, 5, size=len(edges))
+        p, w = S.edges_to_parent(n, [e[0] for e in edges], [e[1] for e in edges], wt,
+                                 root=int(rng.integers(n)))
+        F = rng.standard_normal((n, 3))
+        for policy, leaf in (("adaptive", 1), ("diameter", 1), ("centroid", 1),
+                             ("adaptive", 32)):
+            check(p, w, lambda K: np.linspace(1.0, -0.5, K) ** 3 + 0.3, F,
+                  policy=policy, leaf_max=leaf)
+
+
+def families():
+    rng = np.random.default_rng(9)
+    out = [("rrt500_w8", *(lambda p: (p, S.uniform_weights(p, 1, 8, rng)))(
+        S.random_recursive(500, rng)[0]))]
+    out.append(("grid20_w16", *S.grid_mst(20, 16, rng)))
+    cp = S.caterpillar(60, 3)[0]
+    out.append(("cater60_w8", cp, S.uniform_weights(cp, 1, 8, rng)))
+    out.append(("chp16", *S.caterpillar_hanging_paths(16)))
+    out.append(("spider8x40", *S.spider(8, 40)))
+    out.append(("binary7", *S.balanced_kary(2, 7)))
+    out.append(("ternary5", *S.balanced_kary(3, 5)))
+    out.append(("comb100", *S.comb(100)))
+    out.append(("double_broom160", *S.double_broom(160)))
+    out.append(("star200", *S.star(200)))
+    out.append(("path300", *S.path(300)))
+    out.append(("pref400", *S.preferential_attachment(400, rng)))
+    t1 = S.random_recursive(80, rng)
+    fp, fw, _ = S.forest([(t1[0], S.uniform_weights(t1[0], 1, 4, rng)),
+                          S.grid_mst(7, 9, rng), S.path(1), S.star(5)])
+    out.append(("forest", fp, fw))
+    return out
+
+
+@pytest.mark.parametrize("method", ["auto", "direct", "fft"])
+@pytest.mark.parametrize("policy", ["adaptive", "diameter", "centroid"])
+def test_families_policies_methods(policy, method):
+    rng = np.random.default_rng(11)
+    for name, p, w in families():
+        F = rng.standard_normal((len(p), 5))
+        for leaf in (1, 32):
+            e = check(p, w, lambda K: np.exp(-0.07 * np.arange(K)) + 0.2 / (1 + np.arange(K)),
+                      F, torch.float64, policy=policy, leaf_max=leaf, table_method=method)
+            assert e <= 1e-10, name
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_large_tables_through_global_memory(dtype):
+    # Tables beyond LDS capacity take the global-memory FFT passes: a long
+    # weighted path with a diameter backbone (L2 = 16384) and a long spider
+    # forced to FFT tables.
+    rng = np.random.default_rng(13)
+    p, _ = S.path(3000)
+    w = S.uniform_weights(p, 1, 2, rng)
+    F = rng.standard_normal((len(p), 3))
+    check(p, w, lambda K: np.exp(-0.002 * np.arange(K)), F, dtype, policy="diameter",
+          table_method="fft")
+    p, w = S.spider(8, 3000)
+    F = rng.standard_normal((len(p), 2))
+    check(p, w, lambda K: 1.0 / (1.0 + np.arange(K)) ** 2, F, dtype, table_method="fft")
+
+
+def test_channel_counts_and_vector_field():
+    rng = np.random.default_rng(15)
+    p, _ = S.random_recursive(700, rng)
+    w = S.uniform_weights(p, 1, 6, rng)
+    for d in (1, 2, 3, 16, 33, 64):
+        F = rng.standard_normal((len(p), d))
+        check(p, w, lambda K: np.exp(-0.05 * np.arange(K)), F, torch.float32)
+    t = TreeIntegrator(p, w, device=0)
+    f = torch.exp(-0.05 * torch.arange(t.kernel_length, dtype=torch.float64, device=DEV))
+    x = torch.tensor(rng.standard_normal(len(p)), device=DEV)
+    y = t.integrate(f, x)
+    ref = oracle.integrate(p, w, f.cpu().numpy(), x.cpu().numpy())
+    assert y.shape == x.shape and relerr(y.cpu().numpy(), ref) < 1e-10
+
+
+def test_tiny_and_degenerate():
+    rng = np.random.default_rng(16)
+    f = lambda K: 1.0 + np.arange(K) * 0.0  # f == 1: column sums
+    for p, w in [S.path(1), S.path(2), S.star(3)]:
+        F = rng.standard_normal((len(p), 2))
+        check(p, w, f, F)
+    # forest of singletons: out = f(0) F
+    n = 257
+    p = -np.ones(n, dtype=np.int64)
+    w = np.zeros(n, dtype=np.int32)
+    F = rng.standard_normal((n, 4))
+    t, y = gpu_integrate(p, w, lambda K: 2.5 * np.ones(K), F)
+    np.testing.assert_allclose(y, 2.5 * F, rtol=1e-15)
+
+
+def test_rrt100k_sampled_rows_both_kernels():
+    W = S.workload("rrt100k")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    rows = np.random.default_rng(99).choice(len(p), 512, replace=False)
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    Ft = torch.tensor(F, device=DEV)
+    for name, fn in W["kernels"]:
+        f = torch.tensor(fn(K), dtype=torch.float32, device=DEV)
+        y = t.integrate(f, Ft).cpu().numpy()
+        ref = oracle.integrate(p, w, fn(K), F.astype(np.float64), rows=rows)
+        e = relerr(y[rows], ref)
+        print(f"rrt100k {name}: rel err {e:.2e}", flush=True)
+        assert e <= 1e-4
+
+
+def test_exp_kernel_full_against_tree_recursion():
+    # All rows at N = 1e5 against the independent exp-kernel recursion.
+    W = S.workload("rrt100k")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    f = torch.exp(-0.05 * torch.arange(K, dtype=torch.float64, device=DEV)).float()
+    y = t.integrate(f, torch.tensor(F, device=DEV)).cpu().numpy()
+    ref = oracle.expdp(p, w, [1.0], [np.exp(-0.05)], F.astype(np.float64))
+    e = relerr(y, ref)
+    print(f"rrt100k exp kernel, all rows vs recursion: {e:.2e}", flush=True)
+    assert e <= 1e-4
+
+
+def test_forest_equals_separate_trees_and_determinism():
+    rng = np.random.default_rng(17)
+    trees = []
+    for s in (14, 20, 33):
+        trees.append(S.grid_mst(s, 16, rng))
+    p, w, offs = S.forest(trees)
+    F = rng.standard_normal((len(p), 8)).astype(np.float32)
+    a = rng.standard_normal(3)
+    tab = S.expsum_table(TreeIntegrator(p, w, device=None).kernel_length + 4096, a,
+                         [0.1, 0.2, 0.3])
+    t, y1 = gpu_integrate(p, w, tab, F, torch.float32)
+    _, y2 = gpu_integrate(p, w, tab, F, torch.float32)
+    assert np.array_equal(y1, y2)  # bitwise reproducible
+    for i, (tp, tw_) in enumerate(trees):
+        _, yi = gpu_integrate(tp, tw_, tab, F[offs[i]:offs[i + 1]], torch.float32)
+        ref = oracle.integrate(tp, tw_, tab, F[offs[i]:offs[i + 1]].astype(np.float64))
+        assert relerr(y1[offs[i]:offs[i + 1]], ref) <= 1e-4
+        assert relerr(yi, ref) <= 1e-4
+
+
+def test_argument_errors():
+    p, w = S.path(10)
+    t = TreeIntegrator(p, w, device=0)
+    f = torch.ones(t.kernel_length, dtype=torch.float32, device=DEV)
+    F = torch.ones(10, 2, dtype=torch.float32, device=DEV)
+    with pytest.raises(ValueError):
+        t.integrate(f[:-1], F)              # kernel table too short
+    with pytest.raises(TypeError):
+        t.integrate(f.double(), F)          # dtype mismatch
+    with pytest.raises(ValueError):
+        t.integrate(f, F[:9])               # wrong N
+    with pytest.raises(ValueError):
+        t.integrate(f, F.cpu())             # host tensor
+    h = TreeIntegrator(p, w, device=None)
+    with pytest.raises(TFIError):
+        h.integrate(f, F)                   # host-only plan
