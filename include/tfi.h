@@ -78,7 +78,8 @@ typedef struct {
     int32_t leaf_max;            /* subtrees with at most this many
                                     vertices are integrated densely;
                                     0 = default (32), 1 = only single
-                                    vertices (the plain recursion)         */
+                                    vertices (the plain recursion); at
+                                    most 64                               */
     int32_t device;              /* HIP device ordinal; -1 = host-only
                                     plan (no device upload; for planning
                                     statistics and host-side tests)        */
@@ -160,6 +161,20 @@ int64_t tfi_plan_stats(tfi_handle h, char *json, size_t cap);
  */
 int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
                         size_t cap);
+
+/*
+ * Stage timing. With enable != 0, every later tfi_integrate/tfi_backward
+ * on the handle records a HIP event pair around each stage (on the same
+ * stream as the stage's kernels) and adds the stage's algorithmic bytes
+ * (the bytes the stage must move: inputs read once, outputs written once,
+ * index arrays; independent of caching) to a per-stage tally.
+ * tfi_profile_report waits for the recorded events, writes a JSON object
+ * {"stage": {"launches": n, "ms": total, "bytes": total}, ...} into
+ * json[cap] (truncated to fit), resets the tally and returns the full
+ * length needed, or a negative status.
+ */
+int tfi_profile(tfi_handle h, int enable);
+int64_t tfi_profile_report(tfi_handle h, char *json, size_t cap);
 
 /* Release the handle and all its host and device memory. NULL is a no-op.
  * Work enqueued with the handle must have completed. */

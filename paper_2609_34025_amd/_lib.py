@@ -40,8 +40,8 @@ class BuildOpts(C.Structure):
 _lib = None
 
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
-            "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_destroy",
-            "tfi_last_error"]
+            "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
+            "tfi_profile_report", "tfi_destroy", "tfi_last_error"]
 
 
 def load():
@@ -70,6 +70,10 @@ def load():
     lib.tfi_plan_export.restype = i64
     lib.tfi_destroy.argtypes = [vp]
     lib.tfi_destroy.restype = None
+    lib.tfi_profile.argtypes = [vp, C.c_int]
+    lib.tfi_profile.restype = C.c_int
+    lib.tfi_profile_report.argtypes = [vp, C.c_char_p, C.c_size_t]
+    lib.tfi_profile_report.restype = i64
     lib.tfi_last_error.argtypes = []
     lib.tfi_last_error.restype = C.c_char_p
     _lib = lib

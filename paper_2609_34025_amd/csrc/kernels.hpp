@@ -39,65 +39,115 @@ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
 }
 
 // ------------------------------------------------------------- scatter ----
-// One thread per (A-cell, channel): walks the A-cell's b-cells, each a run
-// of incidences, summing field rows; writes every b-cell sum and the
-// A-cell sum into the value matrix val[(NA + NB) x d] (A-cells first).
-template <typename T>
-__global__ void k_scatter(int64_t NA, int32_t d, const int64_t* __restrict__ a_b_off,
-                          const int64_t* __restrict__ b_inc_off,
-                          const int32_t* __restrict__ inc_v, const T* __restrict__ F,
-                          T* __restrict__ val) {
+// Segmented sums with bounded fan-in. Segment s adds len[s] <= 32 source
+// rows starting at src_beg[s] and writes row dst[s] of the value matrix.
+// Level 0 reads field rows through the incidence vertex list; later levels
+// add partial rows of longer segments (split on the host into pieces), so
+// no thread walks an unbounded run and the summation order is fixed.
+template <typename T, bool INDEXED>
+__global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ seg_src,
+                         const int32_t* __restrict__ seg_len, const int64_t* __restrict__ seg_dst,
+                         const int32_t* __restrict__ idx, const T* __restrict__ src,
+                         T* __restrict__ val) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= NA * d) return;
-    const int64_t a = tid / d;
-    const int32_t c = (int32_t)(tid - a * d);
-    T sa = 0;
-    const int64_t b1 = a_b_off[a + 1];
-    for (int64_t b = a_b_off[a]; b < b1; ++b) {
-        T sb = 0;
-        const int64_t i1 = b_inc_off[b + 1];
-        for (int64_t i = b_inc_off[b]; i < i1; ++i)
-            sb += F[(int64_t)inc_v[i] * d + c];
-        val[(NA + b) * d + c] = sb;
-        sa += sb;
+    if (tid >= nseg * d) return;
+    const int64_t s = tid / d;
+    const int32_t c = (int32_t)(tid - s * d);
+    const int64_t b = seg_src[s];
+    const int32_t n = seg_len[s];
+    T acc = 0;
+#pragma unroll 4
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
+        acc += src[row * d + c];
     }
-    val[a * d + c] = sa;
+    val[seg_dst[s] * d + c] = acc;
 }
 
 // ------------------------------------------------------ direct tables ----
-// One thread per (output cell, channel) of the direct-method jobs. Cell k
-// of the list is table cell dcell[k]; its job's cells are [dbeg, dend).
+// Direct evaluation G(i) = sum_{j in job(i)} f(r_i + r_j + |x_i - x_j|) v(j)
+// for small or sparse tables. A workgroup owns a block of at most
+// kDirOut output cells: either several whole small jobs (sources = the
+// block's own cells) or a slice of one large job (sources = the whole job,
+// streamed through LDS in tiles of kDirTile cells). Channels are processed
+// in chunks of kDirCh. blk[4 b .. 4 b + 3] = (out_beg, out_end, src_beg,
+// src_end) index the direct-cell list (dl_*); dl_jb/dl_je give each cell's
+// job range in the same list.
+constexpr int kDirOut = 64, kDirTile = 256, kDirCh = 16, kDirThreads = 256;
+
 template <typename T>
-__global__ void k_direct(int64_t ncell, int32_t d, const int32_t* __restrict__ dcell,
-                         const int32_t* __restrict__ dbeg, const int32_t* __restrict__ dend,
-                         const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
-                         const int32_t* __restrict__ jc_val, const T* __restrict__ f,
-                         const T* __restrict__ val, T* __restrict__ g) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= ncell * d) return;
-    const int64_t k = tid / d;
-    const int32_t c = (int32_t)(tid - k * d);
-    const int32_t i = dcell[k];
-    const int32_t r = jc_r[i], x = jc_x[i];
-    T s = 0;
-    const int32_t e = dend[k];
-    for (int32_t j = dbeg[k]; j < e; ++j) {
-        const int32_t dx = x - jc_x[j];
-        const int32_t dist = r + jc_r[j] + (dx < 0 ? -dx : dx);
-        s += f[dist] * val[(int64_t)jc_val[j] * d + c];
+__global__ void __launch_bounds__(kDirThreads)
+k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
+         const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
+         const int32_t* __restrict__ dl_jb, const int32_t* __restrict__ dl_je,
+         const T* __restrict__ f, int32_t flds, const T* __restrict__ val,
+         T* __restrict__ g) {
+    __shared__ T sv[kDirTile * kDirCh];
+    __shared__ int32_t sr[kDirTile], sx[kDirTile];
+    extern __shared__ unsigned char dyn_raw[];
+    T* sf = reinterpret_cast<T*>(dyn_raw);
+    const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
+    const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
+    const T* fp = f;
+    if (flds > 0) {
+        for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) sf[k] = f[k];
+        fp = sf;
     }
-    g[(int64_t)jc_val[i] * d + c] = s;
+    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+        const int32_t nch = min(kDirCh, d - c0);
+        const int32_t cpp = kDirThreads / nch;  // output cells per pass
+        const int32_t ci0 = threadIdx.x / nch, c = threadIdx.x - ci0 * nch;
+        const bool lane_ok = ci0 < cpp;
+        T acc[4] = {0, 0, 0, 0};
+        int32_t ri[4], xi[4], jb[4], je[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t i = os + ci0 + q * cpp;
+            const bool ok = lane_ok && i < oe;
+            ri[q] = ok ? dl_r[i] : 0;
+            xi[q] = ok ? dl_x[i] : 0;
+            jb[q] = ok ? dl_jb[i] : 0;
+            je[q] = ok ? dl_je[i] : 0;
+        }
+        for (int32_t ts = ss; ts < se; ts += kDirTile) {
+            const int32_t tn = min(kDirTile, se - ts);
+            __syncthreads();
+            for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
+                sr[k] = dl_r[ts + k];
+                sx[k] = dl_x[ts + k];
+            }
+            for (int32_t e = threadIdx.x; e < tn * nch; e += blockDim.x) {
+                const int32_t k = e / nch, cc = e - k * nch;
+                sv[k * kDirCh + cc] = val[(int64_t)dl_row[ts + k] * d + c0 + cc];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t lo = max(jb[q], ts) - ts, hi = min(je[q], ts + tn) - ts;
+                T a = acc[q];
+                for (int32_t k = lo; k < hi; ++k) {
+                    const int32_t dx = xi[q] - sx[k];
+                    a += fp[ri[q] + sr[k] + (dx < 0 ? -dx : dx)] * sv[k * kDirCh + c];
+                }
+                acc[q] = a;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t i = os + ci0 + q * cpp;
+            if (lane_ok && i < oe) g[(int64_t)dl_row[i] * d + c0 + c] = acc[q];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- gather --
-// One thread per (vertex, channel): sums, over the b-cells holding the
-// vertex, the call's table value at the b-cell's A-cell minus the
-// component correction (if any). Writes every out row.
+// One thread per (vertex, channel): adds, over the calls holding the
+// vertex, the call's table value minus the component correction (row -1
+// when the vertex is on the call's backbone). Writes every out row.
 template <typename T>
-__global__ void k_gather(int64_t N, int32_t d, int64_t NA, const int64_t* __restrict__ v_off,
-                         const int32_t* __restrict__ v_b, const int32_t* __restrict__ b2a,
-                         const int8_t* __restrict__ b_corr, const T* __restrict__ g,
-                         T* __restrict__ out) {
+__global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off,
+                         const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
+                         const T* __restrict__ g, T* __restrict__ out) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= N * d) return;
     const int64_t v = tid / d;
@@ -105,32 +155,62 @@ __global__ void k_gather(int64_t N, int32_t d, int64_t NA, const int64_t* __rest
     T s = 0;
     const int64_t k1 = v_off[v + 1];
     for (int64_t k = v_off[v]; k < k1; ++k) {
-        const int32_t b = v_b[k];
-        s += g[(int64_t)b2a[b] * d + c];
-        if (b_corr[b]) s -= g[(NA + b) * d + c];
+        const int32_t b = gb[k];
+        s += g[(int64_t)ga[k] * d + c];
+        if (b >= 0) s -= g[(int64_t)b * d + c];
     }
     out[v * d + c] = s;
 }
 
 // ----------------------------------------------------------- leaf tiles --
-// One workgroup per leaf tile (a subtree of at most a few dozen vertices):
-// out[v] += sum_w f(D[v, w]) F[w] over the tile.
+// Dense f(D) F on small subtrees. A workgroup owns a group of consecutive
+// tiles with at most kLeafMax vertices in total; the kernel values
+// f(D[i, j]) of every tile and the field rows (kDirCh channels at a time)
+// are staged in LDS, then out[v] += sum_j f(D[v, j]) F[j].
+constexpr int kLeafMax = 64, kLeafThreads = 256;
+
 template <typename T>
-__global__ void k_leaf(int32_t d, const int64_t* __restrict__ leaf_off,
-                       const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
-                       const int32_t* __restrict__ leaf_D, const T* __restrict__ f,
-                       const T* __restrict__ F, T* __restrict__ out) {
-    const int64_t t = blockIdx.x;
-    const int64_t beg = leaf_off[t];
-    const int32_t n = (int32_t)(leaf_off[t + 1] - beg);
-    const int32_t* D = leaf_D + leaf_doff[t];
-    const int32_t* vs = leaf_v + beg;
-    for (int32_t idx = threadIdx.x; idx < n * d; idx += blockDim.x) {
-        const int32_t i = idx / d, c = idx - i * d;
-        T s = 0;
-        for (int32_t j = 0; j < n; ++j)
-            s += f[D[i * n + j]] * F[(int64_t)vs[j] * d + c];
-        out[(int64_t)vs[i] * d + c] += s;
+__global__ void __launch_bounds__(kLeafThreads)
+k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ leaf_off,
+       const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
+       const int32_t* __restrict__ leaf_D, const T* __restrict__ f, const T* __restrict__ F,
+       T* __restrict__ out) {
+    __shared__ T sk[kLeafMax * kLeafMax];
+    __shared__ T sF[kLeafMax * kDirCh];
+    __shared__ int32_t sv[kLeafMax], stile_beg[kLeafMax], stile_n[kLeafMax], skoff[kLeafMax];
+    const int32_t t0 = grp[blockIdx.x], t1 = grp[blockIdx.x + 1];
+    const int64_t vbase = leaf_off[t0];
+    const int32_t nv = (int32_t)(leaf_off[t1] - vbase);
+    const int64_t dbase = leaf_doff[t0];
+    // per-vertex tile bounds and kernel-row offsets
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        const int32_t b = (int32_t)(leaf_off[t] - vbase), n = (int32_t)(leaf_off[t + 1] - leaf_off[t]);
+        const int32_t ko = (int32_t)(leaf_doff[t] - dbase);
+        for (int32_t i = 0; i < n; ++i) {
+            stile_beg[b + i] = b;
+            stile_n[b + i] = n;
+            skoff[b + i] = ko + i * n;
+        }
+    }
+    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) sv[i] = leaf_v[vbase + i];
+    const int32_t nk = (int32_t)(leaf_doff[t1] - dbase);
+    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) sk[k] = f[leaf_D[dbase + k]];
+    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+        const int32_t nch = min(kDirCh, d - c0);
+        __syncthreads();
+        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
+            const int32_t i = e / nch, cc = e - i * nch;
+            sF[i * kDirCh + cc] = F[(int64_t)sv[i] * d + c0 + cc];
+        }
+        __syncthreads();
+        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
+            const int32_t i = e / nch, cc = e - i * nch;
+            const int32_t b = stile_beg[i], n = stile_n[i];
+            const T* krow = sk + skoff[i];
+            T a = 0;
+            for (int32_t j = 0; j < n; ++j) a += krow[j] * sF[(b + j) * kDirCh + cc];
+            out[(int64_t)sv[i] * d + c0 + cc] += a;
+        }
     }
 }
 

@@ -52,6 +52,7 @@ struct Bucket {
     std::vector<int32_t> jobs;  // pairs [cell_beg, cell_end)
     int32_t* d_jobs = nullptr;
     int64_t spec_off = 0;       // element offset into the spectrum arena
+    int64_t cells = 0;          // table cells over the bucket's jobs
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
     int64_t njobs() const { return (int64_t)jobs.size() / 2; }
 };
@@ -75,8 +76,25 @@ struct tfi_plan {
     int64_t *d_b_inc_off = nullptr, *d_a_b_off = nullptr, *d_v_off = nullptr;
     int8_t* d_b_corr = nullptr;
     int32_t *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
-    int32_t *d_dcell = nullptr, *d_dbeg = nullptr, *d_dend = nullptr;
-    int64_t ndirect = 0;
+    // direct tables: cell list in job order, blocks of output cells
+    int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
+    int32_t *d_dl_jb = nullptr, *d_dl_je = nullptr, *d_dblk = nullptr;
+    int64_t ndirect = 0, ndblk = 0;
+    // scatter: levels of bounded segment sums
+    struct SegLevel {
+        bool indexed = false;
+        int64_t n = 0;
+        int64_t* d_src = nullptr;
+        int32_t* d_len = nullptr;
+        int64_t* d_dst = nullptr;
+        int64_t rows_read = 0;
+    };
+    std::vector<SegLevel> seg_levels;
+    int64_t val_rows = 0;  // A-cells, b-cells, then partial rows
+    // gather rows and leaf groups
+    int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr;
+    int64_t nlgrp = 0;
+    int64_t gather_reads = 0;  // table values read by the gather
     int64_t *d_leaf_off = nullptr, *d_leaf_doff = nullptr;
     int32_t *d_leaf_v = nullptr, *d_leaf_D = nullptr;
     std::vector<Bucket> buckets;
@@ -87,11 +105,56 @@ struct tfi_plan {
     // per-dtype scratch (grow-only)
     DeviceBuf val[2], g[2], spec[2], fftbuf[2], ftab[2];
 
+    // stage profiling: event pairs recorded on the launch stream
+    struct Tally {
+        int64_t launches = 0;
+        double ms = 0, bytes = 0;
+    };
+    struct Pending {
+        std::string stage;
+        hipEvent_t e0, e1;
+        double bytes;
+    };
+    bool prof = false;
+    std::map<std::string, Tally> tally;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+
+    hipEvent_t take_event() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    hipEvent_t begin(hipStream_t st) {
+        if (!prof) return nullptr;
+        hipEvent_t e = take_event();
+        if (e) (void)hipEventRecord(e, st);
+        return e;
+    }
+    void end(hipStream_t st, hipEvent_t e0, const char* stage, double bytes) {
+        if (!prof || !e0) return;
+        hipEvent_t e1 = take_event();
+        if (!e1) return;
+        (void)hipEventRecord(e1, st);
+        pending.push_back({stage, e0, e1, bytes});
+    }
+
     ~tfi_plan() {
         if (device >= 0) {
             int prev = 0;
             if (hipGetDevice(&prev) == hipSuccess) {
                 (void)hipSetDevice(device);
+                for (auto& q : pending) {
+                    (void)hipEventSynchronize(q.e1);
+                    pool.push_back(q.e0);
+                    pool.push_back(q.e1);
+                }
+                for (hipEvent_t e : pool) (void)hipEventDestroy(e);
                 for (void* p : allocs) (void)hipFree(p);
                 for (int t = 0; t < 2; ++t)
                     for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &ftab[t]})
@@ -174,18 +237,21 @@ int upload_plan(tfi_plan* h) {
     if ((rc = h->upload(&h->d_leaf_doff, p.leaf_doff))) return rc;
     if ((rc = h->upload(&h->d_leaf_D, p.leaf_D))) return rc;
 
-    // direct-method output cells with their job ranges
-    std::vector<int32_t> dcell, dbeg, dend;
+    // direct-method cells in job order, with each cell's job range
+    std::vector<int32_t> dl_r, dl_x, dl_row, dl_jb, dl_je, dblk;
     std::map<std::pair<int, int>, size_t> bidx;
     const int64_t J = (int64_t)p.job_H.size();
     int maxlg = 1;
     for (int64_t j = 0; j < J; ++j) {
         const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
         if (p.job_method[j] == tfi::METHOD_DIRECT) {
+            const int32_t jb = (int32_t)dl_r.size(), je = jb + (ce - cb);
             for (int32_t i = cb; i < ce; ++i) {
-                dcell.push_back(i);
-                dbeg.push_back(cb);
-                dend.push_back(ce);
+                dl_r.push_back(p.jc_r[i]);
+                dl_x.push_back(p.jc_x[i]);
+                dl_row.push_back(p.jc_val[i]);
+                dl_jb.push_back(jb);
+                dl_je.push_back(je);
             }
         } else {
             auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
@@ -202,13 +268,132 @@ int upload_plan(tfi_plan* h) {
             b.xmax = std::max(b.xmax, p.job_X[j]);
             b.jobs.push_back(cb);
             b.jobs.push_back(ce);
+            b.cells += ce - cb;
             maxlg = std::max(maxlg, std::max(b.lg1, b.lg2));
         }
     }
-    h->ndirect = (int64_t)dcell.size();
-    if ((rc = h->upload(&h->d_dcell, dcell))) return rc;
-    if ((rc = h->upload(&h->d_dbeg, dbeg))) return rc;
-    if ((rc = h->upload(&h->d_dend, dend))) return rc;
+    // blocks: whole small jobs packed up to kDirOut cells, or slices of
+    // kDirOut output cells of one large job with the whole job as sources
+    {
+        const int32_t nd = (int32_t)dl_r.size();
+        int32_t i = 0;
+        while (i < nd) {
+            const int32_t jb = dl_jb[i], je = dl_je[i];
+            if (je - jb > tfi::kDirOut) {
+                for (int32_t o = jb; o < je; o += tfi::kDirOut)
+                    dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
+                i = je;
+                continue;
+            }
+            int32_t e = je;
+            while (e < nd && dl_je[e] - dl_jb[e] <= tfi::kDirOut &&
+                   dl_je[e] - i <= tfi::kDirOut)
+                e = dl_je[e];
+            dblk.insert(dblk.end(), {i, e, i, e});
+            i = e;
+        }
+    }
+    h->ndirect = (int64_t)dl_r.size();
+    h->ndblk = (int64_t)dblk.size() / 4;
+    if ((rc = h->upload(&h->d_dl_r, dl_r))) return rc;
+    if ((rc = h->upload(&h->d_dl_x, dl_x))) return rc;
+    if ((rc = h->upload(&h->d_dl_row, dl_row))) return rc;
+    if ((rc = h->upload(&h->d_dl_jb, dl_jb))) return rc;
+    if ((rc = h->upload(&h->d_dl_je, dl_je))) return rc;
+    if ((rc = h->upload(&h->d_dblk, dblk))) return rc;
+
+    // scatter levels: every b-cell and A-cell is a run of incidences; runs
+    // longer than kSeg are cut into pieces summed into partial rows, which
+    // the next level adds up (again in pieces of at most kSeg)
+    {
+        constexpr int64_t kSeg = 32;
+        struct Seg { int64_t beg, end, dst; };
+        std::vector<Seg> cur;
+        cur.reserve(p.NA + p.NB);
+        for (int64_t b = 0; b < p.NB; ++b)
+            cur.push_back({p.b_inc_off[b], p.b_inc_off[b + 1], p.NA + b});
+        for (int64_t a = 0; a < p.NA; ++a)
+            cur.push_back({p.b_inc_off[p.a_b_off[a]], p.b_inc_off[p.a_b_off[a + 1]], a});
+        int64_t next_row = p.NA + p.NB;
+        bool indexed = true;
+        while (!cur.empty()) {
+            std::vector<Seg> next;
+            std::vector<std::pair<int64_t, int64_t>> order;  // (len, idx)
+            std::vector<int64_t> src, dst;
+            std::vector<int32_t> len;
+            for (const Seg& sg : cur) {
+                const int64_t n = sg.end - sg.beg;
+                if (n <= kSeg) {
+                    src.push_back(sg.beg);
+                    len.push_back((int32_t)n);
+                    dst.push_back(sg.dst);
+                    continue;
+                }
+                const int64_t np = (n + kSeg - 1) / kSeg, r0 = next_row;
+                next_row += np;
+                for (int64_t q = 0; q < np; ++q) {
+                    src.push_back(sg.beg + q * kSeg);
+                    len.push_back((int32_t)std::min(kSeg, n - q * kSeg));
+                    dst.push_back(r0 + q);
+                }
+                next.push_back({r0, r0 + np, sg.dst});
+            }
+            // longest segments first so that a wavefront's lanes finish
+            // together (the order does not change any sum)
+            std::vector<int64_t> perm(src.size());
+            for (size_t k = 0; k < perm.size(); ++k) perm[k] = (int64_t)k;
+            std::stable_sort(perm.begin(), perm.end(),
+                             [&](int64_t a, int64_t b) { return len[a] > len[b]; });
+            std::vector<int64_t> s2(src.size()), d2(src.size());
+            std::vector<int32_t> l2(src.size());
+            int64_t rows = 0;
+            for (size_t k = 0; k < perm.size(); ++k) {
+                s2[k] = src[perm[k]];
+                l2[k] = len[perm[k]];
+                d2[k] = dst[perm[k]];
+                rows += l2[k];
+            }
+            tfi_plan::SegLevel L;
+            L.indexed = indexed;
+            L.n = (int64_t)s2.size();
+            L.rows_read = rows;
+            if ((rc = h->upload(&L.d_src, s2))) return rc;
+            if ((rc = h->upload(&L.d_len, l2))) return rc;
+            if ((rc = h->upload(&L.d_dst, d2))) return rc;
+            h->seg_levels.push_back(L);
+            cur.swap(next);
+            indexed = false;
+        }
+        h->val_rows = next_row;
+    }
+
+    // gather: table row and correction row (or -1) per vertex incidence
+    {
+        std::vector<int32_t> ga(p.v_b.size()), gb(p.v_b.size());
+        h->gather_reads = 0;
+        for (size_t k = 0; k < p.v_b.size(); ++k) {
+            const int32_t b = p.v_b[k];
+            ga[k] = p.b2a[b];
+            gb[k] = p.b_corr[b] ? (int32_t)(p.NA + b) : -1;
+            h->gather_reads += 1 + (p.b_corr[b] ? 1 : 0);
+        }
+        if ((rc = h->upload(&h->d_ga, ga))) return rc;
+        if ((rc = h->upload(&h->d_gb, gb))) return rc;
+    }
+    // leaf groups: consecutive tiles with at most kLeafMax vertices
+    {
+        std::vector<int32_t> grp{0};
+        const int64_t nt = (int64_t)p.leaf_off.size() - 1;
+        int64_t t = 0;
+        while (t < nt) {
+            int64_t e = t + 1;
+            while (e < nt && p.leaf_off[e + 1] - p.leaf_off[t] <= tfi::kLeafMax) ++e;
+            grp.push_back((int32_t)e);
+            t = e;
+        }
+        h->nlgrp = (int64_t)grp.size() - 1;
+        if ((rc = h->upload(&h->d_lgrp, grp))) return rc;
+    }
     h->spec_elems = 0;
     for (Bucket& b : h->buckets) {
         if ((rc = h->upload(&b.d_jobs, b.jobs))) return rc;
@@ -245,9 +430,10 @@ template <typename T>
 int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    const int64_t rows = p.NA + p.NB;
+    const int64_t rows = p.NA + p.NB;  // table-value rows
     int rc;
-    if ((rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(rows, 1) * d * sizeof(T)))) return rc;
+    if ((rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
+        return rc;
     if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(rows, 1) * d * sizeof(T)))) return rc;
     if ((rc = h->ensure(h->spec[ti],
                         (size_t)std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>))))
@@ -270,8 +456,13 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     }
     if (want && (rc = h->ensure(h->fftbuf[ti], want))) return rc;
 
+    const double sz = (double)sizeof(T);
+    const int64_t I = (int64_t)p.inc_v.size();
     // 1. kernel spectra per bucket
+    hipEvent_t ev = h->begin(st);
+    double spec_bytes = 0;
     for (const Bucket& b : h->buckets) {
+        spec_bytes += 2.0 * sz * (double)b.P() + sz * (2.0 * b.hmax + b.xmax + 1);
         if (b.P() <= ldsc) {
             hipLaunchKernelGGL(tfi::k_spectrum_lds<T>, dim3(1), dim3(kThreads),
                                (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1, b.lg2, b.hmax,
@@ -291,24 +482,45 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
                                    (int64_t)1 << b.lg2, tw, h->lgtw);
         }
     }
-    // 2. scatter
-    if (p.NA > 0)
-        hipLaunchKernelGGL(tfi::k_scatter<T>, dim3(blocks_for(p.NA * d)), dim3(kThreads), 0, st,
-                           p.NA, d, h->d_a_b_off, h->d_b_inc_off, h->d_inc_v, F, val);
+    if (!h->buckets.empty()) h->end(st, ev, "spectrum", spec_bytes);
+    // 2. scatter: levels of bounded segment sums
+    for (size_t l = 0; l < h->seg_levels.size(); ++l) {
+        const tfi_plan::SegLevel& L = h->seg_levels[l];
+        ev = h->begin(st);
+        if (L.indexed)
+            hipLaunchKernelGGL((tfi::k_segsum<T, true>), dim3(blocks_for(L.n * d)), dim3(kThreads),
+                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, F, val);
+        else
+            hipLaunchKernelGGL((tfi::k_segsum<T, false>), dim3(blocks_for(L.n * d)),
+                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
+                               (const int32_t*)nullptr, (const T*)val, val);
+        h->end(st, ev, l == 0 ? "scatter" : "scatter_tail",
+               sz * d * (double)(L.rows_read + L.n) + (L.indexed ? 4.0 * L.rows_read : 0.0) +
+                   20.0 * L.n);
+    }
     // 3. direct tables
-    if (h->ndirect > 0)
-        hipLaunchKernelGGL(tfi::k_direct<T>, dim3(blocks_for(h->ndirect * d)), dim3(kThreads), 0,
-                           st, h->ndirect, d, h->d_dcell, h->d_dbeg, h->d_dend, h->d_jc_r,
-                           h->d_jc_x, h->d_jc_val, f, val, g);
+    if (h->ndblk > 0) {
+        ev = h->begin(st);
+        const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
+        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                           (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
+                           h->d_dl_row, h->d_dl_jb, h->d_dl_je, f, flds, val, g);
+        h->end(st, ev, "direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
+    }
     // 4. FFT tables
     for (const Bucket& b : h->buckets) {
+        const int64_t cells = b.cells;
+        const double fft_bytes = 2.0 * sz * d * (double)cells + 12.0 * cells + 2.0 * sz * b.P();
         if (b.P() <= ldsc) {
+            ev = h->begin(st);
             hipLaunchKernelGGL(tfi::k_fft_conv_lds<T>, dim3((unsigned)b.njobs(), npairs),
                                dim3(kThreads), (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1,
                                b.lg2, b.d_jobs, h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g,
                                spec + b.spec_off, tw, h->lgtw);
+            h->end(st, ev, "fft_lds", fft_bytes);
             continue;
         }
+        ev = h->begin(st);
         tfi::cpx<T>* buf = (tfi::cpx<T>*)h->fftbuf[ti].p;
         const int64_t slots_cap = std::min<int64_t>(
             65535, (int64_t)(h->fftbuf[ti].bytes / sizeof(tfi::cpx<T>)) / b.P());
@@ -345,15 +557,23 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
                                dim3(kThreads), 0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs,
                                h->d_jc_r, h->d_jc_x, h->d_jc_val, d, buf, g);
         }
+        h->end(st, ev, "fft_global", fft_bytes);
     }
     // 5. gather (writes every row of out)
+    ev = h->begin(st);
     hipLaunchKernelGGL(tfi::k_gather<T>, dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st, p.N, d,
-                       p.NA, h->d_v_off, h->d_v_b, h->d_b2a, h->d_b_corr, g, out);
+                       h->d_v_off, h->d_ga, h->d_gb, g, out);
+    h->end(st, ev, "gather",
+           sz * d * (double)(h->gather_reads + p.N) + 8.0 * (double)p.v_b.size() + 8.0 * p.N);
     // 6. leaf tiles add their dense values
-    const int64_t nleaf = (int64_t)p.leaf_off.size() - 1;
-    if (nleaf > 0)
-        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)nleaf), dim3(128), 0, st, d,
-                           h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff, h->d_leaf_D, f, F, out);
+    if (h->nlgrp > 0) {
+        ev = h->begin(st);
+        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st,
+                           d, h->d_lgrp, h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff, h->d_leaf_D,
+                           f, F, out);
+        const double nv = (double)p.leaf_v.size();
+        h->end(st, ev, "leaf", 3.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+    }
     TFI_HIP(hipGetLastError());
     return TFI_OK;
 }
@@ -373,6 +593,9 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     tfi::PlanOptions po;
     po.policy = o.policy;
     po.leaf_max = o.leaf_max == 0 ? 32 : o.leaf_max;
+    if (po.leaf_max < 1 || po.leaf_max > tfi::kLeafMax)
+        return fail(TFI_ERR_ARG, "tfi_build: leaf_max must be in [0, " +
+                                     std::to_string(tfi::kLeafMax) + "]");
     po.table_method = o.table_method;
     if (o.device < -1) return fail(TFI_ERR_ARG, "tfi_build: device must be >= -1");
     std::unique_ptr<tfi_plan> h;
@@ -488,6 +711,49 @@ int64_t tfi_plan_export(tfi_handle h, const char* name, void* buf, size_t cap) {
     else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
     if (buf && cap >= bytes && bytes) std::memcpy(buf, src, bytes);
     return (int64_t)bytes;
+}
+
+int tfi_profile(tfi_handle h, int enable) {
+    g_err.clear();
+    if (!h) return fail(TFI_ERR_ARG, "tfi_profile: null handle");
+    h->prof = enable != 0;
+    return TFI_OK;
+}
+
+int64_t tfi_profile_report(tfi_handle h, char* json, size_t cap) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    for (auto& q : h->pending) {
+        TFI_HIP(hipEventSynchronize(q.e1));
+        float ms = 0;
+        TFI_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
+        auto& t = h->tally[q.stage];
+        t.launches++;
+        t.ms += ms;
+        t.bytes += q.bytes;
+        h->pool.push_back(q.e0);
+        h->pool.push_back(q.e1);
+    }
+    h->pending.clear();
+    std::string s = "{";
+    bool first = true;
+    char buf[256];
+    for (auto& kv : h->tally) {
+        std::snprintf(buf, sizeof(buf), "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"bytes\":%.1f}",
+                      first ? "" : ",", kv.first.c_str(), (long long)kv.second.launches,
+                      kv.second.ms, kv.second.bytes);
+        s += buf;
+        first = false;
+    }
+    s += "}";
+    h->tally.clear();
+    if (json && cap > 0) {
+        size_t n = std::min(cap - 1, s.size());
+        std::memcpy(json, s.data(), n);
+        json[n] = 0;
+    }
+    return (int64_t)s.size();
 }
 
 void tfi_destroy(tfi_handle h) { delete h; }

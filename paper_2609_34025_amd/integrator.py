@@ -65,6 +65,20 @@ class TreeIntegrator:
             _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, nbytes))
         return arr
 
+    def profile(self, enable=True):
+        """Record per-stage HIP events and algorithmic bytes from now on."""
+        _lib.check(_lib.load().tfi_profile(self._h, 1 if enable else 0))
+
+    def profile_report(self):
+        """Per-stage {launches, ms, bytes} since the last report (waits for
+        the recorded events)."""
+        lib = _lib.load()
+        buf = C.create_string_buffer(1 << 16)
+        n = _lib.check(lib.tfi_profile_report(self._h, buf, len(buf)))
+        if n >= len(buf):
+            raise RuntimeError("profile report truncated")
+        return json.loads(buf.value.decode())
+
     # ---------------------------------------------------------- compute --
     def _check(self, f, *mats):
         if self.device is None:
