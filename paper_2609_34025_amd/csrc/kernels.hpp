@@ -430,3 +430,282 @@ __global__ void k_zero(T* __restrict__ p, int64_t n) {
 }
 
 }  // namespace tfi
+
+namespace tfi {
+
+// =================================================== kernel-table gradient ==
+// For L = sum(gout * out), dL/df[k] = sum over pairs (v, w) at distance k
+// of <gout[v], F[w]>. Through the decomposition, each table job adds
+// sign * sum_{i, j} [r_i + r_j + |x_i - x_j| = k] <gbar_i, val_j>, where
+// gbar and val are the same cell sums applied to gout and F (call jobs
+// sign +1 on A-cell rows < NA, corrections sign -1 on b-cell rows), and
+// every leaf tile adds its own dense pair histogram. Histograms accumulate
+// in FP64 (LDS bins flushed with FP64 atomics): df is reproducible to FP64
+// rounding, not bitwise.
+constexpr int kDfTile = 64, kDfThreads = 256, kDfHistLds = 4096;
+
+template <typename T>
+__device__ __forceinline__ void hist_add(double* lh, double* gh, int32_t k, double v) {
+    if (lh) atomicAdd(lh + k, v);
+    else atomicAdd(gh + k, v);
+}
+
+// Direct jobs: same blocks as k_direct. Pair dot products are formed over
+// channel chunks in registers (16 pairs per thread), then binned by
+// surrogate distance.
+template <typename T>
+__global__ void __launch_bounds__(kDfThreads)
+k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
+            const int32_t* __restrict__ dl_r, const int32_t* __restrict__ dl_x,
+            const int32_t* __restrict__ dl_row, const int32_t* __restrict__ dl_jb,
+            const int32_t* __restrict__ dl_je, const T* __restrict__ val,
+            const T* __restrict__ valg, int32_t K, double* __restrict__ df) {
+    __shared__ T sG[kDfTile * (kDirCh + 1)], sV[kDfTile * (kDirCh + 1)];
+    __shared__ int32_t sr[kDfTile], sx[kDfTile];
+    __shared__ double lh[kDfHistLds];
+    const bool use_lds = K <= kDfHistLds;
+    double* lhp = use_lds ? lh : nullptr;
+    if (use_lds)
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
+    const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
+    const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
+    const int32_t ii = threadIdx.x & (kDfTile - 1), jj0 = threadIdx.x >> 6;
+    const int32_t i = os + ii;
+    const bool iok = i < oe;
+    const int32_t ri = iok ? dl_r[i] : 0, xi = iok ? dl_x[i] : 0;
+    const int32_t jb = iok ? dl_jb[i] : 0, je = iok ? dl_je[i] : 0;
+    const double sign = (iok && dl_row[i] < NA) ? 1.0 : -1.0;
+    for (int32_t ts = ss; ts < se; ts += kDfTile) {
+        const int32_t tn = min(kDfTile, se - ts);
+        T m[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) m[q] = 0;
+        for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+            const int32_t nch = min(kDirCh, d - c0);
+            __syncthreads();
+            for (int32_t e = threadIdx.x; e < kDfTile * nch; e += blockDim.x) {
+                const int32_t k = e / nch, cc = e - k * nch;
+                sG[k * (kDirCh + 1) + cc] =
+                    (os + k < oe) ? valg[(int64_t)dl_row[os + k] * d + c0 + cc] : (T)0;
+                sV[k * (kDirCh + 1) + cc] =
+                    (k < tn) ? val[(int64_t)dl_row[ts + k] * d + c0 + cc] : (T)0;
+            }
+            if (c0 == 0)
+                for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
+                    sr[k] = dl_r[ts + k];
+                    sx[k] = dl_x[ts + k];
+                }
+            __syncthreads();
+            for (int32_t cc = 0; cc < nch; ++cc) {
+                const T gv = sG[ii * (kDirCh + 1) + cc];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) m[q] += gv * sV[(jj0 + 4 * q) * (kDirCh + 1) + cc];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int32_t j = ts + jj0 + 4 * q;
+            if (iok && j >= jb && j < je && jj0 + 4 * q < tn) {
+                const int32_t dx = xi - sx[jj0 + 4 * q];
+                hist_add<T>(lhp, df, ri + sr[jj0 + 4 * q] + (dx < 0 ? -dx : dx),
+                            sign * (double)m[q]);
+            }
+        }
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
+            if (lh[k] != 0.0) atomicAdd(df + k, lh[k]);
+    }
+}
+
+// Leaf tiles: pairs inside each tile of a group, distance from D.
+template <typename T>
+__global__ void __launch_bounds__(kLeafThreads)
+k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ leaf_off,
+          const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
+          const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
+          const T* __restrict__ gout, int32_t K, double* __restrict__ df) {
+    __shared__ T sG[kLeafMax * (kDirCh + 1)], sF[kLeafMax * (kDirCh + 1)];
+    __shared__ int32_t sv[kLeafMax], stile_beg[kLeafMax], stile_n[kLeafMax], skoff[kLeafMax];
+    __shared__ double lh[kDfHistLds];
+    const bool use_lds = K <= kDfHistLds;
+    double* lhp = use_lds ? lh : nullptr;
+    if (use_lds)
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
+    const int32_t t0 = grp[blockIdx.x], t1 = grp[blockIdx.x + 1];
+    const int64_t vbase = leaf_off[t0];
+    const int32_t nv = (int32_t)(leaf_off[t1] - vbase);
+    const int64_t dbase = leaf_doff[t0];
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        const int32_t b = (int32_t)(leaf_off[t] - vbase), n = (int32_t)(leaf_off[t + 1] - leaf_off[t]);
+        const int32_t ko = (int32_t)(leaf_doff[t] - dbase);
+        for (int32_t i = 0; i < n; ++i) {
+            stile_beg[b + i] = b;
+            stile_n[b + i] = n;
+            skoff[b + i] = ko + i * n;
+        }
+    }
+    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) sv[i] = leaf_v[vbase + i];
+    // thread -> (vertex i, sources j = jj0 + 4 q), 16 pairs per thread
+    const int32_t ii = threadIdx.x & (kLeafMax - 1), jj0 = threadIdx.x >> 6;
+    T m[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) m[q] = 0;
+    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+        const int32_t nch = min(kDirCh, d - c0);
+        __syncthreads();
+        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
+            const int32_t k = e / nch, cc = e - k * nch;
+            sG[k * (kDirCh + 1) + cc] = gout[(int64_t)sv[k] * d + c0 + cc];
+            sF[k * (kDirCh + 1) + cc] = F[(int64_t)sv[k] * d + c0 + cc];
+        }
+        __syncthreads();
+        if (ii < nv) {
+            const int32_t b = stile_beg[ii], n = stile_n[ii];
+            for (int32_t cc = 0; cc < nch; ++cc) {
+                const T gv = sG[ii * (kDirCh + 1) + cc];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int32_t j = jj0 + 4 * q;
+                    if (j < n) m[q] += gv * sF[(b + j) * (kDirCh + 1) + cc];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (ii < nv) {
+        const int32_t n = stile_n[ii];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int32_t j = jj0 + 4 * q;
+            if (j < n) hist_add<T>(lhp, df, leaf_D[dbase + skoff[ii] + j], (double)m[q]);
+        }
+    }
+    if (use_lds) {
+        __syncthreads();
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
+            if (lh[k] != 0.0) atomicAdd(df + k, lh[k]);
+    }
+}
+
+// FFT jobs held in LDS: per channel pair, the forward transforms of the
+// gout table (at output positions) and of the field table (at source
+// positions); the products Zg * conj(Zv) are summed over channel pairs,
+// one inverse transform gives the channel-summed cross-correlation
+// Z[a][b] with a = q + r, b = s - x (mod L2), folded into df[a + |b|].
+// Three LDS tables per workgroup; one workgroup per job.
+template <typename T>
+__global__ void k_df_fft_lds(int lg1, int lg2, int64_t NA, const int32_t* __restrict__ jobs,
+                             const int32_t* __restrict__ job_hx,
+                             const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                             const int32_t* __restrict__ jc_val, int32_t d,
+                             const T* __restrict__ val, const T* __restrict__ valg,
+                             const cpx<T>* __restrict__ tw, int lgtw, double* __restrict__ df) {
+    extern __shared__ unsigned char smem_raw[];
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    cpx<T>* zv = reinterpret_cast<cpx<T>*>(smem_raw);
+    cpx<T>* zg = zv + P;
+    cpx<T>* acc = zg + P;
+    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
+    const int32_t H = job_hx[2 * blockIdx.x], X = job_hx[2 * blockIdx.x + 1];
+    const double sign = jc_val[cb] < NA ? 1.0 : -1.0;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = {(T)0, (T)0};
+    const int32_t npairs = (d + 1) / 2;
+    for (int32_t pr = 0; pr < npairs; ++pr) {
+        const int32_t c0 = 2 * pr, c1 = c0 + 1;
+        const bool has1 = c1 < d;
+        for (int p = threadIdx.x; p < P; p += blockDim.x) {
+            zv[p] = {(T)0, (T)0};
+            zg[p] = {(T)0, (T)0};
+        }
+        __syncthreads();
+        for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
+            const int64_t vr = (int64_t)jc_val[k] * d;
+            const int row = (L1 - jc_r[k]) & (L1 - 1);
+            zv[(row << lg2) + jc_x[k]] = {val[vr + c0], has1 ? val[vr + c1] : (T)0};
+            zg[(jc_r[k] << lg2) + jc_x[k]] = {valg[vr + c0], has1 ? valg[vr + c1] : (T)0};
+        }
+        __syncthreads();
+        fft_axis_lds<T, false>(zv, lg2, L1, 1, L2, tw, lgtw);
+        fft_axis_lds<T, false>(zv, lg1, L2, L2, 1, tw, lgtw);
+        fft_axis_lds<T, false>(zg, lg2, L1, 1, L2, tw, lgtw);
+        fft_axis_lds<T, false>(zg, lg1, L2, L2, 1, tw, lgtw);
+        for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = cadd(acc[p], cmulc(zg[p], zv[p]));
+        __syncthreads();
+    }
+    fft_axis_lds<T, true>(acc, lg1, L2, L2, 1, tw, lgtw);
+    fft_axis_lds<T, true>(acc, lg2, L1, 1, L2, tw, lgtw);
+    const double scale = sign / (double)P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        const int a = p >> lg2, b = p & (L2 - 1);
+        const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
+        if (a <= 2 * H && bs <= X) {
+            const double v = (double)acc[p].x * scale;
+            if (v != 0.0) atomicAdd(df + a + bs, v);
+        }
+    }
+}
+
+// Global-memory variant for tables beyond LDS: fills of the two tables per
+// (job, channel pair) slot, the pair-summed product per job, and the fold.
+template <typename T>
+__global__ void k_fill2_global(int lg1, int lg2, int32_t npairs, const int32_t* __restrict__ jobs,
+                               const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                               const int32_t* __restrict__ jc_val, int32_t d,
+                               const T* __restrict__ val, const T* __restrict__ valg,
+                               cpx<T>* __restrict__ bv, cpx<T>* __restrict__ bg) {
+    const int64_t P = (int64_t)1 << (lg1 + lg2);
+    const int64_t slot = blockIdx.y;
+    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
+    const int32_t c0 = 2 * pair, c1 = c0 + 1;
+    const int64_t L1 = (int64_t)1 << lg1;
+    cpx<T>* zv = bv + slot * P;
+    cpx<T>* zg = bg + slot * P;
+    const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
+    for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
+         k += gridDim.x * blockDim.x) {
+        const int64_t vr = (int64_t)jc_val[k] * d;
+        const int64_t row = (L1 - jc_r[k]) & (L1 - 1);
+        zv[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
+        zg[((int64_t)jc_r[k] << lg2) + jc_x[k]] = {valg[vr + c0], c1 < d ? valg[vr + c1] : (T)0};
+    }
+}
+
+template <typename T>
+__global__ void k_corr_accum_global(int64_t njobs, int32_t npairs, int lgP,
+                                    const cpx<T>* __restrict__ bv, const cpx<T>* __restrict__ bg,
+                                    cpx<T>* __restrict__ acc) {
+    const int64_t P = (int64_t)1 << lgP;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= njobs * P) return;
+    const int64_t job = tid >> lgP, p = tid & (P - 1);
+    cpx<T> s = {(T)0, (T)0};
+    for (int32_t pr = 0; pr < npairs; ++pr) {
+        const int64_t o = (job * npairs + pr) * P + p;
+        s = cadd(s, cmulc(bg[o], bv[o]));
+    }
+    acc[tid] = s;
+}
+
+template <typename T>
+__global__ void k_fold_global(int64_t njobs, int lg1, int lg2, int64_t NA,
+                              const int32_t* __restrict__ jobs, const int32_t* __restrict__ job_hx,
+                              const int32_t* __restrict__ jc_val, const cpx<T>* __restrict__ acc,
+                              double* __restrict__ df) {
+    const int64_t P = (int64_t)1 << (lg1 + lg2);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= njobs * P) return;
+    const int64_t job = tid / P, p = tid - job * P;
+    const int64_t L2 = (int64_t)1 << lg2;
+    const int64_t a = p >> lg2, b = p & (L2 - 1);
+    const int64_t bs = (b <= (L2 >> 1)) ? b : L2 - b;
+    const int32_t H = job_hx[2 * job], X = job_hx[2 * job + 1];
+    if (a <= 2 * (int64_t)H && bs <= X) {
+        const double sign = jc_val[jobs[2 * job]] < NA ? 1.0 : -1.0;
+        const double v = sign * (double)acc[tid].x / (double)P;
+        if (v != 0.0) atomicAdd(df + a + bs, v);
+    }
+}
+
+}  // namespace tfi

@@ -50,7 +50,9 @@ struct Bucket {
     int lg1 = 0, lg2 = 0;
     int32_t hmax = 0, xmax = 0;
     std::vector<int32_t> jobs;  // pairs [cell_beg, cell_end)
+    std::vector<int32_t> hx;    // pairs (H, X) per job
     int32_t* d_jobs = nullptr;
+    int32_t* d_hx = nullptr;
     int64_t spec_off = 0;       // element offset into the spectrum arena
     int64_t cells = 0;          // table cells over the bucket's jobs
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
@@ -103,7 +105,8 @@ struct tfi_plan {
     void* d_tw[2] = {nullptr, nullptr};  // float / double twiddles
 
     // per-dtype scratch (grow-only)
-    DeviceBuf val[2], g[2], spec[2], fftbuf[2], ftab[2];
+    DeviceBuf val[2], g[2], spec[2], fftbuf[2], ftab[2], valg[2], dfbuf[2];
+    int64_t lds_max = 65536;  // bytes of LDS a workgroup may use
 
     // stage profiling: event pairs recorded on the launch stream
     struct Tally {
@@ -157,7 +160,8 @@ struct tfi_plan {
                 for (hipEvent_t e : pool) (void)hipEventDestroy(e);
                 for (void* p : allocs) (void)hipFree(p);
                 for (int t = 0; t < 2; ++t)
-                    for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &ftab[t]})
+                    for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &ftab[t],
+                                         &valg[t], &dfbuf[t]})
                         if (b->p) (void)hipFree(b->p);
                 (void)hipSetDevice(prev);
             }
@@ -268,6 +272,8 @@ int upload_plan(tfi_plan* h) {
             b.xmax = std::max(b.xmax, p.job_X[j]);
             b.jobs.push_back(cb);
             b.jobs.push_back(ce);
+            b.hx.push_back(p.job_H[j]);
+            b.hx.push_back(p.job_X[j]);
             b.cells += ce - cb;
             maxlg = std::max(maxlg, std::max(b.lg1, b.lg2));
         }
@@ -397,6 +403,7 @@ int upload_plan(tfi_plan* h) {
     h->spec_elems = 0;
     for (Bucket& b : h->buckets) {
         if ((rc = h->upload(&b.d_jobs, b.jobs))) return rc;
+        if ((rc = h->upload(&b.d_hx, b.hx))) return rc;
         b.spec_off = h->spec_elems;
         h->spec_elems += b.P();
     }
@@ -423,6 +430,27 @@ int upload_plan(tfi_plan* h) {
 template <typename T>
 int64_t lds_cells() {
     return kLdsBytes / (int64_t)sizeof(tfi::cpx<T>);
+}
+
+// Cell sums of the rows of `src` ([N x d]) into val: A-cells, b-cells and
+// the partial rows of long runs.
+template <typename T>
+void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st) {
+    const double sz = (double)sizeof(T);
+    for (size_t l = 0; l < h->seg_levels.size(); ++l) {
+        const tfi_plan::SegLevel& L = h->seg_levels[l];
+        hipEvent_t ev = h->begin(st);
+        if (L.indexed)
+            hipLaunchKernelGGL((tfi::k_segsum<T, true>), dim3(blocks_for(L.n * d)), dim3(kThreads),
+                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
+        else
+            hipLaunchKernelGGL((tfi::k_segsum<T, false>), dim3(blocks_for(L.n * d)),
+                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
+                               (const int32_t*)nullptr, (const T*)val, val);
+        h->end(st, ev, l == 0 ? "scatter" : "scatter_tail",
+               sz * d * (double)(L.rows_read + L.n) + (L.indexed ? 4.0 * L.rows_read : 0.0) +
+                   20.0 * L.n);
+    }
 }
 
 // Forward integration out = f(D) F on `stream`.
@@ -484,20 +512,7 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     }
     if (!h->buckets.empty()) h->end(st, ev, "spectrum", spec_bytes);
     // 2. scatter: levels of bounded segment sums
-    for (size_t l = 0; l < h->seg_levels.size(); ++l) {
-        const tfi_plan::SegLevel& L = h->seg_levels[l];
-        ev = h->begin(st);
-        if (L.indexed)
-            hipLaunchKernelGGL((tfi::k_segsum<T, true>), dim3(blocks_for(L.n * d)), dim3(kThreads),
-                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, F, val);
-        else
-            hipLaunchKernelGGL((tfi::k_segsum<T, false>), dim3(blocks_for(L.n * d)),
-                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
-                               (const int32_t*)nullptr, (const T*)val, val);
-        h->end(st, ev, l == 0 ? "scatter" : "scatter_tail",
-               sz * d * (double)(L.rows_read + L.n) + (L.indexed ? 4.0 * L.rows_read : 0.0) +
-                   20.0 * L.n);
-    }
+    launch_scatter<T>(h, F, val, d, st);
     // 3. direct tables
     if (h->ndblk > 0) {
         ev = h->begin(st);
@@ -578,6 +593,101 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     return TFI_OK;
 }
 
+// Kernel-table gradient df (FP64, length kernel_len) for L = sum(gout * out).
+template <typename T>
+int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t st) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    int rc;
+    if ((rc = h->ensure(h->val[ti], rowbytes))) return rc;
+    if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
+    T* val = (T*)h->val[ti].p;
+    T* valg = (T*)h->valg[ti].p;
+    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
+    const int32_t K = (int32_t)p.kernel_len;
+    const int32_t npairs = (d + 1) / 2;
+    const double sz = (double)sizeof(T);
+    hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(K)), dim3(kThreads), 0, st, df,
+                       (int64_t)K);
+    launch_scatter<T>(h, F, val, d, st);
+    launch_scatter<T>(h, gout, valg, d, st);
+    if (h->ndblk > 0) {
+        hipEvent_t ev = h->begin(st);
+        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
+                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_dl_jb,
+                           h->d_dl_je, (const T*)val, (const T*)valg, K, df);
+        h->end(st, ev, "df_direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
+    }
+    for (const Bucket& b : h->buckets) {
+        const int64_t P = b.P();
+        const double bytes = 2.0 * sz * d * (double)b.cells + 12.0 * b.cells;
+        if (3 * P * (int64_t)sizeof(tfi::cpx<T>) <= h->lds_max) {
+            hipEvent_t ev = h->begin(st);
+            hipLaunchKernelGGL(tfi::k_df_fft_lds<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
+                               (unsigned)(3 * P * sizeof(tfi::cpx<T>)), st, b.lg1, b.lg2, p.NA,
+                               b.d_jobs, b.d_hx, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
+                               (const T*)val, (const T*)valg, tw, h->lgtw, df);
+            h->end(st, ev, "df_fft_lds", bytes);
+            continue;
+        }
+        // global memory: chunks of jobs, 2 tables per (job, pair) slot
+        const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
+        const int64_t cap = (int64_t)2 << 30;
+        const int64_t jpc = std::max<int64_t>(
+            1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
+        if ((rc = h->ensure(h->dfbuf[ti], (size_t)(std::min(jpc, b.njobs()) * per_job)))) return rc;
+        tfi::cpx<T>* bv = (tfi::cpx<T>*)h->dfbuf[ti].p;
+        hipEvent_t ev = h->begin(st);
+        const int lgP = b.lg1 + b.lg2;
+        for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
+            const int64_t nj = std::min(jpc, b.njobs() - j0);
+            const int64_t nslots = nj * npairs;
+            tfi::cpx<T>* bg = bv + nslots * P;
+            tfi::cpx<T>* acc = bg + nslots * P;
+            const int32_t* jobs = b.d_jobs + 2 * j0;
+            hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(2 * nslots * P)),
+                               dim3(kThreads), 0, st, bv, 2 * nslots * P);
+            hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
+                               0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                               h->d_jc_val, d, (const T*)val, (const T*)valg, bv, bg);
+            const unsigned nb = blocks_for(2 * nslots * P / 2);
+            for (int s = 0; s < b.lg2; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                                   st, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
+                                   h->lgtw);
+            for (int s = 0; s < b.lg1; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                                   st, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
+                                   (int64_t)1 << b.lg2, tw, h->lgtw);
+            hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
+                               dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
+                               (const tfi::cpx<T>*)bg, acc);
+            const unsigned na = blocks_for(nj * P / 2);
+            for (int s = 0; s < b.lg1; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
+                                   st, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
+            for (int s = 0; s < b.lg2; ++s)
+                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
+                                   st, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+            hipLaunchKernelGGL(tfi::k_fold_global<T>, dim3(blocks_for(nj * P)), dim3(kThreads), 0,
+                               st, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
+                               (const tfi::cpx<T>*)acc, df);
+        }
+        h->end(st, ev, "df_fft_global", bytes);
+    }
+    if (h->nlgrp > 0) {
+        hipEvent_t ev = h->begin(st);
+        hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0,
+                           st, d, h->d_lgrp, h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff,
+                           h->d_leaf_D, F, gout, K, df);
+        const double nv = (double)p.leaf_v.size();
+        h->end(st, ev, "df_leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+    }
+    TFI_HIP(hipGetLastError());
+    return TFI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -616,6 +726,11 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
                                          " not available");
         TFI_HIP(hipSetDevice(o.device));
         h->device = o.device;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device) ==
+                hipSuccess &&
+            lds > 0)
+            h->lds_max = std::min<int64_t>(lds, 65536);
         rc = upload_plan(h.get());
         if (rc) return rc;
     }
@@ -650,8 +765,22 @@ int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, i
     int rc = check_handle(h, true);
     if (rc) return rc;
     if (!f || !F || !gout) return fail(TFI_ERR_ARG, "tfi_backward: null pointer");
-    if (df) return fail(TFI_ERR_STATE, "tfi_backward: df is not available in this build");
-    if (dF) return tfi_integrate(h, f, gout, d, dtype, dF, stream);
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_backward: need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64)
+        return fail(TFI_ERR_DTYPE, "tfi_backward: unknown dtype");
+    if (dF && (dF == F || dF == gout))
+        return fail(TFI_ERR_ARG, "tfi_backward: dF must not alias F or gout");
+    hipStream_t st = (hipStream_t)stream;
+    if (dF) {
+        // f(D) is symmetric: dF = f(D) gout
+        rc = tfi_integrate(h, f, gout, d, dtype, dF, stream);
+        if (rc) return rc;
+    }
+    if (df) {
+        if (dtype == TFI_F32)
+            return run_df<float>(h, (const float*)F, (const float*)gout, (int32_t)d, df, st);
+        return run_df<double>(h, (const double*)F, (const double*)gout, (int32_t)d, df, st);
+    }
     return TFI_OK;
 }
 

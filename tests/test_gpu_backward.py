@@ -1,0 +1,153 @@
+"""GPU adjoint: dF and the kernel-table gradient df against the oracle, and
+finite differences through the autograd function with a learnable
+exponential-sum kernel f(k) = sum_j a_j exp(-b_j k)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2609_34025_amd import synth as S
+from paper_2609_34025_amd import TreeIntegrator, TreeIntegrate, expsum_table
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def relerr(y, ref):
+    n = np.linalg.norm(ref)
+    return np.linalg.norm(np.asarray(y, np.float64) - ref) / (n if n > 0 else 1.0)
+
+
+def run_backward(p, w, ftab_fn, F, G, dtype, **opts):
+    t = TreeIntegrator(p, w, device=0, **opts)
+    K = t.kernel_length
+    ftab = ftab_fn(K)
+    f = torch.tensor(ftab, dtype=dtype, device=DEV)
+    dF, df = t.backward(f, torch.tensor(F, dtype=dtype, device=DEV),
+                        torch.tensor(G, dtype=dtype, device=DEV))
+    torch.cuda.synchronize()
+    return t, ftab, dF.cpu().numpy(), df.cpu().numpy()
+
+
+def check_backward(p, w, ftab_fn, F, G, dtype=torch.float64, **opts):
+    t, ftab, dF, df = run_backward(p, w, ftab_fn, F, G, dtype, **opts)
+    K = t.kernel_length
+    ref_dF = oracle.integrate(p, w, ftab, G)
+    ref_df = oracle.pair_hist(p, w, G, F, K)
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    e1, e2 = relerr(dF, ref_dF), relerr(df, ref_df)
+    assert e1 <= tol and e2 <= tol, (e1, e2, opts)
+    return e1, e2
+
+
+def trees():
+    rng = np.random.default_rng(5)
+    out = []
+    p, _ = S.random_recursive(400, rng)
+    out.append(("rrt400_w8", p, S.uniform_weights(p, 1, 8, rng)))
+    out.append(("grid16_w16", *S.grid_mst(16, 16, rng)))
+    out.append(("chp12", *S.caterpillar_hanging_paths(12)))
+    out.append(("spider6x30", *S.spider(6, 30)))
+    cp = S.caterpillar(50, 3)[0]
+    out.append(("cater50_w4", cp, S.uniform_weights(cp, 1, 4, rng)))
+    fp, fw, _ = S.forest([S.grid_mst(9, 5, rng), S.path(1), S.star(7)])
+    out.append(("forest", fp, fw))
+    return out
+
+
+@pytest.mark.parametrize("method", ["auto", "direct", "fft"])
+@pytest.mark.parametrize("policy", ["adaptive", "diameter"])
+@pytest.mark.parametrize("leaf", [1, 32])
+def test_backward_fp64_matches_oracle(method, policy, leaf):
+    rng = np.random.default_rng(3)
+    for name, p, w in trees():
+        F = rng.standard_normal((len(p), 5))
+        G = rng.standard_normal((len(p), 5))
+        check_backward(p, w, lambda K: np.exp(-0.04 * np.arange(K)) * np.cos(0.3 * np.arange(K)),
+                       F, G, torch.float64, policy=policy, leaf_max=leaf, table_method=method)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_backward_large_tables(dtype):
+    # df tables beyond LDS capacity go through the global-memory path
+    rng = np.random.default_rng(8)
+    p, _ = S.path(2500)
+    w = S.uniform_weights(p, 1, 3, rng)
+    F = rng.standard_normal((len(p), 3))
+    G = rng.standard_normal((len(p), 3))
+    check_backward(p, w, lambda K: np.exp(-0.003 * np.arange(K)), F, G, dtype,
+                   policy="diameter", table_method="fft")
+
+
+def test_backward_fp32_wide_forest():
+    # C3-shaped: forest of grid MSTs, 64 channels, exp-sum kernel
+    rng = np.random.default_rng(9)
+    trees_ = [S.grid_mst(int(s), 16, rng) for s in rng.integers(14, 24, size=6)]
+    p, w, _ = S.forest(trees_)
+    a = rng.standard_normal(8)
+    b = rng.uniform(0.01, 0.5, size=8)
+    F = rng.standard_normal((len(p), 64))
+    G = rng.standard_normal((len(p), 64))
+    e1, e2 = check_backward(p, w, lambda K: S.expsum_table(K, a, b), F, G, torch.float32)
+    print(f"forest d=64 fp32: dF {e1:.2e} df {e2:.2e}")
+
+
+def test_autograd_expsum_finite_differences():
+    rng = np.random.default_rng(12)
+    trees_ = [S.grid_mst(s, 16, rng) for s in (5, 7, 6)]
+    p, w, _ = S.forest(trees_)
+    n = len(p)
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    a = torch.tensor(rng.standard_normal(8), device=DEV, requires_grad=True)
+    b = torch.tensor(rng.uniform(0.01, 0.5, 8), device=DEV, requires_grad=True)
+    F = torch.tensor(rng.standard_normal((n, 4)), device=DEV, requires_grad=True)
+    Wt = torch.tensor(rng.standard_normal((n, 4)), device=DEV)
+
+    def loss(a_, b_, F_):
+        return (Wt * TreeIntegrate.apply(t, F_, expsum_table(a_, b_, K))).sum()
+
+    L = loss(a, b, F)
+    L.backward()
+    with torch.no_grad():
+        for theta, g in ((a, a.grad), (b, b.grad)):
+            for k in range(8):
+                h = 1e-6 * max(1.0, abs(theta[k].item()))
+                old = theta[k].item()
+                theta[k] = old + h
+                lp = loss(a, b, F).item()
+                theta[k] = old - h
+                lm = loss(a, b, F).item()
+                theta[k] = old
+                fd = (lp - lm) / (2 * h)
+                assert abs(fd - g[k].item()) <= 1e-6 * max(1.0, abs(fd)), (k, fd, g[k].item())
+        # directional derivatives in F
+        for _ in range(3):
+            E = torch.tensor(rng.standard_normal((n, 4)), device=DEV)
+            h = 1e-6
+            fd = (loss(a, b, F + h * E).item() - loss(a, b, F - h * E).item()) / (2 * h)
+            an = (F.grad * E).sum().item()
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd))
+    # against the oracle's dense gradient
+    hist = oracle.pair_hist(p, w, Wt.cpu().numpy(), F.detach().cpu().numpy(), K)
+    kk = np.arange(K)
+    A, B = a.detach().cpu().numpy(), b.detach().cpu().numpy()
+    da = np.array([(hist * np.exp(-B[j] * kk)).sum() for j in range(8)])
+    db = np.array([-A[j] * (hist * kk * np.exp(-B[j] * kk)).sum() for j in range(8)])
+    assert relerr(a.grad.cpu().numpy(), da) < 1e-10
+    assert relerr(b.grad.cpu().numpy(), db) < 1e-10
+
+
+def test_adjoint_identity_fp32():
+    # <gout, K F> = <K gout, F> with the device forward and adjoint
+    rng = np.random.default_rng(14)
+    W = S.workload("small")
+    p, w = W["parent"], W["weight"]
+    t = TreeIntegrator(p, w, device=0)
+    f = torch.tensor(W["kernels"][0][1](t.kernel_length), dtype=torch.float32, device=DEV)
+    F = torch.tensor(rng.standard_normal((len(p), 6)), dtype=torch.float32, device=DEV)
+    G = torch.tensor(rng.standard_normal((len(p), 6)), dtype=torch.float32, device=DEV)
+    lhs = (G.double() * t.integrate(f, F).double()).sum().item()
+    dF, _ = t.backward(f, F, G, need_df=False)
+    rhs = (dF.double() * F.double()).sum().item()
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
