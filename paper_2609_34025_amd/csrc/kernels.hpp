@@ -38,52 +38,103 @@ __device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
     return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
 }
 
+// ----------------------------------------------------------- vectors ----
+// Four consecutive channels of one row (16 B for float, 32 B for double).
+template <typename T>
+struct vec4 {
+    T x, y, z, w;
+};
+template <typename T>
+__device__ __forceinline__ vec4<T> ld4(const T* p) {
+    return *reinterpret_cast<const vec4<T>*>(p);
+}
+template <>
+__device__ __forceinline__ vec4<float> ld4<float>(const float* p) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    return {v.x, v.y, v.z, v.w};
+}
+template <typename T>
+__device__ __forceinline__ void st4(T* p, vec4<T> v) {
+    *reinterpret_cast<vec4<T>*>(p) = v;
+}
+template <>
+__device__ __forceinline__ void st4<float>(float* p, vec4<float> v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.x, v.y, v.z, v.w);
+}
+template <typename T>
+__device__ __forceinline__ void add4(vec4<T>& a, vec4<T> b) {
+    a.x += b.x; a.y += b.y; a.z += b.z; a.w += b.w;
+}
+template <typename T>
+__device__ __forceinline__ void sub4(vec4<T>& a, vec4<T> b) {
+    a.x -= b.x; a.y -= b.y; a.z -= b.z; a.w -= b.w;
+}
+template <typename T>
+__device__ __forceinline__ void fma4(vec4<T>& a, T s, vec4<T> b) {
+    a.x += s * b.x; a.y += s * b.y; a.z += s * b.z; a.w += s * b.w;
+}
+
 // ------------------------------------------------------------- scatter ----
 // Segmented sums with bounded fan-in. Segment s adds len[s] <= 32 source
 // rows starting at src_beg[s] and writes row dst[s] of the value matrix.
 // Level 0 reads field rows through the incidence vertex list; later levels
 // add partial rows of longer segments (split on the host into pieces), so
 // no thread walks an unbounded run and the summation order is fixed.
-template <typename T, bool INDEXED>
+// VEC = 4: one thread per (segment, 4 channels), requires d % 4 == 0.
+template <typename T, bool INDEXED, int VEC>
 __global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ seg_src,
                          const int32_t* __restrict__ seg_len, const int64_t* __restrict__ seg_dst,
                          const int32_t* __restrict__ idx, const T* __restrict__ src,
                          T* __restrict__ val) {
+    const int32_t dv = d / VEC;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= nseg * d) return;
-    const int64_t s = tid / d;
-    const int32_t c = (int32_t)(tid - s * d);
+    if (tid >= nseg * dv) return;
+    const int64_t s = tid / dv;
+    const int32_t c = (int32_t)(tid - s * dv) * VEC;
     const int64_t b = seg_src[s];
     const int32_t n = seg_len[s];
-    T acc = 0;
+    if (VEC == 4) {
+        vec4<T> acc = {0, 0, 0, 0};
 #pragma unroll 4
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
-        acc += src[row * d + c];
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
+            add4(acc, ld4(src + row * d + c));
+        }
+        st4(val + seg_dst[s] * d + c, acc);
+    } else {
+        T acc = 0;
+#pragma unroll 4
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
+            acc += src[row * d + c];
+        }
+        val[seg_dst[s] * d + c] = acc;
     }
-    val[seg_dst[s] * d + c] = acc;
 }
 
 // ------------------------------------------------------ direct tables ----
 // Direct evaluation G(i) = sum_{j in job(i)} f(r_i + r_j + |x_i - x_j|) v(j)
-// for small or sparse tables. A workgroup owns a block of at most
-// kDirOut output cells: either several whole small jobs (sources = the
-// block's own cells) or a slice of one large job (sources = the whole job,
-// streamed through LDS in tiles of kDirTile cells). Channels are processed
-// in chunks of kDirCh. blk[4 b .. 4 b + 3] = (out_beg, out_end, src_beg,
-// src_end) index the direct-cell list (dl_*); dl_jb/dl_je give each cell's
-// job range in the same list.
-constexpr int kDirOut = 64, kDirTile = 256, kDirCh = 16, kDirThreads = 256;
+// as small register-blocked products: a thread owns 4 cells x 4 channels
+// (16 accumulators), so each kernel value read serves 4 channels and each
+// 4-channel source vector serves 4 cells. Cells of a job are padded to a
+// multiple of 4 (padding cells have row -1: zero source, no output), and
+// jobs are sorted by size, so the lanes of a wavefront run loops of equal
+// length. A workgroup owns kDirOut output cells: whole jobs packed
+// together, or a slice of a larger job whose sources are streamed through
+// LDS in tiles of kDirOut cells. Channels go in chunks of kDirCh.
+// blk[4 b .. 4 b + 3] = (out_beg, out_end, src_beg, src_end) in the padded
+// cell list; qjb/qje give each cell quad's job range in the same list.
+constexpr int kDirOut = 256, kDirCh = 16, kDirThreads = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(kDirThreads)
 k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
          const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
-         const int32_t* __restrict__ dl_jb, const int32_t* __restrict__ dl_je,
+         const int32_t* __restrict__ qjb, const int32_t* __restrict__ qje,
          const T* __restrict__ f, int32_t flds, const T* __restrict__ val,
          T* __restrict__ g) {
-    __shared__ T sv[kDirTile * kDirCh];
-    __shared__ int32_t sr[kDirTile], sx[kDirTile];
+    __shared__ __attribute__((aligned(16))) T sv[kDirOut * kDirCh];
+    __shared__ int32_t sr[kDirOut], sx[kDirOut];
     extern __shared__ unsigned char dyn_raw[];
     T* sf = reinterpret_cast<T*>(dyn_raw);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
@@ -95,121 +146,167 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
     }
     for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
-        const int32_t cpp = kDirThreads / nch;  // output cells per pass
-        const int32_t ci0 = threadIdx.x / nch, c = threadIdx.x - ci0 * nch;
-        const bool lane_ok = ci0 < cpp;
-        T acc[4] = {0, 0, 0, 0};
-        int32_t ri[4], xi[4], jb[4], je[4];
+        const int32_t nq = (nch + 3) >> 2;             // channel quads
+        const int32_t qpp = kDirThreads / nq;          // cell quads per pass
+        const int32_t cq = threadIdx.x / nq, chq = threadIdx.x - cq * nq;
+        const int32_t Q = (os >> 2) + cq;              // this thread's cell quad
+        const bool act = cq < qpp && 4 * Q < oe;
+        int32_t ri[4], xi[4];
+        int32_t jb = 0, je = 0;
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t i = os + ci0 + q * cpp;
-            const bool ok = lane_ok && i < oe;
-            ri[q] = ok ? dl_r[i] : 0;
-            xi[q] = ok ? dl_x[i] : 0;
-            jb[q] = ok ? dl_jb[i] : 0;
-            je[q] = ok ? dl_je[i] : 0;
+            for (int c = 0; c < 4; ++c) {
+                ri[c] = dl_r[4 * Q + c];
+                xi[c] = dl_x[4 * Q + c];
+            }
+            jb = qjb[Q];
+            je = qje[Q];
         }
-        for (int32_t ts = ss; ts < se; ts += kDirTile) {
-            const int32_t tn = min(kDirTile, se - ts);
+        vec4<T> acc[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] = {0, 0, 0, 0};
+        for (int32_t ts = ss; ts < se; ts += kDirOut) {
+            const int32_t tn = min(kDirOut, se - ts);
             __syncthreads();
             for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
                 sr[k] = dl_r[ts + k];
                 sx[k] = dl_x[ts + k];
             }
-            for (int32_t e = threadIdx.x; e < tn * nch; e += blockDim.x) {
-                const int32_t k = e / nch, cc = e - k * nch;
-                sv[k * kDirCh + cc] = val[(int64_t)dl_row[ts + k] * d + c0 + cc];
+            for (int32_t e = threadIdx.x; e < tn * kDirCh; e += blockDim.x) {
+                const int32_t k = e / kDirCh, cc = e - k * kDirCh;
+                const int32_t row = dl_row[ts + k];
+                sv[e] = (row >= 0 && cc < nch) ? val[(int64_t)row * d + c0 + cc] : (T)0;
             }
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t lo = max(jb[q], ts) - ts, hi = min(je[q], ts + tn) - ts;
-                T a = acc[q];
+            if (act) {
+                const int32_t lo = max(jb, ts) - ts, hi = min(je, ts + tn) - ts;
                 for (int32_t k = lo; k < hi; ++k) {
-                    const int32_t dx = xi[q] - sx[k];
-                    a += fp[ri[q] + sr[k] + (dx < 0 ? -dx : dx)] * sv[k * kDirCh + c];
+                    const int32_t rk = sr[k], xk = sx[k];
+                    const vec4<T> v = ld4(sv + k * kDirCh + 4 * chq);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int32_t dx = xi[c] - xk;
+                        fma4(acc[c], fp[ri[c] + rk + (dx < 0 ? -dx : dx)], v);
+                    }
                 }
-                acc[q] = a;
             }
         }
+        if (act) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int32_t i = os + ci0 + q * cpp;
-            if (lane_ok && i < oe) g[(int64_t)dl_row[i] * d + c0 + c] = acc[q];
+            for (int c = 0; c < 4; ++c) {
+                const int32_t row = dl_row[4 * Q + c];
+                if (row < 0) continue;
+                T* out = g + (int64_t)row * d + c0 + 4 * chq;
+                const int32_t left = nch - 4 * chq;
+                if (left >= 4 && ((d & 3) == 0)) {
+                    st4(out, acc[c]);
+                } else {
+                    const T vv[4] = {acc[c].x, acc[c].y, acc[c].z, acc[c].w};
+                    for (int cc = 0; cc < 4 && cc < left; ++cc) out[cc] = vv[cc];
+                }
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------- gather --
-// One thread per (vertex, channel): adds, over the calls holding the
+// One thread per (vertex, VEC channels): adds, over the calls holding the
 // vertex, the call's table value minus the component correction (row -1
 // when the vertex is on the call's backbone). Writes every out row.
-template <typename T>
+template <typename T, int VEC>
 __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off,
                          const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
                          const T* __restrict__ g, T* __restrict__ out) {
+    const int32_t dv = d / VEC;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= N * d) return;
-    const int64_t v = tid / d;
-    const int32_t c = (int32_t)(tid - v * d);
-    T s = 0;
+    if (tid >= N * dv) return;
+    const int64_t v = tid / dv;
+    const int32_t c = (int32_t)(tid - v * dv) * VEC;
     const int64_t k1 = v_off[v + 1];
-    for (int64_t k = v_off[v]; k < k1; ++k) {
-        const int32_t b = gb[k];
-        s += g[(int64_t)ga[k] * d + c];
-        if (b >= 0) s -= g[(int64_t)b * d + c];
+    if (VEC == 4) {
+        vec4<T> s = {0, 0, 0, 0};
+        for (int64_t k = v_off[v]; k < k1; ++k) {
+            const int32_t b = gb[k];
+            add4(s, ld4(g + (int64_t)ga[k] * d + c));
+            if (b >= 0) sub4(s, ld4(g + (int64_t)b * d + c));
+        }
+        st4(out + v * d + c, s);
+    } else {
+        T s = 0;
+        for (int64_t k = v_off[v]; k < k1; ++k) {
+            const int32_t b = gb[k];
+            s += g[(int64_t)ga[k] * d + c];
+            if (b >= 0) s -= g[(int64_t)b * d + c];
+        }
+        out[v * d + c] = s;
     }
-    out[v * d + c] = s;
 }
 
 // ----------------------------------------------------------- leaf tiles --
-// Dense f(D) F on small subtrees. A workgroup owns a group of consecutive
-// tiles with at most kLeafMax vertices in total; the kernel values
-// f(D[i, j]) of every tile and the field rows (kDirCh channels at a time)
-// are staged in LDS, then out[v] += sum_j f(D[v, j]) F[j].
-constexpr int kLeafMax = 64, kLeafThreads = 256;
+// Dense f(D) F on small subtrees, blocked like the direct tables: a thread
+// owns 4 vertices x 4 channels of one tile. A workgroup owns a group of
+// consecutive tiles (at most kLeafQuads vertex quads and kLeafK kernel
+// entries); f(D) of every tile and the field rows (kDirCh channels at a
+// time) are staged in LDS, then out[v] += sum_j f(D[v, j]) F[j].
+// lq[4 q .. 4 q + 3] describes quad q: (first vertex in leaf_v, tile start
+// in leaf_v, tile size, offset of the quad's first kernel row in the
+// group's f(D) block); grp holds quad ranges per group and koff the
+// group's first leaf_D entry and count.
+constexpr int kLeafMax = 64, kLeafQuads = 32, kLeafSlots = 128, kLeafK = 4096,
+              kLeafThreads = 256;
 
 template <typename T>
 __global__ void __launch_bounds__(kLeafThreads)
-k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ leaf_off,
-       const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
+k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ gk,
+       const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
        const int32_t* __restrict__ leaf_D, const T* __restrict__ f, const T* __restrict__ F,
        T* __restrict__ out) {
-    __shared__ T sk[kLeafMax * kLeafMax];
-    __shared__ T sF[kLeafMax * kDirCh];
-    __shared__ int32_t sv[kLeafMax], stile_beg[kLeafMax], stile_n[kLeafMax], skoff[kLeafMax];
-    const int32_t t0 = grp[blockIdx.x], t1 = grp[blockIdx.x + 1];
-    const int64_t vbase = leaf_off[t0];
-    const int32_t nv = (int32_t)(leaf_off[t1] - vbase);
-    const int64_t dbase = leaf_doff[t0];
-    // per-vertex tile bounds and kernel-row offsets
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-        const int32_t b = (int32_t)(leaf_off[t] - vbase), n = (int32_t)(leaf_off[t + 1] - leaf_off[t]);
-        const int32_t ko = (int32_t)(leaf_doff[t] - dbase);
-        for (int32_t i = 0; i < n; ++i) {
-            stile_beg[b + i] = b;
-            stile_n[b + i] = n;
-            skoff[b + i] = ko + i * n;
-        }
-    }
-    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) sv[i] = leaf_v[vbase + i];
-    const int32_t nk = (int32_t)(leaf_doff[t1] - dbase);
-    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) sk[k] = f[leaf_D[dbase + k]];
+    __shared__ T sk[kLeafK];
+    __shared__ __attribute__((aligned(16))) T sF[kLeafSlots * kDirCh];
+    __shared__ int32_t svtx[kLeafSlots];
+    const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1];
+    const int64_t kb = gk[2 * blockIdx.x];
+    const int32_t nk = (int32_t)gk[2 * blockIdx.x + 1];
+    // vertex slots are leaf_v positions [vb, vb + nv): the group's tiles
+    const int32_t vb = lq[4 * q0 + 1];
+    const int32_t nv = lq[4 * (q1 - 1) + 1] + lq[4 * (q1 - 1) + 2] - vb;
+    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) sk[k] = f[leaf_D[kb + k]];
+    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
     for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
+        const int32_t nq = (nch + 3) >> 2;
+        const int32_t qpp = kLeafThreads / nq;
         __syncthreads();
-        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
-            const int32_t i = e / nch, cc = e - i * nch;
-            sF[i * kDirCh + cc] = F[(int64_t)sv[i] * d + c0 + cc];
+        for (int32_t e = threadIdx.x; e < nv * kDirCh; e += blockDim.x) {
+            const int32_t i = e / kDirCh, cc = e - i * kDirCh;
+            sF[e] = (cc < nch) ? F[(int64_t)svtx[i] * d + c0 + cc] : (T)0;
         }
         __syncthreads();
-        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
-            const int32_t i = e / nch, cc = e - i * nch;
-            const int32_t b = stile_beg[i], n = stile_n[i];
-            const T* krow = sk + skoff[i];
-            T a = 0;
-            for (int32_t j = 0; j < n; ++j) a += krow[j] * sF[(b + j) * kDirCh + cc];
-            out[(int64_t)sv[i] * d + c0 + cc] += a;
+        const int32_t cq0 = threadIdx.x / nq;
+        for (int32_t qq = cq0; cq0 < qpp && q0 + qq < q1; qq += qpp) {
+            const int32_t chq = threadIdx.x % nq;
+            const int32_t q = q0 + qq;
+            const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
+            const int32_t krow = lq[4 * q + 3];
+            vec4<T> acc[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[c] = {0, 0, 0, 0};
+            const int32_t rows = min(4, tb + n - first);
+            for (int32_t j = 0; j < n; ++j) {
+                const vec4<T> v = ld4(sF + (tb - vb + j) * kDirCh + 4 * chq);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c < rows) fma4(acc[c], sk[krow + c * n + j], v);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (c >= rows) continue;
+                const int32_t vtx = leaf_v[first + c];
+                T* o = out + (int64_t)vtx * d + c0 + 4 * chq;
+                const int32_t left = nch - 4 * chq;
+                const T vv[4] = {acc[c].x, acc[c].y, acc[c].z, acc[c].w};
+                for (int cc = 0; cc < 4 && cc < left; ++cc) o[cc] += vv[cc];
+            }
         }
     }
 }
@@ -450,15 +547,15 @@ __device__ __forceinline__ void hist_add(double* lh, double* gh, int32_t k, doub
     else atomicAdd(gh + k, v);
 }
 
-// Direct jobs: same blocks as k_direct. Pair dot products are formed over
-// channel chunks in registers (16 pairs per thread), then binned by
-// surrogate distance.
+// Direct jobs: same blocks as k_direct, output cells taken 64 at a time.
+// Pair dot products are formed over channel chunks in registers (16 pairs
+// per thread), then binned by surrogate distance.
 template <typename T>
 __global__ void __launch_bounds__(kDfThreads)
 k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             const int32_t* __restrict__ dl_r, const int32_t* __restrict__ dl_x,
-            const int32_t* __restrict__ dl_row, const int32_t* __restrict__ dl_jb,
-            const int32_t* __restrict__ dl_je, const T* __restrict__ val,
+            const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
+            const int32_t* __restrict__ qje, const T* __restrict__ val,
             const T* __restrict__ valg, int32_t K, double* __restrict__ df) {
     __shared__ T sG[kDfTile * (kDirCh + 1)], sV[kDfTile * (kDirCh + 1)];
     __shared__ int32_t sr[kDfTile], sx[kDfTile];
@@ -468,47 +565,52 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
     if (use_lds)
         for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
-    const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
     const int32_t ii = threadIdx.x & (kDfTile - 1), jj0 = threadIdx.x >> 6;
-    const int32_t i = os + ii;
-    const bool iok = i < oe;
-    const int32_t ri = iok ? dl_r[i] : 0, xi = iok ? dl_x[i] : 0;
-    const int32_t jb = iok ? dl_jb[i] : 0, je = iok ? dl_je[i] : 0;
-    const double sign = (iok && dl_row[i] < NA) ? 1.0 : -1.0;
-    for (int32_t ts = ss; ts < se; ts += kDfTile) {
-        const int32_t tn = min(kDfTile, se - ts);
-        T m[16];
+    for (int32_t oc = os; oc < oe; oc += kDfTile) {
+        const int32_t on = min(kDfTile, oe - oc);
+        const int32_t i = oc + ii;
+        const bool iok = ii < on && dl_row[i] >= 0;
+        const int32_t ri = iok ? dl_r[i] : 0, xi = iok ? dl_x[i] : 0;
+        const int32_t jb = iok ? qjb[i >> 2] : 0, je = iok ? qje[i >> 2] : 0;
+        const double sign = (iok && dl_row[i] < NA) ? 1.0 : -1.0;
+        // sources: the union of the job ranges of this chunk's cells
+        const int32_t ss = qjb[oc >> 2], se = qje[(oc + on - 1) >> 2];
+        for (int32_t ts = ss; ts < se; ts += kDfTile) {
+            const int32_t tn = min(kDfTile, se - ts);
+            T m[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) m[q] = 0;
-        for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
-            const int32_t nch = min(kDirCh, d - c0);
-            __syncthreads();
-            for (int32_t e = threadIdx.x; e < kDfTile * nch; e += blockDim.x) {
-                const int32_t k = e / nch, cc = e - k * nch;
-                sG[k * (kDirCh + 1) + cc] =
-                    (os + k < oe) ? valg[(int64_t)dl_row[os + k] * d + c0 + cc] : (T)0;
-                sV[k * (kDirCh + 1) + cc] =
-                    (k < tn) ? val[(int64_t)dl_row[ts + k] * d + c0 + cc] : (T)0;
-            }
-            if (c0 == 0)
-                for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
-                    sr[k] = dl_r[ts + k];
-                    sx[k] = dl_x[ts + k];
+            for (int q = 0; q < 16; ++q) m[q] = 0;
+            for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+                const int32_t nch = min(kDirCh, d - c0);
+                __syncthreads();
+                for (int32_t e = threadIdx.x; e < kDfTile * nch; e += blockDim.x) {
+                    const int32_t k = e / nch, cc = e - k * nch;
+                    const int32_t ro = (k < on) ? dl_row[oc + k] : -1;
+                    const int32_t rs = (k < tn) ? dl_row[ts + k] : -1;
+                    sG[k * (kDirCh + 1) + cc] = ro >= 0 ? valg[(int64_t)ro * d + c0 + cc] : (T)0;
+                    sV[k * (kDirCh + 1) + cc] = rs >= 0 ? val[(int64_t)rs * d + c0 + cc] : (T)0;
                 }
-            __syncthreads();
-            for (int32_t cc = 0; cc < nch; ++cc) {
-                const T gv = sG[ii * (kDirCh + 1) + cc];
+                if (c0 == 0)
+                    for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
+                        sr[k] = dl_r[ts + k];
+                        sx[k] = dl_x[ts + k];
+                    }
+                __syncthreads();
+                for (int32_t cc = 0; cc < nch; ++cc) {
+                    const T gv = sG[ii * (kDirCh + 1) + cc];
 #pragma unroll
-                for (int q = 0; q < 16; ++q) m[q] += gv * sV[(jj0 + 4 * q) * (kDirCh + 1) + cc];
+                    for (int q = 0; q < 16; ++q)
+                        m[q] += gv * sV[(jj0 + 4 * q) * (kDirCh + 1) + cc];
+                }
             }
-        }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int32_t j = ts + jj0 + 4 * q;
-            if (iok && j >= jb && j < je && jj0 + 4 * q < tn) {
-                const int32_t dx = xi - sx[jj0 + 4 * q];
-                hist_add<T>(lhp, df, ri + sr[jj0 + 4 * q] + (dx < 0 ? -dx : dx),
-                            sign * (double)m[q]);
+            for (int q = 0; q < 16; ++q) {
+                const int32_t j = ts + jj0 + 4 * q;
+                if (iok && j >= jb && j < je && jj0 + 4 * q < tn && m[q] != (T)0) {
+                    const int32_t dx = xi - sx[jj0 + 4 * q];
+                    hist_add<T>(lhp, df, ri + sr[jj0 + 4 * q] + (dx < 0 ? -dx : dx),
+                                sign * (double)m[q]);
+                }
             }
         }
     }
@@ -519,68 +621,47 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
     }
 }
 
-// Leaf tiles: pairs inside each tile of a group, distance from D.
+// Leaf tiles: pairs inside each tile, distance from D. One thread per
+// (quad, source vertex j) pair row: 4 dot products over all channels,
+// read through L2.
 template <typename T>
 __global__ void __launch_bounds__(kLeafThreads)
-k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ leaf_off,
-          const int32_t* __restrict__ leaf_v, const int64_t* __restrict__ leaf_doff,
+k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ gk,
+          const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
           const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
           const T* __restrict__ gout, int32_t K, double* __restrict__ df) {
-    __shared__ T sG[kLeafMax * (kDirCh + 1)], sF[kLeafMax * (kDirCh + 1)];
-    __shared__ int32_t sv[kLeafMax], stile_beg[kLeafMax], stile_n[kLeafMax], skoff[kLeafMax];
     __shared__ double lh[kDfHistLds];
     const bool use_lds = K <= kDfHistLds;
     double* lhp = use_lds ? lh : nullptr;
     if (use_lds)
         for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
-    const int32_t t0 = grp[blockIdx.x], t1 = grp[blockIdx.x + 1];
-    const int64_t vbase = leaf_off[t0];
-    const int32_t nv = (int32_t)(leaf_off[t1] - vbase);
-    const int64_t dbase = leaf_doff[t0];
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-        const int32_t b = (int32_t)(leaf_off[t] - vbase), n = (int32_t)(leaf_off[t + 1] - leaf_off[t]);
-        const int32_t ko = (int32_t)(leaf_doff[t] - dbase);
-        for (int32_t i = 0; i < n; ++i) {
-            stile_beg[b + i] = b;
-            stile_n[b + i] = n;
-            skoff[b + i] = ko + i * n;
-        }
-    }
-    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) sv[i] = leaf_v[vbase + i];
-    // thread -> (vertex i, sources j = jj0 + 4 q), 16 pairs per thread
-    const int32_t ii = threadIdx.x & (kLeafMax - 1), jj0 = threadIdx.x >> 6;
-    T m[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) m[q] = 0;
-    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
-        const int32_t nch = min(kDirCh, d - c0);
-        __syncthreads();
-        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
-            const int32_t k = e / nch, cc = e - k * nch;
-            sG[k * (kDirCh + 1) + cc] = gout[(int64_t)sv[k] * d + c0 + cc];
-            sF[k * (kDirCh + 1) + cc] = F[(int64_t)sv[k] * d + c0 + cc];
-        }
-        __syncthreads();
-        if (ii < nv) {
-            const int32_t b = stile_beg[ii], n = stile_n[ii];
-            for (int32_t cc = 0; cc < nch; ++cc) {
-                const T gv = sG[ii * (kDirCh + 1) + cc];
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    const int32_t j = jj0 + 4 * q;
-                    if (j < n) m[q] += gv * sF[(b + j) * (kDirCh + 1) + cc];
-                }
-            }
-        }
-    }
     __syncthreads();
-    if (ii < nv) {
-        const int32_t n = stile_n[ii];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int32_t j = jj0 + 4 * q;
-            if (j < n) hist_add<T>(lhp, df, leaf_D[dbase + skoff[ii] + j], (double)m[q]);
+    const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1];
+    const int64_t kb = gk[2 * blockIdx.x];
+    // enumerate (quad, j) rows of the group
+    int32_t rows_total = 0;
+    for (int32_t q = q0; q < q1; ++q) rows_total += lq[4 * q + 2];
+    for (int32_t e = threadIdx.x; e < rows_total; e += blockDim.x) {
+        int32_t q = q0, rem = e;
+        while (rem >= lq[4 * q + 2]) {
+            rem -= lq[4 * q + 2];
+            ++q;
         }
+        const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
+        const int32_t krow = lq[4 * q + 3];
+        const int32_t j = rem;
+        const int32_t vj = leaf_v[tb + j];
+        const int32_t rows = min(4, tb + n - first);
+        double acc[4] = {0, 0, 0, 0};
+        for (int c = 0; c < rows; ++c) {
+            const int32_t vi = leaf_v[first + c];
+            T dot = 0;
+            for (int32_t ch = 0; ch < d; ++ch)
+                dot += gout[(int64_t)vi * d + ch] * F[(int64_t)vj * d + ch];
+            acc[c] = (double)dot;
+        }
+        for (int c = 0; c < rows; ++c)
+            if (acc[c] != 0.0) hist_add<T>(lhp, df, leaf_D[kb + krow + c * n + j], acc[c]);
     }
     if (use_lds) {
         __syncthreads();

@@ -78,9 +78,10 @@ struct tfi_plan {
     int64_t *d_b_inc_off = nullptr, *d_a_b_off = nullptr, *d_v_off = nullptr;
     int8_t* d_b_corr = nullptr;
     int32_t *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
-    // direct tables: cell list in job order, blocks of output cells
+    // direct tables: padded cell list (jobs by size), per-quad job ranges,
+    // blocks of output cells
     int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
-    int32_t *d_dl_jb = nullptr, *d_dl_je = nullptr, *d_dblk = nullptr;
+    int32_t *d_qjb = nullptr, *d_qje = nullptr, *d_dblk = nullptr;
     int64_t ndirect = 0, ndblk = 0;
     // scatter: levels of bounded segment sums
     struct SegLevel {
@@ -94,7 +95,8 @@ struct tfi_plan {
     std::vector<SegLevel> seg_levels;
     int64_t val_rows = 0;  // A-cells, b-cells, then partial rows
     // gather rows and leaf groups
-    int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr;
+    int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr, *d_lq = nullptr;
+    int64_t* d_lgk = nullptr;
     int64_t nlgrp = 0;
     int64_t gather_reads = 0;  // table values read by the gather
     int64_t *d_leaf_off = nullptr, *d_leaf_doff = nullptr;
@@ -241,22 +243,14 @@ int upload_plan(tfi_plan* h) {
     if ((rc = h->upload(&h->d_leaf_doff, p.leaf_doff))) return rc;
     if ((rc = h->upload(&h->d_leaf_D, p.leaf_D))) return rc;
 
-    // direct-method cells in job order, with each cell's job range
-    std::vector<int32_t> dl_r, dl_x, dl_row, dl_jb, dl_je, dblk;
+    std::vector<int64_t> djobs;  // direct-method jobs
     std::map<std::pair<int, int>, size_t> bidx;
     const int64_t J = (int64_t)p.job_H.size();
     int maxlg = 1;
     for (int64_t j = 0; j < J; ++j) {
         const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
         if (p.job_method[j] == tfi::METHOD_DIRECT) {
-            const int32_t jb = (int32_t)dl_r.size(), je = jb + (ce - cb);
-            for (int32_t i = cb; i < ce; ++i) {
-                dl_r.push_back(p.jc_r[i]);
-                dl_x.push_back(p.jc_x[i]);
-                dl_row.push_back(p.jc_val[i]);
-                dl_jb.push_back(jb);
-                dl_je.push_back(je);
-            }
+            djobs.push_back(j);
         } else {
             auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
             auto it = bidx.find(key);
@@ -278,35 +272,59 @@ int upload_plan(tfi_plan* h) {
             maxlg = std::max(maxlg, std::max(b.lg1, b.lg2));
         }
     }
-    // blocks: whole small jobs packed up to kDirOut cells, or slices of
-    // kDirOut output cells of one large job with the whole job as sources
+    // direct cells: jobs sorted by size (largest first) so that lanes of a
+    // wavefront run equal loops, each padded to whole quads of 4 cells
+    // (padding: r = x = 0, row -1); blocks pack whole jobs up to kDirOut
+    // cells, larger jobs are cut into kDirOut-cell output slices whose
+    // sources are the whole job.
     {
-        const int32_t nd = (int32_t)dl_r.size();
-        int32_t i = 0;
-        while (i < nd) {
-            const int32_t jb = dl_jb[i], je = dl_je[i];
+        std::stable_sort(djobs.begin(), djobs.end(), [&](int64_t a, int64_t b) {
+            return p.job_cell_off[a + 1] - p.job_cell_off[a] >
+                   p.job_cell_off[b + 1] - p.job_cell_off[b];
+        });
+        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk;
+        std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
+        for (int64_t j : djobs) {
+            const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
+            const int32_t jb = (int32_t)dl_r.size();
+            const int32_t n = ce - cb, np = (n + 3) & ~3;
+            for (int32_t i = 0; i < np; ++i) {
+                const bool real = i < n;
+                dl_r.push_back(real ? p.jc_r[cb + i] : 0);
+                dl_x.push_back(real ? p.jc_x[cb + i] : 0);
+                dl_row.push_back(real ? p.jc_val[cb + i] : -1);
+            }
+            const int32_t je = jb + np;
+            for (int32_t q = 0; q < np / 4; ++q) {
+                qjb.push_back(jb);
+                qje.push_back(je);
+            }
+            jr.emplace_back(jb, je);
+        }
+        size_t k = 0;
+        while (k < jr.size()) {
+            const int32_t jb = jr[k].first, je = jr[k].second;
             if (je - jb > tfi::kDirOut) {
                 for (int32_t o = jb; o < je; o += tfi::kDirOut)
                     dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
-                i = je;
+                ++k;
                 continue;
             }
-            int32_t e = je;
-            while (e < nd && dl_je[e] - dl_jb[e] <= tfi::kDirOut &&
-                   dl_je[e] - i <= tfi::kDirOut)
-                e = dl_je[e];
-            dblk.insert(dblk.end(), {i, e, i, e});
-            i = e;
+            size_t e = k + 1;
+            while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
+            const int32_t end = jr[e - 1].second;
+            dblk.insert(dblk.end(), {jb, end, jb, end});
+            k = e;
         }
+        h->ndirect = (int64_t)dl_r.size();
+        h->ndblk = (int64_t)dblk.size() / 4;
+        if ((rc = h->upload(&h->d_dl_r, dl_r))) return rc;
+        if ((rc = h->upload(&h->d_dl_x, dl_x))) return rc;
+        if ((rc = h->upload(&h->d_dl_row, dl_row))) return rc;
+        if ((rc = h->upload(&h->d_qjb, qjb))) return rc;
+        if ((rc = h->upload(&h->d_qje, qje))) return rc;
+        if ((rc = h->upload(&h->d_dblk, dblk))) return rc;
     }
-    h->ndirect = (int64_t)dl_r.size();
-    h->ndblk = (int64_t)dblk.size() / 4;
-    if ((rc = h->upload(&h->d_dl_r, dl_r))) return rc;
-    if ((rc = h->upload(&h->d_dl_x, dl_x))) return rc;
-    if ((rc = h->upload(&h->d_dl_row, dl_row))) return rc;
-    if ((rc = h->upload(&h->d_dl_jb, dl_jb))) return rc;
-    if ((rc = h->upload(&h->d_dl_je, dl_je))) return rc;
-    if ((rc = h->upload(&h->d_dblk, dblk))) return rc;
 
     // scatter levels: every b-cell and A-cell is a run of incidences; runs
     // longer than kSeg are cut into pieces summed into partial rows, which
@@ -386,19 +404,44 @@ int upload_plan(tfi_plan* h) {
         if ((rc = h->upload(&h->d_ga, ga))) return rc;
         if ((rc = h->upload(&h->d_gb, gb))) return rc;
     }
-    // leaf groups: consecutive tiles with at most kLeafMax vertices
+    // leaf quads (4 vertices of one tile) and groups of consecutive tiles
+    // within the kernel's LDS limits
     {
-        std::vector<int32_t> grp{0};
+        std::vector<int32_t> lq, grp{0};
+        std::vector<int64_t> gk;
         const int64_t nt = (int64_t)p.leaf_off.size() - 1;
         int64_t t = 0;
         while (t < nt) {
-            int64_t e = t + 1;
-            while (e < nt && p.leaf_off[e + 1] - p.leaf_off[t] <= tfi::kLeafMax) ++e;
-            grp.push_back((int32_t)e);
+            const int64_t dbase = p.leaf_doff[t];
+            int64_t quads = 0, verts = 0, kk = 0, e = t;
+            while (e < nt) {
+                const int64_t n = p.leaf_off[e + 1] - p.leaf_off[e];
+                const int64_t nq = (n + 3) / 4;
+                if (e > t && (quads + nq > tfi::kLeafQuads || verts + n > tfi::kLeafSlots ||
+                              kk + n * n > tfi::kLeafK))
+                    break;
+                const int32_t tb = (int32_t)p.leaf_off[e];
+                const int32_t koff = (int32_t)(p.leaf_doff[e] - dbase);
+                for (int64_t q = 0; q < nq; ++q) {
+                    lq.push_back(tb + (int32_t)(4 * q));
+                    lq.push_back(tb);
+                    lq.push_back((int32_t)n);
+                    lq.push_back(koff + (int32_t)(4 * q * n));
+                }
+                quads += nq;
+                verts += n;
+                kk += n * n;
+                ++e;
+            }
+            grp.push_back((int32_t)(lq.size() / 4));
+            gk.push_back(dbase);
+            gk.push_back(kk);
             t = e;
         }
         h->nlgrp = (int64_t)grp.size() - 1;
         if ((rc = h->upload(&h->d_lgrp, grp))) return rc;
+        if ((rc = h->upload(&h->d_lq, lq))) return rc;
+        if ((rc = h->upload(&h->d_lgk, gk))) return rc;
     }
     h->spec_elems = 0;
     for (Bucket& b : h->buckets) {
@@ -432,6 +475,8 @@ int64_t lds_cells() {
     return kLdsBytes / (int64_t)sizeof(tfi::cpx<T>);
 }
 
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 // Cell sums of the rows of `src` ([N x d]) into val: A-cells, b-cells and
 // the partial rows of long runs.
 template <typename T>
@@ -440,11 +485,20 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st
     for (size_t l = 0; l < h->seg_levels.size(); ++l) {
         const tfi_plan::SegLevel& L = h->seg_levels[l];
         hipEvent_t ev = h->begin(st);
-        if (L.indexed)
-            hipLaunchKernelGGL((tfi::k_segsum<T, true>), dim3(blocks_for(L.n * d)), dim3(kThreads),
+        const bool v4 = (d % 4 == 0) && aligned16(src);
+        const int64_t nt = L.n * (v4 ? d / 4 : d);
+        if (L.indexed && v4)
+            hipLaunchKernelGGL((tfi::k_segsum<T, true, 4>), dim3(blocks_for(nt)), dim3(kThreads),
                                0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
+        else if (L.indexed)
+            hipLaunchKernelGGL((tfi::k_segsum<T, true, 1>), dim3(blocks_for(nt)), dim3(kThreads),
+                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
+        else if (d % 4 == 0)
+            hipLaunchKernelGGL((tfi::k_segsum<T, false, 4>), dim3(blocks_for(L.n * (d / 4))),
+                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
+                               (const int32_t*)nullptr, (const T*)val, val);
         else
-            hipLaunchKernelGGL((tfi::k_segsum<T, false>), dim3(blocks_for(L.n * d)),
+            hipLaunchKernelGGL((tfi::k_segsum<T, false, 1>), dim3(blocks_for(L.n * d)),
                                dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
                                (const int32_t*)nullptr, (const T*)val, val);
         h->end(st, ev, l == 0 ? "scatter" : "scatter_tail",
@@ -519,7 +573,7 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
         const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
         hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
                            (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
-                           h->d_dl_row, h->d_dl_jb, h->d_dl_je, f, flds, val, g);
+                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
         h->end(st, ev, "direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
     }
     // 4. FFT tables
@@ -576,16 +630,19 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     }
     // 5. gather (writes every row of out)
     ev = h->begin(st);
-    hipLaunchKernelGGL(tfi::k_gather<T>, dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st, p.N, d,
-                       h->d_v_off, h->d_ga, h->d_gb, g, out);
+    if (d % 4 == 0 && aligned16(out))
+        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(p.N * (d / 4))), dim3(kThreads),
+                           0, st, p.N, d, h->d_v_off, h->d_ga, h->d_gb, g, out);
+    else
+        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st,
+                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, g, out);
     h->end(st, ev, "gather",
            sz * d * (double)(h->gather_reads + p.N) + 8.0 * (double)p.v_b.size() + 8.0 * p.N);
     // 6. leaf tiles add their dense values
     if (h->nlgrp > 0) {
         ev = h->begin(st);
         hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st,
-                           d, h->d_lgrp, h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff, h->d_leaf_D,
-                           f, F, out);
+                           d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
         const double nv = (double)p.leaf_v.size();
         h->end(st, ev, "leaf", 3.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
     }
@@ -615,8 +672,8 @@ int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStr
     if (h->ndblk > 0) {
         hipEvent_t ev = h->begin(st);
         hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
-                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_dl_jb,
-                           h->d_dl_je, (const T*)val, (const T*)valg, K, df);
+                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
+                           h->d_qje, (const T*)val, (const T*)valg, K, df);
         h->end(st, ev, "df_direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
     }
     for (const Bucket& b : h->buckets) {
@@ -679,8 +736,8 @@ int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStr
     if (h->nlgrp > 0) {
         hipEvent_t ev = h->begin(st);
         hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0,
-                           st, d, h->d_lgrp, h->d_leaf_off, h->d_leaf_v, h->d_leaf_doff,
-                           h->d_leaf_D, F, gout, K, df);
+                           st, d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
+                           K, df);
         const double nv = (double)p.leaf_v.size();
         h->end(st, ev, "df_leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
     }
