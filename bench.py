@@ -81,13 +81,18 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    tfi.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # kernel durations: the same steps again with HIP events around every
+    # stage on its launch stream (direct launches instead of graph replay;
+    # the kernels are the same)
+    tfi.profile(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
     tfi.profile(False)
     stages = tfi.profile_report()
     ms_per_step = 1e3 * elapsed / args.steps

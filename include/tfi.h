@@ -87,7 +87,13 @@ typedef struct {
                                     sums, 2 = force FFT for every table    */
     uint64_t memory_budget_bytes;/* cap on device bytes held by the handle
                                     and its per-call scratch; 0 = none     */
-    int32_t reserved[8];
+    int32_t no_graphs;           /* 1 = launch kernels directly instead of
+                                    replaying captured hipGraphs           */
+    float fft_cost;              /* per-job rule: direct sums if
+                                    cells^2 <= fft_cost * P log2 P, FFT
+                                    otherwise (P = padded table cells);
+                                    0 = default (4)                        */
+    int32_t reserved[6];
 } tfi_build_opts;
 
 /*

@@ -34,7 +34,8 @@ class TFIError(RuntimeError):
 class BuildOpts(C.Structure):
     _fields_ = [("policy", C.c_int32), ("leaf_max", C.c_int32), ("device", C.c_int32),
                 ("table_method", C.c_int32), ("memory_budget_bytes", C.c_uint64),
-                ("reserved", C.c_int32 * 8)]
+                ("no_graphs", C.c_int32), ("fft_cost", C.c_float),
+                ("reserved", C.c_int32 * 6)]
 
 
 _lib = None
@@ -88,7 +89,7 @@ def check(rc):
 
 
 def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
-                 table_method="auto", memory_budget=0):
+                 table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0):
     lib = load()
     parent = np.ascontiguousarray(parent, dtype=np.int64)
     weight = np.ascontiguousarray(weight, dtype=np.int32)
@@ -101,6 +102,8 @@ def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
     o.table_method = (TABLE_METHODS[table_method] if isinstance(table_method, str)
                       else int(table_method))
     o.memory_budget_bytes = int(memory_budget)
+    o.no_graphs = 0 if graphs else 1
+    o.fft_cost = float(fft_cost)
     h = C.c_void_p()
     check(lib.tfi_build(parent.ctypes.data, weight.ctypes.data, len(parent),
                         C.byref(o), C.byref(h)))

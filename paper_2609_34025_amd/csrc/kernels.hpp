@@ -212,19 +212,22 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
 // ---------------------------------------------------------------- gather --
 // One thread per (vertex, VEC channels): adds, over the calls holding the
 // vertex, the call's table value minus the component correction (row -1
-// when the vertex is on the call's backbone). Writes every out row.
+// when the vertex is on the call's backbone), on top of the leaf-tile value
+// already stored in out for vertices of leaf tiles. Writes every out row.
 template <typename T, int VEC>
 __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off,
                          const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
-                         const T* __restrict__ g, T* __restrict__ out) {
+                         const int8_t* __restrict__ vleaf, const T* __restrict__ g,
+                         T* __restrict__ out) {
     const int32_t dv = d / VEC;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= N * dv) return;
     const int64_t v = tid / dv;
     const int32_t c = (int32_t)(tid - v * dv) * VEC;
     const int64_t k1 = v_off[v + 1];
+    const bool leaf = vleaf[v] != 0;  // out already holds the leaf tile value
     if (VEC == 4) {
-        vec4<T> s = {0, 0, 0, 0};
+        vec4<T> s = leaf ? ld4(out + v * d + c) : vec4<T>{0, 0, 0, 0};
         for (int64_t k = v_off[v]; k < k1; ++k) {
             const int32_t b = gb[k];
             add4(s, ld4(g + (int64_t)ga[k] * d + c));
@@ -232,7 +235,7 @@ __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off
         }
         st4(out + v * d + c, s);
     } else {
-        T s = 0;
+        T s = leaf ? out[v * d + c] : (T)0;
         for (int64_t k = v_off[v]; k < k1; ++k) {
             const int32_t b = gb[k];
             s += g[(int64_t)ga[k] * d + c];
@@ -247,7 +250,8 @@ __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off
 // owns 4 vertices x 4 channels of one tile. A workgroup owns a group of
 // consecutive tiles (at most kLeafQuads vertex quads and kLeafK kernel
 // entries); f(D) of every tile and the field rows (kDirCh channels at a
-// time) are staged in LDS, then out[v] += sum_j f(D[v, j]) F[j].
+// time) are staged in LDS, then out[v] = sum_j f(D[v, j]) F[j] (the gather
+// adds the cross-call terms afterwards).
 // lq[4 q .. 4 q + 3] describes quad q: (first vertex in leaf_v, tile start
 // in leaf_v, tile size, offset of the quad's first kernel row in the
 // group's f(D) block); grp holds quad ranges per group and koff the
@@ -305,7 +309,7 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
                 T* o = out + (int64_t)vtx * d + c0 + 4 * chq;
                 const int32_t left = nch - 4 * chq;
                 const T vv[4] = {acc[c].x, acc[c].y, acc[c].z, acc[c].w};
-                for (int cc = 0; cc < 4 && cc < left; ++cc) o[cc] += vv[cc];
+                for (int cc = 0; cc < 4 && cc < left; ++cc) o[cc] = vv[cc];
             }
         }
     }
@@ -351,15 +355,22 @@ __device__ void fft_axis_lds(cpx<T>* z, int lgL, int count, int es, int ls,
     }
 }
 
-// Kernel spectrum of one FFT bucket: k[a][b] = f(a + |b|) on the padded
-// L1 x L2 grid (b taken as the signed circular offset), zero outside the
-// bucket's reach a <= 2 Hmax, |b| <= Xmax; forward 2-D transform.
+// Bucket parameters of merged launches: bp[4 b .. 4 b + 3] = (lg1, lg2,
+// Hmax, Xmax) and bo[b] = the bucket's offset in the spectrum arena.
+
+// Kernel spectrum of FFT bucket blockIdx.x: k[a][b] = f(a + |b|) on the
+// padded L1 x L2 grid (b taken as the signed circular offset), zero
+// outside the bucket's reach a <= 2 Hmax, |b| <= Xmax; forward 2-D
+// transform in LDS.
 template <typename T>
-__global__ void k_spectrum_lds(int lg1, int lg2, int32_t hmax, int32_t xmax,
-                               const T* __restrict__ f, const cpx<T>* __restrict__ tw,
-                               int lgtw, cpx<T>* __restrict__ spec) {
+__global__ void k_spectrum_multi(const int32_t* __restrict__ bp, const int64_t* __restrict__ bo,
+                                 const T* __restrict__ f, const cpx<T>* __restrict__ tw, int lgtw,
+                                 cpx<T>* __restrict__ spec) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int lg1 = bp[4 * blockIdx.x], lg2 = bp[4 * blockIdx.x + 1];
+    const int32_t hmax = bp[4 * blockIdx.x + 2], xmax = bp[4 * blockIdx.x + 3];
+    cpx<T>* out = spec + bo[blockIdx.x];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         const int a = p >> lg2, b = p & (L2 - 1);
@@ -371,26 +382,30 @@ __global__ void k_spectrum_lds(int lg1, int lg2, int32_t hmax, int32_t xmax,
     __syncthreads();
     fft_axis_lds<T, false>(z, lg2, L1, 1, L2, tw, lgtw);
     fft_axis_lds<T, false>(z, lg1, L2, L2, 1, tw, lgtw);
-    for (int p = threadIdx.x; p < P; p += blockDim.x) spec[p] = z[p];
+    for (int p = threadIdx.x; p < P; p += blockDim.x) out[p] = z[p];
 }
 
 // FFT convolution of LDS-resident tables: one workgroup per (job, channel
-// pair). Two real channels ride in the real and imaginary parts of one
-// complex table (the kernel is real, so the two results separate again in
-// the real and imaginary parts of the output). Source cell (r, x) goes to
-// row (-r mod L1): the Hankel dependence on q + r becomes a circular
+// pair); fj[3 j .. 3 j + 2] = (first cell, end cell, bucket) of job j.
+// Two real channels ride in the real and imaginary parts of one complex
+// table (the kernel is real, so the two results separate again in the
+// real and imaginary parts of the output). Source cell (r, x) goes to row
+// (-r mod L1): the Hankel dependence on q + r becomes a circular
 // convolution whose output row q needs no shift.
 template <typename T>
-__global__ void k_fft_conv_lds(int lg1, int lg2, const int32_t* __restrict__ jobs,
-                               const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
-                               const int32_t* __restrict__ jc_val, int32_t d,
-                               const T* __restrict__ val, T* __restrict__ g,
-                               const cpx<T>* __restrict__ spec, const cpx<T>* __restrict__ tw,
-                               int lgtw) {
+__global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* __restrict__ bp,
+                                 const int64_t* __restrict__ bo,
+                                 const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                                 const int32_t* __restrict__ jc_val, int32_t d,
+                                 const T* __restrict__ val, T* __restrict__ g,
+                                 const cpx<T>* __restrict__ spec_all,
+                                 const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int32_t cb = fj[3 * blockIdx.x], ce = fj[3 * blockIdx.x + 1], bk = fj[3 * blockIdx.x + 2];
+    const int lg1 = bp[4 * bk], lg2 = bp[4 * bk + 1];
+    const cpx<T>* spec = spec_all + bo[bk];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
-    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
     const int32_t c0 = 2 * blockIdx.y, c1 = c0 + 1;
     const bool has1 = c1 < d;
     for (int p = threadIdx.x; p < P; p += blockDim.x) z[p] = {(T)0, (T)0};

@@ -517,7 +517,7 @@ int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
                const PlanOptions& opt, Plan& plan, std::string& err) {
     plan = Plan();
     if (opt.policy < 0 || opt.policy > 2 || opt.table_method < 0 ||
-        opt.table_method > 2 || opt.leaf_max < 0) {
+        opt.table_method > 2 || opt.leaf_max < 0 || !(opt.fft_cost > 0.0)) {
         err = "tfi_build: invalid option";
         return kErrArg;
     }
@@ -547,7 +547,7 @@ int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
         int64_t P = L1 * L2;
         int64_t nc = plan.job_cell_off[j + 1] - plan.job_cell_off[j];
         double direct = (double)nc * (double)nc;
-        double fft = 4.0 * (double)P * std::log2((double)std::max<int64_t>(P, 2));
+        double fft = opt.fft_cost * (double)P * std::log2((double)std::max<int64_t>(P, 2));
         int32_t m;
         if (opt.table_method == 1) m = METHOD_DIRECT;
         else if (opt.table_method == 2) m = METHOD_FFT;

@@ -32,6 +32,7 @@ struct PlanOptions {
     int32_t policy = 0;       // 0 adaptive, 1 diameter, 2 centroid
     int32_t leaf_max = 32;    // dense tiles for subtrees up to this size
     int32_t table_method = 0; // 0 choose, 1 direct, 2 fft
+    double fft_cost = 4.0;    // direct iff cells^2 <= fft_cost * P log2 P
 };
 
 struct Plan {

@@ -1,16 +1,22 @@
 // tfi.hip -- runtime and C ABI of libtfi.so (declared in include/tfi.h).
 //
 // tfi_build plans on the host (plan.cpp) and uploads the plan once.
-// tfi_integrate enqueues, on the caller's stream:
-//   spectra (per FFT bucket) -> scatter -> direct tables -> FFT tables
-//   -> gather -> leaf tiles.
-// tfi_backward enqueues the same forward on gout for dF (the kernel matrix
-// f(D) is symmetric) and the pair histograms for df.
+// tfi_integrate enqueues one forward pass as a small DAG over three
+// streams of the handle:
+//   main : scatter -> direct tables ----------------> gather
+//   side1: kernel spectra -> (after scatter) FFT tables --^
+//   side2: leaf tiles (store into out) -------------------^
+// joined before the gather, which adds the cross-call terms onto the leaf
+// rows. The DAG is captured once per (dtype, d, pointers) into a hipGraph
+// and replayed (a small LRU cache of executable graphs per handle).
+// tfi_backward runs the same forward on gout for dF (the kernel matrix f(D)
+// is symmetric) and the pair histograms for df as a second DAG.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -40,11 +46,13 @@ int fail(int code, const std::string& msg) {
     } while (0)
 
 constexpr int kThreads = 256;
-constexpr int64_t kLdsBytes = 64 * 1024;
+constexpr int kGraphCache = 16;
 
 inline unsigned blocks_for(int64_t n, int threads = kThreads) {
     return (unsigned)((n + threads - 1) / threads);
 }
+
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 struct Bucket {
     int lg1 = 0, lg2 = 0;
@@ -59,9 +67,31 @@ struct Bucket {
     int64_t njobs() const { return (int64_t)jobs.size() / 2; }
 };
 
+// FFT buckets that fit LDS are launched together per tier of LDS size.
+struct Tier {
+    int64_t lds_bytes = 0;      // dynamic LDS of the merged launch
+    int64_t nbuckets = 0, njobs = 0;
+    int32_t* d_bp = nullptr;    // (lg1, lg2, Hmax, Xmax) per bucket
+    int64_t* d_bo = nullptr;    // spectrum offset per bucket
+    int32_t* d_fj = nullptr;    // (cell_beg, cell_end, bucket) per job
+    double bytes_per_d = 0, bytes_fixed = 0, spec_bytes = 0;
+};
+
 struct DeviceBuf {
     void* p = nullptr;
     size_t bytes = 0;
+};
+
+struct GraphKey {
+    int kind = 0, dtype = 0;
+    int64_t d = 0;
+    const void* p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool operator==(const GraphKey& o) const {
+        if (kind != o.kind || dtype != o.dtype || d != o.d) return false;
+        for (int i = 0; i < 5; ++i)
+            if (p[i] != o.p[i]) return false;
+        return true;
+    }
 };
 
 }  // namespace
@@ -74,10 +104,8 @@ struct tfi_plan {
     std::vector<void*> allocs;
 
     // plan arrays on the device
-    int32_t *d_inc_v = nullptr, *d_v_b = nullptr, *d_b2a = nullptr;
-    int64_t *d_b_inc_off = nullptr, *d_a_b_off = nullptr, *d_v_off = nullptr;
-    int8_t* d_b_corr = nullptr;
-    int32_t *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
+    int32_t *d_inc_v = nullptr, *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
+    int64_t* d_v_off = nullptr;
     // direct tables: padded cell list (jobs by size), per-quad job ranges,
     // blocks of output cells
     int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
@@ -94,23 +122,38 @@ struct tfi_plan {
     };
     std::vector<SegLevel> seg_levels;
     int64_t val_rows = 0;  // A-cells, b-cells, then partial rows
-    // gather rows and leaf groups
+    // gather rows, leaf flags and leaf groups
     int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr, *d_lq = nullptr;
+    int8_t* d_vleaf = nullptr;
     int64_t* d_lgk = nullptr;
     int64_t nlgrp = 0;
     int64_t gather_reads = 0;  // table values read by the gather
-    int64_t *d_leaf_off = nullptr, *d_leaf_doff = nullptr;
     int32_t *d_leaf_v = nullptr, *d_leaf_D = nullptr;
     std::vector<Bucket> buckets;
+    Tier tiers[2][3];               // [float/double][LDS tier]
+    std::vector<int> global_b[2];   // buckets beyond LDS, per dtype
     int64_t spec_elems = 0;
     int lgtw = 1;
     void* d_tw[2] = {nullptr, nullptr};  // float / double twiddles
+    int64_t lds_max = 65536;        // bytes of LDS a workgroup may use
 
     // per-dtype scratch (grow-only)
-    DeviceBuf val[2], g[2], spec[2], fftbuf[2], ftab[2], valg[2], dfbuf[2];
-    int64_t lds_max = 65536;  // bytes of LDS a workgroup may use
+    DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2];
 
-    // stage profiling: event pairs recorded on the launch stream
+    // streams, fork/join events, graph cache
+    hipStream_t s1 = nullptr, s2 = nullptr, cs0 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_a = nullptr, ev_b = nullptr, ev_c = nullptr,
+               ev_in = nullptr, ev_out = nullptr;
+    bool use_graphs = true;
+    struct GraphEntry {
+        GraphKey key;
+        hipGraphExec_t exec;
+        uint64_t last;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t tick = 0;
+
+    // stage profiling: event pairs recorded on the launch streams
     struct Tally {
         int64_t launches = 0;
         double ms = 0, bytes = 0;
@@ -149,25 +192,32 @@ struct tfi_plan {
         pending.push_back({stage, e0, e1, bytes});
     }
 
+    void drop_graphs() {
+        for (auto& g_ : graphs) (void)hipGraphExecDestroy(g_.exec);
+        graphs.clear();
+    }
+
     ~tfi_plan() {
-        if (device >= 0) {
-            int prev = 0;
-            if (hipGetDevice(&prev) == hipSuccess) {
-                (void)hipSetDevice(device);
-                for (auto& q : pending) {
-                    (void)hipEventSynchronize(q.e1);
-                    pool.push_back(q.e0);
-                    pool.push_back(q.e1);
-                }
-                for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-                for (void* p : allocs) (void)hipFree(p);
-                for (int t = 0; t < 2; ++t)
-                    for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &ftab[t],
-                                         &valg[t], &dfbuf[t]})
-                        if (b->p) (void)hipFree(b->p);
-                (void)hipSetDevice(prev);
-            }
+        if (device < 0) return;
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess) return;
+        (void)hipSetDevice(device);
+        (void)hipDeviceSynchronize();
+        drop_graphs();
+        for (auto& q : pending) {
+            pool.push_back(q.e0);
+            pool.push_back(q.e1);
         }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : {ev_fork, ev_a, ev_b, ev_c, ev_in, ev_out})
+            if (e) (void)hipEventDestroy(e);
+        for (hipStream_t s : {s1, s2, cs0})
+            if (s) (void)hipStreamDestroy(s);
+        for (void* p : allocs) (void)hipFree(p);
+        for (int t = 0; t < 2; ++t)
+            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t]})
+                if (b->p) (void)hipFree(b->p);
+        (void)hipSetDevice(prev);
     }
 
     int dalloc(void** p, size_t bytes) {
@@ -195,10 +245,13 @@ struct tfi_plan {
         return TFI_OK;
     }
 
+    // Grow a scratch buffer; graphs that captured the old address are
+    // dropped after the device has drained.
     int ensure(DeviceBuf& b, size_t bytes) {
         if (b.bytes >= bytes && b.p) return TFI_OK;
         if (b.p) {
             TFI_HIP(hipDeviceSynchronize());
+            drop_graphs();
             TFI_HIP(hipFree(b.p));
             dev_bytes -= b.bytes;
             b.p = nullptr;
@@ -229,19 +282,17 @@ int upload_plan(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
     if ((rc = h->upload(&h->d_inc_v, p.inc_v))) return rc;
-    if ((rc = h->upload(&h->d_b_inc_off, p.b_inc_off))) return rc;
-    if ((rc = h->upload(&h->d_a_b_off, p.a_b_off))) return rc;
-    if ((rc = h->upload(&h->d_b2a, p.b2a))) return rc;
-    if ((rc = h->upload(&h->d_b_corr, p.b_corr))) return rc;
     if ((rc = h->upload(&h->d_v_off, p.v_off))) return rc;
-    if ((rc = h->upload(&h->d_v_b, p.v_b))) return rc;
     if ((rc = h->upload(&h->d_jc_r, p.jc_r))) return rc;
     if ((rc = h->upload(&h->d_jc_x, p.jc_x))) return rc;
     if ((rc = h->upload(&h->d_jc_val, p.jc_val))) return rc;
-    if ((rc = h->upload(&h->d_leaf_off, p.leaf_off))) return rc;
     if ((rc = h->upload(&h->d_leaf_v, p.leaf_v))) return rc;
-    if ((rc = h->upload(&h->d_leaf_doff, p.leaf_doff))) return rc;
     if ((rc = h->upload(&h->d_leaf_D, p.leaf_D))) return rc;
+    {
+        std::vector<int8_t> vleaf(p.N, 0);
+        for (int32_t v : p.leaf_v) vleaf[v] = 1;
+        if ((rc = h->upload(&h->d_vleaf, vleaf))) return rc;
+    }
 
     std::vector<int64_t> djobs;  // direct-method jobs
     std::map<std::pair<int, int>, size_t> bidx;
@@ -450,6 +501,59 @@ int upload_plan(tfi_plan* h) {
         b.spec_off = h->spec_elems;
         h->spec_elems += b.P();
     }
+    // LDS tiers per dtype: up to 16 KiB, up to 64 KiB, up to the device
+    // limit; larger tables take the global-memory passes
+    for (int ti = 0; ti < 2; ++ti) {
+        const int64_t cs = ti ? (int64_t)sizeof(tfi::cpx<double>) : (int64_t)sizeof(tfi::cpx<float>);
+        const int64_t lim[3] = {16384, 65536, h->lds_max};
+        std::vector<int32_t> bp[3], fj[3];
+        std::vector<int64_t> bo[3];
+        for (size_t bi = 0; bi < h->buckets.size(); ++bi) {
+            const Bucket& b = h->buckets[bi];
+            const int64_t bytes = b.P() * cs;
+            int t = 0;
+            while (t < 3 && bytes > lim[t]) ++t;
+            if (t == 3) {
+                h->global_b[ti].push_back((int)bi);
+                continue;
+            }
+            Tier& T = h->tiers[ti][t];
+            const int32_t local = (int32_t)(bp[t].size() / 4);
+            bp[t].insert(bp[t].end(), {b.lg1, b.lg2, b.hmax, b.xmax});
+            bo[t].push_back(b.spec_off);
+            for (int64_t j = 0; j < b.njobs(); ++j)
+                fj[t].insert(fj[t].end(), {b.jobs[2 * j], b.jobs[2 * j + 1], local});
+            T.lds_bytes = std::max(T.lds_bytes, bytes);
+            T.bytes_per_d += 2.0 * (double)b.cells;
+            T.bytes_fixed += 12.0 * (double)b.cells;
+            T.spec_bytes += 2.0 * (double)b.P();
+        }
+        for (int t = 0; t < 3; ++t) {
+            Tier& T = h->tiers[ti][t];
+            T.nbuckets = (int64_t)bo[t].size();
+            T.njobs = (int64_t)fj[t].size() / 3;
+            if (!T.nbuckets) continue;
+            if ((rc = h->upload(&T.d_bp, bp[t]))) return rc;
+            if ((rc = h->upload(&T.d_bo, bo[t]))) return rc;
+            if ((rc = h->upload(&T.d_fj, fj[t]))) return rc;
+        }
+    }
+    // LDS beyond 64 KiB needs an opt-in per kernel
+    if (h->lds_max > 65536) {
+        const int lds = (int)h->lds_max;
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_lds<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_lds<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
     // twiddles exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), from long double
     h->lgtw = maxlg;
     const int64_t TW = (int64_t)1 << h->lgtw, nt = TW / 2;
@@ -467,15 +571,14 @@ int upload_plan(tfi_plan* h) {
     if ((rc = h->upload(&td, twd))) return rc;
     h->d_tw[0] = tf;
     h->d_tw[1] = td;
+    // side streams (default priority) and fork/join events
+    TFI_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
+    TFI_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
+    TFI_HIP(hipStreamCreateWithFlags(&h->cs0, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_in, &h->ev_out})
+        TFI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return TFI_OK;
 }
-
-template <typename T>
-int64_t lds_cells() {
-    return kLdsBytes / (int64_t)sizeof(tfi::cpx<T>);
-}
-
-inline bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 // Cell sums of the rows of `src` ([N x d]) into val: A-cells, b-cells and
 // the partial rows of long runs.
@@ -507,195 +610,259 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st
     }
 }
 
-// Forward integration out = f(D) F on `stream`.
+// Global-memory FFT passes of one bucket (tables beyond LDS): forward
+// transform of (job, channel pair) slots, product with the spectrum,
+// inverse, read-back.
 template <typename T>
-int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T* g,
+                       const tfi::cpx<T>* spec, const tfi::cpx<T>* tw, tfi::cpx<T>* buf,
+                       size_t buf_bytes, hipStream_t st) {
+    const int32_t npairs = (d + 1) / 2;
+    const int64_t slots_cap =
+        std::min<int64_t>(65535, (int64_t)(buf_bytes / sizeof(tfi::cpx<T>)) / b.P());
+    const int64_t jobs_per_chunk = std::max<int64_t>(1, slots_cap / npairs);
+    const int lgP = b.lg1 + b.lg2;
+    for (int64_t j0 = 0; j0 < b.njobs(); j0 += jobs_per_chunk) {
+        const int64_t nj = std::min(jobs_per_chunk, b.njobs() - j0);
+        const int64_t nslots = nj * npairs;
+        const int32_t* jobs = b.d_jobs + 2 * j0;
+        hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * b.P())),
+                           dim3(kThreads), 0, st, buf, nslots * b.P());
+        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
+                           st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                           h->d_jc_val, d, val, buf);
+        const unsigned nb = blocks_for(nslots * b.P() / 2);
+        for (int s = 0; s < b.lg2; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                               st, buf, nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
+                               h->lgtw);
+        for (int s = 0; s < b.lg1; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
+                               st, buf, nslots, lgP, b.lg1, b.lg1 - 1 - s, (int64_t)1 << b.lg2,
+                               tw, h->lgtw);
+        hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
+                           dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
+        for (int s = 0; s < b.lg1; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
+                               st, buf, nslots, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
+        for (int s = 0; s < b.lg2; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
+                               st, buf, nslots, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
+                           0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                           h->d_jc_val, d, buf, g);
+    }
+}
+
+template <typename T>
+int prepare_forward(tfi_plan* h, int32_t d) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    const int64_t rows = p.NA + p.NB;  // table-value rows
     int rc;
     if ((rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
         return rc;
-    if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(rows, 1) * d * sizeof(T)))) return rc;
+    if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
+        return rc;
     if ((rc = h->ensure(h->spec[ti],
                         (size_t)std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>))))
         return rc;
-    T* val = (T*)h->val[ti].p;
-    T* g = (T*)h->g[ti].p;
-    tfi::cpx<T>* spec = (tfi::cpx<T>*)h->spec[ti].p;
-    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
-    const int64_t ldsc = lds_cells<T>();
+    // workspace for buckets beyond LDS: chunks of at most 2 GiB (and 65535
+    // job-channel-pair slots)
     const int32_t npairs = (d + 1) / 2;
-
-    // FFT workspace for buckets beyond LDS: jobs are processed in chunks
-    // of at most 2 GiB (and 65535 job-channel-pair slots) per chunk
     size_t want = 0;
-    for (const Bucket& b : h->buckets) {
-        if (b.P() <= ldsc) continue;
+    for (int bi : h->global_b[ti]) {
+        const Bucket& b = h->buckets[bi];
         const size_t one_job = (size_t)b.P() * npairs * sizeof(tfi::cpx<T>);
         const size_t all = one_job * (size_t)b.njobs();
         want = std::max(want, std::max(one_job, std::min(all, (size_t)2 << 30)));
     }
     if (want && (rc = h->ensure(h->fftbuf[ti], want))) return rc;
-
-    const double sz = (double)sizeof(T);
-    const int64_t I = (int64_t)p.inc_v.size();
-    // 1. kernel spectra per bucket
-    hipEvent_t ev = h->begin(st);
-    double spec_bytes = 0;
-    for (const Bucket& b : h->buckets) {
-        spec_bytes += 2.0 * sz * (double)b.P() + sz * (2.0 * b.hmax + b.xmax + 1);
-        if (b.P() <= ldsc) {
-            hipLaunchKernelGGL(tfi::k_spectrum_lds<T>, dim3(1), dim3(kThreads),
-                               (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1, b.lg2, b.hmax,
-                               b.xmax, f, tw, h->lgtw, spec + b.spec_off);
-        } else {
-            tfi::cpx<T>* z = spec + b.spec_off;
-            hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads),
-                               0, st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
-            const int lgP = b.lg1 + b.lg2;
-            for (int s = 0; s < b.lg2; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                                   dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
-                                   (int64_t)1, tw, h->lgtw);
-            for (int s = 0; s < b.lg1; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                                   dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
-                                   (int64_t)1 << b.lg2, tw, h->lgtw);
-        }
-    }
-    if (!h->buckets.empty()) h->end(st, ev, "spectrum", spec_bytes);
-    // 2. scatter: levels of bounded segment sums
-    launch_scatter<T>(h, F, val, d, st);
-    // 3. direct tables
-    if (h->ndblk > 0) {
-        ev = h->begin(st);
-        const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
-        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
-                           (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
-                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
-        h->end(st, ev, "direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
-    }
-    // 4. FFT tables
-    for (const Bucket& b : h->buckets) {
-        const int64_t cells = b.cells;
-        const double fft_bytes = 2.0 * sz * d * (double)cells + 12.0 * cells + 2.0 * sz * b.P();
-        if (b.P() <= ldsc) {
-            ev = h->begin(st);
-            hipLaunchKernelGGL(tfi::k_fft_conv_lds<T>, dim3((unsigned)b.njobs(), npairs),
-                               dim3(kThreads), (unsigned)(b.P() * sizeof(tfi::cpx<T>)), st, b.lg1,
-                               b.lg2, b.d_jobs, h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g,
-                               spec + b.spec_off, tw, h->lgtw);
-            h->end(st, ev, "fft_lds", fft_bytes);
-            continue;
-        }
-        ev = h->begin(st);
-        tfi::cpx<T>* buf = (tfi::cpx<T>*)h->fftbuf[ti].p;
-        const int64_t slots_cap = std::min<int64_t>(
-            65535, (int64_t)(h->fftbuf[ti].bytes / sizeof(tfi::cpx<T>)) / b.P());
-        const int64_t jobs_per_chunk = std::max<int64_t>(1, slots_cap / npairs);
-        const int lgP = b.lg1 + b.lg2;
-        for (int64_t j0 = 0; j0 < b.njobs(); j0 += jobs_per_chunk) {
-            const int64_t nj = std::min(jobs_per_chunk, b.njobs() - j0);
-            const int64_t nslots = nj * npairs;
-            const int32_t* jobs = b.d_jobs + 2 * j0;
-            hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * b.P())),
-                               dim3(kThreads), 0, st, buf, nslots * b.P());
-            hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                               0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r,
-                               h->d_jc_x, h->d_jc_val, d, val, buf);
-            const unsigned nb = blocks_for(nslots * b.P() / 2);
-            for (int s = 0; s < b.lg2; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, buf, nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
-                                   h->lgtw);
-            for (int s = 0; s < b.lg1; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, buf, nslots, lgP, b.lg1, b.lg1 - 1 - s,
-                                   (int64_t)1 << b.lg2, tw, h->lgtw);
-            hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
-                               dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
-            for (int s = 0; s < b.lg1; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
-                                   st, buf, nslots, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw,
-                                   h->lgtw);
-            for (int s = 0; s < b.lg2; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
-                                   st, buf, nslots, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
-            hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots),
-                               dim3(kThreads), 0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs,
-                               h->d_jc_r, h->d_jc_x, h->d_jc_val, d, buf, g);
-        }
-        h->end(st, ev, "fft_global", fft_bytes);
-    }
-    // 5. gather (writes every row of out)
-    ev = h->begin(st);
-    if (d % 4 == 0 && aligned16(out))
-        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(p.N * (d / 4))), dim3(kThreads),
-                           0, st, p.N, d, h->d_v_off, h->d_ga, h->d_gb, g, out);
-    else
-        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st,
-                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, g, out);
-    h->end(st, ev, "gather",
-           sz * d * (double)(h->gather_reads + p.N) + 8.0 * (double)p.v_b.size() + 8.0 * p.N);
-    // 6. leaf tiles add their dense values
-    if (h->nlgrp > 0) {
-        ev = h->begin(st);
-        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st,
-                           d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
-        const double nv = (double)p.leaf_v.size();
-        h->end(st, ev, "leaf", 3.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
-    }
-    TFI_HIP(hipGetLastError());
     return TFI_OK;
 }
 
-// Kernel-table gradient df (FP64, length kernel_len) for L = sum(gout * out).
+// Enqueue out = f(D) F: `s0` is the main stream, s1/s2 the side streams.
 template <typename T>
-int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t st) {
+void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
+                     hipStream_t s1, hipStream_t s2) {
     const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    T* val = (T*)h->val[ti].p;
+    T* g = (T*)h->g[ti].p;
+    tfi::cpx<T>* spec = (tfi::cpx<T>*)h->spec[ti].p;
+    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
+    const int32_t npairs = (d + 1) / 2;
+    const double sz = (double)sizeof(T);
+    hipEvent_t ev;
+
+    (void)hipEventRecord(h->ev_fork, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
+    (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
+
+    // side2: leaf tiles store their dense values into out
+    if (h->nlgrp > 0) {
+        ev = h->begin(s2);
+        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, s2,
+                           d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
+        const double nv = (double)p.leaf_v.size();
+        h->end(s2, ev, "leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+    }
+    (void)hipEventRecord(h->ev_c, s2);
+
+    // side1: kernel spectra of every FFT bucket
+    for (int t = 0; t < 3; ++t) {
+        const Tier& T_ = h->tiers[ti][t];
+        if (!T_.nbuckets) continue;
+        ev = h->begin(s1);
+        hipLaunchKernelGGL(tfi::k_spectrum_multi<T>, dim3((unsigned)T_.nbuckets), dim3(kThreads),
+                           (unsigned)T_.lds_bytes, s1, T_.d_bp, T_.d_bo, f, tw, h->lgtw, spec);
+        h->end(s1, ev, "spectrum", sz * T_.spec_bytes);
+    }
+    for (int bi : h->global_b[ti]) {
+        const Bucket& b = h->buckets[bi];
+        ev = h->begin(s1);
+        tfi::cpx<T>* z = spec + b.spec_off;
+        hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads), 0,
+                           s1, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
+        const int lgP = b.lg1 + b.lg2;
+        for (int s = 0; s < b.lg2; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
+                               dim3(kThreads), 0, s1, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
+                               (int64_t)1, tw, h->lgtw);
+        for (int s = 0; s < b.lg1; ++s)
+            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
+                               dim3(kThreads), 0, s1, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
+                               (int64_t)1 << b.lg2, tw, h->lgtw);
+        h->end(s1, ev, "spectrum_global", 2.0 * sz * (double)b.P());
+    }
+
+    // main: scatter
+    launch_scatter<T>(h, F, val, d, s0);
+    (void)hipEventRecord(h->ev_a, s0);
+
+    // side1: FFT tables once the cell sums exist
+    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+    for (int t = 0; t < 3; ++t) {
+        const Tier& T_ = h->tiers[ti][t];
+        if (!T_.njobs) continue;
+        ev = h->begin(s1);
+        hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, npairs),
+                           dim3(kThreads), (unsigned)T_.lds_bytes, s1, T_.d_fj, T_.d_bp, T_.d_bo,
+                           h->d_jc_r, h->d_jc_x, h->d_jc_val, d, (const T*)val, g,
+                           (const tfi::cpx<T>*)spec, tw, h->lgtw);
+        h->end(s1, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
+    }
+    for (int bi : h->global_b[ti]) {
+        const Bucket& b = h->buckets[bi];
+        ev = h->begin(s1);
+        launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)h->fftbuf[ti].p,
+                             h->fftbuf[ti].bytes, s1);
+        h->end(s1, ev, "fft_global",
+               2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
+    }
+    (void)hipEventRecord(h->ev_b, s1);
+
+    // main: direct tables
+    if (h->ndblk > 0) {
+        ev = h->begin(s0);
+        const int32_t flds =
+            (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
+        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                           (unsigned)(flds * sizeof(T)), s0, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
+                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, (const T*)val, g);
+        h->end(s0, ev, "direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
+    }
+
+    // join, then the gather writes every row of out
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    ev = h->begin(s0);
+    if (d % 4 == 0 && aligned16(out))
+        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(p.N * (d / 4))), dim3(kThreads),
+                           0, s0, p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, (const T*)g,
+                           out);
+    else
+        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, s0,
+                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, (const T*)g, out);
+    h->end(s0, ev, "gather",
+           sz * d * (double)(h->gather_reads + 2 * p.N) + 8.0 * (double)p.v_b.size() + 9.0 * p.N);
+}
+
+template <typename T>
+int prepare_df(tfi_plan* h, int32_t d) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
     const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
     int rc;
     if ((rc = h->ensure(h->val[ti], rowbytes))) return rc;
     if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
+    const int32_t npairs = (d + 1) / 2;
+    size_t want = 0;
+    for (const Bucket& b : h->buckets) {
+        const int64_t P = b.P();
+        if (3 * P * (int64_t)sizeof(tfi::cpx<T>) <= h->lds_max) continue;
+        const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
+        const int64_t cap = (int64_t)2 << 30;
+        const int64_t jpc = std::max<int64_t>(
+            1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
+        want = std::max(want, (size_t)(std::min(jpc, b.njobs()) * per_job));
+    }
+    if (want && (rc = h->ensure(h->dfbuf[ti], want))) return rc;
+    return TFI_OK;
+}
+
+// Enqueue the kernel-table gradient df (FP64, kernel_len entries).
+template <typename T>
+void enqueue_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t s0,
+                hipStream_t s1, hipStream_t s2) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
     T* val = (T*)h->val[ti].p;
     T* valg = (T*)h->valg[ti].p;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const int32_t K = (int32_t)p.kernel_len;
     const int32_t npairs = (d + 1) / 2;
     const double sz = (double)sizeof(T);
-    hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(K)), dim3(kThreads), 0, st, df,
+    hipEvent_t ev;
+    hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(K)), dim3(kThreads), 0, s0, df,
                        (int64_t)K);
-    launch_scatter<T>(h, F, val, d, st);
-    launch_scatter<T>(h, gout, valg, d, st);
-    if (h->ndblk > 0) {
-        hipEvent_t ev = h->begin(st);
-        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
-                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                           h->d_qje, (const T*)val, (const T*)valg, K, df);
-        h->end(st, ev, "df_direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
+    (void)hipEventRecord(h->ev_fork, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
+    (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
+    // side2: leaf pair histograms straight from F and gout
+    if (h->nlgrp > 0) {
+        ev = h->begin(s2);
+        hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0,
+                           s2, d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
+                           K, df);
+        const double nv = (double)p.leaf_v.size();
+        h->end(s2, ev, "df_leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
     }
+    (void)hipEventRecord(h->ev_c, s2);
+    // cell sums of gout on side1, of F on main
+    launch_scatter<T>(h, gout, valg, d, s1);
+    (void)hipEventRecord(h->ev_b, s1);
+    launch_scatter<T>(h, F, val, d, s0);
+    (void)hipEventRecord(h->ev_a, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    // side1: FFT-table cross-correlations
     for (const Bucket& b : h->buckets) {
         const int64_t P = b.P();
         const double bytes = 2.0 * sz * d * (double)b.cells + 12.0 * b.cells;
         if (3 * P * (int64_t)sizeof(tfi::cpx<T>) <= h->lds_max) {
-            hipEvent_t ev = h->begin(st);
+            ev = h->begin(s1);
             hipLaunchKernelGGL(tfi::k_df_fft_lds<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
-                               (unsigned)(3 * P * sizeof(tfi::cpx<T>)), st, b.lg1, b.lg2, p.NA,
+                               (unsigned)(3 * P * sizeof(tfi::cpx<T>)), s1, b.lg1, b.lg2, p.NA,
                                b.d_jobs, b.d_hx, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
                                (const T*)val, (const T*)valg, tw, h->lgtw, df);
-            h->end(st, ev, "df_fft_lds", bytes);
+            h->end(s1, ev, "df_fft_lds", bytes);
             continue;
         }
-        // global memory: chunks of jobs, 2 tables per (job, pair) slot
         const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
         const int64_t cap = (int64_t)2 << 30;
         const int64_t jpc = std::max<int64_t>(
             1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
-        if ((rc = h->ensure(h->dfbuf[ti], (size_t)(std::min(jpc, b.njobs()) * per_job)))) return rc;
         tfi::cpx<T>* bv = (tfi::cpx<T>*)h->dfbuf[ti].p;
-        hipEvent_t ev = h->begin(st);
+        ev = h->begin(s1);
         const int lgP = b.lg1 + b.lg2;
         for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
             const int64_t nj = std::min(jpc, b.njobs() - j0);
@@ -704,45 +871,128 @@ int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStr
             tfi::cpx<T>* acc = bg + nslots * P;
             const int32_t* jobs = b.d_jobs + 2 * j0;
             hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(2 * nslots * P)),
-                               dim3(kThreads), 0, st, bv, 2 * nslots * P);
+                               dim3(kThreads), 0, s1, bv, 2 * nslots * P);
             hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                               0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                               0, s1, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
                                h->d_jc_val, d, (const T*)val, (const T*)valg, bv, bg);
             const unsigned nb = blocks_for(2 * nslots * P / 2);
             for (int s = 0; s < b.lg2; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
+                                   s1, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
                                    h->lgtw);
             for (int s = 0; s < b.lg1; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
+                                   s1, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
                                    (int64_t)1 << b.lg2, tw, h->lgtw);
             hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
-                               dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
+                               dim3(kThreads), 0, s1, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
                                (const tfi::cpx<T>*)bg, acc);
             const unsigned na = blocks_for(nj * P / 2);
             for (int s = 0; s < b.lg1; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   st, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
+                                   s1, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
             for (int s = 0; s < b.lg2; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   st, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+                                   s1, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
             hipLaunchKernelGGL(tfi::k_fold_global<T>, dim3(blocks_for(nj * P)), dim3(kThreads), 0,
-                               st, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
+                               s1, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
                                (const tfi::cpx<T>*)acc, df);
         }
-        h->end(st, ev, "df_fft_global", bytes);
+        h->end(s1, ev, "df_fft_global", bytes);
     }
-    if (h->nlgrp > 0) {
-        hipEvent_t ev = h->begin(st);
-        hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0,
-                           st, d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
-                           K, df);
-        const double nv = (double)p.leaf_v.size();
-        h->end(st, ev, "df_leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+    (void)hipEventRecord(h->ev_b, s1);
+    // main: direct-table pair histograms
+    if (h->ndblk > 0) {
+        ev = h->begin(s0);
+        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
+                           s0, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
+                           h->d_qje, (const T*)val, (const T*)valg, K, df);
+        h->end(s0, ev, "df_direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
     }
-    TFI_HIP(hipGetLastError());
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+}
+
+// Run a DAG either eagerly on (caller stream, s1, s2) or as a cached graph
+// replayed on the handle's capture stream, ordered after the caller's
+// stream and before its later work.
+template <typename Enq>
+int run_dag(tfi_plan* h, const GraphKey& key, hipStream_t caller, Enq enq) {
+    if (h->prof || !h->use_graphs) {
+        enq(caller, h->s1, h->s2);
+        TFI_HIP(hipGetLastError());
+        return TFI_OK;
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : h->graphs)
+        if (e.key == key) {
+            exec = e.exec;
+            e.last = ++h->tick;
+            break;
+        }
+    if (!exec) {
+        hipGraph_t graph = nullptr;
+        TFI_HIP(hipStreamBeginCapture(h->cs0, hipStreamCaptureModeThreadLocal));
+        enq(h->cs0, h->s1, h->s2);
+        hipError_t le = hipGetLastError();
+        hipError_t ce = hipStreamEndCapture(h->cs0, &graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(TFI_ERR_HIP, std::string("graph capture: ") +
+                                         hipGetErrorString(le != hipSuccess ? le : ce));
+        }
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess)
+            return fail(TFI_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        if ((int)h->graphs.size() >= kGraphCache) {
+            auto it = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                       [](const tfi_plan::GraphEntry& a,
+                                          const tfi_plan::GraphEntry& b) { return a.last < b.last; });
+            TFI_HIP(hipStreamSynchronize(h->cs0));
+            (void)hipGraphExecDestroy(it->exec);
+            h->graphs.erase(it);
+        }
+        h->graphs.push_back({key, exec, ++h->tick});
+    }
+    TFI_HIP(hipEventRecord(h->ev_in, caller));
+    TFI_HIP(hipStreamWaitEvent(h->cs0, h->ev_in, 0));
+    TFI_HIP(hipGraphLaunch(exec, h->cs0));
+    TFI_HIP(hipEventRecord(h->ev_out, h->cs0));
+    TFI_HIP(hipStreamWaitEvent(caller, h->ev_out, 0));
     return TFI_OK;
+}
+
+template <typename T>
+int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+    int rc = prepare_forward<T>(h, d);
+    if (rc) return rc;
+    GraphKey key;
+    key.kind = 1;
+    key.dtype = sizeof(T) == 8;
+    key.d = d;
+    key.p[0] = f;
+    key.p[1] = F;
+    key.p[2] = out;
+    return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
+        enqueue_forward<T>(h, f, F, d, out, a, b, c);
+    });
+}
+
+template <typename T>
+int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t st) {
+    int rc = prepare_df<T>(h, d);
+    if (rc) return rc;
+    GraphKey key;
+    key.kind = 2;
+    key.dtype = sizeof(T) == 8;
+    key.d = d;
+    key.p[0] = F;
+    key.p[1] = gout;
+    key.p[2] = df;
+    return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
+        enqueue_df<T>(h, F, gout, d, df, a, b, c);
+    });
 }
 
 }  // namespace
@@ -764,6 +1014,7 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
         return fail(TFI_ERR_ARG, "tfi_build: leaf_max must be in [0, " +
                                      std::to_string(tfi::kLeafMax) + "]");
     po.table_method = o.table_method;
+    po.fft_cost = o.fft_cost == 0.0f ? 4.0 : (double)o.fft_cost;
     if (o.device < -1) return fail(TFI_ERR_ARG, "tfi_build: device must be >= -1");
     std::unique_ptr<tfi_plan> h;
     try {
@@ -775,6 +1026,9 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     int rc = tfi::build_plan(parent, weight, N, po, h->plan, err);
     if (rc) return fail(rc, err);
     h->budget = o.memory_budget_bytes;
+    h->use_graphs = o.no_graphs == 0;
+    if (const char* e = std::getenv("TFI_NO_GRAPHS"))
+        if (e[0] && e[0] != '0') h->use_graphs = false;
     if (o.device >= 0) {
         int count = 0;
         hipError_t e = hipGetDeviceCount(&count);
@@ -787,7 +1041,7 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, o.device) ==
                 hipSuccess &&
             lds > 0)
-            h->lds_max = std::min<int64_t>(lds, 65536);
+            h->lds_max = lds;
         rc = upload_plan(h.get());
         if (rc) return rc;
     }

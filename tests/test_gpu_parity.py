@@ -234,3 +234,30 @@ def test_argument_errors():
     h = TreeIntegrator(p, w, device=None)
     with pytest.raises(TFIError):
         h.integrate(f, F)                   # host-only plan
+
+
+def test_graph_replays_match_eager():
+    # Captured graphs replayed several times, with the program's own eager
+    # work and synchronisations between replays, equal the eager launches.
+    rng = np.random.default_rng(21)
+    W = S.workload("grid512", trees=24)
+    p, w = W["parent"], W["weight"]
+    tg = TreeIntegrator(p, w, device=0)
+    te = TreeIntegrator(p, w, device=0, graphs=False)
+    K = tg.kernel_length
+    f = torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=DEV)
+    F = torch.tensor(W["F"], device=DEV)
+    G = torch.tensor(rng.standard_normal(W["F"].shape), dtype=torch.float32, device=DEV)
+    ref = te.integrate(f, F)
+    rdF, rdf = te.backward(f, F, G)
+    out = torch.empty_like(F)
+    for rep in range(5):
+        y = tg.integrate(f, F)
+        junk = (F * 2.0 + rep).sum()          # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), rep
+        dF, df = tg.backward(f, F, G)
+        torch.cuda.synchronize()
+        assert torch.equal(dF, rdF), rep
+        assert torch.allclose(df, rdf, rtol=1e-12, atol=1e-9), rep
+        del junk
