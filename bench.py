@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched forest forward+backward measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -140,6 +142,8 @@ def main():
                          f"{cpu_s:.1f} s, FP64"}
         log(f"bench: oracle {cpu['value']:.3e} vertex*channels/s on {cores} threads")
 
+    batched = None if args.no_batched else batched_fwd_bwd(args, value)
+
     rec = {
         "metric": METRIC, "value": value, "unit": "vertex*channels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -153,9 +157,106 @@ def main():
         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched_fwd_bwd": batched,
         "stages": stages,
     }
     print(json.dumps(rec), flush=True)
+
+
+def batched_fwd_bwd(args, plain_value):
+    """Training step on a forest: 512 minimum spanning trees of sqrt(n) x
+    sqrt(n) grids (side uniform in {14..64}, weights U{1..16}), F[n x 64]
+    FP32, learnable kernel f(d) = sum_{k<8} a_k exp(-b_k d); loss
+    sum(W * out). One step = forward + backward (dF, da, db) through the
+    autograd function. Parity: out and dF on 512 sampled rows against the
+    oracle; da exactly against the oracle's exp-kernel recursion
+    (da_k = <W, K_k F> with K_k the single exponential e^{-b_k d}); db by a
+    central difference of that recursion in b_k."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, TreeIntegrate, expsum_table
+    from paper_2609_34025_amd import synth as S
+
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    W = S.workload("grid512")
+    gen_s = time.perf_counter() - t0
+    p, w, F = W["parent"], W["weight"], W["F"]
+    n, d = F.shape
+    t0 = time.perf_counter()
+    tfi = TreeIntegrator(p, w, device=0)
+    build_s = time.perf_counter() - t0
+    K = tfi.kernel_length
+    rng = np.random.default_rng(33)
+    Wt = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device=dev)
+    a = torch.tensor(W["a"], dtype=torch.float32, device=dev, requires_grad=True)
+    b = torch.tensor(W["b"], dtype=torch.float32, device=dev, requires_grad=True)
+    Ft = torch.tensor(F, device=dev, requires_grad=True)
+    log(f"batched: {len(W['offsets']) - 1} trees, n={n} d={d} gen {gen_s:.1f}s "
+        f"build {build_s:.2f}s kernel_length={K}")
+    res = {}
+
+    def step():
+        a.grad = b.grad = Ft.grad = None
+        out = TreeIntegrate.apply(tfi, Ft, expsum_table(a, b, K))
+        (Wt * out).sum().backward()
+        res["out"] = out
+
+    steps = max(5, args.steps // 5)
+    for _ in range(max(2, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = n * d / (el / steps)
+    log(f"batched: {1e3 * el / steps:.3f} ms/step fwd+bwd, {value:.4e} vertex*channels/s")
+    tfi.profile(True)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    tfi.profile(False)
+    stages = tfi.profile_report()
+    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"]):
+        log(f"batched stage {k:14s} {v['launches']:4d} launches {1e3 * v['ms'] / v['launches']:10.2f} "
+            f"us/launch")
+
+    # parity
+    rows = np.random.default_rng(99).choice(n, 512, replace=False)
+    A = a.detach().double().cpu().numpy()
+    B = b.detach().double().cpu().numpy()
+    ftab = (A[None, :] * np.exp(-np.arange(K)[:, None] * B[None, :])).sum(1)
+    Fd = F.astype(np.float64)
+    Wd = Wt.double().cpu().numpy()
+    ref = oracle.integrate(p, w, ftab, Fd, rows=rows)
+    y = res["out"].detach().double().cpu().numpy()[rows]
+    e_out = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    refd = oracle.integrate(p, w, ftab, Wd, rows=rows)
+    ydF = Ft.grad.double().cpu().numpy()[rows]
+    e_dF = float(np.linalg.norm(ydF - refd) / np.linalg.norm(refd))
+    da_ref = np.array([np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k])], Fd))
+                       for k in range(8)])
+    hb = 1e-5
+    db_ref = np.array([A[k] * (np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] - hb)], Fd))
+                               - np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] + hb)], Fd)))
+                       / (2 * hb) for k in range(8)])
+    e_da = float(np.linalg.norm(a.grad.double().cpu().numpy() - da_ref) / np.linalg.norm(da_ref))
+    e_db = float(np.linalg.norm(b.grad.double().cpu().numpy() - db_ref) / np.linalg.norm(db_ref))
+    errs = {"out": e_out, "dF": e_dF, "da": e_da, "db": e_db}
+    ok = all(e <= 1e-4 for e in errs.values())
+    log(f"batched: parity {errs} ok={ok}")
+    return {"value": value, "unit": "vertex*channels/s", "steps": steps,
+            "ms_per_step": 1e3 * el / steps, "ratio_vs_plain_fwd": value / plain_value,
+            "workload": "forward+backward (dF, da, db) of 512 grid-MST trees, sides U{14..64}, "
+                        "weights U{1..16}, F[n x 64] fp32, f = sum of 8 exponentials; "
+                        "loss sum(W * out)",
+            "n": int(n), "d": int(d), "trees": int(len(W["offsets"]) - 1),
+            "kernel_length": int(K), "build_s": round(build_s, 3),
+            "parity": {"rows": 512, "rel_err": errs, "ok": ok}, "stages": stages}
 
 
 if __name__ == "__main__":
