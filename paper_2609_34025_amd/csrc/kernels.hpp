@@ -554,12 +554,24 @@ namespace tfi {
 // every leaf tile adds its own dense pair histogram. Histograms accumulate
 // in FP64 (LDS bins flushed with FP64 atomics): df is reproducible to FP64
 // rounding, not bitwise.
-constexpr int kDfTile = 64, kDfThreads = 256, kDfHistLds = 4096;
+constexpr int kDfTile = 64, kDfThreads = 256;
+// LDS histogram bins: 16 KiB in the working precision
+template <typename T>
+constexpr int df_hist_bins() { return 16384 / (int)sizeof(T); }
+
+// Histogram bin add: LDS bins in the working precision when the kernel
+// table fits, else straight FP64 atomics in global memory.
+template <typename T>
+__device__ __forceinline__ void hist_add(T* lh, double* gh, int32_t k, T v) {
+    if (lh) atomicAdd(lh + k, v);
+    else atomicAdd(gh + k, (double)v);
+}
 
 template <typename T>
-__device__ __forceinline__ void hist_add(double* lh, double* gh, int32_t k, double v) {
-    if (lh) atomicAdd(lh + k, v);
-    else atomicAdd(gh + k, v);
+__device__ __forceinline__ void hist_flush(const T* lh, double* gh, int32_t K) {
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
+        if (lh[k] != (T)0) atomicAdd(gh + k, (double)lh[k]);
 }
 
 // Direct jobs: same blocks as k_direct, output cells taken 64 at a time.
@@ -574,11 +586,11 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             const T* __restrict__ valg, int32_t K, double* __restrict__ df) {
     __shared__ T sG[kDfTile * (kDirCh + 1)], sV[kDfTile * (kDirCh + 1)];
     __shared__ int32_t sr[kDfTile], sx[kDfTile];
-    __shared__ double lh[kDfHistLds];
-    const bool use_lds = K <= kDfHistLds;
-    double* lhp = use_lds ? lh : nullptr;
+    __shared__ T lh[df_hist_bins<T>()];
+    const bool use_lds = K <= df_hist_bins<T>();
+    T* lhp = use_lds ? lh : nullptr;
     if (use_lds)
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0;
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int32_t ii = threadIdx.x & (kDfTile - 1), jj0 = threadIdx.x >> 6;
     for (int32_t oc = os; oc < oe; oc += kDfTile) {
@@ -587,7 +599,7 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
         const bool iok = ii < on && dl_row[i] >= 0;
         const int32_t ri = iok ? dl_r[i] : 0, xi = iok ? dl_x[i] : 0;
         const int32_t jb = iok ? qjb[i >> 2] : 0, je = iok ? qje[i >> 2] : 0;
-        const double sign = (iok && dl_row[i] < NA) ? 1.0 : -1.0;
+        const T sign = (iok && dl_row[i] < NA) ? (T)1 : (T)-1;
         // sources: the union of the job ranges of this chunk's cells
         const int32_t ss = qjb[oc >> 2], se = qje[(oc + on - 1) >> 2];
         for (int32_t ts = ss; ts < se; ts += kDfTile) {
@@ -623,92 +635,126 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
                 const int32_t j = ts + jj0 + 4 * q;
                 if (iok && j >= jb && j < je && jj0 + 4 * q < tn && m[q] != (T)0) {
                     const int32_t dx = xi - sx[jj0 + 4 * q];
-                    hist_add<T>(lhp, df, ri + sr[jj0 + 4 * q] + (dx < 0 ? -dx : dx),
-                                sign * (double)m[q]);
+                    hist_add<T>(lhp, df, ri + sr[jj0 + 4 * q] + (dx < 0 ? -dx : dx), sign * m[q]);
                 }
             }
         }
     }
-    if (use_lds) {
-        __syncthreads();
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
-            if (lh[k] != 0.0) atomicAdd(df + k, lh[k]);
-    }
+    if (use_lds) hist_flush<T>(lh, df, K);
 }
 
-// Leaf tiles: pairs inside each tile, distance from D. One thread per
-// (quad, source vertex j) pair row: 4 dot products over all channels,
-// read through L2.
+// Leaf tiles: pairs inside each tile, distance from D. The group's gout
+// and F rows are staged in LDS kDirCh channels at a time; a thread owns up
+// to kDfLeafRows (quad, source j) rows = 4 pair dot products each.
+constexpr int kDfLeafRows = 8;
+
 template <typename T>
 __global__ void __launch_bounds__(kLeafThreads)
 k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ gk,
           const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
           const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
           const T* __restrict__ gout, int32_t K, double* __restrict__ df) {
-    __shared__ double lh[kDfHistLds];
-    const bool use_lds = K <= kDfHistLds;
-    double* lhp = use_lds ? lh : nullptr;
+    __shared__ T sG[kLeafSlots * (kDirCh + 1)], sF[kLeafSlots * (kDirCh + 1)];
+    __shared__ int32_t svtx[kLeafSlots], srow0[kLeafQuads + 1];
+    __shared__ T lh[df_hist_bins<T>()];
+    const bool use_lds = K <= df_hist_bins<T>();
+    T* lhp = use_lds ? lh : nullptr;
     if (use_lds)
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.0;
-    __syncthreads();
-    const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1];
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0;
+    const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1], nq_ = q1 - q0;
     const int64_t kb = gk[2 * blockIdx.x];
-    // enumerate (quad, j) rows of the group
-    int32_t rows_total = 0;
-    for (int32_t q = q0; q < q1; ++q) rows_total += lq[4 * q + 2];
-    for (int32_t e = threadIdx.x; e < rows_total; e += blockDim.x) {
-        int32_t q = q0, rem = e;
-        while (rem >= lq[4 * q + 2]) {
-            rem -= lq[4 * q + 2];
-            ++q;
+    const int32_t vb = lq[4 * q0 + 1];
+    const int32_t nv = lq[4 * (q1 - 1) + 1] + lq[4 * (q1 - 1) + 2] - vb;
+    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int32_t q = 0; q < nq_; ++q) {
+            srow0[q] = acc;
+            acc += lq[4 * (q0 + q) + 2];
         }
+        srow0[nq_] = acc;
+    }
+    __syncthreads();
+    const int32_t rows_total = srow0[nq_];
+    int32_t rq[kDfLeafRows], rj[kDfLeafRows];
+#pragma unroll
+    for (int r = 0; r < kDfLeafRows; ++r) {
+        const int32_t row = threadIdx.x + r * blockDim.x;
+        rq[r] = -1;
+        rj[r] = 0;
+        if (row < rows_total) {
+            int32_t q = 0;
+            while (srow0[q + 1] <= row) ++q;
+            rq[r] = q;
+            rj[r] = row - srow0[q];
+        }
+    }
+    T m[kDfLeafRows][4];
+#pragma unroll
+    for (int r = 0; r < kDfLeafRows; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) m[r][c] = 0;
+    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+        const int32_t nch = min(kDirCh, d - c0);
+        __syncthreads();
+        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
+            const int32_t i = e / nch, cc = e - i * nch;
+            sG[i * (kDirCh + 1) + cc] = gout[(int64_t)svtx[i] * d + c0 + cc];
+            sF[i * (kDirCh + 1) + cc] = F[(int64_t)svtx[i] * d + c0 + cc];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kDfLeafRows; ++r) {
+            if (rq[r] < 0) continue;
+            const int32_t q = q0 + rq[r];
+            const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
+            const int32_t rows = min(4, tb + n - first);
+            const T* fj = sF + (tb - vb + rj[r]) * (kDirCh + 1);
+            for (int32_t cc = 0; cc < nch; ++cc) {
+                const T fv = fj[cc];
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (c < rows) m[r][c] += sG[(first - vb + c) * (kDirCh + 1) + cc] * fv;
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kDfLeafRows; ++r) {
+        if (rq[r] < 0) continue;
+        const int32_t q = q0 + rq[r];
         const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
         const int32_t krow = lq[4 * q + 3];
-        const int32_t j = rem;
-        const int32_t vj = leaf_v[tb + j];
         const int32_t rows = min(4, tb + n - first);
-        double acc[4] = {0, 0, 0, 0};
-        for (int c = 0; c < rows; ++c) {
-            const int32_t vi = leaf_v[first + c];
-            T dot = 0;
-            for (int32_t ch = 0; ch < d; ++ch)
-                dot += gout[(int64_t)vi * d + ch] * F[(int64_t)vj * d + ch];
-            acc[c] = (double)dot;
-        }
         for (int c = 0; c < rows; ++c)
-            if (acc[c] != 0.0) hist_add<T>(lhp, df, leaf_D[kb + krow + c * n + j], acc[c]);
+            if (m[r][c] != (T)0) hist_add<T>(lhp, df, leaf_D[kb + krow + c * n + rj[r]], m[r][c]);
     }
-    if (use_lds) {
-        __syncthreads();
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
-            if (lh[k] != 0.0) atomicAdd(df + k, lh[k]);
-    }
+    if (use_lds) hist_flush<T>(lh, df, K);
 }
 
-// FFT jobs held in LDS: per channel pair, the forward transforms of the
-// gout table (at output positions) and of the field table (at source
-// positions); the products Zg * conj(Zv) are summed over channel pairs,
-// one inverse transform gives the channel-summed cross-correlation
-// Z[a][b] with a = q + r, b = s - x (mod L2), folded into df[a + |b|].
-// Three LDS tables per workgroup; one workgroup per job.
+// FFT jobs, pass 1: one workgroup per (job, group of kDfPairs channel
+// pairs) forms, per pair, the forward transforms of the gout table (at
+// output positions) and of the field table (at source positions), and
+// sums Zg * conj(Zv) over the group's pairs into a partial spectrum
+// written to global memory (slot = job * groups + group).
+constexpr int kDfPairs = 4;
+
 template <typename T>
-__global__ void k_df_fft_lds(int lg1, int lg2, int64_t NA, const int32_t* __restrict__ jobs,
-                             const int32_t* __restrict__ job_hx,
-                             const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
-                             const int32_t* __restrict__ jc_val, int32_t d,
-                             const T* __restrict__ val, const T* __restrict__ valg,
-                             const cpx<T>* __restrict__ tw, int lgtw, double* __restrict__ df) {
+__global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ jobs,
+                                 const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                                 const int32_t* __restrict__ jc_val, int32_t d,
+                                 const T* __restrict__ val, const T* __restrict__ valg,
+                                 const cpx<T>* __restrict__ tw, int lgtw,
+                                 cpx<T>* __restrict__ part) {
     extern __shared__ unsigned char smem_raw[];
+    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
     cpx<T>* zv = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* zg = zv + P;
     cpx<T>* acc = zg + P;
-    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
-    const int32_t H = job_hx[2 * blockIdx.x], X = job_hx[2 * blockIdx.x + 1];
-    const double sign = jc_val[cb] < NA ? 1.0 : -1.0;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = {(T)0, (T)0};
     const int32_t npairs = (d + 1) / 2;
-    for (int32_t pr = 0; pr < npairs; ++pr) {
+    for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = {(T)0, (T)0};
+    const int32_t pe = min(npairs, (int32_t)(blockIdx.y + 1) * kDfPairs);
+    for (int32_t pr = blockIdx.y * kDfPairs; pr < pe; ++pr) {
         const int32_t c0 = 2 * pr, c1 = c0 + 1;
         const bool has1 = c1 < d;
         for (int p = threadIdx.x; p < P; p += blockDim.x) {
@@ -730,17 +776,44 @@ __global__ void k_df_fft_lds(int lg1, int lg2, int64_t NA, const int32_t* __rest
         for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = cadd(acc[p], cmulc(zg[p], zv[p]));
         __syncthreads();
     }
-    fft_axis_lds<T, true>(acc, lg1, L2, L2, 1, tw, lgtw);
-    fft_axis_lds<T, true>(acc, lg2, L1, 1, L2, tw, lgtw);
-    const double scale = sign / (double)P;
+    cpx<T>* out = part + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) out[p] = acc[p];
+}
+
+// FFT jobs, pass 2: one workgroup per job sums the group spectra (fixed
+// order), applies one inverse transform and folds Re Z[a][b] (a = q + r,
+// b = s - x mod L2) into df[a + |b|], binned in LDS.
+template <typename T>
+__global__ void k_df_fft_fold(int lg1, int lg2, const int32_t* __restrict__ jobs,
+                              const int32_t* __restrict__ job_hx, int32_t groups, int64_t NA,
+                              const int32_t* __restrict__ jc_val, const cpx<T>* __restrict__ part,
+                              const cpx<T>* __restrict__ tw, int lgtw, double* __restrict__ df) {
+    extern __shared__ unsigned char smem_raw[];
+    const int32_t cb = jobs[2 * blockIdx.x];
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    const int32_t H = job_hx[2 * blockIdx.x], X = job_hx[2 * blockIdx.x + 1];
+    cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    T* lh = reinterpret_cast<T*>(z + P);
+    const int32_t nk = 2 * H + X + 1;  // bins this job can reach
+    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) lh[k] = 0;
+    const cpx<T>* src = part + (int64_t)blockIdx.x * groups * P;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        cpx<T> s = {(T)0, (T)0};
+        for (int32_t gq = 0; gq < groups; ++gq) s = cadd(s, src[(int64_t)gq * P + p]);
+        z[p] = s;
+    }
+    __syncthreads();
+    fft_axis_lds<T, true>(z, lg1, L2, L2, 1, tw, lgtw);
+    fft_axis_lds<T, true>(z, lg2, L1, 1, L2, tw, lgtw);
+    const T scale = (jc_val[cb] < NA ? (T)1 : (T)-1) / (T)P;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         const int a = p >> lg2, b = p & (L2 - 1);
         const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
-        if (a <= 2 * H && bs <= X) {
-            const double v = (double)acc[p].x * scale;
-            if (v != 0.0) atomicAdd(df + a + bs, v);
-        }
+        if (a <= 2 * H && bs <= X) atomicAdd(lh + a + bs, z[p].x * scale);
     }
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x)
+        if (lh[k] != (T)0) atomicAdd(df + k, (double)lh[k]);
 }
 
 // Global-memory variant for tables beyond LDS: fills of the two tables per

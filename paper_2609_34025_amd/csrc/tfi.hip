@@ -143,7 +143,7 @@ struct tfi_plan {
     // streams, fork/join events, graph cache
     hipStream_t s1 = nullptr, s2 = nullptr, cs0 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_a = nullptr, ev_b = nullptr, ev_c = nullptr,
-               ev_in = nullptr, ev_out = nullptr;
+               ev_d = nullptr, ev_in = nullptr, ev_out = nullptr;
     bool use_graphs = true;
     struct GraphEntry {
         GraphKey key;
@@ -209,7 +209,7 @@ struct tfi_plan {
             pool.push_back(q.e1);
         }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-        for (hipEvent_t e : {ev_fork, ev_a, ev_b, ev_c, ev_in, ev_out})
+        for (hipEvent_t e : {ev_fork, ev_a, ev_b, ev_c, ev_d, ev_in, ev_out})
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : {s1, s2, cs0})
             if (s) (void)hipStreamDestroy(s);
@@ -549,9 +549,13 @@ int upload_plan(tfi_plan* h) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_lds<float>,
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_lds<double>,
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<float>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
     // twiddles exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), from long double
@@ -575,7 +579,8 @@ int upload_plan(tfi_plan* h) {
     TFI_HIP(hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking));
     TFI_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
     TFI_HIP(hipStreamCreateWithFlags(&h->cs0, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_in, &h->ev_out})
+    for (hipEvent_t* e :
+         {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_d, &h->ev_in, &h->ev_out})
         TFI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return TFI_OK;
 }
@@ -680,181 +685,138 @@ int prepare_forward(tfi_plan* h, int32_t d) {
     return TFI_OK;
 }
 
-// Enqueue out = f(D) F: `s0` is the main stream, s1/s2 the side streams.
+// ---- stage helpers (enqueue only; buffers prepared beforehand) ----------
+
 template <typename T>
-void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
-                     hipStream_t s1, hipStream_t s2) {
+void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+    if (h->nlgrp == 0) return;
     const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st, d,
+                       h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
+    const double nv = (double)p.leaf_v.size();
+    h->end(st, ev, "leaf",
+           2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+}
+
+template <typename T>
+void enq_spectra(tfi_plan* h, const T* f, hipStream_t st) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = (T*)h->val[ti].p;
-    T* g = (T*)h->g[ti].p;
     tfi::cpx<T>* spec = (tfi::cpx<T>*)h->spec[ti].p;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
-    const int32_t npairs = (d + 1) / 2;
-    const double sz = (double)sizeof(T);
-    hipEvent_t ev;
-
-    (void)hipEventRecord(h->ev_fork, s0);
-    (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
-    (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
-
-    // side2: leaf tiles store their dense values into out
-    if (h->nlgrp > 0) {
-        ev = h->begin(s2);
-        hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, s2,
-                           d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
-        const double nv = (double)p.leaf_v.size();
-        h->end(s2, ev, "leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
-    }
-    (void)hipEventRecord(h->ev_c, s2);
-
-    // side1: kernel spectra of every FFT bucket
     for (int t = 0; t < 3; ++t) {
         const Tier& T_ = h->tiers[ti][t];
         if (!T_.nbuckets) continue;
-        ev = h->begin(s1);
+        hipEvent_t ev = h->begin(st);
         hipLaunchKernelGGL(tfi::k_spectrum_multi<T>, dim3((unsigned)T_.nbuckets), dim3(kThreads),
-                           (unsigned)T_.lds_bytes, s1, T_.d_bp, T_.d_bo, f, tw, h->lgtw, spec);
-        h->end(s1, ev, "spectrum", sz * T_.spec_bytes);
+                           (unsigned)T_.lds_bytes, st, T_.d_bp, T_.d_bo, f, tw, h->lgtw, spec);
+        h->end(st, ev, "spectrum", sizeof(T) * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
         const Bucket& b = h->buckets[bi];
-        ev = h->begin(s1);
+        hipEvent_t ev = h->begin(st);
         tfi::cpx<T>* z = spec + b.spec_off;
         hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads), 0,
-                           s1, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
+                           st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
         const int lgP = b.lg1 + b.lg2;
         for (int s = 0; s < b.lg2; ++s)
             hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                               dim3(kThreads), 0, s1, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
+                               dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
                                (int64_t)1, tw, h->lgtw);
         for (int s = 0; s < b.lg1; ++s)
             hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                               dim3(kThreads), 0, s1, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
+                               dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
                                (int64_t)1 << b.lg2, tw, h->lgtw);
-        h->end(s1, ev, "spectrum_global", 2.0 * sz * (double)b.P());
+        h->end(st, ev, "spectrum_global", 2.0 * sizeof(T) * (double)b.P());
     }
+}
 
-    // main: scatter
-    launch_scatter<T>(h, F, val, d, s0);
-    (void)hipEventRecord(h->ev_a, s0);
-
-    // side1: FFT tables once the cell sums exist
-    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+template <typename T>
+void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const tfi::cpx<T>* spec = (const tfi::cpx<T>*)h->spec[ti].p;
+    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
+    const int32_t npairs = (d + 1) / 2;
+    const double sz = (double)sizeof(T);
     for (int t = 0; t < 3; ++t) {
         const Tier& T_ = h->tiers[ti][t];
         if (!T_.njobs) continue;
-        ev = h->begin(s1);
+        hipEvent_t ev = h->begin(st);
         hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, npairs),
-                           dim3(kThreads), (unsigned)T_.lds_bytes, s1, T_.d_fj, T_.d_bp, T_.d_bo,
-                           h->d_jc_r, h->d_jc_x, h->d_jc_val, d, (const T*)val, g,
-                           (const tfi::cpx<T>*)spec, tw, h->lgtw);
-        h->end(s1, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
+                           dim3(kThreads), (unsigned)T_.lds_bytes, st, T_.d_fj, T_.d_bp, T_.d_bo,
+                           h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw, h->lgtw);
+        h->end(st, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
         const Bucket& b = h->buckets[bi];
-        ev = h->begin(s1);
+        hipEvent_t ev = h->begin(st);
         launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)h->fftbuf[ti].p,
-                             h->fftbuf[ti].bytes, s1);
-        h->end(s1, ev, "fft_global",
+                             h->fftbuf[ti].bytes, st);
+        h->end(st, ev, "fft_global",
                2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
     }
-    (void)hipEventRecord(h->ev_b, s1);
+}
 
-    // main: direct tables
-    if (h->ndblk > 0) {
-        ev = h->begin(s0);
-        const int32_t flds =
-            (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
-        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
-                           (unsigned)(flds * sizeof(T)), s0, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
-                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, (const T*)val, g);
-        h->end(s0, ev, "direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
-    }
+template <typename T>
+void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStream_t st) {
+    if (h->ndblk == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
+    hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                       (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
+                       h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
+    h->end(st, ev, "direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect);
+}
 
-    // join, then the gather writes every row of out
-    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
-    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
-    ev = h->begin(s0);
+template <typename T>
+void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st) {
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
     if (d % 4 == 0 && aligned16(out))
         hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(p.N * (d / 4))), dim3(kThreads),
-                           0, s0, p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, (const T*)g,
-                           out);
+                           0, st, p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, out);
     else
-        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, s0,
-                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, (const T*)g, out);
-    h->end(s0, ev, "gather",
-           sz * d * (double)(h->gather_reads + 2 * p.N) + 8.0 * (double)p.v_b.size() + 9.0 * p.N);
+        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st,
+                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, out);
+    h->end(st, ev, "gather",
+           sizeof(T) * d * (double)(h->gather_reads + 2 * p.N) + 8.0 * (double)p.v_b.size() +
+               9.0 * p.N);
+}
+
+// LDS budget of the df FFT passes for one bucket (3 tables), 0 if the
+// bucket needs the global-memory path.
+template <typename T>
+int64_t df_lds_bytes(const tfi_plan* h, const Bucket& b) {
+    const int64_t need = 3 * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+    return need <= h->lds_max ? need : 0;
 }
 
 template <typename T>
-int prepare_df(tfi_plan* h, int32_t d) {
-    const int ti = sizeof(T) == 8 ? 1 : 0;
-    const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
-    int rc;
-    if ((rc = h->ensure(h->val[ti], rowbytes))) return rc;
-    if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
-    const int32_t npairs = (d + 1) / 2;
-    size_t want = 0;
-    for (const Bucket& b : h->buckets) {
-        const int64_t P = b.P();
-        if (3 * P * (int64_t)sizeof(tfi::cpx<T>) <= h->lds_max) continue;
-        const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
-        const int64_t cap = (int64_t)2 << 30;
-        const int64_t jpc = std::max<int64_t>(
-            1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
-        want = std::max(want, (size_t)(std::min(jpc, b.njobs()) * per_job));
-    }
-    if (want && (rc = h->ensure(h->dfbuf[ti], want))) return rc;
-    return TFI_OK;
-}
-
-// Enqueue the kernel-table gradient df (FP64, kernel_len entries).
-template <typename T>
-void enqueue_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t s0,
-                hipStream_t s1, hipStream_t s2) {
+void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* df,
+                   hipStream_t st) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = (T*)h->val[ti].p;
-    T* valg = (T*)h->valg[ti].p;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
-    const int32_t K = (int32_t)p.kernel_len;
     const int32_t npairs = (d + 1) / 2;
+    const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
     const double sz = (double)sizeof(T);
-    hipEvent_t ev;
-    hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(K)), dim3(kThreads), 0, s0, df,
-                       (int64_t)K);
-    (void)hipEventRecord(h->ev_fork, s0);
-    (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
-    (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
-    // side2: leaf pair histograms straight from F and gout
-    if (h->nlgrp > 0) {
-        ev = h->begin(s2);
-        hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0,
-                           s2, d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
-                           K, df);
-        const double nv = (double)p.leaf_v.size();
-        h->end(s2, ev, "df_leaf", 2.0 * sz * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
-    }
-    (void)hipEventRecord(h->ev_c, s2);
-    // cell sums of gout on side1, of F on main
-    launch_scatter<T>(h, gout, valg, d, s1);
-    (void)hipEventRecord(h->ev_b, s1);
-    launch_scatter<T>(h, F, val, d, s0);
-    (void)hipEventRecord(h->ev_a, s0);
-    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
-    // side1: FFT-table cross-correlations
     for (const Bucket& b : h->buckets) {
         const int64_t P = b.P();
         const double bytes = 2.0 * sz * d * (double)b.cells + 12.0 * b.cells;
-        if (3 * P * (int64_t)sizeof(tfi::cpx<T>) <= h->lds_max) {
-            ev = h->begin(s1);
-            hipLaunchKernelGGL(tfi::k_df_fft_lds<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
-                               (unsigned)(3 * P * sizeof(tfi::cpx<T>)), s1, b.lg1, b.lg2, p.NA,
-                               b.d_jobs, b.d_hx, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
-                               (const T*)val, (const T*)valg, tw, h->lgtw, df);
-            h->end(s1, ev, "df_fft_lds", bytes);
+        const int64_t lds = df_lds_bytes<T>(h, b);
+        if (lds) {
+            hipEvent_t ev = h->begin(st);
+            tfi::cpx<T>* part = (tfi::cpx<T>*)h->dfbuf[ti].p;
+            hipLaunchKernelGGL(tfi::k_df_fft_partial<T>, dim3((unsigned)b.njobs(), groups),
+                               dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
+                               h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part);
+            const unsigned fold_lds =
+                (unsigned)(P * sizeof(tfi::cpx<T>) + (2 * b.hmax + b.xmax + 1) * sizeof(T));
+            hipLaunchKernelGGL(tfi::k_df_fft_fold<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
+                               fold_lds, st, b.lg1, b.lg2, b.d_jobs, b.d_hx, groups, p.NA,
+                               h->d_jc_val, (const tfi::cpx<T>*)part, tw, h->lgtw, df);
+            h->end(st, ev, "df_fft_lds", bytes);
             continue;
         }
         const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
@@ -862,7 +824,7 @@ void enqueue_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, h
         const int64_t jpc = std::max<int64_t>(
             1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
         tfi::cpx<T>* bv = (tfi::cpx<T>*)h->dfbuf[ti].p;
-        ev = h->begin(s1);
+        hipEvent_t ev = h->begin(st);
         const int lgP = b.lg1 + b.lg2;
         for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
             const int64_t nj = std::min(jpc, b.njobs() - j0);
@@ -871,46 +833,151 @@ void enqueue_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, h
             tfi::cpx<T>* acc = bg + nslots * P;
             const int32_t* jobs = b.d_jobs + 2 * j0;
             hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(2 * nslots * P)),
-                               dim3(kThreads), 0, s1, bv, 2 * nslots * P);
+                               dim3(kThreads), 0, st, bv, 2 * nslots * P);
             hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                               0, s1, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                               h->d_jc_val, d, (const T*)val, (const T*)valg, bv, bg);
+                               0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                               h->d_jc_val, d, val, valg, bv, bg);
             const unsigned nb = blocks_for(2 * nslots * P / 2);
             for (int s = 0; s < b.lg2; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   s1, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
+                                   st, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
                                    h->lgtw);
             for (int s = 0; s < b.lg1; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   s1, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
+                                   st, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
                                    (int64_t)1 << b.lg2, tw, h->lgtw);
             hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
-                               dim3(kThreads), 0, s1, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
+                               dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
                                (const tfi::cpx<T>*)bg, acc);
             const unsigned na = blocks_for(nj * P / 2);
             for (int s = 0; s < b.lg1; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   s1, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
+                                   st, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
             for (int s = 0; s < b.lg2; ++s)
                 hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   s1, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+                                   st, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
             hipLaunchKernelGGL(tfi::k_fold_global<T>, dim3(blocks_for(nj * P)), dim3(kThreads), 0,
-                               s1, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
+                               st, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
                                (const tfi::cpx<T>*)acc, df);
         }
-        h->end(s1, ev, "df_fft_global", bytes);
+        h->end(st, ev, "df_fft_global", bytes);
     }
+}
+
+template <typename T>
+void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* df,
+                   hipStream_t st) {
+    if (h->ndblk == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0, st,
+                       d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje,
+                       val, valg, (int32_t)p.kernel_len, df);
+    h->end(st, ev, "df_direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect);
+}
+
+template <typename T>
+void enq_df_leaf(tfi_plan* h, int32_t d, const T* F, const T* gout, double* df, hipStream_t st) {
+    if (h->nlgrp == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st,
+                       d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
+                       (int32_t)p.kernel_len, df);
+    const double nv = (double)p.leaf_v.size();
+    h->end(st, ev, "df_leaf", 2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+}
+
+inline void fork3(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    (void)hipEventRecord(h->ev_fork, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
+    (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
+}
+
+// Enqueue out = f(D) F: `s0` is the main stream, s1/s2 the side streams.
+template <typename T>
+void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
+                     hipStream_t s1, hipStream_t s2) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    T* val = (T*)h->val[ti].p;
+    T* g = (T*)h->g[ti].p;
+    fork3(h, s0, s1, s2);
+    enq_leaf<T>(h, f, F, d, out, s2);          // side2: leaf rows into out
+    (void)hipEventRecord(h->ev_c, s2);
+    enq_spectra<T>(h, f, s1);                   // side1: kernel spectra
+    launch_scatter<T>(h, F, val, d, s0);        // main: cell sums
+    (void)hipEventRecord(h->ev_a, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+    enq_fft<T>(h, d, val, g, s1);               // side1: FFT tables
     (void)hipEventRecord(h->ev_b, s1);
-    // main: direct-table pair histograms
-    if (h->ndblk > 0) {
-        ev = h->begin(s0);
-        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
-                           s0, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                           h->d_qje, (const T*)val, (const T*)valg, K, df);
-        h->end(s0, ev, "df_direct", 2.0 * sz * d * (double)h->ndirect + 20.0 * h->ndirect);
+    enq_direct<T>(h, f, d, val, g, s0);         // main: direct tables
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    enq_gather<T>(h, d, g, out, s0);            // main: out = leaf + calls
+}
+
+// Enqueue the adjoint: dF = f(D) gout (when dF != null) and the kernel-table
+// gradient df (when df != null). gout is scattered once (it feeds both),
+// F once (df only).
+template <typename T>
+void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
+                      double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    T* val = (T*)h->val[ti].p;
+    T* valg = (T*)h->valg[ti].p;
+    T* g = (T*)h->g[ti].p;
+    if (df)
+        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
+                           s0, df, (int64_t)p.kernel_len);
+    fork3(h, s0, s1, s2);
+    if (dF) enq_leaf<T>(h, f, gout, d, dF, s2);
+    if (df) enq_df_leaf<T>(h, d, F, gout, df, s2);
+    (void)hipEventRecord(h->ev_c, s2);
+    if (df) launch_scatter<T>(h, F, val, d, s1);
+    (void)hipEventRecord(h->ev_d, s1);
+    if (dF) enq_spectra<T>(h, f, s1);
+    launch_scatter<T>(h, gout, valg, d, s0);
+    (void)hipEventRecord(h->ev_a, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+    if (dF) enq_fft<T>(h, d, valg, g, s1);
+    if (df) enq_df_tables<T>(h, d, val, valg, df, s1);
+    (void)hipEventRecord(h->ev_b, s1);
+    if (dF) enq_direct<T>(h, f, d, valg, g, s0);
+    if (df) {
+        (void)hipStreamWaitEvent(s0, h->ev_d, 0);
+        enq_df_direct<T>(h, d, val, valg, df, s0);
     }
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    if (dF) enq_gather<T>(h, d, g, dF, s0);
+}
+
+template <typename T>
+int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
+    int rc = prepare_forward<T>(h, d);
+    if (rc) return rc;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
+    if (!need_df) return TFI_OK;
+    const int32_t npairs = (d + 1) / 2;
+    const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
+    size_t want = 0;
+    for (const Bucket& b : h->buckets) {
+        const int64_t P = b.P();
+        if (df_lds_bytes<T>(h, b)) {
+            want = std::max(want, (size_t)(b.njobs() * groups * P * sizeof(tfi::cpx<T>)));
+            continue;
+        }
+        const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
+        const int64_t cap = (int64_t)2 << 30;
+        const int64_t jpc = std::max<int64_t>(
+            1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
+        want = std::max(want, (size_t)(std::min(jpc, b.njobs()) * per_job));
+    }
+    if (want && (rc = h->ensure(h->dfbuf[ti], want))) return rc;
+    return TFI_OK;
 }
 
 // Run a DAG either eagerly on (caller stream, s1, s2) or as a cached graph
@@ -980,18 +1047,21 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
 }
 
 template <typename T>
-int run_df(tfi_plan* h, const T* F, const T* gout, int32_t d, double* df, hipStream_t st) {
-    int rc = prepare_df<T>(h, d);
+int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
+                 double* df, hipStream_t st) {
+    int rc = prepare_backward<T>(h, d, df != nullptr);
     if (rc) return rc;
     GraphKey key;
     key.kind = 2;
     key.dtype = sizeof(T) == 8;
     key.d = d;
-    key.p[0] = F;
-    key.p[1] = gout;
-    key.p[2] = df;
+    key.p[0] = f;
+    key.p[1] = F;
+    key.p[2] = gout;
+    key.p[3] = dF;
+    key.p[4] = df;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
-        enqueue_df<T>(h, F, gout, d, df, a, b, c);
+        enqueue_backward<T>(h, f, F, gout, d, dF, df, a, b, c);
     });
 }
 
@@ -1081,18 +1151,14 @@ int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, i
         return fail(TFI_ERR_DTYPE, "tfi_backward: unknown dtype");
     if (dF && (dF == F || dF == gout))
         return fail(TFI_ERR_ARG, "tfi_backward: dF must not alias F or gout");
+    if (!dF && !df) return TFI_OK;
     hipStream_t st = (hipStream_t)stream;
-    if (dF) {
-        // f(D) is symmetric: dF = f(D) gout
-        rc = tfi_integrate(h, f, gout, d, dtype, dF, stream);
-        if (rc) return rc;
-    }
-    if (df) {
-        if (dtype == TFI_F32)
-            return run_df<float>(h, (const float*)F, (const float*)gout, (int32_t)d, df, st);
-        return run_df<double>(h, (const double*)F, (const double*)gout, (int32_t)d, df, st);
-    }
-    return TFI_OK;
+    // f(D) is symmetric: dF = f(D) gout
+    if (dtype == TFI_F32)
+        return run_backward<float>(h, (const float*)f, (const float*)F, (const float*)gout,
+                                   (int32_t)d, (float*)dF, df, st);
+    return run_backward<double>(h, (const double*)f, (const double*)F, (const double*)gout,
+                                (int32_t)d, (double*)dF, df, st);
 }
 
 int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
