@@ -39,6 +39,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default direct/FFT rule instead of tuning it")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched forest forward+backward measurement")
     ap.add_argument("--copy-probe", action="store_true",
@@ -66,7 +68,11 @@ def main():
     tabs = [fn(K) for _, fn in W["kernels"]]
     fs = [torch.tensor(t, dtype=torch.float32, device=dev) for t in tabs]
     Ft = torch.tensor(F, device=dev)
-    log(f"bench: N={N} d={d} build {build_s:.2f}s kernel_length={K}")
+    t0 = time.perf_counter()
+    cost = tfi.autotune(fs[0], d) if not args.no_autotune else tfi.stats()["fft_cost"]
+    tune_s = time.perf_counter() - t0
+    log(f"bench: N={N} d={d} build {build_s:.2f}s kernel_length={K} "
+        f"autotuned fft_cost={cost} in {tune_s:.2f}s")
 
     outs = [None, None]
     if args.copy_probe:
@@ -153,7 +159,8 @@ def main():
                                "weights U{1..8}, F[N x 16] fp32 ~ N(0,1), kernels "
                                "exp(-0.05 d) and 1/(1+d)^2 (one step = both kernels)",
                    "N": int(N), "d": int(d), "kernels": 2,
-                   "kernel_length": int(K), "build_s": round(build_s, 3)},
+                   "kernel_length": int(K), "build_s": round(build_s, 3),
+                   "fft_cost": cost},
         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -190,6 +197,12 @@ def batched_fwd_bwd(args, plain_value):
     build_s = time.perf_counter() - t0
     K = tfi.kernel_length
     rng = np.random.default_rng(33)
+    if not args.no_autotune:
+        ftune = torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=dev)
+        cost = tfi.autotune(ftune, d)
+    else:
+        cost = tfi.stats()["fft_cost"]
+    log(f"batched: autotuned fft_cost={cost}")
     Wt = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device=dev)
     a = torch.tensor(W["a"], dtype=torch.float32, device=dev, requires_grad=True)
     b = torch.tensor(W["b"], dtype=torch.float32, device=dev, requires_grad=True)
@@ -255,7 +268,7 @@ def batched_fwd_bwd(args, plain_value):
                         "weights U{1..16}, F[n x 64] fp32, f = sum of 8 exponentials; "
                         "loss sum(W * out)",
             "n": int(n), "d": int(d), "trees": int(len(W["offsets"]) - 1),
-            "kernel_length": int(K), "build_s": round(build_s, 3),
+            "kernel_length": int(K), "build_s": round(build_s, 3), "fft_cost": cost,
             "parity": {"rows": 512, "rel_err": errs, "ok": ok}, "stages": stages}
 
 

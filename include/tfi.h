@@ -169,6 +169,24 @@ int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
                         size_t cap);
 
 /*
+ * Autotuning of the per-table evaluation method. Each candidate value of
+ * the cost constant of tfi_build_opts.fft_cost (0.25, 1, 4, 16, 64)
+ * re-assigns every table job to direct sums or FFT, rebuilds the device
+ * job lists, and times forward integrations of d channels of dtype with
+ * the kernel table f (device, tfi_kernel_length entries) on `stream`
+ * (HIP events; field values do not affect the timing). The fastest value
+ * stays in effect and is written to *best_cost (host). The kernel length
+ * does not change. Uses temporary device memory for two [N x d] fields.
+ * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE (method forced at
+ * build), TFI_ERR_HIP, TFI_ERR_BUDGET, TFI_ERR_OOM.
+ */
+int tfi_autotune(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
+                 float *best_cost, void *stream);
+
+/* Apply a cost constant (e.g. a cached tuning result) without timing. */
+int tfi_set_fft_cost(tfi_handle h, float cost);
+
+/*
  * Stage timing. With enable != 0, every later tfi_integrate/tfi_backward
  * on the handle records a HIP event pair around each stage (on the same
  * stream as the stage's kernels) and adds the stage's algorithmic bytes

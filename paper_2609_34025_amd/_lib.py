@@ -42,7 +42,8 @@ _lib = None
 
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
             "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
-            "tfi_profile_report", "tfi_destroy", "tfi_last_error"]
+            "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
+            "tfi_last_error"]
 
 
 def load():
@@ -75,6 +76,10 @@ def load():
     lib.tfi_profile.restype = C.c_int
     lib.tfi_profile_report.argtypes = [vp, C.c_char_p, C.c_size_t]
     lib.tfi_profile_report.restype = i64
+    lib.tfi_autotune.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
+    lib.tfi_autotune.restype = C.c_int
+    lib.tfi_set_fft_cost.argtypes = [vp, C.c_float]
+    lib.tfi_set_fft_cost.restype = C.c_int
     lib.tfi_last_error.argtypes = []
     lib.tfi_last_error.restype = C.c_char_p
     _lib = lib

@@ -513,6 +513,44 @@ double backbone_score(int64_t nS, int64_t M, const std::vector<int64_t>& compH,
     return s;
 }
 
+void assign_methods(Plan& plan, const PlanOptions& opt) {
+    const int64_t J = (int64_t)plan.job_H.size();
+    plan.job_method.resize(J);
+    plan.sum_P = 0;
+    for (int64_t j = 0; j < J; ++j) {
+        const int64_t P = (int64_t)1 << (plan.job_lg1[j] + plan.job_lg2[j]);
+        const int64_t nc = plan.job_cell_off[j + 1] - plan.job_cell_off[j];
+        const double direct = (double)nc * (double)nc;
+        const double fft = opt.fft_cost * (double)P * std::log2((double)std::max<int64_t>(P, 2));
+        int32_t m;
+        if (opt.table_method == 1) m = METHOD_DIRECT;
+        else if (opt.table_method == 2) m = METHOD_FFT;
+        else m = (direct <= fft) ? METHOD_DIRECT : METHOD_FFT;
+        plan.job_method[j] = m;
+        if (m == METHOD_FFT) plan.sum_P += P;
+    }
+}
+
+uint64_t plan_fingerprint(const Plan& p) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix((uint64_t)p.N);
+    mix((uint64_t)p.NA);
+    mix((uint64_t)p.NB);
+    mix((uint64_t)p.leaf_D.size());
+    for (size_t j = 0; j < p.job_H.size(); ++j) {
+        mix((uint64_t)p.job_H[j]);
+        mix((uint64_t)p.job_X[j]);
+        mix((uint64_t)(p.job_cell_off[j + 1] - p.job_cell_off[j]));
+    }
+    return h;
+}
+
 int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
                const PlanOptions& opt, Plan& plan, std::string& err) {
     plan = Plan();
@@ -535,38 +573,25 @@ int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
         err = "tfi_build: host allocation failed while planning";
         return kErrOom;
     }
-    // per-job evaluation method and padded FFT sizes
+    // padded FFT sizes per job; the kernel table covers the reach of every
+    // job's FFT bucket, so that re-assigning methods (autotuning) never
+    // changes the number of entries of f that may be read
     const int64_t J = (int64_t)plan.job_H.size();
-    plan.job_method.resize(J);
     plan.job_lg1.resize(J);
     plan.job_lg2.resize(J);
     std::map<std::pair<int32_t, int32_t>, std::pair<int64_t, int64_t>> bucket_hx;
     for (int64_t j = 0; j < J; ++j) {
-        int64_t H = plan.job_H[j], X = plan.job_X[j];
-        int64_t L1 = next_pow2(2 * H + 1), L2 = next_pow2(2 * X + 1);
-        int64_t P = L1 * L2;
-        int64_t nc = plan.job_cell_off[j + 1] - plan.job_cell_off[j];
-        double direct = (double)nc * (double)nc;
-        double fft = opt.fft_cost * (double)P * std::log2((double)std::max<int64_t>(P, 2));
-        int32_t m;
-        if (opt.table_method == 1) m = METHOD_DIRECT;
-        else if (opt.table_method == 2) m = METHOD_FFT;
-        else m = (direct <= fft) ? METHOD_DIRECT : METHOD_FFT;
-        plan.job_method[j] = m;
-        plan.job_lg1[j] = ilog2(L1);
-        plan.job_lg2[j] = ilog2(L2);
-        if (m == METHOD_FFT) {
-            plan.sum_P += P;
-            auto& hx = bucket_hx[{plan.job_lg1[j], plan.job_lg2[j]}];
-            hx.first = std::max(hx.first, H);
-            hx.second = std::max(hx.second, X);
-        } else {
-            plan.kernel_len = std::max(plan.kernel_len, 2 * H + X + 1);
-        }
+        const int64_t H = plan.job_H[j], X = plan.job_X[j];
+        plan.job_lg1[j] = ilog2(next_pow2(2 * H + 1));
+        plan.job_lg2[j] = ilog2(next_pow2(2 * X + 1));
+        auto& hx = bucket_hx[{plan.job_lg1[j], plan.job_lg2[j]}];
+        hx.first = std::max(hx.first, H);
+        hx.second = std::max(hx.second, X);
     }
     for (auto& kv : bucket_hx)
         plan.kernel_len = std::max(plan.kernel_len,
                                    2 * kv.second.first + kv.second.second + 1);
+    assign_methods(plan, opt);
     plan.sum_cells = plan.NA + plan.NB;
     return kOk;
 }

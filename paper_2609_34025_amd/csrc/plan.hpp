@@ -85,6 +85,14 @@ struct Plan {
 int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
                const PlanOptions& opt, Plan& plan, std::string& err);
 
+// Per-job evaluation method (direct sums or FFT) from the cost rule
+// cells^2 <= fft_cost * P log2 P, or forced by opt.table_method.
+void assign_methods(Plan& plan, const PlanOptions& opt);
+
+// 64-bit FNV-1a hash of the plan's shape (job sizes and depths), the key of
+// tuned settings.
+uint64_t plan_fingerprint(const Plan& p);
+
 // Score of equation "stad-score" with natural logarithms.
 double backbone_score(int64_t nS, int64_t M, const std::vector<int64_t>& compH,
                       const std::vector<int64_t>& compN);

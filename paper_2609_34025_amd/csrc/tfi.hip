@@ -98,10 +98,13 @@ struct GraphKey {
 
 struct tfi_plan {
     tfi::Plan plan;
+    tfi::PlanOptions popt;
     int device = -1;
     uint64_t budget = 0;
     size_t dev_bytes = 0;
-    std::vector<void*> allocs;
+    std::vector<void*> allocs;   // plan arrays for the handle's lifetime
+    std::vector<void*> mallocs;  // method-dependent arrays (rebuilt on tuning)
+    std::vector<size_t> mbytes;
 
     // plan arrays on the device
     int32_t *d_inc_v = nullptr, *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
@@ -214,6 +217,7 @@ struct tfi_plan {
         for (hipStream_t s : {s1, s2, cs0})
             if (s) (void)hipStreamDestroy(s);
         for (void* p : allocs) (void)hipFree(p);
+        for (void* p : mallocs) (void)hipFree(p);
         for (int t = 0; t < 2; ++t)
             for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t]})
                 if (b->p) (void)hipFree(b->p);
@@ -242,6 +246,39 @@ struct tfi_plan {
         if (!src.empty())
             TFI_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
         *dst = (V*)p;
+        return TFI_OK;
+    }
+
+    template <typename V>
+    int upload_m(V** dst, const std::vector<V>& src) {
+        void* p = nullptr;
+        int rc = dalloc(&p, src.size() * sizeof(V));
+        if (rc) return rc;
+        mallocs.push_back(p);
+        mbytes.push_back(std::max<size_t>(src.size() * sizeof(V), 16));
+        if (!src.empty())
+            TFI_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
+        *dst = (V*)p;
+        return TFI_OK;
+    }
+
+    // Release the method-dependent structures (after the device drained).
+    int free_methods() {
+        TFI_HIP(hipDeviceSynchronize());
+        drop_graphs();
+        for (size_t i = 0; i < mallocs.size(); ++i) {
+            (void)hipFree(mallocs[i]);
+            dev_bytes -= mbytes[i];
+        }
+        mallocs.clear();
+        mbytes.clear();
+        buckets.clear();
+        for (int t = 0; t < 2; ++t) {
+            global_b[t].clear();
+            for (int k = 0; k < 3; ++k) tiers[t][k] = Tier();
+        }
+        ndirect = ndblk = 0;
+        spec_elems = 0;
         return TFI_OK;
     }
 
@@ -278,7 +315,7 @@ int check_handle(tfi_handle h, bool need_device) {
     return TFI_OK;
 }
 
-int upload_plan(tfi_plan* h) {
+int upload_static(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
     if ((rc = h->upload(&h->d_inc_v, p.inc_v))) return rc;
@@ -294,89 +331,9 @@ int upload_plan(tfi_plan* h) {
         if ((rc = h->upload(&h->d_vleaf, vleaf))) return rc;
     }
 
-    std::vector<int64_t> djobs;  // direct-method jobs
-    std::map<std::pair<int, int>, size_t> bidx;
-    const int64_t J = (int64_t)p.job_H.size();
     int maxlg = 1;
-    for (int64_t j = 0; j < J; ++j) {
-        const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
-        if (p.job_method[j] == tfi::METHOD_DIRECT) {
-            djobs.push_back(j);
-        } else {
-            auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
-            auto it = bidx.find(key);
-            if (it == bidx.end()) {
-                it = bidx.emplace(key, h->buckets.size()).first;
-                Bucket b;
-                b.lg1 = key.first;
-                b.lg2 = key.second;
-                h->buckets.push_back(b);
-            }
-            Bucket& b = h->buckets[it->second];
-            b.hmax = std::max(b.hmax, p.job_H[j]);
-            b.xmax = std::max(b.xmax, p.job_X[j]);
-            b.jobs.push_back(cb);
-            b.jobs.push_back(ce);
-            b.hx.push_back(p.job_H[j]);
-            b.hx.push_back(p.job_X[j]);
-            b.cells += ce - cb;
-            maxlg = std::max(maxlg, std::max(b.lg1, b.lg2));
-        }
-    }
-    // direct cells: jobs sorted by size (largest first) so that lanes of a
-    // wavefront run equal loops, each padded to whole quads of 4 cells
-    // (padding: r = x = 0, row -1); blocks pack whole jobs up to kDirOut
-    // cells, larger jobs are cut into kDirOut-cell output slices whose
-    // sources are the whole job.
-    {
-        std::stable_sort(djobs.begin(), djobs.end(), [&](int64_t a, int64_t b) {
-            return p.job_cell_off[a + 1] - p.job_cell_off[a] >
-                   p.job_cell_off[b + 1] - p.job_cell_off[b];
-        });
-        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk;
-        std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
-        for (int64_t j : djobs) {
-            const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
-            const int32_t jb = (int32_t)dl_r.size();
-            const int32_t n = ce - cb, np = (n + 3) & ~3;
-            for (int32_t i = 0; i < np; ++i) {
-                const bool real = i < n;
-                dl_r.push_back(real ? p.jc_r[cb + i] : 0);
-                dl_x.push_back(real ? p.jc_x[cb + i] : 0);
-                dl_row.push_back(real ? p.jc_val[cb + i] : -1);
-            }
-            const int32_t je = jb + np;
-            for (int32_t q = 0; q < np / 4; ++q) {
-                qjb.push_back(jb);
-                qje.push_back(je);
-            }
-            jr.emplace_back(jb, je);
-        }
-        size_t k = 0;
-        while (k < jr.size()) {
-            const int32_t jb = jr[k].first, je = jr[k].second;
-            if (je - jb > tfi::kDirOut) {
-                for (int32_t o = jb; o < je; o += tfi::kDirOut)
-                    dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
-                ++k;
-                continue;
-            }
-            size_t e = k + 1;
-            while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
-            const int32_t end = jr[e - 1].second;
-            dblk.insert(dblk.end(), {jb, end, jb, end});
-            k = e;
-        }
-        h->ndirect = (int64_t)dl_r.size();
-        h->ndblk = (int64_t)dblk.size() / 4;
-        if ((rc = h->upload(&h->d_dl_r, dl_r))) return rc;
-        if ((rc = h->upload(&h->d_dl_x, dl_x))) return rc;
-        if ((rc = h->upload(&h->d_dl_row, dl_row))) return rc;
-        if ((rc = h->upload(&h->d_qjb, qjb))) return rc;
-        if ((rc = h->upload(&h->d_qje, qje))) return rc;
-        if ((rc = h->upload(&h->d_dblk, dblk))) return rc;
-    }
-
+    for (size_t j = 0; j < p.job_lg1.size(); ++j)
+        maxlg = std::max(maxlg, std::max(p.job_lg1[j], p.job_lg2[j]));
     // scatter levels: every b-cell and A-cell is a run of incidences; runs
     // longer than kSeg are cut into pieces summed into partial rows, which
     // the next level adds up (again in pieces of at most kSeg)
@@ -494,50 +451,6 @@ int upload_plan(tfi_plan* h) {
         if ((rc = h->upload(&h->d_lq, lq))) return rc;
         if ((rc = h->upload(&h->d_lgk, gk))) return rc;
     }
-    h->spec_elems = 0;
-    for (Bucket& b : h->buckets) {
-        if ((rc = h->upload(&b.d_jobs, b.jobs))) return rc;
-        if ((rc = h->upload(&b.d_hx, b.hx))) return rc;
-        b.spec_off = h->spec_elems;
-        h->spec_elems += b.P();
-    }
-    // LDS tiers per dtype: up to 16 KiB, up to 64 KiB, up to the device
-    // limit; larger tables take the global-memory passes
-    for (int ti = 0; ti < 2; ++ti) {
-        const int64_t cs = ti ? (int64_t)sizeof(tfi::cpx<double>) : (int64_t)sizeof(tfi::cpx<float>);
-        const int64_t lim[3] = {16384, 65536, h->lds_max};
-        std::vector<int32_t> bp[3], fj[3];
-        std::vector<int64_t> bo[3];
-        for (size_t bi = 0; bi < h->buckets.size(); ++bi) {
-            const Bucket& b = h->buckets[bi];
-            const int64_t bytes = b.P() * cs;
-            int t = 0;
-            while (t < 3 && bytes > lim[t]) ++t;
-            if (t == 3) {
-                h->global_b[ti].push_back((int)bi);
-                continue;
-            }
-            Tier& T = h->tiers[ti][t];
-            const int32_t local = (int32_t)(bp[t].size() / 4);
-            bp[t].insert(bp[t].end(), {b.lg1, b.lg2, b.hmax, b.xmax});
-            bo[t].push_back(b.spec_off);
-            for (int64_t j = 0; j < b.njobs(); ++j)
-                fj[t].insert(fj[t].end(), {b.jobs[2 * j], b.jobs[2 * j + 1], local});
-            T.lds_bytes = std::max(T.lds_bytes, bytes);
-            T.bytes_per_d += 2.0 * (double)b.cells;
-            T.bytes_fixed += 12.0 * (double)b.cells;
-            T.spec_bytes += 2.0 * (double)b.P();
-        }
-        for (int t = 0; t < 3; ++t) {
-            Tier& T = h->tiers[ti][t];
-            T.nbuckets = (int64_t)bo[t].size();
-            T.njobs = (int64_t)fj[t].size() / 3;
-            if (!T.nbuckets) continue;
-            if ((rc = h->upload(&T.d_bp, bp[t]))) return rc;
-            if ((rc = h->upload(&T.d_bo, bo[t]))) return rc;
-            if ((rc = h->upload(&T.d_fj, fj[t]))) return rc;
-        }
-    }
     // LDS beyond 64 KiB needs an opt-in per kernel
     if (h->lds_max > 65536) {
         const int lds = (int)h->lds_max;
@@ -583,6 +496,145 @@ int upload_plan(tfi_plan* h) {
          {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_d, &h->ev_in, &h->ev_out})
         TFI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return TFI_OK;
+}
+
+// Device structures that depend on the per-job method (direct blocks, FFT
+// buckets and their LDS tiers); rebuilt when the methods are re-assigned.
+int upload_methods(tfi_plan* h) {
+    const tfi::Plan& p = h->plan;
+    int rc;
+    std::vector<int64_t> djobs;  // direct-method jobs
+    std::map<std::pair<int, int>, size_t> bidx;
+    const int64_t J = (int64_t)p.job_H.size();
+    for (int64_t j = 0; j < J; ++j) {
+        const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
+        if (p.job_method[j] == tfi::METHOD_DIRECT) {
+            djobs.push_back(j);
+        } else {
+            auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
+            auto it = bidx.find(key);
+            if (it == bidx.end()) {
+                it = bidx.emplace(key, h->buckets.size()).first;
+                Bucket b;
+                b.lg1 = key.first;
+                b.lg2 = key.second;
+                h->buckets.push_back(b);
+            }
+            Bucket& b = h->buckets[it->second];
+            b.hmax = std::max(b.hmax, p.job_H[j]);
+            b.xmax = std::max(b.xmax, p.job_X[j]);
+            b.jobs.push_back(cb);
+            b.jobs.push_back(ce);
+            b.hx.push_back(p.job_H[j]);
+            b.hx.push_back(p.job_X[j]);
+            b.cells += ce - cb;
+        }
+    }
+    // direct cells: jobs sorted by size (largest first) so that lanes of a
+    // wavefront run equal loops, each padded to whole quads of 4 cells
+    // (padding: r = x = 0, row -1); blocks pack whole jobs up to kDirOut
+    // cells, larger jobs are cut into kDirOut-cell output slices whose
+    // sources are the whole job.
+    {
+        std::stable_sort(djobs.begin(), djobs.end(), [&](int64_t a, int64_t b) {
+            return p.job_cell_off[a + 1] - p.job_cell_off[a] >
+                   p.job_cell_off[b + 1] - p.job_cell_off[b];
+        });
+        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk;
+        std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
+        for (int64_t j : djobs) {
+            const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
+            const int32_t jb = (int32_t)dl_r.size();
+            const int32_t n = ce - cb, np = (n + 3) & ~3;
+            for (int32_t i = 0; i < np; ++i) {
+                const bool real = i < n;
+                dl_r.push_back(real ? p.jc_r[cb + i] : 0);
+                dl_x.push_back(real ? p.jc_x[cb + i] : 0);
+                dl_row.push_back(real ? p.jc_val[cb + i] : -1);
+            }
+            const int32_t je = jb + np;
+            for (int32_t q = 0; q < np / 4; ++q) {
+                qjb.push_back(jb);
+                qje.push_back(je);
+            }
+            jr.emplace_back(jb, je);
+        }
+        size_t k = 0;
+        while (k < jr.size()) {
+            const int32_t jb = jr[k].first, je = jr[k].second;
+            if (je - jb > tfi::kDirOut) {
+                for (int32_t o = jb; o < je; o += tfi::kDirOut)
+                    dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
+                ++k;
+                continue;
+            }
+            size_t e = k + 1;
+            while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
+            const int32_t end = jr[e - 1].second;
+            dblk.insert(dblk.end(), {jb, end, jb, end});
+            k = e;
+        }
+        h->ndirect = (int64_t)dl_r.size();
+        h->ndblk = (int64_t)dblk.size() / 4;
+        if ((rc = h->upload_m(&h->d_dl_r, dl_r))) return rc;
+        if ((rc = h->upload_m(&h->d_dl_x, dl_x))) return rc;
+        if ((rc = h->upload_m(&h->d_dl_row, dl_row))) return rc;
+        if ((rc = h->upload_m(&h->d_qjb, qjb))) return rc;
+        if ((rc = h->upload_m(&h->d_qje, qje))) return rc;
+        if ((rc = h->upload_m(&h->d_dblk, dblk))) return rc;
+    }
+
+    h->spec_elems = 0;
+    for (Bucket& b : h->buckets) {
+        if ((rc = h->upload_m(&b.d_jobs, b.jobs))) return rc;
+        if ((rc = h->upload_m(&b.d_hx, b.hx))) return rc;
+        b.spec_off = h->spec_elems;
+        h->spec_elems += b.P();
+    }
+    // LDS tiers per dtype: up to 16 KiB, up to 64 KiB, up to the device
+    // limit; larger tables take the global-memory passes
+    for (int ti = 0; ti < 2; ++ti) {
+        const int64_t cs = ti ? (int64_t)sizeof(tfi::cpx<double>) : (int64_t)sizeof(tfi::cpx<float>);
+        const int64_t lim[3] = {16384, 65536, h->lds_max};
+        std::vector<int32_t> bp[3], fj[3];
+        std::vector<int64_t> bo[3];
+        for (size_t bi = 0; bi < h->buckets.size(); ++bi) {
+            const Bucket& b = h->buckets[bi];
+            const int64_t bytes = b.P() * cs;
+            int t = 0;
+            while (t < 3 && bytes > lim[t]) ++t;
+            if (t == 3) {
+                h->global_b[ti].push_back((int)bi);
+                continue;
+            }
+            Tier& T = h->tiers[ti][t];
+            const int32_t local = (int32_t)(bp[t].size() / 4);
+            bp[t].insert(bp[t].end(), {b.lg1, b.lg2, b.hmax, b.xmax});
+            bo[t].push_back(b.spec_off);
+            for (int64_t j = 0; j < b.njobs(); ++j)
+                fj[t].insert(fj[t].end(), {b.jobs[2 * j], b.jobs[2 * j + 1], local});
+            T.lds_bytes = std::max(T.lds_bytes, bytes);
+            T.bytes_per_d += 2.0 * (double)b.cells;
+            T.bytes_fixed += 12.0 * (double)b.cells;
+            T.spec_bytes += 2.0 * (double)b.P();
+        }
+        for (int t = 0; t < 3; ++t) {
+            Tier& T = h->tiers[ti][t];
+            T.nbuckets = (int64_t)bo[t].size();
+            T.njobs = (int64_t)fj[t].size() / 3;
+            if (!T.nbuckets) continue;
+            if ((rc = h->upload_m(&T.d_bp, bp[t]))) return rc;
+            if ((rc = h->upload_m(&T.d_bo, bo[t]))) return rc;
+            if ((rc = h->upload_m(&T.d_fj, fj[t]))) return rc;
+        }
+    }
+    return TFI_OK;
+}
+
+int upload_plan(tfi_plan* h) {
+    int rc = upload_static(h);
+    if (rc) return rc;
+    return upload_methods(h);
 }
 
 // Cell sums of the rows of `src` ([N x d]) into val: A-cells, b-cells and
@@ -1065,6 +1117,50 @@ int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, 
     });
 }
 
+
+int reassign_methods(tfi_plan* h, double cost) {
+    h->popt.fft_cost = cost;
+    tfi::assign_methods(h->plan, h->popt);
+    int rc = h->free_methods();
+    if (rc) return rc;
+    return upload_methods(h);
+}
+
+template <typename T>
+int time_forward(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, float* ms) {
+    const int64_t n = h->plan.N * (int64_t)d;
+    void* F = nullptr;
+    void* out = nullptr;
+    int rc = h->dalloc(&F, (size_t)n * sizeof(T));
+    if (rc) return rc;
+    rc = h->dalloc(&out, (size_t)n * sizeof(T));
+    if (rc) {
+        (void)hipFree(F);
+        h->dev_bytes -= (size_t)n * sizeof(T);
+        return rc;
+    }
+    hipLaunchKernelGGL(tfi::k_zero<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, (T*)F, n);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    for (int i = 0; i < 2 && !rc; ++i) rc = run_forward<T>(h, f, (const T*)F, d, (T*)out, st);
+    (void)hipEventRecord(e0, st);
+    for (int i = 0; i < reps && !rc; ++i) rc = run_forward<T>(h, f, (const T*)F, d, (T*)out, st);
+    (void)hipEventRecord(e1, st);
+    if (!rc && hipEventSynchronize(e1) == hipSuccess) {
+        (void)hipEventElapsedTime(ms, e0, e1);
+        *ms /= (float)reps;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->drop_graphs();  // they captured the temporary buffers
+    (void)hipFree(F);
+    (void)hipFree(out);
+    h->dev_bytes -= 2 * (size_t)n * sizeof(T);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1095,6 +1191,7 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     std::string err;
     int rc = tfi::build_plan(parent, weight, N, po, h->plan, err);
     if (rc) return fail(rc, err);
+    h->popt = po;
     h->budget = o.memory_budget_bytes;
     h->use_graphs = o.no_graphs == 0;
     if (const char* e = std::getenv("TFI_NO_GRAPHS"))
@@ -1165,6 +1262,10 @@ int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
     g_err.clear();
     if (!h) return fail(TFI_ERR_ARG, "tfi_plan_stats: null handle");
     std::string s = tfi::plan_stats_json(h->plan);
+    char fp[32];
+    std::snprintf(fp, sizeof(fp), "%016llx", (unsigned long long)tfi::plan_fingerprint(h->plan));
+    s += ",\"fingerprint\":\"" + std::string(fp) + "\",\"fft_cost\":" +
+         std::to_string(h->popt.fft_cost);
     s += ",\"device\":" + std::to_string(h->device) +
          ",\"device_bytes\":" + std::to_string(h->dev_bytes) +
          ",\"arrays\":{\"job_H\":\"i32\",\"job_X\":\"i32\",\"job_sign\":\"i32\","
@@ -1217,6 +1318,45 @@ int64_t tfi_plan_export(tfi_handle h, const char* name, void* buf, size_t cap) {
     else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
     if (buf && cap >= bytes && bytes) std::memcpy(buf, src, bytes);
     return (int64_t)bytes;
+}
+
+int tfi_set_fft_cost(tfi_handle h, float cost) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!(cost > 0.0f)) return fail(TFI_ERR_ARG, "tfi_set_fft_cost: cost must be > 0");
+    return reassign_methods(h, cost);
+}
+
+int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, float* best_cost,
+                 void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f || !best_cost) return fail(TFI_ERR_ARG, "tfi_autotune: null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_autotune: need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64)
+        return fail(TFI_ERR_DTYPE, "tfi_autotune: unknown dtype");
+    if (h->popt.table_method != 0)
+        return fail(TFI_ERR_STATE, "tfi_autotune: table method is forced for this handle");
+    hipStream_t st = (hipStream_t)stream;
+    const float cands[] = {0.25f, 1.0f, 4.0f, 16.0f, 64.0f};
+    float best = (float)h->popt.fft_cost, best_ms = 1e30f;
+    for (float c : cands) {
+        if ((rc = reassign_methods(h, c))) return rc;
+        float ms = 1e30f;
+        rc = dtype == TFI_F32
+                 ? time_forward<float>(h, (const float*)f, (int32_t)d, st, 5, &ms)
+                 : time_forward<double>(h, (const double*)f, (int32_t)d, st, 5, &ms);
+        if (rc) return rc;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    }
+    if ((rc = reassign_methods(h, best))) return rc;
+    *best_cost = best;
+    return TFI_OK;
 }
 
 int tfi_profile(tfi_handle h, int enable) {

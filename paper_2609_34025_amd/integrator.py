@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import json
+import os
 
 import numpy as np
 import torch
@@ -68,6 +69,37 @@ class TreeIntegrator:
         if nbytes:
             _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, nbytes))
         return arr
+
+    def autotune(self, f, d, cache=None):
+        """Choose the per-table method rule (direct sums vs FFT) by timing
+        forward passes of ``d`` channels in ``f``'s dtype; the fastest
+        setting stays in effect. ``cache``: optional JSON file of tuned
+        values keyed by (plan fingerprint, d, dtype), read before and
+        updated after tuning. Returns the chosen cost constant."""
+        self._check(f)
+        key = f"{self.stats()['fingerprint']}:{int(d)}:{str(f.dtype)}"
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fp:
+                table = json.load(fp)
+        lib = _lib.load()
+        if key in table:
+            _lib.check(lib.tfi_set_fft_cost(self._h, float(table[key])))
+            return float(table[key])
+        best = C.c_float()
+        _lib.check(lib.tfi_autotune(self._h, f.data_ptr(), int(d), _DTYPES[f.dtype],
+                                    C.byref(best), self._stream(self.device)))
+        if cache:
+            table[key] = best.value
+            tmp = f"{cache}.{os.getpid()}.tmp"
+            with open(tmp, "w") as fp:
+                json.dump(table, fp, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return best.value
+
+    def set_fft_cost(self, cost):
+        """Apply a direct-vs-FFT cost constant without timing."""
+        _lib.check(_lib.load().tfi_set_fft_cost(self._h, float(cost)))
 
     def profile(self, enable=True):
         """Record per-stage HIP events and algorithmic bytes from now on."""

@@ -262,3 +262,28 @@ def test_graph_replays_match_eager():
         # df bins in the working precision with atomics: equal to rounding
         assert ((df - rdf).norm() / rdf.norm()).item() < 1e-6, rep
         del junk
+
+
+def test_autotune_keeps_results_and_kernel_length(tmp_path):
+    rng = np.random.default_rng(23)
+    W = S.workload("grid512", trees=16, d=8)
+    p, w, F = W["parent"], W["weight"], W["F"]
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    ftab = W["kernels"][0][1](K)
+    f = torch.tensor(ftab, dtype=torch.float32, device=DEV)
+    cache = str(tmp_path / "tune.json")
+    c = t.autotune(f, F.shape[1], cache=cache)
+    assert c in (0.25, 1.0, 4.0, 16.0, 64.0)
+    assert t.kernel_length == K and t.stats()["fft_cost"] == pytest.approx(c)
+    rows = rng.choice(len(p), 256, replace=False)
+    y = t.integrate(f, torch.tensor(F, device=DEV)).cpu().numpy()
+    ref = oracle.integrate(p, w, ftab, F.astype(np.float64), rows=rows)
+    assert relerr(y[rows], ref) <= 1e-4
+    # a second handle takes the cached value without timing
+    t2 = TreeIntegrator(p, w, device=0)
+    assert t2.autotune(f, F.shape[1], cache=cache) == c
+    for cost in (0.25, 64.0):
+        t2.set_fft_cost(cost)
+        y2 = t2.integrate(f, torch.tensor(F, device=DEV)).cpu().numpy()
+        assert relerr(y2[rows], ref) <= 1e-4
