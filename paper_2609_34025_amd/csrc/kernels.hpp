@@ -490,6 +490,71 @@ __global__ void k_fft_stage_global(cpx<T>* __restrict__ buf, int64_t nslots, int
     }
 }
 
+// Blocked pass of the in-place transform along one axis of length 2^lgL
+// (element stride es) of every line (nlines per slot, line stride ls) of
+// every slot (2^lgP elements apart): the radix-2 stages whose butterfly
+// spans are 2^lglo .. 2^(lglo+k-1), done in LDS. A workgroup owns one
+// butterfly group -- the 2^k elements that differ in index bits
+// [lglo, lglo + k) -- for C = 2^lgC consecutive values of the bits below
+// lglo (consecutive addresses when es = 1). Forward (DIF) passes go from
+// the high bits down, inverse (DIT) passes from the low bits up, with the
+// same twiddles exp(-+2 pi i j / 2h) as the LDS transform.
+template <typename T, bool INV>
+__global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
+                           int64_t nlines, int lglo, int k, int lgC,
+                           const cpx<T>* __restrict__ tw, int lgtw) {
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    const int64_t C = (int64_t)1 << lgC;
+    const int64_t nlo = ((int64_t)1 << lglo) >> lgC;       // low-bit chunks
+    const int64_t nhi = (int64_t)1 << (lgL - lglo - k);    // high-bit values
+    int64_t g = blockIdx.x;
+    const int64_t lo_chunk = g % nlo;
+    g /= nlo;
+    const int64_t hi = g % nhi;
+    g /= nhi;
+    const int64_t line = g % nlines;
+    const int64_t slot = g / nlines;
+    cpx<T>* base = buf + (slot << lgP) + line * ls;
+    const int64_t i0 = (hi << (lglo + k)) + lo_chunk * C;
+    const int n = 1 << (k + lgC);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int64_t j = e >> lgC, lo = e & (C - 1);
+        z[e] = base[(i0 + (j << lglo) + lo) * es];
+    }
+    __syncthreads();
+    const int half = n >> 1;
+    for (int s = 0; s < k; ++s) {
+        const int m = INV ? s : (k - 1 - s);  // local span 2^m in j
+        for (int bi = threadIdx.x; bi < half; bi += blockDim.x) {
+            const int lo = bi & (int)(C - 1);
+            const int jb = bi >> lgC;  // butterfly index within the group
+            const int jj = jb & ((1 << m) - 1), blk = jb >> m;
+            const int j0 = (blk << (m + 1)) + jj;
+            const int a0 = (j0 << lgC) + lo, a1 = a0 + (1 << (m + lgC));
+            // global span h = 2^(lglo + m); exponent = index mod h
+            const int lh = lglo + m;
+            const int64_t ex = ((int64_t)jj << lglo) + (lo_chunk * C + lo);
+            const cpx<T> w = tw[ex << (lgtw - lh - 1)];
+            const cpx<T> u = z[a0];
+            const cpx<T> v = z[a1];
+            if (!INV) {
+                z[a0] = cadd(u, v);
+                z[a1] = cmul(csub(u, v), w);
+            } else {
+                const cpx<T> vw = cmulc(v, w);
+                z[a0] = cadd(u, vw);
+                z[a1] = csub(u, vw);
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int64_t j = e >> lgC, lo = e & (C - 1);
+        base[(i0 + (j << lglo) + lo) * es] = z[e];
+    }
+}
+
 template <typename T>
 __global__ void k_spec_fill_global(int lg1, int lg2, int32_t hmax, int32_t xmax,
                                    const T* __restrict__ f, cpx<T>* __restrict__ z) {

@@ -667,6 +667,58 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st
     }
 }
 
+// Pass schedule of a transform along an axis of 2^lgL points: groups of up
+// to 8 index bits with 16 consecutive low indices per workgroup, or one
+// pass when the axis fits 4096 points. Listed in DIF order (high bits
+// first); the inverse runs them in reverse.
+struct PassSpec {
+    int lglo, k, lgC;
+};
+
+inline std::vector<PassSpec> fft_passes(int lgL) {
+    std::vector<PassSpec> v;
+    int hi = lgL;
+    while (hi > 0) {
+        if (hi <= 12) {
+            v.push_back({0, hi, 0});
+            break;
+        }
+        v.push_back({hi - 8, 8, 4});
+        hi -= 8;
+    }
+    return v;
+}
+
+template <typename T, bool INV>
+void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
+                 int64_t nlines, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
+    std::vector<PassSpec> ps = fft_passes(lgL);
+    if (INV) std::reverse(ps.begin(), ps.end());
+    for (const PassSpec& q : ps) {
+        const int64_t groups = nslots * nlines * ((int64_t)1 << (lgL - q.lglo - q.k)) *
+                               (((int64_t)1 << q.lglo) >> q.lgC);
+        const unsigned lds = (unsigned)(((int64_t)1 << (q.k + q.lgC)) * sizeof(tfi::cpx<T>));
+        hipLaunchKernelGGL((tfi::k_fft_pass<T, INV>), dim3((unsigned)groups), dim3(kThreads), lds,
+                           st, buf, lgP, lgL, es, ls, nlines, q.lglo, q.k, q.lgC, tw, lgtw);
+    }
+}
+
+// Forward 2-D transform (rows, then columns) or inverse (columns, then
+// rows) of nslots tables of 2^lg1 x 2^lg2 points.
+template <typename T, bool INV>
+void launch_fft2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::cpx<T>* tw,
+                 int lgtw, hipStream_t st) {
+    const int lgP = lg1 + lg2;
+    const int64_t L1 = (int64_t)1 << lg1, L2 = (int64_t)1 << lg2;
+    if (!INV) {
+        if (lg2) launch_axis<T, false>(buf, nslots, lgP, lg2, 1, L2, L1, tw, lgtw, st);
+        if (lg1) launch_axis<T, false>(buf, nslots, lgP, lg1, L2, 1, L2, tw, lgtw, st);
+    } else {
+        if (lg1) launch_axis<T, true>(buf, nslots, lgP, lg1, L2, 1, L2, tw, lgtw, st);
+        if (lg2) launch_axis<T, true>(buf, nslots, lgP, lg2, 1, L2, L1, tw, lgtw, st);
+    }
+}
+
 // Global-memory FFT passes of one bucket (tables beyond LDS): forward
 // transform of (job, channel pair) slots, product with the spectrum,
 // inverse, read-back.
@@ -688,23 +740,10 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
         hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, val, buf);
-        const unsigned nb = blocks_for(nslots * b.P() / 2);
-        for (int s = 0; s < b.lg2; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                               st, buf, nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
-                               h->lgtw);
-        for (int s = 0; s < b.lg1; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                               st, buf, nslots, lgP, b.lg1, b.lg1 - 1 - s, (int64_t)1 << b.lg2,
-                               tw, h->lgtw);
+        launch_fft2<T, false>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, st);
         hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
                            dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
-        for (int s = 0; s < b.lg1; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
-                               st, buf, nslots, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
-        for (int s = 0; s < b.lg2; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(nb), dim3(kThreads), 0,
-                               st, buf, nslots, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+        launch_fft2<T, true>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, st);
         hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                            0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, buf, g);
@@ -770,15 +809,7 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st) {
         tfi::cpx<T>* z = spec + b.spec_off;
         hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
-        const int lgP = b.lg1 + b.lg2;
-        for (int s = 0; s < b.lg2; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                               dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg2, b.lg2 - 1 - s,
-                               (int64_t)1, tw, h->lgtw);
-        for (int s = 0; s < b.lg1; ++s)
-            hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(blocks_for(b.P() / 2)),
-                               dim3(kThreads), 0, st, z, (int64_t)1, lgP, b.lg1, b.lg1 - 1 - s,
-                               (int64_t)1 << b.lg2, tw, h->lgtw);
+        launch_fft2<T, false>(z, 1, b.lg1, b.lg2, tw, h->lgtw, st);
         h->end(st, ev, "spectrum_global", 2.0 * sizeof(T) * (double)b.P());
     }
 }
@@ -889,25 +920,11 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
             hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                                0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
                                h->d_jc_val, d, val, valg, bv, bg);
-            const unsigned nb = blocks_for(2 * nslots * P / 2);
-            for (int s = 0; s < b.lg2; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, bv, 2 * nslots, lgP, b.lg2, b.lg2 - 1 - s, (int64_t)1, tw,
-                                   h->lgtw);
-            for (int s = 0; s < b.lg1; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, false>), dim3(nb), dim3(kThreads), 0,
-                                   st, bv, 2 * nslots, lgP, b.lg1, b.lg1 - 1 - s,
-                                   (int64_t)1 << b.lg2, tw, h->lgtw);
+            launch_fft2<T, false>(bv, 2 * nslots, b.lg1, b.lg2, tw, h->lgtw, st);
             hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
                                dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
                                (const tfi::cpx<T>*)bg, acc);
-            const unsigned na = blocks_for(nj * P / 2);
-            for (int s = 0; s < b.lg1; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   st, acc, nj, lgP, b.lg1, s, (int64_t)1 << b.lg2, tw, h->lgtw);
-            for (int s = 0; s < b.lg2; ++s)
-                hipLaunchKernelGGL((tfi::k_fft_stage_global<T, true>), dim3(na), dim3(kThreads), 0,
-                                   st, acc, nj, lgP, b.lg2, s, (int64_t)1, tw, h->lgtw);
+            launch_fft2<T, true>(acc, nj, b.lg1, b.lg2, tw, h->lgtw, st);
             hipLaunchKernelGGL(tfi::k_fold_global<T>, dim3(blocks_for(nj * P)), dim3(kThreads), 0,
                                st, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
                                (const tfi::cpx<T>*)acc, df);
