@@ -93,7 +93,11 @@ typedef struct {
                                     cells^2 <= fft_cost * P log2 P, FFT
                                     otherwise (P = padded table cells);
                                     0 = default (4)                        */
-    int32_t reserved[6];
+    int32_t direct_kernel;       /* direct sums: 0 = matrix cores for FP32
+                                    with d >= 8, vector ALU otherwise;
+                                    1 = vector ALU; 2 = matrix cores when
+                                    the dtype is FP32                      */
+    int32_t reserved[5];
 } tfi_build_opts;
 
 /*

@@ -35,7 +35,7 @@ class BuildOpts(C.Structure):
     _fields_ = [("policy", C.c_int32), ("leaf_max", C.c_int32), ("device", C.c_int32),
                 ("table_method", C.c_int32), ("memory_budget_bytes", C.c_uint64),
                 ("no_graphs", C.c_int32), ("fft_cost", C.c_float),
-                ("reserved", C.c_int32 * 6)]
+                ("direct_kernel", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 _lib = None
@@ -94,7 +94,8 @@ def check(rc):
 
 
 def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
-                 table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0):
+                 table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0,
+                 direct_kernel="auto"):
     lib = load()
     parent = np.ascontiguousarray(parent, dtype=np.int64)
     weight = np.ascontiguousarray(weight, dtype=np.int32)
@@ -109,6 +110,7 @@ def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
     o.memory_budget_bytes = int(memory_budget)
     o.no_graphs = 0 if graphs else 1
     o.fft_cost = float(fft_cost)
+    o.direct_kernel = {"auto": 0, "vector": 1, "mfma": 2}[direct_kernel]
     h = C.c_void_p()
     check(lib.tfi_build(parent.ctypes.data, weight.ctypes.data, len(parent),
                         C.byref(o), C.byref(h)))

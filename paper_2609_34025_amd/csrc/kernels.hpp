@@ -209,6 +209,118 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
     }
 }
 
+// Direct tables on the matrix cores (FP32): per job, G = Kmat V with
+// Kmat[i][k] = f(r_i + r_k + |x_i - x_k|) is a dense product, evaluated
+// with v_mfma_f32_16x16x4f32 (D[16x16] += A[16x4] B[4x16]; lane l holds
+// A[l%16][l/16] and B[l/16][l%16] and receives D[4(l/16)+r][l%16] in its
+// r-th result register). A wave owns 16-cell row tiles of the block's
+// output cells; for every k-step of 4 sources each lane forms its one
+// kernel entry (0 outside its row's job) and reuses it for all 16-channel
+// tiles, read from an LDS tile of kMfSrc source cells x up to kMfCh
+// channels. Blocks, padding and job ranges are those of k_direct.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+constexpr int kMfSrc = kDirOut;  // source cells per LDS tile
+
+__global__ void __launch_bounds__(kDirThreads)
+k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
+              const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
+              const int32_t* __restrict__ qjb, const int32_t* __restrict__ qje,
+              const float* __restrict__ f, int32_t flds, const float* __restrict__ val,
+              float* __restrict__ g) {
+    __shared__ float sv[kMfSrc * 17];
+    __shared__ int32_t sr[kMfSrc], sx[kMfSrc];
+    extern __shared__ unsigned char dyn_raw[];
+    float* sf = reinterpret_cast<float*>(dyn_raw);
+    const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
+    const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
+    const float* fp = f;
+    if (flds > 0) {
+        for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) sf[k] = f[k];
+        fp = sf;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;  // A row / k of this lane
+    const int32_t ntiles = (oe - os + 15) >> 4;
+    // this wave's row tiles t = wave + 4 q (at most 4): row data per lane
+    int32_t ri[4], xi[4], jb[4], je[4], tjb[4], tje[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t t = wave + 4 * q;
+        const int32_t i = os + 16 * t + lr;
+        const bool ok = t < ntiles && i < oe;
+        ri[q] = ok ? dl_r[i] : 0;
+        xi[q] = ok ? dl_x[i] : 0;
+        jb[q] = ok ? qjb[i >> 2] : 0;
+        je[q] = ok ? qje[i >> 2] : 0;
+        if (t < ntiles) {
+            tjb[q] = qjb[(os + 16 * t) >> 2];
+            tje[q] = qje[(min(oe, os + 16 * t + 16) - 1) >> 2];
+        } else {
+            tjb[q] = tje[q] = 0;
+        }
+    }
+    for (int32_t c0 = 0; c0 < d; c0 += 16) {
+        const int32_t nch = min(16, d - c0);
+        v4f_t acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+        for (int32_t ts = ss; ts < se; ts += kMfSrc) {
+            const int32_t tn = min(kMfSrc, se - ts);
+            __syncthreads();
+            for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
+                sr[k] = dl_r[ts + k];
+                sx[k] = dl_x[ts + k];
+            }
+            for (int32_t e = threadIdx.x; e < tn * 16; e += blockDim.x) {
+                const int32_t k = e >> 4, cc = e & 15;
+                const int32_t row = dl_row[ts + k];
+                sv[k * 17 + cc] = (row >= 0 && cc < nch) ? val[(int64_t)row * d + c0 + cc] : 0.f;
+            }
+            __syncthreads();
+            int32_t kb[4], ke[4];
+            int32_t lo = 1 << 30, hi = -1;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                kb[q] = max(tjb[q], ts);
+                ke[q] = min(tje[q], ts + tn);
+                if (kb[q] < ke[q]) {
+                    lo = min(lo, kb[q]);
+                    hi = max(hi, ke[q]);
+                }
+            }
+            // the four row tiles advance together: independent MFMA chains
+            for (int32_t k4 = lo; k4 < hi; k4 += 4) {
+                const int32_t k = k4 + lk, kl = k - ts;
+                const float b = sv[kl * 17 + lr];
+                const int32_t rk = sr[kl], xk = sx[kl];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (k4 < kb[q] || k4 >= ke[q]) continue;  // uniform per wave
+                    float a = 0.f;
+                    if (k >= jb[q] && k < je[q]) {
+                        const int32_t dx = xi[q] - xk;
+                        a = fp[ri[q] + rk + (dx < 0 ? -dx : dx)];
+                    }
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        // D[4 (l/16) + r][l % 16] of every row tile
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int32_t t = wave + 4 * q;
+            if (t >= ntiles || lr >= nch) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int32_t i = os + 16 * t + 4 * lk + r;
+                if (i >= oe) continue;
+                const int32_t row = dl_row[i];
+                if (row >= 0) g[(int64_t)row * d + c0 + lr] = acc[q][r];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- gather --
 // One thread per (vertex, VEC channels): adds, over the calls holding the
 // vertex, the call's table value minus the component correction (row -1

@@ -148,6 +148,7 @@ struct tfi_plan {
     hipEvent_t ev_fork = nullptr, ev_a = nullptr, ev_b = nullptr, ev_c = nullptr,
                ev_d = nullptr, ev_in = nullptr, ev_out = nullptr;
     bool use_graphs = true;
+    int direct_kernel = 0;  // 0 auto, 1 vector, 2 matrix cores (FP32)
     struct GraphEntry {
         GraphKey key;
         hipGraphExec_t exec;
@@ -846,9 +847,16 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
     const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
-    hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
-                       (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
-                       h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
+    const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
+    if (mfma)
+        hipLaunchKernelGGL(tfi::k_direct_mfma, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                           (unsigned)(flds * sizeof(float)), st, d, h->d_dblk, h->d_dl_r,
+                           h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, (const float*)f, flds,
+                           (const float*)val, (float*)g);
+    else
+        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                           (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
+                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
     h->end(st, ev, "direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect);
 }
 
@@ -1211,6 +1219,9 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     h->popt = po;
     h->budget = o.memory_budget_bytes;
     h->use_graphs = o.no_graphs == 0;
+    if (o.direct_kernel < 0 || o.direct_kernel > 2)
+        return fail(TFI_ERR_ARG, "tfi_build: direct_kernel must be 0, 1 or 2");
+    h->direct_kernel = o.direct_kernel;
     if (const char* e = std::getenv("TFI_NO_GRAPHS"))
         if (e[0] && e[0] != '0') h->use_graphs = false;
     if (o.device >= 0) {

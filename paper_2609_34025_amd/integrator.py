@@ -37,16 +37,19 @@ class TreeIntegrator:
     graphs  replay captured hipGraphs (True) or launch kernels directly.
     fft_cost  direct sums for a table iff cells^2 <= fft_cost * P log2 P
             (0 = default 4).
+    direct_kernel  'auto' (matrix cores for FP32 with d >= 8), 'vector' or
+            'mfma'.
     """
 
     def __init__(self, parent, weight, *, policy="adaptive", leaf_max=0, device=0,
-                 table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0):
+                 table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0,
+                 direct_kernel="auto"):
         if device is not None and isinstance(device, torch.device):
             device = device.index or 0
         self._h = _lib.build_handle(parent, weight, policy=policy, leaf_max=leaf_max,
                                     device=device, table_method=table_method,
                                     memory_budget=memory_budget, graphs=graphs,
-                                    fft_cost=fft_cost)
+                                    fft_cost=fft_cost, direct_kernel=direct_kernel)
         self.device = None if device is None else torch.device("cuda", int(device))
         lib = _lib.load()
         self.num_vertices = int(lib.tfi_num_vertices(self._h))

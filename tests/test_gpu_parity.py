@@ -138,13 +138,16 @@ def test_large_tables_through_global_memory(dtype):
     check(p, w, lambda K: 1.0 / (1.0 + np.arange(K)) ** 2, F, dtype, table_method="fft")
 
 
-def test_channel_counts_and_vector_field():
+@pytest.mark.parametrize("kernel", ["vector", "mfma"])
+def test_channel_counts_and_vector_field(kernel):
     rng = np.random.default_rng(15)
     p, _ = S.random_recursive(700, rng)
     w = S.uniform_weights(p, 1, 6, rng)
-    for d in (1, 2, 3, 16, 33, 64):
+    for d in (1, 2, 3, 16, 33, 64, 100):
         F = rng.standard_normal((len(p), d))
-        check(p, w, lambda K: np.exp(-0.05 * np.arange(K)), F, torch.float32)
+        for method in ("auto", "direct"):
+            check(p, w, lambda K: np.exp(-0.05 * np.arange(K)), F, torch.float32,
+                  direct_kernel=kernel, table_method=method)
     t = TreeIntegrator(p, w, device=0)
     f = torch.exp(-0.05 * torch.arange(t.kernel_length, dtype=torch.float64, device=DEV))
     x = torch.tensor(rng.standard_normal(len(p)), device=DEV)
