@@ -27,8 +27,62 @@ METRIC = ("vertex·channels integrated/s, fwd+bwd batched vs plain fwd, "
           "at rel err ≤1e-4")
 
 
+# published dense peaks of one MI355X (FP32 vector includes packed issue)
+PEAK_TFLOPS = {"mfma": {"f32": 157.3, "f64": 78.6}, "alu": {"f32": 157.3, "f64": 78.6}}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+LIB_SOURCES = ["kernels.hpp", "tfi.hip", "plan.cpp", "plan.hpp"]
+
+
+def measured_traffic(workload, stage):
+    """HBM bytes per launch of a stage from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary has
+    no line for it or the library sources changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_pmc.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for name in LIB_SOURCES:
+        with open(os.path.join(ROOT, "paper_2609_34025_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
+    pat = re.compile(r"<!-- traffic workload=(\S+) stage=(\S+) bytes_per_launch=(\d+) "
+                     r"sources_sha256=([0-9a-f]+) -->")
+    with open(path) as fh:
+        for line in fh:
+            m = pat.search(line)
+            if m and m.group(1) == workload and m.group(2) == stage and m.group(4) == sha:
+                return int(m.group(3))
+    return None
+
+
+def stage_roofline(name, sd, dtype, workload=None):
+    """Roofline entry of one profiled stage ({launches, ms, bytes, flops})."""
+    sec = sd["ms"] * 1e-3
+    gbs = sd["bytes"] / sec / 1e9
+    unit = "mfma" if name.endswith("_mfma") else "alu"
+    peak_tf = PEAK_TFLOPS[unit][dtype]
+    flops = sd.get("flops", 0.0)
+    if flops and flops / (peak_tf * 1e12) > sd["bytes"] / (HBM_PEAK_GBS * 1e9):
+        tfs = flops / sec / 1e12
+        r = {"bound": unit, "achieved": round(tfs, 3), "peak": peak_tf, "unit": "TFLOP/s",
+             "frac": round(tfs / peak_tf, 4), "hbm_gbs": round(gbs, 2)}
+    else:
+        r = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if flops:
+            r["tflops"] = round(flops / sec / 1e12, 3)
+    r.update({"kernel": name, "traffic": measured_traffic(workload, name) if workload else None,
+              "launch_us": round(1e3 * sd["ms"] / sd["launches"], 3),
+              "bytes_per_launch": sd["bytes"] / sd["launches"],
+              "flops_per_launch": flops / sd["launches"]})
+    return r
 
 
 def main():
@@ -41,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default direct/FFT rule instead of tuning it")
+    ap.add_argument("--fft-cost", type=float, default=None,
+                    help="use this direct/FFT cost constant instead of tuning it")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched forest forward+backward measurement")
     ap.add_argument("--copy-probe", action="store_true",
@@ -69,7 +125,11 @@ def main():
     fs = [torch.tensor(t, dtype=torch.float32, device=dev) for t in tabs]
     Ft = torch.tensor(F, device=dev)
     t0 = time.perf_counter()
-    cost = tfi.autotune(fs[0], d) if not args.no_autotune else tfi.stats()["fft_cost"]
+    if args.fft_cost is not None:
+        tfi.set_fft_cost(args.fft_cost)
+        cost = args.fft_cost
+    else:
+        cost = tfi.autotune(fs[0], d) if not args.no_autotune else tfi.stats()["fft_cost"]
     tune_s = time.perf_counter() - t0
     log(f"bench: N={N} d={d} build {build_s:.2f}s kernel_length={K} "
         f"autotuned fft_cost={cost} in {tune_s:.2f}s")
@@ -117,26 +177,28 @@ def main():
     ok = all(e <= 1e-4 for e in errs.values())
     log(f"bench: parity {errs} ok={ok}")
 
-    # dominant stage and its roofline (algorithmic bytes / event time)
+    # dominant stage and its roofline: algorithmic bytes and, for the
+    # contraction stages, flops per launch over the event-timed launch
+    # duration; the bound is whichever peak the stage's work would take
+    # longer to reach
     dom = max(stages, key=lambda k: stages[k]["ms"])
-    sd = stages[dom]
-    achieved = sd["bytes"] / (sd["ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
-                "launch_us": round(1e3 * sd["ms"] / sd["launches"], 3),
-                "bytes_per_launch": sd["bytes"] / sd["launches"]}
+    roofline = stage_roofline(dom, stages[dom], "f32", "rrt100k")
 
     cpu = None
     if not args.no_cpu_baseline:
         Fd = F.astype(np.float64)
         cores = oracle.num_threads()
-        probe = np.arange(0, N, N // 32)[:32]
-        t0 = time.perf_counter()
-        for tab in tabs:
-            oracle.integrate(p, w, tab, Fd, rows=probe)
-        per_row = (time.perf_counter() - t0) / len(probe)
-        nrows = int(min(N, max(64, args.cpu_seconds / max(per_row, 1e-9))))
+        # marginal cost per row from two probe sizes (each call also pays a
+        # fixed setup: adjacency build and thread start)
+        probe_t = []
+        for m in (64, 512):
+            probe = np.random.default_rng(m).choice(N, m, replace=False)
+            t0 = time.perf_counter()
+            for tab in tabs:
+                oracle.integrate(p, w, tab, Fd, rows=probe)
+            probe_t.append(time.perf_counter() - t0)
+        per_row = max((probe_t[1] - probe_t[0]) / 448, probe_t[1] / 512 * 0.25, 1e-9)
+        nrows = int(min(N, max(512, args.cpu_seconds / per_row)))
         sample = np.random.default_rng(7).choice(N, nrows, replace=False)
         t0 = time.perf_counter()
         for tab in tabs:
@@ -197,7 +259,10 @@ def batched_fwd_bwd(args, plain_value):
     build_s = time.perf_counter() - t0
     K = tfi.kernel_length
     rng = np.random.default_rng(33)
-    if not args.no_autotune:
+    if args.fft_cost is not None:
+        tfi.set_fft_cost(args.fft_cost)
+        cost = args.fft_cost
+    elif not args.no_autotune:
         ftune = torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=dev)
         cost = tfi.autotune(ftune, d)
     else:
@@ -237,6 +302,8 @@ def batched_fwd_bwd(args, plain_value):
     for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"]):
         log(f"batched stage {k:14s} {v['launches']:4d} launches {1e3 * v['ms'] / v['launches']:10.2f} "
             f"us/launch")
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    roofline = stage_roofline(dom, stages[dom], "f32", "grid512")
 
     # parity
     rows = np.random.default_rng(99).choice(n, 512, replace=False)
@@ -269,7 +336,8 @@ def batched_fwd_bwd(args, plain_value):
                         "loss sum(W * out)",
             "n": int(n), "d": int(d), "trees": int(len(W["offsets"]) - 1),
             "kernel_length": int(K), "build_s": round(build_s, 3), "fft_cost": cost,
-            "parity": {"rows": 512, "rel_err": errs, "ok": ok}, "stages": stages}
+            "parity": {"rows": 512, "rel_err": errs, "ok": ok}, "roofline": roofline,
+            "stages": stages}
 
 
 if __name__ == "__main__":

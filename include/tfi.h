@@ -195,9 +195,14 @@ int tfi_set_fft_cost(tfi_handle h, float cost);
  * on the handle records a HIP event pair around each stage (on the same
  * stream as the stage's kernels) and adds the stage's algorithmic bytes
  * (the bytes the stage must move: inputs read once, outputs written once,
- * index arrays; independent of caching) to a per-stage tally.
+ * index arrays; independent of caching) and, for the stages that are
+ * dense contractions (direct table sums, dense leaf tiles and their df
+ * counterparts), their arithmetic (2 flops per multiply-add over the
+ * unpadded cell or vertex pairs; 0 for the other stages) to a per-stage
+ * tally.
  * tfi_profile_report waits for the recorded events, writes a JSON object
- * {"stage": {"launches": n, "ms": total, "bytes": total}, ...} into
+ * {"stage": {"launches": n, "ms": total, "bytes": total, "flops": total},
+ * ...} into
  * json[cap] (truncated to fit), resets the tally and returns the full
  * length needed, or a negative status.
  */

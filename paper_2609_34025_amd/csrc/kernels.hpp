@@ -544,9 +544,10 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
 }
 
 // ---------------------------------------------- FFT through global memory --
-// Tables too large for LDS: the same in-place DIF/DIT transforms, one
-// radix-2 stage per launch over every (job, channel pair) line set of a
-// bucket. Buffer layout: slot s = job * npairs + pair holds P complex.
+// Tables too large for LDS: the same in-place DIF/DIT transforms over every
+// (job, channel pair) slot of a bucket, as blocked passes (k_fft_pass) of up
+// to 12 radix-2 stages each, every pass staged through LDS. Buffer layout:
+// slot s = job * npairs + pair holds P complex.
 template <typename T>
 __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
                               const int32_t* __restrict__ jobs,
@@ -565,40 +566,6 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
         const int64_t row = (L1 - jc_r[k]) & (L1 - 1);
         const int64_t vr = (int64_t)jc_val[k] * d;
         z[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
-    }
-}
-
-template <typename T, bool INV>
-__global__ void k_fft_stage_global(cpx<T>* __restrict__ buf, int64_t nslots, int lgP, int lgL,
-                                   int lh, int64_t es, const cpx<T>* __restrict__ tw, int lgtw) {
-    // Butterflies of span 2^lh along an axis of length 2^lgL with element
-    // stride es; every slot holds one 2^lgP-element array.
-    const int64_t P = (int64_t)1 << lgP;
-    const int64_t per_slot = P >> 1;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= nslots * per_slot) return;
-    const int64_t slot = tid / per_slot;
-    const int64_t bi = tid - slot * per_slot;
-    const int64_t half = (int64_t)1 << (lgL - 1);
-    const int64_t line = bi / half;
-    const int64_t m = bi - line * half;
-    const int64_t h = (int64_t)1 << lh;
-    const int64_t j = m & (h - 1);
-    const int64_t blk = m >> lh;
-    // line index -> base offset: lines enumerate the other axis
-    const int64_t base = (es == 1) ? line << lgL : line;
-    const int64_t i0 = slot * P + base + ((blk << (lh + 1)) + j) * es;
-    const int64_t i1 = i0 + h * es;
-    const cpx<T> w = tw[j << (lgtw - lh - 1)];
-    const cpx<T> u = buf[i0];
-    const cpx<T> v = buf[i1];
-    if (!INV) {
-        buf[i0] = cadd(u, v);
-        buf[i1] = cmul(csub(u, v), w);
-    } else {
-        const cpx<T> vw = cmulc(v, w);
-        buf[i0] = cadd(u, vw);
-        buf[i1] = csub(u, vw);
     }
 }
 

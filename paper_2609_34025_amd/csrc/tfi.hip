@@ -114,6 +114,7 @@ struct tfi_plan {
     int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
     int32_t *d_qjb = nullptr, *d_qje = nullptr, *d_dblk = nullptr;
     int64_t ndirect = 0, ndblk = 0;
+    double direct_pairs = 0;  // sum over direct jobs of cells^2 (unpadded)
     // scatter: levels of bounded segment sums
     struct SegLevel {
         bool indexed = false;
@@ -146,7 +147,7 @@ struct tfi_plan {
     // streams, fork/join events, graph cache
     hipStream_t s1 = nullptr, s2 = nullptr, cs0 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_a = nullptr, ev_b = nullptr, ev_c = nullptr,
-               ev_d = nullptr, ev_in = nullptr, ev_out = nullptr;
+               ev_d = nullptr;
     bool use_graphs = true;
     int direct_kernel = 0;  // 0 auto, 1 vector, 2 matrix cores (FP32)
     struct GraphEntry {
@@ -160,12 +161,12 @@ struct tfi_plan {
     // stage profiling: event pairs recorded on the launch streams
     struct Tally {
         int64_t launches = 0;
-        double ms = 0, bytes = 0;
+        double ms = 0, bytes = 0, flops = 0;
     };
     struct Pending {
         std::string stage;
         hipEvent_t e0, e1;
-        double bytes;
+        double bytes, flops;
     };
     bool prof = false;
     std::map<std::string, Tally> tally;
@@ -188,12 +189,15 @@ struct tfi_plan {
         if (e) (void)hipEventRecord(e, st);
         return e;
     }
-    void end(hipStream_t st, hipEvent_t e0, const char* stage, double bytes) {
+    // bytes: algorithmic HBM bytes of the stage; flops: its arithmetic
+    // (2 per multiply-add) where the stage is a contraction, else 0
+    void end(hipStream_t st, hipEvent_t e0, const char* stage, double bytes,
+             double flops = 0) {
         if (!prof || !e0) return;
         hipEvent_t e1 = take_event();
         if (!e1) return;
         (void)hipEventRecord(e1, st);
-        pending.push_back({stage, e0, e1, bytes});
+        pending.push_back({stage, e0, e1, bytes, flops});
     }
 
     void drop_graphs() {
@@ -213,7 +217,7 @@ struct tfi_plan {
             pool.push_back(q.e1);
         }
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-        for (hipEvent_t e : {ev_fork, ev_a, ev_b, ev_c, ev_d, ev_in, ev_out})
+        for (hipEvent_t e : {ev_fork, ev_a, ev_b, ev_c, ev_d})
             if (e) (void)hipEventDestroy(e);
         for (hipStream_t s : {s1, s2, cs0})
             if (s) (void)hipStreamDestroy(s);
@@ -279,6 +283,7 @@ struct tfi_plan {
             for (int k = 0; k < 3; ++k) tiers[t][k] = Tier();
         }
         ndirect = ndblk = 0;
+        direct_pairs = 0;
         spec_elems = 0;
         return TFI_OK;
     }
@@ -494,7 +499,7 @@ int upload_static(tfi_plan* h) {
     TFI_HIP(hipStreamCreateWithFlags(&h->s2, hipStreamNonBlocking));
     TFI_HIP(hipStreamCreateWithFlags(&h->cs0, hipStreamNonBlocking));
     for (hipEvent_t* e :
-         {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_d, &h->ev_in, &h->ev_out})
+         {&h->ev_fork, &h->ev_a, &h->ev_b, &h->ev_c, &h->ev_d})
         TFI_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return TFI_OK;
 }
@@ -547,6 +552,7 @@ int upload_methods(tfi_plan* h) {
             const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
             const int32_t jb = (int32_t)dl_r.size();
             const int32_t n = ce - cb, np = (n + 3) & ~3;
+            h->direct_pairs += (double)n * n;
             for (int32_t i = 0; i < np; ++i) {
                 const bool real = i < n;
                 dl_r.push_back(real ? p.jc_r[cb + i] : 0);
@@ -788,7 +794,8 @@ void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_
                        h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
     const double nv = (double)p.leaf_v.size();
     h->end(st, ev, "leaf",
-           2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+           2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size(),
+           2.0 * d * (double)p.leaf_pairs);
 }
 
 template <typename T>
@@ -857,7 +864,9 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
         hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
                            (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
                            h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
-    h->end(st, ev, "direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect);
+    h->end(st, ev, mfma ? "direct_mfma" : "direct",
+           2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
+           2.0 * d * h->direct_pairs);
 }
 
 template <typename T>
@@ -950,7 +959,8 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
     hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0, st,
                        d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje,
                        val, valg, (int32_t)p.kernel_len, df);
-    h->end(st, ev, "df_direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect);
+    h->end(st, ev, "df_direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
+           2.0 * d * h->direct_pairs);
 }
 
 template <typename T>
@@ -962,7 +972,8 @@ void enq_df_leaf(tfi_plan* h, int32_t d, const T* F, const T* gout, double* df, 
                        d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
                        (int32_t)p.kernel_len, df);
     const double nv = (double)p.leaf_v.size();
-    h->end(st, ev, "df_leaf", 2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size());
+    h->end(st, ev, "df_leaf", 2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size(),
+           2.0 * d * (double)p.leaf_pairs);
 }
 
 inline void fork3(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
@@ -1062,7 +1073,14 @@ int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
 // stream and before its later work.
 template <typename Enq>
 int run_dag(tfi_plan* h, const GraphKey& key, hipStream_t caller, Enq enq) {
-    if (h->prof || !h->use_graphs) {
+    if (h->prof) {
+        // stage timing: every stage on the caller's stream, one after the
+        // other, so that each event pair brackets that stage's kernels alone
+        enq(caller, caller, caller);
+        TFI_HIP(hipGetLastError());
+        return TFI_OK;
+    }
+    if (!h->use_graphs) {
         enq(caller, h->s1, h->s2);
         TFI_HIP(hipGetLastError());
         return TFI_OK;
@@ -1093,17 +1111,15 @@ int run_dag(tfi_plan* h, const GraphKey& key, hipStream_t caller, Enq enq) {
             auto it = std::min_element(h->graphs.begin(), h->graphs.end(),
                                        [](const tfi_plan::GraphEntry& a,
                                           const tfi_plan::GraphEntry& b) { return a.last < b.last; });
-            TFI_HIP(hipStreamSynchronize(h->cs0));
+            TFI_HIP(hipDeviceSynchronize());  // the evicted graph may still run
             (void)hipGraphExecDestroy(it->exec);
             h->graphs.erase(it);
         }
         h->graphs.push_back({key, exec, ++h->tick});
     }
-    TFI_HIP(hipEventRecord(h->ev_in, caller));
-    TFI_HIP(hipStreamWaitEvent(h->cs0, h->ev_in, 0));
-    TFI_HIP(hipGraphLaunch(exec, h->cs0));
-    TFI_HIP(hipEventRecord(h->ev_out, h->cs0));
-    TFI_HIP(hipStreamWaitEvent(caller, h->ev_out, 0));
+    // the executable graph runs in order on the caller's stream (its side
+    // branches fork from and join back into that stream)
+    TFI_HIP(hipGraphLaunch(exec, caller));
     return TFI_OK;
 }
 
@@ -1406,6 +1422,7 @@ int64_t tfi_profile_report(tfi_handle h, char* json, size_t cap) {
         t.launches++;
         t.ms += ms;
         t.bytes += q.bytes;
+        t.flops += q.flops;
         h->pool.push_back(q.e0);
         h->pool.push_back(q.e1);
     }
@@ -1414,9 +1431,10 @@ int64_t tfi_profile_report(tfi_handle h, char* json, size_t cap) {
     bool first = true;
     char buf[256];
     for (auto& kv : h->tally) {
-        std::snprintf(buf, sizeof(buf), "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"bytes\":%.1f}",
+        std::snprintf(buf, sizeof(buf),
+                      "%s\"%s\":{\"launches\":%lld,\"ms\":%.6f,\"bytes\":%.1f,\"flops\":%.1f}",
                       first ? "" : ",", kv.first.c_str(), (long long)kv.second.launches,
-                      kv.second.ms, kv.second.bytes);
+                      kv.second.ms, kv.second.bytes, kv.second.flops);
         s += buf;
         first = false;
     }
