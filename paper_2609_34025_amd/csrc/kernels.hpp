@@ -787,6 +787,131 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
     if (use_lds) hist_flush<T>(lh, df, K);
 }
 
+// Direct jobs on the matrix cores (FP32). The pair terms <gbar_i, val_j>
+// of a job are its Gram matrix Gbar V^T, formed in 16 x 16 blocks with
+// v_mfma_f32_16x16x4f32 and binned by surrogate distance. The sum runs over
+// all channels, so any fixed assignment of channels to the four k-slots of
+// an MFMA step works when both operands use the same one: in a chunk of
+// 4 * CPL channels, lane (lr, lk) supplies channels c0 + lk * CPL + s at
+// step s, for gbar of row lr of the row tile (A[lr][lk]) and val of source
+// lr of the source tile (B[lk][lr]), so both come as contiguous runs of a
+// row. Result register r of lane (lr, lk) is the pair (row 4 lk + r,
+// source lr). A wave owns the row tiles t = wave + 4 q (q < 4) of the
+// block's output cells, keeps their gbar runs in registers, and streams
+// source tiles of 16 cells straight from memory (sources of a job are
+// consecutive value rows). Blocks, padding and job ranges are those of
+// k_direct.
+template <int CPL>
+__device__ __forceinline__ void load_run(const float* __restrict__ base, int32_t row, int32_t d,
+                                         int32_t ch0, float (&v)[CPL]) {
+    if (row < 0) {
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) v[s] = 0.f;
+        return;
+    }
+    const float* p = base + (int64_t)row * d + ch0;
+    if ((CPL & 3) == 0 && (d & 3) == 0 && ch0 + CPL <= d) {
+#pragma unroll
+        for (int s = 0; s < CPL; s += 4) {
+            const float4 q = *reinterpret_cast<const float4*>(p + s);
+            v[s] = q.x;
+            v[s + 1] = q.y;
+            v[s + 2] = q.z;
+            v[s + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < CPL; ++s) v[s] = (ch0 + s < d) ? p[s] : 0.f;
+    }
+}
+
+template <int CPL>
+__global__ void __launch_bounds__(kDirThreads)
+k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
+                 const int32_t* __restrict__ dl_r, const int32_t* __restrict__ dl_x,
+                 const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
+                 const int32_t* __restrict__ qje, const float* __restrict__ val,
+                 const float* __restrict__ valg, int32_t K, double* __restrict__ df) {
+    __shared__ float lh[df_hist_bins<float>()];
+    const bool use_lds = K <= df_hist_bins<float>();
+    float* lhp = use_lds ? lh : nullptr;
+    if (use_lds)
+        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.f;
+    __syncthreads();
+    const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int32_t ntiles = (oe - os + 15) >> 4;
+    // per row tile: the A-side row (lr), the result-side rows 4 lk + r with
+    // their coordinates and signs (0 for padding), the quad's job range and
+    // the tile's source range
+    int32_t arow[4], rr[4][4], rx[4][4], qb[4], qe[4], tjb[4], tje[4];
+    float coef[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t t = wave + 4 * q;
+        const int32_t tb = os + 16 * t;
+        const bool tok = t < ntiles;
+        arow[q] = (tok && tb + lr < oe) ? dl_row[tb + lr] : -1;
+        const int32_t Q = (tb >> 2) + lk;
+        const bool qok = tok && 4 * Q < oe;
+        qb[q] = qok ? qjb[Q] : 0;
+        qe[q] = qok ? qje[Q] : 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int32_t i = 4 * Q + r;
+            const int32_t row = qok ? dl_row[i] : -1;
+            rr[q][r] = qok ? dl_r[i] : 0;
+            rx[q][r] = qok ? dl_x[i] : 0;
+            coef[q][r] = row < 0 ? 0.f : (row < NA ? 1.f : -1.f);
+        }
+        if (tok) {
+            tjb[q] = qjb[tb >> 2];
+            tje[q] = qje[(min(oe, tb + 16) - 1) >> 2];
+        } else {
+            tjb[q] = tje[q] = 0;
+        }
+    }
+    int32_t lo = 1 << 30, hi = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (tjb[q] < tje[q]) {
+            lo = min(lo, tjb[q]);
+            hi = max(hi, tje[q]);
+        }
+    for (int32_t c0 = 0; c0 < d; c0 += 4 * CPL) {
+        const int32_t ch0 = c0 + lk * CPL;
+        float gq[4][CPL];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) load_run<CPL>(valg, arow[q], d, ch0, gq[q]);
+        for (int32_t k16 = lo; k16 < hi; k16 += 16) {
+            const int32_t j = k16 + lr;
+            const bool jok = j < hi;
+            const int32_t jrow = jok ? dl_row[j] : -1;
+            const int32_t rj = jok ? dl_r[j] : 0, xj = jok ? dl_x[j] : 0;
+            float vs[CPL];
+            load_run<CPL>(val, jrow, d, ch0, vs);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (k16 + 16 <= tjb[q] || k16 >= tje[q]) continue;  // uniform per wave
+                v4f_t acc = (v4f_t){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < CPL; ++s)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(gq[q][s], vs[s], acc, 0, 0, 0);
+                if (jrow < 0 || j < qb[q] || j >= qe[q]) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (coef[q][r] == 0.f || acc[r] == 0.f) continue;
+                    const int32_t dx = rx[q][r] - xj;
+                    hist_add<float>(lhp, df, rr[q][r] + rj + (dx < 0 ? -dx : dx),
+                                    coef[q][r] * acc[r]);
+                }
+            }
+        }
+    }
+    if (use_lds) hist_flush<float>(lh, df, K);
+}
+
 // Leaf tiles: pairs inside each tile, distance from D. The group's gout
 // and F rows are staged in LDS kDirCh channels at a time; a thread owns up
 // to kDfLeafRows (quad, source j) rows = 4 pair dot products each.

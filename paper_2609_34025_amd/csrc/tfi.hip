@@ -956,10 +956,30 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
     if (h->ndblk == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
-    hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0, st,
-                       d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje,
-                       val, valg, (int32_t)p.kernel_len, df);
-    h->end(st, ev, "df_direct", 2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
+    const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
+    if (mfma) {
+        // channels per lane per chunk: the smallest run that covers d (up to 16)
+        const int cpl = d > 32 ? 16 : d > 16 ? 8 : d > 8 ? 4 : d > 4 ? 2 : 1;
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads), 0, st, d,
+                               p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
+                               h->d_qje, (const float*)val, (const float*)valg,
+                               (int32_t)p.kernel_len, df);
+        };
+        switch (cpl) {
+            case 16: launch(tfi::k_df_direct_mfma<16>); break;
+            case 8: launch(tfi::k_df_direct_mfma<8>); break;
+            case 4: launch(tfi::k_df_direct_mfma<4>); break;
+            case 2: launch(tfi::k_df_direct_mfma<2>); break;
+            default: launch(tfi::k_df_direct_mfma<1>); break;
+        }
+    } else {
+        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
+                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
+                           h->d_qje, val, valg, (int32_t)p.kernel_len, df);
+    }
+    h->end(st, ev, mfma ? "df_direct_mfma" : "df_direct",
+           2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
            2.0 * d * h->direct_pairs);
 }
 

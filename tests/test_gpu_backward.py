@@ -151,3 +151,19 @@ def test_adjoint_identity_fp32():
     dF, _ = t.backward(f, F, G, need_df=False)
     rhs = (dF.double() * F.double()).sum().item()
     assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+
+
+@pytest.mark.parametrize("kernel", ["vector", "mfma"])
+def test_backward_fp32_channel_counts(kernel):
+    # df of direct tables through both pair-product kernels; the matrix-core
+    # kernel takes channel runs of 1, 2, 4, 8 and 16 per lane and chunks of
+    # 64 channels beyond that
+    rng = np.random.default_rng(21)
+    p, _ = S.random_recursive(600, rng)
+    w = S.uniform_weights(p, 1, 6, rng)
+    for d in (1, 3, 5, 8, 12, 17, 33, 64, 100):
+        F = rng.standard_normal((len(p), d))
+        G = rng.standard_normal((len(p), d))
+        for method in ("direct", "auto"):
+            check_backward(p, w, lambda K: np.exp(-0.05 * np.arange(K)) + 0.1 / (1 + np.arange(K)),
+                           F, G, torch.float32, table_method=method, direct_kernel=kernel)
