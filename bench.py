@@ -264,7 +264,7 @@ def batched_fwd_bwd(args, plain_value):
         cost = args.fft_cost
     elif not args.no_autotune:
         ftune = torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=dev)
-        cost = tfi.autotune(ftune, d)
+        cost = tfi.autotune(ftune, d, backward=True)
     else:
         cost = tfi.stats()["fft_cost"]
     log(f"batched: autotuned fft_cost={cost}")

@@ -174,18 +174,21 @@ int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
 
 /*
  * Autotuning of the per-table evaluation method. Each candidate value of
- * the cost constant of tfi_build_opts.fft_cost (0.25, 1, 4, 16, 64)
- * re-assigns every table job to direct sums or FFT, rebuilds the device
- * job lists, and times forward integrations of d channels of dtype with
- * the kernel table f (device, tfi_kernel_length entries) on `stream`
- * (HIP events; field values do not affect the timing). The fastest value
- * stays in effect and is written to *best_cost (host). The kernel length
- * does not change. Uses temporary device memory for two [N x d] fields.
+ * the cost constant of tfi_build_opts.fft_cost (0.25, 1, 2, 4, 8, 16, 32,
+ * 64) re-assigns every table job to direct sums or FFT, rebuilds the
+ * device job lists, and times passes of d channels of dtype with the kernel
+ * table f (device, tfi_kernel_length entries) on `stream` (HIP events).
+ * with_backward = 0 times forward integrations; with_backward != 0 times a
+ * forward integration followed by the adjoint with both dF and df (the
+ * work of one training step). The timed fields hold ones. The fastest
+ * value stays in effect and is written to *best_cost (host). The kernel
+ * length does not change. Uses temporary device memory for three [N x d]
+ * fields and one FP64 kernel-length histogram.
  * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE (method forced at
  * build), TFI_ERR_HIP, TFI_ERR_BUDGET, TFI_ERR_OOM.
  */
 int tfi_autotune(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
-                 float *best_cost, void *stream);
+                 int with_backward, float *best_cost, void *stream);
 
 /* Apply a cost constant (e.g. a cached tuning result) without timing. */
 int tfi_set_fft_cost(tfi_handle h, float cost);

@@ -76,7 +76,7 @@ def load():
     lib.tfi_profile.restype = C.c_int
     lib.tfi_profile_report.argtypes = [vp, C.c_char_p, C.c_size_t]
     lib.tfi_profile_report.restype = i64
-    lib.tfi_autotune.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
+    lib.tfi_autotune.argtypes = [vp, vp, i64, C.c_int, C.c_int, C.POINTER(C.c_float), vp]
     lib.tfi_autotune.restype = C.c_int
     lib.tfi_set_fft_cost.argtypes = [vp, C.c_float]
     lib.tfi_set_fft_cost.restype = C.c_int

@@ -81,6 +81,11 @@ __device__ __forceinline__ void fma4(vec4<T>& a, T s, vec4<T> b) {
 // add partial rows of longer segments (split on the host into pieces), so
 // no thread walks an unbounded run and the summation order is fixed.
 // VEC = 4: one thread per (segment, 4 channels), requires d % 4 == 0.
+// Rows are taken kSegBatch at a time: all their row indices are loaded,
+// then all their values, so a batch waits for memory twice however long it
+// is (the additions keep the order of the rows).
+constexpr int kSegBatch = 8;
+
 template <typename T, bool INDEXED, int VEC>
 __global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ seg_src,
                          const int32_t* __restrict__ seg_len, const int64_t* __restrict__ seg_dst,
@@ -93,23 +98,37 @@ __global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ se
     const int32_t c = (int32_t)(tid - s * dv) * VEC;
     const int64_t b = seg_src[s];
     const int32_t n = seg_len[s];
-    if (VEC == 4) {
-        vec4<T> acc = {0, 0, 0, 0};
-#pragma unroll 4
-        for (int32_t i = 0; i < n; ++i) {
-            const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
-            add4(acc, ld4(src + row * d + c));
+    vec4<T> acc = {0, 0, 0, 0};
+    for (int32_t i0 = 0; i0 < n; i0 += kSegBatch) {
+        int64_t rows[kSegBatch];
+#pragma unroll
+        for (int u = 0; u < kSegBatch; ++u) {
+            const int32_t i = min(i0 + u, n - 1);  // clamped: loads stay in the run
+            rows[u] = INDEXED ? (int64_t)idx[b + i] : b + i;
         }
-        st4(val + seg_dst[s] * d + c, acc);
-    } else {
-        T acc = 0;
-#pragma unroll 4
-        for (int32_t i = 0; i < n; ++i) {
-            const int64_t row = INDEXED ? (int64_t)idx[b + i] : b + i;
-            acc += src[row * d + c];
+        // value loads predicated on the run length (issued together, no
+        // load for rows past the end)
+        if (VEC == 4) {
+            vec4<T> v[kSegBatch];
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u)
+                v[u] = (i0 + u < n) ? ld4(src + rows[u] * d + c) : vec4<T>{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u)
+                if (i0 + u < n) add4(acc, v[u]);
+        } else {
+            T v[kSegBatch];
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u) v[u] = (i0 + u < n) ? src[rows[u] * d + c] : (T)0;
+#pragma unroll
+            for (int u = 0; u < kSegBatch; ++u)
+                if (i0 + u < n) acc.x += v[u];
         }
-        val[seg_dst[s] * d + c] = acc;
     }
+    if (VEC == 4)
+        st4(val + seg_dst[s] * d + c, acc);
+    else
+        val[seg_dst[s] * d + c] = acc.x;
 }
 
 // ------------------------------------------------------ direct tables ----
@@ -125,6 +144,39 @@ __global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ se
 // blk[4 b .. 4 b + 3] = (out_beg, out_end, src_beg, src_end) in the padded
 // cell list; qjb/qje give each cell quad's job range in the same list.
 constexpr int kDirOut = 256, kDirCh = 16, kDirThreads = 256;
+
+// Stage tn (1 <= tn <= kDirOut) source cells ts .. ts + tn of the padded
+// cell list into LDS: coordinates into sr/sx and value rows (channels
+// c0 .. c0 + nch, nch <= 16) into sv at row stride SV, zero beyond tn and
+// for padding cells. A workgroup of kDirThreads threads, 16 rows per
+// thread: all row indices are loaded first, then all values (addresses
+// clamped into range rather than branched around), so a tile waits for
+// memory twice.
+template <typename T, int SV>
+__device__ __forceinline__ void stage_cells(const int32_t* __restrict__ dl_r,
+                                            const int32_t* __restrict__ dl_x,
+                                            const int32_t* __restrict__ dl_row, int32_t ts,
+                                            int32_t tn, const T* __restrict__ val, int32_t d,
+                                            int32_t c0, int32_t nch, int32_t* sr, int32_t* sx,
+                                            T* sv) {
+    const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+    const int32_t ccs = min(cc, nch - 1);
+    int32_t rows[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) rows[i] = dl_row[ts + min(k0 + 16 * i, tn - 1)];
+    T v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = val[(int64_t)max(rows[i], 0) * d + c0 + ccs];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int32_t k = k0 + 16 * i;
+        sv[k * SV + cc] = (k < tn && rows[i] >= 0 && cc < nch) ? v[i] : (T)0;
+    }
+    if ((int32_t)threadIdx.x < tn) {
+        sr[threadIdx.x] = dl_r[ts + threadIdx.x];
+        sx[threadIdx.x] = dl_x[ts + threadIdx.x];
+    }
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kDirThreads)
@@ -151,32 +203,21 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
         const int32_t cq = threadIdx.x / nq, chq = threadIdx.x - cq * nq;
         const int32_t Q = (os >> 2) + cq;              // this thread's cell quad
         const bool act = cq < qpp && 4 * Q < oe;
+        const int32_t Qs = act ? Q : (os >> 2);        // clamped: loads stay in range
         int32_t ri[4], xi[4];
-        int32_t jb = 0, je = 0;
-        if (act) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                ri[c] = dl_r[4 * Q + c];
-                xi[c] = dl_x[4 * Q + c];
-            }
-            jb = qjb[Q];
-            je = qje[Q];
+        for (int c = 0; c < 4; ++c) {
+            ri[c] = dl_r[4 * Qs + c];
+            xi[c] = dl_x[4 * Qs + c];
         }
+        const int32_t jb = act ? qjb[Qs] : 0, je = act ? qje[Qs] : 0;
         vec4<T> acc[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[c] = {0, 0, 0, 0};
         for (int32_t ts = ss; ts < se; ts += kDirOut) {
             const int32_t tn = min(kDirOut, se - ts);
             __syncthreads();
-            for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
-                sr[k] = dl_r[ts + k];
-                sx[k] = dl_x[ts + k];
-            }
-            for (int32_t e = threadIdx.x; e < tn * kDirCh; e += blockDim.x) {
-                const int32_t k = e / kDirCh, cc = e - k * kDirCh;
-                const int32_t row = dl_row[ts + k];
-                sv[e] = (row >= 0 && cc < nch) ? val[(int64_t)row * d + c0 + cc] : (T)0;
-            }
+            stage_cells<T, kDirCh>(dl_r, dl_x, dl_row, ts, tn, val, d, c0, nch, sr, sx, sv);
             __syncthreads();
             if (act) {
                 const int32_t lo = max(jb, ts) - ts, hi = min(je, ts + tn) - ts;
@@ -215,20 +256,32 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
 // A[l%16][l/16] and B[l/16][l%16] and receives D[4(l/16)+r][l%16] in its
 // r-th result register). A wave owns 16-cell row tiles of the block's
 // output cells; for every k-step of 4 sources each lane forms its one
-// kernel entry (0 outside its row's job) and reuses it for all 16-channel
-// tiles, read from an LDS tile of kMfSrc source cells x up to kMfCh
-// channels. Blocks, padding and job ranges are those of k_direct.
+// kernel entry (0 outside its row's job) and uses it for the NCH 16-channel
+// chunks of a pass, whose values come from an LDS tile of source cells x
+// 16 NCH channels. Blocks, padding and job ranges are those of k_direct.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
-constexpr int kMfSrc = kDirOut;  // source cells per LDS tile
+constexpr int kMfSrc = kDirOut;  // source cells per LDS tile (one chunk)
 
+// LDS tile shape of a pass of NCH chunks: source rows, and a row stride
+// that is 16 or 48 modulo 64 so that the 64 lanes of a B read hit distinct
+// banks.
+template <int NCH>
+struct MfTile {
+    static constexpr int rows = NCH == 1 ? kMfSrc : kMfSrc / 2;
+    static constexpr int stride = NCH == 1 ? 16 : NCH <= 3 ? 48 : 80;
+};
+
+template <int NCH>
 __global__ void __launch_bounds__(kDirThreads)
 k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
               const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
               const int32_t* __restrict__ qjb, const int32_t* __restrict__ qje,
               const float* __restrict__ f, int32_t flds, const float* __restrict__ val,
               float* __restrict__ g) {
-    __shared__ float sv[kMfSrc * 17];
-    __shared__ int32_t sr[kMfSrc], sx[kMfSrc];
+    constexpr int ROWS = MfTile<NCH>::rows, SV = MfTile<NCH>::stride;
+    constexpr int PER = ROWS / 16;  // staged rows per thread
+    __shared__ __attribute__((aligned(16))) float sv[ROWS * SV];
+    __shared__ int32_t sr[ROWS], sx[ROWS];
     extern __shared__ unsigned char dyn_raw[];
     float* sf = reinterpret_cast<float*>(dyn_raw);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
@@ -248,33 +301,53 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
         const int32_t t = wave + 4 * q;
         const int32_t i = os + 16 * t + lr;
         const bool ok = t < ntiles && i < oe;
-        ri[q] = ok ? dl_r[i] : 0;
-        xi[q] = ok ? dl_x[i] : 0;
-        jb[q] = ok ? qjb[i >> 2] : 0;
-        je[q] = ok ? qje[i >> 2] : 0;
-        if (t < ntiles) {
-            tjb[q] = qjb[(os + 16 * t) >> 2];
-            tje[q] = qje[(min(oe, os + 16 * t + 16) - 1) >> 2];
-        } else {
-            tjb[q] = tje[q] = 0;
-        }
+        const int32_t is = ok ? i : os;  // clamped: loads stay in range
+        ri[q] = dl_r[is];
+        xi[q] = dl_x[is];
+        jb[q] = ok ? qjb[is >> 2] : 0;
+        je[q] = ok ? qje[is >> 2] : 0;
+        const bool tok = t < ntiles;
+        const int32_t tb = tok ? os + 16 * t : os;
+        const int32_t tjb_ = qjb[tb >> 2], tje_ = qje[(min(oe, tb + 16) - 1) >> 2];
+        tjb[q] = tok ? tjb_ : 0;
+        tje[q] = tok ? tje_ : 0;
     }
-    for (int32_t c0 = 0; c0 < d; c0 += 16) {
-        const int32_t nch = min(16, d - c0);
-        v4f_t acc[4];
+    for (int32_t c0 = 0; c0 < d; c0 += 16 * NCH) {
+        v4f_t acc[NCH][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = (v4f_t){0.f, 0.f, 0.f, 0.f};
-        for (int32_t ts = ss; ts < se; ts += kMfSrc) {
-            const int32_t tn = min(kMfSrc, se - ts);
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[ch][q] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+        for (int32_t ts = ss; ts < se; ts += ROWS) {
+            const int32_t tn = min(ROWS, se - ts);
             __syncthreads();
-            for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
-                sr[k] = dl_r[ts + k];
-                sx[k] = dl_x[ts + k];
-            }
-            for (int32_t e = threadIdx.x; e < tn * 16; e += blockDim.x) {
-                const int32_t k = e >> 4, cc = e & 15;
-                const int32_t row = dl_row[ts + k];
-                sv[k * 17 + cc] = (row >= 0 && cc < nch) ? val[(int64_t)row * d + c0 + cc] : 0.f;
+            {
+                // stage the tile: all row indices, then all values of the
+                // pass's channels (addresses clamped into range)
+                const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+                int32_t rows[PER];
+#pragma unroll
+                for (int i = 0; i < PER; ++i) rows[i] = dl_row[ts + min(k0 + 16 * i, tn - 1)];
+                float v[NCH][PER];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int32_t c = min(c0 + 16 * ch + cc, d - 1);
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) v[ch][i] = val[(int64_t)max(rows[i], 0) * d + c];
+                }
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const bool cok = c0 + 16 * ch + cc < d;
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        const int32_t k = k0 + 16 * i;
+                        sv[k * SV + 16 * ch + cc] = (k < tn && rows[i] >= 0 && cok) ? v[ch][i] : 0.f;
+                    }
+                }
+                if ((int32_t)threadIdx.x < tn) {
+                    sr[threadIdx.x] = dl_r[ts + threadIdx.x];
+                    sx[threadIdx.x] = dl_x[ts + threadIdx.x];
+                }
             }
             __syncthreads();
             int32_t kb[4], ke[4];
@@ -288,11 +361,14 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
                     hi = max(hi, ke[q]);
                 }
             }
-            // the four row tiles advance together: independent MFMA chains
+            // the four row tiles advance together: independent MFMA chains;
+            // one kernel entry per lane and row tile serves every chunk
             for (int32_t k4 = lo; k4 < hi; k4 += 4) {
                 const int32_t k = k4 + lk, kl = k - ts;
-                const float b = sv[kl * 17 + lr];
                 const int32_t rk = sr[kl], xk = sx[kl];
+                float b[NCH];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) b[ch] = sv[kl * SV + 16 * ch + lr];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (k4 < kb[q] || k4 >= ke[q]) continue;  // uniform per wave
@@ -301,21 +377,28 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
                         const int32_t dx = xi[q] - xk;
                         a = fp[ri[q] + rk + (dx < 0 ? -dx : dx)];
                     }
-                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[q], 0, 0, 0);
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch)
+                        acc[ch][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ch], acc[ch][q], 0, 0, 0);
                 }
             }
         }
-        // D[4 (l/16) + r][l % 16] of every row tile
+        // D[4 (l/16) + r][l % 16] of every row tile and chunk
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int32_t t = wave + 4 * q;
-            if (t >= ntiles || lr >= nch) continue;
+            if (t >= ntiles) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int32_t i = os + 16 * t + 4 * lk + r;
                 if (i >= oe) continue;
                 const int32_t row = dl_row[i];
-                if (row >= 0) g[(int64_t)row * d + c0 + lr] = acc[q][r];
+                if (row < 0) continue;
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int32_t c = c0 + 16 * ch + lr;
+                    if (c < d) g[(int64_t)row * d + c] = acc[ch][q][r];
+                }
             }
         }
     }
@@ -326,6 +409,8 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
 // vertex, the call's table value minus the component correction (row -1
 // when the vertex is on the call's backbone), on top of the leaf-tile value
 // already stored in out for vertices of leaf tiles. Writes every out row.
+constexpr int kGatherBatch = 4;
+
 template <typename T, int VEC>
 __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off,
                          const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
@@ -336,25 +421,52 @@ __global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off
     if (tid >= N * dv) return;
     const int64_t v = tid / dv;
     const int32_t c = (int32_t)(tid - v * dv) * VEC;
-    const int64_t k1 = v_off[v + 1];
+    const int64_t k0 = v_off[v], k1 = v_off[v + 1];
     const bool leaf = vleaf[v] != 0;  // out already holds the leaf tile value
-    if (VEC == 4) {
-        vec4<T> s = leaf ? ld4(out + v * d + c) : vec4<T>{0, 0, 0, 0};
-        for (int64_t k = v_off[v]; k < k1; ++k) {
-            const int32_t b = gb[k];
-            add4(s, ld4(g + (int64_t)ga[k] * d + c));
-            if (b >= 0) sub4(s, ld4(g + (int64_t)b * d + c));
-        }
-        st4(out + v * d + c, s);
-    } else {
-        T s = leaf ? out[v * d + c] : (T)0;
-        for (int64_t k = v_off[v]; k < k1; ++k) {
-            const int32_t b = gb[k];
-            s += g[(int64_t)ga[k] * d + c];
-            if (b >= 0) s -= g[(int64_t)b * d + c];
-        }
-        out[v * d + c] = s;
+    vec4<T> s = {0, 0, 0, 0};
+    if (leaf) {
+        if (VEC == 4) s = ld4(out + v * d + c);
+        else s.x = out[v * d + c];
     }
+    // calls taken kGatherBatch at a time: indices first, then table rows
+    for (int64_t kk = k0; kk < k1; kk += kGatherBatch) {
+        int32_t a[kGatherBatch], b[kGatherBatch];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) {
+            const int64_t k = min(kk + u, k1 - 1);
+            a[u] = ga[k];
+            b[u] = gb[k];
+        }
+        if (VEC == 4) {
+            vec4<T> ra[kGatherBatch], rb[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                ra[u] = ld4(g + (int64_t)a[u] * d + c);
+                rb[u] = ld4(g + (int64_t)(b[u] >= 0 ? b[u] : a[u]) * d + c);
+            }
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                if (kk + u >= k1) continue;
+                add4(s, ra[u]);
+                if (b[u] >= 0) sub4(s, rb[u]);
+            }
+        } else {
+            T ra[kGatherBatch], rb[kGatherBatch];
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                ra[u] = g[(int64_t)a[u] * d + c];
+                rb[u] = g[(int64_t)(b[u] >= 0 ? b[u] : a[u]) * d + c];
+            }
+#pragma unroll
+            for (int u = 0; u < kGatherBatch; ++u) {
+                if (kk + u >= k1) continue;
+                s.x += ra[u];
+                if (b[u] >= 0) s.x -= rb[u];
+            }
+        }
+    }
+    if (VEC == 4) st4(out + v * d + c, s);
+    else out[v * d + c] = s.x;
 }
 
 // ----------------------------------------------------------- leaf tiles --
@@ -386,16 +498,42 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
     // vertex slots are leaf_v positions [vb, vb + nv): the group's tiles
     const int32_t vb = lq[4 * q0 + 1];
     const int32_t nv = lq[4 * (q1 - 1) + 1] + lq[4 * (q1 - 1) + 2] - vb;
-    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) sk[k] = f[leaf_D[kb + k]];
+    {
+        // f(D) of the group: all distance loads first, then the table entries
+        constexpr int kPer = kLeafK / kLeafThreads;
+        int32_t di[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            di[i] = leaf_D[kb + min((int32_t)threadIdx.x + kLeafThreads * i, nk - 1)];
+        T fv[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) fv[i] = f[di[i]];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int32_t k = threadIdx.x + kLeafThreads * i;
+            if (k < nk) sk[k] = fv[i];
+        }
+    }
     for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
     for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         const int32_t nq = (nch + 3) >> 2;
         const int32_t qpp = kLeafThreads / nq;
         __syncthreads();
-        for (int32_t e = threadIdx.x; e < nv * kDirCh; e += blockDim.x) {
-            const int32_t i = e / kDirCh, cc = e - i * kDirCh;
-            sF[e] = (cc < nch) ? F[(int64_t)svtx[i] * d + c0 + cc] : (T)0;
+        {
+            // field rows of the group's vertices, all loads in flight at once
+            constexpr int kPer = kLeafSlots / (kLeafThreads / 16);
+            const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+            const int32_t ccs = min(cc, nch - 1);
+            T v[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i)
+                v[i] = F[(int64_t)svtx[min(k0 + 16 * i, nv - 1)] * d + c0 + ccs];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int32_t k = k0 + 16 * i;
+                if (k < nv) sF[k * kDirCh + cc] = (cc < nch) ? v[i] : (T)0;
+            }
         }
         __syncthreads();
         const int32_t cq0 = threadIdx.x / nq;
@@ -685,6 +823,12 @@ __global__ void k_zero(T* __restrict__ p, int64_t n) {
     if (tid < n) p[tid] = T{};
 }
 
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid < n) p[tid] = v;
+}
+
 }  // namespace tfi
 
 namespace tfi {
@@ -727,14 +871,16 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             const int32_t* __restrict__ dl_r, const int32_t* __restrict__ dl_x,
             const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
             const int32_t* __restrict__ qje, const T* __restrict__ val,
-            const T* __restrict__ valg, int32_t K, double* __restrict__ df) {
+            const T* __restrict__ valg, const int32_t* __restrict__ dbin,
+            double* __restrict__ df) {
     __shared__ T sG[kDfTile * (kDirCh + 1)], sV[kDfTile * (kDirCh + 1)];
     __shared__ int32_t sr[kDfTile], sx[kDfTile];
     __shared__ T lh[df_hist_bins<T>()];
-    const bool use_lds = K <= df_hist_bins<T>();
+    const int32_t Kb = dbin[blockIdx.x];  // bins this block can reach
+    const bool use_lds = Kb <= df_hist_bins<T>();
     T* lhp = use_lds ? lh : nullptr;
     if (use_lds)
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0;
+        for (int32_t k = threadIdx.x; k < Kb; k += blockDim.x) lh[k] = 0;
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int32_t ii = threadIdx.x & (kDfTile - 1), jj0 = threadIdx.x >> 6;
     for (int32_t oc = os; oc < oe; oc += kDfTile) {
@@ -754,12 +900,32 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
                 const int32_t nch = min(kDirCh, d - c0);
                 __syncthreads();
-                for (int32_t e = threadIdx.x; e < kDfTile * nch; e += blockDim.x) {
-                    const int32_t k = e / nch, cc = e - k * nch;
-                    const int32_t ro = (k < on) ? dl_row[oc + k] : -1;
-                    const int32_t rs = (k < tn) ? dl_row[ts + k] : -1;
-                    sG[k * (kDirCh + 1) + cc] = ro >= 0 ? valg[(int64_t)ro * d + c0 + cc] : (T)0;
-                    sV[k * (kDirCh + 1) + cc] = rs >= 0 ? val[(int64_t)rs * d + c0 + cc] : (T)0;
+                {
+                    // both tiles' rows: all row indices first, then all values
+                    constexpr int kPer = kDfTile / (kDfThreads / 16);
+                    const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+                    const int32_t ccs = min(cc, nch - 1);
+                    int32_t ro[kPer], rs[kPer];
+#pragma unroll
+                    for (int i = 0; i < kPer; ++i) {
+                        const int32_t k = k0 + 16 * i;
+                        ro[i] = dl_row[oc + min(k, on - 1)];
+                        rs[i] = dl_row[ts + min(k, tn - 1)];
+                    }
+                    T vg[kPer], vv[kPer];
+#pragma unroll
+                    for (int i = 0; i < kPer; ++i) {
+                        vg[i] = valg[(int64_t)max(ro[i], 0) * d + c0 + ccs];
+                        vv[i] = val[(int64_t)max(rs[i], 0) * d + c0 + ccs];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kPer; ++i) {
+                        const int32_t k = k0 + 16 * i;
+                        if (cc < nch) {
+                            sG[k * (kDirCh + 1) + cc] = (k < on && ro[i] >= 0) ? vg[i] : (T)0;
+                            sV[k * (kDirCh + 1) + cc] = (k < tn && rs[i] >= 0) ? vv[i] : (T)0;
+                        }
+                    }
                 }
                 if (c0 == 0)
                     for (int32_t k = threadIdx.x; k < tn; k += blockDim.x) {
@@ -784,7 +950,7 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             }
         }
     }
-    if (use_lds) hist_flush<T>(lh, df, K);
+    if (use_lds) hist_flush<T>(lh, df, Kb);
 }
 
 // Direct jobs on the matrix cores (FP32). The pair terms <gbar_i, val_j>
@@ -800,7 +966,10 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
 // block's output cells, keeps their gbar runs in registers, and streams
 // source tiles of 16 cells straight from memory (sources of a job are
 // consecutive value rows). Blocks, padding and job ranges are those of
-// k_direct.
+// k_direct. dbin[b] bounds the distance bins of block b's pairs (one past
+// the largest 2 r + x extent of its jobs): the LDS histogram is cleared and
+// flushed over that range only, and a block whose bins do not fit in LDS
+// adds straight to df.
 template <int CPL>
 __device__ __forceinline__ void load_run(const float* __restrict__ base, int32_t row, int32_t d,
                                          int32_t ch0, float (&v)[CPL]) {
@@ -831,12 +1000,14 @@ k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
                  const int32_t* __restrict__ dl_r, const int32_t* __restrict__ dl_x,
                  const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
                  const int32_t* __restrict__ qje, const float* __restrict__ val,
-                 const float* __restrict__ valg, int32_t K, double* __restrict__ df) {
+                 const float* __restrict__ valg, const int32_t* __restrict__ dbin,
+                 double* __restrict__ df) {
     __shared__ float lh[df_hist_bins<float>()];
-    const bool use_lds = K <= df_hist_bins<float>();
+    const int32_t Kb = dbin[blockIdx.x];  // bins this block can reach
+    const bool use_lds = Kb <= df_hist_bins<float>();
     float* lhp = use_lds ? lh : nullptr;
     if (use_lds)
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0.f;
+        for (int32_t k = threadIdx.x; k < Kb; k += blockDim.x) lh[k] = 0.f;
     __syncthreads();
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -909,12 +1080,14 @@ k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             }
         }
     }
-    if (use_lds) hist_flush<float>(lh, df, K);
+    if (use_lds) hist_flush<float>(lh, df, Kb);
 }
 
 // Leaf tiles: pairs inside each tile, distance from D. The group's gout
 // and F rows are staged in LDS kDirCh channels at a time; a thread owns up
-// to kDfLeafRows (quad, source j) rows = 4 pair dot products each.
+// to kDfLeafRows (quad, source j) rows = 4 pair dot products each. lbin[g]
+// is one past the largest distance inside group g's tiles: the LDS
+// histogram is cleared and flushed over that range only.
 constexpr int kDfLeafRows = 8;
 
 template <typename T>
@@ -922,10 +1095,12 @@ __global__ void __launch_bounds__(kLeafThreads)
 k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ gk,
           const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
           const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
-          const T* __restrict__ gout, int32_t K, double* __restrict__ df) {
+          const T* __restrict__ gout, const int32_t* __restrict__ lbin,
+          double* __restrict__ df) {
     __shared__ T sG[kLeafSlots * (kDirCh + 1)], sF[kLeafSlots * (kDirCh + 1)];
     __shared__ int32_t svtx[kLeafSlots], srow0[kLeafQuads + 1];
     __shared__ T lh[df_hist_bins<T>()];
+    const int32_t K = lbin[blockIdx.x];  // bins this group's pairs can reach
     const bool use_lds = K <= df_hist_bins<T>();
     T* lhp = use_lds ? lh : nullptr;
     if (use_lds)
@@ -966,10 +1141,26 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
     for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         __syncthreads();
-        for (int32_t e = threadIdx.x; e < nv * nch; e += blockDim.x) {
-            const int32_t i = e / nch, cc = e - i * nch;
-            sG[i * (kDirCh + 1) + cc] = gout[(int64_t)svtx[i] * d + c0 + cc];
-            sF[i * (kDirCh + 1) + cc] = F[(int64_t)svtx[i] * d + c0 + cc];
+        {
+            // gout and field rows of the group's vertices, all loads at once
+            constexpr int kPer = kLeafSlots / (kLeafThreads / 16);
+            const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+            const int32_t ccs = min(cc, nch - 1);
+            T vg[kPer], vf[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int64_t o = (int64_t)svtx[min(k0 + 16 * i, nv - 1)] * d + c0 + ccs;
+                vg[i] = gout[o];
+                vf[i] = F[o];
+            }
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int32_t k = k0 + 16 * i;
+                if (k < nv && cc < nch) {
+                    sG[k * (kDirCh + 1) + cc] = vg[i];
+                    sF[k * (kDirCh + 1) + cc] = vf[i];
+                }
+            }
         }
         __syncthreads();
 #pragma unroll

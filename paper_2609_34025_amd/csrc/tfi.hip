@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -113,6 +114,8 @@ struct tfi_plan {
     // blocks of output cells
     int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
     int32_t *d_qjb = nullptr, *d_qje = nullptr, *d_dblk = nullptr;
+    int32_t* d_dbin = nullptr;  // per direct block: bound of its pair distances
+    int32_t dbin_max = 0;
     int64_t ndirect = 0, ndblk = 0;
     double direct_pairs = 0;  // sum over direct jobs of cells^2 (unpadded)
     // scatter: levels of bounded segment sums
@@ -130,6 +133,7 @@ struct tfi_plan {
     int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr, *d_lq = nullptr;
     int8_t* d_vleaf = nullptr;
     int64_t* d_lgk = nullptr;
+    int32_t* d_lbin = nullptr;  // per leaf group: bound of its distances
     int64_t nlgrp = 0;
     int64_t gather_reads = 0;  // table values read by the gather
     int32_t *d_leaf_v = nullptr, *d_leaf_D = nullptr;
@@ -284,6 +288,7 @@ struct tfi_plan {
         }
         ndirect = ndblk = 0;
         direct_pairs = 0;
+        dbin_max = 0;
         spec_elems = 0;
         return TFI_OK;
     }
@@ -423,6 +428,7 @@ int upload_static(tfi_plan* h) {
     {
         std::vector<int32_t> lq, grp{0};
         std::vector<int64_t> gk;
+        std::vector<int32_t> lbin;  // per group: 1 + largest distance in its tiles
         const int64_t nt = (int64_t)p.leaf_off.size() - 1;
         int64_t t = 0;
         while (t < nt) {
@@ -450,12 +456,16 @@ int upload_static(tfi_plan* h) {
             grp.push_back((int32_t)(lq.size() / 4));
             gk.push_back(dbase);
             gk.push_back(kk);
+            int32_t dmax = 0;
+            for (int64_t u = dbase; u < dbase + kk; ++u) dmax = std::max(dmax, p.leaf_D[u]);
+            lbin.push_back((int32_t)std::min<int64_t>((int64_t)dmax + 1, p.kernel_len));
             t = e;
         }
         h->nlgrp = (int64_t)grp.size() - 1;
         if ((rc = h->upload(&h->d_lgrp, grp))) return rc;
         if ((rc = h->upload(&h->d_lq, lq))) return rc;
         if ((rc = h->upload(&h->d_lgk, gk))) return rc;
+        if ((rc = h->upload(&h->d_lbin, lbin))) return rc;
     }
     // LDS beyond 64 KiB needs an opt-in per kernel
     if (h->lds_max > 65536) {
@@ -546,13 +556,24 @@ int upload_methods(tfi_plan* h) {
             return p.job_cell_off[a + 1] - p.job_cell_off[a] >
                    p.job_cell_off[b + 1] - p.job_cell_off[b];
         });
-        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk;
+        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk, dbin;
         std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
+        std::vector<int32_t> jbin;                    // per job: 1 + largest pair distance
         for (int64_t j : djobs) {
             const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
             const int32_t jb = (int32_t)dl_r.size();
             const int32_t n = ce - cb, np = (n + 3) & ~3;
             h->direct_pairs += (double)n * n;
+            {
+                int32_t rmax = 0, xmin = INT32_MAX, xmax = INT32_MIN;
+                for (int32_t i = cb; i < ce; ++i) {
+                    rmax = std::max(rmax, p.jc_r[i]);
+                    xmin = std::min(xmin, p.jc_x[i]);
+                    xmax = std::max(xmax, p.jc_x[i]);
+                }
+                const int64_t b = n > 0 ? 2 * (int64_t)rmax + (xmax - xmin) + 1 : 1;
+                jbin.push_back((int32_t)std::min<int64_t>(b, p.kernel_len));
+            }
             for (int32_t i = 0; i < np; ++i) {
                 const bool real = i < n;
                 dl_r.push_back(real ? p.jc_r[cb + i] : 0);
@@ -570,8 +591,10 @@ int upload_methods(tfi_plan* h) {
         while (k < jr.size()) {
             const int32_t jb = jr[k].first, je = jr[k].second;
             if (je - jb > tfi::kDirOut) {
-                for (int32_t o = jb; o < je; o += tfi::kDirOut)
+                for (int32_t o = jb; o < je; o += tfi::kDirOut) {
                     dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
+                    dbin.push_back(jbin[k]);
+                }
                 ++k;
                 continue;
             }
@@ -579,6 +602,9 @@ int upload_methods(tfi_plan* h) {
             while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
             const int32_t end = jr[e - 1].second;
             dblk.insert(dblk.end(), {jb, end, jb, end});
+            int32_t bmax = 1;
+            for (size_t u = k; u < e; ++u) bmax = std::max(bmax, jbin[u]);
+            dbin.push_back(bmax);
             k = e;
         }
         h->ndirect = (int64_t)dl_r.size();
@@ -589,6 +615,8 @@ int upload_methods(tfi_plan* h) {
         if ((rc = h->upload_m(&h->d_qjb, qjb))) return rc;
         if ((rc = h->upload_m(&h->d_qje, qje))) return rc;
         if ((rc = h->upload_m(&h->d_dblk, dblk))) return rc;
+        if ((rc = h->upload_m(&h->d_dbin, dbin))) return rc;
+        h->dbin_max = dbin.empty() ? 0 : *std::max_element(dbin.begin(), dbin.end());
     }
 
     h->spec_elems = 0;
@@ -855,11 +883,22 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
     hipEvent_t ev = h->begin(st);
     const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
     const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
-    if (mfma)
-        hipLaunchKernelGGL(tfi::k_direct_mfma, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
-                           (unsigned)(flds * sizeof(float)), st, d, h->d_dblk, h->d_dl_r,
-                           h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, (const float*)f, flds,
-                           (const float*)val, (float*)g);
+    if (mfma) {
+        // 16-channel chunks per pass: one kernel entry serves all of them
+        const int nch = d > 48 ? 4 : d > 32 ? 3 : d > 16 ? 2 : 1;
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+                               (unsigned)(flds * sizeof(float)), st, d, h->d_dblk, h->d_dl_r,
+                               h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, (const float*)f, flds,
+                               (const float*)val, (float*)g);
+        };
+        switch (nch) {
+            case 4: launch(tfi::k_direct_mfma<4>); break;
+            case 3: launch(tfi::k_direct_mfma<3>); break;
+            case 2: launch(tfi::k_direct_mfma<2>); break;
+            default: launch(tfi::k_direct_mfma<1>); break;
+        }
+    }
     else
         hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
                            (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
@@ -960,11 +999,12 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
     if (mfma) {
         // channels per lane per chunk: the smallest run that covers d (up to 16)
         const int cpl = d > 32 ? 16 : d > 16 ? 8 : d > 8 ? 4 : d > 4 ? 2 : 1;
+        // histogram copies: as many as fit (up to 16) in 80 KiB of LDS, so
+        // that two blocks share a CU; none when one copy does not fit
         auto launch = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads), 0, st, d,
                                p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                               h->d_qje, (const float*)val, (const float*)valg,
-                               (int32_t)p.kernel_len, df);
+                               h->d_qje, (const float*)val, (const float*)valg, h->d_dbin, df);
         };
         switch (cpl) {
             case 16: launch(tfi::k_df_direct_mfma<16>); break;
@@ -976,7 +1016,7 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
     } else {
         hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
                            st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                           h->d_qje, val, valg, (int32_t)p.kernel_len, df);
+                           h->d_qje, val, valg, h->d_dbin, df);
     }
     h->end(st, ev, mfma ? "df_direct_mfma" : "df_direct",
            2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
@@ -990,7 +1030,7 @@ void enq_df_leaf(tfi_plan* h, int32_t d, const T* F, const T* gout, double* df, 
     hipEvent_t ev = h->begin(st);
     hipLaunchKernelGGL(tfi::k_df_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st,
                        d, h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, F, gout,
-                       (int32_t)p.kernel_len, df);
+                       h->d_lbin, df);
     const double nv = (double)p.leaf_v.size();
     h->end(st, ev, "df_leaf", 2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size(),
            2.0 * d * (double)p.leaf_pairs);
@@ -1187,26 +1227,46 @@ int reassign_methods(tfi_plan* h, double cost) {
     return upload_methods(h);
 }
 
+// Average time of `reps` passes (after two untimed ones) on fields of ones:
+// forward integrations, or forward + adjoint (dF and df) when with_bwd.
 template <typename T>
-int time_forward(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, float* ms) {
+int time_pass(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, bool with_bwd,
+              float* ms) {
     const int64_t n = h->plan.N * (int64_t)d;
-    void* F = nullptr;
-    void* out = nullptr;
-    int rc = h->dalloc(&F, (size_t)n * sizeof(T));
-    if (rc) return rc;
-    rc = h->dalloc(&out, (size_t)n * sizeof(T));
+    const size_t fb = (size_t)n * sizeof(T), hb = (size_t)h->plan.kernel_len * sizeof(double);
+    void* buf[4] = {nullptr, nullptr, nullptr, nullptr};  // F, gout, out/dF, df
+    const size_t sz[4] = {fb, fb, fb, hb};
+    int rc = TFI_OK;
+    for (int i = 0; i < 4 && !rc; ++i)
+        if (i < 2 || i == 2 || with_bwd) rc = h->dalloc(&buf[i], sz[i]);
+    auto release = [&]() {
+        for (int i = 0; i < 4; ++i)
+            if (buf[i]) {
+                (void)hipFree(buf[i]);
+                h->dev_bytes -= sz[i];
+            }
+    };
     if (rc) {
-        (void)hipFree(F);
-        h->dev_bytes -= (size_t)n * sizeof(T);
+        release();
         return rc;
     }
-    hipLaunchKernelGGL(tfi::k_zero<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, (T*)F, n);
+    hipLaunchKernelGGL(tfi::k_fill<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, (T*)buf[0], n,
+                       (T)1);
+    hipLaunchKernelGGL(tfi::k_fill<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, (T*)buf[1], n,
+                       (T)1);
+    auto pass = [&]() {
+        int r = run_forward<T>(h, f, (const T*)buf[0], d, (T*)buf[2], st);
+        if (!r && with_bwd)
+            r = run_backward<T>(h, f, (const T*)buf[0], (const T*)buf[1], d, (T*)buf[2],
+                                (double*)buf[3], st);
+        return r;
+    };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    for (int i = 0; i < 2 && !rc; ++i) rc = run_forward<T>(h, f, (const T*)F, d, (T*)out, st);
+    for (int i = 0; i < 2 && !rc; ++i) rc = pass();
     (void)hipEventRecord(e0, st);
-    for (int i = 0; i < reps && !rc; ++i) rc = run_forward<T>(h, f, (const T*)F, d, (T*)out, st);
+    for (int i = 0; i < reps && !rc; ++i) rc = pass();
     (void)hipEventRecord(e1, st);
     if (!rc && hipEventSynchronize(e1) == hipSuccess) {
         (void)hipEventElapsedTime(ms, e0, e1);
@@ -1216,9 +1276,7 @@ int time_forward(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, f
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->drop_graphs();  // they captured the temporary buffers
-    (void)hipFree(F);
-    (void)hipFree(out);
-    h->dev_bytes -= 2 * (size_t)n * sizeof(T);
+    release();
     return rc;
 }
 
@@ -1392,8 +1450,8 @@ int tfi_set_fft_cost(tfi_handle h, float cost) {
     return reassign_methods(h, cost);
 }
 
-int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, float* best_cost,
-                 void* stream) {
+int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int with_backward,
+                 float* best_cost, void* stream) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
@@ -1404,14 +1462,15 @@ int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, float*
     if (h->popt.table_method != 0)
         return fail(TFI_ERR_STATE, "tfi_autotune: table method is forced for this handle");
     hipStream_t st = (hipStream_t)stream;
-    const float cands[] = {0.25f, 1.0f, 4.0f, 16.0f, 64.0f};
+    const float cands[] = {0.25f, 1.0f, 2.0f, 4.0f, 8.0f, 16.0f, 32.0f, 64.0f};
     float best = (float)h->popt.fft_cost, best_ms = 1e30f;
     for (float c : cands) {
         if ((rc = reassign_methods(h, c))) return rc;
         float ms = 1e30f;
-        rc = dtype == TFI_F32
-                 ? time_forward<float>(h, (const float*)f, (int32_t)d, st, 5, &ms)
-                 : time_forward<double>(h, (const double*)f, (int32_t)d, st, 5, &ms);
+        rc = dtype == TFI_F32 ? time_pass<float>(h, (const float*)f, (int32_t)d, st, 5,
+                                                 with_backward != 0, &ms)
+                              : time_pass<double>(h, (const double*)f, (int32_t)d, st, 5,
+                                                  with_backward != 0, &ms);
         if (rc) return rc;
         if (ms < best_ms) {
             best_ms = ms;

@@ -73,14 +73,16 @@ class TreeIntegrator:
             _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, nbytes))
         return arr
 
-    def autotune(self, f, d, cache=None):
+    def autotune(self, f, d, cache=None, backward=False):
         """Choose the per-table method rule (direct sums vs FFT) by timing
-        forward passes of ``d`` channels in ``f``'s dtype; the fastest
+        passes of ``d`` channels in ``f``'s dtype: forward integrations, or
+        forward + adjoint (dF and df) with ``backward=True``; the fastest
         setting stays in effect. ``cache``: optional JSON file of tuned
-        values keyed by (plan fingerprint, d, dtype), read before and
+        values keyed by (plan fingerprint, d, dtype, pass), read before and
         updated after tuning. Returns the chosen cost constant."""
         self._check(f)
-        key = f"{self.stats()['fingerprint']}:{int(d)}:{str(f.dtype)}"
+        key = (f"{self.stats()['fingerprint']}:{int(d)}:{str(f.dtype)}:"
+               f"{'fwdbwd' if backward else 'fwd'}")
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as fp:
@@ -91,7 +93,8 @@ class TreeIntegrator:
             return float(table[key])
         best = C.c_float()
         _lib.check(lib.tfi_autotune(self._h, f.data_ptr(), int(d), _DTYPES[f.dtype],
-                                    C.byref(best), self._stream(self.device)))
+                                    1 if backward else 0, C.byref(best),
+                                    self._stream(self.device)))
         if cache:
             table[key] = best.value
             tmp = f"{cache}.{os.getpid()}.tmp"

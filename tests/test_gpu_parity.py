@@ -143,7 +143,7 @@ def test_channel_counts_and_vector_field(kernel):
     rng = np.random.default_rng(15)
     p, _ = S.random_recursive(700, rng)
     w = S.uniform_weights(p, 1, 6, rng)
-    for d in (1, 2, 3, 16, 33, 64, 100):
+    for d in (1, 2, 3, 16, 20, 33, 48, 64, 65, 100):
         F = rng.standard_normal((len(p), d))
         for method in ("auto", "direct"):
             check(p, w, lambda K: np.exp(-0.05 * np.arange(K)), F, torch.float32,
@@ -267,6 +267,9 @@ def test_graph_replays_match_eager():
         del junk
 
 
+CANDIDATES = (0.25, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0)
+
+
 def test_autotune_keeps_results_and_kernel_length(tmp_path):
     rng = np.random.default_rng(23)
     W = S.workload("grid512", trees=16, d=8)
@@ -277,7 +280,7 @@ def test_autotune_keeps_results_and_kernel_length(tmp_path):
     f = torch.tensor(ftab, dtype=torch.float32, device=DEV)
     cache = str(tmp_path / "tune.json")
     c = t.autotune(f, F.shape[1], cache=cache)
-    assert c in (0.25, 1.0, 4.0, 16.0, 64.0)
+    assert c in CANDIDATES
     assert t.kernel_length == K and t.stats()["fft_cost"] == pytest.approx(c)
     rows = rng.choice(len(p), 256, replace=False)
     y = t.integrate(f, torch.tensor(F, device=DEV)).cpu().numpy()
@@ -290,3 +293,14 @@ def test_autotune_keeps_results_and_kernel_length(tmp_path):
         t2.set_fft_cost(cost)
         y2 = t2.integrate(f, torch.tensor(F, device=DEV)).cpu().numpy()
         assert relerr(y2[rows], ref) <= 1e-4
+    # tuning on forward + adjoint passes keeps the adjoint exact as well
+    t3 = TreeIntegrator(p, w, device=0)
+    c3 = t3.autotune(f, F.shape[1], cache=cache, backward=True)
+    assert c3 in CANDIDATES and t3.kernel_length == K
+    G = rng.standard_normal(F.shape)
+    dF, df = t3.backward(f, torch.tensor(F, device=DEV),
+                         torch.tensor(G, dtype=torch.float32, device=DEV))
+    ref_dF = oracle.integrate(p, w, ftab, G, rows=rows)
+    assert relerr(dF.cpu().numpy()[rows], ref_dF) <= 1e-4
+    ref_df = oracle.pair_hist(p, w, G, F.astype(np.float64), K)
+    assert relerr(df.cpu().numpy(), ref_df) <= 1e-4
