@@ -156,6 +156,41 @@ int tfi_backward(tfi_handle h, const void *f, const void *F,
                  double *df, void *stream);
 
 /*
+ * Kernels given as sums of exponentials (appendix "Specialized Kernels",
+ * lemma "stad-specialized-cross" and algorithm "CrossSubRoutineExp"):
+ *   f(k) = sum_{l < nterm} c[l] * lambda[l]^k,   lambda[l] > 0,
+ * on the integer lattice distances of the tree. Every table job is
+ * evaluated by two backbone sweeps per term, in time linear in its cells,
+ * instead of direct sums or FFT; the leaf tiles use f tabulated on the
+ * device. Results equal tfi_integrate with that f table (up to rounding).
+ *   nterm   1 <= nterm <= TFI_EXPSUM_MAX_TERMS
+ *   c       device dtype[nterm]
+ *   lambda  device dtype[nterm], every entry > 0
+ *   F, d, out, stream as in tfi_integrate.
+ * Errors as tfi_integrate.
+ */
+#define TFI_EXPSUM_MAX_TERMS 16
+int tfi_integrate_expsum(tfi_handle h, int32_t nterm, const void *c,
+                         const void *lambda, const void *F, int64_t d,
+                         tfi_dtype dtype, void *out, void *stream);
+
+/*
+ * Adjoint of tfi_integrate_expsum for L = sum(gout * out):
+ *   dF  = K gout, device dtype[N x d], may be NULL;
+ *   s0[l] = sum_{v, w} lambda[l]^dist(v,w) <gout[v, :], F[w, :]>,
+ *   s1[l] = sum_{v, w} dist(v,w) lambda[l]^dist(v,w) <gout[v, :], F[w, :]>,
+ *   device double[nterm] each (overwritten), both NULL or both given.
+ * Then dL/dc[l] = s0[l] and dL/dlambda[l] = c[l] * s1[l] / lambda[l]; with
+ * lambda = exp(-b), dL/db[l] = -c[l] * s1[l]. s0/s1 accumulate with FP64
+ * atomics (reproducible to rounding, not bitwise).
+ * Errors as tfi_integrate.
+ */
+int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void *c,
+                        const void *lambda, const void *F, const void *gout,
+                        int64_t d, tfi_dtype dtype, void *dF, double *s0,
+                        double *s1, void *stream);
+
+/*
  * Plan statistics as a JSON object written to the host buffer json[cap]
  * (NUL-terminated, truncated to fit). Returns the full length needed
  * (excluding the NUL), or a negative status.

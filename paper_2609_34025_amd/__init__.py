@@ -4,13 +4,14 @@
 the adaptive backbone/centroid decomposition with FFT or direct interaction
 tables in HIP kernels for gfx950 (libtfi.so, C ABI in include/tfi.h).
 
-Submodules: ``integrator`` (TreeIntegrator, TreeIntegrate, expsum_table),
+Submodules: ``integrator`` (TreeIntegrator, TreeIntegrate, ExpSumIntegrate,
+expsum_table), ``sinkhorn``,
 ``synth`` (seeded synthetic inputs), ``build`` (compiles libtfi.so).
 Names are imported lazily so that ``synth`` works without torch or the
 built library.
 """
 
-__all__ = ["TreeIntegrator", "TreeIntegrate", "expsum_table"]
+__all__ = ["TreeIntegrator", "TreeIntegrate", "ExpSumIntegrate", "expsum_table"]
 
 
 def __getattr__(name):

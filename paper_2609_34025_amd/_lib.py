@@ -43,7 +43,7 @@ _lib = None
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
             "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
-            "tfi_last_error"]
+            "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum"]
 
 
 def load():
@@ -80,6 +80,11 @@ def load():
     lib.tfi_autotune.restype = C.c_int
     lib.tfi_set_fft_cost.argtypes = [vp, C.c_float]
     lib.tfi_set_fft_cost.restype = C.c_int
+    lib.tfi_integrate_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, i64, C.c_int, vp, vp]
+    lib.tfi_integrate_expsum.restype = C.c_int
+    lib.tfi_backward_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp,
+                                        vp]
+    lib.tfi_backward_expsum.restype = C.c_int
     lib.tfi_last_error.argtypes = []
     lib.tfi_last_error.restype = C.c_char_p
     _lib = lib

@@ -27,6 +27,7 @@
 
 #include "../../include/tfi.h"
 #include "kernels.hpp"
+#include "kernels_expsum.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -84,12 +85,12 @@ struct DeviceBuf {
 };
 
 struct GraphKey {
-    int kind = 0, dtype = 0;
+    int kind = 0, dtype = 0, n = 0;
     int64_t d = 0;
-    const void* p[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const void* p[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     bool operator==(const GraphKey& o) const {
-        if (kind != o.kind || dtype != o.dtype || d != o.d) return false;
-        for (int i = 0; i < 5; ++i)
+        if (kind != o.kind || dtype != o.dtype || n != o.n || d != o.d) return false;
+        for (int i = 0; i < 8; ++i)
             if (p[i] != o.p[i]) return false;
         return true;
     }
@@ -147,6 +148,14 @@ struct tfi_plan {
 
     // per-dtype scratch (grow-only)
     DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2];
+    // exponential sums: per-term power table and f table, sweep scratch,
+    // leaf pair histogram (FP64)
+    DeviceBuf expw[2], exps[2], hleaf;
+    // table jobs for the sweep evaluator: ids sorted by size, cell offsets,
+    // first scratch position (-1: one backbone position), signs
+    int32_t *d_ej1 = nullptr, *d_ejm = nullptr, *d_jsign = nullptr;
+    int64_t *d_joff = nullptr, *d_jpos = nullptr;
+    int64_t nej1 = 0, nejm = 0, npos_multi = 0;
 
     // streams, fork/join events, graph cache
     hipStream_t s1 = nullptr, s2 = nullptr, cs0 = nullptr;
@@ -228,8 +237,10 @@ struct tfi_plan {
         for (void* p : allocs) (void)hipFree(p);
         for (void* p : mallocs) (void)hipFree(p);
         for (int t = 0; t < 2; ++t)
-            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t]})
+            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t],
+                                 &expw[t], &exps[t]})
                 if (b->p) (void)hipFree(b->p);
+        if (hleaf.p) (void)hipFree(hleaf.p);
         (void)hipSetDevice(prev);
     }
 
@@ -486,6 +497,44 @@ int upload_static(tfi_plan* h) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
+    // sweep evaluator job lists (exponential-sum kernels)
+    {
+        const int64_t J = (int64_t)p.job_H.size();
+        std::vector<int32_t> ej1, ejm;  // one backbone position / several
+        std::vector<int64_t> jpos(J, -1);
+        int64_t npos = 0;
+        for (int64_t j = 0; j < J; ++j) {
+            const int64_t cb = p.job_cell_off[j], ce = p.job_cell_off[j + 1];
+            if (ce <= cb) continue;
+            int64_t np = 1;
+            for (int64_t i = cb + 1; i < ce; ++i) {
+                if (p.jc_x[i] < p.jc_x[i - 1])
+                    return fail(TFI_ERR_STATE, "internal: job cells not sorted by position");
+                np += p.jc_x[i] != p.jc_x[i - 1];
+            }
+            if (np > 1) {
+                jpos[j] = npos;
+                npos += np;
+                ejm.push_back((int32_t)j);
+            } else {
+                ej1.push_back((int32_t)j);
+            }
+        }
+        auto by_size = [&](int32_t a, int32_t b) {
+            return p.job_cell_off[a + 1] - p.job_cell_off[a] >
+                   p.job_cell_off[b + 1] - p.job_cell_off[b];
+        };
+        std::stable_sort(ej1.begin(), ej1.end(), by_size);
+        std::stable_sort(ejm.begin(), ejm.end(), by_size);
+        h->nej1 = (int64_t)ej1.size();
+        h->nejm = (int64_t)ejm.size();
+        h->npos_multi = npos;
+        if ((rc = h->upload(&h->d_ej1, ej1))) return rc;
+        if ((rc = h->upload(&h->d_ejm, ejm))) return rc;
+        if ((rc = h->upload(&h->d_joff, p.job_cell_off))) return rc;
+        if ((rc = h->upload(&h->d_jpos, jpos))) return rc;
+        if ((rc = h->upload(&h->d_jsign, p.job_sign))) return rc;
     }
     // twiddles exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), from long double
     h->lgtw = maxlg;
@@ -1219,6 +1268,183 @@ int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, 
 }
 
 
+// ---- kernels given as sums of exponentials: sweep evaluator -------------
+
+// Lanes per table job: the smallest power of two >= d, at most 64.
+inline int32_t exp_group(int32_t d) {
+    int32_t gs = 1;
+    while (gs < d && gs < 64) gs <<= 1;
+    return gs;
+}
+
+template <typename T>
+int prepare_expsum(tfi_plan* h, int32_t nterm, int32_t d, bool bwd, bool grad) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    int rc;
+    const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    if ((rc = h->ensure(h->val[ti], rowbytes))) return rc;
+    if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
+        return rc;
+    if ((rc = h->ensure(h->expw[ti], (size_t)(nterm + 1) * p.kernel_len * sizeof(T)))) return rc;
+    const size_t nq = grad ? 5 : 2;
+    if (h->npos_multi > 0 &&
+        (rc = h->ensure(h->exps[ti], (size_t)h->npos_multi * nq * nterm * d * sizeof(T))))
+        return rc;
+    if (bwd && (rc = h->ensure(h->valg[ti], rowbytes))) return rc;
+    if (grad && (rc = h->ensure(h->hleaf, (size_t)p.kernel_len * sizeof(double)))) return rc;
+    return TFI_OK;
+}
+
+// Power table lam_l^k and f table for the leaf tiles.
+template <typename T>
+void enq_expsum_prep(tfi_plan* h, int32_t nterm, const T* c, const T* lam, hipStream_t st) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const int64_t K = h->plan.kernel_len;
+    T* pw = (T*)h->expw[ti].p;
+    hipEvent_t ev = h->begin(st);
+    hipLaunchKernelGGL(tfi::k_expsum_prep<T>, dim3(blocks_for(K)), dim3(kThreads), 0, st, nterm, c,
+                       lam, (int32_t)K, pw, pw + (size_t)nterm * K);
+    h->end(st, ev, "expsum_prep", sizeof(T) * (double)(nterm + 1) * K);
+}
+
+template <typename T, bool GRAD, bool MULTI>
+void launch_expsum_jobs(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
+                        const T* valg, T* g, double* m0, double* m1, hipStream_t st) {
+    const int64_t nj = MULTI ? h->nejm : h->nej1;
+    if (nj == 0) return;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const int32_t gs = exp_group(d), gpb = tfi::kExpThreads / gs;
+    const unsigned blocks = (unsigned)((nj + gpb - 1) / gpb);
+    const T* pw = (const T*)h->expw[ti].p;
+    T* scr = (T*)h->exps[ti].p;
+    auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(tfi::kExpThreads), 0, st, nterm, d, gs,
+                           (int32_t)nj, MULTI ? h->d_ejm : h->d_ej1, h->d_joff, h->d_jpos,
+                           h->d_jsign, h->d_jc_r, h->d_jc_x, h->d_jc_val, c, pw,
+                           (int32_t)h->plan.kernel_len, val, valg, g, scr, m0, m1);
+    };
+    if (nterm <= 1) launch(tfi::k_expsum_jobs<T, 1, GRAD, MULTI>);
+    else if (nterm <= 2) launch(tfi::k_expsum_jobs<T, 2, GRAD, MULTI>);
+    else if (nterm <= 4) launch(tfi::k_expsum_jobs<T, 4, GRAD, MULTI>);
+    else if (nterm <= 8) launch(tfi::k_expsum_jobs<T, 8, GRAD, MULTI>);
+    else launch(tfi::k_expsum_jobs<T, 16, GRAD, MULTI>);
+}
+
+template <typename T, bool GRAD>
+void enq_expsum_jobs(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
+                     const T* valg, T* g, double* m0, double* m1, hipStream_t st) {
+    if (h->nej1 + h->nejm == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    launch_expsum_jobs<T, GRAD, false>(h, nterm, c, d, val, valg, g, m0, m1, st);
+    launch_expsum_jobs<T, GRAD, true>(h, nterm, c, d, val, valg, g, m0, m1, st);
+    const double cells = (double)p.jc_r.size();
+    h->end(st, ev, GRAD ? "expsum_grad" : "expsum",
+           2.0 * sizeof(T) * d * cells + 12.0 * cells, (GRAD ? 10.0 : 4.0) * nterm * d * cells);
+}
+
+// out = f(D) F for f(k) = sum_l c_l lam_l^k.
+template <typename T>
+void enqueue_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
+                            int32_t d, T* out, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    T* val = (T*)h->val[ti].p;
+    T* g = (T*)h->g[ti].p;
+    const T* ftab = (const T*)h->expw[ti].p + (size_t)nterm * h->plan.kernel_len;
+    enq_expsum_prep<T>(h, nterm, c, lam, s0);
+    fork3(h, s0, s1, s2);
+    enq_leaf<T>(h, ftab, F, d, out, s2);  // side2: leaf rows into out
+    (void)hipEventRecord(h->ev_c, s2);
+    (void)hipEventRecord(h->ev_b, s1);
+    launch_scatter<T>(h, F, val, d, s0);  // main: cell sums, sweeps
+    enq_expsum_jobs<T, false>(h, nterm, c, d, val, nullptr, g, nullptr, nullptr, s0);
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    enq_gather<T>(h, d, g, out, s0);
+}
+
+// dF = f(D) gout (when dF != null) and the moments m0/m1 (when non-null).
+template <typename T>
+void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
+                             const T* gout, int32_t d, T* dF, double* m0, double* m1,
+                             hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    const tfi::Plan& p = h->plan;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    T* val = (T*)h->val[ti].p;
+    T* valg = (T*)h->valg[ti].p;
+    T* g = (T*)h->g[ti].p;
+    const T* pw = (const T*)h->expw[ti].p;
+    const T* ftab = pw + (size_t)nterm * p.kernel_len;
+    double* hl = (double*)h->hleaf.p;
+    const bool grad = m0 != nullptr;
+    enq_expsum_prep<T>(h, nterm, c, lam, s0);
+    if (grad) {
+        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(1), dim3(kThreads), 0, s0, m0, (int64_t)nterm);
+        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(1), dim3(kThreads), 0, s0, m1, (int64_t)nterm);
+        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
+                           s0, hl, (int64_t)p.kernel_len);
+    }
+    fork3(h, s0, s1, s2);
+    if (dF) enq_leaf<T>(h, ftab, gout, d, dF, s2);
+    if (grad) {
+        enq_df_leaf<T>(h, d, F, gout, hl, s2);  // leaf pair histogram
+        hipLaunchKernelGGL(tfi::k_expsum_leaf_moments<T>, dim3((unsigned)nterm),
+                           dim3(tfi::kExpThreads), 0, s2, (int32_t)p.kernel_len, pw, hl, m0, m1);
+    }
+    (void)hipEventRecord(h->ev_c, s2);
+    if (grad) launch_scatter<T>(h, F, val, d, s1);
+    (void)hipEventRecord(h->ev_d, s1);
+    launch_scatter<T>(h, gout, valg, d, s0);
+    if (dF) enq_expsum_jobs<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, nullptr, s0);
+    (void)hipStreamWaitEvent(s0, h->ev_d, 0);
+    if (grad) enq_expsum_jobs<T, true>(h, nterm, c, d, val, valg, nullptr, m0, m1, s0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    if (dF) enq_gather<T>(h, d, g, dF, s0);
+}
+
+template <typename T>
+int run_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
+                       int32_t d, T* out, hipStream_t st) {
+    int rc = prepare_expsum<T>(h, nterm, d, false, false);
+    if (rc) return rc;
+    GraphKey key;
+    key.kind = 3;
+    key.dtype = sizeof(T) == 8;
+    key.n = nterm;
+    key.d = d;
+    key.p[0] = c;
+    key.p[1] = lam;
+    key.p[2] = F;
+    key.p[3] = out;
+    return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t cc) {
+        enqueue_forward_expsum<T>(h, nterm, c, lam, F, d, out, a, b, cc);
+    });
+}
+
+template <typename T>
+int run_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
+                        const T* gout, int32_t d, T* dF, double* m0, double* m1,
+                        hipStream_t st) {
+    int rc = prepare_expsum<T>(h, nterm, d, true, m0 != nullptr);
+    if (rc) return rc;
+    GraphKey key;
+    key.kind = 4;
+    key.dtype = sizeof(T) == 8;
+    key.n = nterm;
+    key.d = d;
+    key.p[0] = c;
+    key.p[1] = lam;
+    key.p[2] = F;
+    key.p[3] = gout;
+    key.p[4] = dF;
+    key.p[5] = m0;
+    key.p[6] = m1;
+    return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t cc) {
+        enqueue_backward_expsum<T>(h, nterm, c, lam, F, gout, d, dF, m0, m1, a, b, cc);
+    });
+}
+
 int reassign_methods(tfi_plan* h, double cost) {
     h->popt.fft_cost = cost;
     tfi::assign_methods(h->plan, h->popt);
@@ -1378,6 +1604,57 @@ int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, i
                                    (int32_t)d, (float*)dF, df, st);
     return run_backward<double>(h, (const double*)f, (const double*)F, (const double*)gout,
                                 (int32_t)d, (double*)dF, df, st);
+}
+
+int tfi_integrate_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                         const void* F, int64_t d, tfi_dtype dtype, void* out, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!c || !lambda || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate_expsum: null pointer");
+    if (nterm < 1 || nterm > tfi::kExpMaxTerms)
+        return fail(TFI_ERR_ARG, "tfi_integrate_expsum: need 1 <= nterm <= 16");
+    if (d < 1 || d > (1 << 20))
+        return fail(TFI_ERR_ARG, "tfi_integrate_expsum: need 1 <= d <= 2^20");
+    if (F == out) return fail(TFI_ERR_ARG, "tfi_integrate_expsum: out must not alias F");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return run_forward_expsum<float>(h, nterm, (const float*)c, (const float*)lambda,
+                                         (const float*)F, (int32_t)d, (float*)out, st);
+    if (dtype == TFI_F64)
+        return run_forward_expsum<double>(h, nterm, (const double*)c, (const double*)lambda,
+                                          (const double*)F, (int32_t)d, (double*)out, st);
+    return fail(TFI_ERR_DTYPE, "tfi_integrate_expsum: unknown dtype");
+}
+
+int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                        const void* F, const void* gout, int64_t d, tfi_dtype dtype, void* dF,
+                        double* s0, double* s1, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!c || !lambda || !F || !gout)
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum: null pointer");
+    if (nterm < 1 || nterm > tfi::kExpMaxTerms)
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum: need 1 <= nterm <= 16");
+    if (d < 1 || d > (1 << 20))
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum: need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64)
+        return fail(TFI_ERR_DTYPE, "tfi_backward_expsum: unknown dtype");
+    if ((s0 == nullptr) != (s1 == nullptr))
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum: s0 and s1 are both given or both null");
+    if (s0 && s0 == s1) return fail(TFI_ERR_ARG, "tfi_backward_expsum: s0 must not alias s1");
+    if (dF && (dF == F || dF == gout))
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum: dF must not alias F or gout");
+    if (!dF && !s0) return TFI_OK;
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return run_backward_expsum<float>(h, nterm, (const float*)c, (const float*)lambda,
+                                          (const float*)F, (const float*)gout, (int32_t)d,
+                                          (float*)dF, s0, s1, st);
+    return run_backward_expsum<double>(h, nterm, (const double*)c, (const double*)lambda,
+                                       (const double*)F, (const double*)gout, (int32_t)d,
+                                       (double*)dF, s0, s1, st);
 }
 
 int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {

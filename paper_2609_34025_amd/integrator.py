@@ -21,6 +21,8 @@ import torch
 
 from . import _lib
 
+EXPSUM_MAX_TERMS = 16
+
 _DTYPES = {torch.float32: _lib.TFI_F32, torch.float64: _lib.TFI_F64}
 
 
@@ -175,6 +177,49 @@ class TreeIntegrator:
                                     self._stream(self.device)))
         return dF, df
 
+    def _check_expsum(self, c, lam, F):
+        self._check(F.new_zeros(self.kernel_length), F)
+        for t in (c, lam):
+            if t.dtype != F.dtype or t.device != self.device or t.dim() != 1 \
+                    or not t.is_contiguous():
+                raise ValueError("c and lam must be contiguous 1-D tensors of the field's "
+                                 "dtype on the integrator's device")
+        if c.numel() != lam.numel() or not 1 <= c.numel() <= EXPSUM_MAX_TERMS:
+            raise ValueError(f"c and lam need the same length, 1..{EXPSUM_MAX_TERMS}")
+
+    def integrate_expsum(self, c, lam, F):
+        """out = f(D) F for f(k) = sum_l c[l] lam[l]**k (lam > 0), by backbone
+        sweeps per table job instead of direct sums or FFT."""
+        self._check_expsum(c, lam, F)
+        d = 1 if F.dim() == 1 else F.shape[1]
+        out = torch.empty_like(F)
+        if d == 0:
+            return out
+        _lib.check(_lib.load().tfi_integrate_expsum(
+            self._h, int(c.numel()), c.data_ptr(), lam.data_ptr(), F.data_ptr(), d,
+            _DTYPES[F.dtype], out.data_ptr(), self._stream(self.device)))
+        return out
+
+    def backward_expsum(self, c, lam, F, gout, need_dF=True, need_moments=True):
+        """Adjoint of ``integrate_expsum`` for L = sum(gout * out): returns
+        ``(dF, s0, s1)`` with s0[l] = sum lam[l]**dist <gout_v, F_w> and
+        s1[l] = sum dist lam[l]**dist <gout_v, F_w> (float64), so that
+        dL/dc = s0 and dL/dlam = c s1 / lam."""
+        self._check_expsum(c, lam, F)
+        if F.shape != gout.shape or gout.dtype != F.dtype or not gout.is_contiguous():
+            raise ValueError("gout must be a contiguous tensor like F")
+        d = 1 if F.dim() == 1 else F.shape[1]
+        n = int(c.numel())
+        dF = torch.empty_like(F) if need_dF else None
+        s0 = torch.empty(n, dtype=torch.float64, device=self.device) if need_moments else None
+        s1 = torch.empty(n, dtype=torch.float64, device=self.device) if need_moments else None
+        _lib.check(_lib.load().tfi_backward_expsum(
+            self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
+            _DTYPES[F.dtype], dF.data_ptr() if dF is not None else None,
+            s0.data_ptr() if s0 is not None else None,
+            s1.data_ptr() if s1 is not None else None, self._stream(self.device)))
+        return dF, s0, s1
+
     def close(self):
         h, self._h = getattr(self, "_h", None), None
         if h:
@@ -210,6 +255,32 @@ class TreeIntegrate(torch.autograd.Function):
             full[:k] = df[:k].to(f.dtype)
             df = full
         return None, dF, df
+
+
+class ExpSumIntegrate(torch.autograd.Function):
+    """``out = ExpSumIntegrate.apply(integrator, F, a, b)`` for the kernel
+    f(d) = sum_l a[l] exp(-b[l] d), evaluated by backbone sweeps, with
+    gradients for F, a and b from the exact moments of the adjoint."""
+
+    @staticmethod
+    def forward(ctx, integrator, F, a, b):
+        lam = torch.exp(-b)
+        ctx.integrator = integrator
+        ctx.save_for_backward(F, a, lam)
+        return integrator.integrate_expsum(a.contiguous(), lam.contiguous(), F)
+
+    @staticmethod
+    def backward(ctx, gout):
+        F, a, lam = ctx.saved_tensors
+        need_dF = ctx.needs_input_grad[1]
+        need_ab = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        if not (need_dF or need_ab):
+            return None, None, None, None
+        dF, s0, s1 = ctx.integrator.backward_expsum(a.contiguous(), lam.contiguous(), F,
+                                                    gout.contiguous(), need_dF, need_ab)
+        da = s0.to(a.dtype) if need_ab else None
+        db = (-a * s1.to(a.dtype)) if need_ab else None
+        return None, dF, da, db
 
 
 def expsum_table(a, b, length):
