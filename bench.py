@@ -167,6 +167,26 @@ def main():
     value = 2 * N * d / (elapsed / args.steps)
     log(f"bench: {ms_per_step:.4f} ms/step, {value:.4e} vertex*channels/s")
 
+    # the exponential kernel through each evaluator (per integration)
+    lam_t = torch.tensor([float(np.exp(-0.05))], dtype=torch.float32, device=dev)
+    one_t = torch.ones(1, dtype=torch.float32, device=dev)
+    exp_ms = {}
+    for name, call in (("table", lambda: tfi.integrate(fs[0], Ft)),
+                       ("sweep", lambda: tfi.integrate_expsum(one_t, lam_t, Ft))):
+        for _ in range(3):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            y_exp = call()
+        torch.cuda.synchronize()
+        exp_ms[name] = 1e3 * (time.perf_counter() - t0) / args.steps
+    rows_e = np.random.default_rng(98).choice(N, 256, replace=False)
+    ref_e = oracle.integrate(p, w, tabs[0], F.astype(np.float64), rows=rows_e)
+    exp_sweep_err = float(np.linalg.norm(y_exp.cpu().numpy()[rows_e] - ref_e) / np.linalg.norm(ref_e))
+    log(f"bench: exp kernel per integration: table {exp_ms['table']:.4f} ms, "
+        f"sweep {exp_ms['sweep']:.4f} ms (sweep parity {exp_sweep_err:.2e})")
+
     # parity on 512 sampled rows of the last step's outputs
     rows = np.random.default_rng(99).choice(N, 512, replace=False)
     errs = {}
@@ -224,6 +244,8 @@ def main():
                    "kernel_length": int(K), "build_s": round(build_s, 3),
                    "fft_cost": cost},
         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
+        "exp_kernel_ms_per_integration": {k: round(v, 5) for k, v in exp_ms.items()},
+        "exp_kernel_sweep_rel_err": exp_sweep_err,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
@@ -236,8 +258,12 @@ def batched_fwd_bwd(args, plain_value):
     """Training step on a forest: 512 minimum spanning trees of sqrt(n) x
     sqrt(n) grids (side uniform in {14..64}, weights U{1..16}), F[n x 64]
     FP32, learnable kernel f(d) = sum_{k<8} a_k exp(-b_k d); loss
-    sum(W * out). One step = forward + backward (dF, da, db) through the
-    autograd function. Parity: out and dF on 512 sampled rows against the
+    sum(W * out). One step = forward + backward (dF, da, db) through an
+    autograd function, timed for two evaluators of the same kernel: the
+    backbone sweeps for exponential sums (ExpSumIntegrate, the reported
+    value) and the general kernel-table path (TreeIntegrate with the table
+    built from a, b; its direct/FFT rule autotuned on forward+adjoint
+    passes). Parity of each: out and dF on 512 sampled rows against the
     oracle; da exactly against the oracle's exp-kernel recursion
     (da_k = <W, K_k F> with K_k the single exponential e^{-b_k d}); db by a
     central difference of that recursion in b_k."""
@@ -245,7 +271,8 @@ def batched_fwd_bwd(args, plain_value):
     import torch
 
     import oracle
-    from paper_2609_34025_amd import TreeIntegrator, TreeIntegrate, expsum_table
+    from paper_2609_34025_amd import (ExpSumIntegrate, TreeIntegrator, TreeIntegrate,
+                                      expsum_table)
     from paper_2609_34025_amd import synth as S
 
     dev = torch.device("cuda", 0)
@@ -267,77 +294,94 @@ def batched_fwd_bwd(args, plain_value):
         cost = tfi.autotune(ftune, d, backward=True)
     else:
         cost = tfi.stats()["fft_cost"]
-    log(f"batched: autotuned fft_cost={cost}")
+    log(f"batched: {len(W['offsets']) - 1} trees, n={n} d={d} gen {gen_s:.1f}s "
+        f"build {build_s:.2f}s kernel_length={K} table-path fft_cost={cost}")
     Wt = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device=dev)
     a = torch.tensor(W["a"], dtype=torch.float32, device=dev, requires_grad=True)
     b = torch.tensor(W["b"], dtype=torch.float32, device=dev, requires_grad=True)
     Ft = torch.tensor(F, device=dev, requires_grad=True)
-    log(f"batched: {len(W['offsets']) - 1} trees, n={n} d={d} gen {gen_s:.1f}s "
-        f"build {build_s:.2f}s kernel_length={K}")
-    res = {}
 
-    def step():
-        a.grad = b.grad = Ft.grad = None
-        out = TreeIntegrate.apply(tfi, Ft, expsum_table(a, b, K))
-        (Wt * out).sum().backward()
-        res["out"] = out
-
-    steps = max(5, args.steps // 5)
-    for _ in range(max(2, args.warmup)):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    value = n * d / (el / steps)
-    log(f"batched: {1e3 * el / steps:.3f} ms/step fwd+bwd, {value:.4e} vertex*channels/s")
-    tfi.profile(True)
-    for _ in range(2):
-        step()
-    torch.cuda.synchronize()
-    tfi.profile(False)
-    stages = tfi.profile_report()
-    for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"]):
-        log(f"batched stage {k:14s} {v['launches']:4d} launches {1e3 * v['ms'] / v['launches']:10.2f} "
-            f"us/launch")
-    dom = max(stages, key=lambda k: stages[k]["ms"])
-    roofline = stage_roofline(dom, stages[dom], "f32", "grid512")
-
-    # parity
+    # oracle references, shared by both evaluators
     rows = np.random.default_rng(99).choice(n, 512, replace=False)
     A = a.detach().double().cpu().numpy()
     B = b.detach().double().cpu().numpy()
     ftab = (A[None, :] * np.exp(-np.arange(K)[:, None] * B[None, :])).sum(1)
     Fd = F.astype(np.float64)
     Wd = Wt.double().cpu().numpy()
-    ref = oracle.integrate(p, w, ftab, Fd, rows=rows)
-    y = res["out"].detach().double().cpu().numpy()[rows]
-    e_out = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
-    refd = oracle.integrate(p, w, ftab, Wd, rows=rows)
-    ydF = Ft.grad.double().cpu().numpy()[rows]
-    e_dF = float(np.linalg.norm(ydF - refd) / np.linalg.norm(refd))
+    ref_out = oracle.integrate(p, w, ftab, Fd, rows=rows)
+    ref_dF = oracle.integrate(p, w, ftab, Wd, rows=rows)
     da_ref = np.array([np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k])], Fd))
                        for k in range(8)])
     hb = 1e-5
     db_ref = np.array([A[k] * (np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] - hb)], Fd))
                                - np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] + hb)], Fd)))
                        / (2 * hb) for k in range(8)])
-    e_da = float(np.linalg.norm(a.grad.double().cpu().numpy() - da_ref) / np.linalg.norm(da_ref))
-    e_db = float(np.linalg.norm(b.grad.double().cpu().numpy() - db_ref) / np.linalg.norm(db_ref))
-    errs = {"out": e_out, "dF": e_dF, "da": e_da, "db": e_db}
-    ok = all(e <= 1e-4 for e in errs.values())
-    log(f"batched: parity {errs} ok={ok}")
-    return {"value": value, "unit": "vertex*channels/s", "steps": steps,
-            "ms_per_step": 1e3 * el / steps, "ratio_vs_plain_fwd": value / plain_value,
+
+    def rel(x, r):
+        return float(np.linalg.norm(x - r) / np.linalg.norm(r))
+
+    paths = {
+        "sweep": lambda: ExpSumIntegrate.apply(tfi, Ft, a, b),
+        "table": lambda: TreeIntegrate.apply(tfi, Ft, expsum_table(a, b, K)),
+    }
+    results = {}
+    for name, fwd in paths.items():
+        res = {}
+
+        def step():
+            a.grad = b.grad = Ft.grad = None
+            out = fwd()
+            (Wt * out).sum().backward()
+            res["out"] = out
+
+        steps = max(5, args.steps // 5)
+        for _ in range(max(2, args.warmup)):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        value = n * d / (el / steps)
+        log(f"batched[{name}]: {1e3 * el / steps:.3f} ms/step fwd+bwd, "
+            f"{value:.4e} vertex*channels/s")
+        tfi.profile(True)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        tfi.profile(False)
+        stages = tfi.profile_report()
+        for k, v in sorted(stages.items(), key=lambda kv: -kv[1]["ms"]):
+            log(f"batched[{name}] stage {k:16s} {v['launches']:4d} launches "
+                f"{1e3 * v['ms'] / v['launches']:10.2f} us/launch")
+        dom = max(stages, key=lambda k: stages[k]["ms"])
+        errs = {"out": rel(res["out"].detach().double().cpu().numpy()[rows], ref_out),
+                "dF": rel(Ft.grad.double().cpu().numpy()[rows], ref_dF),
+                "da": rel(a.grad.double().cpu().numpy(), da_ref),
+                "db": rel(b.grad.double().cpu().numpy(), db_ref)}
+        ok = all(e <= 1e-4 for e in errs.values())
+        log(f"batched[{name}]: parity {errs} ok={ok}")
+        results[name] = {"value": value, "steps": steps, "ms_per_step": 1e3 * el / steps,
+                         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
+                         "roofline": stage_roofline(dom, stages[dom], "f32", "grid512"),
+                         "stages": stages}
+    best = results["sweep"]
+    return {"value": best["value"], "unit": "vertex*channels/s", "steps": best["steps"],
+            "ms_per_step": best["ms_per_step"], "ratio_vs_plain_fwd": best["value"] / plain_value,
+            "evaluator": "backbone sweeps for exponential sums (ExpSumIntegrate)",
             "workload": "forward+backward (dF, da, db) of 512 grid-MST trees, sides U{14..64}, "
                         "weights U{1..16}, F[n x 64] fp32, f = sum of 8 exponentials; "
                         "loss sum(W * out)",
             "n": int(n), "d": int(d), "trees": int(len(W["offsets"]) - 1),
-            "kernel_length": int(K), "build_s": round(build_s, 3), "fft_cost": cost,
-            "parity": {"rows": 512, "rel_err": errs, "ok": ok}, "roofline": roofline,
-            "stages": stages}
+            "kernel_length": int(K), "build_s": round(build_s, 3),
+            "parity": best["parity"], "roofline": best["roofline"], "stages": best["stages"],
+            "table_path": {"value": results["table"]["value"],
+                           "ms_per_step": results["table"]["ms_per_step"],
+                           "ratio_vs_plain_fwd": results["table"]["value"] / plain_value,
+                           "fft_cost": cost, "parity": results["table"]["parity"],
+                           "roofline": results["table"]["roofline"],
+                           "stages": results["table"]["stages"]}}
 
 
 if __name__ == "__main__":

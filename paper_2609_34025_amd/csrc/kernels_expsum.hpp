@@ -58,18 +58,18 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-// One group of gs lanes (gs divides 64) per table job, taken in the order
-// ej (jobs sorted by size); lane c of a group handles channels c, c + gs,
-// ... Cells of a job are sorted by backbone position.
-// MULTI = false: every job of the list has one backbone position (centroid
-// backbones, corrections): a = sum lam^r v and the table value lam^r a.
-// MULTI = true: jobs with several positions; jpos[job] is the job's first
-// slot in `scratch`, which holds per position NQ quantities x nterm terms
-// x d channels (forward: L, a; gradient: L, a, L^r, a^r, M).
+// Jobs with several backbone positions (diameter backbones): one group of
+// gs lanes (gs divides 64) per job, taken in the order ej (jobs sorted by
+// size); lane c of a group handles channels c, c + gs, ... and sweeps the
+// job's cells (sorted by backbone position) forward, then backward.
+// jpos[job] is the job's first slot in `scratch`, which holds per position
+// NQ quantities x nterm terms x d channels (forward: L, a; gradient: L, a,
+// L^r, a^r, M).
 // GRAD = false: writes the table value of every cell to g[row].
-// GRAD = true: adds the job's signed moments to s0/s1 (FP64, one atomic
-// per workgroup and term); valg holds the gout cell sums.
-template <typename T, int NJ, bool GRAD, bool MULTI>
+// GRAD = true: writes the workgroup's signed moments (sum over its jobs) to
+// row mbase + blockIdx.x of mrow ([row][s0 | s1][nterm], FP64); valg holds
+// the gout cell sums.
+template <typename T, int NJ, bool GRAD>
 __global__ void __launch_bounds__(kExpThreads)
 k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
               const int32_t* __restrict__ ej, const int64_t* __restrict__ joff,
@@ -78,9 +78,8 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
               const int32_t* __restrict__ jc_val, const T* __restrict__ c,
               const T* __restrict__ pw, int32_t K, const T* __restrict__ val,
               const T* __restrict__ valg, T* __restrict__ g, T* __restrict__ scratch,
-              double* __restrict__ s0, double* __restrict__ s1) {
+              double* __restrict__ mrow, int64_t mbase) {
     constexpr int NQ = GRAD ? 5 : 2;
-    constexpr int B = 4;  // cells per batch of loads (single-position jobs)
     const int32_t gpb = kExpThreads / gs;
     const int32_t grp = threadIdx.x / gs, lc = threadIdx.x - grp * gs;
     const int32_t jn = blockIdx.x * gpb + grp;
@@ -95,69 +94,7 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
     const int64_t cb = active ? joff[job] : 0, ce = active ? joff[job + 1] : 0;
     const T sgn = (GRAD && active && jsign[job] < 0) ? (T)-1 : (T)1;
     for (int32_t ch = lc; active && ch < d && cb < ce; ch += gs) {
-        if constexpr (!MULTI) {
-            // a (and a^r) over the job's cells, loads in batches
-            T A[NJ], Ar[NJ];
-#pragma unroll
-            for (int l = 0; l < NJ; ++l) A[l] = Ar[l] = (T)0;
-            for (int64_t i0 = cb; i0 < ce; i0 += B) {
-                int32_t rr[B];
-                int64_t o[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    const int64_t i = min(i0 + u, ce - 1);
-                    rr[u] = jc_r[i];
-                    o[u] = (int64_t)jc_val[i] * d + ch;
-                }
-                T v[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) v[u] = (i0 + u < ce) ? val[o[u]] : (T)0;
-#pragma unroll
-                for (int u = 0; u < B; ++u)
-#pragma unroll
-                    for (int l = 0; l < NJ; ++l) {
-                        if (l >= nterm) continue;
-                        const T w = pw[(int64_t)l * K + rr[u]] * v[u];
-                        A[l] += w;
-                        if (GRAD) Ar[l] += (T)rr[u] * w;
-                    }
-            }
-            // table values (or moments) at the cells
-            for (int64_t i0 = cb; i0 < ce; i0 += B) {
-                int32_t rr[B];
-                int64_t o[B];
-#pragma unroll
-                for (int u = 0; u < B; ++u) {
-                    const int64_t i = min(i0 + u, ce - 1);
-                    rr[u] = jc_r[i];
-                    o[u] = (int64_t)jc_val[i] * d + ch;
-                }
-                if (!GRAD) {
-#pragma unroll
-                    for (int u = 0; u < B; ++u) {
-                        if (i0 + u >= ce) continue;
-                        T sum = (T)0;
-#pragma unroll
-                        for (int l = 0; l < NJ; ++l)
-                            if (l < nterm) sum += cl[l] * pw[(int64_t)l * K + rr[u]] * A[l];
-                        g[o[u]] = sum;
-                    }
-                } else {
-                    T gv[B];
-#pragma unroll
-                    for (int u = 0; u < B; ++u) gv[u] = (i0 + u < ce) ? sgn * valg[o[u]] : (T)0;
-#pragma unroll
-                    for (int u = 0; u < B; ++u)
-#pragma unroll
-                        for (int l = 0; l < NJ; ++l) {
-                            if (l >= nterm) continue;
-                            const T w = pw[(int64_t)l * K + rr[u]];
-                            m0[l] += (double)(gv[u] * w * A[l]);
-                            m1[l] += (double)(gv[u] * w * ((T)rr[u] * A[l] + Ar[l]));
-                        }
-                }
-            }
-        } else {
+        {
             const int64_t pos0 = jpos[job];
             auto slot = [&](int64_t p, int q, int l) -> T& {
                 return scratch[((p * NQ + q) * nterm + l) * (int64_t)d + ch];
@@ -264,22 +201,239 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
     }
     if (GRAD) {
         __shared__ double red[kExpThreads / 64];
+        double* row = mrow + (mbase + blockIdx.x) * 2 * nterm;
         for (int l = 0; l < nterm && l < NJ; ++l) {
             const double t0 = block_sum(m0[l], red);
-            if (threadIdx.x == 0 && t0 != 0.0) atomicAdd(s0 + l, t0);
+            if (threadIdx.x == 0) row[l] = t0;
             const double t1 = block_sum(m1[l], red);
-            if (threadIdx.x == 0 && t1 != 0.0) atomicAdd(s1 + l, t1);
+            if (threadIdx.x == 0) row[nterm + l] = t1;
         }
     }
 }
 
+// ---- single-position jobs, split into chunks of cells -------------------
+// A job with one backbone position needs, per term l and channel c, the
+// sums a_l = sum_i lam_l^{r_i} v_i (forward) or a_l, a^r_l (r-weighted) and
+// their gout counterparts b_l, b^r_l (moments). Cells are taken in chunks
+// of at most kExpChunk; chunk k covers cells ck[3k+1] .. ck[3k+2] of job
+// ck[3k]. A workgroup per chunk: the chunk's weights lam_l^r go to LDS;
+// thread (cell group g, lane c) sums the cells g, g + CG, ... for its
+// channel; the partial sums are reduced over the cell groups (wave
+// shuffles, then LDS across waves).
+// cslot[k] < 0: the chunk is its whole job and the workgroup finishes it
+// (forward: table values lam_l^r sum_l c_l a_l; moments: row mbase + k of
+// mrow gets sign <b_l, a_l> and sign (<b^r_l, a_l> + <b_l, a^r_l>)). Else
+// the sums go to partial slot cslot[k] ([NQ][nterm][d]) for
+// k_expsum_jobsum (and the moment row is zero).
+constexpr int kExpChunk = 256;
+
+// Dynamic LDS bytes of k_expsum_chunks<T, NJ, *>.
+template <typename T, int NJ>
+constexpr int expsum_chunk_lds() {
+    return (int)sizeof(T) * (NJ * kExpChunk + (kExpThreads / 64) * NJ * 64) + 8 * kExpChunk;
+}
+
+template <typename T, int NJ, bool GRAD>
+__global__ void __launch_bounds__(kExpThreads)
+k_expsum_chunks(int32_t nterm, int32_t d, int32_t gs, const int32_t* __restrict__ ck,
+                const int32_t* __restrict__ cslot, const int32_t* __restrict__ jsign,
+                const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_val,
+                const T* __restrict__ c, const T* __restrict__ pw, int32_t K,
+                const T* __restrict__ val, const T* __restrict__ valg, T* __restrict__ g,
+                T* __restrict__ part, double* __restrict__ mrow, int64_t mbase) {
+    constexpr int NQ = GRAD ? 4 : 1;
+    // dynamic LDS (expsum_chunk_lds bytes): weights lam_l^r of the chunk's
+    // cells [NJ][kExpChunk], the cross-wave reduction buffer [4][NJ][64],
+    // cell rows and depths
+    extern __shared__ unsigned char dyn_raw[];
+    T* sw = reinterpret_cast<T*>(dyn_raw);
+    T* red = sw + NJ * kExpChunk;
+    int32_t* srow = reinterpret_cast<int32_t*>(red + (kExpThreads / 64) * NJ * 64);
+    int32_t* sr = srow + kExpChunk;
+    __shared__ double dred[kExpThreads / 64];
+    const int32_t job = ck[3 * blockIdx.x];
+    const int32_t cb = ck[3 * blockIdx.x + 1], ce = ck[3 * blockIdx.x + 2];
+    const int32_t n = ce - cb;  // 1 .. kExpChunk
+    const int32_t slot = cslot[blockIdx.x];
+    const T sgn = (GRAD && jsign[job] < 0) ? (T)-1 : (T)1;
+    if ((int32_t)threadIdx.x < n) {
+        const int32_t i = cb + threadIdx.x;
+        const int32_t r = jc_r[i];
+        sr[threadIdx.x] = r;
+        srow[threadIdx.x] = jc_val[i];
+#pragma unroll
+        for (int l = 0; l < NJ; ++l)
+            sw[l * kExpChunk + threadIdx.x] = l < nterm ? pw[(int64_t)l * K + r] : (T)0;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t lc = lane % gs, cgw = lane / gs;
+    const int32_t cgpw = 64 / gs, CG = (kExpThreads / 64) * cgpw;
+    const int32_t cg = wave * cgpw + cgw;
+    double m0[NJ], m1[NJ];
+#pragma unroll
+    for (int l = 0; l < NJ; ++l) m0[l] = m1[l] = 0.0;
+    for (int32_t c0 = 0; c0 < d; c0 += gs) {
+        const int32_t ch = c0 + lc;
+        const bool chok = ch < d;
+        T acc[NQ][NJ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) acc[q][l] = (T)0;
+        // this thread's cells, loads four at a time
+        for (int32_t k0 = cg; k0 < n; k0 += 4 * CG) {
+            T v[4], gv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t k = k0 + u * CG;
+                const bool ok = chok && k < n;
+                const int64_t o = (int64_t)srow[min(k, n - 1)] * d + min(ch, d - 1);
+                v[u] = ok ? val[o] : (T)0;
+                if (GRAD) gv[u] = ok ? valg[o] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int32_t k = min(k0 + u * CG, n - 1);
+                const T rk = (T)sr[k];
+#pragma unroll
+                for (int l = 0; l < NJ; ++l) {
+                    const T w = sw[l * kExpChunk + k];
+                    acc[0][l] += w * v[u];
+                    if (GRAD) {
+                        acc[1][l] += rk * w * v[u];
+                        acc[2][l] += w * gv[u];
+                        acc[3][l] += rk * w * gv[u];
+                    }
+                }
+            }
+        }
+        // reduce over the cell groups: inside the wave, then across waves
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+            for (int l = 0; l < NJ; ++l)
+                for (int o = gs; o < 64; o <<= 1) acc[q][l] += __shfl_xor(acc[q][l], o, 64);
+        // totals of this channel round, in every thread of the channel (one
+        // quantity at a time through the reduction buffer)
+        T tot[NQ][NJ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            __syncthreads();
+            if (cgw == 0)
+#pragma unroll
+                for (int l = 0; l < NJ; ++l) red[(wave * NJ + l) * 64 + lc] = acc[q][l];
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) {
+                T t = (T)0;
+#pragma unroll
+                for (int w = 0; w < kExpThreads / 64; ++w) t += red[(w * NJ + l) * 64 + lc];
+                tot[q][l] = t;
+            }
+        }
+        if (slot >= 0) {
+            if (cg == 0 && chok)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+#pragma unroll
+                    for (int l = 0; l < NJ; ++l)
+                        if (l < nterm) part[(((int64_t)slot * NQ + q) * nterm + l) * d + ch] = tot[q][l];
+        } else if (!GRAD) {
+            T cl[NJ];
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) cl[l] = l < nterm ? c[l] * tot[0][l] : (T)0;
+            for (int32_t k = cg; k < n && chok; k += CG) {
+                T sum = (T)0;
+#pragma unroll
+                for (int l = 0; l < NJ; ++l) sum += cl[l] * sw[l * kExpChunk + k];
+                g[(int64_t)srow[k] * d + ch] = sum;
+            }
+        } else if (cg == 0 && chok) {
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) {
+                m0[l] += (double)(sgn * tot[2][l] * tot[0][l]);
+                m1[l] += (double)(sgn * (tot[3][l] * tot[0][l] + tot[2][l] * tot[1][l]));
+            }
+        }
+    }
+    if (GRAD) {  // every workgroup writes its row (zeros for partial chunks)
+        double* row = mrow + (mbase + blockIdx.x) * 2 * nterm;
+        for (int l = 0; l < nterm && l < NJ; ++l) {
+            const double t0 = block_sum(m0[l], dred);
+            if (threadIdx.x == 0) row[l] = t0;
+            const double t1 = block_sum(m1[l], dred);
+            if (threadIdx.x == 0) row[nterm + l] = t1;
+        }
+    }
+}
+
+// Jobs of several chunks: one workgroup per job sums its chunks' partial
+// slots (jslot[2j] .. jslot[2j] + jslot[2j + 1] - 1, in order) into the
+// first slot; with GRAD it then writes the job's moments (sign jsg[j]) to
+// row mbase + j of mrow.
+template <typename T, int NJ, bool GRAD>
+__global__ void __launch_bounds__(kExpThreads)
+k_expsum_jobsum(int32_t nterm, int32_t d, const int32_t* __restrict__ jslot,
+                const int32_t* __restrict__ jsg, T* __restrict__ part,
+                double* __restrict__ mrow, int64_t mbase) {
+    constexpr int NQ = GRAD ? 4 : 1;
+    __shared__ double dred[kExpThreads / 64];
+    const int64_t first = jslot[2 * blockIdx.x];
+    const int32_t cnt = jslot[2 * blockIdx.x + 1];
+    const double sgn = jsg[blockIdx.x] < 0 ? -1.0 : 1.0;
+    const int64_t per = (int64_t)NQ * nterm * d;
+    for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
+        T t = part[first * per + e];
+        for (int32_t k = 1; k < cnt; ++k) t += part[(first + k) * per + e];
+        part[first * per + e] = t;
+    }
+    if (!GRAD) return;
+    __syncthreads();
+    const T* P = part + first * per;
+    for (int l = 0; l < nterm && l < NJ; ++l) {
+        double a0 = 0.0, a1 = 0.0;
+        for (int32_t ch = threadIdx.x; ch < d; ch += blockDim.x) {
+            const double A = P[(0 * nterm + l) * d + ch], Ar = P[(1 * nterm + l) * d + ch];
+            const double B = P[(2 * nterm + l) * d + ch], Br = P[(3 * nterm + l) * d + ch];
+            a0 += B * A;
+            a1 += Br * A + B * Ar;
+        }
+        const double t0 = block_sum(a0, dred);
+        if (threadIdx.x == 0) mrow[(mbase + blockIdx.x) * 2 * nterm + l] = sgn * t0;
+        const double t1 = block_sum(a1, dred);
+        if (threadIdx.x == 0) mrow[(mbase + blockIdx.x) * 2 * nterm + nterm + l] = sgn * t1;
+    }
+}
+
+// Table values of the chunks of several-chunk jobs (forward), from the
+// job's summed slot: ck as in k_expsum_chunks, tslot[k] = that slot.
+template <typename T, int NJ>
+__global__ void __launch_bounds__(kExpThreads)
+k_expsum_expand(int32_t nterm, int32_t d, const int32_t* __restrict__ ck,
+                const int32_t* __restrict__ tslot, const int32_t* __restrict__ jc_r,
+                const int32_t* __restrict__ jc_val, const T* __restrict__ c,
+                const T* __restrict__ pw, int32_t K, const T* __restrict__ part,
+                T* __restrict__ g) {
+    const int32_t cb = ck[3 * blockIdx.x + 1], ce = ck[3 * blockIdx.x + 2];
+    const T* P = part + (int64_t)tslot[blockIdx.x] * nterm * d;
+    for (int64_t e = threadIdx.x; e < (int64_t)(ce - cb) * d; e += blockDim.x) {
+        const int32_t i = cb + (int32_t)(e / d), ch = (int32_t)(e % d);
+        const int32_t r = jc_r[i];
+        T sum = (T)0;
+        for (int l = 0; l < nterm && l < NJ; ++l)
+            sum += c[l] * pw[(int64_t)l * K + r] * P[(int64_t)l * d + ch];
+        g[(int64_t)jc_val[i] * d + ch] = sum;
+    }
+}
+
 // Leaf-tile part of the moments from the leaf pair histogram h[k]:
-// s0_l += sum_k lam_l^k h[k], s1_l += sum_k k lam_l^k h[k]. One workgroup
-// per term.
+// sum_k lam_l^k h[k] and sum_k k lam_l^k h[k]. One workgroup per term l,
+// writing row mbase + l of mrow (its other entries zero).
 template <typename T>
 __global__ void __launch_bounds__(kExpThreads)
-k_expsum_leaf_moments(int32_t K, const T* __restrict__ pw, const double* __restrict__ h,
-                      double* __restrict__ s0, double* __restrict__ s1) {
+k_expsum_leaf_moments(int32_t nterm, int32_t K, const T* __restrict__ pw,
+                      const double* __restrict__ h, double* __restrict__ mrow, int64_t mbase) {
     __shared__ double red[kExpThreads / 64];
     const int l = blockIdx.x;
     double a = 0.0, b = 0.0;
@@ -288,10 +442,28 @@ k_expsum_leaf_moments(int32_t K, const T* __restrict__ pw, const double* __restr
         a += w;
         b += (double)k * w;
     }
-    const double ta = block_sum(a, red);
-    if (threadIdx.x == 0) atomicAdd(s0 + l, ta);
+    const double ta = block_sum(a, red);  // totals in thread 0
     const double tb = block_sum(b, red);
-    if (threadIdx.x == 0) atomicAdd(s1 + l, tb);
+    if (threadIdx.x == 0) {
+        double* row = mrow + (mbase + l) * 2 * nterm;
+        for (int e = 0; e < 2 * nterm; ++e) row[e] = e == l ? ta : (e == nterm + l ? tb : 0.0);
+    }
+}
+
+// s0[l] / s1[l] = column l / nterm + l of the moment rows mrow[0 .. rows),
+// summed in a fixed order (one workgroup per column): reproducible bitwise.
+__global__ void __launch_bounds__(kExpThreads)
+k_expsum_moments(int32_t nterm, int64_t rows, const double* __restrict__ mrow,
+                 double* __restrict__ s0, double* __restrict__ s1) {
+    __shared__ double red[kExpThreads / 64];
+    const int col = blockIdx.x;
+    double a = 0.0;
+    for (int64_t r = threadIdx.x; r < rows; r += blockDim.x) a += mrow[r * 2 * nterm + col];
+    const double t = block_sum(a, red);
+    if (threadIdx.x == 0) {
+        if (col < nterm) s0[col] = t;
+        else s1[col - nterm] = t;
+    }
 }
 
 }  // namespace tfi
