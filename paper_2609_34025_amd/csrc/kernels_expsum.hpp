@@ -211,219 +211,154 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
     }
 }
 
-// ---- single-position jobs, split into chunks of cells -------------------
+// ---- one-position jobs, one wavefront each ------------------------------
 // A job with one backbone position needs, per term l and channel c, the
 // sums a_l = sum_i lam_l^{r_i} v_i (forward) or a_l, a^r_l (r-weighted) and
-// their gout counterparts b_l, b^r_l (moments). Cells are taken in chunks
-// of at most kExpChunk; chunk k covers cells ck[3k+1] .. ck[3k+2] of job
-// ck[3k]. A workgroup per chunk: the chunk's weights lam_l^r go to LDS;
-// thread (cell group g, lane c) sums the cells g, g + CG, ... for its
-// channel; the partial sums are reduced over the cell groups (wave
-// shuffles, then LDS across waves).
-// cslot[k] < 0: the chunk is its whole job and the workgroup finishes it
-// (forward: table values lam_l^r sum_l c_l a_l; moments: row mbase + k of
-// mrow gets sign <b_l, a_l> and sign (<b^r_l, a_l> + <b_l, a^r_l>)). Else
-// the sums go to partial slot cslot[k] ([NQ][nterm][d]) for
-// k_expsum_jobsum (and the moment row is zero).
-constexpr int kExpChunk = 256;
-
-// Dynamic LDS bytes of k_expsum_chunks<T, NJ, *>.
-template <typename T, int NJ>
-constexpr int expsum_chunk_lds() {
-    return (int)sizeof(T) * (NJ * kExpChunk + (kExpThreads / 64) * NJ * 64) + 8 * kExpChunk;
-}
-
+// their gout counterparts b_l, b^r_l (moments). One wavefront per job (jobs
+// in the order ej, by size): lane (s, c) = (lane / gs, lane % gs), with gs
+// the smallest power of two >= d (at most 64), handles channels c, c + gs,
+// ... and, of every step of 64 cells, the cells s, s + S, ... (S = 64 / gs
+// cell subgroups). In a step lane k reads cell k's depth, row and weights
+// lam_l^r once; the others take them by cross-lane shuffle, so the walk
+// needs neither LDS nor workgroup barriers (and every shuffle runs with the
+// whole wavefront active). The subgroups' sums are combined by shuffles.
+// Forward: a second walk writes the table values lam_l^r sum_l c_l a_l.
+// Moments: subgroup 0 adds sign <b_l, a_l> and sign (<b^r_l, a_l> + <b_l,
+// a^r_l>) over its channels; the workgroup total goes to row mbase +
+// blockIdx.x of mrow ([s0 | s1][nterm]).
 template <typename T, int NJ, bool GRAD>
 __global__ void __launch_bounds__(kExpThreads)
-k_expsum_chunks(int32_t nterm, int32_t d, int32_t gs, const int32_t* __restrict__ ck,
-                const int32_t* __restrict__ cslot, const int32_t* __restrict__ jsign,
-                const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_val,
-                const T* __restrict__ c, const T* __restrict__ pw, int32_t K,
-                const T* __restrict__ val, const T* __restrict__ valg, T* __restrict__ g,
-                T* __restrict__ part, double* __restrict__ mrow, int64_t mbase) {
+k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
+              const int32_t* __restrict__ ej, const int64_t* __restrict__ joff,
+              const int32_t* __restrict__ jsign, const int32_t* __restrict__ jc_r,
+              const int32_t* __restrict__ jc_val, const T* __restrict__ c,
+              const T* __restrict__ pw, int32_t K, const T* __restrict__ val,
+              const T* __restrict__ valg, T* __restrict__ g, double* __restrict__ mrow,
+              int64_t mbase) {
     constexpr int NQ = GRAD ? 4 : 1;
-    // dynamic LDS (expsum_chunk_lds bytes): weights lam_l^r of the chunk's
-    // cells [NJ][kExpChunk], the cross-wave reduction buffer [4][NJ][64],
-    // cell rows and depths
-    extern __shared__ unsigned char dyn_raw[];
-    T* sw = reinterpret_cast<T*>(dyn_raw);
-    T* red = sw + NJ * kExpChunk;
-    int32_t* srow = reinterpret_cast<int32_t*>(red + (kExpThreads / 64) * NJ * 64);
-    int32_t* sr = srow + kExpChunk;
-    __shared__ double dred[kExpThreads / 64];
-    const int32_t job = ck[3 * blockIdx.x];
-    const int32_t cb = ck[3 * blockIdx.x + 1], ce = ck[3 * blockIdx.x + 2];
-    const int32_t n = ce - cb;  // 1 .. kExpChunk
-    const int32_t slot = cslot[blockIdx.x];
-    const T sgn = (GRAD && jsign[job] < 0) ? (T)-1 : (T)1;
-    if ((int32_t)threadIdx.x < n) {
-        const int32_t i = cb + threadIdx.x;
-        const int32_t r = jc_r[i];
-        sr[threadIdx.x] = r;
-        srow[threadIdx.x] = jc_val[i];
+    constexpr int B = 4;  // cells per subgroup and batch of value loads
+    const int lane = threadIdx.x & 63;
+    const int32_t jn = blockIdx.x * (kExpThreads / 64) + (threadIdx.x >> 6);
+    const bool active = jn < njobs;  // uniform per wavefront
+    const int32_t S = 64 / gs, sub = lane / gs, lc = lane - sub * gs;
+    const int32_t job = active ? ej[jn] : 0;
+    const int64_t cb = active ? joff[job] : 0, ce = active ? joff[job + 1] : 0;
+    const T sgn = (GRAD && active && jsign[job] < 0) ? (T)-1 : (T)1;
+    T cl[NJ];
 #pragma unroll
-        for (int l = 0; l < NJ; ++l)
-            sw[l * kExpChunk + threadIdx.x] = l < nterm ? pw[(int64_t)l * K + r] : (T)0;
-    }
-    __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t lc = lane % gs, cgw = lane / gs;
-    const int32_t cgpw = 64 / gs, CG = (kExpThreads / 64) * cgpw;
-    const int32_t cg = wave * cgpw + cgw;
+    for (int l = 0; l < NJ; ++l) cl[l] = (!GRAD && l < nterm) ? c[l] : (T)0;
     double m0[NJ], m1[NJ];
 #pragma unroll
     for (int l = 0; l < NJ; ++l) m0[l] = m1[l] = 0.0;
     for (int32_t c0 = 0; c0 < d; c0 += gs) {
         const int32_t ch = c0 + lc;
         const bool chok = ch < d;
+        const int32_t chs = min(ch, d - 1);
         T acc[NQ][NJ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int l = 0; l < NJ; ++l) acc[q][l] = (T)0;
-        // this thread's cells, loads four at a time
-        for (int32_t k0 = cg; k0 < n; k0 += 4 * CG) {
-            T v[4], gv[4];
+        for (int64_t k0 = cb; k0 < ce; k0 += 64) {
+            const int32_t nk = (int32_t)min((int64_t)64, ce - k0);
+            const int64_t mine = k0 + min(lane, nk - 1);
+            const int32_t rmine = jc_r[mine], rowmine = jc_val[mine];
+            T wmine[NJ];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t k = k0 + u * CG;
-                const bool ok = chok && k < n;
-                const int64_t o = (int64_t)srow[min(k, n - 1)] * d + min(ch, d - 1);
-                v[u] = ok ? val[o] : (T)0;
-                if (GRAD) gv[u] = ok ? valg[o] : (T)0;
-            }
+            for (int l = 0; l < NJ; ++l) wmine[l] = l < nterm ? pw[(int64_t)l * K + rmine] : (T)0;
+            for (int32_t k = 0; k < nk; k += S * B) {  // uniform in the wavefront
+                int32_t kk[B], rowk[B];
+                T rk[B], v[B], gv[B];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int32_t k = min(k0 + u * CG, n - 1);
-                const T rk = (T)sr[k];
+                for (int u = 0; u < B; ++u) {
+                    kk[u] = k + u * S + sub;
+                    const int32_t src = min(kk[u], nk - 1);
+                    rowk[u] = __shfl(rowmine, src, 64);
+                    rk[u] = GRAD ? (T)__shfl(rmine, src, 64) : (T)0;
+                }
 #pragma unroll
-                for (int l = 0; l < NJ; ++l) {
-                    const T w = sw[l * kExpChunk + k];
-                    acc[0][l] += w * v[u];
-                    if (GRAD) {
-                        acc[1][l] += rk * w * v[u];
-                        acc[2][l] += w * gv[u];
-                        acc[3][l] += rk * w * gv[u];
+                for (int u = 0; u < B; ++u) {
+                    const bool ok = chok && kk[u] < nk;
+                    const int64_t o = (int64_t)rowk[u] * d + chs;
+                    v[u] = ok ? val[o] : (T)0;
+                    gv[u] = (GRAD && ok) ? valg[o] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int32_t src = min(kk[u], nk - 1);
+#pragma unroll
+                    for (int l = 0; l < NJ; ++l) {
+                        if (l >= nterm) continue;
+                        const T w = __shfl(wmine[l], src, 64);
+                        acc[0][l] += w * v[u];
+                        if (GRAD) {
+                            acc[1][l] += rk[u] * w * v[u];
+                            acc[2][l] += w * gv[u];
+                            acc[3][l] += rk[u] * w * gv[u];
+                        }
                     }
                 }
             }
         }
-        // reduce over the cell groups: inside the wave, then across waves
+        // combine the cell subgroups (lanes gs, 2 gs, ... apart)
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
 #pragma unroll
             for (int l = 0; l < NJ; ++l)
                 for (int o = gs; o < 64; o <<= 1) acc[q][l] += __shfl_xor(acc[q][l], o, 64);
-        // totals of this channel round, in every thread of the channel (one
-        // quantity at a time through the reduction buffer)
-        T tot[NQ][NJ];
+        if (!GRAD) {
+            T ca[NJ];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            __syncthreads();
-            if (cgw == 0)
+            for (int l = 0; l < NJ; ++l) ca[l] = cl[l] * acc[0][l];
+            for (int64_t k0 = cb; k0 < ce; k0 += 64) {
+                const int32_t nk = (int32_t)min((int64_t)64, ce - k0);
+                const int64_t mine = k0 + min(lane, nk - 1);
+                const int32_t rmine = jc_r[mine], rowmine = jc_val[mine];
+                T wmine[NJ];
 #pragma unroll
-                for (int l = 0; l < NJ; ++l) red[(wave * NJ + l) * 64 + lc] = acc[q][l];
-            __syncthreads();
-#pragma unroll
-            for (int l = 0; l < NJ; ++l) {
-                T t = (T)0;
-#pragma unroll
-                for (int w = 0; w < kExpThreads / 64; ++w) t += red[(w * NJ + l) * 64 + lc];
-                tot[q][l] = t;
-            }
-        }
-        if (slot >= 0) {
-            if (cg == 0 && chok)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q)
+                for (int l = 0; l < NJ; ++l)
+                    wmine[l] = l < nterm ? pw[(int64_t)l * K + rmine] : (T)0;
+                for (int32_t k = 0; k < nk; k += S) {  // uniform in the wavefront
+                    const int32_t kk = k + sub, src = min(kk, nk - 1);
+                    const int32_t rowk = __shfl(rowmine, src, 64);
+                    T sum = (T)0;
 #pragma unroll
                     for (int l = 0; l < NJ; ++l)
-                        if (l < nterm) part[(((int64_t)slot * NQ + q) * nterm + l) * d + ch] = tot[q][l];
-        } else if (!GRAD) {
-            T cl[NJ];
-#pragma unroll
-            for (int l = 0; l < NJ; ++l) cl[l] = l < nterm ? c[l] * tot[0][l] : (T)0;
-            for (int32_t k = cg; k < n && chok; k += CG) {
-                T sum = (T)0;
-#pragma unroll
-                for (int l = 0; l < NJ; ++l) sum += cl[l] * sw[l * kExpChunk + k];
-                g[(int64_t)srow[k] * d + ch] = sum;
+                        if (l < nterm) sum += ca[l] * __shfl(wmine[l], src, 64);
+                    if (chok && kk < nk) g[(int64_t)rowk * d + ch] = sum;
+                }
             }
-        } else if (cg == 0 && chok) {
+        } else if (chok && sub == 0) {
 #pragma unroll
             for (int l = 0; l < NJ; ++l) {
-                m0[l] += (double)(sgn * tot[2][l] * tot[0][l]);
-                m1[l] += (double)(sgn * (tot[3][l] * tot[0][l] + tot[2][l] * tot[1][l]));
+                m0[l] += (double)(sgn * acc[2][l] * acc[0][l]);
+                m1[l] += (double)(sgn * (acc[3][l] * acc[0][l] + acc[2][l] * acc[1][l]));
             }
         }
     }
-    if (GRAD) {  // every workgroup writes its row (zeros for partial chunks)
-        double* row = mrow + (mbase + blockIdx.x) * 2 * nterm;
-        for (int l = 0; l < nterm && l < NJ; ++l) {
-            const double t0 = block_sum(m0[l], dred);
-            if (threadIdx.x == 0) row[l] = t0;
-            const double t1 = block_sum(m1[l], dred);
-            if (threadIdx.x == 0) row[nterm + l] = t1;
+    if (GRAD) {
+        // workgroup totals in one pass: wave shuffles, then LDS across waves
+        __shared__ double red[kExpThreads / 64][2 * NJ];
+#pragma unroll
+        for (int l = 0; l < NJ; ++l)
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                m0[l] += __shfl_xor(m0[l], o, 64);
+                m1[l] += __shfl_xor(m1[l], o, 64);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) {
+                red[threadIdx.x >> 6][l] = m0[l];
+                red[threadIdx.x >> 6][NJ + l] = m1[l];
+            }
+        __syncthreads();
+        if ((int32_t)threadIdx.x < 2 * nterm) {
+            const int e = threadIdx.x < nterm ? threadIdx.x : NJ + threadIdx.x - nterm;
+            double t = 0.0;
+            for (int w = 0; w < kExpThreads / 64; ++w) t += red[w][e];
+            mrow[(mbase + blockIdx.x) * 2 * nterm + threadIdx.x] = t;
         }
-    }
-}
-
-// Jobs of several chunks: one workgroup per job sums its chunks' partial
-// slots (jslot[2j] .. jslot[2j] + jslot[2j + 1] - 1, in order) into the
-// first slot; with GRAD it then writes the job's moments (sign jsg[j]) to
-// row mbase + j of mrow.
-template <typename T, int NJ, bool GRAD>
-__global__ void __launch_bounds__(kExpThreads)
-k_expsum_jobsum(int32_t nterm, int32_t d, const int32_t* __restrict__ jslot,
-                const int32_t* __restrict__ jsg, T* __restrict__ part,
-                double* __restrict__ mrow, int64_t mbase) {
-    constexpr int NQ = GRAD ? 4 : 1;
-    __shared__ double dred[kExpThreads / 64];
-    const int64_t first = jslot[2 * blockIdx.x];
-    const int32_t cnt = jslot[2 * blockIdx.x + 1];
-    const double sgn = jsg[blockIdx.x] < 0 ? -1.0 : 1.0;
-    const int64_t per = (int64_t)NQ * nterm * d;
-    for (int64_t e = threadIdx.x; e < per; e += blockDim.x) {
-        T t = part[first * per + e];
-        for (int32_t k = 1; k < cnt; ++k) t += part[(first + k) * per + e];
-        part[first * per + e] = t;
-    }
-    if (!GRAD) return;
-    __syncthreads();
-    const T* P = part + first * per;
-    for (int l = 0; l < nterm && l < NJ; ++l) {
-        double a0 = 0.0, a1 = 0.0;
-        for (int32_t ch = threadIdx.x; ch < d; ch += blockDim.x) {
-            const double A = P[(0 * nterm + l) * d + ch], Ar = P[(1 * nterm + l) * d + ch];
-            const double B = P[(2 * nterm + l) * d + ch], Br = P[(3 * nterm + l) * d + ch];
-            a0 += B * A;
-            a1 += Br * A + B * Ar;
-        }
-        const double t0 = block_sum(a0, dred);
-        if (threadIdx.x == 0) mrow[(mbase + blockIdx.x) * 2 * nterm + l] = sgn * t0;
-        const double t1 = block_sum(a1, dred);
-        if (threadIdx.x == 0) mrow[(mbase + blockIdx.x) * 2 * nterm + nterm + l] = sgn * t1;
-    }
-}
-
-// Table values of the chunks of several-chunk jobs (forward), from the
-// job's summed slot: ck as in k_expsum_chunks, tslot[k] = that slot.
-template <typename T, int NJ>
-__global__ void __launch_bounds__(kExpThreads)
-k_expsum_expand(int32_t nterm, int32_t d, const int32_t* __restrict__ ck,
-                const int32_t* __restrict__ tslot, const int32_t* __restrict__ jc_r,
-                const int32_t* __restrict__ jc_val, const T* __restrict__ c,
-                const T* __restrict__ pw, int32_t K, const T* __restrict__ part,
-                T* __restrict__ g) {
-    const int32_t cb = ck[3 * blockIdx.x + 1], ce = ck[3 * blockIdx.x + 2];
-    const T* P = part + (int64_t)tslot[blockIdx.x] * nterm * d;
-    for (int64_t e = threadIdx.x; e < (int64_t)(ce - cb) * d; e += blockDim.x) {
-        const int32_t i = cb + (int32_t)(e / d), ch = (int32_t)(e % d);
-        const int32_t r = jc_r[i];
-        T sum = (T)0;
-        for (int l = 0; l < nterm && l < NJ; ++l)
-            sum += c[l] * pw[(int64_t)l * K + r] * P[(int64_t)l * d + ch];
-        g[(int64_t)jc_val[i] * d + ch] = sum;
     }
 }
 

@@ -153,17 +153,9 @@ struct tfi_plan {
     DeviceBuf expw[2], exps[2], hleaf;
     // table jobs for the sweep evaluator: ids sorted by size, cell offsets,
     // first scratch position (-1: one backbone position), signs
-    int32_t *d_ejm = nullptr, *d_jsign = nullptr;
+    int32_t *d_ej1 = nullptr, *d_ejm = nullptr, *d_jsign = nullptr;
     int64_t *d_joff = nullptr, *d_jpos = nullptr;
-    int64_t nejm = 0, npos_multi = 0;
-    // one-position jobs in chunks of cells: (job, first, end) per chunk and
-    // its partial slot (-1: the chunk is its whole job); jobs of several
-    // chunks: (first slot, count) and sign; their chunks again with the
-    // job's first slot, for the expansion
-    int32_t *d_ck = nullptr, *d_cslot = nullptr, *d_jslot = nullptr, *d_jsg = nullptr;
-    int32_t *d_ckm = nullptr, *d_tslot = nullptr;
-    int64_t nck = 0, nmcjob = 0, nckm = 0, nslots = 0;
-    DeviceBuf expp[2];  // chunk partial sums
+    int64_t nej1 = 0, nejm = 0, npos_multi = 0;
     DeviceBuf mrows;    // per-workgroup gradient moments (FP64)
 
     // streams, fork/join events, graph cache
@@ -247,7 +239,7 @@ struct tfi_plan {
         for (void* p : mallocs) (void)hipFree(p);
         for (int t = 0; t < 2; ++t)
             for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t],
-                                 &expw[t], &exps[t], &expp[t]})
+                                 &expw[t], &exps[t]})
                 if (b->p) (void)hipFree(b->p);
         if (hleaf.p) (void)hipFree(hleaf.p);
         if (mrows.p) (void)hipFree(mrows.p);
@@ -537,56 +529,14 @@ int upload_static(tfi_plan* h) {
         };
         std::stable_sort(ej1.begin(), ej1.end(), by_size);
         std::stable_sort(ejm.begin(), ejm.end(), by_size);
+        h->nej1 = (int64_t)ej1.size();
         h->nejm = (int64_t)ejm.size();
         h->npos_multi = npos;
+        if ((rc = h->upload(&h->d_ej1, ej1))) return rc;
         if ((rc = h->upload(&h->d_ejm, ejm))) return rc;
-        std::vector<int32_t> ck, cslot, jslot, jsg, ckm, tslot;
-        int32_t nslot = 0;
-        for (int32_t j : ej1) {
-            const int64_t cb = p.job_cell_off[j], ce = p.job_cell_off[j + 1];
-            if (ce > INT32_MAX) return fail(TFI_ERR_STATE, "internal: too many cells");
-            if (ce - cb <= tfi::kExpChunk) {
-                ck.insert(ck.end(), {j, (int32_t)cb, (int32_t)ce});
-                cslot.push_back(-1);
-                continue;
-            }
-            const int32_t first = nslot;
-            int32_t cnt = 0;
-            for (int64_t o = cb; o < ce; o += tfi::kExpChunk, ++cnt) {
-                const int32_t e = (int32_t)std::min<int64_t>(ce, o + tfi::kExpChunk);
-                ck.insert(ck.end(), {j, (int32_t)o, e});
-                cslot.push_back(nslot++);
-                ckm.insert(ckm.end(), {j, (int32_t)o, e});
-                tslot.push_back(first);
-            }
-            jslot.insert(jslot.end(), {first, cnt});
-            jsg.push_back(p.job_sign[j]);
-        }
-        h->nck = (int64_t)cslot.size();
-        h->nmcjob = (int64_t)jsg.size();
-        h->nckm = (int64_t)tslot.size();
-        h->nslots = nslot;
-        if ((rc = h->upload(&h->d_ck, ck))) return rc;
-        if ((rc = h->upload(&h->d_cslot, cslot))) return rc;
-        if ((rc = h->upload(&h->d_jslot, jslot))) return rc;
-        if ((rc = h->upload(&h->d_jsg, jsg))) return rc;
-        if ((rc = h->upload(&h->d_ckm, ckm))) return rc;
-        if ((rc = h->upload(&h->d_tslot, tslot))) return rc;
         if ((rc = h->upload(&h->d_joff, p.job_cell_off))) return rc;
         if ((rc = h->upload(&h->d_jpos, jpos))) return rc;
         if ((rc = h->upload(&h->d_jsign, p.job_sign))) return rc;
-    }
-    // dynamic LDS of the exponential-sum chunk kernels beyond 64 KiB
-    {
-        const int need = tfi::expsum_chunk_lds<double, 16>();
-        if (need > 65536) {
-            if (need > h->lds_max)
-                return fail(TFI_ERR_STATE, "device LDS too small for the sweep evaluator");
-            TFI_HIP(hipFuncSetAttribute((const void*)(tfi::k_expsum_chunks<double, 16, false>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, need));
-            TFI_HIP(hipFuncSetAttribute((const void*)(tfi::k_expsum_chunks<double, 16, true>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, need));
-        }
     }
     // twiddles exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), from long double
     h->lgtw = maxlg;
@@ -1329,11 +1279,11 @@ inline int32_t exp_group(int32_t d) {
     return gs;
 }
 
-// Gradient moment rows: one per workgroup of the chunk, job-sum and
-// multi-position kernels, one per term for the leaf tiles.
+// Gradient moment rows: one per workgroup of the one-position and
+// multi-position job kernels, one per term for the leaf tiles.
 inline int64_t expsum_moment_rows(const tfi_plan* h, int32_t d, int32_t nterm) {
-    const int64_t gpb = tfi::kExpThreads / exp_group(d);
-    return h->nck + h->nmcjob + (h->nejm + gpb - 1) / gpb + nterm;
+    const int64_t gpb = tfi::kExpThreads / exp_group(d), wpb = tfi::kExpThreads / 64;
+    return (h->nej1 + wpb - 1) / wpb + (h->nejm + gpb - 1) / gpb + nterm;
 }
 
 template <typename T>
@@ -1349,9 +1299,6 @@ int prepare_expsum(tfi_plan* h, int32_t nterm, int32_t d, bool bwd, bool grad) {
     const size_t nq = grad ? 5 : 2;
     if (h->npos_multi > 0 &&
         (rc = h->ensure(h->exps[ti], (size_t)h->npos_multi * nq * nterm * d * sizeof(T))))
-        return rc;
-    if (h->nslots > 0 &&
-        (rc = h->ensure(h->expp[ti], (size_t)h->nslots * (grad ? 4 : 1) * nterm * d * sizeof(T))))
         return rc;
     if (bwd && (rc = h->ensure(h->valg[ti], rowbytes))) return rc;
     if (grad && (rc = h->ensure(h->hleaf, (size_t)p.kernel_len * sizeof(double)))) return rc;
@@ -1371,6 +1318,28 @@ void enq_expsum_prep(tfi_plan* h, int32_t nterm, const T* c, const T* lam, hipSt
     hipLaunchKernelGGL(tfi::k_expsum_prep<T>, dim3(blocks_for(K)), dim3(kThreads), 0, st, nterm, c,
                        lam, (int32_t)K, pw, pw + (size_t)nterm * K);
     h->end(st, ev, "expsum_prep", sizeof(T) * (double)(nterm + 1) * K);
+}
+
+template <typename T, bool GRAD>
+void launch_expsum_wave(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
+                        const T* valg, T* g, double* mrow, int64_t& mbase, hipStream_t st) {
+    const int64_t nj = h->nej1;
+    if (nj == 0) return;
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const int32_t gs = exp_group(d), wpb = tfi::kExpThreads / 64;  // one job per wavefront
+    const unsigned blocks = (unsigned)((nj + wpb - 1) / wpb);
+    const T* pw = (const T*)h->expw[ti].p;
+    auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(blocks), dim3(tfi::kExpThreads), 0, st, nterm, d, gs,
+                           (int32_t)nj, h->d_ej1, h->d_joff, h->d_jsign, h->d_jc_r, h->d_jc_val, c,
+                           pw, (int32_t)h->plan.kernel_len, val, valg, g, mrow, mbase);
+    };
+    if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD>);
+    else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD>);
+    else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD>);
+    else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD>);
+    else launch(tfi::k_expsum_wave<T, 16, GRAD>);
+    mbase += blocks;
 }
 
 template <typename T, bool GRAD>
@@ -1397,55 +1366,17 @@ void launch_expsum_multi(tfi_plan* h, int32_t nterm, const T* c, int32_t d, cons
     mbase += blocks;
 }
 
-// One-position jobs: chunk sums (finishing single-chunk jobs), then the
-// jobs of several chunks.
-template <typename T, int NJ, bool GRAD>
-void launch_expsum_chunks_nj(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
-                             const T* valg, T* g, double* mrow, int64_t& mbase,
-                             hipStream_t st) {
-    const int ti = sizeof(T) == 8 ? 1 : 0;
-    const T* pw = (const T*)h->expw[ti].p;
-    T* part = (T*)h->expp[ti].p;
-    const int32_t K = (int32_t)h->plan.kernel_len;
-    const unsigned lds = (unsigned)tfi::expsum_chunk_lds<T, NJ>();
-    hipLaunchKernelGGL((tfi::k_expsum_chunks<T, NJ, GRAD>), dim3((unsigned)h->nck),
-                       dim3(tfi::kExpThreads), lds, st, nterm,
-                       d, exp_group(d), h->d_ck, h->d_cslot, h->d_jsign, h->d_jc_r, h->d_jc_val, c,
-                       pw, K, val, valg, g, part, mrow, mbase);
-    mbase += h->nck;
-    if (h->nmcjob == 0) return;
-    hipLaunchKernelGGL((tfi::k_expsum_jobsum<T, NJ, GRAD>), dim3((unsigned)h->nmcjob),
-                       dim3(tfi::kExpThreads), 0, st, nterm, d, h->d_jslot, h->d_jsg, part, mrow,
-                       mbase);
-    mbase += h->nmcjob;
-    if (!GRAD)
-        hipLaunchKernelGGL((tfi::k_expsum_expand<T, NJ>), dim3((unsigned)h->nckm),
-                           dim3(tfi::kExpThreads), 0, st, nterm, d, h->d_ckm, h->d_tslot,
-                           h->d_jc_r, h->d_jc_val, c, pw, K, (const T*)part, g);
-}
-
-template <typename T, bool GRAD>
-void launch_expsum_chunks(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
-                          const T* valg, T* g, double* mrow, int64_t& mb, hipStream_t st) {
-    if (h->nck == 0) return;
-    if (nterm <= 1) launch_expsum_chunks_nj<T, 1, GRAD>(h, nterm, c, d, val, valg, g, mrow, mb, st);
-    else if (nterm <= 2) launch_expsum_chunks_nj<T, 2, GRAD>(h, nterm, c, d, val, valg, g, mrow, mb, st);
-    else if (nterm <= 4) launch_expsum_chunks_nj<T, 4, GRAD>(h, nterm, c, d, val, valg, g, mrow, mb, st);
-    else if (nterm <= 8) launch_expsum_chunks_nj<T, 8, GRAD>(h, nterm, c, d, val, valg, g, mrow, mb, st);
-    else launch_expsum_chunks_nj<T, 16, GRAD>(h, nterm, c, d, val, valg, g, mrow, mb, st);
-}
-
 // Table values (forward) or gradient moment rows (leaf rows excluded) of
-// every table job: one-position jobs in chunks, then the jobs with several
-// backbone positions.
+// every table job: one-position jobs (a wavefront each), then the jobs with
+// several backbone positions.
 template <typename T, bool GRAD>
 void enq_expsum_jobs(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
                      const T* valg, T* g, double* mrow, hipStream_t st) {
-    if (h->nck + h->nejm == 0) return;
+    if (h->nej1 + h->nejm == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
     int64_t mbase = 0;
-    launch_expsum_chunks<T, GRAD>(h, nterm, c, d, val, valg, g, mrow, mbase, st);
+    launch_expsum_wave<T, GRAD>(h, nterm, c, d, val, valg, g, mrow, mbase, st);
     launch_expsum_multi<T, GRAD>(h, nterm, c, d, val, valg, g, mrow, mbase, st);
     const double cells = (double)p.jc_r.size();
     h->end(st, ev, GRAD ? "expsum_grad" : "expsum",
