@@ -35,7 +35,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "tfi.hip", "plan.cpp", "plan.hpp"]
+LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "kernels_conv1d.hpp", "tfi.hip", "plan.cpp", "plan.hpp"]
 
 
 def measured_traffic(workload, stage):
@@ -99,6 +99,10 @@ def main():
                     help="use this direct/FFT cost constant instead of tuning it")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched forest forward+backward measurement")
+    ap.add_argument("--no-wide", action="store_true",
+                    help="skip the wide-channel (C = 4160) patch-grid measurement")
+    ap.add_argument("--wide-only", action="store_true",
+                    help="run only the wide-channel measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -114,6 +118,9 @@ def main():
     from paper_2609_34025_amd import TreeIntegrator, synth as S
 
     dev = torch.device("cuda", 0)
+    if args.wide_only:
+        print(json.dumps({"wide_channel": wide_channel(args)}), flush=True)
+        return
     W = S.workload("rrt100k")
     p, w, F = W["parent"], W["weight"], W["F"]
     N, d = F.shape
@@ -231,6 +238,7 @@ def main():
         log(f"bench: oracle {cpu['value']:.3e} vertex*channels/s on {cores} threads")
 
     batched = None if args.no_batched else batched_fwd_bwd(args, value)
+    wide = None if args.no_wide else wide_channel(args)
 
     rec = {
         "metric": METRIC, "value": value, "unit": "vertex*channels/s", "n_gpus": 1,
@@ -249,6 +257,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
+        "wide_channel": wide,
         "stages": stages,
     }
     print(json.dumps(rec), flush=True)
@@ -384,6 +393,90 @@ def batched_fwd_bwd(args, plain_value):
                            "fft_cost": cost, "parity": results["table"]["parity"],
                            "roofline": results["table"]["roofline"],
                            "stages": results["table"]["stages"]}}
+
+
+
+# The paper's 32-core CPU timings of one integration at C = 4160 (seconds;
+# tables "vit-runtime" and "vit-crossover"), quoted as context only.
+PAPER_CPU_S = {("serpentine", 1024): 0.39, ("serpentine", 4096): 1.76,
+               ("serpentine", 16384): 8.02, ("serpentine", 65536): 37.82,
+               ("serpentine", 262144): 165.67, ("random", 65536): 121.4,
+               ("comb", 65536): 231.1, ("fishbone", 65536): 91.4}
+
+
+def wide_channel(args):
+    """Masked-linear-attention payload (C = 4160 channels) on patch-grid
+    spanning trees: serpentine paths from a 32x32 to a 512x512 grid, and the
+    random, comb and fishbone trees at 256x256. FP32 forward, graph replay,
+    parity on sampled rows x channels against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+
+    dev = torch.device("cuda", 0)
+    cases = [("serpentine", s) for s in (32, 64, 128, 256, 384, 512)]
+    cases += [("random", 256), ("comb", 256), ("fishbone", 256)]
+    out_cases = []
+    roofline = None
+    for kind, side in cases:
+        W = S.workload("attn", tree=kind, side=side)
+        p, w = W["parent"], W["weight"]
+        n, C = len(p), W["d"]
+        t0 = time.perf_counter()
+        tfi = TreeIntegrator(p, w, device=0)
+        build_s = time.perf_counter() - t0
+        K = tfi.kernel_length
+        tab = W["kernels"][0][1](K)
+        f = torch.tensor(tab, dtype=torch.float32, device=dev)
+        phi = torch.from_numpy(W["phi"]).to(dev)
+        v = torch.from_numpy(W["v"]).to(dev)
+        # payload [phi v^T | phi] built on the device (input preparation)
+        F = torch.cat([(phi[:, :, None] * v[:, None, :]).reshape(n, -1), phi], 1).contiguous()
+        del phi, v
+        cost = tfi.autotune(f, C)
+        reps = 3 if n >= 100000 else 5
+        for _ in range(2):
+            y = tfi.integrate(f, F)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            y = tfi.integrate(f, F)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        tfi.profile(True)
+        tfi.integrate(f, F)
+        torch.cuda.synchronize()
+        tfi.profile(False)
+        stages = tfi.profile_report()
+        rng = np.random.default_rng(side)
+        rows = np.sort(rng.choice(n, 32, replace=False))
+        chans = np.sort(rng.choice(C, 64, replace=False))
+        Fs = F[:, chans].double().cpu().numpy()
+        ref = oracle.integrate(p, w, tab, Fs, rows=rows)
+        got = y[rows][:, chans].double().cpu().numpy()
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        rec = {"tree": kind, "side": side, "N": n, "C": C, "ms": round(ms, 4),
+               "value": n * C / (ms * 1e-3), "build_s": round(build_s, 3),
+               "fft_cost": cost, "rel_err": err, "ok": err <= 1e-4,
+               "stages_ms": {k: round(v["ms"], 4) for k, v in stages.items()}}
+        if (kind, n) in PAPER_CPU_S:
+            rec["paper_cpu_s"] = PAPER_CPU_S[(kind, n)]
+        out_cases.append(rec)
+        log(f"wide[{kind} {side}x{side}] N={n} C={C}: {ms:.3f} ms/integration "
+            f"({rec['value']:.3e} vertex*channels/s), parity {err:.2e}")
+        if kind == "serpentine" and side == 512:
+            dom = max(stages, key=lambda k: stages[k]["ms"])
+            roofline = stage_roofline(dom, stages[dom], "f32", "serpentine512")
+        del tfi, F, y
+        torch.cuda.empty_cache()
+    return {"unit": "vertex*channels/s (forward, one integration)", "dtype": "f32",
+            "payload": "x_j = [vec(phi_j v_j^T) | phi_j], r = dh = 64, C = 4160; "
+                       "mask f = exp(u d^2 + v d + w), u=-1e-5, v=-0.01, w=0.5",
+            "parity": "32 sampled rows x 64 sampled channels vs FP64 oracle",
+            "paper_cpu_s": "32-core CPU, context only",
+            "cases": out_cases, "roofline": roofline}
 
 
 if __name__ == "__main__":

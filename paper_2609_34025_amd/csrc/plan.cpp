@@ -288,7 +288,7 @@ void Planner::emit_leaf(const std::vector<int32_t>& S0) {
         for (int32_t u : order) {
             plan.leaf_D[base + i * n + loc[u]] = (int32_t)dist[u];
             plan.kernel_len = std::max(plan.kernel_len, dist[u] + 1);
-            plan.diameter = std::max(plan.diameter, dist[u]);
+            plan.max_backbone = std::max(plan.max_backbone, dist[u]);
         }
     }
     plan.leaf_doff.push_back((int64_t)plan.leaf_D.size());
@@ -359,7 +359,7 @@ void Planner::emit_table(const Decomp& D, int32_t level) {
     }
     plan.incidences += (int64_t)recs.size();
     plan.sum_M += (D.H + 1) * (D.X + 1);
-    plan.diameter = std::max(plan.diameter, D.X);
+    plan.max_backbone = std::max(plan.max_backbone, D.X);
 }
 
 int Planner::run(const std::vector<int32_t>& roots, std::string& err) {
@@ -627,7 +627,7 @@ std::string plan_stats_json(const Plan& p) {
       << ",\"correction_jobs\":" << corrjobs
       << ",\"direct_jobs\":" << direct << ",\"direct_pairs\":" << direct_pairs
       << ",\"fft_jobs\":" << fft
-      << ",\"kernel_length\":" << p.kernel_len << ",\"diameter\":" << p.diameter
+      << ",\"kernel_length\":" << p.kernel_len << ",\"max_backbone\":" << p.max_backbone
       << ",\"root\":{\"m\":" << p.root_m << ",\"X\":" << p.root_X
       << ",\"H\":" << p.root_H << ",\"choice\":\""
       << (p.root_choice == 1 ? "centroid" : p.root_choice == 0 ? "diameter" : "leaf")

@@ -28,6 +28,7 @@
 #include "../../include/tfi.h"
 #include "kernels.hpp"
 #include "kernels_expsum.hpp"
+#include "kernels_conv1d.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -63,6 +64,11 @@ struct Bucket {
     std::vector<int32_t> hx;    // pairs (H, X) per job
     int32_t* d_jobs = nullptr;
     int32_t* d_hx = nullptr;
+    // 1-D buckets (lg1 = 0) beyond LDS: per job, the source row of the cell
+    // at each backbone coordinate x <= xmax, or -1 (stride mstride = xmax+1)
+    int32_t* d_map = nullptr;
+    int32_t* d_vmap = nullptr;  // the same with the cell's vertex (whole-path plans)
+    int64_t mstride = 0;
     int64_t spec_off = 0;       // element offset into the spectrum arena
     int64_t cells = 0;          // table cells over the bucket's jobs
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
@@ -136,6 +142,11 @@ struct tfi_plan {
     int64_t* d_lgk = nullptr;
     int32_t* d_lbin = nullptr;  // per leaf group: bound of its distances
     int64_t nlgrp = 0;
+    // per dtype: every job is a 1-D job beyond LDS whose cells are single
+    // vertices held by no other call, with no corrections and no leaf tiles
+    // (e.g. a forest of paths, each its own backbone); the convolution kernels
+    // then read the field and write the output directly
+    bool path_mode[2] = {false, false};
     int64_t gather_reads = 0;  // table values read by the gather
     int32_t *d_leaf_v = nullptr, *d_leaf_D = nullptr;
     std::vector<Bucket> buckets;
@@ -297,6 +308,7 @@ struct tfi_plan {
         buckets.clear();
         for (int t = 0; t < 2; ++t) {
             global_b[t].clear();
+            path_mode[t] = false;
             for (int k = 0; k < 3; ++k) tiers[t][k] = Tier();
         }
         ndirect = ndblk = 0;
@@ -338,6 +350,9 @@ int check_handle(tfi_handle h, bool need_device) {
     }
     return TFI_OK;
 }
+
+template <typename T>
+int conv1d_lds_optin(int lds);
 
 int upload_static(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
@@ -499,6 +514,9 @@ int upload_static(tfi_plan* h) {
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
         TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+        int rc1 = conv1d_lds_optin<float>(lds);
+        if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
+        if (rc1) return rc1;
     }
     // sweep evaluator job lists (exponential-sum kernels)
     {
@@ -567,6 +585,45 @@ int upload_static(tfi_plan* h) {
 
 // Device structures that depend on the per-job method (direct blocks, FFT
 // buckets and their LDS tiers); rebuilt when the methods are re-assigned.
+// LDS beyond 64 KiB for the 1-D convolution kernels of every channel tile.
+template <typename T, int TC>
+int conv1d_lds_optin_tc(int lds) {
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    return TFI_OK;
+}
+
+template <typename T>
+int conv1d_lds_optin(int lds) {
+    int rc = conv1d_lds_optin_tc<T, 16>(lds);
+    if (!rc) rc = conv1d_lds_optin_tc<T, 8>(lds);
+    if (!rc) rc = conv1d_lds_optin_tc<T, 4>(lds);
+    if (!rc) rc = conv1d_lds_optin_tc<T, 2>(lds);
+    if (!rc) rc = conv1d_lds_optin_tc<T, 1>(lds);
+    return rc;
+}
+
+// Plan shape of whole-path mode: no leaf tiles, every vertex in exactly one
+// b-cell of one incidence, no corrections, every A-cell one b-cell, and every
+// job a call job of one row (H = 0) evaluated by FFT.
+bool whole_path_plan(const tfi::Plan& p) {
+    if (p.leaf_off.size() > 1 || p.NB != p.N || p.NA != p.NB) return false;
+    for (int64_t v = 0; v < p.N; ++v)
+        if (p.v_off[v + 1] - p.v_off[v] != 1) return false;
+    for (int64_t b = 0; b < p.NB; ++b)
+        if (p.b_corr[b] || p.b_inc_off[b + 1] - p.b_inc_off[b] != 1) return false;
+    for (int64_t a = 0; a < p.NA; ++a)
+        if (p.a_b_off[a + 1] - p.a_b_off[a] != 1) return false;
+    for (size_t j = 0; j < p.job_sign.size(); ++j)
+        if (p.job_sign[j] != 1 || p.job_lg1[j] != 0 || p.job_method[j] != tfi::METHOD_FFT)
+            return false;
+    return true;
+}
+
 int upload_methods(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
@@ -704,6 +761,40 @@ int upload_methods(tfi_plan* h) {
             T.bytes_fixed += 12.0 * (double)b.cells;
             T.spec_bytes += 2.0 * (double)b.P();
         }
+        for (int bi : h->global_b[ti]) {
+            Bucket& b = h->buckets[bi];
+            if (b.lg1 != 0 || b.d_map) continue;
+            std::vector<int32_t> map((size_t)b.njobs() * (b.xmax + 1), -1);
+            bool ok = true;
+            for (int64_t j = 0; j < b.njobs() && ok; ++j)
+                for (int32_t k = b.jobs[2 * j]; k < b.jobs[2 * j + 1]; ++k) {
+                    if (p.jc_r[k] != 0 || p.jc_x[k] < 0 || p.jc_x[k] > b.xmax) {
+                        ok = false;
+                        break;
+                    }
+                    map[(size_t)j * (b.xmax + 1) + p.jc_x[k]] = p.jc_val[k];
+                }
+            if (!ok) continue;
+            if ((rc = h->upload_m(&b.d_map, map))) return rc;
+            b.mstride = b.xmax + 1;
+        }
+        h->path_mode[ti] = fj[0].empty() && fj[1].empty() && fj[2].empty() &&
+                           h->ndirect == 0 && whole_path_plan(p);
+        for (int bi : h->global_b[ti])
+            if (!h->buckets[bi].d_map) h->path_mode[ti] = false;
+        if (h->path_mode[ti])
+            for (int bi : h->global_b[ti]) {
+                Bucket& b = h->buckets[bi];
+                if (b.d_vmap) continue;
+                std::vector<int32_t> vmap((size_t)b.njobs() * b.mstride, -1);
+                for (int64_t j = 0; j < b.njobs(); ++j)
+                    for (int32_t k = b.jobs[2 * j]; k < b.jobs[2 * j + 1]; ++k) {
+                        const int32_t a = p.jc_val[k];
+                        vmap[(size_t)j * b.mstride + p.jc_x[k]] =
+                            p.inc_v[p.b_inc_off[p.a_b_off[a]]];
+                    }
+                if ((rc = h->upload_m(&b.d_vmap, vmap))) return rc;
+            }
         for (int t = 0; t < 3; ++t) {
             Tier& T = h->tiers[ti][t];
             T.nbuckets = (int64_t)bo[t].size();
@@ -805,6 +896,98 @@ void launch_fft2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::
     }
 }
 
+// Shape of the 1-D convolution kernels for a bucket: TC channel pairs per
+// slot point and the split lg = lgH + lgL of the point index. TC starts at
+// one 128-byte line per point (the high-bit passes read and write points
+// 2^lgL apart, and a partial line would be fetched once per workgroup that
+// reads a part of it); the strided high-bit blocks (2^lgH points x TC) stay
+// within 64 KiB of LDS, the contiguous low-bit blocks within 128 KiB, and
+// both within 2^10 points. Returns 0 when the bucket takes the blocked 2-D
+// passes instead.
+template <typename T>
+int conv1d_tc(const Bucket& b, int32_t d, int* lgL_out = nullptr) {
+    if (b.lg1 != 0 || !b.d_map || b.lg2 < 2 || b.lg2 > 20) return 0;
+    const int lg = b.lg2;
+    const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
+    const int64_t npairs = (d + 1) / 2;
+    int tc = (int)(128 / cs);
+    while (tc > 1 && tc / 2 >= npairs) tc >>= 1;
+    for (; tc >= 1; tc >>= 1) {
+        int lgH = lg - lg / 2;
+        while (lgH > 1 && ((int64_t)1 << lgH) * tc * cs > 65536) --lgH;
+        const int lgL = lg - lgH;
+        if (lgH > 10 || lgL > 10 || ((int64_t)1 << lgL) * tc * cs > 131072) continue;
+        if ((npairs + tc - 1) / tc > 65535) return 0;
+        if (lgL_out) *lgL_out = lgL;
+        return tc;
+    }
+    return 0;
+}
+
+// Bytes of one job's slots in the FFT work buffer.
+template <typename T>
+int64_t fft_job_bytes(const Bucket& b, int32_t d) {
+    const int64_t npairs = (d + 1) / 2;
+    const int tc = conv1d_tc<T>(b, d);
+    const int64_t pairs = tc ? (npairs + tc - 1) / tc * tc : npairs;
+    return pairs * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+}
+
+template <typename T, int TC>
+void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t d, const T* val,
+                      T* g, const tfi::cpx<T>* spec, const tfi::cpx<T>* tw, tfi::cpx<T>* buf,
+                      size_t buf_bytes, hipStream_t st) {
+    int lgL = 0;
+    (void)conv1d_tc<T>(b, d, &lgL);
+    const int lg = b.lg2, lgH = lg - lgL;
+    const int32_t ntiles = ((d + 1) / 2 + TC - 1) / TC;
+    const int64_t job_bytes = (int64_t)ntiles * TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+    const int64_t jpc =
+        std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)buf_bytes / job_bytes));
+    // LDS block: 2^RA rows of (2^RB x TC + pad) complex; 2^RB x TC threads
+    const int hRB = lgH / 2, hRA = lgH - hRB, lRB = lgL / 2, lRA = lgL - lRB;
+    const unsigned lds_hi = (unsigned)(((int64_t)1 << hRA) * ((TC << hRB) + tfi::kC1Pad) *
+                                       sizeof(tfi::cpx<T>));
+    const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((TC << lRB) + tfi::kC1Pad) *
+                                       sizeof(tfi::cpx<T>));
+    const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(TC << lRB);
+    for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
+        const int64_t nj = std::min(jpc, b.njobs() - j0);
+        const int32_t* map = bmap + j0 * b.mstride;
+        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, false>),
+                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
+                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
+                           tw, h->lgtw);
+        hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC>),
+                           dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
+                           lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
+        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, true>),
+                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
+                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g,
+                           buf, tw, h->lgtw);
+    }
+}
+
+// src rows -> dst rows through bmap (b.d_map: value and table rows;
+// b.d_vmap: field and output rows).
+template <typename T>
+void launch_conv1d(tfi_plan* h, int tc, const Bucket& b, const int32_t* bmap, int32_t d,
+                   const T* src, T* dst, const tfi::cpx<T>* spec, const tfi::cpx<T>* tw,
+                   tfi::cpx<T>* buf, size_t buf_bytes, hipStream_t st) {
+    switch (tc) {
+#define TFI_C1(TCV)                                                                         \
+    case TCV:                                                                               \
+        launch_conv1d_tc<T, TCV>(h, b, bmap, d, src, dst, spec, tw, buf, buf_bytes, st);    \
+        break;
+        TFI_C1(16)
+        TFI_C1(8)
+        TFI_C1(4)
+        TFI_C1(2)
+#undef TFI_C1
+        default: launch_conv1d_tc<T, 1>(h, b, bmap, d, src, dst, spec, tw, buf, buf_bytes, st);
+    }
+}
+
 // Global-memory FFT passes of one bucket (tables beyond LDS): forward
 // transform of (job, channel pair) slots, product with the spectrum,
 // inverse, read-back.
@@ -812,6 +995,10 @@ template <typename T>
 void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T* g,
                        const tfi::cpx<T>* spec, const tfi::cpx<T>* tw, tfi::cpx<T>* buf,
                        size_t buf_bytes, hipStream_t st) {
+    if (const int tc = conv1d_tc<T>(b, d)) {
+        launch_conv1d<T>(h, tc, b, b.d_map, d, val, g, spec, tw, buf, buf_bytes, st);
+        return;
+    }
     const int32_t npairs = (d + 1) / 2;
     const int64_t slots_cap =
         std::min<int64_t>(65535, (int64_t)(buf_bytes / sizeof(tfi::cpx<T>)) / b.P());
@@ -836,25 +1023,39 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
     }
 }
 
+// Whole-path mode applies to this dtype and channel count.
 template <typename T>
-int prepare_forward(tfi_plan* h, int32_t d) {
+bool path_direct(const tfi_plan* h, int32_t d) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    if (!h->path_mode[ti] || h->global_b[ti].empty()) return false;
+    for (int bi : h->global_b[ti])
+        if (!conv1d_tc<T>(h->buckets[bi], d) || !h->buckets[bi].d_vmap) return false;
+    return true;
+}
+
+// Scratch of a forward (or of dF); `general` asks for the value and table
+// rows even where whole-path mode would not use them.
+template <typename T>
+int prepare_forward(tfi_plan* h, int32_t d, bool general = false) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
     int rc;
-    if ((rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
+    const bool rows = general || !path_direct<T>(h, d);
+    if (rows &&
+        (rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
         return rc;
-    if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
+    if (rows &&
+        (rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
         return rc;
     if ((rc = h->ensure(h->spec[ti],
                         (size_t)std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>))))
         return rc;
-    // workspace for buckets beyond LDS: chunks of at most 2 GiB (and 65535
-    // job-channel-pair slots)
-    const int32_t npairs = (d + 1) / 2;
+    // workspace for buckets beyond LDS: chunks of at most 2 GiB, or one
+    // job's slots when a job alone is larger
     size_t want = 0;
     for (int bi : h->global_b[ti]) {
         const Bucket& b = h->buckets[bi];
-        const size_t one_job = (size_t)b.P() * npairs * sizeof(tfi::cpx<T>);
+        const size_t one_job = (size_t)fft_job_bytes<T>(b, d);
         const size_t all = one_job * (size_t)b.njobs();
         want = std::max(want, std::max(one_job, std::min(all, (size_t)2 << 30)));
     }
@@ -922,7 +1123,7 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st) {
         hipEvent_t ev = h->begin(st);
         launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)h->fftbuf[ti].p,
                              h->fftbuf[ti].bytes, st);
-        h->end(st, ev, "fft_global",
+        h->end(st, ev, conv1d_tc<T>(b, d) ? "fft_conv1d" : "fft_global",
                2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
     }
 }
@@ -1094,9 +1295,32 @@ inline void fork3(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
 }
 
 // Enqueue out = f(D) F: `s0` is the main stream, s1/s2 the side streams.
+// Whole-path mode: kernel spectra, then the convolution of every job from the
+// field rows straight into the output rows.
+template <typename T>
+void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    enq_spectra<T>(h, f, st);
+    const tfi::cpx<T>* spec = (const tfi::cpx<T>*)h->spec[ti].p;
+    const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
+    const double sz = (double)sizeof(T);
+    for (int bi : h->global_b[ti]) {
+        const Bucket& b = h->buckets[bi];
+        hipEvent_t ev = h->begin(st);
+        launch_conv1d<T>(h, conv1d_tc<T>(b, d), b, b.d_vmap, d, F, out, spec, tw,
+                         (tfi::cpx<T>*)h->fftbuf[ti].p, h->fftbuf[ti].bytes, st);
+        h->end(st, ev, "fft_conv1d_path",
+               2.0 * sz * d * (double)b.cells + 4.0 * b.cells + 2.0 * sz * b.P());
+    }
+}
+
 template <typename T>
 void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
                      hipStream_t s1, hipStream_t s2) {
+    if (path_direct<T>(h, d)) {
+        enqueue_path<T>(h, f, F, d, out, s0);
+        return;
+    }
     const int ti = sizeof(T) == 8 ? 1 : 0;
     T* val = (T*)h->val[ti].p;
     T* g = (T*)h->g[ti].p;
@@ -1121,6 +1345,10 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
 template <typename T>
 void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
                       double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    if (!df && path_direct<T>(h, d)) {
+        if (dF) enqueue_path<T>(h, f, gout, d, dF, s0);
+        return;
+    }
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
     T* val = (T*)h->val[ti].p;
@@ -1154,8 +1382,9 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
 
 template <typename T>
 int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
-    int rc = prepare_forward<T>(h, d);
+    int rc = prepare_forward<T>(h, d, need_df);
     if (rc) return rc;
+    if (!need_df && path_direct<T>(h, d)) return TFI_OK;
     const int ti = sizeof(T) == 8 ? 1 : 0;
     const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
     if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;

@@ -31,6 +31,8 @@ __all__ = [
     "comb", "broom", "double_broom", "spider",
     "random_recursive", "random_mst_topology", "preferential_attachment",
     "binary_random_recursive", "grid_mst", "sphere_knn_mst",
+    "patch_grid_tree", "attention_features", "attention_payload",
+    "topo_mask_table",
     "uniform_weights", "normal_field", "dirichlet_field",
     "exp_table", "inv_sq_table", "inv_table", "expsum_table", "ones_table",
     "workload",
@@ -313,6 +315,118 @@ def grid_mst(side, wmax, rng):
     return edges_to_parent(n, r, c, tw)
 
 
+# ------------------------------------------ patch-grid spanning trees --
+
+def _hilbert_order(s):
+    """Grid cells ``(row, col)`` of an ``s x s`` grid (``s`` a power of
+    two) in Hilbert-curve order, as row-major ids."""
+    n = s * s
+    t = np.arange(n, dtype=np.int64)
+    x = np.zeros(n, dtype=np.int64)
+    y = np.zeros(n, dtype=np.int64)
+    q = 1
+    while q < s:
+        rx = 1 & (t // 2)
+        ry = 1 & (t ^ rx)
+        flip = ry == 0
+        swap_x = np.where(flip & (rx == 1), q - 1 - x, x)
+        swap_y = np.where(flip & (rx == 1), q - 1 - y, y)
+        x, y = np.where(flip, swap_y, swap_x), np.where(flip, swap_x, swap_y)
+        x = x + q * rx
+        y = y + q * ry
+        t = t // 4
+        q *= 2
+    return y * s + x
+
+
+def patch_grid_tree(kind, side, rng=None):
+    """Spanning tree of the unit-weight ``side x side`` 4-neighbour patch
+    grid, vertices numbered row-major (vertex ``i*side + j`` is patch
+    ``(i, j)``), as in the tree sweep of the paper's vision-transformer
+    appendix (subsection "Tree families"):
+
+    ``serpentine``  row-major boustrophedon Hamiltonian path;
+    ``hilbert``     Hilbert-curve Hamiltonian path (``side`` a power of 2);
+    ``comb``        spine on row 0, a full-height tooth below every column;
+    ``fishbone``    spine on the central row ``side // 2``, ribs up and down
+                    every column;
+    ``random``      Kruskal spanning tree with i.i.d. uniform edge keys
+                    (``rng`` required).
+    """
+    s = int(side)
+    n = s * s
+    idx = np.arange(n, dtype=np.int64).reshape(s, s)
+    if kind in ("serpentine", "hilbert"):
+        if kind == "serpentine":
+            rows = idx.copy()
+            rows[1::2] = rows[1::2, ::-1]
+            order = rows.ravel()
+        else:
+            if s & (s - 1):
+                raise ValueError("hilbert needs a power-of-two side")
+            order = _hilbert_order(s)
+        p = np.empty(n, dtype=np.int64)
+        p[order[0]] = -1
+        p[order[1:]] = order[:-1]
+        return p, _unit(p)
+    if kind == "comb":
+        p = np.empty((s, s), dtype=np.int64)
+        p[0, 0] = -1
+        p[0, 1:] = idx[0, :-1]
+        p[1:, :] = idx[:-1, :]
+        p = p.ravel()
+        return p, _unit(p)
+    if kind == "fishbone":
+        c = s // 2
+        p = np.empty((s, s), dtype=np.int64)
+        p[c, 0] = -1
+        p[c, 1:] = idx[c, :-1]
+        p[:c, :] = idx[1:c + 1, :]
+        p[c + 1:, :] = idx[c:-1, :]
+        p = p.ravel()
+        return p, _unit(p)
+    if kind == "random":
+        if rng is None:
+            raise ValueError("random needs an rng")
+        right_u = idx[:, :-1].ravel()
+        right_v = idx[:, 1:].ravel()
+        down_u = idx[:-1, :].ravel()
+        down_v = idx[1:, :].ravel()
+        us = np.concatenate([right_u, down_u])
+        vs = np.concatenate([right_v, down_v])
+        key = rng.random(len(us)) + 1e-12
+        r, c = _mst_edges(n, us, vs, key)
+        return edges_to_parent(n, r, c)
+    raise KeyError(kind)
+
+
+def attention_features(n, r, dh, rng):
+    """Per-token positive random features ``phi[n x r]`` (log-normal,
+    unit mean) and values ``v[n x dh]`` ~ N(0,1), both FP32."""
+    phi = np.exp(0.5 * rng.standard_normal((n, r)) - 0.125).astype(np.float32)
+    v = rng.standard_normal((n, dh)).astype(np.float32)
+    return phi, v
+
+
+def attention_payload(phi, v):
+    """Stacked masked-linear-attention payload of the paper's reduction
+    (appendix "Masked linear attention as tree-field integration"):
+    ``x_j = [vec(phi_j v_j^T) | phi_j]`` with ``C = r*(dh+1)`` channels,
+    channel ``a*dh + b`` holding ``phi_j[a] v_j[b]`` and channel
+    ``r*dh + a`` holding ``phi_j[a]``."""
+    phi = np.asarray(phi)
+    v = np.asarray(v)
+    n, r = phi.shape
+    outer = (phi[:, :, None] * v[:, None, :]).reshape(n, -1)
+    return np.concatenate([outer, phi], axis=1)
+
+
+def topo_mask_table(length, u, v, w):
+    """Topological mask ``f(k) = exp(u k^2 + v k + w)`` on the lattice."""
+    k = np.arange(length, dtype=np.float64)
+    return np.exp(u * k * k + v * k + w)
+
+
 def sphere_knn_mst(n, k, bins_per_unit, rng):
     """``n`` points uniform on the unit sphere, symmetrised k-NN graph,
     Euclidean MST (components joined by their shortest connecting edge),
@@ -440,6 +554,12 @@ def workload(name, seed=None, **kw):
                 f = exp(-d/3.2) in lattice units, Dirichlet(1) marginals.
     ``cater2m`` / ``binary2m`` N=2e6 caterpillar / binary random recursive
                 tree, weights U{1..8}, F[N x 32] FP32, f = exp(-0.01 d).
+    ``attn``    masked linear attention on a ``side x side`` patch grid
+                (``tree`` = serpentine, hilbert, comb, fishbone or random;
+                default serpentine, side 256), unit weights, features
+                phi[N x 64] and values v[N x 64] (payload C = 4160 channels,
+                built by ``attention_payload``), mask
+                f = exp(u d^2 + v d + w) with u = -1e-5, v = -0.01, w = 0.5.
 
     Returns a dict with ``parent``, ``weight``, ``F`` and workload metadata;
     kernel tables are built by the caller once the required table length is
@@ -495,4 +615,16 @@ def workload(name, seed=None, **kw):
         F = normal_field(len(p), kw.get("d", 32), rng, np.float32)
         return dict(parent=p, weight=w, F=F, dtype="f32",
                     kernels=[("exp0.01", lambda L: exp_table(L, 0.01))])
+    if name == "attn":
+        rng = np.random.default_rng(6 if seed is None else seed)
+        side = kw.get("side", 256)
+        kind = kw.get("tree", "serpentine")
+        p, w = patch_grid_tree(kind, side, rng)
+        r = kw.get("r", 64)
+        dh = kw.get("dh", 64)
+        phi, v = attention_features(len(p), r, dh, rng)
+        mask = (-1e-5, -0.01, 0.5)
+        return dict(parent=p, weight=w, phi=phi, v=v, dtype="f32", mask=mask,
+                    d=r * (dh + 1), tree=kind, side=side,
+                    kernels=[("topo", lambda L: topo_mask_table(L, *mask))])
     raise KeyError(name)
