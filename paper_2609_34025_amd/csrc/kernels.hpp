@@ -84,18 +84,34 @@ __device__ __forceinline__ void fma4(vec4<T>& a, T s, vec4<T> b) {
 // Rows are taken kSegBatch at a time: all their row indices are loaded,
 // then all their values, so a batch waits for memory twice however long it
 // is (the additions keep the order of the rows).
+// Wide rows go in column tiles of ct VEC-groups, the tile index slowest:
+// every segment's slice of one tile is summed before the next tile starts,
+// so the rows read again by later segments are still in cache (ct = d/VEC
+// is one tile, the whole row).
 constexpr int kSegBatch = 8;
 
+// Thread -> (row index, first channel) under column tiling; false when the
+// thread is past the end.
+template <int VEC>
+__device__ __forceinline__ bool tile_coords(int64_t tid, int64_t nrows, int32_t d, int32_t ct,
+                                            int64_t& r, int32_t& c) {
+    const int64_t per_tile = nrows * ct;
+    const int64_t tile = tid / per_tile;
+    const int64_t rem = tid - tile * per_tile;
+    r = rem / ct;
+    c = (int32_t)((tile * ct + (rem - r * ct)) * VEC);
+    return c < d;
+}
+
 template <typename T, bool INDEXED, int VEC>
-__global__ void k_segsum(int64_t nseg, int32_t d, const int64_t* __restrict__ seg_src,
+__global__ void k_segsum(int64_t nseg, int32_t d, int32_t ct, const int64_t* __restrict__ seg_src,
                          const int32_t* __restrict__ seg_len, const int64_t* __restrict__ seg_dst,
                          const int32_t* __restrict__ idx, const T* __restrict__ src,
                          T* __restrict__ val) {
-    const int32_t dv = d / VEC;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= nseg * dv) return;
-    const int64_t s = tid / dv;
-    const int32_t c = (int32_t)(tid - s * dv) * VEC;
+    int64_t s;
+    int32_t c;
+    if (!tile_coords<VEC>(tid, nseg, d, ct, s, c) || s >= nseg) return;
     const int64_t b = seg_src[s];
     const int32_t n = seg_len[s];
     vec4<T> acc = {0, 0, 0, 0};
@@ -405,22 +421,23 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
 }
 
 // ---------------------------------------------------------------- gather --
-// One thread per (vertex, VEC channels): adds, over the calls holding the
+// One thread per (vertex, VEC channels), in column tiles like the scatter
+// (the table rows of one tile stay in cache across vertices): adds, over the
+// calls holding the
 // vertex, the call's table value minus the component correction (row -1
 // when the vertex is on the call's backbone), on top of the leaf-tile value
 // already stored in out for vertices of leaf tiles. Writes every out row.
 constexpr int kGatherBatch = 4;
 
 template <typename T, int VEC>
-__global__ void k_gather(int64_t N, int32_t d, const int64_t* __restrict__ v_off,
+__global__ void k_gather(int64_t N, int32_t d, int32_t ct, const int64_t* __restrict__ v_off,
                          const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
                          const int8_t* __restrict__ vleaf, const T* __restrict__ g,
                          T* __restrict__ out) {
-    const int32_t dv = d / VEC;
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= N * dv) return;
-    const int64_t v = tid / dv;
-    const int32_t c = (int32_t)(tid - v * dv) * VEC;
+    int64_t v;
+    int32_t c;
+    if (!tile_coords<VEC>(tid, N, d, ct, v, c) || v >= N) return;
     const int64_t k0 = v_off[v], k1 = v_off[v + 1];
     const bool leaf = vleaf[v] != 0;  // out already holds the leaf tile value
     vec4<T> s = {0, 0, 0, 0};

@@ -746,6 +746,10 @@ int upload_methods(tfi_plan* h) {
             const int64_t bytes = b.P() * cs;
             int t = 0;
             while (t < 3 && bytes > lim[t]) ++t;
+            // long 1-D tables take the channel-tiled convolution kernels even
+            // when one channel pair would fit LDS (the LDS kernels read one
+            // pair per workgroup: 8 bytes of every row)
+            if (b.lg1 == 0 && b.lg2 >= 10) t = 3;
             if (t == 3) {
                 h->global_b[ti].push_back((int)bi);
                 continue;
@@ -816,27 +820,43 @@ int upload_plan(tfi_plan* h) {
 
 // Cell sums of the rows of `src` ([N x d]) into val: A-cells, b-cells and
 // the partial rows of long runs.
+// Column tile, in groups of vec channels, of the row kernels (scatter,
+// gather): a 256-byte slice for rows wider than 512 bytes, else the whole
+// row; and the thread count that covers nrows rows in such tiles.
+template <typename T>
+int32_t col_tile(int32_t d, int vec) {
+    const int32_t dv = d / vec;
+    if ((int64_t)d * (int64_t)sizeof(T) <= 512) return dv;
+    return std::max<int32_t>(1, 256 / (vec * (int32_t)sizeof(T)));
+}
+
+inline int64_t tiled_threads(int64_t nrows, int32_t dv, int32_t ct) {
+    return (int64_t)((dv + ct - 1) / ct) * nrows * ct;
+}
+
 template <typename T>
 void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st) {
     const double sz = (double)sizeof(T);
     for (size_t l = 0; l < h->seg_levels.size(); ++l) {
         const tfi_plan::SegLevel& L = h->seg_levels[l];
         hipEvent_t ev = h->begin(st);
-        const bool v4 = (d % 4 == 0) && aligned16(src);
-        const int64_t nt = L.n * (v4 ? d / 4 : d);
+        const bool v4 = (d % 4 == 0) && (L.indexed ? aligned16(src) : aligned16(val));
+        const int vec = v4 ? 4 : 1;
+        const int32_t ct = col_tile<T>(d, vec);
+        const int64_t nt = tiled_threads(L.n, d / vec, ct);
         if (L.indexed && v4)
             hipLaunchKernelGGL((tfi::k_segsum<T, true, 4>), dim3(blocks_for(nt)), dim3(kThreads),
-                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
+                               0, st, L.n, d, ct, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
         else if (L.indexed)
             hipLaunchKernelGGL((tfi::k_segsum<T, true, 1>), dim3(blocks_for(nt)), dim3(kThreads),
-                               0, st, L.n, d, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
-        else if (d % 4 == 0)
-            hipLaunchKernelGGL((tfi::k_segsum<T, false, 4>), dim3(blocks_for(L.n * (d / 4))),
-                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
+                               0, st, L.n, d, ct, L.d_src, L.d_len, L.d_dst, h->d_inc_v, src, val);
+        else if (v4)
+            hipLaunchKernelGGL((tfi::k_segsum<T, false, 4>), dim3(blocks_for(nt)),
+                               dim3(kThreads), 0, st, L.n, d, ct, L.d_src, L.d_len, L.d_dst,
                                (const int32_t*)nullptr, (const T*)val, val);
         else
-            hipLaunchKernelGGL((tfi::k_segsum<T, false, 1>), dim3(blocks_for(L.n * d)),
-                               dim3(kThreads), 0, st, L.n, d, L.d_src, L.d_len, L.d_dst,
+            hipLaunchKernelGGL((tfi::k_segsum<T, false, 1>), dim3(blocks_for(nt)),
+                               dim3(kThreads), 0, st, L.n, d, ct, L.d_src, L.d_len, L.d_dst,
                                (const int32_t*)nullptr, (const T*)val, val);
         h->end(st, ev, l == 0 ? "scatter" : "scatter_tail",
                sz * d * (double)(L.rows_read + L.n) + (L.indexed ? 4.0 * L.rows_read : 0.0) +
@@ -1164,12 +1184,17 @@ template <typename T>
 void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st) {
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
-    if (d % 4 == 0 && aligned16(out))
-        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(p.N * (d / 4))), dim3(kThreads),
-                           0, st, p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, out);
-    else
-        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(p.N * d)), dim3(kThreads), 0, st,
-                           p.N, d, h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, out);
+    if (d % 4 == 0 && aligned16(out)) {
+        const int32_t ct = col_tile<T>(d, 4);
+        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(tiled_threads(p.N, d / 4, ct))),
+                           dim3(kThreads), 0, st, p.N, d, ct, h->d_v_off, h->d_ga, h->d_gb,
+                           h->d_vleaf, g, out);
+    } else {
+        const int32_t ct = col_tile<T>(d, 1);
+        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(tiled_threads(p.N, d, ct))),
+                           dim3(kThreads), 0, st, p.N, d, ct, h->d_v_off, h->d_ga, h->d_gb,
+                           h->d_vleaf, g, out);
+    }
     h->end(st, ev, "gather",
            sizeof(T) * d * (double)(h->gather_reads + 2 * p.N) + 8.0 * (double)p.v_b.size() +
                9.0 * p.N);
