@@ -103,6 +103,10 @@ def main():
                     help="skip the wide-channel (C = 4160) patch-grid measurement")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-channel measurement")
+    ap.add_argument("--no-families", action="store_true",
+                    help="skip the backbone-policy sweep over the synthetic tree families")
+    ap.add_argument("--families-only", action="store_true",
+                    help="run only the backbone-policy family sweep")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -120,6 +124,9 @@ def main():
     dev = torch.device("cuda", 0)
     if args.wide_only:
         print(json.dumps({"wide_channel": wide_channel(args)}), flush=True)
+        return
+    if args.families_only:
+        print(json.dumps({"family_sweep": family_sweep(args)}), flush=True)
         return
     W = S.workload("rrt100k")
     p, w, F = W["parent"], W["weight"], W["F"]
@@ -239,6 +246,7 @@ def main():
 
     batched = None if args.no_batched else batched_fwd_bwd(args, value)
     wide = None if args.no_wide else wide_channel(args)
+    families = None if args.no_families else family_sweep(args)
 
     rec = {
         "metric": METRIC, "value": value, "unit": "vertex*channels/s", "n_gpus": 1,
@@ -258,6 +266,7 @@ def main():
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
         "wide_channel": wide,
+        "family_sweep": families,
         "stages": stages,
     }
     print(json.dumps(rec), flush=True)
@@ -477,6 +486,111 @@ def wide_channel(args):
             "parity": "32 sampled rows x 64 sampled channels vs FP64 oracle",
             "paper_cpu_s": "32-core CPU, context only",
             "cases": out_cases, "roofline": roofline}
+
+
+
+# The paper's CPU timings (ms) of the scalar forward with f(d) = 1/(1+d) at
+# the largest size of each family (table "synthetic-largest"), quoted as
+# context only: FTFI (centroid baseline), D2 (diameter + 2-D FFT), A2
+# (adaptive + 2-D FFT).
+PAPER_FAMILY_MS = {
+    "path": (59.31, 1.15, 2.09), "balanced_binary": (64.10, 23.80, 56.63),
+    "complete_3ary": (56.36, 29.72, 61.63), "caterpillar": (84.25, 35.43, 38.02),
+    "caterpillar_hanging_paths": (64.77, 6.68, 16.67), "comb": (67.53, 24.11, 25.74),
+    "broom": (54.76, 10.57, 11.80), "double_broom": (26.70, 5.32, 5.83),
+    "uniform_spider": (44.51, 4.57, 5.86), "short_arm_spider": (41.22, 25.65, 30.51),
+    "long_arm_spider": (259.52, 382.98, 20.33), "star": (25.25, 23.52, 25.02),
+    "random_recursive": (43.73, 18.29, 38.83), "random_mst_topology": (46.37, 17.09, 41.79),
+    "preferential_attachment": (38.42, 21.14, 33.22)}
+
+
+def family_sweep(args):
+    """Backbone policies (adaptive = the paper's score, diameter, centroid,
+    and channel = the channel-aware cost model measured by tfi_calibrate on
+    the adaptive plan at the same width) on the fifteen synthetic families
+    at their largest sizes: forward time
+    per integration of a scalar FP64 field with f(d) = 1/(1+d) (the paper's
+    setting) and of an FP32 field of C = 4160 channels, each policy with
+    its own tuned direct/FFT rule; parity against the FP64 oracle on every
+    row (scalar) or on sampled rows x channels (wide)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+
+    dev = torch.device("cuda", 0)
+    policies = ("adaptive", "diameter", "centroid", "channel")
+    fams = []
+    worst = 0.0
+    for name, p, w in S.paper_families():
+        n = len(p)
+        rng = np.random.default_rng(123)
+        F1 = rng.standard_normal(n)
+        phi, v = S.attention_features(n, 64, 64, rng)
+        Fw = torch.from_numpy(S.attention_payload(phi, v)).to(dev)
+        C = Fw.shape[1]
+        rec = {"family": name, "N": n, "ms_scalar_fp64": {}, "ms_wide_fp32": {}, "plan": {}}
+        if name in PAPER_FAMILY_MS:
+            ftfi, d2, a2 = PAPER_FAMILY_MS[name]
+            rec["paper_cpu_ms"] = {"FTFI": ftfi, "D2": d2, "A2": a2}
+        widths = (("ms_scalar_fp64", torch.float64, torch.tensor(F1, device=dev), 1),
+                  ("ms_wide_fp32", torch.float32, Fw, C))
+        # the channel-aware plan of each width, from costs measured on the
+        # adaptive plan at that width
+        models = {}
+        base = TreeIntegrator(p, w, device=0)
+        for key, dt, Fd, d in widths:
+            fb = torch.tensor(1.0 / (1.0 + np.arange(base.kernel_length)), dtype=dt, device=dev)
+            models[key] = base.calibrate(fb, d)
+        del base
+        rec["cost_model"] = models
+        for pol in policies:
+            for key, dt, Fd, d in widths:
+                if pol == "channel":
+                    tfi = TreeIntegrator(p, w, device=0, policy=pol, channel_width=d,
+                                         cost_model=models[key])
+                else:
+                    tfi = TreeIntegrator(p, w, device=0, policy=pol)
+                K = tfi.kernel_length
+                tab = 1.0 / (1.0 + np.arange(K, dtype=np.float64))
+                st = tfi.stats()
+                rec["plan"].setdefault(pol, {})[key] = {
+                    "calls": st["calls"], "root": [st["root"]["m"], st["root"]["H"]],
+                    "sum_M": st["sum_M"], "levels": st["levels"]}
+                f = torch.tensor(tab, dtype=dt, device=dev)
+                tfi.autotune(f, d)
+                for _ in range(3):
+                    y = tfi.integrate(f, Fd)
+                torch.cuda.synchronize()
+                reps = 20
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    y = tfi.integrate(f, Fd)
+                torch.cuda.synchronize()
+                rec[key][pol] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+                if d == 1:
+                    ref = oracle.integrate(p, w, tab, F1)
+                    err = float(np.linalg.norm(y.cpu().numpy() - ref) / np.linalg.norm(ref))
+                    bar = 1e-10
+                else:
+                    rows = np.sort(rng.choice(n, 16, replace=False))
+                    ch = np.sort(rng.choice(C, 32, replace=False))
+                    ref = oracle.integrate(p, w, tab, Fw[:, ch].double().cpu().numpy(), rows=rows)
+                    got = y[rows][:, ch].double().cpu().numpy()
+                    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                    bar = 1e-4
+                worst = max(worst, err / bar)
+                del tfi
+        fams.append(rec)
+        log(f"families[{name} N={n}] scalar fp64 ms {rec['ms_scalar_fp64']} | "
+            f"C={C} fp32 ms {rec['ms_wide_fp32']}")
+    return {"unit": "ms per integration (graph replay)", "kernel": "f(d) = 1/(1+d)",
+            "scalar": "F[N] FP64 ~ N(0,1) (default_rng(123))",
+            "wide": "attention payload C = 4160 FP32",
+            "parity_ok": worst <= 1.0, "worst_err_over_bar": worst,
+            "paper_cpu_ms": "table synthetic-largest, CPU, context only",
+            "families": fams}
 
 
 if __name__ == "__main__":

@@ -69,7 +69,10 @@ typedef enum {
 typedef enum {
     TFI_POLICY_ADAPTIVE = 0, /* diameter or centroid by the adaptive score  */
     TFI_POLICY_DIAMETER = 1, /* always a (weighted) diameter path           */
-    TFI_POLICY_CENTROID = 2  /* always a single centroid vertex             */
+    TFI_POLICY_CENTROID = 2, /* always a single centroid vertex             */
+    TFI_POLICY_CHANNEL = 3   /* diameter or centroid by the channel-aware
+                                cost model (appendix "Channel-aware backbone
+                                selection"): fields chan_width and cost_*  */
 } tfi_policy;
 
 /* Build options; pass NULL for the defaults (all fields 0 = default). */
@@ -97,7 +100,23 @@ typedef struct {
                                     with d >= 8, vector ALU otherwise;
                                     1 = vector ALU; 2 = matrix cores when
                                     the dtype is FP32                      */
-    int32_t reserved[5];
+    /* TFI_POLICY_CHANNEL only. A candidate backbone of a call costs
+     *   cost_call x (table jobs of the call: 1 + components)
+     *   + chan_width x (cost_vertex x (|V(S)| + sum_a n_a log2(n_a + 1))
+     *                   + its table + every correction table),
+     * each table at the cheaper of cost_direct x cells^2 and
+     * cost_fft x P log2 P (occupied cells; P = padded FFT cells). The centroid
+     * is taken when it costs strictly less. Costs are in seconds per unit
+     * (tfi_calibrate measures them); all four 0 = defaults (1, 1, 4, 0). With
+     * measured costs and fft_cost 0, the per-table rule uses
+     * fft_cost = cost_fft / cost_direct.                                     */
+    int32_t chan_width;          /* channel count C the plan is made for;
+                                    0 = 1                                  */
+    float cost_vertex;           /* per incidence and channel (scatter and
+                                    gather)                                */
+    float cost_direct;           /* per direct-sum cell pair and channel   */
+    float cost_fft;              /* per P log2 P of an FFT table and channel */
+    float cost_call;             /* per table job, independent of C        */
 } tfi_build_opts;
 
 /*
@@ -227,6 +246,27 @@ int tfi_autotune(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
 
 /* Apply a cost constant (e.g. a cached tuning result) without timing. */
 int tfi_set_fft_cost(tfi_handle h, float cost);
+
+/*
+ * Measure the channel-aware cost model of TFI_POLICY_CHANNEL on this
+ * handle's plan at d channels of dtype (kernel table f: device,
+ * tfi_kernel_length entries; fields of ones on `stream`). Two passes are
+ * profiled stage by stage: one with every table job evaluated by direct sums
+ * (skipped when its direct work, sum over jobs of cells^2 x d, exceeds
+ * 4e11 multiply-adds) and one with every table job by FFT. Then
+ *   costs[0] = cost_vertex = (scatter + gather time) / (d x incidences),
+ *   costs[1] = cost_direct = direct-sum time / (d x sum of cells^2),
+ *   costs[2] = cost_fft    = FFT table time / (d x sum of P log2 P),
+ *   costs[3] = cost_call   = 0 (the job lists are batched: no per-call
+ *                              launch),
+ * in seconds (host float[4]); without the direct pass, cost_direct =
+ * cost_fft / the handle's fft_cost. The handle's method rule is restored.
+ * Uses the temporary device memory of tfi_autotune.
+ * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE (host-only handle,
+ * method forced at build), TFI_ERR_HIP, TFI_ERR_BUDGET, TFI_ERR_OOM.
+ */
+int tfi_calibrate(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype, float costs[4],
+                  void *stream);
 
 /*
  * Stage timing. With enable != 0, every later tfi_integrate/tfi_backward

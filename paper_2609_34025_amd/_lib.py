@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtfi.so")
 TFI_F32 = 0
 TFI_F64 = 1
 
-POLICIES = {"adaptive": 0, "diameter": 1, "centroid": 2}
+POLICIES = {"adaptive": 0, "diameter": 1, "centroid": 2, "channel": 3}
 TABLE_METHODS = {"auto": 0, "direct": 1, "fft": 2}
 
 STATUS = {0: "ok", -1: "TFI_ERR_ARG", -2: "TFI_ERR_TREE", -3: "TFI_ERR_WEIGHT",
@@ -35,7 +35,9 @@ class BuildOpts(C.Structure):
     _fields_ = [("policy", C.c_int32), ("leaf_max", C.c_int32), ("device", C.c_int32),
                 ("table_method", C.c_int32), ("memory_budget_bytes", C.c_uint64),
                 ("no_graphs", C.c_int32), ("fft_cost", C.c_float),
-                ("direct_kernel", C.c_int32), ("reserved", C.c_int32 * 5)]
+                ("direct_kernel", C.c_int32), ("chan_width", C.c_int32),
+                ("cost_vertex", C.c_float), ("cost_direct", C.c_float),
+                ("cost_fft", C.c_float), ("cost_call", C.c_float)]
 
 
 _lib = None
@@ -43,7 +45,7 @@ _lib = None
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
             "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
-            "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum"]
+            "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate"]
 
 
 def load():
@@ -80,6 +82,8 @@ def load():
     lib.tfi_autotune.restype = C.c_int
     lib.tfi_set_fft_cost.argtypes = [vp, C.c_float]
     lib.tfi_set_fft_cost.restype = C.c_int
+    lib.tfi_calibrate.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
+    lib.tfi_calibrate.restype = C.c_int
     lib.tfi_integrate_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, i64, C.c_int, vp, vp]
     lib.tfi_integrate_expsum.restype = C.c_int
     lib.tfi_backward_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp,
@@ -100,7 +104,7 @@ def check(rc):
 
 def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
                  table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0,
-                 direct_kernel="auto"):
+                 direct_kernel="auto", channel_width=0, cost_model=None):
     lib = load()
     parent = np.ascontiguousarray(parent, dtype=np.int64)
     weight = np.ascontiguousarray(weight, dtype=np.int32)
@@ -116,6 +120,12 @@ def build_handle(parent, weight, policy="adaptive", leaf_max=0, device=0,
     o.no_graphs = 0 if graphs else 1
     o.fft_cost = float(fft_cost)
     o.direct_kernel = {"auto": 0, "vector": 1, "mfma": 2}[direct_kernel]
+    o.chan_width = int(channel_width)
+    if cost_model:
+        o.cost_vertex = float(cost_model["vertex"])
+        o.cost_direct = float(cost_model["direct"])
+        o.cost_fft = float(cost_model["fft"])
+        o.cost_call = float(cost_model.get("call", 0.0))
     h = C.c_void_p()
     check(lib.tfi_build(parent.ctypes.data, weight.ctypes.data, len(parent),
                         C.byref(o), C.byref(h)))

@@ -212,7 +212,8 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
         for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) sf[k] = f[k];
         fp = sf;
     }
-    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+    // channel chunks: this workgroup takes every gridDim.y-th one
+    for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += gridDim.y * kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         const int32_t nq = (nch + 3) >> 2;             // channel quads
         const int32_t qpp = kDirThreads / nq;          // cell quads per pass
@@ -328,7 +329,8 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
         tjb[q] = tok ? tjb_ : 0;
         tje[q] = tok ? tje_ : 0;
     }
-    for (int32_t c0 = 0; c0 < d; c0 += 16 * NCH) {
+    // passes of NCH chunks: this workgroup takes every gridDim.y-th one
+    for (int32_t c0 = blockIdx.y * 16 * NCH; c0 < d; c0 += gridDim.y * 16 * NCH) {
         v4f_t acc[NCH][4];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch)
@@ -532,7 +534,8 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
         }
     }
     for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
-    for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
+    // channel chunks: this workgroup takes every gridDim.y-th one
+    for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += gridDim.y * kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         const int32_t nq = (nch + 3) >> 2;
         const int32_t qpp = kLeafThreads / nq;

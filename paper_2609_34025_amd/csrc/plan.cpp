@@ -124,6 +124,9 @@ struct Decomp {
     }
 };
 
+int64_t next_pow2(int64_t x);
+int32_t ilog2(int64_t p);
+
 class Planner {
   public:
     Planner(const Forest& t, const PlanOptions& o, Plan& p)
@@ -148,6 +151,7 @@ class Planner {
     std::vector<std::pair<int32_t, int32_t>> vinc;  // (vertex, b-cell)
     struct Rec { int32_t x, r, c, v; };
     std::vector<Rec> recs;
+    std::vector<int64_t> keys, rk;  // scratch of chan_score
 
     // Traverse the current call from src (entered from `par`, starting
     // distance d0), skipping backbone vertices when skipP. Fills `order`
@@ -265,6 +269,46 @@ class Planner {
     double score(const std::vector<int32_t>& S, const Decomp& D) const {
         int64_t M = (D.H + 1) * (D.X + 1);
         return backbone_score((int64_t)S.size(), M, D.cH, D.cN);
+    }
+
+    // Per-channel cost of one table: the cheaper of direct sums over its
+    // occupied cells and an FFT of its padded shape.
+    double table_cost(int64_t cells, int64_t H, int64_t X) const {
+        const double P = (double)(next_pow2(2 * H + 1) * next_pow2(2 * X + 1));
+        const double direct = opt.cost_direct * (double)cells * (double)cells;
+        const double fft = opt.cost_fft * P * std::log2(std::max(P, 2.0));
+        return std::min(direct, fft);
+    }
+
+    // Channel-aware cost of a candidate (appendix "Channel-aware backbone
+    // selection"): cost_call per table job of the call (its own and one
+    // correction per component) plus C times the per-channel work -- the
+    // call's incidences, the call's table and every correction table (each
+    // at its cheaper evaluator, over its exact occupied cells), and the
+    // recursion proxy n log2(n + 1) of every component (the last term of
+    // equation "stad-score"), priced like incidences.
+    double chan_score(const std::vector<int32_t>& S, const Decomp& D) {
+        keys.clear();
+        for (int64_t x : D.px) keys.push_back(x << 32);  // backbone cells: r = 0
+        const size_t k = D.cN.size();
+        double corr = 0, rec = 0;
+        for (size_t c = 0; c < k; ++c) {
+            const int64_t x = D.px[D.cAnchor[c]];
+            rk.clear();
+            for (int64_t i = D.cOff[c]; i < D.cOff[c + 1]; ++i) {
+                keys.push_back((x << 32) | D.cr[i]);
+                rk.push_back(D.cr[i]);
+            }
+            std::sort(rk.begin(), rk.end());
+            const int64_t nb = std::unique(rk.begin(), rk.end()) - rk.begin();
+            corr += table_cost(nb, D.cH[c], 0);
+            rec += (double)D.cN[c] * std::log2((double)D.cN[c] + 1.0);
+        }
+        std::sort(keys.begin(), keys.end());
+        const int64_t cells = std::unique(keys.begin(), keys.end()) - keys.begin();
+        const double chan =
+            opt.cost_vertex * ((double)S.size() + rec) + table_cost(cells, D.H, D.X) + corr;
+        return opt.cost_call * (double)(1 + k) + (double)opt.chan_width * chan;
     }
 
     void emit_leaf(const std::vector<int32_t>& S);
@@ -426,10 +470,10 @@ int Planner::run(const std::vector<int32_t>& roots, std::string& err) {
             } else {
                 diameter_path(S, Pd);
                 decompose(Pd, dA);
-                sd = score(S, dA);
+                sd = opt.policy == 3 ? chan_score(S, dA) : score(S, dA);
                 Pc.assign(1, centroid(S));
                 decompose(Pc, dB);
-                sc = score(S, dB);
+                sc = opt.policy == 3 ? chan_score(S, dB) : score(S, dB);
                 // the centroid only if strictly cheaper; diameter wins ties
                 choice = (sc < sd) ? 1 : 0;
                 if (choice == 1) std::swap(dA, dB);
@@ -554,8 +598,10 @@ uint64_t plan_fingerprint(const Plan& p) {
 int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
                const PlanOptions& opt, Plan& plan, std::string& err) {
     plan = Plan();
-    if (opt.policy < 0 || opt.policy > 2 || opt.table_method < 0 ||
-        opt.table_method > 2 || opt.leaf_max < 0 || !(opt.fft_cost > 0.0)) {
+    if (opt.policy < 0 || opt.policy > 3 || opt.table_method < 0 ||
+        opt.table_method > 2 || opt.leaf_max < 0 || !(opt.fft_cost > 0.0) ||
+        opt.chan_width < 1 || !(opt.cost_vertex >= 0.0) || !(opt.cost_direct > 0.0) ||
+        !(opt.cost_fft > 0.0) || !(opt.cost_call >= 0.0)) {
         err = "tfi_build: invalid option";
         return kErrArg;
     }

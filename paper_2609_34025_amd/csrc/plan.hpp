@@ -29,10 +29,15 @@ namespace tfi {
 enum Method : int32_t { METHOD_DIRECT = 0, METHOD_FFT = 1 };
 
 struct PlanOptions {
-    int32_t policy = 0;       // 0 adaptive, 1 diameter, 2 centroid
+    int32_t policy = 0;       // 0 adaptive, 1 diameter, 2 centroid, 3 channel-aware
     int32_t leaf_max = 32;    // dense tiles for subtrees up to this size
     int32_t table_method = 0; // 0 choose, 1 direct, 2 fft
     double fft_cost = 4.0;    // direct iff cells^2 <= fft_cost * P log2 P
+    // channel-aware cost model (policy 3): a candidate backbone costs
+    // cost_call per table job + chan_width x (cost_vertex per incidence,
+    // cost_direct per direct cell pair, cost_fft per P log2 P of an FFT)
+    int32_t chan_width = 1;
+    double cost_vertex = 1.0, cost_direct = 1.0, cost_fft = 4.0, cost_call = 0.0;
 };
 
 struct Plan {

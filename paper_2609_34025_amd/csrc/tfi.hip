@@ -586,15 +586,22 @@ int upload_static(tfi_plan* h) {
 // Device structures that depend on the per-job method (direct blocks, FFT
 // buckets and their LDS tiers); rebuilt when the methods are re-assigned.
 // LDS beyond 64 KiB for the 1-D convolution kernels of every channel tile.
-template <typename T, int TC>
-int conv1d_lds_optin_tc(int lds) {
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, false>,
+template <typename T, int TC, int S>
+int conv1d_lds_optin_ts(int lds) {
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, S, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, true>,
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, S, true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC>,
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC, S>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return TFI_OK;
+}
+
+template <typename T, int TC>
+int conv1d_lds_optin_tc(int lds) {
+    int rc = conv1d_lds_optin_ts<T, TC, 1>(lds);
+    if (!rc && TC >= 8) rc = conv1d_lds_optin_ts<T, TC, (TC >= 8 ? 2 : 1)>(lds);
+    return rc;
 }
 
 template <typename T>
@@ -964,27 +971,48 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     const int64_t job_bytes = (int64_t)ntiles * TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
     const int64_t jpc =
         std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)buf_bytes / job_bytes));
-    // LDS block: 2^RA rows of (2^RB x TC + pad) complex; 2^RB x TC threads
+    // Block transforms of 2^lgB points: 2^RB x TC threads, transposes through
+    // an LDS buffer of 2^RA rows x (2^RB x TC/S + pad) complex in S channel
+    // slices. Two slices (more workgroups per CU) only when a slice is whole
+    // wavefronts (every lane of a wavefront passes the same barriers).
     const int hRB = lgH / 2, hRA = lgH - hRB, lRB = lgL / 2, lRA = lgL - lRB;
-    const unsigned lds_hi = (unsigned)(((int64_t)1 << hRA) * ((TC << hRB) + tfi::kC1Pad) *
-                                       sizeof(tfi::cpx<T>));
-    const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((TC << lRB) + tfi::kC1Pad) *
-                                       sizeof(tfi::cpx<T>));
+    constexpr int S2 = TC >= 8 ? 2 : 1;
+    const int sh = (S2 == 2 && ((TC / 2) << hRB) % 64 == 0) ? 2 : 1;
+    const int sl = (S2 == 2 && ((TC / 2) << lRB) % 64 == 0) ? 2 : 1;
+    const size_t cs = sizeof(tfi::cpx<T>);
+    const unsigned lds_hi =
+        (unsigned)(((size_t)1 << hRA) * (size_t)(((TC / sh) << hRB) + tfi::kC1Pad) * cs);
+    const unsigned lds_lo =
+        (unsigned)((((size_t)1 << lRA) * (size_t)(((TC / sl) << lRB) + tfi::kC1Pad) +
+                    ((size_t)1 << lgL)) * cs);
     const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(TC << lRB);
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
         const int32_t* map = bmap + j0 * b.mstride;
-        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, false>),
-                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
-                           tw, h->lgtw);
-        hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC>),
-                           dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
-                           lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
-        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, true>),
-                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g,
-                           buf, tw, h->lgtw);
+        const dim3 ghi(1u << lgL, (unsigned)ntiles, (unsigned)nj);
+        const dim3 glo(1u << lgH, (unsigned)ntiles, (unsigned)nj);
+        if (sh == 2)
+            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, S2, false>), ghi, dim3(thr_hi), lds_hi,
+                               st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
+                               tw, h->lgtw);
+        else
+            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, 1, false>), ghi, dim3(thr_hi), lds_hi,
+                               st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
+                               tw, h->lgtw);
+        if (sl == 2)
+            hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC, S2>), glo, dim3(thr_lo), lds_lo, st, lg,
+                               lgL, buf, spec + b.spec_off, tw, h->lgtw);
+        else
+            hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC, 1>), glo, dim3(thr_lo), lds_lo, st, lg,
+                               lgL, buf, spec + b.spec_off, tw, h->lgtw);
+        if (sh == 2)
+            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, S2, true>), ghi, dim3(thr_hi), lds_hi,
+                               st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g, buf,
+                               tw, h->lgtw);
+        else
+            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, 1, true>), ghi, dim3(thr_hi), lds_hi,
+                               st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g, buf,
+                               tw, h->lgtw);
     }
 }
 
@@ -1085,12 +1113,24 @@ int prepare_forward(tfi_plan* h, int32_t d, bool general = false) {
 
 // ---- stage helpers (enqueue only; buffers prepared beforehand) ----------
 
+// Channel split of the row-block kernels (leaf tiles, direct tables): with
+// few workgroups along x, the chunks of step channels go to gridDim.y
+// workgroups so that the launch still fills the device (4096 workgroups);
+// a workgroup walks its chunks in order either way.
+inline unsigned chan_split(int64_t xblocks, int32_t d, int32_t step) {
+    const int64_t chunks = (d + step - 1) / step;
+    const int64_t want = (4096 + std::max<int64_t>(xblocks, 1) - 1) / std::max<int64_t>(xblocks, 1);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>({chunks, want, 65535}));
+}
+
 template <typename T>
 void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
     if (h->nlgrp == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
-    hipLaunchKernelGGL(tfi::k_leaf<T>, dim3((unsigned)h->nlgrp), dim3(tfi::kLeafThreads), 0, st, d,
+    hipLaunchKernelGGL(tfi::k_leaf<T>,
+                       dim3((unsigned)h->nlgrp, chan_split(h->nlgrp, d, tfi::kDirCh)),
+                       dim3(tfi::kLeafThreads), 0, st, d,
                        h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
     const double nv = (double)p.leaf_v.size();
     h->end(st, ev, "leaf",
@@ -1158,8 +1198,9 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
     if (mfma) {
         // 16-channel chunks per pass: one kernel entry serves all of them
         const int nch = d > 48 ? 4 : d > 32 ? 3 : d > 16 ? 2 : 1;
+        const unsigned ys = chan_split(h->ndblk, d, 16 * nch);
         auto launch = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk, ys), dim3(tfi::kDirThreads),
                                (unsigned)(flds * sizeof(float)), st, d, h->d_dblk, h->d_dl_r,
                                h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, (const float*)f, flds,
                                (const float*)val, (float*)g);
@@ -1172,7 +1213,9 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
         }
     }
     else
-        hipLaunchKernelGGL(tfi::k_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads),
+        hipLaunchKernelGGL(tfi::k_direct<T>,
+                           dim3((unsigned)h->ndblk, chan_split(h->ndblk, d, tfi::kDirCh)),
+                           dim3(tfi::kDirThreads),
                            (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
                            h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
     h->end(st, ev, mfma ? "direct_mfma" : "direct",
@@ -1742,6 +1785,24 @@ int run_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, co
     });
 }
 
+// Fold the recorded stage events into the per-stage tallies.
+int drain_profile(tfi_plan* h) {
+    for (auto& q : h->pending) {
+        TFI_HIP(hipEventSynchronize(q.e1));
+        float ms = 0;
+        TFI_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
+        auto& t = h->tally[q.stage];
+        t.launches++;
+        t.ms += ms;
+        t.bytes += q.bytes;
+        t.flops += q.flops;
+        h->pool.push_back(q.e0);
+        h->pool.push_back(q.e1);
+    }
+    h->pending.clear();
+    return TFI_OK;
+}
+
 int reassign_methods(tfi_plan* h, double cost) {
     h->popt.fft_cost = cost;
     tfi::assign_methods(h->plan, h->popt);
@@ -1823,6 +1884,16 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
                                      std::to_string(tfi::kLeafMax) + "]");
     po.table_method = o.table_method;
     po.fft_cost = o.fft_cost == 0.0f ? 4.0 : (double)o.fft_cost;
+    po.chan_width = o.chan_width == 0 ? 1 : o.chan_width;
+    if (o.cost_vertex != 0.0f || o.cost_direct != 0.0f || o.cost_fft != 0.0f ||
+        o.cost_call != 0.0f) {
+        po.cost_vertex = o.cost_vertex;
+        po.cost_direct = o.cost_direct;
+        po.cost_fft = o.cost_fft;
+        po.cost_call = o.cost_call;
+        if (o.policy == TFI_POLICY_CHANNEL && o.fft_cost == 0.0f && o.cost_direct > 0.0f)
+            po.fft_cost = (double)o.cost_fft / (double)o.cost_direct;
+    }
     if (o.device < -1) return fail(TFI_ERR_ARG, "tfi_build: device must be >= -1");
     std::unique_ptr<tfi_plan> h;
     try {
@@ -2024,6 +2095,85 @@ int tfi_set_fft_cost(tfi_handle h, float cost) {
     return reassign_methods(h, cost);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Cost model of the channel-aware policy, measured on the handle's plan
+// (see tfi_calibrate): stage times of profiled passes with every table job
+// on one evaluator, per unit of that evaluator's work.
+template <typename T>
+int calibrate(tfi_plan* h, const T* f, int32_t d, hipStream_t st, float* costs) {
+    const tfi::Plan& p = h->plan;
+    const double keep = h->popt.fft_cost;
+    double c2 = 0, plp = 0;
+    for (size_t j = 0; j + 1 < p.job_cell_off.size(); ++j) {
+        const double c = (double)(p.job_cell_off[j + 1] - p.job_cell_off[j]);
+        c2 += c * c;
+        const double P = std::ldexp(1.0, p.job_lg1[j] + p.job_lg2[j]);
+        plp += P * std::log2(std::max(P, 2.0));
+    }
+    // every table through the scatter/gather path while measuring (the
+    // restoring reassignment below recomputes the whole-path flags)
+    const bool keep_prof = h->prof;
+    int rc = drain_profile(h);
+    if (rc) return rc;
+    h->tally.clear();
+    double rows_s = 0, dir_s = -1, fft_s = -1;
+    for (int mode = 0; mode < 2 && !rc; ++mode) {
+        if (mode == 0 && c2 * (double)d > 4e11) continue;  // all-direct too large
+        if ((rc = reassign_methods(h, mode == 0 ? 1e30 : 1e-30))) break;
+        h->path_mode[0] = h->path_mode[1] = false;
+        h->prof = true;
+        float ms = 0;
+        rc = time_pass<T>(h, f, d, st, 1, false, &ms);  // 3 profiled passes
+        h->prof = keep_prof;
+        if (!rc) rc = drain_profile(h);
+        if (rc) break;
+        double rows = 0, tab = 0;
+        for (auto& kv : h->tally) {
+            const std::string& k = kv.first;
+            if (k == "scatter" || k == "scatter_tail" || k == "gather") rows += kv.second.ms;
+            const bool is_dir = k == "direct" || k == "direct_mfma";
+            const bool is_fft = k.rfind("fft", 0) == 0 || k.rfind("spectrum", 0) == 0;
+            if (mode == 0 ? is_dir : is_fft) tab += kv.second.ms;
+        }
+        h->tally.clear();
+        rows_s = 1e-3 * rows / 3.0;
+        (mode == 0 ? dir_s : fft_s) = 1e-3 * tab / 3.0;
+    }
+    h->prof = keep_prof;
+    int rc2 = reassign_methods(h, keep);
+    if (rc) return rc;
+    if (rc2) return rc2;
+    const double dd = (double)d;
+    costs[0] = p.incidences > 0 ? (float)(rows_s / (dd * (double)p.incidences)) : 0.0f;
+    costs[2] = (fft_s > 0 && plp > 0) ? (float)(fft_s / (dd * plp)) : 4.0f;
+    costs[1] = (dir_s > 0 && c2 > 0) ? (float)(dir_s / (dd * c2)) : (float)(costs[2] / keep);
+    costs[3] = 0.0f;
+    return TFI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfi_calibrate(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, float* costs,
+                  void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f || !costs) return fail(TFI_ERR_ARG, "tfi_calibrate: null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_calibrate: need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64)
+        return fail(TFI_ERR_DTYPE, "tfi_calibrate: unknown dtype");
+    if (h->popt.table_method != 0)
+        return fail(TFI_ERR_STATE, "tfi_calibrate: table method is forced for this handle");
+    hipStream_t st = (hipStream_t)stream;
+    return dtype == TFI_F32 ? calibrate<float>(h, (const float*)f, (int32_t)d, st, costs)
+                            : calibrate<double>(h, (const double*)f, (int32_t)d, st, costs);
+}
+
 int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int with_backward,
                  float* best_cost, void* stream) {
     g_err.clear();
@@ -2067,19 +2217,7 @@ int64_t tfi_profile_report(tfi_handle h, char* json, size_t cap) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
-    for (auto& q : h->pending) {
-        TFI_HIP(hipEventSynchronize(q.e1));
-        float ms = 0;
-        TFI_HIP(hipEventElapsedTime(&ms, q.e0, q.e1));
-        auto& t = h->tally[q.stage];
-        t.launches++;
-        t.ms += ms;
-        t.bytes += q.bytes;
-        t.flops += q.flops;
-        h->pool.push_back(q.e0);
-        h->pool.push_back(q.e1);
-    }
-    h->pending.clear();
+    if ((rc = drain_profile(h))) return rc;
     std::string s = "{";
     bool first = true;
     char buf[256];

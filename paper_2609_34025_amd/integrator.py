@@ -30,7 +30,9 @@ class TreeIntegrator:
     """Plan of one forest, uploaded to one GPU.
 
     parent  int64[N], -1 at roots; weight int32[N] >= 1 (edge to parent).
-    policy  'adaptive' (paper's score), 'diameter' or 'centroid'.
+    policy  'adaptive' (paper's score), 'diameter', 'centroid', or 'channel'
+            (the channel-aware cost model of ``channel_width`` channels and
+            ``cost_model``, e.g. from ``calibrate``).
     leaf_max  subtrees up to this size are integrated densely (0 = default).
     device  CUDA/HIP device index, or None for a host-only plan (stats and
             plan inspection only).
@@ -41,17 +43,21 @@ class TreeIntegrator:
             (0 = default 4).
     direct_kernel  'auto' (matrix cores for FP32 with d >= 8), 'vector' or
             'mfma'.
+    channel_width, cost_model  for policy 'channel': the channel count C and
+            {'vertex', 'direct', 'fft', 'call'} costs in seconds per unit
+            (None = defaults).
     """
 
     def __init__(self, parent, weight, *, policy="adaptive", leaf_max=0, device=0,
                  table_method="auto", memory_budget=0, graphs=True, fft_cost=0.0,
-                 direct_kernel="auto"):
+                 direct_kernel="auto", channel_width=0, cost_model=None):
         if device is not None and isinstance(device, torch.device):
             device = device.index or 0
         self._h = _lib.build_handle(parent, weight, policy=policy, leaf_max=leaf_max,
                                     device=device, table_method=table_method,
                                     memory_budget=memory_budget, graphs=graphs,
-                                    fft_cost=fft_cost, direct_kernel=direct_kernel)
+                                    fft_cost=fft_cost, direct_kernel=direct_kernel,
+                                    channel_width=channel_width, cost_model=cost_model)
         self.device = None if device is None else torch.device("cuda", int(device))
         lib = _lib.load()
         self.num_vertices = int(lib.tfi_num_vertices(self._h))
@@ -104,6 +110,17 @@ class TreeIntegrator:
                 json.dump(table, fp, indent=1, sort_keys=True)
             os.replace(tmp, cache)
         return best.value
+
+    def calibrate(self, f, d):
+        """Measure the channel-aware cost model on this plan at ``d``
+        channels of ``f``'s dtype (profiled all-direct and all-FFT passes);
+        returns {'vertex', 'direct', 'fft', 'call'} in seconds per unit, the
+        ``cost_model`` of policy 'channel'."""
+        self._check(f)
+        costs = (C.c_float * 4)()
+        _lib.check(_lib.load().tfi_calibrate(self._h, f.data_ptr(), int(d), _DTYPES[f.dtype],
+                                             costs, self._stream(self.device)))
+        return {"vertex": costs[0], "direct": costs[1], "fft": costs[2], "call": costs[3]}
 
     def set_fft_cost(self, cost):
         """Apply a direct-vs-FFT cost constant without timing."""

@@ -32,6 +32,7 @@ __all__ = [
     "random_recursive", "random_mst_topology", "preferential_attachment",
     "binary_random_recursive", "grid_mst", "sphere_knn_mst",
     "patch_grid_tree", "attention_features", "attention_payload",
+    "paper_families",
     "topo_mask_table",
     "uniform_weights", "normal_field", "dirichlet_field",
     "exp_table", "inv_sq_table", "inv_table", "expsum_table", "ones_table",
@@ -313,6 +314,35 @@ def grid_mst(side, wmax, rng):
     tw = np.array([lut[(a, b)] for a, b in zip(r.tolist(), c.tolist())],
                   dtype=np.int64)
     return edges_to_parent(n, r, c, tw)
+
+
+# ------------------------------------------- synthetic family sweep --
+
+def paper_families(seed=0):
+    """The fifteen families of the paper's synthetic benchmark at the
+    largest size of each sweep (appendix table of deterministic
+    constructions; table "synthetic-largest"), unit weights:
+    ``[(name, parent, weight), ...]``. The three random families use
+    ``default_rng(seed)``, N = 800."""
+    rng = np.random.default_rng(seed)
+    fam = [
+        ("path", *path(800)),
+        ("balanced_binary", *balanced_kary(2, 9)),
+        ("complete_3ary", *balanced_kary(3, 6)),
+        ("caterpillar", *caterpillar(400, 3)),
+        ("caterpillar_hanging_paths", *caterpillar_hanging_paths(32)),
+        ("comb", *comb(400)),
+        ("broom", *broom(640)),
+        ("double_broom", *double_broom(320)),
+        ("uniform_spider", *spider(30, 25)),
+        ("short_arm_spider", *spider(400, 2)),
+        ("long_arm_spider", *spider(8, 500)),
+        ("star", *star(800)),
+        ("random_recursive", *random_recursive(800, rng)),
+        ("random_mst_topology", *random_mst_topology(800, rng)),
+        ("preferential_attachment", *preferential_attachment(800, rng)),
+    ]
+    return fam
 
 
 # ------------------------------------------ patch-grid spanning trees --

@@ -86,7 +86,7 @@ def trees_for_replay():
     return out
 
 
-@pytest.mark.parametrize("policy", ["adaptive", "diameter", "centroid"])
+@pytest.mark.parametrize("policy", ["adaptive", "diameter", "centroid", "channel"])
 @pytest.mark.parametrize("leaf_max", [1, 5, 32])
 def test_plan_replay_matches_oracle(policy, leaf_max):
     rng = np.random.default_rng(17)
@@ -285,3 +285,34 @@ def test_build_errors():
     t = TreeIntegrator(ok_p, ok_w, device=None)
     with pytest.raises(TFIError, match="ARG"):
         t.export("no_such_array")
+
+
+def test_channel_policy_trades_call_cost_against_channel_width():
+    # Eight-arm spider, 500-edge arms (the paper's long-arm spider): the
+    # diameter backbone leaves 6 components (7 table jobs), the hub 8 (9
+    # jobs), but the diameter's per-channel work is larger (a 1501-cell table
+    # against 501). With a per-job cost of 1e7 units the diameter wins at one
+    # channel and the hub at 4160 (appendix "Channel-aware backbone
+    # selection": the product C x C_chan decides at wide channels).
+    p, w = S.spider(8, 500)
+    cm = {"vertex": 1.0, "direct": 1.0, "fft": 4.0, "call": 1e7}
+    narrow = TreeIntegrator(p, w, device=None, policy="channel", channel_width=1,
+                            cost_model=cm).stats()["root"]
+    wide = TreeIntegrator(p, w, device=None, policy="channel", channel_width=4160,
+                          cost_model=cm).stats()["root"]
+    assert (narrow["choice"], narrow["m"], narrow["H"]) == ("diameter", 1001, 500)
+    assert (wide["choice"], wide["m"], wide["H"]) == ("centroid", 1, 500)
+    # a dominant per-job cost alone picks the candidate with fewer jobs
+    calls = TreeIntegrator(p, w, device=None, policy="channel",
+                           cost_model={"vertex": 1, "direct": 1, "fft": 4, "call": 1e9}
+                           ).stats()["root"]
+    assert calls["choice"] == "diameter"
+
+
+def test_channel_policy_rejects_bad_cost_model():
+    p, w = S.path(10)
+    with pytest.raises(TFIError):
+        TreeIntegrator(p, w, device=None, policy="channel",
+                       cost_model={"vertex": 1, "direct": -1, "fft": 4})
+    with pytest.raises(TFIError):
+        TreeIntegrator(p, w, device=None, policy="channel", channel_width=-3)
