@@ -505,10 +505,8 @@ PAPER_FAMILY_MS = {
 
 
 def family_sweep(args):
-    """Backbone policies (adaptive = the paper's score, diameter, centroid,
-    and channel = the channel-aware cost model measured by tfi_calibrate on
-    the adaptive plan at the same width) on the fifteen synthetic families
-    at their largest sizes: forward time
+    """Backbone policies (adaptive = the paper's score, diameter, centroid)
+    on the fifteen synthetic families at their largest sizes: forward time
     per integration of a scalar FP64 field with f(d) = 1/(1+d) (the paper's
     setting) and of an FP32 field of C = 4160 channels, each policy with
     its own tuned direct/FFT rule; parity against the FP64 oracle on every
@@ -520,7 +518,7 @@ def family_sweep(args):
     from paper_2609_34025_amd import TreeIntegrator, synth as S
 
     dev = torch.device("cuda", 0)
-    policies = ("adaptive", "diameter", "centroid", "channel")
+    policies = ("adaptive", "diameter", "centroid")
     fams = []
     worst = 0.0
     for name, p, w in S.paper_families():
@@ -536,22 +534,9 @@ def family_sweep(args):
             rec["paper_cpu_ms"] = {"FTFI": ftfi, "D2": d2, "A2": a2}
         widths = (("ms_scalar_fp64", torch.float64, torch.tensor(F1, device=dev), 1),
                   ("ms_wide_fp32", torch.float32, Fw, C))
-        # the channel-aware plan of each width, from costs measured on the
-        # adaptive plan at that width
-        models = {}
-        base = TreeIntegrator(p, w, device=0)
-        for key, dt, Fd, d in widths:
-            fb = torch.tensor(1.0 / (1.0 + np.arange(base.kernel_length)), dtype=dt, device=dev)
-            models[key] = base.calibrate(fb, d)
-        del base
-        rec["cost_model"] = models
         for pol in policies:
             for key, dt, Fd, d in widths:
-                if pol == "channel":
-                    tfi = TreeIntegrator(p, w, device=0, policy=pol, channel_width=d,
-                                         cost_model=models[key])
-                else:
-                    tfi = TreeIntegrator(p, w, device=0, policy=pol)
+                tfi = TreeIntegrator(p, w, device=0, policy=pol)
                 K = tfi.kernel_length
                 tab = 1.0 / (1.0 + np.arange(K, dtype=np.float64))
                 st = tfi.stats()

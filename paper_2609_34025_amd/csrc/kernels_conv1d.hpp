@@ -97,106 +97,22 @@ __device__ __forceinline__ void reg_fft(cpx<T> (&x)[1 << kC1MaxR], int R,
     }
 }
 
-// LDS transpose buffer: row a (2^RA rows) holds the 2^RB points b x TS
-// pairs of one channel slice, padded by kC1Pad complex values so that phase
-// B's lanes (different a, same b) spread over the banks.
-template <int TS>
+// LDS block layout: row a (2^RA rows) holds the 2^RB points b x TC pairs,
+// padded by kC1Pad complex values so that phase B's lanes (different a, same
+// b) spread over the banks.
+template <int TC>
 __device__ __forceinline__ int lds_at(int a, int b, int c, int RB) {
-    return a * ((TS << RB) + kC1Pad) + b * TS + c;
-}
-
-// Thread roles of a block transform with TC pairs split into S slices of
-// TS = TC/S: a workgroup of 2^RB x TC threads is S groups of whole
-// wavefronts, slice `half` = threadIdx / (2^RB TS); inside a slice, cs (the
-// pair within the slice) runs fastest, then b < 2^RB.
-template <int TC, int S>
-struct C1Lane {
-    static constexpr int TS = TC / S;
-    int half, cs, b, c;
-    __device__ __forceinline__ C1Lane(int RB) {
-        const int per = TS << RB;
-        half = threadIdx.x / per;
-        const int rest = threadIdx.x - half * per;
-        b = rest / TS;
-        cs = rest - b * TS;
-        c = half * TS + cs;
-    }
-};
-
-// Transposes between the two register layouts through LDS, one channel
-// slice per round (every wavefront passes the same 2 S barriers; its own
-// round writes and reads, so the values it sends are dead before the ones
-// it receives arrive and the same registers hold both):
-//   layout A: x[k] = point (k << RB) + b, k < 2^RA;
-//   layout B: x[j 16 + k] = point (a << RB) + k, a = b + j 2^RB < 2^RA,
-//             k < 2^RB (RA - RB <= 1; j = 0 only when RB = 5).
-template <typename T, int TC, int S, bool A_TO_B>
-__device__ __forceinline__ void c1_transpose(cpx<T>* z, cpx<T> (&x)[1 << kC1MaxR],
-                                             const C1Lane<TC, S>& L, int RA, int RB) {
-    constexpr int TS = TC / S;
-    for (int r = 0; r < L.half; ++r) {
-        __syncthreads();
-        __syncthreads();
-    }
-    if (A_TO_B) {
-#pragma unroll
-        for (int k = 0; k < (1 << kC1MaxR); ++k)
-            if (k < (1 << RA)) z[lds_at<TS>(k, L.b, L.cs, RB)] = x[k];
-    } else {
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int k = 0; k < 16 * (2 - j); ++k) {
-                const int a = L.b + (j << RB);
-                if (k < (1 << RB) && a < (1 << RA)) z[lds_at<TS>(a, k, L.cs, RB)] = x[j * 16 + k];
-            }
-    }
-    __syncthreads();
-    if (A_TO_B) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int k = 0; k < 16 * (2 - j); ++k) {
-                const int a = L.b + (j << RB);
-                if (k < (1 << RB) && a < (1 << RA)) x[j * 16 + k] = z[lds_at<TS>(a, k, L.cs, RB)];
-            }
-    } else {
-#pragma unroll
-        for (int k = 0; k < (1 << kC1MaxR); ++k)
-            if (k < (1 << RA)) x[k] = z[lds_at<TS>(k, L.b, L.cs, RB)];
-    }
-    __syncthreads();
-    for (int r = L.half + 1; r < S; ++r) {
-        __syncthreads();
-        __syncthreads();
-    }
-}
-
-// The 2^RB points of value a of layout B (slot j) as a register block.
-template <typename T>
-__device__ __forceinline__ void c1_get(cpx<T> (&w)[1 << kC1MaxR], const cpx<T> (&x)[1 << kC1MaxR],
-                                       int j, int RB) {
-#pragma unroll
-    for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RB) && j * 16 + k < (1 << kC1MaxR)) w[k] = x[j * 16 + k];
-}
-template <typename T>
-__device__ __forceinline__ void c1_put(cpx<T> (&x)[1 << kC1MaxR], const cpx<T> (&w)[1 << kC1MaxR],
-                                       int j, int RB) {
-#pragma unroll
-    for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RB) && j * 16 + k < (1 << kC1MaxR)) x[j * 16 + k] = w[k];
+    return a * ((TC << RB) + kC1Pad) + b * TC + c;
 }
 
 // High-bit passes. Grid: (2^lgL low values l, tiles, jobs of the chunk);
-// block: 2^RB x TC threads, RB = lgB/2, lgB = lg - lgL; transposes in S
-// channel slices.
+// block: 2^RB x TC threads, RB = lgB/2, lgB = lg - lgL.
 // INV = false: gather the cells' channel pairs [tile TC, tile TC + TC) from
 // src (rows of d channels) at the points of low value l, DIF stages of bits
 // [lgL, lg), store to buf.
 // INV = true: load from buf, DIT stages of bits [lgL, lg), write the rows of
 // the occupied points to dst, scaled by 1/P.
-template <typename T, int TC, int S, bool INV>
+template <typename T, int TC, bool INV>
 __global__ void __launch_bounds__(512)
 k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int64_t mstride,
             int32_t d, const T* __restrict__ src, T* __restrict__ dst,
@@ -204,18 +120,18 @@ k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int6
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int lgB = lg - lgL, RB = lgB / 2, RA = lgB - RB;
-    const C1Lane<TC, S> L(RB);
-    const int b = L.b, c = L.c;
     const int64_t l = blockIdx.x;
     const int64_t slot = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
     const int32_t* mp = map + (int64_t)blockIdx.z * mstride;
     cpx<T>* sb = buf + (slot << lg) * TC;
+    const int c = threadIdx.x % TC;
+    const int b = threadIdx.x / TC;  // phase A: low bits; phase B: first high value
     const int32_t ch = 2 * (blockIdx.y * TC + c);
     const bool has0 = ch < d, has1 = ch + 1 < d;
     // points beyond xmax are zero: e <= emax
     const int64_t emax64 = (int64_t)xmax >= l ? (((int64_t)xmax - l) >> lgL) : -1;
     const int emax = (int)(emax64 < (1 << lgB) - 1 ? emax64 : (1 << lgB) - 1);
-    cpx<T> x[1 << kC1MaxR], w[1 << kC1MaxR];
+    cpx<T> x[1 << kC1MaxR];
     // every global load that does not depend on the data is issued first:
     // the stage factors of both phases and the map rows of phase A's points
     cpx<T> fsA[kC1MaxR], fsB[kC1MaxR];
@@ -239,38 +155,49 @@ k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int6
             }
         }
         reg_fft<T, false, true>(x, RA, fsA);
-        c1_transpose<T, TC, S, true>(z, x, L, RA, RB);
-        // phase B: points e = (a << RB) + k, a = b + j 2^RB
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int a = b + (j << RB);
-            if (a >= (1 << RA)) continue;
-            c1_get(w, x, j, RB);
-            reg_fft<T, false, true>(w, RB, fsB);
+        for (int k = 0; k < (1 << kC1MaxR); ++k)
+            if (k < (1 << RA)) z[lds_at<TC>(k, b, c, RB)] = x[k];
+        __syncthreads();
+        // phase B: points e = (a << RB) + k, a = b + j 2^RB
+        for (int a = b; a < (1 << RA); a += (1 << RB)) {
 #pragma unroll
             for (int k = 0; k < (1 << kC1MaxR); ++k)
-                if (k < (1 << RB)) sb[((((int64_t)a << RB) + k) << lgL | l) * TC + c] = w[k];
+                if (k < (1 << RB)) x[k] = z[lds_at<TC>(a, k, c, RB)];
+            reg_fft<T, false, true>(x, RB, fsB);
+#pragma unroll
+            for (int k = 0; k < (1 << kC1MaxR); ++k)
+                if (k < (1 << RB)) sb[((((int64_t)a << RB) + k) << lgL | l) * TC + c] = x[k];
         }
     } else {
-        // phase B first (DIT goes from the low bits up): the points of both
-        // values of a are loaded before either is transformed
+        // phase B first (DIT goes from the low bits up). RA - RB <= 1: a thread
+        // has one or two values of a, and the points of both (at most 32, slot
+        // j 16 + k) are loaded before either is transformed
+        cpx<T> y[1 << kC1MaxR];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int k = 0; k < 16 * (2 - j); ++k) {
                 const int a = b + (j << RB);
                 if (k < (1 << RB) && a < (1 << RA))
-                    x[j * 16 + k] = sb[((((int64_t)a << RB) + k) << lgL | l) * TC + c];
+                    y[j * 16 + k] = sb[((((int64_t)a << RB) + k) << lgL | l) * TC + c];
             }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int a = b + (j << RB);
             if (a >= (1 << RA)) continue;
-            c1_get(w, x, j, RB);
-            reg_fft<T, true, true>(w, RB, fsB);
-            c1_put(x, w, j, RB);
+#pragma unroll
+            for (int k = 0; k < (1 << kC1MaxR); ++k)
+                if (k < (1 << RB) && j * 16 + k < (1 << kC1MaxR)) x[k] = y[j * 16 + k];
+            reg_fft<T, true, true>(x, RB, fsB);
+#pragma unroll
+            for (int k = 0; k < (1 << kC1MaxR); ++k)
+                if (k < (1 << RB)) z[lds_at<TC>(a, k, c, RB)] = x[k];
         }
-        c1_transpose<T, TC, S, false>(z, x, L, RA, RB);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < (1 << kC1MaxR); ++k)
+            if (k < (1 << RA)) x[k] = z[lds_at<TC>(k, b, c, RB)];
         reg_fft<T, true, true>(x, RA, fsA);
         const T scale = (T)1 / (T)((int64_t)1 << lg);
 #pragma unroll
@@ -285,50 +212,68 @@ k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int6
 }
 
 // Low-bit pass. Grid: (2^(lg - lgL) high values h, tiles, jobs of the chunk);
-// block: 2^(lgL/2) x TC threads; transposes in S channel slices, the kernel
-// spectrum of the block staged in LDS after the transpose buffer. The 2^lgL
-// consecutive points x TC pairs of one h are contiguous in buf: DIF stages
-// of bits [0, lgL), product with the kernel spectrum, DIT stages, store back.
-template <typename T, int TC, int S>
+// block: 2^(lgL/2) x TC threads. The 2^lgL consecutive points x TC pairs of
+// one h are contiguous in buf: DIF stages of bits [0, lgL), product with the
+// kernel spectrum, DIT stages, store back.
+template <typename T, int TC>
 __global__ void __launch_bounds__(512)
 k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ spec,
             const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int RB = lgL / 2, RA = lgL - RB;
-    cpx<T>* zs = z + (1 << RA) * (((TC / S) << RB) + kC1Pad);  // spectrum block
-    const C1Lane<TC, S> L(RB);
-    const int b = L.b, c = L.c;
     const int64_t h = blockIdx.x;
     const int64_t slot = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
     cpx<T>* sb = buf + ((slot << lg) + (h << lgL)) * TC;
     const cpx<T>* sp = spec + (h << lgL);
-    for (int e = threadIdx.x; e < (1 << lgL); e += blockDim.x) zs[e] = sp[e];
-    cpx<T> x[1 << kC1MaxR], w[1 << kC1MaxR];
+    const int c = threadIdx.x % TC;
+    const int b = threadIdx.x / TC;
+    cpx<T> x[1 << kC1MaxR];
     cpx<T> fs[kC1MaxR];
     const cpx<T> one[kC1MaxR] = {};
+    // phase A: DIF of the high bits of the block index; the stage factors and
+    // the kernel spectrum of phase B's points (a = b + j 2^RB, j < 2; at most
+    // 32 values, slot j 16 + k) are loaded up front with the data
     stage_factors(fs, RA, RB, b, tw, lgtw);
-    // phase A: DIF of the high bits of the block index
+    cpx<T> spv[1 << kC1MaxR];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int k = 0; k < 16 * (2 - j); ++k) {
+            const int a = b + (j << RB);
+            if (k < (1 << RB) && a < (1 << RA)) spv[j * 16 + k] = sp[(a << RB) + k];
+        }
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)
         if (k < (1 << RA)) x[k] = sb[((k << RB) + b) * TC + c];
     reg_fft<T, false, true>(x, RA, fs);
-    c1_transpose<T, TC, S, true>(z, x, L, RA, RB);  // its barriers also cover zs
+#pragma unroll
+    for (int k = 0; k < (1 << kC1MaxR); ++k)
+        if (k < (1 << RA)) z[lds_at<TC>(k, b, c, RB)] = x[k];
+    __syncthreads();
     // phase B: DIF of the low bits, spectrum product, DIT of the low bits
+    // (RA - RB <= 1, so a thread has at most two values of a)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int a = b + (j << RB);
         if (a >= (1 << RA)) continue;
-        c1_get(w, x, j, RB);
-        reg_fft<T, false, false>(w, RB, one);
 #pragma unroll
         for (int k = 0; k < (1 << kC1MaxR); ++k)
-            if (k < (1 << RB)) w[k] = cmul(w[k], zs[(a << RB) + k]);
-        reg_fft<T, true, false>(w, RB, one);
-        c1_put(x, w, j, RB);
+            if (k < (1 << RB)) x[k] = z[lds_at<TC>(a, k, c, RB)];
+        reg_fft<T, false, false>(x, RB, one);
+#pragma unroll
+        for (int k = 0; k < (1 << kC1MaxR); ++k)
+            if (k < (1 << RB) && j * 16 + k < (1 << kC1MaxR)) x[k] = cmul(x[k], spv[j * 16 + k]);
+        reg_fft<T, true, false>(x, RB, one);
+#pragma unroll
+        for (int k = 0; k < (1 << kC1MaxR); ++k)
+            if (k < (1 << RB)) z[lds_at<TC>(a, k, c, RB)] = x[k];
     }
-    c1_transpose<T, TC, S, false>(z, x, L, RA, RB);
+    __syncthreads();
     // phase A again: DIT of the high bits
+#pragma unroll
+    for (int k = 0; k < (1 << kC1MaxR); ++k)
+        if (k < (1 << RA)) x[k] = z[lds_at<TC>(k, b, c, RB)];
     reg_fft<T, true, true>(x, RA, fs);
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)

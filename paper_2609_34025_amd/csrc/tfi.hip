@@ -21,7 +21,9 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -354,6 +356,37 @@ int check_handle(tfi_handle h, bool need_device) {
 template <typename T>
 int conv1d_lds_optin(int lds);
 
+// LDS beyond 64 KiB needs an opt-in per kernel. The attribute belongs to
+// the kernel in this process on the current device, so it is set once per
+// device, not per handle.
+int lds_optin_once(int device, int lds) {
+    static std::mutex mu;
+    static std::set<int> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count(device)) return TFI_OK;
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<float>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    int rc1 = conv1d_lds_optin<float>(lds);
+    if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
+    if (rc1) return rc1;
+    done.insert(device);
+    return TFI_OK;
+}
+
 int upload_static(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
@@ -495,27 +528,8 @@ int upload_static(tfi_plan* h) {
         if ((rc = h->upload(&h->d_lgk, gk))) return rc;
         if ((rc = h->upload(&h->d_lbin, lbin))) return rc;
     }
-    // LDS beyond 64 KiB needs an opt-in per kernel
     if (h->lds_max > 65536) {
-        const int lds = (int)h->lds_max;
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<float>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-        int rc1 = conv1d_lds_optin<float>(lds);
-        if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
+        const int rc1 = lds_optin_once(h->device, (int)h->lds_max);
         if (rc1) return rc1;
     }
     // sweep evaluator job lists (exponential-sum kernels)
@@ -586,22 +600,15 @@ int upload_static(tfi_plan* h) {
 // Device structures that depend on the per-job method (direct blocks, FFT
 // buckets and their LDS tiers); rebuilt when the methods are re-assigned.
 // LDS beyond 64 KiB for the 1-D convolution kernels of every channel tile.
-template <typename T, int TC, int S>
-int conv1d_lds_optin_ts(int lds) {
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, S, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, S, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC, S>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    return TFI_OK;
-}
-
 template <typename T, int TC>
 int conv1d_lds_optin_tc(int lds) {
-    int rc = conv1d_lds_optin_ts<T, TC, 1>(lds);
-    if (!rc && TC >= 8) rc = conv1d_lds_optin_ts<T, TC, (TC >= 8 ? 2 : 1)>(lds);
-    return rc;
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    return TFI_OK;
 }
 
 template <typename T>
@@ -971,48 +978,27 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     const int64_t job_bytes = (int64_t)ntiles * TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
     const int64_t jpc =
         std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)buf_bytes / job_bytes));
-    // Block transforms of 2^lgB points: 2^RB x TC threads, transposes through
-    // an LDS buffer of 2^RA rows x (2^RB x TC/S + pad) complex in S channel
-    // slices. Two slices (more workgroups per CU) only when a slice is whole
-    // wavefronts (every lane of a wavefront passes the same barriers).
+    // LDS block: 2^RA rows of (2^RB x TC + pad) complex; 2^RB x TC threads
     const int hRB = lgH / 2, hRA = lgH - hRB, lRB = lgL / 2, lRA = lgL - lRB;
-    constexpr int S2 = TC >= 8 ? 2 : 1;
-    const int sh = (S2 == 2 && ((TC / 2) << hRB) % 64 == 0) ? 2 : 1;
-    const int sl = (S2 == 2 && ((TC / 2) << lRB) % 64 == 0) ? 2 : 1;
-    const size_t cs = sizeof(tfi::cpx<T>);
-    const unsigned lds_hi =
-        (unsigned)(((size_t)1 << hRA) * (size_t)(((TC / sh) << hRB) + tfi::kC1Pad) * cs);
-    const unsigned lds_lo =
-        (unsigned)((((size_t)1 << lRA) * (size_t)(((TC / sl) << lRB) + tfi::kC1Pad) +
-                    ((size_t)1 << lgL)) * cs);
+    const unsigned lds_hi = (unsigned)(((int64_t)1 << hRA) * ((TC << hRB) + tfi::kC1Pad) *
+                                       sizeof(tfi::cpx<T>));
+    const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((TC << lRB) + tfi::kC1Pad) *
+                                       sizeof(tfi::cpx<T>));
     const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(TC << lRB);
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
         const int32_t* map = bmap + j0 * b.mstride;
-        const dim3 ghi(1u << lgL, (unsigned)ntiles, (unsigned)nj);
-        const dim3 glo(1u << lgH, (unsigned)ntiles, (unsigned)nj);
-        if (sh == 2)
-            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, S2, false>), ghi, dim3(thr_hi), lds_hi,
-                               st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
-                               tw, h->lgtw);
-        else
-            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, 1, false>), ghi, dim3(thr_hi), lds_hi,
-                               st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
-                               tw, h->lgtw);
-        if (sl == 2)
-            hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC, S2>), glo, dim3(thr_lo), lds_lo, st, lg,
-                               lgL, buf, spec + b.spec_off, tw, h->lgtw);
-        else
-            hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC, 1>), glo, dim3(thr_lo), lds_lo, st, lg,
-                               lgL, buf, spec + b.spec_off, tw, h->lgtw);
-        if (sh == 2)
-            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, S2, true>), ghi, dim3(thr_hi), lds_hi,
-                               st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g, buf,
-                               tw, h->lgtw);
-        else
-            hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, 1, true>), ghi, dim3(thr_hi), lds_hi,
-                               st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g, buf,
-                               tw, h->lgtw);
+        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, false>),
+                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
+                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
+                           tw, h->lgtw);
+        hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC>),
+                           dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
+                           lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
+        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, true>),
+                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
+                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g,
+                           buf, tw, h->lgtw);
     }
 }
 
