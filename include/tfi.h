@@ -161,6 +161,25 @@ int tfi_integrate(tfi_handle h, const void *f, const void *F, int64_t d,
                   tfi_dtype dtype, void *out, void *stream);
 
 /*
+ * Several kernels over one field: out[i] = K_i F with K_i[v, w] =
+ * f[i](dist(v, w)), for i < nk (Section 1, equation "integration", once per
+ * kernel). The cell sums of F (equation "stad-E" and the A-cells of
+ * Section 2.2) do not depend on the kernel, so they are formed once; each
+ * kernel then has its own spectra, tables, leaf tiles and gather. Each
+ * out[i] equals what tfi_integrate(h, f[i], F, ...) writes, bit for bit.
+ *   nk   1 <= nk <= TFI_MULTI_MAX
+ *   f    host array of nk device pointers, each dtype[tfi_kernel_length(h)]
+ *   F    device dtype[N x d]
+ *   out  host array of nk device pointers, each dtype[N x d]; distinct, none
+ *        aliasing F
+ * Scratch grows with nk: nk table arrays and nk spectrum arenas.
+ * Errors: as tfi_integrate.
+ */
+#define TFI_MULTI_MAX 4
+int tfi_integrate_multi(tfi_handle h, int32_t nk, const void *const *f, const void *F,
+                        int64_t d, tfi_dtype dtype, void *const *out, void *stream);
+
+/*
  * Adjoint of tfi_integrate for the loss L = sum(gout * out):
  *   dF = K gout (K is symmetric), device dtype[N x d], may be NULL;
  *   df[k] = sum_{v, w : dist(v, w) = k} <gout[v, :], F[w, :]>, the

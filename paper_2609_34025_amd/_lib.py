@@ -45,7 +45,8 @@ _lib = None
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
             "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
-            "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate"]
+            "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
+            "tfi_integrate_multi"]
 
 
 def load():
@@ -84,6 +85,9 @@ def load():
     lib.tfi_set_fft_cost.restype = C.c_int
     lib.tfi_calibrate.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
     lib.tfi_calibrate.restype = C.c_int
+    lib.tfi_integrate_multi.argtypes = [vp, C.c_int32, C.POINTER(vp), vp, i64, C.c_int,
+                                        C.POINTER(vp), vp]
+    lib.tfi_integrate_multi.restype = C.c_int
     lib.tfi_integrate_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, i64, C.c_int, vp, vp]
     lib.tfi_integrate_expsum.restype = C.c_int
     lib.tfi_backward_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp,

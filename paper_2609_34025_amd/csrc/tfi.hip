@@ -95,10 +95,10 @@ struct DeviceBuf {
 struct GraphKey {
     int kind = 0, dtype = 0, n = 0;
     int64_t d = 0;
-    const void* p[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const void* p[12] = {};
     bool operator==(const GraphKey& o) const {
         if (kind != o.kind || dtype != o.dtype || n != o.n || d != o.d) return false;
-        for (int i = 0; i < 8; ++i)
+        for (int i = 0; i < 12; ++i)
             if (p[i] != o.p[i]) return false;
         return true;
     }
@@ -1068,9 +1068,10 @@ bool path_direct(const tfi_plan* h, int32_t d) {
 }
 
 // Scratch of a forward (or of dF); `general` asks for the value and table
-// rows even where whole-path mode would not use them.
+// rows even where whole-path mode would not use them; nk kernels in one
+// call take nk table arrays and nk spectrum arenas.
 template <typename T>
-int prepare_forward(tfi_plan* h, int32_t d, bool general = false) {
+int prepare_forward(tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
     int rc;
@@ -1078,11 +1079,11 @@ int prepare_forward(tfi_plan* h, int32_t d, bool general = false) {
     if (rows &&
         (rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
         return rc;
-    if (rows &&
-        (rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
+    if (rows && (rc = h->ensure(h->g[ti], (size_t)nk * std::max<int64_t>(p.NA + p.NB, 1) * d *
+                                              sizeof(T))))
         return rc;
-    if ((rc = h->ensure(h->spec[ti],
-                        (size_t)std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>))))
+    if ((rc = h->ensure(h->spec[ti], (size_t)nk * std::max<int64_t>(h->spec_elems, 1) *
+                                         sizeof(tfi::cpx<T>))))
         return rc;
     // workspace for buckets beyond LDS: chunks of at most 2 GiB, or one
     // job's slots when a job alone is larger
@@ -1124,10 +1125,12 @@ void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_
            2.0 * d * (double)p.leaf_pairs);
 }
 
+// Kernel spectra of every FFT bucket into spec (default: the handle's arena;
+// several kernels of one call use consecutive arenas).
 template <typename T>
-void enq_spectra(tfi_plan* h, const T* f, hipStream_t st) {
+void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nullptr) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    tfi::cpx<T>* spec = (tfi::cpx<T>*)h->spec[ti].p;
+    if (!spec) spec = (tfi::cpx<T>*)h->spec[ti].p;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     for (int t = 0; t < 3; ++t) {
         const Tier& T_ = h->tiers[ti][t];
@@ -1149,9 +1152,10 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st) {
 }
 
 template <typename T>
-void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st) {
+void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st,
+             const tfi::cpx<T>* spec = nullptr) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    const tfi::cpx<T>* spec = (const tfi::cpx<T>*)h->spec[ti].p;
+    if (!spec) spec = (const tfi::cpx<T>*)h->spec[ti].p;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const int32_t npairs = (d + 1) / 2;
     const double sz = (double)sizeof(T);
@@ -1352,10 +1356,11 @@ inline void fork3(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
 // Whole-path mode: kernel spectra, then the convolution of every job from the
 // field rows straight into the output rows.
 template <typename T>
-void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st,
+                  tfi::cpx<T>* spec = nullptr) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    enq_spectra<T>(h, f, st);
-    const tfi::cpx<T>* spec = (const tfi::cpx<T>*)h->spec[ti].p;
+    if (!spec) spec = (tfi::cpx<T>*)h->spec[ti].p;
+    enq_spectra<T>(h, f, st, spec);
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const double sz = (double)sizeof(T);
     for (int bi : h->global_b[ti]) {
@@ -1391,6 +1396,38 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     enq_gather<T>(h, d, g, out, s0);            // main: out = leaf + calls
+}
+
+// Several kernels over one field: the cell sums depend only on F, so the
+// scatter runs once; kernel i has its own spectra, tables (rows i of the
+// table arrays), leaf rows and gather into out[i].
+template <typename T>
+void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, int32_t d,
+                           T* const* out, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const tfi::Plan& p = h->plan;
+    tfi::cpx<T>* spec0 = (tfi::cpx<T>*)h->spec[ti].p;
+    const int64_t sstride = std::max<int64_t>(h->spec_elems, 1);
+    if (path_direct<T>(h, d)) {
+        for (int i = 0; i < nk; ++i) enqueue_path<T>(h, f[i], F, d, out[i], s0, spec0 + i * sstride);
+        return;
+    }
+    T* val = (T*)h->val[ti].p;
+    T* g0 = (T*)h->g[ti].p;
+    const int64_t gstride = std::max<int64_t>(p.NA + p.NB, 1) * (int64_t)d;
+    fork3(h, s0, s1, s2);
+    for (int i = 0; i < nk; ++i) enq_leaf<T>(h, f[i], F, d, out[i], s2);
+    (void)hipEventRecord(h->ev_c, s2);
+    for (int i = 0; i < nk; ++i) enq_spectra<T>(h, f[i], s1, spec0 + i * sstride);
+    launch_scatter<T>(h, F, val, d, s0);
+    (void)hipEventRecord(h->ev_a, s0);
+    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+    for (int i = 0; i < nk; ++i) enq_fft<T>(h, d, val, g0 + i * gstride, s1, spec0 + i * sstride);
+    (void)hipEventRecord(h->ev_b, s1);
+    for (int i = 0; i < nk; ++i) enq_direct<T>(h, f[i], d, val, g0 + i * gstride, s0);
+    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    for (int i = 0; i < nk; ++i) enq_gather<T>(h, d, g0 + i * gstride, out[i], s0);
 }
 
 // Enqueue the adjoint: dF = f(D) gout (when dF != null) and the kernel-table
@@ -1530,6 +1567,26 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     key.p[2] = out;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
         enqueue_forward<T>(h, f, F, d, out, a, b, c);
+    });
+}
+
+template <typename T>
+int run_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, int32_t d,
+                      T* const* out, hipStream_t st) {
+    int rc = prepare_forward<T>(h, d, false, nk);
+    if (rc) return rc;
+    GraphKey key;
+    key.kind = 5;
+    key.dtype = sizeof(T) == 8;
+    key.n = nk;
+    key.d = d;
+    key.p[0] = F;
+    for (int i = 0; i < nk; ++i) {
+        key.p[1 + 2 * i] = f[i];
+        key.p[2 + 2 * i] = out[i];
+    }
+    return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
+        enqueue_forward_multi<T>(h, nk, f, F, d, out, a, b, c);
     });
 }
 
@@ -1937,6 +1994,33 @@ int tfi_integrate(tfi_handle h, const void* f, const void* F, int64_t d, tfi_dty
         return run_forward<double>(h, (const double*)f, (const double*)F, (int32_t)d,
                                    (double*)out, st);
     return fail(TFI_ERR_DTYPE, "tfi_integrate: unknown dtype");
+}
+
+int tfi_integrate_multi(tfi_handle h, int32_t nk, const void* const* f, const void* F,
+                        int64_t d, tfi_dtype dtype, void* const* out, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (nk < 1 || nk > TFI_MULTI_MAX)
+        return fail(TFI_ERR_ARG, "tfi_integrate_multi: need 1 <= nk <= TFI_MULTI_MAX");
+    if (!f || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate_multi: null pointer");
+    if (d < 1 || d > (1 << 20))
+        return fail(TFI_ERR_ARG, "tfi_integrate_multi: need 1 <= d <= 2^20");
+    for (int i = 0; i < nk; ++i) {
+        if (!f[i] || !out[i]) return fail(TFI_ERR_ARG, "tfi_integrate_multi: null pointer");
+        if (out[i] == F) return fail(TFI_ERR_ARG, "tfi_integrate_multi: out must not alias F");
+        for (int j = 0; j < i; ++j)
+            if (out[j] == out[i])
+                return fail(TFI_ERR_ARG, "tfi_integrate_multi: outputs must be distinct");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return run_forward_multi<float>(h, nk, (const float* const*)f, (const float*)F,
+                                        (int32_t)d, (float* const*)out, st);
+    if (dtype == TFI_F64)
+        return run_forward_multi<double>(h, nk, (const double* const*)f, (const double*)F,
+                                         (int32_t)d, (double* const*)out, st);
+    return fail(TFI_ERR_DTYPE, "tfi_integrate_multi: unknown dtype");
 }
 
 int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, int64_t d,

@@ -176,6 +176,29 @@ class TreeIntegrator:
                                      self._stream(self.device)))
         return out
 
+    def integrate_many(self, fs, F):
+        """[f_i(D) F for f_i in fs] in one call (at most 4 kernel tables of
+        one dtype): the cell sums of F are formed once for all kernels."""
+        fs = list(fs)
+        if not 1 <= len(fs) <= 4:
+            raise ValueError("integrate_many takes 1 to 4 kernel tables")
+        if any(f.dtype != fs[0].dtype for f in fs):
+            raise TypeError("kernel tables must share one dtype")
+        for f in fs:
+            self._check(f, F)
+        d = 1 if F.dim() == 1 else F.shape[1]
+        outs = [torch.empty_like(F) for _ in fs]
+        if d == 0:
+            return outs
+        lib = _lib.load()
+        vp = C.c_void_p
+        fp = (vp * len(fs))(*[f.data_ptr() for f in fs])
+        op = (vp * len(fs))(*[o.data_ptr() for o in outs])
+        _lib.check(lib.tfi_integrate_multi(self._h, len(fs), fp, F.data_ptr(), d,
+                                           _DTYPES[fs[0].dtype], op,
+                                           self._stream(self.device)))
+        return outs
+
     def backward(self, f, F, gout, need_dF=True, need_df=True):
         """Adjoint of ``integrate`` for L = sum(gout * out): returns
         ``(dF, df)``; df is float64 of length ``kernel_length``."""
