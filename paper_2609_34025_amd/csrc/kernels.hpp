@@ -276,6 +276,8 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
 // kernel entry (0 outside its row's job) and uses it for the NCH 16-channel
 // chunks of a pass, whose values come from an LDS tile of source cells x
 // 16 NCH channels. Blocks, padding and job ranges are those of k_direct.
+// NK = 2 evaluates two kernel tables (f, f1 into g, g1) over the same value
+// tiles: each lane forms one entry per kernel and the B operand is shared.
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 constexpr int kMfSrc = kDirOut;  // source cells per LDS tile (one chunk)
 
@@ -288,13 +290,13 @@ struct MfTile {
     static constexpr int stride = NCH == 1 ? 16 : NCH <= 3 ? 48 : 80;
 };
 
-template <int NCH>
+template <int NCH, int NK>
 __global__ void __launch_bounds__(kDirThreads)
 k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
               const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
               const int32_t* __restrict__ qjb, const int32_t* __restrict__ qje,
-              const float* __restrict__ f, int32_t flds, const float* __restrict__ val,
-              float* __restrict__ g) {
+              const float* __restrict__ f, const float* __restrict__ f1, int32_t flds,
+              const float* __restrict__ val, float* __restrict__ g, float* __restrict__ g1) {
     constexpr int ROWS = MfTile<NCH>::rows, SV = MfTile<NCH>::stride;
     constexpr int PER = ROWS / 16;  // staged rows per thread
     __shared__ __attribute__((aligned(16))) float sv[ROWS * SV];
@@ -303,10 +305,16 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
     float* sf = reinterpret_cast<float*>(dyn_raw);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
-    const float* fp = f;
+    const float* fp[NK];
+    fp[0] = f;
+    if (NK > 1) fp[NK - 1] = f1;
     if (flds > 0) {
-        for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) sf[k] = f[k];
-        fp = sf;
+        for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) {
+            sf[k] = f[k];
+            if (NK > 1) sf[flds + k] = f1[k];
+        }
+#pragma unroll
+        for (int u = 0; u < NK; ++u) fp[u] = sf + u * flds;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;  // A row / k of this lane
@@ -331,11 +339,13 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
     }
     // passes of NCH chunks: this workgroup takes every gridDim.y-th one
     for (int32_t c0 = blockIdx.y * 16 * NCH; c0 < d; c0 += gridDim.y * 16 * NCH) {
-        v4f_t acc[NCH][4];
+        v4f_t acc[NK][NCH][4];
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
+        for (int u = 0; u < NK; ++u)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[ch][q] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u][ch][q] = (v4f_t){0.f, 0.f, 0.f, 0.f};
         for (int32_t ts = ss; ts < se; ts += ROWS) {
             const int32_t tn = min(ROWS, se - ts);
             __syncthreads();
@@ -390,14 +400,21 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (k4 < kb[q] || k4 >= ke[q]) continue;  // uniform per wave
-                    float a = 0.f;
-                    if (k >= jb[q] && k < je[q]) {
+                    float a[NK];
+#pragma unroll
+                    for (int u = 0; u < NK; ++u) a[u] = 0.f;
+                    if (k >= jb[q] && k < je[q]) {  // entries of the lane's own job only
                         const int32_t dx = xi[q] - xk;
-                        a = fp[ri[q] + rk + (dx < 0 ? -dx : dx)];
+                        const int32_t e = ri[q] + rk + (dx < 0 ? -dx : dx);
+#pragma unroll
+                        for (int u = 0; u < NK; ++u) a[u] = fp[u][e];
                     }
 #pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch)
-                        acc[ch][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[ch], acc[ch][q], 0, 0, 0);
+                    for (int u = 0; u < NK; ++u)
+#pragma unroll
+                        for (int ch = 0; ch < NCH; ++ch)
+                            acc[u][ch][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a[u], b[ch], acc[u][ch][q], 0, 0, 0);
                 }
             }
         }
@@ -415,7 +432,10 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int32_t c = c0 + 16 * ch + lr;
-                    if (c < d) g[(int64_t)row * d + c] = acc[ch][q][r];
+                    if (c < d) {
+                        g[(int64_t)row * d + c] = acc[0][ch][q][r];
+                        if (NK > 1) g1[(int64_t)row * d + c] = acc[NK - 1][ch][q][r];
+                    }
                 }
             }
         }
@@ -429,63 +449,83 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
 // vertex, the call's table value minus the component correction (row -1
 // when the vertex is on the call's backbone), on top of the leaf-tile value
 // already stored in out for vertices of leaf tiles. Writes every out row.
+// NK = 2 gathers the tables g, g1 of two kernels into out, out1 with one
+// pass over the index lists (the summation order of each is unchanged).
 constexpr int kGatherBatch = 4;
 
-template <typename T, int VEC>
+template <typename T, int VEC, int NK>
 __global__ void k_gather(int64_t N, int32_t d, int32_t ct, const int64_t* __restrict__ v_off,
                          const int32_t* __restrict__ ga, const int32_t* __restrict__ gb,
                          const int8_t* __restrict__ vleaf, const T* __restrict__ g,
-                         T* __restrict__ out) {
+                         const T* __restrict__ g1, T* __restrict__ out, T* __restrict__ out1) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t v;
     int32_t c;
     if (!tile_coords<VEC>(tid, N, d, ct, v, c) || v >= N) return;
+    const T* gk[NK];
+    T* ok[NK];
+    gk[0] = g;
+    ok[0] = out;
+    if (NK > 1) {
+        gk[NK - 1] = g1;
+        ok[NK - 1] = out1;
+    }
     const int64_t k0 = v_off[v], k1 = v_off[v + 1];
     const bool leaf = vleaf[v] != 0;  // out already holds the leaf tile value
-    vec4<T> s = {0, 0, 0, 0};
-    if (leaf) {
-        if (VEC == 4) s = ld4(out + v * d + c);
-        else s.x = out[v * d + c];
+    vec4<T> s[NK];
+#pragma unroll
+    for (int u = 0; u < NK; ++u) {
+        s[u] = {0, 0, 0, 0};
+        if (leaf) {
+            if (VEC == 4) s[u] = ld4(ok[u] + v * d + c);
+            else s[u].x = ok[u][v * d + c];
+        }
     }
     // calls taken kGatherBatch at a time: indices first, then table rows
     for (int64_t kk = k0; kk < k1; kk += kGatherBatch) {
         int32_t a[kGatherBatch], b[kGatherBatch];
 #pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) {
-            const int64_t k = min(kk + u, k1 - 1);
-            a[u] = ga[k];
-            b[u] = gb[k];
+        for (int w = 0; w < kGatherBatch; ++w) {
+            const int64_t k = min(kk + w, k1 - 1);
+            a[w] = ga[k];
+            b[w] = gb[k];
         }
-        if (VEC == 4) {
-            vec4<T> ra[kGatherBatch], rb[kGatherBatch];
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) {
-                ra[u] = ld4(g + (int64_t)a[u] * d + c);
-                rb[u] = ld4(g + (int64_t)(b[u] >= 0 ? b[u] : a[u]) * d + c);
-            }
+        for (int u = 0; u < NK; ++u) {
+            if (VEC == 4) {
+                vec4<T> ra[kGatherBatch], rb[kGatherBatch];
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) {
-                if (kk + u >= k1) continue;
-                add4(s, ra[u]);
-                if (b[u] >= 0) sub4(s, rb[u]);
-            }
-        } else {
-            T ra[kGatherBatch], rb[kGatherBatch];
+                for (int w = 0; w < kGatherBatch; ++w) {
+                    ra[w] = ld4(gk[u] + (int64_t)a[w] * d + c);
+                    rb[w] = ld4(gk[u] + (int64_t)(b[w] >= 0 ? b[w] : a[w]) * d + c);
+                }
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) {
-                ra[u] = g[(int64_t)a[u] * d + c];
-                rb[u] = g[(int64_t)(b[u] >= 0 ? b[u] : a[u]) * d + c];
-            }
+                for (int w = 0; w < kGatherBatch; ++w) {
+                    if (kk + w >= k1) continue;
+                    add4(s[u], ra[w]);
+                    if (b[w] >= 0) sub4(s[u], rb[w]);
+                }
+            } else {
+                T ra[kGatherBatch], rb[kGatherBatch];
 #pragma unroll
-            for (int u = 0; u < kGatherBatch; ++u) {
-                if (kk + u >= k1) continue;
-                s.x += ra[u];
-                if (b[u] >= 0) s.x -= rb[u];
+                for (int w = 0; w < kGatherBatch; ++w) {
+                    ra[w] = gk[u][(int64_t)a[w] * d + c];
+                    rb[w] = gk[u][(int64_t)(b[w] >= 0 ? b[w] : a[w]) * d + c];
+                }
+#pragma unroll
+                for (int w = 0; w < kGatherBatch; ++w) {
+                    if (kk + w >= k1) continue;
+                    s[u].x += ra[w];
+                    if (b[w] >= 0) s[u].x -= rb[w];
+                }
             }
         }
     }
-    if (VEC == 4) st4(out + v * d + c, s);
-    else out[v * d + c] = s.x;
+#pragma unroll
+    for (int u = 0; u < NK; ++u) {
+        if (VEC == 4) st4(ok[u] + v * d + c, s[u]);
+        else ok[u][v * d + c] = s[u].x;
+    }
 }
 
 // ----------------------------------------------------------- leaf tiles --

@@ -1178,59 +1178,92 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st,
     }
 }
 
+// Direct tables of one kernel (f into g), or of two (also f1 into g1): on
+// the matrix cores both share one launch and its value tiles; otherwise one
+// launch each.
 template <typename T>
-void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStream_t st) {
+void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStream_t st,
+                const T* f1 = nullptr, T* g1 = nullptr) {
     if (h->ndblk == 0) return;
     const tfi::Plan& p = h->plan;
-    hipEvent_t ev = h->begin(st);
-    const int32_t flds = (p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
+    const int nk = f1 ? 2 : 1;
     const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
+    if (!mfma && f1) {
+        enq_direct<T>(h, f, d, val, g, st);
+        enq_direct<T>(h, f1, d, val, g1, st);
+        return;
+    }
+    hipEvent_t ev = h->begin(st);
+    const int32_t flds =
+        (nk * p.kernel_len * (int64_t)sizeof(T) <= 16384) ? (int32_t)p.kernel_len : 0;
     if (mfma) {
         // 16-channel chunks per pass: one kernel entry serves all of them
         const int nch = d > 48 ? 4 : d > 32 ? 3 : d > 16 ? 2 : 1;
         const unsigned ys = chan_split(h->ndblk, d, 16 * nch);
+        const unsigned lds = (unsigned)(nk * flds * sizeof(float));
         auto launch = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk, ys), dim3(tfi::kDirThreads),
-                               (unsigned)(flds * sizeof(float)), st, d, h->d_dblk, h->d_dl_r,
-                               h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, (const float*)f, flds,
-                               (const float*)val, (float*)g);
+            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk, ys), dim3(tfi::kDirThreads), lds, st,
+                               d, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
+                               h->d_qje, (const float*)f, (const float*)f1, flds,
+                               (const float*)val, (float*)g, (float*)g1);
         };
-        switch (nch) {
-            case 4: launch(tfi::k_direct_mfma<4>); break;
-            case 3: launch(tfi::k_direct_mfma<3>); break;
-            case 2: launch(tfi::k_direct_mfma<2>); break;
-            default: launch(tfi::k_direct_mfma<1>); break;
+        if (nk == 2) {
+            switch (nch) {
+                case 4: launch(tfi::k_direct_mfma<4, 2>); break;
+                case 3: launch(tfi::k_direct_mfma<3, 2>); break;
+                case 2: launch(tfi::k_direct_mfma<2, 2>); break;
+                default: launch(tfi::k_direct_mfma<1, 2>); break;
+            }
+        } else {
+            switch (nch) {
+                case 4: launch(tfi::k_direct_mfma<4, 1>); break;
+                case 3: launch(tfi::k_direct_mfma<3, 1>); break;
+                case 2: launch(tfi::k_direct_mfma<2, 1>); break;
+                default: launch(tfi::k_direct_mfma<1, 1>); break;
+            }
         }
-    }
-    else
+    } else {
         hipLaunchKernelGGL(tfi::k_direct<T>,
                            dim3((unsigned)h->ndblk, chan_split(h->ndblk, d, tfi::kDirCh)),
-                           dim3(tfi::kDirThreads),
-                           (unsigned)(flds * sizeof(T)), st, d, h->d_dblk, h->d_dl_r, h->d_dl_x,
-                           h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val, g);
+                           dim3(tfi::kDirThreads), (unsigned)(flds * sizeof(T)), st, d, h->d_dblk,
+                           h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val,
+                           g);
+    }
+    // bytes: the value rows once, the table rows of every kernel
     h->end(st, ev, mfma ? "direct_mfma" : "direct",
-           2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
-           2.0 * d * h->direct_pairs);
+           sizeof(T) * d * (double)h->ndirect * (1 + nk) + 20.0 * h->ndirect,
+           2.0 * nk * d * h->direct_pairs);
 }
 
+// Gather of one kernel's tables (g into out), or of two (also g1 into out1)
+// in one pass over the index lists.
 template <typename T>
-void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st) {
+void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st,
+                const T* g1 = nullptr, T* out1 = nullptr) {
     const tfi::Plan& p = h->plan;
+    const int nk = g1 ? 2 : 1;
     hipEvent_t ev = h->begin(st);
-    if (d % 4 == 0 && aligned16(out)) {
-        const int32_t ct = col_tile<T>(d, 4);
-        hipLaunchKernelGGL((tfi::k_gather<T, 4>), dim3(blocks_for(tiled_threads(p.N, d / 4, ct))),
-                           dim3(kThreads), 0, st, p.N, d, ct, h->d_v_off, h->d_ga, h->d_gb,
-                           h->d_vleaf, g, out);
-    } else {
-        const int32_t ct = col_tile<T>(d, 1);
-        hipLaunchKernelGGL((tfi::k_gather<T, 1>), dim3(blocks_for(tiled_threads(p.N, d, ct))),
-                           dim3(kThreads), 0, st, p.N, d, ct, h->d_v_off, h->d_ga, h->d_gb,
-                           h->d_vleaf, g, out);
-    }
+    const bool v4 = d % 4 == 0 && aligned16(out) && (!out1 || aligned16(out1));
+    const int vec = v4 ? 4 : 1;
+    const int32_t ct = col_tile<T>(d, vec);
+    const dim3 grid(blocks_for(tiled_threads(p.N, d / vec, ct)));
+    if (v4 && nk == 2)
+        hipLaunchKernelGGL((tfi::k_gather<T, 4, 2>), grid, dim3(kThreads), 0, st, p.N, d, ct,
+                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, g1, out, out1);
+    else if (v4)
+        hipLaunchKernelGGL((tfi::k_gather<T, 4, 1>), grid, dim3(kThreads), 0, st, p.N, d, ct,
+                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, (const T*)nullptr, out,
+                           (T*)nullptr);
+    else if (nk == 2)
+        hipLaunchKernelGGL((tfi::k_gather<T, 1, 2>), grid, dim3(kThreads), 0, st, p.N, d, ct,
+                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, g1, out, out1);
+    else
+        hipLaunchKernelGGL((tfi::k_gather<T, 1, 1>), grid, dim3(kThreads), 0, st, p.N, d, ct,
+                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, (const T*)nullptr, out,
+                           (T*)nullptr);
     h->end(st, ev, "gather",
-           sizeof(T) * d * (double)(h->gather_reads + 2 * p.N) + 8.0 * (double)p.v_b.size() +
-               9.0 * p.N);
+           nk * sizeof(T) * d * (double)(h->gather_reads + 2 * p.N) +
+               8.0 * (double)p.v_b.size() + 9.0 * p.N);
 }
 
 // LDS budget of the df FFT passes for one bucket (3 tables), 0 if the
@@ -1424,10 +1457,20 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     (void)hipStreamWaitEvent(s1, h->ev_a, 0);
     for (int i = 0; i < nk; ++i) enq_fft<T>(h, d, val, g0 + i * gstride, s1, spec0 + i * sstride);
     (void)hipEventRecord(h->ev_b, s1);
-    for (int i = 0; i < nk; ++i) enq_direct<T>(h, f[i], d, val, g0 + i * gstride, s0);
+    // kernels in pairs: one launch per pair for the direct tables and the
+    // gather
+    for (int i = 0; i < nk; i += 2) {
+        const bool two = i + 1 < nk;
+        enq_direct<T>(h, f[i], d, val, g0 + i * gstride, s0, two ? f[i + 1] : nullptr,
+                      two ? g0 + (i + 1) * gstride : nullptr);
+    }
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
-    for (int i = 0; i < nk; ++i) enq_gather<T>(h, d, g0 + i * gstride, out[i], s0);
+    for (int i = 0; i < nk; i += 2) {
+        const bool two = i + 1 < nk;
+        enq_gather<T>(h, d, g0 + i * gstride, out[i], s0,
+                      two ? g0 + (i + 1) * gstride : nullptr, two ? out[i + 1] : nullptr);
+    }
 }
 
 // Enqueue the adjoint: dF = f(D) gout (when dF != null) and the kernel-table
