@@ -32,10 +32,15 @@
 // a compile-time 32nd root of unity times one factor per stage (s = shift + u,
 // j0 = the index bits below shift), loaded once per phase.
 //
-// Cells reach the kernels through map[job * mstride + x] = source row of the
-// cell at backbone coordinate x, or -1 (unoccupied lattice point); points
-// beyond xmax are zero. Two real channels ride in one complex value, as in
-// the other FFT paths.
+// Cells reach the kernels through map[job * mstride + c] = row of the cell
+// at coordinate c <= cmax, or -1 (unoccupied lattice point). A one-row table
+// (H = 0) is indexed by the backbone coordinate x: source and output at
+// point x. A one-column table (a single backbone position: G(q) =
+// sum_r f(q + r) A_r, the Hankel product of a centroid call or of a
+// correction) is indexed by the depth r: the source sits at point -r mod P
+// (reflect), so that the circular convolution puts f(q + r) A_r at output
+// point q. Two real channels ride in one complex value, as in the other FFT
+// paths.
 #pragma once
 
 #include "kernels.hpp"
@@ -114,8 +119,8 @@ __device__ __forceinline__ int lds_at(int a, int b, int c, int RB) {
 // the occupied points to dst, scaled by 1/P.
 template <typename T, int TC, bool INV>
 __global__ void __launch_bounds__(512)
-k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int64_t mstride,
-            int32_t d, const T* __restrict__ src, T* __restrict__ dst,
+k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restrict__ map,
+            int64_t mstride, int32_t d, const T* __restrict__ src, T* __restrict__ dst,
             cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -128,9 +133,13 @@ k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int6
     const int b = threadIdx.x / TC;  // phase A: low bits; phase B: first high value
     const int32_t ch = 2 * (blockIdx.y * TC + c);
     const bool has0 = ch < d, has1 = ch + 1 < d;
-    // points beyond xmax are zero: e <= emax
-    const int64_t emax64 = (int64_t)xmax >= l ? (((int64_t)xmax - l) >> lgL) : -1;
-    const int emax = (int)(emax64 < (1 << lgB) - 1 ? emax64 : (1 << lgB) - 1);
+    // unreflected, points beyond cmax are zero: e <= emax; reflected (the
+    // sources of a one-column table) every e is looked at
+    const bool refl = !INV && reflect != 0;
+    const int64_t emax64 = (int64_t)cmax >= l ? (((int64_t)cmax - l) >> lgL) : -1;
+    const int emax = refl ? (1 << lgB) - 1
+                          : (int)(emax64 < (1 << lgB) - 1 ? emax64 : (1 << lgB) - 1);
+    const int64_t pmask = ((int64_t)1 << lg) - 1;
     cpx<T> x[1 << kC1MaxR];
     // every global load that does not depend on the data is issued first:
     // the stage factors of both phases and the map rows of phase A's points
@@ -141,7 +150,9 @@ k_conv1d_hi(int lg, int lgL, int32_t xmax, const int32_t* __restrict__ map, int6
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k) {
         const int e = (k << RB) + b;
-        row[k] = (k < (1 << RA) && e <= emax) ? mp[((int64_t)e << lgL) + l] : -1;
+        const int64_t i = ((int64_t)e << lgL) + l;
+        const int64_t pos = refl ? ((pmask + 1 - i) & pmask) : i;
+        row[k] = (k < (1 << RA) && e <= emax && pos <= cmax) ? mp[pos] : -1;
     }
     if (!INV) {
         // phase A: points e = (k << RB) + b, gathered through the map

@@ -66,11 +66,16 @@ struct Bucket {
     std::vector<int32_t> hx;    // pairs (H, X) per job
     int32_t* d_jobs = nullptr;
     int32_t* d_hx = nullptr;
-    // 1-D buckets (lg1 = 0) beyond LDS: per job, the source row of the cell
-    // at each backbone coordinate x <= xmax, or -1 (stride mstride = xmax+1)
+    // 1-D buckets for the channel-tiled convolution: per job, the value row of
+    // the cell at each coordinate c <= cmax, or -1 (stride mstride = cmax+1).
+    // One row (lg1 = 0): c = backbone coordinate x. One column (lg2 = 0,
+    // single-position jobs): c = depth r; the source sits at point -r mod P
+    // (reflect) and the output at point r.
     int32_t* d_map = nullptr;
     int32_t* d_vmap = nullptr;  // the same with the cell's vertex (whole-path plans)
     int64_t mstride = 0;
+    int32_t cmax = 0;
+    bool reflect = false;
     int64_t spec_off = 0;       // element offset into the spectrum arena
     int64_t cells = 0;          // table cells over the bucket's jobs
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
@@ -763,7 +768,7 @@ int upload_methods(tfi_plan* h) {
             // long 1-D tables take the channel-tiled convolution kernels even
             // when one channel pair would fit LDS (the LDS kernels read one
             // pair per workgroup: 8 bytes of every row)
-            if (b.lg1 == 0 && b.lg2 >= 10) t = 3;
+            if ((b.lg1 == 0 || b.lg2 == 0) && b.lg1 + b.lg2 >= 10) t = 3;
             if (t == 3) {
                 h->global_b[ti].push_back((int)bi);
                 continue;
@@ -781,20 +786,26 @@ int upload_methods(tfi_plan* h) {
         }
         for (int bi : h->global_b[ti]) {
             Bucket& b = h->buckets[bi];
-            if (b.lg1 != 0 || b.d_map) continue;
-            std::vector<int32_t> map((size_t)b.njobs() * (b.xmax + 1), -1);
+            if ((b.lg1 != 0 && b.lg2 != 0) || b.d_map) continue;
+            const bool col = b.lg1 != 0;  // one column: cells by depth
+            const int32_t cmax = col ? b.hmax : b.xmax;
+            std::vector<int32_t> map((size_t)b.njobs() * (cmax + 1), -1);
             bool ok = true;
             for (int64_t j = 0; j < b.njobs() && ok; ++j)
                 for (int32_t k = b.jobs[2 * j]; k < b.jobs[2 * j + 1]; ++k) {
-                    if (p.jc_r[k] != 0 || p.jc_x[k] < 0 || p.jc_x[k] > b.xmax) {
+                    const int32_t c = col ? p.jc_r[k] : p.jc_x[k];
+                    const int32_t other = col ? p.jc_x[k] : p.jc_r[k];
+                    if (other != 0 || c < 0 || c > cmax) {
                         ok = false;
                         break;
                     }
-                    map[(size_t)j * (b.xmax + 1) + p.jc_x[k]] = p.jc_val[k];
+                    map[(size_t)j * (cmax + 1) + c] = p.jc_val[k];
                 }
             if (!ok) continue;
             if ((rc = h->upload_m(&b.d_map, map))) return rc;
-            b.mstride = b.xmax + 1;
+            b.mstride = cmax + 1;
+            b.cmax = cmax;
+            b.reflect = col;
         }
         h->path_mode[ti] = fj[0].empty() && fj[1].empty() && fj[2].empty() &&
                            h->ndirect == 0 && whole_path_plan(p);
@@ -940,8 +951,9 @@ void launch_fft2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::
 // passes instead.
 template <typename T>
 int conv1d_tc(const Bucket& b, int32_t d, int* lgL_out = nullptr) {
-    if (b.lg1 != 0 || !b.d_map || b.lg2 < 2 || b.lg2 > 20) return 0;
-    const int lg = b.lg2;
+    if (!b.d_map) return 0;
+    const int lg = b.lg1 + b.lg2;
+    if (lg < 2 || lg > 20) return 0;
     const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
     const int64_t npairs = (d + 1) / 2;
     int tc = (int)(128 / cs);
@@ -973,7 +985,7 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
                       size_t buf_bytes, hipStream_t st) {
     int lgL = 0;
     (void)conv1d_tc<T>(b, d, &lgL);
-    const int lg = b.lg2, lgH = lg - lgL;
+    const int lg = b.lg1 + b.lg2, lgH = lg - lgL;
     const int32_t ntiles = ((d + 1) / 2 + TC - 1) / TC;
     const int64_t job_bytes = (int64_t)ntiles * TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
     const int64_t jpc =
@@ -990,15 +1002,15 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
         const int32_t* map = bmap + j0 * b.mstride;
         hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, false>),
                            dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, val, (T*)nullptr, buf,
-                           tw, h->lgtw);
+                           lds_hi, st, lg, lgL, b.cmax, (int)b.reflect, map, b.mstride, d, val,
+                           (T*)nullptr, buf, tw, h->lgtw);
         hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC>),
                            dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
                            lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
         hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, true>),
                            dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.xmax, map, b.mstride, d, (const T*)nullptr, g,
-                           buf, tw, h->lgtw);
+                           lds_hi, st, lg, lgL, b.cmax, 0, map, b.mstride, d, (const T*)nullptr,
+                           g, buf, tw, h->lgtw);
     }
 }
 

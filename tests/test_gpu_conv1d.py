@@ -154,3 +154,29 @@ def test_long_path_backward_dF_and_df_fp64():
     e2 = relerr(df.cpu().numpy(), h)
     print(f"  err dF {e1:.2e} df {e2:.2e}", flush=True)
     assert e1 <= 1e-10 and e2 <= 1e-10, (e1, e2)
+
+
+@pytest.mark.parametrize("dtype,d", [(torch.float64, 5), (torch.float32, 33)])
+def test_one_column_tables(dtype, d):
+    """Centroid calls and corrections are one-column tables (a single
+    backbone position, G(q) = sum_r f(q + r) A_r): the hub of a long-arm
+    spider has depth 1000, so its table and the arms' corrections take the
+    channel-tiled kernels with reflected sources."""
+    p, w = S.spider(8, 1000)
+    rng = np.random.default_rng(21 + d)
+    print(f"conv1d one-column spider 8x1000 d={d} {dtype}", flush=True)
+    F = rng.standard_normal((len(p), d))
+    rows = np.sort(rng.choice(len(p), 200, replace=False))
+    t = TreeIntegrator(p, w, device=0, policy="centroid", table_method="fft")
+    K = t.kernel_length
+    f = torch.tensor(wavy(K), dtype=dtype, device=DEV)
+    t.profile(True)
+    y = t.integrate(f, torch.tensor(F, dtype=dtype, device=DEV))
+    torch.cuda.synchronize()
+    st = t.profile_report()
+    t.profile(False)
+    assert "fft_conv1d" in st, st
+    ref = oracle.integrate(p, w, wavy(K), F, rows=rows)
+    e = relerr(y.cpu().numpy()[rows], ref)
+    print(f"  err {e:.2e}", flush=True)
+    assert e <= TOL[dtype], e
