@@ -103,6 +103,9 @@ def main():
                     help="skip the wide-channel (C = 4160) patch-grid measurement")
     ap.add_argument("--wide-only", action="store_true",
                     help="run only the wide-channel measurement")
+    ap.add_argument("--wide-cases", default=None,
+                    help="comma-separated tree:side cases of the wide-channel measurement "
+                         "(default: serpentine 32..512, random/comb/fishbone 256)")
     ap.add_argument("--no-families", action="store_true",
                     help="skip the backbone-policy sweep over the synthetic tree families")
     ap.add_argument("--families-only", action="store_true",
@@ -441,8 +444,11 @@ def wide_channel(args):
     from paper_2609_34025_amd import TreeIntegrator, synth as S
 
     dev = torch.device("cuda", 0)
-    cases = [("serpentine", s) for s in (32, 64, 128, 256, 384, 512)]
-    cases += [("random", 256), ("comb", 256), ("fishbone", 256)]
+    if args.wide_cases:
+        cases = [(c.split(":")[0], int(c.split(":")[1])) for c in args.wide_cases.split(",")]
+    else:
+        cases = [("serpentine", s) for s in (32, 64, 128, 256, 384, 512)]
+        cases += [("random", 256), ("comb", 256), ("fishbone", 256)]
     out_cases = []
     roofline = None
     for kind, side in cases:
