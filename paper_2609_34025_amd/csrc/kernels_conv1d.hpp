@@ -32,6 +32,10 @@
 // a compile-time 32nd root of unity times one factor per stage (s = shift + u,
 // j0 = the index bits below shift), loaded once per phase.
 //
+// The split of the point index is a template argument (LGB, LGL) for the
+// block sizes of large transforms, so that the register loops and stages
+// unroll into straight-line code; 0 takes it from the arguments.
+//
 // Cells reach the kernels through map[job * mstride + c] = row of the cell
 // at coordinate c <= cmax, or -1 (unoccupied lattice point). A one-row table
 // (H = 0) is indexed by the backbone coordinate x: source and output at
@@ -102,6 +106,27 @@ __device__ __forceinline__ void reg_fft(cpx<T> (&x)[1 << kC1MaxR], int R,
     }
 }
 
+// One channel pair of a row as a single 8- or 16-byte access (the pair
+// starts at an even channel of a row of even length, in a buffer aligned to
+// two elements).
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_pair(const T* p) {
+    if constexpr (sizeof(T) == 4) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        return {v.x, v.y};
+    } else {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        return {v.x, v.y};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(T* p, cpx<T> v) {
+    if constexpr (sizeof(T) == 4)
+        *reinterpret_cast<float2*>(p) = make_float2(v.x, v.y);
+    else
+        *reinterpret_cast<double2*>(p) = make_double2(v.x, v.y);
+}
+
 // LDS block layout: row a (2^RA rows) holds the 2^RB points b x TC pairs,
 // padded by kC1Pad complex values so that phase B's lanes (different a, same
 // b) spread over the banks.
@@ -117,14 +142,15 @@ __device__ __forceinline__ int lds_at(int a, int b, int c, int RB) {
 // [lgL, lg), store to buf.
 // INV = true: load from buf, DIT stages of bits [lgL, lg), write the rows of
 // the occupied points to dst, scaled by 1/P.
-template <typename T, int TC, bool INV>
+template <typename T, int TC, bool INV, int LGB = 0>
 __global__ void __launch_bounds__(512)
 k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restrict__ map,
             int64_t mstride, int32_t d, const T* __restrict__ src, T* __restrict__ dst,
             cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int lgB = lg - lgL, RB = lgB / 2, RA = lgB - RB;
+    const int lgB = LGB ? LGB : lg - lgL, RB = lgB / 2, RA = lgB - RB;
+    if (LGB) lgL = lg - LGB;
     const int64_t l = blockIdx.x;
     const int64_t slot = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
     const int32_t* mp = map + (int64_t)blockIdx.z * mstride;
@@ -133,6 +159,9 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
     const int b = threadIdx.x / TC;  // phase A: low bits; phase B: first high value
     const int32_t ch = 2 * (blockIdx.y * TC + c);
     const bool has0 = ch < d, has1 = ch + 1 < d;
+    // rows of even length in an aligned buffer: one access per channel pair
+    const T* io = INV ? dst : src;
+    const bool pairs = (d & 1) == 0 && ((uintptr_t)io & (2 * sizeof(T) - 1)) == 0;
     // unreflected, points beyond cmax are zero: e <= emax; reflected (the
     // sources of a one-column table) every e is looked at
     const bool refl = !INV && reflect != 0;
@@ -156,13 +185,21 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
     }
     if (!INV) {
         // phase A: points e = (k << RB) + b, gathered through the map
+        if (pairs) {
 #pragma unroll
-        for (int k = 0; k < (1 << kC1MaxR); ++k) {
-            x[k] = {(T)0, (T)0};
-            if (row[k] >= 0 && has0) {
-                const T* p = src + (int64_t)row[k] * d + ch;
-                x[k].x = p[0];
-                if (has1) x[k].y = p[1];
+            for (int k = 0; k < (1 << kC1MaxR); ++k) {
+                x[k] = {(T)0, (T)0};
+                if (row[k] >= 0 && has0) x[k] = ld_pair(src + (int64_t)row[k] * d + ch);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < (1 << kC1MaxR); ++k) {
+                x[k] = {(T)0, (T)0};
+                if (row[k] >= 0 && has0) {
+                    const T* p = src + (int64_t)row[k] * d + ch;
+                    x[k].x = p[0];
+                    if (has1) x[k].y = p[1];
+                }
             }
         }
         reg_fft<T, false, true>(x, RA, fsA);
@@ -211,12 +248,20 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
             if (k < (1 << RA)) x[k] = z[lds_at<TC>(k, b, c, RB)];
         reg_fft<T, true, true>(x, RA, fsA);
         const T scale = (T)1 / (T)((int64_t)1 << lg);
+        if (pairs) {
 #pragma unroll
-        for (int k = 0; k < (1 << kC1MaxR); ++k) {
-            if (row[k] >= 0 && has0) {
-                T* p = dst + (int64_t)row[k] * d + ch;
-                p[0] = x[k].x * scale;
-                if (has1) p[1] = x[k].y * scale;
+            for (int k = 0; k < (1 << kC1MaxR); ++k)
+                if (row[k] >= 0 && has0)
+                    st_pair(dst + (int64_t)row[k] * d + ch,
+                            cpx<T>{x[k].x * scale, x[k].y * scale});
+        } else {
+#pragma unroll
+            for (int k = 0; k < (1 << kC1MaxR); ++k) {
+                if (row[k] >= 0 && has0) {
+                    T* p = dst + (int64_t)row[k] * d + ch;
+                    p[0] = x[k].x * scale;
+                    if (has1) p[1] = x[k].y * scale;
+                }
             }
         }
     }
@@ -226,12 +271,13 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
 // block: 2^(lgL/2) x TC threads. The 2^lgL consecutive points x TC pairs of
 // one h are contiguous in buf: DIF stages of bits [0, lgL), product with the
 // kernel spectrum, DIT stages, store back.
-template <typename T, int TC>
+template <typename T, int TC, int LGL = 0>
 __global__ void __launch_bounds__(512)
 k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ spec,
             const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
+    if (LGL) lgL = LGL;
     const int RB = lgL / 2, RA = lgL - RB;
     const int64_t h = blockIdx.x;
     const int64_t slot = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
@@ -242,10 +288,18 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
     cpx<T> x[1 << kC1MaxR];
     cpx<T> fs[kC1MaxR];
     const cpx<T> one[kC1MaxR] = {};
-    // phase A: DIF of the high bits of the block index; the stage factors and
-    // the kernel spectrum of phase B's points (a = b + j 2^RB, j < 2; at most
-    // 32 values, slot j 16 + k) are loaded up front with the data
+    // phase A: DIF of the high bits of the block index
     stage_factors(fs, RA, RB, b, tw, lgtw);
+#pragma unroll
+    for (int k = 0; k < (1 << kC1MaxR); ++k)
+        if (k < (1 << RA)) x[k] = sb[((k << RB) + b) * TC + c];
+    reg_fft<T, false, true>(x, RA, fs);
+#pragma unroll
+    for (int k = 0; k < (1 << kC1MaxR); ++k)
+        if (k < (1 << RA)) z[lds_at<TC>(k, b, c, RB)] = x[k];
+    // the kernel spectrum of phase B's points (a = b + j 2^RB, j < 2; at most
+    // 32 values, slot j 16 + k) is requested before the barrier, once the
+    // block's values have left the registers
     cpx<T> spv[1 << kC1MaxR];
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -254,13 +308,6 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
             const int a = b + (j << RB);
             if (k < (1 << RB) && a < (1 << RA)) spv[j * 16 + k] = sp[(a << RB) + k];
         }
-#pragma unroll
-    for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RA)) x[k] = sb[((k << RB) + b) * TC + c];
-    reg_fft<T, false, true>(x, RA, fs);
-#pragma unroll
-    for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RA)) z[lds_at<TC>(k, b, c, RB)] = x[k];
     __syncthreads();
     // phase B: DIF of the low bits, spectrum product, DIT of the low bits
     // (RA - RB <= 1, so a thread has at most two values of a)
@@ -281,7 +328,11 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
             if (k < (1 << RB)) z[lds_at<TC>(a, k, c, RB)] = x[k];
     }
     __syncthreads();
-    // phase A again: DIT of the high bits
+    // phase A again: DIT of the high bits. The stage factors pass through an
+    // empty register constraint so that the twiddle products of the forward
+    // phase are formed again here rather than kept live across phase B.
+#pragma unroll
+    for (int u = 0; u < kC1MaxR; ++u) asm volatile("" : "+v"(fs[u].x), "+v"(fs[u].y));
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)
         if (k < (1 << RA)) x[k] = z[lds_at<TC>(k, b, c, RB)];

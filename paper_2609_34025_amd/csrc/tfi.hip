@@ -22,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 #include <new>
 #include <set>
 #include <string>
@@ -605,15 +606,36 @@ int upload_static(tfi_plan* h) {
 // Device structures that depend on the per-job method (direct blocks, FFT
 // buckets and their LDS tiers); rebuilt when the methods are re-assigned.
 // LDS beyond 64 KiB for the 1-D convolution kernels of every channel tile.
-template <typename T, int TC>
-int conv1d_lds_optin_tc(int lds) {
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, false>,
+template <typename T, int TC, int LG>
+int conv1d_lds_optin_lg(int lds) {
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, false, LG>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, true>,
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_hi<T, TC, true, LG>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
-    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC>,
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC, LG>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     return TFI_OK;
+}
+
+// Block splits compiled with fixed sizes (straight-line register stages):
+// FP32 with full-line tiles, blocks of 2^7 .. 2^10 points. FP64 at these
+// sizes runs out of registers unrolled and keeps the runtime split.
+constexpr int kC1FixedMin = 7, kC1FixedMax = 10;
+template <typename T, int TC>
+constexpr bool conv1d_fixed() {
+    return std::is_same<T, float>::value && TC == 16;
+}
+
+template <typename T, int TC>
+int conv1d_lds_optin_tc(int lds) {
+    int rc = conv1d_lds_optin_lg<T, TC, 0>(lds);
+    if constexpr (conv1d_fixed<T, TC>()) {
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 7>(lds);
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 8>(lds);
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 9>(lds);
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 10>(lds);
+    }
+    return rc;
 }
 
 template <typename T>
@@ -997,20 +1019,37 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((TC << lRB) + tfi::kC1Pad) *
                                        sizeof(tfi::cpx<T>));
     const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(TC << lRB);
+    // kernel instances: the fixed split where one is compiled, else runtime
+    using HiK = void (*)(int, int, int32_t, int, const int32_t*, int64_t, int32_t, const T*, T*,
+                         tfi::cpx<T>*, const tfi::cpx<T>*, int);
+    using LoK = void (*)(int, int, tfi::cpx<T>*, const tfi::cpx<T>*, const tfi::cpx<T>*, int);
+    HiK hi_fwd = tfi::k_conv1d_hi<T, TC, false, 0>, hi_inv = tfi::k_conv1d_hi<T, TC, true, 0>;
+    LoK lo = tfi::k_conv1d_lo<T, TC, 0>;
+    if constexpr (conv1d_fixed<T, TC>()) {
+#define TFI_C1_FIXED(LG)                                         \
+    if (lgH == LG) {                                             \
+        hi_fwd = tfi::k_conv1d_hi<T, TC, false, LG>;             \
+        hi_inv = tfi::k_conv1d_hi<T, TC, true, LG>;              \
+    }                                                            \
+    if (lgL == LG) lo = tfi::k_conv1d_lo<T, TC, LG>;
+        TFI_C1_FIXED(7)
+        TFI_C1_FIXED(8)
+        TFI_C1_FIXED(9)
+        TFI_C1_FIXED(10)
+#undef TFI_C1_FIXED
+        static_assert(kC1FixedMin == 7 && kC1FixedMax == 10, "fixed splits listed above");
+    }
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
         const int32_t* map = bmap + j0 * b.mstride;
-        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, false>),
-                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.cmax, (int)b.reflect, map, b.mstride, d, val,
-                           (T*)nullptr, buf, tw, h->lgtw);
-        hipLaunchKernelGGL((tfi::k_conv1d_lo<T, TC>),
-                           dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
+        hipLaunchKernelGGL(hi_fwd, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
+                           dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, (int)b.reflect, map,
+                           b.mstride, d, val, (T*)nullptr, buf, tw, h->lgtw);
+        hipLaunchKernelGGL(lo, dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
                            lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
-        hipLaunchKernelGGL((tfi::k_conv1d_hi<T, TC, true>),
-                           dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj), dim3(thr_hi),
-                           lds_hi, st, lg, lgL, b.cmax, 0, map, b.mstride, d, (const T*)nullptr,
-                           g, buf, tw, h->lgtw);
+        hipLaunchKernelGGL(hi_inv, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
+                           dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, 0, map, b.mstride, d,
+                           (const T*)nullptr, g, buf, tw, h->lgtw);
     }
 }
 
