@@ -267,24 +267,41 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
     }
 }
 
-// Low-bit pass. Grid: (2^(lg - lgL) high values h, tiles, jobs of the chunk);
-// block: 2^(lgL/2) x TC threads. The 2^lgL consecutive points x TC pairs of
-// one h are contiguous in buf: DIF stages of bits [0, lgL), product with the
-// kernel spectrum, DIT stages, store back.
-template <typename T, int TC, int LGL = 0>
+// Low-bit pass. Grid: (2^(lg - lgL) high values h x TC / CW channel parts,
+// tiles, jobs of the chunk); block: 2^(lgL/2) x CW threads. The 2^lgL
+// consecutive points x TC pairs of one h are contiguous in buf: DIF stages of
+// bits [0, lgL), product with the kernel spectrum, DIT stages, store back.
+// With CW < TC a workgroup takes CW of the TC pairs (a smaller LDS block, so
+// that two workgroups share a CU); the parts of one h are dispatched 8
+// workgroups apart, which places them on the same XCD (workgroups go to the
+// XCDs in turn), so each 128-byte row is fetched into one L2 only.
+template <typename T, int TC, int LGL = 0, int CW = TC>
 __global__ void __launch_bounds__(512)
 k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ spec,
             const cpx<T>* __restrict__ tw, int lgtw) {
+    static_assert(CW <= TC && TC % CW == 0, "channel parts divide the tile");
+    constexpr int NS = TC / CW;
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     if (LGL) lgL = LGL;
     const int RB = lgL / 2, RA = lgL - RB;
-    const int64_t h = blockIdx.x;
+    int64_t h = blockIdx.x;
+    int c0 = 0;
+    if (NS > 1) {
+        if (gridDim.x >= 8 * NS) {
+            const int w = (int)(blockIdx.x % (8 * NS));
+            h = (int64_t)(blockIdx.x / (8 * NS)) * 8 + (w & 7);
+            c0 = (w >> 3) * CW;
+        } else {
+            h = blockIdx.x / NS;
+            c0 = (int)(blockIdx.x % NS) * CW;
+        }
+    }
     const int64_t slot = (int64_t)blockIdx.z * gridDim.y + blockIdx.y;
-    cpx<T>* sb = buf + ((slot << lg) + (h << lgL)) * TC;
+    cpx<T>* sb = buf + ((slot << lg) + (h << lgL)) * TC + c0;
     const cpx<T>* sp = spec + (h << lgL);
-    const int c = threadIdx.x % TC;
-    const int b = threadIdx.x / TC;
+    const int c = threadIdx.x % CW;
+    const int b = threadIdx.x / CW;
     cpx<T> x[1 << kC1MaxR];
     cpx<T> fs[kC1MaxR];
     const cpx<T> one[kC1MaxR] = {};
@@ -296,7 +313,7 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
     reg_fft<T, false, true>(x, RA, fs);
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RA)) z[lds_at<TC>(k, b, c, RB)] = x[k];
+        if (k < (1 << RA)) z[lds_at<CW>(k, b, c, RB)] = x[k];
     // the kernel spectrum of phase B's points (a = b + j 2^RB, j < 2; at most
     // 32 values, slot j 16 + k) is requested before the barrier, once the
     // block's values have left the registers
@@ -317,7 +334,7 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
         if (a >= (1 << RA)) continue;
 #pragma unroll
         for (int k = 0; k < (1 << kC1MaxR); ++k)
-            if (k < (1 << RB)) x[k] = z[lds_at<TC>(a, k, c, RB)];
+            if (k < (1 << RB)) x[k] = z[lds_at<CW>(a, k, c, RB)];
         reg_fft<T, false, false>(x, RB, one);
 #pragma unroll
         for (int k = 0; k < (1 << kC1MaxR); ++k)
@@ -325,7 +342,7 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
         reg_fft<T, true, false>(x, RB, one);
 #pragma unroll
         for (int k = 0; k < (1 << kC1MaxR); ++k)
-            if (k < (1 << RB)) z[lds_at<TC>(a, k, c, RB)] = x[k];
+            if (k < (1 << RB)) z[lds_at<CW>(a, k, c, RB)] = x[k];
     }
     __syncthreads();
     // phase A again: DIT of the high bits. The stage factors pass through an
@@ -335,7 +352,7 @@ k_conv1d_lo(int lg, int lgL, cpx<T>* __restrict__ buf, const cpx<T>* __restrict_
     for (int u = 0; u < kC1MaxR; ++u) asm volatile("" : "+v"(fs[u].x), "+v"(fs[u].y));
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)
-        if (k < (1 << RA)) x[k] = z[lds_at<TC>(k, b, c, RB)];
+        if (k < (1 << RA)) x[k] = z[lds_at<CW>(k, b, c, RB)];
     reg_fft<T, true, true>(x, RA, fs);
 #pragma unroll
     for (int k = 0; k < (1 << kC1MaxR); ++k)

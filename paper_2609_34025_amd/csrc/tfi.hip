@@ -634,6 +634,9 @@ int conv1d_lds_optin_tc(int lds) {
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 8>(lds);
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 9>(lds);
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 10>(lds);
+        if (!rc)
+            TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC, 10, TC / 2>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     }
     return rc;
 }
@@ -1016,9 +1019,14 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     const int hRB = lgH / 2, hRA = lgH - hRB, lRB = lgL / 2, lRA = lgL - lRB;
     const unsigned lds_hi = (unsigned)(((int64_t)1 << hRA) * ((TC << hRB) + tfi::kC1Pad) *
                                        sizeof(tfi::cpx<T>));
-    const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((TC << lRB) + tfi::kC1Pad) *
+    // the low-bit blocks of 2^10 points take their TC pairs in two workgroups
+    // of TC / 2 (two per CU instead of one)
+    int lo_parts = 1;
+    if constexpr (conv1d_fixed<T, TC>()) lo_parts = lgL == 10 ? 2 : 1;
+    const int lo_cw = TC / lo_parts;
+    const unsigned lds_lo = (unsigned)(((int64_t)1 << lRA) * ((lo_cw << lRB) + tfi::kC1Pad) *
                                        sizeof(tfi::cpx<T>));
-    const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(TC << lRB);
+    const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(lo_cw << lRB);
     // kernel instances: the fixed split where one is compiled, else runtime
     using HiK = void (*)(int, int, int32_t, int, const int32_t*, int64_t, int32_t, const T*, T*,
                          tfi::cpx<T>*, const tfi::cpx<T>*, int);
@@ -1037,6 +1045,7 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
         TFI_C1_FIXED(9)
         TFI_C1_FIXED(10)
 #undef TFI_C1_FIXED
+        if (lo_parts == 2) lo = tfi::k_conv1d_lo<T, TC, 10, TC / 2>;
         static_assert(kC1FixedMin == 7 && kC1FixedMax == 10, "fixed splits listed above");
     }
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
@@ -1045,7 +1054,8 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
         hipLaunchKernelGGL(hi_fwd, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
                            dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, (int)b.reflect, map,
                            b.mstride, d, val, (T*)nullptr, buf, tw, h->lgtw);
-        hipLaunchKernelGGL(lo, dim3(1u << lgH, (unsigned)ntiles, (unsigned)nj), dim3(thr_lo),
+        hipLaunchKernelGGL(lo, dim3((1u << lgH) * lo_parts, (unsigned)ntiles, (unsigned)nj),
+                           dim3(thr_lo),
                            lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
         hipLaunchKernelGGL(hi_inv, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
                            dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, 0, map, b.mstride, d,
