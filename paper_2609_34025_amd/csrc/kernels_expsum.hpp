@@ -211,6 +211,24 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
     }
 }
 
+// Value of lane src (uniform over the wavefront) in every lane, through the
+// scalar registers.
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int src) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+    } else {
+        const long long b = __double_as_longlong(v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, src);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), src);
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+}
+template <>
+__device__ __forceinline__ int32_t lane_value<int32_t>(int32_t v, int src) {
+    return __builtin_amdgcn_readlane(v, src);
+}
+
 // ---- one-position jobs, one wavefront each ------------------------------
 // A job with one backbone position needs, per term l and channel c, the
 // sums a_l = sum_i lam_l^{r_i} v_i (forward) or a_l, a^r_l (r-weighted) and
@@ -226,7 +244,10 @@ k_expsum_jobs(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
 // Moments: subgroup 0 adds sign <b_l, a_l> and sign (<b^r_l, a_l> + <b_l,
 // a^r_l>) over its channels; the workgroup total goes to row mbase +
 // blockIdx.x of mrow ([s0 | s1][nterm]).
-template <typename T, int NJ, bool GRAD>
+// WHOLE (gs = 64, i.e. d > 32): one cell subgroup, so the cell a step works
+// on is the same in every lane; its row, depth and weights are read from the
+// owning lane into scalar registers, and eight cell rows are loaded per step.
+template <typename T, int NJ, bool GRAD, bool WHOLE = false>
 __global__ void __launch_bounds__(kExpThreads)
 k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
               const int32_t* __restrict__ ej, const int64_t* __restrict__ joff,
@@ -236,11 +257,12 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
               const T* __restrict__ valg, T* __restrict__ g, double* __restrict__ mrow,
               int64_t mbase) {
     constexpr int NQ = GRAD ? 4 : 1;
-    constexpr int B = 4;  // cells per subgroup and batch of value loads
+    constexpr int B = WHOLE ? 8 : 4;  // cells per subgroup and batch of value loads
     const int lane = threadIdx.x & 63;
     const int32_t jn = blockIdx.x * (kExpThreads / 64) + (threadIdx.x >> 6);
     const bool active = jn < njobs;  // uniform per wavefront
-    const int32_t S = 64 / gs, sub = lane / gs, lc = lane - sub * gs;
+    if (WHOLE) gs = 64;
+    const int32_t S = WHOLE ? 1 : 64 / gs, sub = WHOLE ? 0 : lane / gs, lc = lane - sub * gs;
     const int32_t job = active ? ej[jn] : 0;
     const int64_t cb = active ? joff[job] : 0, ce = active ? joff[job + 1] : 0;
     const T sgn = (GRAD && active && jsign[job] < 0) ? (T)-1 : (T)1;
@@ -273,8 +295,10 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
                 for (int u = 0; u < B; ++u) {
                     kk[u] = k + u * S + sub;
                     const int32_t src = min(kk[u], nk - 1);
-                    rowk[u] = __shfl(rowmine, src, 64);
-                    rk[u] = GRAD ? (T)__shfl(rmine, src, 64) : (T)0;
+                    rowk[u] = WHOLE ? lane_value(rowmine, src) : __shfl(rowmine, src, 64);
+                    rk[u] = !GRAD  ? (T)0
+                            : WHOLE ? (T)lane_value(rmine, src)
+                                    : (T)__shfl(rmine, src, 64);
                 }
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
@@ -289,7 +313,7 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
 #pragma unroll
                     for (int l = 0; l < NJ; ++l) {
                         if (l >= nterm) continue;
-                        const T w = __shfl(wmine[l], src, 64);
+                        const T w = WHOLE ? lane_value(wmine[l], src) : __shfl(wmine[l], src, 64);
                         acc[0][l] += w * v[u];
                         if (GRAD) {
                             acc[1][l] += rk[u] * w * v[u];
@@ -320,11 +344,14 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
                     wmine[l] = l < nterm ? pw[(int64_t)l * K + rmine] : (T)0;
                 for (int32_t k = 0; k < nk; k += S) {  // uniform in the wavefront
                     const int32_t kk = k + sub, src = min(kk, nk - 1);
-                    const int32_t rowk = __shfl(rowmine, src, 64);
+                    const int32_t rowk =
+                        WHOLE ? lane_value(rowmine, src) : __shfl(rowmine, src, 64);
                     T sum = (T)0;
 #pragma unroll
                     for (int l = 0; l < NJ; ++l)
-                        if (l < nterm) sum += ca[l] * __shfl(wmine[l], src, 64);
+                        if (l < nterm)
+                            sum += ca[l] * (WHOLE ? lane_value(wmine[l], src)
+                                                  : __shfl(wmine[l], src, 64));
                     if (chok && kk < nk) g[(int64_t)rowk * d + ch] = sum;
                 }
             }

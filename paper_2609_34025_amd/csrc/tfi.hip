@@ -1778,7 +1778,13 @@ void launch_expsum_wave(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const
                            (int32_t)nj, h->d_ej1, h->d_joff, h->d_jsign, h->d_jc_r, h->d_jc_val, c,
                            pw, (int32_t)h->plan.kernel_len, val, valg, g, mrow, mbase);
     };
-    if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD>);
+    if (gs == 64) {  // one cell subgroup: the lane-uniform walk
+        if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD, true>);
+        else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD, true>);
+        else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD, true>);
+        else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD, true>);
+        else launch(tfi::k_expsum_wave<T, 16, GRAD, true>);
+    } else if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD>);
     else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD>);
     else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD>);
     else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD>);

@@ -103,6 +103,36 @@ def test_expsum_fp32_channel_counts(d):
         assert relerr(s1.cpu().numpy(), r1) <= 1e-4
 
 
+@pytest.mark.parametrize("policy", ["adaptive", "centroid"])
+def test_expsum_fp64_wide_rows(policy):
+    """d > 32: a one-position job's cell walk is the same in every lane (the
+    cell's row and weights pass through scalar registers, two halves per
+    double)."""
+    rng = np.random.default_rng(77)
+    p, w, _ = S.forest([S.grid_mst(14, 16, rng), S.spider(5, 30)])
+    d = 40
+    print(f"expsum fp64 wide rows policy={policy} N={len(p)} d={d}", flush=True)
+    t = TreeIntegrator(p, w, device=0, policy=policy)
+    K = t.kernel_length
+    c = rng.standard_normal(8)
+    lam = rng.uniform(0.55, 0.99, 8)
+    F = rng.standard_normal((len(p), d))
+    G = rng.standard_normal((len(p), d))
+    ct, lt = torch.tensor(c, device=DEV), torch.tensor(lam, device=DEV)
+    Ft = torch.tensor(F, device=DEV)
+    y = t.integrate_expsum(ct, lt, Ft).cpu().numpy()
+    dF, s0, s1 = t.backward_expsum(ct, lt, Ft, torch.tensor(G, device=DEV))
+    ftab = table(c, lam, K)
+    h = oracle.pair_hist(p, w, G, F, K)
+    k = np.arange(K)
+    r0 = np.array([(lam[l] ** k * h).sum() for l in range(8)])
+    r1 = np.array([(k * lam[l] ** k * h).sum() for l in range(8)])
+    errs = (relerr(y, oracle.integrate(p, w, ftab, F)),
+            relerr(dF.cpu().numpy(), oracle.integrate(p, w, ftab, G)),
+            relerr(s0.cpu().numpy(), r0), relerr(s1.cpu().numpy(), r1))
+    assert max(errs) <= 1e-10, errs
+
+
 def test_expsum_autograd_matches_fd_and_table_path():
     rng = np.random.default_rng(55)
     p, w, _ = S.forest([S.grid_mst(s, 16, rng) for s in (6, 8, 7)])
