@@ -219,14 +219,50 @@ int tfi_integrate_expsum(tfi_handle h, int32_t nterm, const void *c,
  *   s1[l] = sum_{v, w} dist(v,w) lambda[l]^dist(v,w) <gout[v, :], F[w, :]>,
  *   device double[nterm] each (overwritten), both NULL or both given.
  * Then dL/dc[l] = s0[l] and dL/dlambda[l] = c[l] * s1[l] / lambda[l]; with
- * lambda = exp(-b), dL/db[l] = -c[l] * s1[l]. s0/s1 accumulate with FP64
- * atomics (reproducible to rounding, not bitwise).
+ * lambda = exp(-b), dL/db[l] = -c[l] * s1[l]. s0/s1 are FP64 sums of
+ * per-workgroup rows in a fixed order, but their leaf-tile part comes from
+ * a pair histogram binned with atomics (LDS bins in the field's precision,
+ * then FP64): reproducible to that rounding, not bitwise.
  * Errors as tfi_integrate.
  */
 int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void *c,
                         const void *lambda, const void *F, const void *gout,
                         int64_t d, tfi_dtype dtype, void *dF, double *s0,
                         double *s1, void *stream);
+
+/*
+ * Cell sums kept from the forward for the backward (a training step saves
+ * them instead of scattering F a second time). The cell sums are the
+ * per-cell field totals of every table job (the A-cells of a call, the
+ * b-cells of its components) that both passes start from: the
+ * accumulation of F by depth and backbone position in the pseudocode for
+ * the cross terms (appendix "Algorithmic Details and Deferred Proofs").
+ *
+ * tfi_cell_rows: rows of the cell-sum array of h (>= 1), or a negative
+ * status.
+ *
+ * tfi_integrate_expsum_cells: tfi_integrate_expsum that also leaves the
+ * cell sums of F in cells, device dtype[tfi_cell_rows(h) x d] owned by the
+ * caller (overwritten; must not alias F or out).
+ *
+ * tfi_backward_expsum_cells: tfi_backward_expsum that takes the cell sums
+ * of F from cells, as written by tfi_integrate_expsum_cells on the same
+ * handle with the same F and d, instead of forming them again. F is still
+ * read (leaf tiles). dF is bitwise that of tfi_backward_expsum, s0/s1 the
+ * same to the rounding of the leaf histogram.
+ *
+ * Errors as tfi_integrate_expsum; cells == NULL is TFI_ERR_ARG.
+ */
+int64_t tfi_cell_rows(tfi_handle h);
+int tfi_integrate_expsum_cells(tfi_handle h, int32_t nterm, const void *c,
+                               const void *lambda, const void *F, int64_t d,
+                               tfi_dtype dtype, void *out, void *cells,
+                               void *stream);
+int tfi_backward_expsum_cells(tfi_handle h, int32_t nterm, const void *c,
+                              const void *lambda, const void *F,
+                              const void *cells, const void *gout, int64_t d,
+                              tfi_dtype dtype, void *dF, double *s0, double *s1,
+                              void *stream);
 
 /*
  * Plan statistics as a JSON object written to the host buffer json[cap]

@@ -46,7 +46,8 @@ EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate
             "tfi_backward", "tfi_plan_stats", "tfi_plan_export", "tfi_profile",
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
             "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
-            "tfi_integrate_multi"]
+            "tfi_integrate_multi", "tfi_cell_rows", "tfi_integrate_expsum_cells",
+            "tfi_backward_expsum_cells"]
 
 
 def load():
@@ -93,6 +94,14 @@ def load():
     lib.tfi_backward_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp,
                                         vp]
     lib.tfi_backward_expsum.restype = C.c_int
+    lib.tfi_cell_rows.argtypes = [vp]
+    lib.tfi_cell_rows.restype = i64
+    lib.tfi_integrate_expsum_cells.argtypes = [vp, C.c_int32, vp, vp, vp, i64, C.c_int, vp, vp,
+                                               vp]
+    lib.tfi_integrate_expsum_cells.restype = C.c_int
+    lib.tfi_backward_expsum_cells.argtypes = [vp, C.c_int32, vp, vp, vp, vp, vp, i64, C.c_int, vp,
+                                              vp, vp, vp]
+    lib.tfi_backward_expsum_cells.restype = C.c_int
     lib.tfi_last_error.argtypes = []
     lib.tfi_last_error.restype = C.c_char_p
     _lib = lib

@@ -1836,9 +1836,10 @@ void enq_expsum_jobs(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T*
 // out = f(D) F for f(k) = sum_l c_l lam_l^k.
 template <typename T>
 void enqueue_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
-                            int32_t d, T* out, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+                            int32_t d, T* out, T* cells, hipStream_t s0, hipStream_t s1,
+                            hipStream_t s2) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = (T*)h->val[ti].p;
+    T* val = cells ? cells : (T*)h->val[ti].p;  // the cell sums of F
     T* g = (T*)h->g[ti].p;
     const T* ftab = (const T*)h->expw[ti].p + (size_t)nterm * h->plan.kernel_len;
     enq_expsum_prep<T>(h, nterm, c, lam, s0);
@@ -1854,13 +1855,16 @@ void enqueue_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam
 }
 
 // dF = f(D) gout (when dF != null) and the moments m0/m1 (when non-null).
+// cells: the cell sums of F left by the forward (then F is not scattered
+// again), or null.
 template <typename T>
 void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
-                             const T* gout, int32_t d, T* dF, double* m0, double* m1,
-                             hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+                             const T* cells, const T* gout, int32_t d, T* dF, double* m0,
+                             double* m1, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
     T* val = (T*)h->val[ti].p;
+    const T* valF = cells ? cells : val;
     T* valg = (T*)h->valg[ti].p;
     T* g = (T*)h->g[ti].p;
     const T* pw = (const T*)h->expw[ti].p;
@@ -1882,12 +1886,12 @@ void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* la
                            mrow, rows - nterm);
     }
     (void)hipEventRecord(h->ev_c, s2);
-    if (grad) launch_scatter<T>(h, F, val, d, s1);
+    if (grad && !cells) launch_scatter<T>(h, F, val, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
     launch_scatter<T>(h, gout, valg, d, s0);
     if (dF) enq_expsum_jobs<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, s0);
     (void)hipStreamWaitEvent(s0, h->ev_d, 0);
-    if (grad) enq_expsum_jobs<T, true>(h, nterm, c, d, val, valg, nullptr, mrow, s0);
+    if (grad) enq_expsum_jobs<T, true>(h, nterm, c, d, valF, valg, nullptr, mrow, s0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     if (grad)
         hipLaunchKernelGGL(tfi::k_expsum_moments, dim3((unsigned)(2 * nterm)),
@@ -1898,7 +1902,7 @@ void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* la
 
 template <typename T>
 int run_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
-                       int32_t d, T* out, hipStream_t st) {
+                       int32_t d, T* out, T* cells, hipStream_t st) {
     int rc = prepare_expsum<T>(h, nterm, d, false, false);
     if (rc) return rc;
     GraphKey key;
@@ -1910,15 +1914,16 @@ int run_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, con
     key.p[1] = lam;
     key.p[2] = F;
     key.p[3] = out;
+    key.p[4] = cells;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t cc) {
-        enqueue_forward_expsum<T>(h, nterm, c, lam, F, d, out, a, b, cc);
+        enqueue_forward_expsum<T>(h, nterm, c, lam, F, d, out, cells, a, b, cc);
     });
 }
 
 template <typename T>
 int run_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, const T* F,
-                        const T* gout, int32_t d, T* dF, double* m0, double* m1,
-                        hipStream_t st) {
+                        const T* cells, const T* gout, int32_t d, T* dF, double* m0,
+                        double* m1, hipStream_t st) {
     int rc = prepare_expsum<T>(h, nterm, d, true, m0 != nullptr);
     if (rc) return rc;
     GraphKey key;
@@ -1933,8 +1938,9 @@ int run_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam, co
     key.p[4] = dF;
     key.p[5] = m0;
     key.p[6] = m1;
+    key.p[7] = cells;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t cc) {
-        enqueue_backward_expsum<T>(h, nterm, c, lam, F, gout, d, dF, m0, m1, a, b, cc);
+        enqueue_backward_expsum<T>(h, nterm, c, lam, F, cells, gout, d, dF, m0, m1, a, b, cc);
     });
 }
 
@@ -2154,55 +2160,107 @@ int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, i
                                 (int32_t)d, (double*)dF, df, st);
 }
 
-int tfi_integrate_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
-                         const void* F, int64_t d, tfi_dtype dtype, void* out, void* stream) {
+namespace {
+int integrate_expsum_impl(const char* fn, tfi_handle h, int32_t nterm, const void* c,
+                          const void* lambda, const void* F, int64_t d, tfi_dtype dtype,
+                          void* out, void* cells, void* stream) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
-    if (!c || !lambda || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate_expsum: null pointer");
+    const std::string f(fn);
+    if (!c || !lambda || !F || !out) return fail(TFI_ERR_ARG, f + ": null pointer");
     if (nterm < 1 || nterm > tfi::kExpMaxTerms)
-        return fail(TFI_ERR_ARG, "tfi_integrate_expsum: need 1 <= nterm <= 16");
-    if (d < 1 || d > (1 << 20))
-        return fail(TFI_ERR_ARG, "tfi_integrate_expsum: need 1 <= d <= 2^20");
-    if (F == out) return fail(TFI_ERR_ARG, "tfi_integrate_expsum: out must not alias F");
+        return fail(TFI_ERR_ARG, f + ": need 1 <= nterm <= 16");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, f + ": need 1 <= d <= 2^20");
+    if (F == out) return fail(TFI_ERR_ARG, f + ": out must not alias F");
+    if (cells && (cells == F || cells == out))
+        return fail(TFI_ERR_ARG, f + ": cells must not alias F or out");
     hipStream_t st = (hipStream_t)stream;
     if (dtype == TFI_F32)
         return run_forward_expsum<float>(h, nterm, (const float*)c, (const float*)lambda,
-                                         (const float*)F, (int32_t)d, (float*)out, st);
+                                         (const float*)F, (int32_t)d, (float*)out,
+                                         (float*)cells, st);
     if (dtype == TFI_F64)
         return run_forward_expsum<double>(h, nterm, (const double*)c, (const double*)lambda,
-                                          (const double*)F, (int32_t)d, (double*)out, st);
-    return fail(TFI_ERR_DTYPE, "tfi_integrate_expsum: unknown dtype");
+                                          (const double*)F, (int32_t)d, (double*)out,
+                                          (double*)cells, st);
+    return fail(TFI_ERR_DTYPE, f + ": unknown dtype");
+}
+}  // namespace
+
+int tfi_integrate_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                         const void* F, int64_t d, tfi_dtype dtype, void* out, void* stream) {
+    return integrate_expsum_impl("tfi_integrate_expsum", h, nterm, c, lambda, F, d, dtype, out,
+                                 nullptr, stream);
 }
 
-int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
-                        const void* F, const void* gout, int64_t d, tfi_dtype dtype, void* dF,
-                        double* s0, double* s1, void* stream) {
+int tfi_integrate_expsum_cells(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                               const void* F, int64_t d, tfi_dtype dtype, void* out,
+                               void* cells, void* stream) {
+    if (!cells) {
+        g_err.clear();
+        return fail(TFI_ERR_ARG, "tfi_integrate_expsum_cells: null pointer");
+    }
+    return integrate_expsum_impl("tfi_integrate_expsum_cells", h, nterm, c, lambda, F, d, dtype,
+                                 out, cells, stream);
+}
+
+namespace {
+int backward_expsum_impl(const char* fn, tfi_handle h, int32_t nterm, const void* c,
+                         const void* lambda, const void* F, const void* cells,
+                         const void* gout, int64_t d, tfi_dtype dtype, void* dF, double* s0,
+                         double* s1, void* stream) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
-    if (!c || !lambda || !F || !gout)
-        return fail(TFI_ERR_ARG, "tfi_backward_expsum: null pointer");
+    const std::string f(fn);
+    if (!c || !lambda || !F || !gout) return fail(TFI_ERR_ARG, f + ": null pointer");
     if (nterm < 1 || nterm > tfi::kExpMaxTerms)
-        return fail(TFI_ERR_ARG, "tfi_backward_expsum: need 1 <= nterm <= 16");
-    if (d < 1 || d > (1 << 20))
-        return fail(TFI_ERR_ARG, "tfi_backward_expsum: need 1 <= d <= 2^20");
-    if (dtype != TFI_F32 && dtype != TFI_F64)
-        return fail(TFI_ERR_DTYPE, "tfi_backward_expsum: unknown dtype");
+        return fail(TFI_ERR_ARG, f + ": need 1 <= nterm <= 16");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, f + ": need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64) return fail(TFI_ERR_DTYPE, f + ": unknown dtype");
     if ((s0 == nullptr) != (s1 == nullptr))
-        return fail(TFI_ERR_ARG, "tfi_backward_expsum: s0 and s1 are both given or both null");
-    if (s0 && s0 == s1) return fail(TFI_ERR_ARG, "tfi_backward_expsum: s0 must not alias s1");
-    if (dF && (dF == F || dF == gout))
-        return fail(TFI_ERR_ARG, "tfi_backward_expsum: dF must not alias F or gout");
+        return fail(TFI_ERR_ARG, f + ": s0 and s1 are both given or both null");
+    if (s0 && s0 == s1) return fail(TFI_ERR_ARG, f + ": s0 must not alias s1");
+    if (dF && (dF == F || dF == gout || dF == cells))
+        return fail(TFI_ERR_ARG, f + ": dF must not alias F, cells or gout");
     if (!dF && !s0) return TFI_OK;
     hipStream_t st = (hipStream_t)stream;
     if (dtype == TFI_F32)
         return run_backward_expsum<float>(h, nterm, (const float*)c, (const float*)lambda,
-                                          (const float*)F, (const float*)gout, (int32_t)d,
-                                          (float*)dF, s0, s1, st);
+                                          (const float*)F, (const float*)cells,
+                                          (const float*)gout, (int32_t)d, (float*)dF, s0, s1,
+                                          st);
     return run_backward_expsum<double>(h, nterm, (const double*)c, (const double*)lambda,
-                                       (const double*)F, (const double*)gout, (int32_t)d,
-                                       (double*)dF, s0, s1, st);
+                                       (const double*)F, (const double*)cells,
+                                       (const double*)gout, (int32_t)d, (double*)dF, s0, s1,
+                                       st);
+}
+}  // namespace
+
+int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                        const void* F, const void* gout, int64_t d, tfi_dtype dtype, void* dF,
+                        double* s0, double* s1, void* stream) {
+    return backward_expsum_impl("tfi_backward_expsum", h, nterm, c, lambda, F, nullptr, gout, d,
+                                dtype, dF, s0, s1, stream);
+}
+
+int tfi_backward_expsum_cells(tfi_handle h, int32_t nterm, const void* c, const void* lambda,
+                              const void* F, const void* cells, const void* gout, int64_t d,
+                              tfi_dtype dtype, void* dF, double* s0, double* s1, void* stream) {
+    if (!cells) {
+        g_err.clear();
+        return fail(TFI_ERR_ARG, "tfi_backward_expsum_cells: null pointer");
+    }
+    return backward_expsum_impl("tfi_backward_expsum_cells", h, nterm, c, lambda, F, cells, gout,
+                                d, dtype, dF, s0, s1, stream);
+}
+
+int64_t tfi_cell_rows(tfi_handle h) {
+    g_err.clear();
+    int rc = check_handle(h, false);
+    if (rc) return rc;
+    return std::max<int64_t>(h->val_rows, 1);
 }
 
 int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {

@@ -227,24 +227,37 @@ class TreeIntegrator:
         if c.numel() != lam.numel() or not 1 <= c.numel() <= EXPSUM_MAX_TERMS:
             raise ValueError(f"c and lam need the same length, 1..{EXPSUM_MAX_TERMS}")
 
-    def integrate_expsum(self, c, lam, F):
+    def integrate_expsum(self, c, lam, F, keep_cells=False):
         """out = f(D) F for f(k) = sum_l c[l] lam[l]**k (lam > 0), by backbone
-        sweeps per table job instead of direct sums or FFT."""
+        sweeps per table job instead of direct sums or FFT. With
+        ``keep_cells`` returns ``(out, cells)``: the cell sums of F, which
+        ``backward_expsum(..., cells=cells)`` then reads instead of forming
+        them again."""
         self._check_expsum(c, lam, F)
         d = 1 if F.dim() == 1 else F.shape[1]
         out = torch.empty_like(F)
         if d == 0:
+            return (out, None) if keep_cells else out
+        lib = _lib.load()
+        if not keep_cells:
+            _lib.check(lib.tfi_integrate_expsum(
+                self._h, int(c.numel()), c.data_ptr(), lam.data_ptr(), F.data_ptr(), d,
+                _DTYPES[F.dtype], out.data_ptr(), self._stream(self.device)))
             return out
-        _lib.check(_lib.load().tfi_integrate_expsum(
+        rows = lib.tfi_cell_rows(self._h)
+        _lib.check(rows if rows < 0 else 0)
+        cells = torch.empty((rows, d), dtype=F.dtype, device=F.device)
+        _lib.check(lib.tfi_integrate_expsum_cells(
             self._h, int(c.numel()), c.data_ptr(), lam.data_ptr(), F.data_ptr(), d,
-            _DTYPES[F.dtype], out.data_ptr(), self._stream(self.device)))
-        return out
+            _DTYPES[F.dtype], out.data_ptr(), cells.data_ptr(), self._stream(self.device)))
+        return out, cells
 
-    def backward_expsum(self, c, lam, F, gout, need_dF=True, need_moments=True):
+    def backward_expsum(self, c, lam, F, gout, need_dF=True, need_moments=True, cells=None):
         """Adjoint of ``integrate_expsum`` for L = sum(gout * out): returns
         ``(dF, s0, s1)`` with s0[l] = sum lam[l]**dist <gout_v, F_w> and
         s1[l] = sum dist lam[l]**dist <gout_v, F_w> (float64), so that
-        dL/dc = s0 and dL/dlam = c s1 / lam."""
+        dL/dc = s0 and dL/dlam = c s1 / lam. ``cells``: the cell sums of F
+        from ``integrate_expsum(..., keep_cells=True)`` with the same F."""
         self._check_expsum(c, lam, F)
         if F.shape != gout.shape or gout.dtype != F.dtype or not gout.is_contiguous():
             raise ValueError("gout must be a contiguous tensor like F")
@@ -253,11 +266,21 @@ class TreeIntegrator:
         dF = torch.empty_like(F) if need_dF else None
         s0 = torch.empty(n, dtype=torch.float64, device=self.device) if need_moments else None
         s1 = torch.empty(n, dtype=torch.float64, device=self.device) if need_moments else None
-        _lib.check(_lib.load().tfi_backward_expsum(
-            self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
-            _DTYPES[F.dtype], dF.data_ptr() if dF is not None else None,
-            s0.data_ptr() if s0 is not None else None,
-            s1.data_ptr() if s1 is not None else None, self._stream(self.device)))
+        lib = _lib.load()
+        ptrs = (_DTYPES[F.dtype], dF.data_ptr() if dF is not None else None,
+                s0.data_ptr() if s0 is not None else None,
+                s1.data_ptr() if s1 is not None else None, self._stream(self.device))
+        if cells is None:
+            _lib.check(lib.tfi_backward_expsum(
+                self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
+                *ptrs))
+        else:
+            if (cells.dtype != F.dtype or cells.device != F.device or not cells.is_contiguous()
+                    or tuple(cells.shape) != (lib.tfi_cell_rows(self._h), d)):
+                raise ValueError("cells must be the tensor integrate_expsum kept for this F")
+            _lib.check(lib.tfi_backward_expsum_cells(
+                self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), cells.data_ptr(),
+                gout.data_ptr(), d, *ptrs))
         return dF, s0, s1
 
     def close(self):
@@ -306,18 +329,26 @@ class ExpSumIntegrate(torch.autograd.Function):
     def forward(ctx, integrator, F, a, b):
         lam = torch.exp(-b)
         ctx.integrator = integrator
-        ctx.save_for_backward(F, a, lam)
-        return integrator.integrate_expsum(a.contiguous(), lam.contiguous(), F)
+        # the moments need the cell sums of F: keep the forward's
+        keep = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
+        if keep:
+            out, cells = integrator.integrate_expsum(a.contiguous(), lam.contiguous(), F,
+                                                     keep_cells=True)
+        else:
+            out, cells = integrator.integrate_expsum(a.contiguous(), lam.contiguous(), F), None
+        ctx.save_for_backward(F, a, lam, cells)
+        return out
 
     @staticmethod
     def backward(ctx, gout):
-        F, a, lam = ctx.saved_tensors
+        F, a, lam, cells = ctx.saved_tensors
         need_dF = ctx.needs_input_grad[1]
         need_ab = ctx.needs_input_grad[2] or ctx.needs_input_grad[3]
         if not (need_dF or need_ab):
             return None, None, None, None
         dF, s0, s1 = ctx.integrator.backward_expsum(a.contiguous(), lam.contiguous(), F,
-                                                    gout.contiguous(), need_dF, need_ab)
+                                                    gout.contiguous(), need_dF, need_ab,
+                                                    cells=cells)
         da = s0.to(a.dtype) if need_ab else None
         db = (-a * s1.to(a.dtype)) if need_ab else None
         return None, dF, da, db

@@ -133,6 +133,38 @@ def test_expsum_fp64_wide_rows(policy):
     assert max(errs) <= 1e-10, errs
 
 
+@pytest.mark.parametrize("dtype,d", [(torch.float32, 64), (torch.float64, 3)])
+def test_expsum_kept_cells_bitwise(dtype, d):
+    """The backward that reads the forward's cell sums equals the one that
+    forms them again, also when the handle ran another field in between: dF
+    bit for bit, the moments to the rounding of the leaf pair histogram
+    (binned with atomics); misuse of the cells argument is an error."""
+    rng = np.random.default_rng(91)
+    cp = S.caterpillar(40, 3)[0]
+    p, w, _ = S.forest([S.grid_mst(16, 16, rng), (cp, S.uniform_weights(cp, 1, 4, rng))])
+    print(f"expsum kept cells N={len(p)} d={d} {dtype}", flush=True)
+    t = TreeIntegrator(p, w, device=0)
+    ct = torch.tensor(rng.standard_normal(8), dtype=dtype, device=DEV)
+    lt = torch.tensor(np.exp(-rng.uniform(0.01, 0.5, 8)), dtype=dtype, device=DEV)
+    F1 = torch.tensor(rng.standard_normal((len(p), d)), dtype=dtype, device=DEV)
+    F2 = torch.tensor(rng.standard_normal((len(p), d)), dtype=dtype, device=DEV)
+    G = torch.tensor(rng.standard_normal((len(p), d)), dtype=dtype, device=DEV)
+    ref = t.integrate_expsum(ct, lt, F1)
+    out, cells = t.integrate_expsum(ct, lt, F1, keep_cells=True)
+    assert torch.equal(out, ref)
+    t.integrate_expsum(ct, lt, F2)  # the handle's own buffers now hold F2
+    for _ in range(2):  # eager, then graph replay
+        a = t.backward_expsum(ct, lt, F1, G)
+        b = t.backward_expsum(ct, lt, F1, G, cells=cells)
+        torch.cuda.synchronize()
+        assert torch.equal(a[0], b[0])
+        tol = 1e-5 if dtype == torch.float32 else 1e-12
+        for x, y in zip(a[1:], b[1:]):
+            assert relerr(y.cpu().numpy(), x.cpu().numpy()) <= tol
+    with pytest.raises(ValueError):
+        t.backward_expsum(ct, lt, F1, G, cells=cells[1:])
+
+
 def test_expsum_autograd_matches_fd_and_table_path():
     rng = np.random.default_rng(55)
     p, w, _ = S.forest([S.grid_mst(s, 16, rng) for s in (6, 8, 7)])
