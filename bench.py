@@ -97,6 +97,8 @@ def main():
                     help="keep the default direct/FFT rule instead of tuning it")
     ap.add_argument("--fft-cost", type=float, default=None,
                     help="use this direct/FFT cost constant instead of tuning it")
+    ap.add_argument("--leaf-max", type=int, default=None,
+                    help="dense leaf-tile size of the plain-forward plan instead of tuning it")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched forest forward+backward measurement")
     ap.add_argument("--no-wide", action="store_true",
@@ -114,7 +116,7 @@ def main():
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
@@ -134,24 +136,37 @@ def main():
     W = S.workload("rrt100k")
     p, w, F = W["parent"], W["weight"], W["F"]
     N, d = F.shape
+    def tables(K):
+        return [torch.tensor(fn(K), dtype=torch.float32, device=dev) for _, fn in W["kernels"]]
+
     t0 = time.perf_counter()
-    tfi = TreeIntegrator(p, w, device=0)
-    build_s = time.perf_counter() - t0
+    leaf_tuning = None
+    if args.leaf_max is not None or args.fft_cost is not None or args.no_autotune:
+        tfi = TreeIntegrator(p, w, device=0, leaf_max=args.leaf_max or 0)
+        build_s = time.perf_counter() - t0
+        fs = tables(tfi.kernel_length)
+        t0 = time.perf_counter()
+        if args.fft_cost is not None:
+            tfi.set_fft_cost(args.fft_cost)
+            cost = args.fft_cost
+        else:
+            cost = tfi.autotune(fs[0], d) if not args.no_autotune else tfi.stats()["fft_cost"]
+    else:
+        # plan per leaf-tile size, each with its table rule autotuned; the
+        # fastest is kept (setup, outside the timed steps)
+        tfi = TreeIntegrator.tuned(p, w, tables, d, device=0)
+        build_s = time.perf_counter() - t0
+        fs = tables(tfi.kernel_length)
+        cost = tfi.stats()["fft_cost"]
+        leaf_tuning = tfi.tuning
+    tune_s = time.perf_counter() - t0
     K = tfi.kernel_length
     tabs = [fn(K) for _, fn in W["kernels"]]
-    fs = [torch.tensor(t, dtype=torch.float32, device=dev) for t in tabs]
     Ft = torch.tensor(F, device=dev)
-    t0 = time.perf_counter()
-    if args.fft_cost is not None:
-        tfi.set_fft_cost(args.fft_cost)
-        cost = args.fft_cost
-    else:
-        cost = tfi.autotune(fs[0], d) if not args.no_autotune else tfi.stats()["fft_cost"]
-    tune_s = time.perf_counter() - t0
     log(f"bench: N={N} d={d} build {build_s:.2f}s kernel_length={K} "
         f"autotuned fft_cost={cost} in {tune_s:.2f}s")
 
-    outs = [None, None]
+    outs = [torch.empty_like(Ft) for _ in fs]
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -160,12 +175,13 @@ def main():
         del src, dst
 
     def step():
-        # both kernels in one call: the cell sums of F are formed once
-        outs[:] = tfi.integrate_many(fs, Ft)
+        # both kernels in one call: the cell sums of F are formed once; the
+        # results go to the same tensors every step
+        tfi.integrate_many(fs, Ft, out=outs)
 
     def step_separate():
         for i, f in enumerate(fs):
-            outs[i] = tfi.integrate(f, Ft)
+            tfi.integrate(f, Ft, out=outs[i])
 
     for _ in range(args.warmup):
         step()
@@ -276,7 +292,10 @@ def main():
                                "tfi_integrate_multi call: the cell sums of F are formed once)",
                    "N": int(N), "d": int(d), "kernels": 2,
                    "kernel_length": int(K), "build_s": round(build_s, 3),
-                   "fft_cost": cost},
+                   "fft_cost": cost,
+                   "leaf_max": int(getattr(tfi, "leaf_max", None) or args.leaf_max or 32),
+                   "leaf_tuning_ms": ({str(k): round(v, 4) for k, v in leaf_tuning.items()}
+                                      if leaf_tuning else None)},
         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
         "ms_per_step_two_calls": round(separate_ms, 5),
         "exp_kernel_ms_per_integration": {k: round(v, 5) for k, v in exp_ms.items()},

@@ -611,6 +611,7 @@ int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
     if (rc) return rc;
     plan.N = N;
     plan.roots = (int64_t)roots.size();
+    plan.leaf_max = opt.leaf_max;
     try {
         Planner pl(T, opt, plan);
         rc = pl.run(roots, err);
@@ -661,7 +662,8 @@ std::string plan_stats_json(const Plan& p) {
         }
     }
     o << "{\"N\":" << p.N << ",\"roots\":" << p.roots
-      << ",\"calls\":" << p.calls << ",\"leaf_calls\":" << p.leaf_calls
+      << ",\"calls\":" << p.calls << ",\"leaf_max\":" << p.leaf_max
+      << ",\"leaf_calls\":" << p.leaf_calls
       << ",\"singleton_calls\":" << p.singleton_calls
       << ",\"diameter_choices\":" << p.diam_choices
       << ",\"centroid_choices\":" << p.centroid_choices

@@ -73,6 +73,7 @@ struct Plan {
     // ---- statistics ----------------------------------------------------------
     int64_t kernel_len = 1;   // entries of f read by any stage
     int64_t max_backbone = 0; // longest backbone or leaf-tile distance
+    int32_t leaf_max = 0;     // dense-tile size the plan was built with
     int64_t calls = 0, leaf_calls = 0, singleton_calls = 0;
     int64_t diam_choices = 0, centroid_choices = 0;
     int32_t levels = 0;

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import ctypes as C
 import json
+import time
 import os
 
 import numpy as np
@@ -62,6 +63,49 @@ class TreeIntegrator:
         lib = _lib.load()
         self.num_vertices = int(lib.tfi_num_vertices(self._h))
         self.kernel_length = int(lib.tfi_kernel_length(self._h))
+
+    @classmethod
+    def tuned(cls, parent, weight, f, d, *, leaf_sizes=(16, 32, 48, 64), device=0, reps=30,
+              **options):
+        """Plan with the fastest dense leaf-tile size for forward integrations
+        of ``d`` channels with the kernel table ``f`` (or a list of tables,
+        integrated together as by ``integrate_many``; or a callable that
+        returns them for a kernel length, since the length a plan needs can
+        depend on its leaf tiles). One plan per size in
+        ``leaf_sizes`` is built, its table rule autotuned (``autotune``) and
+        ``reps`` integrations of a zero field timed; the fastest plan is
+        returned with ``tuning`` = {leaf size: ms per integration}. Larger
+        tiles trade incidences and table work for dense n^2 tile work, so the
+        best size depends on the tree, d and the dtype. ``options`` go to the
+        constructor."""
+        best, times = None, {}
+        for leaf in leaf_sizes:
+            t = cls(parent, weight, leaf_max=int(leaf), device=device, **options)
+            fs = f(t.kernel_length) if callable(f) else f
+            fs = list(fs) if isinstance(fs, (list, tuple)) else [fs]
+            t.autotune(fs[0], d)
+            F = torch.zeros((t.num_vertices, int(d)), dtype=fs[0].dtype, device=t.device)
+            outs = [torch.empty_like(F) for _ in fs]
+            run = ((lambda: t.integrate_many(fs, F, out=outs)) if len(fs) > 1
+                   else (lambda: t.integrate(fs[0], F, out=outs[0])))
+            for _ in range(3):
+                run()
+            torch.cuda.synchronize(t.device)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run()
+            torch.cuda.synchronize(t.device)
+            times[int(leaf)] = 1e3 * (time.perf_counter() - t0) / reps
+            del F, outs
+            if best is None or times[int(leaf)] < times[best[0]]:
+                if best is not None:
+                    best[1].close()
+                best = (int(leaf), t)
+            else:
+                t.close()
+        best[1].tuning = times
+        best[1].leaf_max = best[0]
+        return best[1]
 
     # ------------------------------------------------------------- info --
     def stats(self):
@@ -163,11 +207,26 @@ class TreeIntegrator:
     def _stream(dev):
         return torch.cuda.current_stream(dev).cuda_stream
 
-    def integrate(self, f, F):
-        """out = f(D) F for F of shape [N] or [N, d]."""
+    @staticmethod
+    def _out_like(F, out):
+        """``out`` checked to be a tensor F's shape, dtype and device (and
+        distinct from F), or a new one."""
+        if out is None:
+            return torch.empty_like(F)
+        if (out.shape != F.shape or out.dtype != F.dtype or out.device != F.device
+                or not out.is_contiguous()):
+            raise ValueError("out must be a contiguous tensor like F")
+        if out.data_ptr() == F.data_ptr():
+            raise ValueError("out must not alias F")
+        return out
+
+    def integrate(self, f, F, out=None):
+        """out = f(D) F for F of shape [N] or [N, d]. ``out``: optional
+        preallocated result (a loop that reuses it replays one captured
+        graph; a new tensor per call may need a graph per address)."""
         self._check(f, F)
         d = 1 if F.dim() == 1 else F.shape[1]
-        out = torch.empty_like(F)
+        out = self._out_like(F, out)
         if d == 0:
             return out
         lib = _lib.load()
@@ -176,9 +235,10 @@ class TreeIntegrator:
                                      self._stream(self.device)))
         return out
 
-    def integrate_many(self, fs, F):
+    def integrate_many(self, fs, F, out=None):
         """[f_i(D) F for f_i in fs] in one call (at most 4 kernel tables of
-        one dtype): the cell sums of F are formed once for all kernels."""
+        one dtype): the cell sums of F are formed once for all kernels.
+        ``out``: optional list of preallocated results, one per table."""
         fs = list(fs)
         if not 1 <= len(fs) <= 4:
             raise ValueError("integrate_many takes 1 to 4 kernel tables")
@@ -187,7 +247,11 @@ class TreeIntegrator:
         for f in fs:
             self._check(f, F)
         d = 1 if F.dim() == 1 else F.shape[1]
-        outs = [torch.empty_like(F) for _ in fs]
+        if out is not None and len(out) != len(fs):
+            raise ValueError("out needs one tensor per kernel table")
+        outs = [self._out_like(F, None if out is None else out[i]) for i in range(len(fs))]
+        if len({o.data_ptr() for o in outs}) != len(outs):
+            raise ValueError("the outputs must be distinct tensors")
         if d == 0:
             return outs
         lib = _lib.load()

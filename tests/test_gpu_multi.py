@@ -74,3 +74,55 @@ def test_multi_argument_errors():
         t.integrate_many([f] * 5, F)
     with pytest.raises(TypeError):
         t.integrate_many([f, f.double()], F)
+
+
+def test_tuned_leaf_size():
+    """TreeIntegrator.tuned builds one plan per leaf-tile size, keeps the
+    fastest, and that plan integrates like any other (oracle on rows)."""
+    rng = np.random.default_rng(12)
+    p, _ = S.random_recursive(5000, rng)
+    w = S.uniform_weights(p, 1, 8, rng)
+    d = 16
+    print(f"tuned leaf sizes rrt N={len(p)} d={d}", flush=True)
+    make = lambda K: [torch.tensor(t, dtype=torch.float32, device=DEV) for t in kernels(K, 2)]
+    t = TreeIntegrator.tuned(p, w, make, d, leaf_sizes=(8, 64), reps=5)
+    assert set(t.tuning) == {8, 64} and t.leaf_max in t.tuning
+    assert t.tuning[t.leaf_max] == min(t.tuning.values())
+    assert t.stats()["leaf_max"] == t.leaf_max
+    F = rng.standard_normal((len(p), d))
+    outs = t.integrate_many(make(t.kernel_length), torch.tensor(F, dtype=torch.float32, device=DEV))
+    rows = np.sort(rng.choice(len(p), 128, replace=False))
+    for tab, y in zip(kernels(t.kernel_length, 2), outs):
+        ref = oracle.integrate(p, w, tab, F, rows=rows)
+        e = np.linalg.norm(y.cpu().numpy()[rows] - ref) / np.linalg.norm(ref)
+        assert e <= 1e-4, e
+
+
+def test_preallocated_outputs():
+    """out= writes the same values into the caller's tensors (one graph for
+    the loop); bad out arguments are errors."""
+    rng = np.random.default_rng(14)
+    p, _ = S.random_recursive(3000, rng)
+    w = S.uniform_weights(p, 1, 8, rng)
+    d = 8
+    print(f"preallocated outputs rrt N={len(p)} d={d}", flush=True)
+    t = TreeIntegrator(p, w, device=0)
+    fs = [torch.tensor(x, dtype=torch.float32, device=DEV) for x in kernels(t.kernel_length, 2)]
+    F = torch.tensor(rng.standard_normal((len(p), d)), dtype=torch.float32, device=DEV)
+    ref = t.integrate_many(fs, F)
+    outs = [torch.full_like(F, float("nan")) for _ in fs]
+    for _ in range(3):
+        got = t.integrate_many(fs, F, out=outs)
+        torch.cuda.synchronize()
+        assert all(g is o for g, o in zip(got, outs))
+        assert all(torch.equal(a, b) for a, b in zip(ref, outs))
+    one = torch.empty_like(F)
+    assert t.integrate(fs[0], F, out=one) is one and torch.equal(one, t.integrate(fs[0], F))
+    with pytest.raises(ValueError):
+        t.integrate(fs[0], F, out=F)
+    with pytest.raises(ValueError):
+        t.integrate(fs[0], F, out=one[:-1])
+    with pytest.raises(ValueError):
+        t.integrate_many(fs, F, out=[one, one])
+    with pytest.raises(ValueError):
+        t.integrate_many(fs, F, out=[one])
