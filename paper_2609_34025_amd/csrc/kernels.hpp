@@ -539,16 +539,20 @@ __global__ void k_gather(int64_t N, int32_t d, int32_t ct, const int64_t* __rest
 // in leaf_v, tile size, offset of the quad's first kernel row in the
 // group's f(D) block); grp holds quad ranges per group and koff the
 // group's first leaf_D entry and count.
+// NK = 2: two kernels f, f1 over the same tiles in one launch (the
+// distances and field rows are staged once; out1 = f1(D) F); the threads
+// take (kernel, quad) tasks, so the sums are those of two NK = 1 launches.
 constexpr int kLeafMax = 64, kLeafQuads = 32, kLeafSlots = 128, kLeafK = 4096,
               kLeafThreads = 256;
 
-template <typename T>
+template <typename T, int NK = 1>
 __global__ void __launch_bounds__(kLeafThreads)
 k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ gk,
        const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
        const int32_t* __restrict__ leaf_D, const T* __restrict__ f, const T* __restrict__ F,
-       T* __restrict__ out) {
-    __shared__ T sk[kLeafK];
+       T* __restrict__ out, const T* __restrict__ f1 = nullptr, T* __restrict__ out1 = nullptr) {
+    static_assert(NK == 1 || NK == 2, "one or two kernels");
+    __shared__ T sk[NK * kLeafK];
     __shared__ __attribute__((aligned(16))) T sF[kLeafSlots * kDirCh];
     __shared__ int32_t svtx[kLeafSlots];
     const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1];
@@ -564,13 +568,17 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
 #pragma unroll
         for (int i = 0; i < kPer; ++i)
             di[i] = leaf_D[kb + min((int32_t)threadIdx.x + kLeafThreads * i, nk - 1)];
-        T fv[kPer];
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) fv[i] = f[di[i]];
+        for (int u = 0; u < NK; ++u) {
+            const T* fu = u ? f1 : f;
+            T fv[kPer];
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int32_t k = threadIdx.x + kLeafThreads * i;
-            if (k < nk) sk[k] = fv[i];
+            for (int i = 0; i < kPer; ++i) fv[i] = fu[di[i]];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int32_t k = threadIdx.x + kLeafThreads * i;
+                if (k < nk) sk[u * kLeafK + k] = fv[i];
+            }
         }
     }
     for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
@@ -597,7 +605,12 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
         }
         __syncthreads();
         const int32_t cq0 = threadIdx.x / nq;
-        for (int32_t qq = cq0; cq0 < qpp && q0 + qq < q1; qq += qpp) {
+        const int32_t nquads = q1 - q0;
+        for (int32_t tq = cq0; cq0 < qpp && tq < NK * nquads; tq += qpp) {
+            const int32_t u = NK > 1 && tq >= nquads ? 1 : 0;
+            const int32_t qq = tq - u * nquads;
+            const T* sku = sk + u * kLeafK;
+            T* outu = u ? out1 : out;
             const int32_t chq = threadIdx.x % nq;
             const int32_t q = q0 + qq;
             const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
@@ -610,13 +623,13 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
                 const vec4<T> v = ld4(sF + (tb - vb + j) * kDirCh + 4 * chq);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (c < rows) fma4(acc[c], sk[krow + c * n + j], v);
+                    if (c < rows) fma4(acc[c], sku[krow + c * n + j], v);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 if (c >= rows) continue;
                 const int32_t vtx = leaf_v[first + c];
-                T* o = out + (int64_t)vtx * d + c0 + 4 * chq;
+                T* o = outu + (int64_t)vtx * d + c0 + 4 * chq;
                 const int32_t left = nch - 4 * chq;
                 const T vv[4] = {acc[c].x, acc[c].y, acc[c].z, acc[c].w};
                 for (int cc = 0; cc < 4 && cc < left; ++cc) o[cc] = vv[cc];

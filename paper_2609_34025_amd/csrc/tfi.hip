@@ -1172,18 +1172,34 @@ inline unsigned chan_split(int64_t xblocks, int32_t d, int32_t step) {
 }
 
 template <typename T>
-void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
+void enq_leaf(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st,
+              const T* f1 = nullptr, T* out1 = nullptr) {
     if (h->nlgrp == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
-    hipLaunchKernelGGL(tfi::k_leaf<T>,
-                       dim3((unsigned)h->nlgrp, chan_split(h->nlgrp, d, tfi::kDirCh)),
-                       dim3(tfi::kLeafThreads), 0, st, d,
-                       h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out);
+    const dim3 grid((unsigned)h->nlgrp, chan_split(h->nlgrp, d, tfi::kDirCh));
+    const int nk = f1 ? 2 : 1;
+    if (nk == 2) {
+        if constexpr (sizeof(T) == 4) {
+            hipLaunchKernelGGL((tfi::k_leaf<T, 2>), grid, dim3(tfi::kLeafThreads), 0, st, d,
+                               h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F,
+                               out, f1, out1);
+        } else {  // FP64: one launch per kernel
+            for (int u = 0; u < 2; ++u)
+                hipLaunchKernelGGL((tfi::k_leaf<T, 1>), grid, dim3(tfi::kLeafThreads), 0, st, d,
+                                   h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D,
+                                   u ? f1 : f, F, u ? out1 : out, (const T*)nullptr,
+                                   (T*)nullptr);
+        }
+    } else {
+        hipLaunchKernelGGL((tfi::k_leaf<T, 1>), grid, dim3(tfi::kLeafThreads), 0, st, d,
+                           h->d_lgrp, h->d_lgk, h->d_lq, h->d_leaf_v, h->d_leaf_D, f, F, out,
+                           (const T*)nullptr, (T*)nullptr);
+    }
     const double nv = (double)p.leaf_v.size();
     h->end(st, ev, "leaf",
-           2.0 * sizeof(T) * d * nv + 4.0 * nv + 4.0 * (double)p.leaf_D.size(),
-           2.0 * d * (double)p.leaf_pairs);
+           sizeof(T) * d * nv * (1.0 + nk) + 4.0 * nv + 4.0 * (double)p.leaf_D.size(),
+           2.0 * d * nk * (double)p.leaf_pairs);
 }
 
 // Kernel spectra of every FFT bucket into spec (default: the handle's arena;
@@ -1510,7 +1526,14 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     T* g0 = (T*)h->g[ti].p;
     const int64_t gstride = std::max<int64_t>(p.NA + p.NB, 1) * (int64_t)d;
     fork3(h, s0, s1, s2);
-    for (int i = 0; i < nk; ++i) enq_leaf<T>(h, f[i], F, d, out[i], s2);
+    // leaf tiles in pairs of kernels (FP32: two FP64 f(D) blocks would not
+    // fit the LDS of one workgroup)
+    for (int i = 0; i < nk;) {
+        const bool two = sizeof(T) == 4 && i + 1 < nk;
+        enq_leaf<T>(h, f[i], F, d, out[i], s2, two ? f[i + 1] : nullptr,
+                    two ? out[i + 1] : nullptr);
+        i += two ? 2 : 1;
+    }
     (void)hipEventRecord(h->ev_c, s2);
     for (int i = 0; i < nk; ++i) enq_spectra<T>(h, f[i], s1, spec0 + i * sstride);
     launch_scatter<T>(h, F, val, d, s0);
