@@ -1462,6 +1462,27 @@ inline void fork3(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
     (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
 }
 
+// Whether the plan has FFT tables in dtype T (LDS tiers or global buckets):
+// without them the forward leaves the FFT side stream out of the DAG, so
+// that a captured graph holds no empty branch (each cross-queue edge costs
+// microseconds at replay).
+template <typename T>
+bool fft_work(const tfi_plan* h) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    for (int t = 0; t < 3; ++t)
+        if (h->tiers[ti][t].nbuckets || h->tiers[ti][t].njobs) return true;
+    return !h->global_b[ti].empty();
+}
+
+// Fork the side streams that have work from s0.
+inline void fork_sides(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t s2, bool use1,
+                       bool use2) {
+    if (!use1 && !use2) return;
+    (void)hipEventRecord(h->ev_fork, s0);
+    if (use1) (void)hipStreamWaitEvent(s1, h->ev_fork, 0);
+    if (use2) (void)hipStreamWaitEvent(s2, h->ev_fork, 0);
+}
+
 // Enqueue out = f(D) F: `s0` is the main stream, s1/s2 the side streams.
 // Whole-path mode: kernel spectra, then the convolution of every job from the
 // field rows straight into the output rows.
@@ -1493,18 +1514,23 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
     const int ti = sizeof(T) == 8 ? 1 : 0;
     T* val = (T*)h->val[ti].p;
     T* g = (T*)h->g[ti].p;
-    fork3(h, s0, s1, s2);
-    enq_leaf<T>(h, f, F, d, out, s2);          // side2: leaf rows into out
-    (void)hipEventRecord(h->ev_c, s2);
-    enq_spectra<T>(h, f, s1);                   // side1: kernel spectra
+    const bool use1 = fft_work<T>(h), use2 = h->nlgrp > 0;
+    fork_sides(h, s0, s1, s2, use1, use2);
+    if (use2) {
+        enq_leaf<T>(h, f, F, d, out, s2);      // side2: leaf rows into out
+        (void)hipEventRecord(h->ev_c, s2);
+    }
+    if (use1) enq_spectra<T>(h, f, s1);         // side1: kernel spectra
     launch_scatter<T>(h, F, val, d, s0);        // main: cell sums
-    (void)hipEventRecord(h->ev_a, s0);
-    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-    enq_fft<T>(h, d, val, g, s1);               // side1: FFT tables
-    (void)hipEventRecord(h->ev_b, s1);
+    if (use1) {
+        (void)hipEventRecord(h->ev_a, s0);
+        (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+        enq_fft<T>(h, d, val, g, s1);           // side1: FFT tables
+        (void)hipEventRecord(h->ev_b, s1);
+    }
     enq_direct<T>(h, f, d, val, g, s0);         // main: direct tables
-    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
-    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    if (use1) (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    if (use2) (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     enq_gather<T>(h, d, g, out, s0);            // main: out = leaf + calls
 }
 
@@ -1525,22 +1551,32 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     T* val = (T*)h->val[ti].p;
     T* g0 = (T*)h->g[ti].p;
     const int64_t gstride = std::max<int64_t>(p.NA + p.NB, 1) * (int64_t)d;
-    fork3(h, s0, s1, s2);
+    const bool use1 = fft_work<T>(h), use2 = h->nlgrp > 0;
+    fork_sides(h, s0, s1, s2, use1, use2);
+    // the main chain is enqueued first (in a captured graph the first chain
+    // keeps the launch queue, so the gather follows the direct tables on
+    // one queue and its wait for the side streams finds them done)
+    launch_scatter<T>(h, F, val, d, s0);
     // leaf tiles in pairs of kernels (FP32: two FP64 f(D) blocks would not
     // fit the LDS of one workgroup)
-    for (int i = 0; i < nk;) {
-        const bool two = sizeof(T) == 4 && i + 1 < nk;
-        enq_leaf<T>(h, f[i], F, d, out[i], s2, two ? f[i + 1] : nullptr,
-                    two ? out[i + 1] : nullptr);
-        i += two ? 2 : 1;
+    if (use2) {
+        for (int i = 0; i < nk;) {
+            const bool two = sizeof(T) == 4 && i + 1 < nk;
+            enq_leaf<T>(h, f[i], F, d, out[i], s2, two ? f[i + 1] : nullptr,
+                        two ? out[i + 1] : nullptr);
+            i += two ? 2 : 1;
+        }
+        (void)hipEventRecord(h->ev_c, s2);
     }
-    (void)hipEventRecord(h->ev_c, s2);
-    for (int i = 0; i < nk; ++i) enq_spectra<T>(h, f[i], s1, spec0 + i * sstride);
-    launch_scatter<T>(h, F, val, d, s0);
-    (void)hipEventRecord(h->ev_a, s0);
-    (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-    for (int i = 0; i < nk; ++i) enq_fft<T>(h, d, val, g0 + i * gstride, s1, spec0 + i * sstride);
-    (void)hipEventRecord(h->ev_b, s1);
+    if (use1)
+        for (int i = 0; i < nk; ++i) enq_spectra<T>(h, f[i], s1, spec0 + i * sstride);
+    if (use1) {
+        (void)hipEventRecord(h->ev_a, s0);
+        (void)hipStreamWaitEvent(s1, h->ev_a, 0);
+        for (int i = 0; i < nk; ++i)
+            enq_fft<T>(h, d, val, g0 + i * gstride, s1, spec0 + i * sstride);
+        (void)hipEventRecord(h->ev_b, s1);
+    }
     // kernels in pairs: one launch per pair for the direct tables and the
     // gather
     for (int i = 0; i < nk; i += 2) {
@@ -1548,8 +1584,8 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
         enq_direct<T>(h, f[i], d, val, g0 + i * gstride, s0, two ? f[i + 1] : nullptr,
                       two ? g0 + (i + 1) * gstride : nullptr);
     }
-    (void)hipStreamWaitEvent(s0, h->ev_b, 0);
-    (void)hipStreamWaitEvent(s0, h->ev_c, 0);
+    if (use1) (void)hipStreamWaitEvent(s0, h->ev_b, 0);
+    if (use2) (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     for (int i = 0; i < nk; i += 2) {
         const bool two = i + 1 < nk;
         enq_gather<T>(h, d, g0 + i * gstride, out[i], s0,
