@@ -554,54 +554,57 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
     static_assert(NK == 1 || NK == 2, "one or two kernels");
     __shared__ T sk[NK * kLeafK];
     __shared__ __attribute__((aligned(16))) T sF[kLeafSlots * kDirCh];
-    __shared__ int32_t svtx[kLeafSlots];
     const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1];
     const int64_t kb = gk[2 * blockIdx.x];
     const int32_t nk = (int32_t)gk[2 * blockIdx.x + 1];
     // vertex slots are leaf_v positions [vb, vb + nv): the group's tiles
     const int32_t vb = lq[4 * q0 + 1];
     const int32_t nv = lq[4 * (q1 - 1) + 1] + lq[4 * (q1 - 1) + 2] - vb;
-    {
-        // f(D) of the group: all distance loads first, then the table entries
-        constexpr int kPer = kLeafK / kLeafThreads;
-        int32_t di[kPer];
+    // the two independent load chains are issued together: distances, then
+    // the kernel entries they select; vertex ids, then the field rows
+    constexpr int kPerK = kLeafK / kLeafThreads;
+    constexpr int kPerF = kLeafSlots / (kLeafThreads / 16);
+    const int32_t lc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+    int32_t di[kPerK];
 #pragma unroll
-        for (int i = 0; i < kPer; ++i)
-            di[i] = leaf_D[kb + min((int32_t)threadIdx.x + kLeafThreads * i, nk - 1)];
+    for (int i = 0; i < kPerK; ++i)
+        di[i] = leaf_D[kb + min((int32_t)threadIdx.x + kLeafThreads * i, nk - 1)];
+    int32_t vt[kPerF];
 #pragma unroll
-        for (int u = 0; u < NK; ++u) {
-            const T* fu = u ? f1 : f;
-            T fv[kPer];
+    for (int i = 0; i < kPerF; ++i) vt[i] = leaf_v[vb + min(k0 + 16 * i, nv - 1)];
+    T fv[NK][kPerK];
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) fv[i] = fu[di[i]];
+    for (int u = 0; u < NK; ++u) {
+        const T* fu = u ? f1 : f;
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int32_t k = threadIdx.x + kLeafThreads * i;
-                if (k < nk) sk[u * kLeafK + k] = fv[i];
-            }
-        }
+        for (int i = 0; i < kPerK; ++i) fv[u][i] = fu[di[i]];
     }
-    for (int32_t i = threadIdx.x; i < nv; i += blockDim.x) svtx[i] = leaf_v[vb + i];
     // channel chunks: this workgroup takes every gridDim.y-th one
+    bool stage_k = true;
     for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += gridDim.y * kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         const int32_t nq = (nch + 3) >> 2;
         const int32_t qpp = kLeafThreads / nq;
-        __syncthreads();
-        {
-            // field rows of the group's vertices, all loads in flight at once
-            constexpr int kPer = kLeafSlots / (kLeafThreads / 16);
-            const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
-            const int32_t ccs = min(cc, nch - 1);
-            T v[kPer];
+        // field rows of the group's vertices, all loads in flight at once
+        const int32_t ccs = min(lc, nch - 1);
+        T v[kPerF];
 #pragma unroll
-            for (int i = 0; i < kPer; ++i)
-                v[i] = F[(int64_t)svtx[min(k0 + 16 * i, nv - 1)] * d + c0 + ccs];
+        for (int i = 0; i < kPerF; ++i) v[i] = F[(int64_t)vt[i] * d + c0 + ccs];
+        if (stage_k) {
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int32_t k = k0 + 16 * i;
-                if (k < nv) sF[k * kDirCh + cc] = (cc < nch) ? v[i] : (T)0;
-            }
+            for (int u = 0; u < NK; ++u)
+#pragma unroll
+                for (int i = 0; i < kPerK; ++i) {
+                    const int32_t k = threadIdx.x + kLeafThreads * i;
+                    if (k < nk) sk[u * kLeafK + k] = fv[u][i];
+                }
+            stage_k = false;
+        }
+        __syncthreads();  // the previous chunk's products are done with sF
+#pragma unroll
+        for (int i = 0; i < kPerF; ++i) {
+            const int32_t k = k0 + 16 * i;
+            if (k < nv) sF[k * kDirCh + lc] = (lc < nch) ? v[i] : (T)0;
         }
         __syncthreads();
         const int32_t cq0 = threadIdx.x / nq;
