@@ -38,10 +38,12 @@ def log(msg):
 LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "kernels_conv1d.hpp", "tfi.hip", "plan.cpp", "plan.hpp"]
 
 
-def measured_traffic(workload, stage):
+def measured_traffic(workload, stage, plan="-"):
     """HBM bytes per launch of a stage from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when the summary has
-    no line for it or the library sources changed since it was taken."""
+    no line for it, the plan differs (leaf-tile size and direct/FFT rule,
+    where the workload tunes them) or the library sources changed since it
+    was taken."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "hbm_traffic_pmc.md")
@@ -52,17 +54,18 @@ def measured_traffic(workload, stage):
         with open(os.path.join(ROOT, "paper_2609_34025_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     sha = h.hexdigest()
-    pat = re.compile(r"<!-- traffic workload=(\S+) stage=(\S+) bytes_per_launch=(\d+) "
-                     r"sources_sha256=([0-9a-f]+) -->")
+    pat = re.compile(r"<!-- traffic workload=(\S+) stage=(\S+) (?:plan=(\S+) )?"
+                     r"bytes_per_launch=(\d+) sources_sha256=([0-9a-f]+) -->")
     with open(path) as fh:
         for line in fh:
             m = pat.search(line)
-            if m and m.group(1) == workload and m.group(2) == stage and m.group(4) == sha:
-                return int(m.group(3))
+            if (m and m.group(1) == workload and m.group(2) == stage
+                    and (m.group(3) or "-") == plan and m.group(5) == sha):
+                return int(m.group(4))
     return None
 
 
-def stage_roofline(name, sd, dtype, workload=None):
+def stage_roofline(name, sd, dtype, workload=None, plan="-"):
     """Roofline entry of one profiled stage ({launches, ms, bytes, flops})."""
     sec = sd["ms"] * 1e-3
     gbs = sd["bytes"] / sec / 1e9
@@ -78,7 +81,8 @@ def stage_roofline(name, sd, dtype, workload=None):
              "frac": round(gbs / HBM_PEAK_GBS, 4)}
         if flops:
             r["tflops"] = round(flops / sec / 1e12, 3)
-    r.update({"kernel": name, "traffic": measured_traffic(workload, name) if workload else None,
+    r.update({"kernel": name,
+              "traffic": measured_traffic(workload, name, plan) if workload else None,
               "launch_us": round(1e3 * sd["ms"] / sd["launches"], 3),
               "bytes_per_launch": sd["bytes"] / sd["launches"],
               "flops_per_launch": flops / sd["launches"]})
@@ -249,7 +253,12 @@ def main():
     # duration; the bound is whichever peak the stage's work would take
     # longer to reach
     dom = max(stages, key=lambda k: stages[k]["ms"])
-    roofline = stage_roofline(dom, stages[dom], "f32", "rrt100k")
+    leaf_used = int(getattr(tfi, "leaf_max", None) or args.leaf_max or 32)
+    # plan key of the counter lines: leaf-tile size and how many tables the
+    # direct/FFT rule sends to the FFT (the tuned constant itself may differ
+    # between runs that assign the same methods)
+    plan_key = f"leaf{leaf_used}_fft{tfi.stats()['fft_jobs']}"
+    roofline = stage_roofline(dom, stages[dom], "f32", "rrt100k", plan=plan_key)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -293,7 +302,7 @@ def main():
                    "N": int(N), "d": int(d), "kernels": 2,
                    "kernel_length": int(K), "build_s": round(build_s, 3),
                    "fft_cost": cost,
-                   "leaf_max": int(getattr(tfi, "leaf_max", None) or args.leaf_max or 32),
+                   "leaf_max": leaf_used, "plan_key": plan_key,
                    "leaf_tuning_ms": ({str(k): round(v, 4) for k, v in leaf_tuning.items()}
                                       if leaf_tuning else None)},
         "parity": {"rows": 512, "rel_err": errs, "ok": ok},
@@ -422,7 +431,9 @@ def batched_fwd_bwd(args, plain_value):
                          "parity": {"rows": 512, "rel_err": errs, "ok": ok},
                          "roofline": stage_roofline(dom, stages[dom], "f32",
                                                     "grid512_sweep" if name == "sweep"
-                                                    else "grid512"),
+                                                    else "grid512",
+                                                    plan="-" if name == "sweep"
+                                                    else f"fft{tfi.stats()['fft_jobs']}"),
                          "stages": stages}
     best = results["sweep"]
     return {"value": best["value"], "unit": "vertex*channels/s", "steps": best["steps"],
@@ -437,7 +448,8 @@ def batched_fwd_bwd(args, plain_value):
             "table_path": {"value": results["table"]["value"],
                            "ms_per_step": results["table"]["ms_per_step"],
                            "ratio_vs_plain_fwd": results["table"]["value"] / plain_value,
-                           "fft_cost": cost, "parity": results["table"]["parity"],
+                           "fft_cost": cost, "plan_key": f"fft{tfi.stats()['fft_jobs']}",
+                           "parity": results["table"]["parity"],
                            "roofline": results["table"]["roofline"],
                            "stages": results["table"]["stages"]}}
 
