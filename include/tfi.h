@@ -254,6 +254,23 @@ int tfi_backward_expsum(tfi_handle h, int32_t nterm, const void *c,
  * Errors as tfi_integrate_expsum; cells == NULL is TFI_ERR_ARG.
  */
 int64_t tfi_cell_rows(tfi_handle h);
+
+/*
+ * The same for kernel tables: tfi_integrate_cells is tfi_integrate that
+ * also leaves the cell sums of F in cells (device dtype[tfi_cell_rows(h) x
+ * d], caller-owned, overwritten; must not alias F or out; the plan's
+ * whole-path shortcut is not taken, since it forms no cell sums).
+ * tfi_backward_cells is tfi_backward that takes them for df instead of
+ * scattering F again (same handle, F and d as the forward; dF must not
+ * alias cells). dF is bitwise that of tfi_backward, df the same to the
+ * rounding of its atomic histograms. Errors as tfi_integrate; cells ==
+ * NULL is TFI_ERR_ARG.
+ */
+int tfi_integrate_cells(tfi_handle h, const void *f, const void *F, int64_t d,
+                        tfi_dtype dtype, void *out, void *cells, void *stream);
+int tfi_backward_cells(tfi_handle h, const void *f, const void *F,
+                       const void *cells, const void *gout, int64_t d,
+                       tfi_dtype dtype, void *dF, double *df, void *stream);
 int tfi_integrate_expsum_cells(tfi_handle h, int32_t nterm, const void *c,
                                const void *lambda, const void *F, int64_t d,
                                tfi_dtype dtype, void *out, void *cells,

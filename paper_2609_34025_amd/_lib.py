@@ -47,7 +47,7 @@ EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
             "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
             "tfi_integrate_multi", "tfi_cell_rows", "tfi_integrate_expsum_cells",
-            "tfi_backward_expsum_cells"]
+            "tfi_backward_expsum_cells", "tfi_integrate_cells", "tfi_backward_cells"]
 
 
 def load():
@@ -94,6 +94,10 @@ def load():
     lib.tfi_backward_expsum.argtypes = [vp, C.c_int32, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp,
                                         vp]
     lib.tfi_backward_expsum.restype = C.c_int
+    lib.tfi_integrate_cells.argtypes = [vp, vp, vp, i64, C.c_int, vp, vp, vp]
+    lib.tfi_integrate_cells.restype = C.c_int
+    lib.tfi_backward_cells.argtypes = [vp, vp, vp, vp, vp, i64, C.c_int, vp, vp, vp]
+    lib.tfi_backward_cells.restype = C.c_int
     lib.tfi_cell_rows.argtypes = [vp]
     lib.tfi_cell_rows.restype = i64
     lib.tfi_integrate_expsum_cells.argtypes = [vp, C.c_int32, vp, vp, vp, i64, C.c_int, vp, vp,

@@ -1506,13 +1506,15 @@ void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStr
 
 template <typename T>
 void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
-                     hipStream_t s1, hipStream_t s2) {
-    if (path_direct<T>(h, d)) {
+                     hipStream_t s1, hipStream_t s2, T* cells = nullptr) {
+    // cells: caller's buffer for the cell sums of F (kept for a backward with
+    // df), which whole-path mode would not form
+    if (!cells && path_direct<T>(h, d)) {
         enqueue_path<T>(h, f, F, d, out, s0);
         return;
     }
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = (T*)h->val[ti].p;
+    T* val = cells ? cells : (T*)h->val[ti].p;
     T* g = (T*)h->g[ti].p;
     const bool use1 = fft_work<T>(h), use2 = h->nlgrp > 0;
     fork_sides(h, s0, s1, s2, use1, use2);
@@ -1598,7 +1600,8 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
 // F once (df only).
 template <typename T>
 void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
-                      double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
+                      double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2,
+                      const T* cells = nullptr) {
     if (!df && path_direct<T>(h, d)) {
         if (dF) enqueue_path<T>(h, f, gout, d, dF, s0);
         return;
@@ -1615,19 +1618,21 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     if (dF) enq_leaf<T>(h, f, gout, d, dF, s2);
     if (df) enq_df_leaf<T>(h, d, F, gout, df, s2);
     (void)hipEventRecord(h->ev_c, s2);
-    if (df) launch_scatter<T>(h, F, val, d, s1);
+    // the cell sums of F: kept from the forward, or formed here
+    const T* valF = cells ? cells : val;
+    if (df && !cells) launch_scatter<T>(h, F, val, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
     if (dF) enq_spectra<T>(h, f, s1);
     launch_scatter<T>(h, gout, valg, d, s0);
     (void)hipEventRecord(h->ev_a, s0);
     (void)hipStreamWaitEvent(s1, h->ev_a, 0);
     if (dF) enq_fft<T>(h, d, valg, g, s1);
-    if (df) enq_df_tables<T>(h, d, val, valg, df, s1);
+    if (df) enq_df_tables<T>(h, d, valF, valg, df, s1);
     (void)hipEventRecord(h->ev_b, s1);
     if (dF) enq_direct<T>(h, f, d, valg, g, s0);
     if (df) {
         (void)hipStreamWaitEvent(s0, h->ev_d, 0);
-        enq_df_direct<T>(h, d, val, valg, df, s0);
+        enq_df_direct<T>(h, d, valF, valg, df, s0);
     }
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
@@ -1718,8 +1723,9 @@ int run_dag(tfi_plan* h, const GraphKey& key, hipStream_t caller, Enq enq) {
 }
 
 template <typename T>
-int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st) {
-    int rc = prepare_forward<T>(h, d);
+int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st,
+                T* cells = nullptr) {
+    int rc = prepare_forward<T>(h, d, cells != nullptr);
     if (rc) return rc;
     GraphKey key;
     key.kind = 1;
@@ -1728,8 +1734,9 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     key.p[0] = f;
     key.p[1] = F;
     key.p[2] = out;
+    key.p[3] = cells;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
-        enqueue_forward<T>(h, f, F, d, out, a, b, c);
+        enqueue_forward<T>(h, f, F, d, out, a, b, c, cells);
     });
 }
 
@@ -1755,7 +1762,7 @@ int run_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, int32_
 
 template <typename T>
 int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
-                 double* df, hipStream_t st) {
+                 double* df, hipStream_t st, const T* cells = nullptr) {
     int rc = prepare_backward<T>(h, d, df != nullptr);
     if (rc) return rc;
     GraphKey key;
@@ -1767,8 +1774,9 @@ int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, 
     key.p[2] = gout;
     key.p[3] = dF;
     key.p[4] = df;
+    key.p[5] = cells;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
-        enqueue_backward<T>(h, f, F, gout, d, dF, df, a, b, c);
+        enqueue_backward<T>(h, f, F, gout, d, dF, df, a, b, c, cells);
     });
 }
 
@@ -2154,21 +2162,41 @@ int64_t tfi_num_vertices(tfi_handle h) { return h ? h->plan.N : -1; }
 
 int64_t tfi_kernel_length(tfi_handle h) { return h ? h->plan.kernel_len : -1; }
 
-int tfi_integrate(tfi_handle h, const void* f, const void* F, int64_t d, tfi_dtype dtype,
-                  void* out, void* stream) {
+namespace {
+int integrate_impl(const char* fn, tfi_handle h, const void* f, const void* F, int64_t d,
+                   tfi_dtype dtype, void* out, void* cells, void* stream) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
-    if (!f || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate: null pointer");
-    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_integrate: need 1 <= d <= 2^20");
-    if (F == out) return fail(TFI_ERR_ARG, "tfi_integrate: out must not alias F");
+    const std::string fs(fn);
+    if (!f || !F || !out) return fail(TFI_ERR_ARG, fs + ": null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, fs + ": need 1 <= d <= 2^20");
+    if (F == out) return fail(TFI_ERR_ARG, fs + ": out must not alias F");
+    if (cells && (cells == F || cells == out))
+        return fail(TFI_ERR_ARG, fs + ": cells must not alias F or out");
     hipStream_t st = (hipStream_t)stream;
     if (dtype == TFI_F32)
-        return run_forward<float>(h, (const float*)f, (const float*)F, (int32_t)d, (float*)out, st);
+        return run_forward<float>(h, (const float*)f, (const float*)F, (int32_t)d, (float*)out, st,
+                                  (float*)cells);
     if (dtype == TFI_F64)
         return run_forward<double>(h, (const double*)f, (const double*)F, (int32_t)d,
-                                   (double*)out, st);
-    return fail(TFI_ERR_DTYPE, "tfi_integrate: unknown dtype");
+                                   (double*)out, st, (double*)cells);
+    return fail(TFI_ERR_DTYPE, fs + ": unknown dtype");
+}
+}  // namespace
+
+int tfi_integrate(tfi_handle h, const void* f, const void* F, int64_t d, tfi_dtype dtype,
+                  void* out, void* stream) {
+    return integrate_impl("tfi_integrate", h, f, F, d, dtype, out, nullptr, stream);
+}
+
+int tfi_integrate_cells(tfi_handle h, const void* f, const void* F, int64_t d, tfi_dtype dtype,
+                        void* out, void* cells, void* stream) {
+    if (!cells) {
+        g_err.clear();
+        return fail(TFI_ERR_ARG, "tfi_integrate_cells: null pointer");
+    }
+    return integrate_impl("tfi_integrate_cells", h, f, F, d, dtype, out, cells, stream);
 }
 
 int tfi_integrate_multi(tfi_handle h, int32_t nk, const void* const* f, const void* F,
@@ -2198,25 +2226,43 @@ int tfi_integrate_multi(tfi_handle h, int32_t nk, const void* const* f, const vo
     return fail(TFI_ERR_DTYPE, "tfi_integrate_multi: unknown dtype");
 }
 
-int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, int64_t d,
-                 tfi_dtype dtype, void* dF, double* df, void* stream) {
+namespace {
+int backward_impl(const char* fn, tfi_handle h, const void* f, const void* F, const void* cells,
+                  const void* gout, int64_t d, tfi_dtype dtype, void* dF, double* df,
+                  void* stream) {
     g_err.clear();
     int rc = check_handle(h, true);
     if (rc) return rc;
-    if (!f || !F || !gout) return fail(TFI_ERR_ARG, "tfi_backward: null pointer");
-    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_backward: need 1 <= d <= 2^20");
-    if (dtype != TFI_F32 && dtype != TFI_F64)
-        return fail(TFI_ERR_DTYPE, "tfi_backward: unknown dtype");
-    if (dF && (dF == F || dF == gout))
-        return fail(TFI_ERR_ARG, "tfi_backward: dF must not alias F or gout");
+    const std::string fs(fn);
+    if (!f || !F || !gout) return fail(TFI_ERR_ARG, fs + ": null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, fs + ": need 1 <= d <= 2^20");
+    if (dtype != TFI_F32 && dtype != TFI_F64) return fail(TFI_ERR_DTYPE, fs + ": unknown dtype");
+    if (dF && (dF == F || dF == gout || dF == cells))
+        return fail(TFI_ERR_ARG, fs + ": dF must not alias F, cells or gout");
     if (!dF && !df) return TFI_OK;
     hipStream_t st = (hipStream_t)stream;
     // f(D) is symmetric: dF = f(D) gout
     if (dtype == TFI_F32)
         return run_backward<float>(h, (const float*)f, (const float*)F, (const float*)gout,
-                                   (int32_t)d, (float*)dF, df, st);
+                                   (int32_t)d, (float*)dF, df, st, (const float*)cells);
     return run_backward<double>(h, (const double*)f, (const double*)F, (const double*)gout,
-                                (int32_t)d, (double*)dF, df, st);
+                                (int32_t)d, (double*)dF, df, st, (const double*)cells);
+}
+}  // namespace
+
+int tfi_backward(tfi_handle h, const void* f, const void* F, const void* gout, int64_t d,
+                 tfi_dtype dtype, void* dF, double* df, void* stream) {
+    return backward_impl("tfi_backward", h, f, F, nullptr, gout, d, dtype, dF, df, stream);
+}
+
+int tfi_backward_cells(tfi_handle h, const void* f, const void* F, const void* cells,
+                       const void* gout, int64_t d, tfi_dtype dtype, void* dF, double* df,
+                       void* stream) {
+    if (!cells) {
+        g_err.clear();
+        return fail(TFI_ERR_ARG, "tfi_backward_cells: null pointer");
+    }
+    return backward_impl("tfi_backward_cells", h, f, F, cells, gout, d, dtype, dF, df, stream);
 }
 
 namespace {

@@ -220,20 +220,39 @@ class TreeIntegrator:
             raise ValueError("out must not alias F")
         return out
 
-    def integrate(self, f, F, out=None):
+    def integrate(self, f, F, out=None, keep_cells=False):
         """out = f(D) F for F of shape [N] or [N, d]. ``out``: optional
         preallocated result (a loop that reuses it replays one captured
-        graph; a new tensor per call may need a graph per address)."""
+        graph; a new tensor per call may need a graph per address). With
+        ``keep_cells`` returns ``(out, cells)``: the cell sums of F, which
+        ``backward(..., cells=cells)`` reads for df instead of forming them
+        again."""
         self._check(f, F)
         d = 1 if F.dim() == 1 else F.shape[1]
         out = self._out_like(F, out)
         if d == 0:
-            return out
+            return (out, None) if keep_cells else out
         lib = _lib.load()
-        _lib.check(lib.tfi_integrate(self._h, f.data_ptr(), F.data_ptr(), d,
-                                     _DTYPES[f.dtype], out.data_ptr(),
-                                     self._stream(self.device)))
-        return out
+        if not keep_cells:
+            _lib.check(lib.tfi_integrate(self._h, f.data_ptr(), F.data_ptr(), d,
+                                         _DTYPES[f.dtype], out.data_ptr(),
+                                         self._stream(self.device)))
+            return out
+        cells = self._new_cells(F, d)
+        _lib.check(lib.tfi_integrate_cells(self._h, f.data_ptr(), F.data_ptr(), d,
+                                           _DTYPES[f.dtype], out.data_ptr(), cells.data_ptr(),
+                                           self._stream(self.device)))
+        return out, cells
+
+    def _new_cells(self, F, d):
+        rows = _lib.load().tfi_cell_rows(self._h)
+        _lib.check(rows if rows < 0 else 0)
+        return torch.empty((rows, d), dtype=F.dtype, device=F.device)
+
+    def _check_cells(self, cells, F, d):
+        if (cells.dtype != F.dtype or cells.device != F.device or not cells.is_contiguous()
+                or tuple(cells.shape) != (_lib.load().tfi_cell_rows(self._h), d)):
+            raise ValueError("cells must be the tensor the forward kept for this F")
 
     def integrate_many(self, fs, F, out=None):
         """[f_i(D) F for f_i in fs] in one call (at most 4 kernel tables of
@@ -263,9 +282,10 @@ class TreeIntegrator:
                                            self._stream(self.device)))
         return outs
 
-    def backward(self, f, F, gout, need_dF=True, need_df=True):
+    def backward(self, f, F, gout, need_dF=True, need_df=True, cells=None):
         """Adjoint of ``integrate`` for L = sum(gout * out): returns
-        ``(dF, df)``; df is float64 of length ``kernel_length``."""
+        ``(dF, df)``; df is float64 of length ``kernel_length``. ``cells``:
+        the cell sums of F from ``integrate(..., keep_cells=True)``."""
         self._check(f, F, gout)
         if F.shape != gout.shape:
             raise ValueError("F and gout must have the same shape")
@@ -274,11 +294,15 @@ class TreeIntegrator:
         df = (torch.zeros(self.kernel_length, dtype=torch.float64, device=self.device)
               if need_df else None)
         lib = _lib.load()
-        _lib.check(lib.tfi_backward(self._h, f.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
-                                    _DTYPES[f.dtype],
-                                    dF.data_ptr() if dF is not None else None,
-                                    df.data_ptr() if df is not None else None,
-                                    self._stream(self.device)))
+        tail = (d, _DTYPES[f.dtype], dF.data_ptr() if dF is not None else None,
+                df.data_ptr() if df is not None else None, self._stream(self.device))
+        if cells is None:
+            _lib.check(lib.tfi_backward(self._h, f.data_ptr(), F.data_ptr(), gout.data_ptr(),
+                                        *tail))
+        else:
+            self._check_cells(cells, F, d)
+            _lib.check(lib.tfi_backward_cells(self._h, f.data_ptr(), F.data_ptr(),
+                                              cells.data_ptr(), gout.data_ptr(), *tail))
         return dF, df
 
     def _check_expsum(self, c, lam, F):
@@ -308,9 +332,7 @@ class TreeIntegrator:
                 self._h, int(c.numel()), c.data_ptr(), lam.data_ptr(), F.data_ptr(), d,
                 _DTYPES[F.dtype], out.data_ptr(), self._stream(self.device)))
             return out
-        rows = lib.tfi_cell_rows(self._h)
-        _lib.check(rows if rows < 0 else 0)
-        cells = torch.empty((rows, d), dtype=F.dtype, device=F.device)
+        cells = self._new_cells(F, d)
         _lib.check(lib.tfi_integrate_expsum_cells(
             self._h, int(c.numel()), c.data_ptr(), lam.data_ptr(), F.data_ptr(), d,
             _DTYPES[F.dtype], out.data_ptr(), cells.data_ptr(), self._stream(self.device)))
@@ -339,9 +361,7 @@ class TreeIntegrator:
                 self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), gout.data_ptr(), d,
                 *ptrs))
         else:
-            if (cells.dtype != F.dtype or cells.device != F.device or not cells.is_contiguous()
-                    or tuple(cells.shape) != (lib.tfi_cell_rows(self._h), d)):
-                raise ValueError("cells must be the tensor integrate_expsum kept for this F")
+            self._check_cells(cells, F, d)
             _lib.check(lib.tfi_backward_expsum_cells(
                 self._h, n, c.data_ptr(), lam.data_ptr(), F.data_ptr(), cells.data_ptr(),
                 gout.data_ptr(), d, *ptrs))
@@ -366,16 +386,22 @@ class TreeIntegrate(torch.autograd.Function):
     @staticmethod
     def forward(ctx, integrator, F, f):
         ctx.integrator = integrator
-        ctx.save_for_backward(F, f)
-        return integrator.integrate(f, F)
+        # df needs the cell sums of F: keep the forward's
+        if ctx.needs_input_grad[2]:
+            out, cells = integrator.integrate(f, F, keep_cells=True)
+        else:
+            out, cells = integrator.integrate(f, F), None
+        ctx.save_for_backward(F, f, cells)
+        return out
 
     @staticmethod
     def backward(ctx, gout):
-        F, f = ctx.saved_tensors
+        F, f, cells = ctx.saved_tensors
         need_dF, need_df = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         if not (need_dF or need_df):
             return None, None, None
-        dF, df = ctx.integrator.backward(f, F, gout.contiguous(), need_dF, need_df)
+        dF, df = ctx.integrator.backward(f, F, gout.contiguous(), need_dF, need_df,
+                                         cells=cells if need_df else None)
         if df is not None:
             full = torch.zeros_like(f)
             k = min(f.numel(), df.numel())

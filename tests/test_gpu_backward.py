@@ -167,3 +167,53 @@ def test_backward_fp32_channel_counts(kernel):
         for method in ("direct", "auto"):
             check_backward(p, w, lambda K: np.exp(-0.05 * np.arange(K)) + 0.1 / (1 + np.arange(K)),
                            F, G, torch.float32, table_method=method, direct_kernel=kernel)
+
+
+@pytest.mark.parametrize("case", ["rrt_fft_f64", "grid_direct_f32", "path_f32"])
+def test_kept_cells_table_path(case):
+    """tfi_integrate_cells / tfi_backward_cells: the forward that keeps the
+    cell sums gives the same output (bit for bit on general plans; a path,
+    which would take whole-path mode, goes through the general path and
+    matches the oracle), and the backward that reads them gives dF bit for
+    bit and df to the rounding of its atomic histograms, also with another
+    field run on the handle in between."""
+    rng = np.random.default_rng(61)
+    opts, dtype, d = {}, torch.float32, 8
+    if case == "rrt_fft_f64":
+        p, _ = S.random_recursive(3000, rng)
+        w = S.uniform_weights(p, 1, 6, rng)
+        opts, dtype, d = {"table_method": "fft"}, torch.float64, 3
+    elif case == "grid_direct_f32":
+        p, w = S.grid_mst(30, 9, rng)
+        opts, d = {"table_method": "direct"}, 16
+    else:
+        p, w = S.path(6000)
+    print(f"kept cells table path {case} N={len(p)} d={d}", flush=True)
+    t = TreeIntegrator(p, w, device=0, **opts)
+    K = t.kernel_length
+    k = np.arange(K)
+    tab = np.exp(-0.03 * k) * (1 + 0.3 * np.cos(0.2 * k))
+    f = torch.tensor(tab, dtype=dtype, device=DEV)
+    F = torch.tensor(rng.standard_normal((len(p), d)), dtype=dtype, device=DEV)
+    G = torch.tensor(rng.standard_normal((len(p), d)), dtype=dtype, device=DEV)
+    ref = t.integrate(f, F)
+    out, cells = t.integrate(f, F, keep_cells=True)
+    torch.cuda.synchronize()
+    rows = np.sort(rng.choice(len(p), 128, replace=False))
+    o = oracle.integrate(p, w, tab, F.double().cpu().numpy(), rows=rows)
+    tol = 1e-10 if dtype == torch.float64 else 1e-4
+    assert relerr(out.cpu().numpy()[rows], o) <= tol
+    if case != "path_f32":
+        assert torch.equal(out, ref)
+    t.integrate(f, torch.randn_like(F))  # the handle's own buffers now hold another field
+    for _ in range(2):  # eager, then graph replay
+        dF0, df0 = t.backward(f, F, G)
+        dF1, df1 = t.backward(f, F, G, cells=cells)
+        torch.cuda.synchronize()
+        assert torch.equal(dF0, dF1)
+        assert relerr(df1.cpu().numpy(), df0.cpu().numpy()) <= (1e-12 if dtype == torch.float64
+                                                                   else 1e-5)
+    h = oracle.pair_hist(p, w, G.double().cpu().numpy(), F.double().cpu().numpy(), K)
+    assert relerr(df1.cpu().numpy(), h) <= tol
+    with pytest.raises(ValueError):
+        t.backward(f, F, G, cells=cells[:-1])
