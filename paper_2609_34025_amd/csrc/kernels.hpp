@@ -90,6 +90,17 @@ __device__ __forceinline__ void fma4(vec4<T>& a, T s, vec4<T> b) {
 // is one tile, the whole row).
 constexpr int kSegBatch = 8;
 
+// Workgroups are dispatched to the 8 XCDs in turn, and each XCD has its own
+// L2. Logical block of this workgroup such that every XCD takes one
+// contiguous range of logical blocks, in order (a bijection on
+// [0, gridDim.x)): rows that neighbouring logical blocks share are then
+// fetched into one L2.
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t n = gridDim.x, b = blockIdx.x;
+    const int64_t q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 // Thread -> (row index, first channel) under column tiling; false when the
 // thread is past the end.
 template <int VEC>
@@ -108,7 +119,7 @@ __global__ void k_segsum(int64_t nseg, int32_t d, int32_t ct, const int64_t* __r
                          const int32_t* __restrict__ seg_len, const int64_t* __restrict__ seg_dst,
                          const int32_t* __restrict__ idx, const T* __restrict__ src,
                          T* __restrict__ val) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tid = xcd_block() * blockDim.x + threadIdx.x;
     int64_t s;
     int32_t c;
     if (!tile_coords<VEC>(tid, nseg, d, ct, s, c) || s >= nseg) return;

@@ -449,11 +449,23 @@ int upload_static(tfi_plan* h) {
                 next.push_back({r0, r0 + np, sg.dst});
             }
             // longest segments first so that a wavefront's lanes finish
-            // together (the order does not change any sum)
+            // together; the field-row level goes by blocks of 2^12 vertex
+            // ids first (the first row's vertex), so that the cells of all
+            // levels over one region of the forest (one tree of a batch)
+            // run together and share its rows in cache. The order does not
+            // change any sum.
             std::vector<int64_t> perm(src.size());
             for (size_t k = 0; k < perm.size(); ++k) perm[k] = (int64_t)k;
-            std::stable_sort(perm.begin(), perm.end(),
-                             [&](int64_t a, int64_t b) { return len[a] > len[b]; });
+            if (indexed) {
+                std::vector<int32_t> vblk(src.size());
+                for (size_t k = 0; k < src.size(); ++k) vblk[k] = p.inc_v[src[k]] >> 12;
+                std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) {
+                    return vblk[a] != vblk[b] ? vblk[a] < vblk[b] : len[a] > len[b];
+                });
+            } else {
+                std::stable_sort(perm.begin(), perm.end(),
+                                 [&](int64_t a, int64_t b) { return len[a] > len[b]; });
+            }
             std::vector<int64_t> s2(src.size()), d2(src.size());
             std::vector<int32_t> l2(src.size());
             int64_t rows = 0;
