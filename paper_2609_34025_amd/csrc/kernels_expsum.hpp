@@ -247,7 +247,10 @@ __device__ __forceinline__ int32_t lane_value<int32_t>(int32_t v, int src) {
 // WHOLE (gs = 64, i.e. d > 32): one cell subgroup, so the cell a step works
 // on is the same in every lane; its row, depth and weights are read from the
 // owning lane into scalar registers, and eight cell rows are loaded per step.
-template <typename T, int NJ, bool GRAD, bool WHOLE = false>
+// DF (with GRAD): the same launch also writes the dF table values of the
+// gout sums (the forward's second walk on b_l), bit-identical to a forward
+// launch over valg.
+template <typename T, int NJ, bool GRAD, bool WHOLE = false, bool DF = false>
 __global__ void __launch_bounds__(kExpThreads)
 k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
               const int32_t* __restrict__ ej, const int64_t* __restrict__ joff,
@@ -268,7 +271,7 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
     const T sgn = (GRAD && active && jsign[job] < 0) ? (T)-1 : (T)1;
     T cl[NJ];
 #pragma unroll
-    for (int l = 0; l < NJ; ++l) cl[l] = (!GRAD && l < nterm) ? c[l] : (T)0;
+    for (int l = 0; l < NJ; ++l) cl[l] = ((!GRAD || DF) && l < nterm) ? c[l] : (T)0;
     double m0[NJ], m1[NJ];
 #pragma unroll
     for (int l = 0; l < NJ; ++l) m0[l] = m1[l] = 0.0;
@@ -330,10 +333,17 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
 #pragma unroll
             for (int l = 0; l < NJ; ++l)
                 for (int o = gs; o < 64; o <<= 1) acc[q][l] += __shfl_xor(acc[q][l], o, 64);
-        if (!GRAD) {
+        if (GRAD && chok && sub == 0) {
+#pragma unroll
+            for (int l = 0; l < NJ; ++l) {
+                m0[l] += (double)(sgn * acc[2][l] * acc[0][l]);
+                m1[l] += (double)(sgn * (acc[3][l] * acc[0][l] + acc[2][l] * acc[1][l]));
+            }
+        }
+        if (!GRAD || DF) {
             T ca[NJ];
 #pragma unroll
-            for (int l = 0; l < NJ; ++l) ca[l] = cl[l] * acc[0][l];
+            for (int l = 0; l < NJ; ++l) ca[l] = cl[l] * acc[GRAD ? 2 : 0][l];
             for (int64_t k0 = cb; k0 < ce; k0 += 64) {
                 const int32_t nk = (int32_t)min((int64_t)64, ce - k0);
                 const int64_t mine = k0 + min(lane, nk - 1);
@@ -354,12 +364,6 @@ k_expsum_wave(int32_t nterm, int32_t d, int32_t gs, int32_t njobs,
                                                   : __shfl(wmine[l], src, 64));
                     if (chok && kk < nk) g[(int64_t)rowk * d + ch] = sum;
                 }
-            }
-        } else if (chok && sub == 0) {
-#pragma unroll
-            for (int l = 0; l < NJ; ++l) {
-                m0[l] += (double)(sgn * acc[2][l] * acc[0][l]);
-                m1[l] += (double)(sgn * (acc[3][l] * acc[0][l] + acc[2][l] * acc[1][l]));
             }
         }
     }

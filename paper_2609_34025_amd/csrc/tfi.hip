@@ -1843,7 +1843,7 @@ void enq_expsum_prep(tfi_plan* h, int32_t nterm, const T* c, const T* lam, hipSt
     h->end(st, ev, "expsum_prep", sizeof(T) * (double)(nterm + 1) * K);
 }
 
-template <typename T, bool GRAD>
+template <typename T, bool GRAD, bool DF = false>
 void launch_expsum_wave(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
                         const T* valg, T* g, double* mrow, int64_t& mbase, hipStream_t st) {
     const int64_t nj = h->nej1;
@@ -1858,16 +1858,16 @@ void launch_expsum_wave(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const
                            pw, (int32_t)h->plan.kernel_len, val, valg, g, mrow, mbase);
     };
     if (gs == 64) {  // one cell subgroup: the lane-uniform walk
-        if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD, true>);
-        else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD, true>);
-        else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD, true>);
-        else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD, true>);
-        else launch(tfi::k_expsum_wave<T, 16, GRAD, true>);
-    } else if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD>);
-    else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD>);
-    else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD>);
-    else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD>);
-    else launch(tfi::k_expsum_wave<T, 16, GRAD>);
+        if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD, true, DF>);
+        else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD, true, DF>);
+        else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD, true, DF>);
+        else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD, true, DF>);
+        else launch(tfi::k_expsum_wave<T, 16, GRAD, true, DF>);
+    } else if (nterm <= 1) launch(tfi::k_expsum_wave<T, 1, GRAD, false, DF>);
+    else if (nterm <= 2) launch(tfi::k_expsum_wave<T, 2, GRAD, false, DF>);
+    else if (nterm <= 4) launch(tfi::k_expsum_wave<T, 4, GRAD, false, DF>);
+    else if (nterm <= 8) launch(tfi::k_expsum_wave<T, 8, GRAD, false, DF>);
+    else launch(tfi::k_expsum_wave<T, 16, GRAD, false, DF>);
     mbase += blocks;
 }
 
@@ -1910,6 +1910,24 @@ void enq_expsum_jobs(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T*
     const double cells = (double)p.jc_r.size();
     h->end(st, ev, GRAD ? "expsum_grad" : "expsum",
            2.0 * sizeof(T) * d * cells + 12.0 * cells, (GRAD ? 10.0 : 4.0) * nterm * d * cells);
+}
+
+// Backward with both dF and the moments: the one-position jobs in one launch
+// that reads the F and gout cell sums once and writes the moment rows and
+// the dF tables; the multi-position jobs as in the separate passes.
+template <typename T>
+void enq_expsum_jobs_fused(tfi_plan* h, int32_t nterm, const T* c, int32_t d, const T* val,
+                           const T* valg, T* g, double* mrow, hipStream_t st) {
+    if (h->nej1 + h->nejm == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    int64_t mbase = 0, unused = 0;
+    launch_expsum_wave<T, true, true>(h, nterm, c, d, val, valg, g, mrow, mbase, st);
+    launch_expsum_multi<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, unused, st);
+    launch_expsum_multi<T, true>(h, nterm, c, d, val, valg, nullptr, mrow, mbase, st);
+    const double cells = (double)p.jc_r.size();
+    h->end(st, ev, "expsum_grad_df", 3.0 * sizeof(T) * d * cells + 12.0 * cells,
+           14.0 * nterm * d * cells);
 }
 
 // out = f(D) F for f(k) = sum_l c_l lam_l^k.
@@ -1968,9 +1986,10 @@ void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* la
     if (grad && !cells) launch_scatter<T>(h, F, val, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
     launch_scatter<T>(h, gout, valg, d, s0);
-    if (dF) enq_expsum_jobs<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, s0);
+    if (dF && !grad) enq_expsum_jobs<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, s0);
     (void)hipStreamWaitEvent(s0, h->ev_d, 0);
-    if (grad) enq_expsum_jobs<T, true>(h, nterm, c, d, valF, valg, nullptr, mrow, s0);
+    if (grad && dF) enq_expsum_jobs_fused<T>(h, nterm, c, d, valF, valg, g, mrow, s0);
+    else if (grad) enq_expsum_jobs<T, true>(h, nterm, c, d, valF, valg, nullptr, mrow, s0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     if (grad)
         hipLaunchKernelGGL(tfi::k_expsum_moments, dim3((unsigned)(2 * nterm)),

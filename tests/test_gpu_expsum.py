@@ -165,6 +165,34 @@ def test_expsum_kept_cells_bitwise(dtype, d):
         t.backward_expsum(ct, lt, F1, G, cells=cells[1:])
 
 
+@pytest.mark.parametrize("policy", ["adaptive", "diameter"])
+@pytest.mark.parametrize("d", [5, 40])
+def test_expsum_fused_backward_dF_bitwise(policy, d):
+    """With moments and dF together, one launch per one-position job writes
+    both; its dF equals the forward integration of gout bit for bit, as does
+    the dF-only backward."""
+    rng = np.random.default_rng(5 + d)
+    p, w, _ = S.forest([S.grid_mst(15, 16, rng), S.spider(4, 25), S.path(60)])
+    print(f"expsum fused backward policy={policy} N={len(p)} d={d}", flush=True)
+    t = TreeIntegrator(p, w, device=0, policy=policy)
+    ct = torch.tensor(rng.standard_normal(8), dtype=torch.float32, device=DEV)
+    lt = torch.tensor(np.exp(-rng.uniform(0.01, 0.5, 8)), dtype=torch.float32, device=DEV)
+    F = torch.tensor(rng.standard_normal((len(p), d)), dtype=torch.float32, device=DEV)
+    G = torch.tensor(rng.standard_normal((len(p), d)), dtype=torch.float32, device=DEV)
+    ref = t.integrate_expsum(ct, lt, G)
+    for _ in range(2):  # eager, then graph replay
+        dF, s0, s1 = t.backward_expsum(ct, lt, F, G)
+        dF2, _, _ = t.backward_expsum(ct, lt, F, G, need_moments=False)
+        torch.cuda.synchronize()
+        assert torch.equal(dF, ref) and torch.equal(dF2, ref)
+    K = t.kernel_length
+    c32, l32 = ct.double().cpu().numpy(), lt.double().cpu().numpy()
+    h = oracle.pair_hist(p, w, G.double().cpu().numpy(), F.double().cpu().numpy(), K)
+    k = np.arange(K)
+    r0 = np.array([(l32[l] ** k * h).sum() for l in range(8)])
+    assert relerr(s0.cpu().numpy(), r0) <= 1e-4
+
+
 def test_expsum_autograd_matches_fd_and_table_path():
     rng = np.random.default_rng(55)
     p, w, _ = S.forest([S.grid_mst(s, 16, rng) for s in (6, 8, 7)])
