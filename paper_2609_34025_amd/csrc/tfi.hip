@@ -296,7 +296,7 @@ struct tfi_plan {
         int rc = dalloc(&p, src.size() * sizeof(V));
         if (rc) return rc;
         mallocs.push_back(p);
-        mbytes.push_back(std::max<size_t>(src.size() * sizeof(V), 16));
+        mbytes.push_back(src.empty() ? 16 : src.size() * sizeof(V));  // as dalloc counted
         if (!src.empty())
             TFI_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
         *dst = (V*)p;
@@ -1147,7 +1147,7 @@ template <typename T>
 int prepare_forward(tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    int rc;
+    int rc = 0;
     const bool rows = general || !path_direct<T>(h, d);
     if (rows &&
         (rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
