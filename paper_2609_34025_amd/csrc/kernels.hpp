@@ -590,17 +590,22 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
 #pragma unroll
         for (int i = 0; i < kPerK; ++i) fv[u][i] = fu[di[i]];
     }
-    // channel chunks: this workgroup takes every gridDim.y-th one
+    // channel chunks: this workgroup takes every gridDim.y-th one. The field
+    // rows of a chunk (all loads in flight at once) are requested before the
+    // products of the previous chunk, so they arrive while it computes.
+    const int32_t cstep = gridDim.y * kDirCh;
+    T v[kPerF];
+    auto load_rows = [&](int32_t c) {
+        const int32_t ccs = min(lc, min(kDirCh, d - c) - 1);
+#pragma unroll
+        for (int i = 0; i < kPerF; ++i) v[i] = F[(int64_t)vt[i] * d + c + ccs];
+    };
+    if (blockIdx.y * kDirCh < d) load_rows(blockIdx.y * kDirCh);
     bool stage_k = true;
-    for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += gridDim.y * kDirCh) {
+    for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += cstep) {
         const int32_t nch = min(kDirCh, d - c0);
         const int32_t nq = (nch + 3) >> 2;
         const int32_t qpp = kLeafThreads / nq;
-        // field rows of the group's vertices, all loads in flight at once
-        const int32_t ccs = min(lc, nch - 1);
-        T v[kPerF];
-#pragma unroll
-        for (int i = 0; i < kPerF; ++i) v[i] = F[(int64_t)vt[i] * d + c0 + ccs];
         if (stage_k) {
 #pragma unroll
             for (int u = 0; u < NK; ++u)
@@ -618,6 +623,7 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
             if (k < nv) sF[k * kDirCh + lc] = (lc < nch) ? v[i] : (T)0;
         }
         __syncthreads();
+        if (c0 + cstep < d) load_rows(c0 + cstep);
         const int32_t cq0 = threadIdx.x / nq;
         const int32_t nquads = q1 - q0;
         for (int32_t tq = cq0; cq0 < qpp && tq < NK * nquads; tq += qpp) {
