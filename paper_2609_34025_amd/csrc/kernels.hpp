@@ -1231,31 +1231,35 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
     for (int r = 0; r < kDfLeafRows; ++r)
 #pragma unroll
         for (int c = 0; c < 4; ++c) m[r][c] = 0;
+    // gout and field rows of the group's vertices, a chunk of kDirCh channels
+    // at a time with all loads in flight at once; the next chunk's rows are
+    // requested before the current chunk's products
+    constexpr int kPer = kLeafSlots / (kLeafThreads / 16);
+    const int32_t lc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
+    T vg[kPer], vf[kPer];
+    auto load_rows = [&](int32_t c) {
+        const int32_t ccs = min(lc, min(kDirCh, d - c) - 1);
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int64_t o = (int64_t)svtx[min(k0 + 16 * i, nv - 1)] * d + c + ccs;
+            vg[i] = gout[o];
+            vf[i] = F[o];
+        }
+    };
+    load_rows(0);
     for (int32_t c0 = 0; c0 < d; c0 += kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
         __syncthreads();
-        {
-            // gout and field rows of the group's vertices, all loads at once
-            constexpr int kPer = kLeafSlots / (kLeafThreads / 16);
-            const int32_t cc = threadIdx.x & 15, k0 = threadIdx.x >> 4;
-            const int32_t ccs = min(cc, nch - 1);
-            T vg[kPer], vf[kPer];
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int64_t o = (int64_t)svtx[min(k0 + 16 * i, nv - 1)] * d + c0 + ccs;
-                vg[i] = gout[o];
-                vf[i] = F[o];
-            }
-#pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int32_t k = k0 + 16 * i;
-                if (k < nv && cc < nch) {
-                    sG[k * (kDirCh + 1) + cc] = vg[i];
-                    sF[k * (kDirCh + 1) + cc] = vf[i];
-                }
+        for (int i = 0; i < kPer; ++i) {
+            const int32_t k = k0 + 16 * i;
+            if (k < nv && lc < nch) {
+                sG[k * (kDirCh + 1) + lc] = vg[i];
+                sF[k * (kDirCh + 1) + lc] = vf[i];
             }
         }
         __syncthreads();
+        if (c0 + kDirCh < d) load_rows(c0 + kDirCh);
 #pragma unroll
         for (int r = 0; r < kDfLeafRows; ++r) {
             if (rq[r] < 0) continue;
