@@ -101,6 +101,9 @@ def main():
                     help="keep the default direct/FFT rule instead of tuning it")
     ap.add_argument("--fft-cost", type=float, default=None,
                     help="use this direct/FFT cost constant instead of tuning it")
+    ap.add_argument("--batched-fft-cost", type=float, default=None,
+                    help="direct/FFT cost constant of the batched table path instead of "
+                         "tuning it (default: --fft-cost when given)")
     ap.add_argument("--leaf-max", type=int, default=None,
                     help="dense leaf-tile size of the plain-forward plan instead of tuning it")
     ap.add_argument("--no-batched", action="store_true",
@@ -351,9 +354,10 @@ def batched_fwd_bwd(args, plain_value):
     build_s = time.perf_counter() - t0
     K = tfi.kernel_length
     rng = np.random.default_rng(33)
-    if args.fft_cost is not None:
-        tfi.set_fft_cost(args.fft_cost)
-        cost = args.fft_cost
+    pinned = args.batched_fft_cost if args.batched_fft_cost is not None else args.fft_cost
+    if pinned is not None:
+        tfi.set_fft_cost(pinned)
+        cost = pinned
     elif not args.no_autotune:
         ftune = torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=dev)
         cost = tfi.autotune(ftune, d, backward=True)
