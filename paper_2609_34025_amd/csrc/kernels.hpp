@@ -1190,7 +1190,11 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
           const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
           const T* __restrict__ gout, const int32_t* __restrict__ lbin,
           double* __restrict__ df) {
-    __shared__ T sG[kLeafSlots * (kDirCh + 1)], sF[kLeafSlots * (kDirCh + 1)];
+    // rows of kDirCh channels at a 16-byte aligned stride, read 4 channels
+    // at a time
+    constexpr int kStride = kDirCh + 4;
+    __shared__ __attribute__((aligned(16))) T sG[kLeafSlots * kStride];
+    __shared__ __attribute__((aligned(16))) T sF[kLeafSlots * kStride];
     __shared__ int32_t svtx[kLeafSlots], srow0[kLeafQuads + 1];
     __shared__ T lh[df_hist_bins<T>()];
     const int32_t K = lbin[blockIdx.x];  // bins this group's pairs can reach
@@ -1253,9 +1257,9 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
             const int32_t k = k0 + 16 * i;
-            if (k < nv && lc < nch) {
-                sG[k * (kDirCh + 1) + lc] = vg[i];
-                sF[k * (kDirCh + 1) + lc] = vf[i];
+            if (k < nv) {  // channels past the chunk's end are zero
+                sG[k * kStride + lc] = lc < nch ? vg[i] : (T)0;
+                sF[k * kStride + lc] = lc < nch ? vf[i] : (T)0;
             }
         }
         __syncthreads();
@@ -1266,12 +1270,19 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
             const int32_t q = q0 + rq[r];
             const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
             const int32_t rows = min(4, tb + n - first);
-            const T* fj = sF + (tb - vb + rj[r]) * (kDirCh + 1);
-            for (int32_t cc = 0; cc < nch; ++cc) {
-                const T fv = fj[cc];
+            const T* fj = sF + (tb - vb + rj[r]) * kStride;
+            for (int32_t cc = 0; cc < nch; cc += 4) {
+                const vec4<T> fv = ld4(fj + cc);
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (c < rows) m[r][c] += sG[(first - vb + c) * (kDirCh + 1) + cc] * fv;
+                for (int c = 0; c < 4; ++c) {
+                    if (c >= rows) continue;
+                    const vec4<T> gv = ld4(sG + (first - vb + c) * kStride + cc);
+                    // the channels in order, as one product each
+                    m[r][c] += gv.x * fv.x;
+                    m[r][c] += gv.y * fv.y;
+                    m[r][c] += gv.z * fv.z;
+                    m[r][c] += gv.w * fv.w;
+                }
             }
         }
     }
