@@ -141,6 +141,33 @@ def test_large_tables_through_global_memory(dtype):
     check(p, w, lambda K: 1.0 / (1.0 + np.arange(K)) ** 2, F, dtype, table_method="fft")
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_leaf_tiles_short_and_long_distances(dtype):
+    # Leaf tiles gather the kernel table through their own distances: light
+    # weights (short leaf distances, many repeated table entries) and heavy
+    # weights (leaf distances in the thousands, beyond any short table
+    # prefix). One and two kernels per launch, several channel counts.
+    rng = np.random.default_rng(21)
+    for lo, hi in ((1, 5), (300, 600)):
+        p, _ = S.random_recursive(1500, rng)
+        w = S.uniform_weights(p, lo, hi, rng)
+        t = TreeIntegrator(p, w, device=0, leaf_max=64)
+        K = t.kernel_length
+        if lo > 1:
+            assert K > 8192
+        fns = [lambda K: np.exp(-3.0 * np.arange(K) / K),
+               lambda K: 1.0 / (1.0 + np.arange(K) / 50.0)]
+        for d in (1, 16, 40):
+            F = rng.standard_normal((len(p), d))
+            Ft = torch.tensor(F, dtype=dtype, device=DEV)
+            fs = [torch.tensor(fn(K), dtype=dtype, device=DEV) for fn in fns]
+            ys = [t.integrate(fs[0], Ft)] + t.integrate_many(fs, Ft)
+            refs = [oracle.integrate(p, w, fn(K), F) for fn in fns]
+            for y, ref in zip(ys, [refs[0]] + refs):
+                e = relerr(y.cpu().numpy(), ref)
+                assert e <= TOL[dtype], (lo, hi, d, e)
+
+
 @pytest.mark.parametrize("kernel", ["vector", "mfma"])
 def test_channel_counts_and_vector_field(kernel):
     rng = np.random.default_rng(15)
