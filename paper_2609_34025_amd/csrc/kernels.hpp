@@ -634,7 +634,12 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
             const int32_t chq = threadIdx.x % nq;
             const int32_t q = q0 + qq;
             const int32_t first = lq[4 * q], tb = lq[4 * q + 1], n = lq[4 * q + 2];
-            const int32_t krow = lq[4 * q + 3];
+            // f(D) of a tile is symmetric: entry (row r, column j) is read
+            // at column-major position j n + r, so the quads of one tile
+            // read neighbouring LDS words instead of words n apart (which
+            // share a bank); the values and their order are unchanged
+            const int32_t r0 = first - tb;
+            const int32_t kt = lq[4 * q + 3] - r0 * n + r0;
             vec4<T> acc[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[c] = {0, 0, 0, 0};
@@ -643,7 +648,7 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
                 const vec4<T> v = ld4(sF + (tb - vb + j) * kDirCh + 4 * chq);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    if (c < rows) fma4(acc[c], sku[krow + c * n + j], v);
+                    if (c < rows) fma4(acc[c], sku[kt + j * n + c], v);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
