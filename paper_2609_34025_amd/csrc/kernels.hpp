@@ -492,15 +492,26 @@ __global__ void k_gather(int64_t N, int32_t d, int32_t ct, const int64_t* __rest
             else s[u].x = ok[u][v * d + c];
         }
     }
-    // calls taken kGatherBatch at a time: indices first, then table rows
+    // calls taken kGatherBatch at a time: indices first, then table rows;
+    // the next batch's indices are requested with this batch's rows
+    int32_t an[kGatherBatch], bn[kGatherBatch];
+    auto load_idx = [&](int64_t kk) {
+#pragma unroll
+        for (int w = 0; w < kGatherBatch; ++w) {
+            const int64_t k = max(min(kk + w, k1 - 1), (int64_t)0);
+            an[w] = ga[k];
+            bn[w] = gb[k];
+        }
+    };
+    if (k0 < k1) load_idx(k0);
     for (int64_t kk = k0; kk < k1; kk += kGatherBatch) {
         int32_t a[kGatherBatch], b[kGatherBatch];
 #pragma unroll
         for (int w = 0; w < kGatherBatch; ++w) {
-            const int64_t k = min(kk + w, k1 - 1);
-            a[w] = ga[k];
-            b[w] = gb[k];
+            a[w] = an[w];
+            b[w] = bn[w];
         }
+        if (kk + kGatherBatch < k1) load_idx(kk + kGatherBatch);
 #pragma unroll
         for (int u = 0; u < NK; ++u) {
             if (VEC == 4) {
