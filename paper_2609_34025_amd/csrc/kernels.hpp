@@ -330,11 +330,20 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;  // A row / k of this lane
     const int32_t ntiles = (oe - os + 15) >> 4;
-    // this wave's row tiles t = wave + 4 q (at most 4): row data per lane
+    // this wave's row tiles (at most 4 of the block's at most 16). Passes of
+    // one chunk take a contiguous run t = wave tpw + q (q < tpw): the jobs of
+    // its tiles, and with them the source range the wave walks, are
+    // neighbours. Passes of several chunks, with more MFMA work per source
+    // step, take t = wave + 4 q, which measured faster there.
+    const int32_t tpw = (ntiles + 3) >> 2;
+    auto row_tile = [&](int q) -> int32_t {
+        if (NCH > 1) return wave + 4 * q;
+        return q < tpw ? wave * tpw + q : ntiles;
+    };
     int32_t ri[4], xi[4], jb[4], je[4], tjb[4], tje[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int32_t t = wave + 4 * q;
+        const int32_t t = row_tile(q);
         const int32_t i = os + 16 * t + lr;
         const bool ok = t < ntiles && i < oe;
         const int32_t is = ok ? i : os;  // clamped: loads stay in range
@@ -432,7 +441,7 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
         // D[4 (l/16) + r][l % 16] of every row tile and chunk
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int32_t t = wave + 4 * q;
+            const int32_t t = row_tile(q);
             if (t >= ntiles) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -1071,8 +1080,8 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
 // step s, for gbar of row lr of the row tile (A[lr][lk]) and val of source
 // lr of the source tile (B[lk][lr]), so both come as contiguous runs of a
 // row. Result register r of lane (lr, lk) is the pair (row 4 lk + r,
-// source lr). A wave owns the row tiles t = wave + 4 q (q < 4) of the
-// block's output cells, keeps their gbar runs in registers, and streams
+// source lr). A wave owns a contiguous run of up to 4 row tiles of the
+// block's output cells (neighbouring jobs, so a short source range), keeps their gbar runs in registers, and streams
 // source tiles of 16 cells straight from memory (sources of a job are
 // consecutive value rows). Blocks, padding and job ranges are those of
 // k_direct. dbin[b] bounds the distance bins of block b's pairs (one past
@@ -1127,9 +1136,10 @@ k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
     // the tile's source range
     int32_t arow[4], rr[4][4], rx[4][4], qb[4], qe[4], tjb[4], tje[4];
     float coef[4][4];
+    const int32_t tpw = (ntiles + 3) >> 2;  // a contiguous run of row tiles per wave
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int32_t t = wave + 4 * q;
+        const int32_t t = q < tpw ? wave * tpw + q : ntiles;
         const int32_t tb = os + 16 * t;
         const bool tok = t < ntiles;
         arow[q] = (tok && tb + lr < oe) ? dl_row[tb + lr] : -1;
