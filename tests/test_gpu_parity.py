@@ -217,6 +217,37 @@ def test_rrt100k_sampled_rows_both_kernels():
         assert e <= 1e-4
 
 
+def test_rrt100k_timed_configuration():
+    # The plain forward exactly as the benchmark times it: leaf tiles of up
+    # to 64 vertices, the direct/FFT rule autotuned, both kernels in one
+    # call on preallocated outputs, replayed several times (one graph);
+    # sampled rows of every replay against the oracle.
+    W = S.workload("rrt100k")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    rows = np.random.default_rng(98).choice(len(p), 384, replace=False)
+    t = TreeIntegrator(p, w, device=0, leaf_max=64)
+    K = t.kernel_length
+    fs = [torch.tensor(fn(K), dtype=torch.float32, device=DEV) for _, fn in W["kernels"]]
+    t.autotune(fs[0], F.shape[1])
+    Ft = torch.tensor(F, device=DEV)
+    outs = [torch.full_like(Ft, float("nan")) for _ in fs]
+    refs = [oracle.integrate(p, w, fn(K), F.astype(np.float64), rows=rows)
+            for _, fn in W["kernels"]]
+    first = None
+    for rep in range(4):
+        t.integrate_many(fs, Ft, out=outs)
+        torch.cuda.synchronize()
+        ys = [o.cpu().numpy() for o in outs]
+        for (name, _), y, ref in zip(W["kernels"], ys, refs):
+            e = relerr(y[rows], ref)
+            print(f"rrt100k timed {name} replay {rep}: rel err {e:.2e}", flush=True)
+            assert e <= 1e-4
+        if first is None:
+            first = ys
+        else:
+            assert all(np.array_equal(a, b) for a, b in zip(first, ys))
+
+
 def test_exp_kernel_full_against_tree_recursion():
     # All rows at N = 1e5 against the independent exp-kernel recursion.
     W = S.workload("rrt100k")
