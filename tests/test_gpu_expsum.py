@@ -256,3 +256,47 @@ def test_expsum_graph_replay_and_errors():
     with pytest.raises(ValueError):
         t.integrate_expsum(torch.zeros(17, device=DEV, dtype=torch.float64),
                            torch.ones(17, device=DEV, dtype=torch.float64), F)
+
+
+def test_grid512_timed_configuration():
+    # The batched training step at full size, as the benchmark times it:
+    # 512 grid-MST trees, d = 64, f = 8 exponentials, loss sum(W * out);
+    # the sweep evaluator and the table path (rule autotuned on forward +
+    # adjoint passes). out and dF on sampled rows against the oracle, da
+    # against the oracle's exp-kernel recursion (da_k = <W, K_k F>).
+    W = S.workload("grid512")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    n, d = F.shape
+    rng = np.random.default_rng(34)
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    t.autotune(torch.tensor(W["kernels"][0][1](K), dtype=torch.float32, device=DEV), d,
+               backward=True)
+    Wt = torch.tensor(rng.standard_normal((n, d)), dtype=torch.float32, device=DEV)
+    a = torch.tensor(W["a"], dtype=torch.float32, device=DEV, requires_grad=True)
+    b = torch.tensor(W["b"], dtype=torch.float32, device=DEV, requires_grad=True)
+    Ft = torch.tensor(F, device=DEV, requires_grad=True)
+    rows = np.random.default_rng(35).choice(n, 256, replace=False)
+    A = a.detach().double().cpu().numpy()
+    B = b.detach().double().cpu().numpy()
+    ftab = table(A, np.exp(-B), K)
+    Fd = F.astype(np.float64)
+    Wd = Wt.double().cpu().numpy()
+    ref_out = oracle.integrate(p, w, ftab, Fd, rows=rows)
+    ref_dF = oracle.integrate(p, w, ftab, Wd, rows=rows)
+    da_ref = np.array([np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k])], Fd))
+                       for k in range(len(A))])
+    paths = {"sweep": lambda: ExpSumIntegrate.apply(t, Ft, a, b),
+             "table": lambda: TreeIntegrate.apply(t, Ft, expsum_table(a, b, K))}
+    for name, fwd in paths.items():
+        for rep in range(2):
+            a.grad = b.grad = Ft.grad = None
+            out = fwd()
+            (Wt * out).sum().backward()
+            torch.cuda.synchronize()
+            errs = {"out": relerr(out.detach().cpu().numpy()[rows], ref_out),
+                    "dF": relerr(Ft.grad.cpu().numpy()[rows], ref_dF),
+                    "da": relerr(a.grad.cpu().numpy(), da_ref)}
+            print(f"grid512 {name} step {rep}: {errs}", flush=True)
+            assert max(errs.values()) <= 1e-4, (name, rep, errs)
+            assert torch.isfinite(b.grad).all()
