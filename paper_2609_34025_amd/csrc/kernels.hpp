@@ -125,6 +125,9 @@ __global__ void k_segsum(int64_t nseg, int32_t d, int32_t ct, const int64_t* __r
     if (!tile_coords<VEC>(tid, nseg, d, ct, s, c) || s >= nseg) return;
     const int64_t b = seg_src[s];
     const int32_t n = seg_len[s];
+    // rows per batch: the tail levels (consecutive partial rows, no index
+    // loads) take twice as many, so a run of 32 needs two rounds
+    constexpr int kSegBatch = INDEXED ? tfi::kSegBatch : 2 * tfi::kSegBatch;
     vec4<T> acc = {0, 0, 0, 0};
     for (int32_t i0 = 0; i0 < n; i0 += kSegBatch) {
         int64_t rows[kSegBatch];
