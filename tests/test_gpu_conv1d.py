@@ -180,3 +180,49 @@ def test_one_column_tables(dtype, d):
     e = relerr(y.cpu().numpy()[rows], ref)
     print(f"  err {e:.2e}", flush=True)
     assert e <= TOL[dtype], e
+
+
+@pytest.mark.parametrize("side", [384, 512])
+def test_serpentine_full_size_c4160(side):
+    """The masked-attention payload at full width (C = 4160, r = dh = 64) on
+    the 384 x 384 and 512 x 512 serpentine paths, as the benchmark runs it:
+    P = 2^19 lattice points, 16 channel pairs per slot, the 2^9-point
+    high-bit passes and the 2^10-point low-bit pass in two channel halves.
+    32 sampled rows x 64 sampled channels against the FP64 oracle (every
+    channel is integrated on its own, so a channel subset of F gives the
+    same rows of those channels), and a graph replay that reproduces the
+    profiled run bit for bit."""
+    W = S.workload("attn", tree="serpentine", side=side)
+    p, w = W["parent"], W["weight"]
+    n, C = len(p), W["d"]
+    print(f"conv1d serpentine side={side} N={n} C={C} fp32", flush=True)
+    t = TreeIntegrator(p, w, device=0)
+    K = t.kernel_length
+    tab = W["kernels"][0][1](K)
+    f = torch.tensor(tab, dtype=torch.float32, device=DEV)
+    phi = torch.from_numpy(W["phi"]).to(DEV)
+    v = torch.from_numpy(W["v"]).to(DEV)
+    F = torch.cat([(phi[:, :, None] * v[:, None, :]).reshape(n, -1), phi], 1).contiguous()
+    del phi, v
+    t.profile(True)
+    y = t.integrate(f, F)
+    torch.cuda.synchronize()
+    st = t.profile_report()
+    t.profile(False)
+    assert "fft_conv1d_path" in st, st
+    again = t.integrate(f, F)
+    torch.cuda.synchronize()
+    assert torch.equal(again, y)
+    del again
+    rng = np.random.default_rng(side)
+    rows = np.sort(rng.choice(n, 32, replace=False))
+    chans = np.sort(rng.choice(C, 64, replace=False))
+    Fs = F[:, torch.from_numpy(chans).to(DEV)].double().cpu().numpy()
+    got = y[torch.from_numpy(rows).to(DEV)][:, torch.from_numpy(chans).to(DEV)]
+    got = got.double().cpu().numpy()
+    ref = oracle.integrate(p, w, tab, Fs, rows=rows)
+    e = relerr(got, ref)
+    print(f"  err {e:.2e}", flush=True)
+    assert e <= TOL[torch.float32], e
+    del t, F, y
+    torch.cuda.empty_cache()

@@ -262,8 +262,9 @@ def test_grid512_timed_configuration():
     # The batched training step at full size, as the benchmark times it:
     # 512 grid-MST trees, d = 64, f = 8 exponentials, loss sum(W * out);
     # the sweep evaluator and the table path (rule autotuned on forward +
-    # adjoint passes). out and dF on sampled rows against the oracle, da
-    # against the oracle's exp-kernel recursion (da_k = <W, K_k F>).
+    # adjoint passes). out and dF on sampled rows against the oracle; da and
+    # db against the oracle's exp-kernel recursion (da_k = <W, K_k F>, db_k
+    # by a central difference of it in b_k).
     W = S.workload("grid512")
     p, w, F = W["parent"], W["weight"], W["F"]
     n, d = F.shape
@@ -286,6 +287,15 @@ def test_grid512_timed_configuration():
     ref_dF = oracle.integrate(p, w, ftab, Wd, rows=rows)
     da_ref = np.array([np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k])], Fd))
                        for k in range(len(A))])
+    # db_k = -a_k sum_{v,w} D e^{-b_k D} <W_v, F_w> = a_k dL_k/db_k with
+    # L_k(b) = <W, K_b F> and K_b the single exponential e^{-b D}: a central
+    # difference of the oracle's exp-kernel recursion in b (step 1e-5; its
+    # truncation error is orders below the 1e-4 bar)
+    hb = 1e-5
+    db_ref = np.array([A[k] * (np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] - hb)], Fd))
+                               - np.sum(Wd * oracle.expdp(p, w, [1.0], [np.exp(-B[k] + hb)],
+                                                          Fd))) / (2 * hb)
+                       for k in range(len(A))])
     paths = {"sweep": lambda: ExpSumIntegrate.apply(t, Ft, a, b),
              "table": lambda: TreeIntegrate.apply(t, Ft, expsum_table(a, b, K))}
     for name, fwd in paths.items():
@@ -296,7 +306,7 @@ def test_grid512_timed_configuration():
             torch.cuda.synchronize()
             errs = {"out": relerr(out.detach().cpu().numpy()[rows], ref_out),
                     "dF": relerr(Ft.grad.cpu().numpy()[rows], ref_dF),
-                    "da": relerr(a.grad.cpu().numpy(), da_ref)}
+                    "da": relerr(a.grad.cpu().numpy(), da_ref),
+                    "db": relerr(b.grad.cpu().numpy(), db_ref)}
             print(f"grid512 {name} step {rep}: {errs}", flush=True)
             assert max(errs.values()) <= 1e-4, (name, rep, errs)
-            assert torch.isfinite(b.grad).all()
