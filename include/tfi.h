@@ -180,6 +180,28 @@ int tfi_integrate_multi(tfi_handle h, int32_t nk, const void *const *f, const vo
                         int64_t d, tfi_dtype dtype, void *const *out, void *stream);
 
 /*
+ * tfi_integrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result from the same kernels, with every scratch buffer of the
+ * pass (cell sums, table rows, kernel spectra, FFT slots) carved out of one
+ * fixed device array of TFI_NOALLOC_SCRATCH_BYTES bytes per GPU, held from
+ * the library's first use of that GPU until the process ends. The call
+ * allocates nothing and captures no graph: the kernels are launched
+ * directly on `stream` and the handle's two side streams, joined back into
+ * `stream` before the pass ends. Stage profiling is off during the call.
+ *  - Arguments, layouts and ownership as tfi_integrate; the caller still
+ *    provides f, F and out.
+ *  - TFI_ERR_BUDGET (before anything is launched) when the plan needs more
+ *    scratch at this d and dtype than the array holds.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents. Calls whose work overlaps on one GPU (two streams, or
+ *    two handles used at the same time) race on it: order them.
+ */
+#define TFI_NOALLOC_SCRATCH_BYTES (128u << 20)
+int tfi_integrate_noalloc(tfi_handle h, const void *f, const void *F, int64_t d,
+                          tfi_dtype dtype, void *out, void *stream);
+
+/*
  * Adjoint of tfi_integrate for the loss L = sum(gout * out):
  *   dF = K gout (K is symmetric), device dtype[N x d], may be NULL;
  *   df[k] = sum_{v, w : dist(v, w) = k} <gout[v, :], F[w, :]>, the

@@ -47,7 +47,12 @@ EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate
             "tfi_profile_report", "tfi_autotune", "tfi_set_fft_cost", "tfi_destroy",
             "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
             "tfi_integrate_multi", "tfi_cell_rows", "tfi_integrate_expsum_cells",
-            "tfi_backward_expsum_cells", "tfi_integrate_cells", "tfi_backward_cells"]
+            "tfi_backward_expsum_cells", "tfi_integrate_cells", "tfi_backward_cells",
+            "tfi_integrate_noalloc"]
+
+# bytes of the fixed device scratch array of tfi_integrate_noalloc
+# (TFI_NOALLOC_SCRATCH_BYTES in include/tfi.h)
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 def load():
@@ -68,6 +73,8 @@ def load():
     lib.tfi_kernel_length.restype = i64
     lib.tfi_integrate.argtypes = [vp, vp, vp, i64, C.c_int, vp, vp]
     lib.tfi_integrate.restype = C.c_int
+    lib.tfi_integrate_noalloc.argtypes = [vp, vp, vp, i64, C.c_int, vp, vp]
+    lib.tfi_integrate_noalloc.restype = C.c_int
     lib.tfi_backward.argtypes = [vp, vp, vp, vp, i64, C.c_int, vp, vp, vp]
     lib.tfi_backward.restype = C.c_int
     lib.tfi_plan_stats.argtypes = [vp, C.c_char_p, C.c_size_t]

@@ -1140,34 +1140,67 @@ bool path_direct(const tfi_plan* h, int32_t d) {
     return true;
 }
 
-// Scratch of a forward (or of dF); `general` asks for the value and table
-// rows even where whole-path mode would not use them; nk kernels in one
-// call take nk table arrays and nk spectrum arenas.
+// Scratch of one forward pass (or of dF): cell sums, table rows, kernel
+// spectra and the FFT work buffer of the buckets beyond LDS.
+struct Work {
+    void* val = nullptr;   // [val_rows x d] cell sums
+    void* g = nullptr;     // [nk x (NA + NB) x d] table rows
+    void* spec = nullptr;  // [nk x spec_elems] complex spectra
+    void* fft = nullptr;   // FFT slots of the global buckets
+    size_t fft_bytes = 0;
+};
+
+// Bytes of each part of Work; `general` asks for the value and table rows
+// even where whole-path mode would not use them; nk kernels in one call
+// take nk table arrays and nk spectrum arenas. The FFT workspace holds
+// chunks of at most 2 GiB, or one job's slots when a job alone is larger.
+struct WorkSizes {
+    size_t val = 0, g = 0, spec = 0, fft = 0;
+};
+
 template <typename T>
-int prepare_forward(tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
+WorkSizes forward_sizes(const tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    int rc = 0;
+    WorkSizes z;
     const bool rows = general || !path_direct<T>(h, d);
-    if (rows &&
-        (rc = h->ensure(h->val[ti], (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T))))
-        return rc;
-    if (rows && (rc = h->ensure(h->g[ti], (size_t)nk * std::max<int64_t>(p.NA + p.NB, 1) * d *
-                                              sizeof(T))))
-        return rc;
-    if ((rc = h->ensure(h->spec[ti], (size_t)nk * std::max<int64_t>(h->spec_elems, 1) *
-                                         sizeof(tfi::cpx<T>))))
-        return rc;
-    // workspace for buckets beyond LDS: chunks of at most 2 GiB, or one
-    // job's slots when a job alone is larger
-    size_t want = 0;
+    if (rows) {
+        z.val = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+        z.g = (size_t)nk * std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T);
+    }
+    z.spec = (size_t)nk * std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>);
     for (int bi : h->global_b[ti]) {
         const Bucket& b = h->buckets[bi];
         const size_t one_job = (size_t)fft_job_bytes<T>(b, d);
         const size_t all = one_job * (size_t)b.njobs();
-        want = std::max(want, std::max(one_job, std::min(all, (size_t)2 << 30)));
+        z.fft = std::max(z.fft, std::max(one_job, std::min(all, (size_t)2 << 30)));
     }
-    if (want && (rc = h->ensure(h->fftbuf[ti], want))) return rc;
+    return z;
+}
+
+// The handle's own scratch buffers as a Work (after prepare_forward).
+template <typename T>
+Work handle_work(const tfi_plan* h) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    Work w;
+    w.val = h->val[ti].p;
+    w.g = h->g[ti].p;
+    w.spec = h->spec[ti].p;
+    w.fft = h->fftbuf[ti].p;
+    w.fft_bytes = h->fftbuf[ti].bytes;
+    return w;
+}
+
+// Grow the handle's scratch to the sizes of a forward.
+template <typename T>
+int prepare_forward(tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const WorkSizes z = forward_sizes<T>(h, d, general, nk);
+    int rc = 0;
+    if (z.val && (rc = h->ensure(h->val[ti], z.val))) return rc;
+    if (z.g && (rc = h->ensure(h->g[ti], z.g))) return rc;
+    if ((rc = h->ensure(h->spec[ti], z.spec))) return rc;
+    if (z.fft && (rc = h->ensure(h->fftbuf[ti], z.fft))) return rc;
     return TFI_OK;
 }
 
@@ -1241,10 +1274,10 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nu
 }
 
 template <typename T>
-void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st,
+void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const Work& w,
              const tfi::cpx<T>* spec = nullptr) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    if (!spec) spec = (const tfi::cpx<T>*)h->spec[ti].p;
+    if (!spec) spec = (const tfi::cpx<T>*)w.spec;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const int32_t npairs = (d + 1) / 2;
     const double sz = (double)sizeof(T);
@@ -1260,8 +1293,7 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st,
     for (int bi : h->global_b[ti]) {
         const Bucket& b = h->buckets[bi];
         hipEvent_t ev = h->begin(st);
-        launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)h->fftbuf[ti].p,
-                             h->fftbuf[ti].bytes, st);
+        launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)w.fft, w.fft_bytes, st);
         h->end(st, ev, conv1d_tc<T>(b, d) ? "fft_conv1d" : "fft_global",
                2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
     }
@@ -1500,9 +1532,9 @@ inline void fork_sides(tfi_plan* h, hipStream_t s0, hipStream_t s1, hipStream_t 
 // field rows straight into the output rows.
 template <typename T>
 void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st,
-                  tfi::cpx<T>* spec = nullptr) {
+                  const Work& w, tfi::cpx<T>* spec = nullptr) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    if (!spec) spec = (tfi::cpx<T>*)h->spec[ti].p;
+    if (!spec) spec = (tfi::cpx<T>*)w.spec;
     enq_spectra<T>(h, f, st, spec);
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const double sz = (double)sizeof(T);
@@ -1510,7 +1542,7 @@ void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStr
         const Bucket& b = h->buckets[bi];
         hipEvent_t ev = h->begin(st);
         launch_conv1d<T>(h, conv1d_tc<T>(b, d), b, b.d_vmap, d, F, out, spec, tw,
-                         (tfi::cpx<T>*)h->fftbuf[ti].p, h->fftbuf[ti].bytes, st);
+                         (tfi::cpx<T>*)w.fft, w.fft_bytes, st);
         h->end(st, ev, "fft_conv1d_path",
                2.0 * sz * d * (double)b.cells + 4.0 * b.cells + 2.0 * sz * b.P());
     }
@@ -1518,28 +1550,27 @@ void enqueue_path(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStr
 
 template <typename T>
 void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t s0,
-                     hipStream_t s1, hipStream_t s2, T* cells = nullptr) {
+                     hipStream_t s1, hipStream_t s2, const Work& w, T* cells = nullptr) {
     // cells: caller's buffer for the cell sums of F (kept for a backward with
     // df), which whole-path mode would not form
     if (!cells && path_direct<T>(h, d)) {
-        enqueue_path<T>(h, f, F, d, out, s0);
+        enqueue_path<T>(h, f, F, d, out, s0, w);
         return;
     }
-    const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = cells ? cells : (T*)h->val[ti].p;
-    T* g = (T*)h->g[ti].p;
+    T* val = cells ? cells : (T*)w.val;
+    T* g = (T*)w.g;
     const bool use1 = fft_work<T>(h), use2 = h->nlgrp > 0;
     fork_sides(h, s0, s1, s2, use1, use2);
     if (use2) {
         enq_leaf<T>(h, f, F, d, out, s2);      // side2: leaf rows into out
         (void)hipEventRecord(h->ev_c, s2);
     }
-    if (use1) enq_spectra<T>(h, f, s1);         // side1: kernel spectra
+    if (use1) enq_spectra<T>(h, f, s1, (tfi::cpx<T>*)w.spec);  // side1: kernel spectra
     launch_scatter<T>(h, F, val, d, s0);        // main: cell sums
     if (use1) {
         (void)hipEventRecord(h->ev_a, s0);
         (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-        enq_fft<T>(h, d, val, g, s1);           // side1: FFT tables
+        enq_fft<T>(h, d, val, g, s1, w);        // side1: FFT tables
         (void)hipEventRecord(h->ev_b, s1);
     }
     enq_direct<T>(h, f, d, val, g, s0);         // main: direct tables
@@ -1554,16 +1585,17 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
 template <typename T>
 void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, int32_t d,
                            T* const* out, hipStream_t s0, hipStream_t s1, hipStream_t s2) {
-    const int ti = sizeof(T) == 8 ? 1 : 0;
     const tfi::Plan& p = h->plan;
-    tfi::cpx<T>* spec0 = (tfi::cpx<T>*)h->spec[ti].p;
+    const Work w = handle_work<T>(h);
+    tfi::cpx<T>* spec0 = (tfi::cpx<T>*)w.spec;
     const int64_t sstride = std::max<int64_t>(h->spec_elems, 1);
     if (path_direct<T>(h, d)) {
-        for (int i = 0; i < nk; ++i) enqueue_path<T>(h, f[i], F, d, out[i], s0, spec0 + i * sstride);
+        for (int i = 0; i < nk; ++i)
+            enqueue_path<T>(h, f[i], F, d, out[i], s0, w, spec0 + i * sstride);
         return;
     }
-    T* val = (T*)h->val[ti].p;
-    T* g0 = (T*)h->g[ti].p;
+    T* val = (T*)w.val;
+    T* g0 = (T*)w.g;
     const int64_t gstride = std::max<int64_t>(p.NA + p.NB, 1) * (int64_t)d;
     const bool use1 = fft_work<T>(h), use2 = h->nlgrp > 0;
     fork_sides(h, s0, s1, s2, use1, use2);
@@ -1588,7 +1620,7 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
         (void)hipEventRecord(h->ev_a, s0);
         (void)hipStreamWaitEvent(s1, h->ev_a, 0);
         for (int i = 0; i < nk; ++i)
-            enq_fft<T>(h, d, val, g0 + i * gstride, s1, spec0 + i * sstride);
+            enq_fft<T>(h, d, val, g0 + i * gstride, s1, w, spec0 + i * sstride);
         (void)hipEventRecord(h->ev_b, s1);
     }
     // kernels in pairs: one launch per pair for the direct tables and the
@@ -1614,15 +1646,16 @@ template <typename T>
 void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
                       double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2,
                       const T* cells = nullptr) {
+    const Work w = handle_work<T>(h);
     if (!df && path_direct<T>(h, d)) {
-        if (dF) enqueue_path<T>(h, f, gout, d, dF, s0);
+        if (dF) enqueue_path<T>(h, f, gout, d, dF, s0, w);
         return;
     }
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
-    T* val = (T*)h->val[ti].p;
+    T* val = (T*)w.val;
     T* valg = (T*)h->valg[ti].p;
-    T* g = (T*)h->g[ti].p;
+    T* g = (T*)w.g;
     if (df)
         hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
                            s0, df, (int64_t)p.kernel_len);
@@ -1634,11 +1667,11 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     const T* valF = cells ? cells : val;
     if (df && !cells) launch_scatter<T>(h, F, val, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
-    if (dF) enq_spectra<T>(h, f, s1);
+    if (dF) enq_spectra<T>(h, f, s1, (tfi::cpx<T>*)w.spec);
     launch_scatter<T>(h, gout, valg, d, s0);
     (void)hipEventRecord(h->ev_a, s0);
     (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-    if (dF) enq_fft<T>(h, d, valg, g, s1);
+    if (dF) enq_fft<T>(h, d, valg, g, s1, w);
     if (df) enq_df_tables<T>(h, d, valF, valg, df, s1);
     (void)hipEventRecord(h->ev_b, s1);
     if (dF) enq_direct<T>(h, f, d, valg, g, s0);
@@ -1747,9 +1780,75 @@ int run_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStrea
     key.p[1] = F;
     key.p[2] = out;
     key.p[3] = cells;
+    const Work w = handle_work<T>(h);
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
-        enqueue_forward<T>(h, f, F, d, out, a, b, c, cells);
+        enqueue_forward<T>(h, f, F, d, out, a, b, c, w, cells);
     });
+}
+
+// ---- forward without allocation -------------------------------------------
+// Scratch of tfi_integrate_noalloc: one fixed array in the code object, so
+// each GPU the library runs on holds its own copy until the process ends.
+// Host code never uses the array's name as an address: its device address
+// is taken once per device with hipGetSymbolAddress and kept here.
+constexpr size_t kNoAllocBytes = (size_t)TFI_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on `device`, which must be current.
+int scratch_address(int device, unsigned char** out) {
+    static std::mutex mu;
+    static std::map<int, unsigned char*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *out = it->second;
+        return TFI_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(TFI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e));
+    addr[device] = (unsigned char*)ptr;
+    *out = (unsigned char*)ptr;
+    return TFI_OK;
+}
+
+// The forward of run_forward, launched directly on (caller, s1, s2) with its
+// Work carved out of the device's scratch array: no allocation, no graph.
+template <typename T>
+int run_forward_noalloc(tfi_plan* h, const T* f, const T* F, int32_t d, T* out,
+                        hipStream_t st) {
+    const WorkSizes z = forward_sizes<T>(h, d);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    const size_t o_val = take(z.val), o_g = take(z.g), o_spec = take(z.spec),
+                 o_fft = take(z.fft);
+    if (off > kNoAllocBytes)
+        return fail(TFI_ERR_BUDGET,
+                    "tfi_integrate_noalloc: this plan needs " + std::to_string(off) +
+                        " bytes of scratch at d = " + std::to_string(d) + ", more than the " +
+                        std::to_string(kNoAllocBytes) + " bytes of the fixed scratch array");
+    unsigned char* base = nullptr;
+    int rc = scratch_address(h->device, &base);
+    if (rc) return rc;
+    Work w;
+    w.val = z.val ? base + o_val : nullptr;
+    w.g = z.g ? base + o_g : nullptr;
+    w.spec = base + o_spec;
+    w.fft = z.fft ? base + o_fft : nullptr;
+    w.fft_bytes = z.fft;
+    // stage events would be created on demand: none while this runs
+    const bool keep_prof = h->prof;
+    h->prof = false;
+    enqueue_forward<T>(h, f, F, d, out, st, h->s1, h->s2, w);
+    h->prof = keep_prof;
+    TFI_HIP(hipGetLastError());
+    return TFI_OK;
 }
 
 template <typename T>
@@ -2459,6 +2558,25 @@ int64_t tfi_plan_export(tfi_handle h, const char* name, void* buf, size_t cap) {
     else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
     if (buf && cap >= bytes && bytes) std::memcpy(buf, src, bytes);
     return (int64_t)bytes;
+}
+
+int tfi_integrate_noalloc(tfi_handle h, const void* f, const void* F, int64_t d,
+                          tfi_dtype dtype, void* out, void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f || !F || !out) return fail(TFI_ERR_ARG, "tfi_integrate_noalloc: null pointer");
+    if (d < 1 || d > (1 << 20))
+        return fail(TFI_ERR_ARG, "tfi_integrate_noalloc: need 1 <= d <= 2^20");
+    if (F == out) return fail(TFI_ERR_ARG, "tfi_integrate_noalloc: out must not alias F");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return run_forward_noalloc<float>(h, (const float*)f, (const float*)F, (int32_t)d,
+                                          (float*)out, st);
+    if (dtype == TFI_F64)
+        return run_forward_noalloc<double>(h, (const double*)f, (const double*)F, (int32_t)d,
+                                           (double*)out, st);
+    return fail(TFI_ERR_DTYPE, "tfi_integrate_noalloc: unknown dtype");
 }
 
 int tfi_set_fft_cost(tfi_handle h, float cost) {

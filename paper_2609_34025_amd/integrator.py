@@ -244,6 +244,24 @@ class TreeIntegrator:
                                            self._stream(self.device)))
         return out, cells
 
+    def integrate_noalloc(self, f, F, out):
+        """``integrate`` into the preallocated ``out`` without any device
+        allocation by the library: its scratch comes from one fixed array per
+        GPU (``_lib.NOALLOC_SCRATCH_BYTES``), shared by every such call on
+        that GPU, and the kernels are launched directly (no graph). Raises
+        ``TFIError`` (TFI_ERR_BUDGET) when the plan needs more scratch at
+        this width than the array holds. Calls that overlap on one GPU race
+        on the shared array."""
+        self._check(f, F)
+        d = 1 if F.dim() == 1 else F.shape[1]
+        out = self._out_like(F, out)
+        if d == 0:
+            return out
+        _lib.check(_lib.load().tfi_integrate_noalloc(self._h, f.data_ptr(), F.data_ptr(), d,
+                                                     _DTYPES[f.dtype], out.data_ptr(),
+                                                     self._stream(self.device)))
+        return out
+
     def _new_cells(self, F, d):
         rows = _lib.load().tfi_cell_rows(self._h)
         _lib.check(rows if rows < 0 else 0)
