@@ -35,7 +35,8 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "kernels_conv1d.hpp", "tfi.hip", "plan.cpp", "plan.hpp"]
+LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "kernels_conv1d.hpp", "kernels_cells.hpp",
+               "tfi.hip", "plan.cpp", "plan.hpp"]
 
 
 def measured_traffic(workload, stage, plan="-"):

@@ -331,7 +331,9 @@ int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
  * work of one training step). The timed fields hold ones. The fastest
  * value stays in effect and is written to *best_cost (host). The kernel
  * length does not change. Uses temporary device memory for three [N x d]
- * fields and one FP64 kernel-length histogram.
+ * fields and one FP64 kernel-length histogram. With the chosen constant it
+ * then times both strategies of the cell sums (tfi_set_scatter) and keeps
+ * the faster.
  * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE (method forced at
  * build), TFI_ERR_HIP, TFI_ERR_BUDGET, TFI_ERR_OOM.
  */
@@ -340,6 +342,20 @@ int tfi_autotune(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
 
 /* Apply a cost constant (e.g. a cached tuning result) without timing. */
 int tfi_set_fft_cost(tfi_handle h, float cost);
+
+/*
+ * Strategy of the cell sums b_alpha[r] (equation "stad-E") and A_r[x]
+ * (Section 2.2) that every pass forms first:
+ *   0  pieces: the incidences in segments of at most 16, runs of 64
+ *      segments per workgroup summed through LDS, cells cut between
+ *      workgroups added by a second launch (two launches);
+ *   1  levels: every segment of at most 32 incidences its own thread group,
+ *      longer runs summed level by level (one launch per level);
+ *  -1  by width (the default): pieces up to 16 channels, levels above.
+ * Both give the same cell sums up to the order of the additions.
+ * Errors: TFI_ERR_ARG (method outside [-1, 1]), TFI_ERR_STATE, TFI_ERR_HIP.
+ */
+int tfi_set_scatter(tfi_handle h, int32_t method);
 
 /*
  * Measure the channel-aware cost model of TFI_POLICY_CHANNEL on this

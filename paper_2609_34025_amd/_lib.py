@@ -48,7 +48,7 @@ EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate
             "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
             "tfi_integrate_multi", "tfi_cell_rows", "tfi_integrate_expsum_cells",
             "tfi_backward_expsum_cells", "tfi_integrate_cells", "tfi_backward_cells",
-            "tfi_integrate_noalloc"]
+            "tfi_integrate_noalloc", "tfi_set_scatter"]
 
 # bytes of the fixed device scratch array of tfi_integrate_noalloc
 # (TFI_NOALLOC_SCRATCH_BYTES in include/tfi.h)
@@ -91,6 +91,8 @@ def load():
     lib.tfi_autotune.restype = C.c_int
     lib.tfi_set_fft_cost.argtypes = [vp, C.c_float]
     lib.tfi_set_fft_cost.restype = C.c_int
+    lib.tfi_set_scatter.argtypes = [vp, C.c_int32]
+    lib.tfi_set_scatter.restype = C.c_int
     lib.tfi_calibrate.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
     lib.tfi_calibrate.restype = C.c_int
     lib.tfi_integrate_multi.argtypes = [vp, C.c_int32, C.POINTER(vp), vp, i64, C.c_int,

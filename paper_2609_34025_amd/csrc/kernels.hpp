@@ -1,8 +1,9 @@
 // kernels.hpp -- gfx950 device kernels of the tree field integrator.
 //
 // Stages of one integration (all calls of all recursion levels at once):
-//   scatter  : b-cell sums b_alpha[r] (equation "stad-E") and A-cell sums
-//              A_r[x] (Section 2.2) from the field rows of their vertices;
+//   cells    : b-cell sums b_alpha[r] (equation "stad-E") and A-cell sums
+//              A_r[x] (Section 2.2) from the field rows of their vertices
+//              (kernels_cells.hpp);
 //   tables   : every table job evaluates, at its own occupied cells,
 //                G(i) = sum_j f(r_i + r_j + |x_i - x_j|) * val(j)
 //              by direct sums (small or sparse tables) or by one FFT
@@ -74,22 +75,7 @@ __device__ __forceinline__ void fma4(vec4<T>& a, T s, vec4<T> b) {
     a.x += s * b.x; a.y += s * b.y; a.z += s * b.z; a.w += s * b.w;
 }
 
-// ------------------------------------------------------------- scatter ----
-// Segmented sums with bounded fan-in. Segment s adds len[s] <= 32 source
-// rows starting at src_beg[s] and writes row dst[s] of the value matrix.
-// Level 0 reads field rows through the incidence vertex list; later levels
-// add partial rows of longer segments (split on the host into pieces), so
-// no thread walks an unbounded run and the summation order is fixed.
-// VEC = 4: one thread per (segment, 4 channels), requires d % 4 == 0.
-// Rows are taken kSegBatch at a time: all their row indices are loaded,
-// then all their values, so a batch waits for memory twice however long it
-// is (the additions keep the order of the rows).
-// Wide rows go in column tiles of ct VEC-groups, the tile index slowest:
-// every segment's slice of one tile is summed before the next tile starts,
-// so the rows read again by later segments are still in cache (ct = d/VEC
-// is one tile, the whole row).
-constexpr int kSegBatch = 8;
-
+// ------------------------------------------------------------ row tiles ----
 // Workgroups are dispatched to the 8 XCDs in turn, and each XCD has its own
 // L2. Logical block of this workgroup such that every XCD takes one
 // contiguous range of logical blocks, in order (a bijection on
@@ -113,6 +99,22 @@ __device__ __forceinline__ bool tile_coords(int64_t tid, int64_t nrows, int32_t 
     c = (int32_t)((tile * ct + (rem - r * ct)) * VEC);
     return c < d;
 }
+
+// -------------------------------------------------------- level scatter ----
+// Segmented sums with bounded fan-in. Segment s adds len[s] <= 32 source
+// rows starting at src_beg[s] and writes row dst[s] of the value matrix.
+// Level 0 reads field rows through the incidence vertex list; later levels
+// add partial rows of longer segments (split on the host into pieces), so
+// no thread walks an unbounded run and the summation order is fixed.
+// VEC = 4: one thread per (segment, 4 channels), requires d % 4 == 0.
+// Rows are taken kSegBatch at a time: all their row indices are loaded,
+// then all their values, so a batch waits for memory twice however long it
+// is (the additions keep the order of the rows).
+// Wide rows go in column tiles of ct VEC-groups, the tile index slowest:
+// every segment's slice of one tile is summed before the next tile starts,
+// so the rows read again by later segments are still in cache (ct = d/VEC
+// is one tile, the whole row).
+constexpr int kSegBatch = 8;
 
 template <typename T, bool INDEXED, int VEC>
 __global__ void k_segsum(int64_t nseg, int32_t d, int32_t ct, const int64_t* __restrict__ seg_src,

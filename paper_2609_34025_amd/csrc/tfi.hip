@@ -32,6 +32,7 @@
 #include "kernels.hpp"
 #include "kernels_expsum.hpp"
 #include "kernels_conv1d.hpp"
+#include "kernels_cells.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -98,6 +99,34 @@ struct DeviceBuf {
     size_t bytes = 0;
 };
 
+// Direct-sum tables of a set of jobs: padded cell list (jobs by size),
+// per-quad job ranges, blocks of output cells.
+struct DirectSet {
+    int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
+    int32_t *d_qjb = nullptr, *d_qje = nullptr, *d_dblk = nullptr;
+    int32_t* d_dbin = nullptr;  // per direct block: bound of its pair distances
+    int32_t dbin_max = 0;
+    int64_t ndirect = 0, ndblk = 0;
+    double direct_pairs = 0;  // sum over the jobs of cells^2 (unpadded)
+};
+
+// Pieces of the cell-sum kernel (k_cells): their segments, b-cell and
+// A-cell entries, and the cells cut between pieces (see kernels_cells.hpp).
+struct CellPlan {
+    int64_t npieces = 0, nsegs = 0, nbent = 0, naent = 0;
+    int64_t part_rows = 0;  // partial rows of the cells cut between pieces
+    int64_t ncomb = 0;      // cells cut between pieces
+    int64_t max_rows = 0;   // LDS rows (segments + b-cells) of the largest piece
+    int32_t *d_piece = nullptr, *d_seg = nullptr, *d_bent = nullptr, *d_aent = nullptr,
+            *d_comb = nullptr;
+};
+
+// The cell-sum kernel's arrays on the host (uploaded into CellPlan).
+struct CellHost {
+    CellPlan stats;
+    std::vector<int32_t> piece, seg, bent, aent, comb;
+};
+
 struct GraphKey {
     int kind = 0, dtype = 0, n = 0;
     int64_t d = 0;
@@ -125,15 +154,12 @@ struct tfi_plan {
     // plan arrays on the device
     int32_t *d_inc_v = nullptr, *d_jc_r = nullptr, *d_jc_x = nullptr, *d_jc_val = nullptr;
     int64_t* d_v_off = nullptr;
-    // direct tables: padded cell list (jobs by size), per-quad job ranges,
-    // blocks of output cells
-    int32_t *d_dl_r = nullptr, *d_dl_x = nullptr, *d_dl_row = nullptr;
-    int32_t *d_qjb = nullptr, *d_qje = nullptr, *d_dblk = nullptr;
-    int32_t* d_dbin = nullptr;  // per direct block: bound of its pair distances
-    int32_t dbin_max = 0;
-    int64_t ndirect = 0, ndblk = 0;
-    double direct_pairs = 0;  // sum over direct jobs of cells^2 (unpadded)
-    // scatter: levels of bounded segment sums
+    // direct tables: every direct job (adjoint, cell-keeping forward), and
+    // those of the calls the fused call kernel leaves to the table kernels
+    DirectSet dall;
+    // cell sums: pieces of the cell-sum kernel
+    CellPlan cells;
+    // cell sums: levels of bounded segment sums (the other strategy)
     struct SegLevel {
         bool indexed = false;
         int64_t n = 0;
@@ -143,7 +169,10 @@ struct tfi_plan {
         int64_t rows_read = 0;
     };
     std::vector<SegLevel> seg_levels;
-    int64_t val_rows = 0;  // A-cells, b-cells, then partial rows
+    // cell-sum strategy: -1 by width (pieces up to 16 channels), 0 pieces,
+    // 1 levels (tfi_autotune times both)
+    int scatter_pick = -1;
+    int64_t val_rows = 0;  // A-cells, b-cells, then partial rows of the levels
     // gather rows, leaf flags and leaf groups
     int32_t *d_ga = nullptr, *d_gb = nullptr, *d_lgrp = nullptr, *d_lq = nullptr;
     int8_t* d_vleaf = nullptr;
@@ -166,7 +195,7 @@ struct tfi_plan {
     int64_t lds_max = 65536;        // bytes of LDS a workgroup may use
 
     // per-dtype scratch (grow-only)
-    DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2];
+    DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2], part[2], partg[2];
     // exponential sums: per-term power table and f table, sweep scratch,
     // leaf pair histogram (FP64)
     DeviceBuf expw[2], exps[2], hleaf;
@@ -257,7 +286,8 @@ struct tfi_plan {
         for (void* p : allocs) (void)hipFree(p);
         for (void* p : mallocs) (void)hipFree(p);
         for (int t = 0; t < 2; ++t)
-            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t],
+            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t], &part[t],
+                                 &partg[t],
                                  &expw[t], &exps[t]})
                 if (b->p) (void)hipFree(b->p);
         if (hleaf.p) (void)hipFree(hleaf.p);
@@ -319,9 +349,7 @@ struct tfi_plan {
             path_mode[t] = false;
             for (int k = 0; k < 3; ++k) tiers[t][k] = Tier();
         }
-        ndirect = ndblk = 0;
-        direct_pairs = 0;
-        dbin_max = 0;
+        dall = DirectSet();
         spec_elems = 0;
         return TFI_OK;
     }
@@ -390,6 +418,128 @@ int lds_optin_once(int device, int lds) {
     if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
     if (rc1) return rc1;
     done.insert(device);
+    return TFI_OK;
+}
+
+// ---- cell-sum pieces ----------------------------------------------------------
+// Segments per piece of the cell-sum kernel.
+constexpr int64_t kPieceSegs = 64;
+
+// Pieces of the cell-sum kernel (kernels_cells.hpp): every b-cell cut into
+// segments of at most kCallSeg incidences, the segment list of all calls (in
+// b-cell order) cut into pieces of kPieceSegs segments; a cell that a
+// piece's ends cut is written as partial rows (one per piece holding part of
+// it) that the combine launch adds in piece order.
+int plan_cells(const tfi::Plan& p, CellHost& H) {
+    H = CellHost();
+    CellPlan& C = H.stats;
+    const int64_t NB = p.NB;
+    std::vector<int32_t>&piece = H.piece, &seg = H.seg, &bent = H.bent, &aent = H.aent,
+                           &comb = H.comb;
+    std::vector<int64_t> bseg0(NB + 1, 0);  // first segment of each b-cell
+    for (int64_t b = 0; b < NB; ++b) {
+        bseg0[b] = (int64_t)seg.size() / 2;
+        for (int64_t i = p.b_inc_off[b]; i < p.b_inc_off[b + 1]; i += tfi::kCallSeg) {
+            seg.push_back((int32_t)i);
+            seg.push_back((int32_t)std::min<int64_t>(tfi::kCallSeg, p.b_inc_off[b + 1] - i));
+        }
+    }
+    const int64_t nseg = (int64_t)seg.size() / 2;
+    bseg0[NB] = nseg;
+    for (int64_t b = 0; b < NB; ++b)
+        if (bseg0[b + 1] <= bseg0[b])
+            return fail(TFI_ERR_STATE, "internal: a b-cell without incidences");
+    // cut cells: (0 b-cell / 1 A-cell, id) -> their entries, in piece order
+    std::map<std::pair<int, int64_t>, std::vector<int64_t>> cut;
+    std::vector<std::pair<int, int64_t>> cut_order;
+    int64_t part_rows = 0, mrows = 1, b = 0;
+    for (int64_t ps0 = 0; ps0 < nseg; ps0 += kPieceSegs) {
+        const int64_t ps1 = std::min(nseg, ps0 + kPieceSegs);
+        while (bseg0[b + 1] <= ps0) ++b;  // the b-cell holding segment ps0
+        const int64_t e0 = (int64_t)bent.size() / tfi::kCallBEnt,
+                      q0 = (int64_t)aent.size() / tfi::kCallAEnt;
+        int64_t bb = b;
+        for (; bb < NB && bseg0[bb] < ps1; ++bb) {
+            const int64_t lo = std::max(bseg0[bb], ps0), hi = std::min(bseg0[bb + 1], ps1);
+            bent.insert(bent.end(), {(int32_t)bb, (int32_t)(lo - ps0), (int32_t)(hi - ps0), -1});
+            if (lo != bseg0[bb] || hi != bseg0[bb + 1]) {
+                const auto key = std::make_pair(0, bb);
+                if (!cut.count(key)) cut_order.push_back(key);
+                cut[key].push_back((int64_t)bent.size() / tfi::kCallBEnt - 1);
+            }
+        }
+        const int64_t e1 = (int64_t)bent.size() / tfi::kCallBEnt;
+        // the A-cells of the b-cells touched (each A-cell is a run of b-cells)
+        for (int64_t a = p.b2a[b]; a <= p.b2a[bb - 1]; ++a) {
+            const int64_t ab0 = p.a_b_off[a], ab1 = p.a_b_off[a + 1];
+            const int64_t alo = std::max<int64_t>(ab0, b) - b, ahi = std::min<int64_t>(ab1, bb) - b;
+            aent.insert(aent.end(), {(int32_t)a, (int32_t)alo, (int32_t)ahi, -1});
+            if (bseg0[ab0] < ps0 || bseg0[ab1] > ps1) {
+                const auto key = std::make_pair(1, a);
+                if (!cut.count(key)) cut_order.push_back(key);
+                cut[key].push_back((int64_t)aent.size() / tfi::kCallAEnt - 1);
+            }
+        }
+        const int64_t q1 = (int64_t)aent.size() / tfi::kCallAEnt;
+        piece.insert(piece.end(), {(int32_t)ps0, (int32_t)ps1, (int32_t)e0, (int32_t)e1,
+                                   (int32_t)q0, (int32_t)q1, 0, 0});
+        mrows = std::max(mrows, (ps1 - ps0) + (e1 - e0));
+    }
+    // partial rows of each cut cell, consecutive in piece order
+    for (const auto& key : cut_order) {
+        const std::vector<int64_t>& ents = cut[key];
+        comb.insert(comb.end(), {key.first, (int32_t)key.second, (int32_t)part_rows,
+                                 (int32_t)ents.size()});
+        for (int64_t ent : ents) {
+            if (key.first == 0)
+                bent[ent * tfi::kCallBEnt + 3] = (int32_t)part_rows++;
+            else
+                aent[ent * tfi::kCallAEnt + 3] = (int32_t)part_rows++;
+        }
+    }
+    // pieces by blocks of 2^12 vertex ids (of their first incidence), in
+    // order within a block: the pieces of all levels over one region of the
+    // forest (one tree of a batch) run together and share its field rows in
+    // cache; the kernel gives each XCD a contiguous range of this order
+    {
+        const int64_t np = (int64_t)piece.size() / tfi::kCallRec;
+        std::vector<int64_t> order(np), key(np);
+        for (int64_t k = 0; k < np; ++k) {
+            order[k] = k;
+            key[k] = p.inc_v[seg[2 * (size_t)piece[k * tfi::kCallRec]]] >> 12;
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        std::vector<int32_t> sorted(piece.size());
+        for (int64_t k = 0; k < np; ++k)
+            std::copy(piece.begin() + order[k] * tfi::kCallRec,
+                      piece.begin() + (order[k] + 1) * tfi::kCallRec,
+                      sorted.begin() + k * tfi::kCallRec);
+        piece.swap(sorted);
+    }
+    C.npieces = (int64_t)piece.size() / tfi::kCallRec;
+    C.nsegs = (int64_t)seg.size() / 2;
+    C.nbent = (int64_t)bent.size() / tfi::kCallBEnt;
+    C.naent = (int64_t)aent.size() / tfi::kCallAEnt;
+    C.part_rows = part_rows;
+    C.ncomb = (int64_t)comb.size() / 4;
+    C.max_rows = mrows;
+    if (part_rows > INT32_MAX || (int64_t)seg.size() > INT32_MAX)
+        return fail(TFI_ERR_STATE, "internal: cell-sum indices exceed 32 bits");
+    return TFI_OK;
+}
+
+int build_cells(tfi_plan* h) {
+    CellHost H;
+    int rc = plan_cells(h->plan, H);
+    if (rc) return rc;
+    CellPlan& C = h->cells;
+    C = H.stats;
+    if ((rc = h->upload(&C.d_piece, H.piece))) return rc;
+    if ((rc = h->upload(&C.d_seg, H.seg))) return rc;
+    if ((rc = h->upload(&C.d_bent, H.bent))) return rc;
+    if ((rc = h->upload(&C.d_aent, H.aent))) return rc;
+    if ((rc = h->upload(&C.d_comb, H.comb))) return rc;
     return TFI_OK;
 }
 
@@ -488,6 +638,8 @@ int upload_static(tfi_plan* h) {
         }
         h->val_rows = next_row;
     }
+    // cell sums, the other strategy: pieces of the cell-sum kernel
+    if ((rc = build_cells(h))) return rc;
 
     // gather: table row and correction row (or -1) per vertex incidence
     {
@@ -680,6 +832,83 @@ bool whole_path_plan(const tfi::Plan& p) {
     return true;
 }
 
+// Direct tables of a list of jobs: jobs sorted by size (largest first) so
+// that lanes of a wavefront run equal loops, each padded to whole quads of 4
+// cells (padding: r = x = 0, row -1); blocks pack whole jobs up to kDirOut
+// cells, larger jobs are cut into kDirOut-cell output slices whose sources
+// are the whole job.
+int build_direct(tfi_plan* h, std::vector<int64_t> djobs, DirectSet& ds) {
+    const tfi::Plan& p = h->plan;
+    int rc;
+    ds = DirectSet();
+    std::stable_sort(djobs.begin(), djobs.end(), [&](int64_t a, int64_t b) {
+        return p.job_cell_off[a + 1] - p.job_cell_off[a] >
+               p.job_cell_off[b + 1] - p.job_cell_off[b];
+    });
+    std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk, dbin;
+    std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
+    std::vector<int32_t> jbin;                    // per job: 1 + largest pair distance
+    for (int64_t j : djobs) {
+        const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
+        const int32_t jb = (int32_t)dl_r.size();
+        const int32_t n = ce - cb, np = (n + 3) & ~3;
+        ds.direct_pairs += (double)n * n;
+        {
+            int32_t rmax = 0, xmin = INT32_MAX, xmax = INT32_MIN;
+            for (int32_t i = cb; i < ce; ++i) {
+                rmax = std::max(rmax, p.jc_r[i]);
+                xmin = std::min(xmin, p.jc_x[i]);
+                xmax = std::max(xmax, p.jc_x[i]);
+            }
+            const int64_t b = n > 0 ? 2 * (int64_t)rmax + (xmax - xmin) + 1 : 1;
+            jbin.push_back((int32_t)std::min<int64_t>(b, p.kernel_len));
+        }
+        for (int32_t i = 0; i < np; ++i) {
+            const bool real = i < n;
+            dl_r.push_back(real ? p.jc_r[cb + i] : 0);
+            dl_x.push_back(real ? p.jc_x[cb + i] : 0);
+            dl_row.push_back(real ? p.jc_val[cb + i] : -1);
+        }
+        const int32_t je = jb + np;
+        for (int32_t q = 0; q < np / 4; ++q) {
+            qjb.push_back(jb);
+            qje.push_back(je);
+        }
+        jr.emplace_back(jb, je);
+    }
+    size_t k = 0;
+    while (k < jr.size()) {
+        const int32_t jb = jr[k].first, je = jr[k].second;
+        if (je - jb > tfi::kDirOut) {
+            for (int32_t o = jb; o < je; o += tfi::kDirOut) {
+                dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
+                dbin.push_back(jbin[k]);
+            }
+            ++k;
+            continue;
+        }
+        size_t e = k + 1;
+        while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
+        const int32_t end = jr[e - 1].second;
+        dblk.insert(dblk.end(), {jb, end, jb, end});
+        int32_t bmax = 1;
+        for (size_t u = k; u < e; ++u) bmax = std::max(bmax, jbin[u]);
+        dbin.push_back(bmax);
+        k = e;
+    }
+    ds.ndirect = (int64_t)dl_r.size();
+    ds.ndblk = (int64_t)dblk.size() / 4;
+    if ((rc = h->upload_m(&ds.d_dl_r, dl_r))) return rc;
+    if ((rc = h->upload_m(&ds.d_dl_x, dl_x))) return rc;
+    if ((rc = h->upload_m(&ds.d_dl_row, dl_row))) return rc;
+    if ((rc = h->upload_m(&ds.d_qjb, qjb))) return rc;
+    if ((rc = h->upload_m(&ds.d_qje, qje))) return rc;
+    if ((rc = h->upload_m(&ds.d_dblk, dblk))) return rc;
+    if ((rc = h->upload_m(&ds.d_dbin, dbin))) return rc;
+    ds.dbin_max = dbin.empty() ? 0 : *std::max_element(dbin.begin(), dbin.end());
+    return TFI_OK;
+}
+
 int upload_methods(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
@@ -710,78 +939,7 @@ int upload_methods(tfi_plan* h) {
             b.cells += ce - cb;
         }
     }
-    // direct cells: jobs sorted by size (largest first) so that lanes of a
-    // wavefront run equal loops, each padded to whole quads of 4 cells
-    // (padding: r = x = 0, row -1); blocks pack whole jobs up to kDirOut
-    // cells, larger jobs are cut into kDirOut-cell output slices whose
-    // sources are the whole job.
-    {
-        std::stable_sort(djobs.begin(), djobs.end(), [&](int64_t a, int64_t b) {
-            return p.job_cell_off[a + 1] - p.job_cell_off[a] >
-                   p.job_cell_off[b + 1] - p.job_cell_off[b];
-        });
-        std::vector<int32_t> dl_r, dl_x, dl_row, qjb, qje, dblk, dbin;
-        std::vector<std::pair<int32_t, int32_t>> jr;  // padded job ranges
-        std::vector<int32_t> jbin;                    // per job: 1 + largest pair distance
-        for (int64_t j : djobs) {
-            const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
-            const int32_t jb = (int32_t)dl_r.size();
-            const int32_t n = ce - cb, np = (n + 3) & ~3;
-            h->direct_pairs += (double)n * n;
-            {
-                int32_t rmax = 0, xmin = INT32_MAX, xmax = INT32_MIN;
-                for (int32_t i = cb; i < ce; ++i) {
-                    rmax = std::max(rmax, p.jc_r[i]);
-                    xmin = std::min(xmin, p.jc_x[i]);
-                    xmax = std::max(xmax, p.jc_x[i]);
-                }
-                const int64_t b = n > 0 ? 2 * (int64_t)rmax + (xmax - xmin) + 1 : 1;
-                jbin.push_back((int32_t)std::min<int64_t>(b, p.kernel_len));
-            }
-            for (int32_t i = 0; i < np; ++i) {
-                const bool real = i < n;
-                dl_r.push_back(real ? p.jc_r[cb + i] : 0);
-                dl_x.push_back(real ? p.jc_x[cb + i] : 0);
-                dl_row.push_back(real ? p.jc_val[cb + i] : -1);
-            }
-            const int32_t je = jb + np;
-            for (int32_t q = 0; q < np / 4; ++q) {
-                qjb.push_back(jb);
-                qje.push_back(je);
-            }
-            jr.emplace_back(jb, je);
-        }
-        size_t k = 0;
-        while (k < jr.size()) {
-            const int32_t jb = jr[k].first, je = jr[k].second;
-            if (je - jb > tfi::kDirOut) {
-                for (int32_t o = jb; o < je; o += tfi::kDirOut) {
-                    dblk.insert(dblk.end(), {o, std::min(je, o + tfi::kDirOut), jb, je});
-                    dbin.push_back(jbin[k]);
-                }
-                ++k;
-                continue;
-            }
-            size_t e = k + 1;
-            while (e < jr.size() && jr[e].second - jb <= tfi::kDirOut) ++e;
-            const int32_t end = jr[e - 1].second;
-            dblk.insert(dblk.end(), {jb, end, jb, end});
-            int32_t bmax = 1;
-            for (size_t u = k; u < e; ++u) bmax = std::max(bmax, jbin[u]);
-            dbin.push_back(bmax);
-            k = e;
-        }
-        h->ndirect = (int64_t)dl_r.size();
-        h->ndblk = (int64_t)dblk.size() / 4;
-        if ((rc = h->upload_m(&h->d_dl_r, dl_r))) return rc;
-        if ((rc = h->upload_m(&h->d_dl_x, dl_x))) return rc;
-        if ((rc = h->upload_m(&h->d_dl_row, dl_row))) return rc;
-        if ((rc = h->upload_m(&h->d_qjb, qjb))) return rc;
-        if ((rc = h->upload_m(&h->d_qje, qje))) return rc;
-        if ((rc = h->upload_m(&h->d_dblk, dblk))) return rc;
-        if ((rc = h->upload_m(&h->d_dbin, dbin))) return rc;
-        h->dbin_max = dbin.empty() ? 0 : *std::max_element(dbin.begin(), dbin.end());
-    }
+    if ((rc = build_direct(h, djobs, h->dall))) return rc;
 
     h->spec_elems = 0;
     for (Bucket& b : h->buckets) {
@@ -845,7 +1003,7 @@ int upload_methods(tfi_plan* h) {
             b.reflect = col;
         }
         h->path_mode[ti] = fj[0].empty() && fj[1].empty() && fj[2].empty() &&
-                           h->ndirect == 0 && whole_path_plan(p);
+                           h->dall.ndirect == 0 && whole_path_plan(p);
         for (int bi : h->global_b[ti])
             if (!h->buckets[bi].d_map) h->path_mode[ti] = false;
         if (h->path_mode[ti])
@@ -896,8 +1054,63 @@ inline int64_t tiled_threads(int64_t nrows, int32_t dv, int32_t ct) {
     return (int64_t)((dv + ct - 1) / ct) * nrows * ct;
 }
 
+// Threads per row (up to 16) and VEC of the cell-sum kernel at d channels:
+// chunks of up to 64 channels.
+inline void cell_shape(int32_t d, bool v4, int* lanes, int* vec) {
+    *vec = v4 ? 4 : 1;
+    const int32_t w = std::min<int32_t>(64, d);
+    const int32_t need = w / *vec + (w % *vec != 0);
+    int l = 1;
+    while (l < need) l <<= 1;
+    *lanes = std::min(l, 16);
+}
+
+// Cell sums of the rows of src ([N x d]) into val: A-cells at rows
+// [0, NA), b-cells at NA + b (kernels_cells.hpp); part holds the partial
+// rows of the cells cut between pieces (part_rows x d).
 template <typename T>
-void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st) {
+void launch_scatter_pieces(tfi_plan* h, const T* src, T* val, T* part, int32_t d,
+                           hipStream_t st) {
+    const CellPlan& C = h->cells;
+    if (C.npieces == 0) return;
+    const tfi::Plan& p = h->plan;
+    hipEvent_t ev = h->begin(st);
+    const bool v4 = d % 4 == 0 && aligned16(src);
+    int lanes = 1, vec = 1;
+    cell_shape(d, v4, &lanes, &vec);
+    const unsigned lds = (unsigned)((size_t)C.max_rows * lanes * vec * sizeof(T));
+    if (v4)
+        hipLaunchKernelGGL((tfi::k_cells<T, 4>), dim3((unsigned)C.npieces), dim3(tfi::kCallThreads),
+                           lds, st, d, (int32_t)lanes, C.d_piece, C.d_seg, C.d_bent, C.d_aent,
+                           h->d_inc_v, src, (int64_t)p.NA, part, val);
+    else
+        hipLaunchKernelGGL((tfi::k_cells<T, 1>), dim3((unsigned)C.npieces), dim3(tfi::kCallThreads),
+                           lds, st, d, (int32_t)lanes, C.d_piece, C.d_seg, C.d_bent, C.d_aent,
+                           h->d_inc_v, src, (int64_t)p.NA, part, val);
+    const double sz = (double)sizeof(T);
+    h->end(st, ev, "scatter",
+           sz * d * ((double)p.incidences + (double)(C.nbent + C.naent)) + 4.0 * p.incidences +
+               8.0 * C.nsegs + 16.0 * (C.nbent + C.naent) + 4.0 * tfi::kCallRec * C.npieces);
+    if (C.ncomb > 0) {  // cells cut between pieces: their partial rows in order
+        hipEvent_t ev2 = h->begin(st);
+        const dim3 grid(blocks_for(C.ncomb * lanes, tfi::kCallThreads));
+        if (v4)
+            hipLaunchKernelGGL((tfi::k_cells_combine<T, 4>), grid, dim3(tfi::kCallThreads), 0, st,
+                               d, (int32_t)lanes, (int32_t)C.ncomb, C.d_comb, (const T*)part, val,
+                               (int64_t)p.NA);
+        else
+            hipLaunchKernelGGL((tfi::k_cells_combine<T, 1>), grid, dim3(tfi::kCallThreads), 0, st,
+                               d, (int32_t)lanes, (int32_t)C.ncomb, C.d_comb, (const T*)part, val,
+                               (int64_t)p.NA);
+        h->end(st, ev2, "scatter_combine",
+               sz * d * ((double)C.part_rows + (double)C.ncomb) + 16.0 * C.ncomb);
+    }
+}
+
+// Cell sums by levels of bounded segment sums (k_segsum): field rows per
+// segment of at most 32 incidences, then partial rows level by level.
+template <typename T>
+void launch_scatter_levels(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st) {
     const double sz = (double)sizeof(T);
     for (size_t l = 0; l < h->seg_levels.size(); ++l) {
         const tfi_plan::SegLevel& L = h->seg_levels[l];
@@ -924,6 +1137,24 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, int32_t d, hipStream_t st
                sz * d * (double)(L.rows_read + L.n) + (L.indexed ? 4.0 * L.rows_read : 0.0) +
                    20.0 * L.n);
     }
+}
+
+// Whether the cell sums at d channels go through the pieces (k_cells) or
+// the levels (k_segsum): pieces put fewer launches and round trips on the
+// chain and suit larger cells; levels run every segment as its own thread
+// group and suit many tiny cells at wide rows. tfi_autotune times both.
+inline bool scatter_pieces(const tfi_plan* h, int32_t d) {
+    return h->scatter_pick >= 0 ? h->scatter_pick == 0 : d <= 16;
+}
+
+// Cell sums of the rows of src ([N x d]) into val (A-cells at [0, NA),
+// b-cells at NA + b); part: partial rows of the pieces.
+template <typename T>
+void launch_scatter(tfi_plan* h, const T* src, T* val, T* part, int32_t d, hipStream_t st) {
+    if (scatter_pieces(h, d))
+        launch_scatter_pieces<T>(h, src, val, part, d, st);
+    else
+        launch_scatter_levels<T>(h, src, val, d, st);
 }
 
 // Pass schedule of a transform along an axis of 2^lgL points: groups of up
@@ -1143,11 +1374,12 @@ bool path_direct(const tfi_plan* h, int32_t d) {
 // Scratch of one forward pass (or of dF): cell sums, table rows, kernel
 // spectra and the FFT work buffer of the buckets beyond LDS.
 struct Work {
-    void* val = nullptr;   // [val_rows x d] cell sums
+    void* val = nullptr;   // [NA + NB, d] cell sums
     void* g = nullptr;     // [nk x (NA + NB) x d] table rows
     void* spec = nullptr;  // [nk x spec_elems] complex spectra
     void* fft = nullptr;   // FFT slots of the global buckets
     size_t fft_bytes = 0;
+    void* part = nullptr;  // [part_rows x d] partial rows of cells cut between pieces
 };
 
 // Bytes of each part of Work; `general` asks for the value and table rows
@@ -1155,7 +1387,7 @@ struct Work {
 // take nk table arrays and nk spectrum arenas. The FFT workspace holds
 // chunks of at most 2 GiB, or one job's slots when a job alone is larger.
 struct WorkSizes {
-    size_t val = 0, g = 0, spec = 0, fft = 0;
+    size_t val = 0, g = 0, spec = 0, fft = 0, part = 0;
 };
 
 template <typename T>
@@ -1167,6 +1399,8 @@ WorkSizes forward_sizes(const tfi_plan* h, int32_t d, bool general = false, int 
     if (rows) {
         z.val = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
         z.g = (size_t)nk * std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T);
+        if (scatter_pieces(h, d))
+            z.part = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     }
     z.spec = (size_t)nk * std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>);
     for (int bi : h->global_b[ti]) {
@@ -1188,6 +1422,7 @@ Work handle_work(const tfi_plan* h) {
     w.spec = h->spec[ti].p;
     w.fft = h->fftbuf[ti].p;
     w.fft_bytes = h->fftbuf[ti].bytes;
+    w.part = h->part[ti].p;
     return w;
 }
 
@@ -1201,6 +1436,7 @@ int prepare_forward(tfi_plan* h, int32_t d, bool general = false, int nk = 1) {
     if (z.g && (rc = h->ensure(h->g[ti], z.g))) return rc;
     if ((rc = h->ensure(h->spec[ti], z.spec))) return rc;
     if (z.fft && (rc = h->ensure(h->fftbuf[ti], z.fft))) return rc;
+    if (z.part && (rc = h->ensure(h->part[ti], z.part))) return rc;
     return TFI_OK;
 }
 
@@ -1303,15 +1539,15 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
 // the matrix cores both share one launch and its value tiles; otherwise one
 // launch each.
 template <typename T>
-void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStream_t st,
-                const T* f1 = nullptr, T* g1 = nullptr) {
-    if (h->ndblk == 0) return;
+void enq_direct(tfi_plan* h, const DirectSet& ds, const T* f, int32_t d, const T* val, T* g,
+                hipStream_t st, const T* f1 = nullptr, T* g1 = nullptr) {
+    if (ds.ndblk == 0) return;
     const tfi::Plan& p = h->plan;
     const int nk = f1 ? 2 : 1;
     const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
     if (!mfma && f1) {
-        enq_direct<T>(h, f, d, val, g, st);
-        enq_direct<T>(h, f1, d, val, g1, st);
+        enq_direct<T>(h, ds, f, d, val, g, st);
+        enq_direct<T>(h, ds, f1, d, val, g1, st);
         return;
     }
     hipEvent_t ev = h->begin(st);
@@ -1320,12 +1556,12 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
     if (mfma) {
         // 16-channel chunks per pass: one kernel entry serves all of them
         const int nch = d > 48 ? 4 : d > 32 ? 3 : d > 16 ? 2 : 1;
-        const unsigned ys = chan_split(h->ndblk, d, 16 * nch);
+        const unsigned ys = chan_split(ds.ndblk, d, 16 * nch);
         const unsigned lds = (unsigned)(nk * flds * sizeof(float));
         auto launch = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk, ys), dim3(tfi::kDirThreads), lds, st,
-                               d, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                               h->d_qje, (const float*)f, (const float*)f1, flds,
+            hipLaunchKernelGGL(kern, dim3((unsigned)ds.ndblk, ys), dim3(tfi::kDirThreads), lds, st,
+                               d, ds.d_dblk, ds.d_dl_r, ds.d_dl_x, ds.d_dl_row, ds.d_qjb,
+                               ds.d_qje, (const float*)f, (const float*)f1, flds,
                                (const float*)val, (float*)g, (float*)g1);
         };
         if (nk == 2) {
@@ -1345,15 +1581,15 @@ void enq_direct(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStrea
         }
     } else {
         hipLaunchKernelGGL(tfi::k_direct<T>,
-                           dim3((unsigned)h->ndblk, chan_split(h->ndblk, d, tfi::kDirCh)),
-                           dim3(tfi::kDirThreads), (unsigned)(flds * sizeof(T)), st, d, h->d_dblk,
-                           h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb, h->d_qje, f, flds, val,
+                           dim3((unsigned)ds.ndblk, chan_split(ds.ndblk, d, tfi::kDirCh)),
+                           dim3(tfi::kDirThreads), (unsigned)(flds * sizeof(T)), st, d, ds.d_dblk,
+                           ds.d_dl_r, ds.d_dl_x, ds.d_dl_row, ds.d_qjb, ds.d_qje, f, flds, val,
                            g);
     }
     // bytes: the value rows once, the table rows of every kernel
     h->end(st, ev, mfma ? "direct_mfma" : "direct",
-           sizeof(T) * d * (double)h->ndirect * (1 + nk) + 20.0 * h->ndirect,
-           2.0 * nk * d * h->direct_pairs);
+           sizeof(T) * d * (double)ds.ndirect * (1 + nk) + 20.0 * ds.ndirect,
+           2.0 * nk * d * ds.direct_pairs);
 }
 
 // Gather of one kernel's tables (g into out), or of two (also g1 into out1)
@@ -1363,6 +1599,9 @@ void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st,
                 const T* g1 = nullptr, T* out1 = nullptr) {
     const tfi::Plan& p = h->plan;
     const int nk = g1 ? 2 : 1;
+    const int32_t* ga = h->d_ga;
+    const int32_t* gb = h->d_gb;
+    const double reads = (double)h->gather_reads;
     hipEvent_t ev = h->begin(st);
     const bool v4 = d % 4 == 0 && aligned16(out) && (!out1 || aligned16(out1));
     const int vec = v4 ? 4 : 1;
@@ -1370,20 +1609,20 @@ void enq_gather(tfi_plan* h, int32_t d, const T* g, T* out, hipStream_t st,
     const dim3 grid(blocks_for(tiled_threads(p.N, d / vec, ct)));
     if (v4 && nk == 2)
         hipLaunchKernelGGL((tfi::k_gather<T, 4, 2>), grid, dim3(kThreads), 0, st, p.N, d, ct,
-                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, g1, out, out1);
+                           h->d_v_off, ga, gb, h->d_vleaf, g, g1, out, out1);
     else if (v4)
         hipLaunchKernelGGL((tfi::k_gather<T, 4, 1>), grid, dim3(kThreads), 0, st, p.N, d, ct,
-                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, (const T*)nullptr, out,
+                           h->d_v_off, ga, gb, h->d_vleaf, g, (const T*)nullptr, out,
                            (T*)nullptr);
     else if (nk == 2)
         hipLaunchKernelGGL((tfi::k_gather<T, 1, 2>), grid, dim3(kThreads), 0, st, p.N, d, ct,
-                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, g1, out, out1);
+                           h->d_v_off, ga, gb, h->d_vleaf, g, g1, out, out1);
     else
         hipLaunchKernelGGL((tfi::k_gather<T, 1, 1>), grid, dim3(kThreads), 0, st, p.N, d, ct,
-                           h->d_v_off, h->d_ga, h->d_gb, h->d_vleaf, g, (const T*)nullptr, out,
+                           h->d_v_off, ga, gb, h->d_vleaf, g, (const T*)nullptr, out,
                            (T*)nullptr);
     h->end(st, ev, "gather",
-           nk * sizeof(T) * d * (double)(h->gather_reads + 2 * p.N) +
+           nk * sizeof(T) * d * (reads + 2 * p.N) +
                8.0 * (double)p.v_b.size() + 9.0 * p.N);
 }
 
@@ -1456,7 +1695,7 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
 template <typename T>
 void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* df,
                    hipStream_t st) {
-    if (h->ndblk == 0) return;
+    if (h->dall.ndblk == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
     const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
@@ -1466,9 +1705,9 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
         // histogram copies: as many as fit (up to 16) in 80 KiB of LDS, so
         // that two blocks share a CU; none when one copy does not fit
         auto launch = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)h->ndblk), dim3(tfi::kDirThreads), 0, st, d,
-                               p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                               h->d_qje, (const float*)val, (const float*)valg, h->d_dbin, df);
+            hipLaunchKernelGGL(kern, dim3((unsigned)h->dall.ndblk), dim3(tfi::kDirThreads), 0, st, d,
+                               p.NA, h->dall.d_dblk, h->dall.d_dl_r, h->dall.d_dl_x, h->dall.d_dl_row, h->dall.d_qjb,
+                               h->dall.d_qje, (const float*)val, (const float*)valg, h->dall.d_dbin, df);
         };
         switch (cpl) {
             case 16: launch(tfi::k_df_direct_mfma<16>); break;
@@ -1478,13 +1717,13 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
             default: launch(tfi::k_df_direct_mfma<1>); break;
         }
     } else {
-        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->ndblk), dim3(tfi::kDfThreads), 0,
-                           st, d, p.NA, h->d_dblk, h->d_dl_r, h->d_dl_x, h->d_dl_row, h->d_qjb,
-                           h->d_qje, val, valg, h->d_dbin, df);
+        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->dall.ndblk), dim3(tfi::kDfThreads), 0,
+                           st, d, p.NA, h->dall.d_dblk, h->dall.d_dl_r, h->dall.d_dl_x, h->dall.d_dl_row, h->dall.d_qjb,
+                           h->dall.d_qje, val, valg, h->dall.d_dbin, df);
     }
     h->end(st, ev, mfma ? "df_direct_mfma" : "df_direct",
-           2.0 * sizeof(T) * d * (double)h->ndirect + 20.0 * h->ndirect,
-           2.0 * d * h->direct_pairs);
+           2.0 * sizeof(T) * d * (double)h->dall.ndirect + 20.0 * h->dall.ndirect,
+           2.0 * d * h->dall.direct_pairs);
 }
 
 template <typename T>
@@ -1566,14 +1805,14 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
         (void)hipEventRecord(h->ev_c, s2);
     }
     if (use1) enq_spectra<T>(h, f, s1, (tfi::cpx<T>*)w.spec);  // side1: kernel spectra
-    launch_scatter<T>(h, F, val, d, s0);        // main: cell sums
+    launch_scatter<T>(h, F, val, (T*)w.part, d, s0);  // main: cell sums
     if (use1) {
         (void)hipEventRecord(h->ev_a, s0);
         (void)hipStreamWaitEvent(s1, h->ev_a, 0);
         enq_fft<T>(h, d, val, g, s1, w);        // side1: FFT tables
         (void)hipEventRecord(h->ev_b, s1);
     }
-    enq_direct<T>(h, f, d, val, g, s0);         // main: direct tables
+    enq_direct<T>(h, h->dall, f, d, val, g, s0);  // main: direct tables
     if (use1) (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     if (use2) (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     enq_gather<T>(h, d, g, out, s0);            // main: out = leaf + calls
@@ -1602,7 +1841,7 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     // the main chain is enqueued first (in a captured graph the first chain
     // keeps the launch queue, so the gather follows the direct tables on
     // one queue and its wait for the side streams finds them done)
-    launch_scatter<T>(h, F, val, d, s0);
+    launch_scatter<T>(h, F, val, (T*)w.part, d, s0);
     // leaf tiles in pairs of kernels (FP32: two FP64 f(D) blocks would not
     // fit the LDS of one workgroup)
     if (use2) {
@@ -1627,7 +1866,7 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     // gather
     for (int i = 0; i < nk; i += 2) {
         const bool two = i + 1 < nk;
-        enq_direct<T>(h, f[i], d, val, g0 + i * gstride, s0, two ? f[i + 1] : nullptr,
+        enq_direct<T>(h, h->dall, f[i], d, val, g0 + i * gstride, s0, two ? f[i + 1] : nullptr,
                       two ? g0 + (i + 1) * gstride : nullptr);
     }
     if (use1) (void)hipStreamWaitEvent(s0, h->ev_b, 0);
@@ -1647,8 +1886,8 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
                       double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2,
                       const T* cells = nullptr) {
     const Work w = handle_work<T>(h);
-    if (!df && path_direct<T>(h, d)) {
-        if (dF) enqueue_path<T>(h, f, gout, d, dF, s0, w);
+    if (!df) {  // dF alone is the forward applied to gout
+        if (dF) enqueue_forward<T>(h, f, gout, d, dF, s0, s1, s2, w);
         return;
     }
     const tfi::Plan& p = h->plan;
@@ -1665,16 +1904,16 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     (void)hipEventRecord(h->ev_c, s2);
     // the cell sums of F: kept from the forward, or formed here
     const T* valF = cells ? cells : val;
-    if (df && !cells) launch_scatter<T>(h, F, val, d, s1);
+    if (df && !cells) launch_scatter<T>(h, F, val, (T*)w.part, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
     if (dF) enq_spectra<T>(h, f, s1, (tfi::cpx<T>*)w.spec);
-    launch_scatter<T>(h, gout, valg, d, s0);
+    launch_scatter<T>(h, gout, valg, (T*)h->partg[ti].p, d, s0);
     (void)hipEventRecord(h->ev_a, s0);
     (void)hipStreamWaitEvent(s1, h->ev_a, 0);
     if (dF) enq_fft<T>(h, d, valg, g, s1, w);
     if (df) enq_df_tables<T>(h, d, valF, valg, df, s1);
     (void)hipEventRecord(h->ev_b, s1);
-    if (dF) enq_direct<T>(h, f, d, valg, g, s0);
+    if (dF) enq_direct<T>(h, h->dall, f, d, valg, g, s0);
     if (df) {
         (void)hipStreamWaitEvent(s0, h->ev_d, 0);
         enq_df_direct<T>(h, d, valF, valg, df, s0);
@@ -1688,11 +1927,14 @@ template <typename T>
 int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
     int rc = prepare_forward<T>(h, d, need_df);
     if (rc) return rc;
-    if (!need_df && path_direct<T>(h, d)) return TFI_OK;
+    if (!need_df) return TFI_OK;  // dF alone runs the forward on gout
     const int ti = sizeof(T) == 8 ? 1 : 0;
     const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
     if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
-    if (!need_df) return TFI_OK;
+    if (scatter_pieces(h, d) &&
+        (rc = h->ensure(h->partg[ti], (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d *
+                                          sizeof(T))))
+        return rc;
     const int32_t npairs = (d + 1) / 2;
     const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
     size_t want = 0;
@@ -1827,7 +2069,7 @@ int run_forward_noalloc(tfi_plan* h, const T* f, const T* F, int32_t d, T* out,
         return at;
     };
     const size_t o_val = take(z.val), o_g = take(z.g), o_spec = take(z.spec),
-                 o_fft = take(z.fft);
+                 o_fft = take(z.fft), o_part = take(z.part);
     if (off > kNoAllocBytes)
         return fail(TFI_ERR_BUDGET,
                     "tfi_integrate_noalloc: this plan needs " + std::to_string(off) +
@@ -1842,6 +2084,7 @@ int run_forward_noalloc(tfi_plan* h, const T* f, const T* F, int32_t d, T* out,
     w.spec = base + o_spec;
     w.fft = z.fft ? base + o_fft : nullptr;
     w.fft_bytes = z.fft;
+    w.part = z.part ? base + o_part : nullptr;
     // stage events would be created on demand: none while this runs
     const bool keep_prof = h->prof;
     h->prof = false;
@@ -1914,7 +2157,10 @@ int prepare_expsum(tfi_plan* h, int32_t nterm, int32_t d, bool bwd, bool grad) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
     int rc;
     const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    const size_t partbytes = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     if ((rc = h->ensure(h->val[ti], rowbytes))) return rc;
+    const bool pieces = scatter_pieces(h, d);
+    if (pieces && (rc = h->ensure(h->part[ti], partbytes))) return rc;
     if ((rc = h->ensure(h->g[ti], (size_t)std::max<int64_t>(p.NA + p.NB, 1) * d * sizeof(T))))
         return rc;
     if ((rc = h->ensure(h->expw[ti], (size_t)(nterm + 1) * p.kernel_len * sizeof(T)))) return rc;
@@ -1923,6 +2169,7 @@ int prepare_expsum(tfi_plan* h, int32_t nterm, int32_t d, bool bwd, bool grad) {
         (rc = h->ensure(h->exps[ti], (size_t)h->npos_multi * nq * nterm * d * sizeof(T))))
         return rc;
     if (bwd && (rc = h->ensure(h->valg[ti], rowbytes))) return rc;
+    if (bwd && pieces && (rc = h->ensure(h->partg[ti], partbytes))) return rc;
     if (grad && (rc = h->ensure(h->hleaf, (size_t)p.kernel_len * sizeof(double)))) return rc;
     if (grad && (rc = h->ensure(h->mrows, (size_t)expsum_moment_rows(h, d, nterm) * 2 * nterm *
                                               sizeof(double))))
@@ -2043,7 +2290,7 @@ void enqueue_forward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* lam
     enq_leaf<T>(h, ftab, F, d, out, s2);  // side2: leaf rows into out
     (void)hipEventRecord(h->ev_c, s2);
     (void)hipEventRecord(h->ev_b, s1);
-    launch_scatter<T>(h, F, val, d, s0);  // main: cell sums, sweeps
+    launch_scatter<T>(h, F, val, (T*)h->part[ti].p, d, s0);  // main: cell sums, sweeps
     enq_expsum_jobs<T, false>(h, nterm, c, d, val, nullptr, g, nullptr, s0);
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
@@ -2082,9 +2329,9 @@ void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* la
                            mrow, rows - nterm);
     }
     (void)hipEventRecord(h->ev_c, s2);
-    if (grad && !cells) launch_scatter<T>(h, F, val, d, s1);
+    if (grad && !cells) launch_scatter<T>(h, F, val, (T*)h->part[ti].p, d, s1);
     (void)hipEventRecord(h->ev_d, s1);
-    launch_scatter<T>(h, gout, valg, d, s0);
+    launch_scatter<T>(h, gout, valg, (T*)h->partg[ti].p, d, s0);
     if (dF && !grad) enq_expsum_jobs<T, false>(h, nterm, c, d, valg, nullptr, g, nullptr, s0);
     (void)hipStreamWaitEvent(s0, h->ev_d, 0);
     if (grad && dF) enq_expsum_jobs_fused<T>(h, nterm, c, d, valF, valg, g, mrow, s0);
@@ -2268,6 +2515,7 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     h->direct_kernel = o.direct_kernel;
     if (const char* e = std::getenv("TFI_NO_GRAPHS"))
         if (e[0] && e[0] != '0') h->use_graphs = false;
+
     if (o.device >= 0) {
         int count = 0;
         hipError_t e = hipGetDeviceCount(&count);
@@ -2506,6 +2754,9 @@ int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
     std::snprintf(fp, sizeof(fp), "%016llx", (unsigned long long)tfi::plan_fingerprint(h->plan));
     s += ",\"fingerprint\":\"" + std::string(fp) + "\",\"fft_cost\":" +
          std::to_string(h->popt.fft_cost);
+    s += ",\"scatter_pick\":" + std::to_string(h->scatter_pick) +
+         ",\"cell_pieces\":" + std::to_string(h->cells.npieces) +
+         ",\"cell_cuts\":" + std::to_string(h->cells.ncomb);
     s += ",\"device\":" + std::to_string(h->device) +
          ",\"device_bytes\":" + std::to_string(h->dev_bytes) +
          ",\"arrays\":{\"job_H\":\"i32\",\"job_X\":\"i32\",\"job_sign\":\"i32\","
@@ -2513,7 +2764,9 @@ int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
          "\"job_cell_off\":\"i64\",\"jc_r\":\"i32\",\"jc_x\":\"i32\",\"jc_val\":\"i32\","
          "\"inc_v\":\"i32\",\"b_inc_off\":\"i64\",\"a_b_off\":\"i64\",\"b2a\":\"i32\","
          "\"b_corr\":\"i8\",\"v_off\":\"i64\",\"v_b\":\"i32\",\"leaf_off\":\"i64\","
-         "\"leaf_v\":\"i32\",\"leaf_doff\":\"i64\",\"leaf_D\":\"i32\"}}";
+         "\"leaf_v\":\"i32\",\"leaf_doff\":\"i64\",\"leaf_D\":\"i32\","
+         "\"cells_piece\":\"i32\",\"cells_seg\":\"i32\",\"cells_bent\":\"i32\","
+         "\"cells_aent\":\"i32\",\"cells_comb\":\"i32\"}}";
     if (json && cap > 0) {
         size_t n = std::min(cap - 1, s.size());
         std::memcpy(json, s.data(), n);
@@ -2555,6 +2808,20 @@ int64_t tfi_plan_export(tfi_handle h, const char* name, void* buf, size_t cap) {
     else if (n == "leaf_v") pick(p.leaf_v);
     else if (n == "leaf_doff") pick(p.leaf_doff);
     else if (n == "leaf_D") pick(p.leaf_D);
+    else if (n.rfind("cells_", 0) == 0) {
+        // the cell-sum kernel's piece arrays (planned again here, so
+        // host-only handles export them too)
+        static thread_local CellHost H;
+        const int rc = plan_cells(p, H);
+        if (rc) return rc;
+        const std::string k = n.substr(6);
+        if (k == "piece") pick(H.piece);
+        else if (k == "seg") pick(H.seg);
+        else if (k == "bent") pick(H.bent);
+        else if (k == "aent") pick(H.aent);
+        else if (k == "comb") pick(H.comb);
+        else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
+    }
     else return fail(TFI_ERR_ARG, "tfi_plan_export: unknown array '" + n + "'");
     if (buf && cap >= bytes && bytes) std::memcpy(buf, src, bytes);
     return (int64_t)bytes;
@@ -2577,6 +2844,19 @@ int tfi_integrate_noalloc(tfi_handle h, const void* f, const void* F, int64_t d,
         return run_forward_noalloc<double>(h, (const double*)f, (const double*)F, (int32_t)d,
                                            (double*)out, st);
     return fail(TFI_ERR_DTYPE, "tfi_integrate_noalloc: unknown dtype");
+}
+
+int tfi_set_scatter(tfi_handle h, int32_t method) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (method < -1 || method > 1) return fail(TFI_ERR_ARG, "tfi_set_scatter: method must be -1, 0 or 1");
+    if (h->scatter_pick != method) {
+        TFI_HIP(hipDeviceSynchronize());
+        h->drop_graphs();  // they hold the other strategy's launches
+        h->scatter_pick = method;
+    }
+    return TFI_OK;
 }
 
 int tfi_set_fft_cost(tfi_handle h, float cost) {
@@ -2694,6 +2974,17 @@ int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int wi
         }
     }
     if ((rc = reassign_methods(h, best))) return rc;
+    // the cell-sum strategy at this width: pieces or levels, the faster pass
+    float sms[2] = {1e30f, 1e30f};
+    for (int m = 0; m < 2 && !rc; ++m) {
+        h->scatter_pick = m;
+        rc = dtype == TFI_F32 ? time_pass<float>(h, (const float*)f, (int32_t)d, st, 5,
+                                                 with_backward != 0, &sms[m])
+                              : time_pass<double>(h, (const double*)f, (int32_t)d, st, 5,
+                                                  with_backward != 0, &sms[m]);
+    }
+    h->scatter_pick = sms[0] <= sms[1] ? 0 : 1;
+    if (rc) return rc;
     *best_cost = best;
     return TFI_OK;
 }

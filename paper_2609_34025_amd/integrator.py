@@ -170,6 +170,12 @@ class TreeIntegrator:
         """Apply a direct-vs-FFT cost constant without timing."""
         _lib.check(_lib.load().tfi_set_fft_cost(self._h, float(cost)))
 
+    def set_scatter(self, method):
+        """Strategy of the cell sums: 'pieces', 'levels' or 'auto' (by
+        width; ``autotune`` times both and keeps the faster)."""
+        m = {"auto": -1, "pieces": 0, "levels": 1}[method]
+        _lib.check(_lib.load().tfi_set_scatter(self._h, m))
+
     def profile(self, enable=True):
         """Record per-stage HIP events and algorithmic bytes from now on."""
         _lib.check(_lib.load().tfi_profile(self._h, 1 if enable else 0))

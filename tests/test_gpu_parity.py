@@ -365,3 +365,43 @@ def test_autotune_keeps_results_and_kernel_length(tmp_path):
     assert relerr(dF.cpu().numpy()[rows], ref_dF) <= 1e-4
     ref_df = oracle.pair_hist(p, w, G, F.astype(np.float64), K)
     assert relerr(df.cpu().numpy(), ref_df) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype,d,leaf", [(torch.float64, 3, 32), (torch.float64, 16, 64),
+                                          (torch.float32, 16, 64), (torch.float32, 5, 1),
+                                          (torch.float32, 64, 32)])
+def test_cell_sum_pieces(dtype, d, leaf):
+    """The cell sums of large calls come from several pieces (workgroups)
+    whose cut cells a second launch adds in piece order: a weighted random
+    tree (its root call spans many pieces) and a broom (one depth class of
+    thousands of bristles, a b-cell cut across pieces) against the oracle;
+    graph replays reproduce the result bit for bit."""
+    rng = np.random.default_rng(17 + d + leaf)
+    p1, _ = S.random_recursive(6000, rng)
+    p2, w2 = S.broom(1500)
+    p, w, _ = S.forest([(p1, S.uniform_weights(p1, 1, 8, rng)), (p2, w2)])
+    F = rng.standard_normal((len(p), d))
+    ftab = lambda K: np.exp(-0.04 * np.arange(K)) + 0.3 / (1.0 + np.arange(K)) ** 2
+    t = TreeIntegrator(p, w, device=0, leaf_max=leaf)
+    K = t.kernel_length
+    f = torch.tensor(ftab(K), dtype=dtype, device=DEV)
+    Ft = torch.tensor(F, dtype=dtype, device=DEV)
+    t.set_scatter("pieces")
+    t.profile(True)
+    y = t.integrate(f, Ft)
+    torch.cuda.synchronize()
+    st = t.profile_report()
+    t.profile(False)
+    assert "scatter" in st and "scatter_combine" in st, st
+    out = torch.empty_like(Ft)
+    for _ in range(3):
+        t.integrate(f, Ft, out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, y)
+    t.set_scatter("levels")
+    y1 = t.integrate(f, Ft)
+    torch.cuda.synchronize()
+    ref = oracle.integrate(p, w, ftab(K), F)
+    e, e1 = relerr(y.cpu().numpy(), ref), relerr(y1.cpu().numpy(), ref)
+    print(f"cell-sum pieces {dtype} d={d} leaf={leaf}: {e:.2e} (levels {e1:.2e})", flush=True)
+    assert e <= TOL[dtype] and e1 <= TOL[dtype], (e, e1)
