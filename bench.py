@@ -124,6 +124,10 @@ def main():
                     help="(default) leave the family sweep out")
     ap.add_argument("--families-only", action="store_true",
                     help="run only the backbone-policy family sweep")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the FP64 2000-vertex, Sinkhorn and 2M-vertex configurations")
+    ap.add_argument("--configs-only", action="store_true",
+                    help="run only those three configurations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -144,6 +148,10 @@ def main():
         return
     if args.families_only:
         print(json.dumps({"family_sweep": family_sweep(args)}), flush=True)
+        return
+    if args.configs_only:
+        print(json.dumps({"small_fp64": small_fp64(args), "sinkhorn": sinkhorn_sphere(args),
+                          "large": large_trees(args)}), flush=True)
         return
     W = S.workload("rrt100k")
     p, w, F = W["parent"], W["weight"], W["F"]
@@ -296,6 +304,9 @@ def main():
 
     batched = None if args.no_batched else batched_fwd_bwd(args, value)
     wide = None if args.no_wide else wide_channel(args)
+    small = sink = large = None
+    if not args.no_configs:
+        small, sink, large = small_fp64(args), sinkhorn_sphere(args), large_trees(args)
     families = family_sweep(args) if (args.families and not args.no_families) else None
 
     rec = {
@@ -321,6 +332,10 @@ def main():
         "cpu_baseline": cpu,
         "batched_fwd_bwd": batched,
         "wide_channel": wide,
+        "k3_roofline": (wide or {}).get("k3_roofline"),
+        "small_fp64": small,
+        "sinkhorn": sink,
+        "large": large,
         "family_sweep": families,
         "stages": stages,
     }
@@ -491,6 +506,7 @@ def wide_channel(args):
         cases += [("random", 256), ("comb", 256), ("fishbone", 256)]
     out_cases = []
     roofline = None
+    k3 = {}
     for kind, side in cases:
         W = S.workload("attn", tree=kind, side=side)
         p, w = W["parent"], W["weight"]
@@ -540,6 +556,11 @@ def wide_channel(args):
         if kind == "serpentine" and side == 512:
             dom = max(stages, key=lambda k: stages[k]["ms"])
             roofline = stage_roofline(dom, stages[dom], "f32", "serpentine512")
+        # the FFT cross-interaction stages of this case (1-D convolution,
+        # 2-D LDS and global passes): algorithmic bytes over event time
+        for k, sd in stages.items():
+            if k.startswith("fft") and sd["ms"] > 0:
+                k3[f"{kind}{side}/{k}"] = stage_roofline(k, sd, "f32", f"{kind}{side}")
         del tfi, F, y
         torch.cuda.empty_cache()
     return {"unit": "vertex*channels/s (forward, one integration)", "dtype": "f32",
@@ -547,8 +568,199 @@ def wide_channel(args):
                        "mask f = exp(u d^2 + v d + w), u=-1e-5, v=-0.01, w=0.5",
             "parity": "32 sampled rows x 64 sampled channels vs FP64 oracle",
             "paper_cpu_s": "32-core CPU, context only",
-            "cases": out_cases, "roofline": roofline}
+            "cases": out_cases, "roofline": roofline, "k3_roofline": k3}
 
+
+
+def _timed(call, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        call()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def _stages(tfi, call):
+    import torch
+    tfi.profile(True)
+    call()
+    torch.cuda.synchronize()
+    tfi.profile(False)
+    return tfi.profile_report()
+
+
+def small_fp64(args):
+    """Plain forward of the small configuration: random recursive tree
+    N = 2000 (parent of i uniform in [0, i)), weights U{1..4}, F[N x 4] FP64
+    ~ N(0, 1), f(d) = exp(-0.1 d). Timed as graph replays into one output;
+    parity on every row against the FP64 oracle (bar 1e-10)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+
+    dev = torch.device("cuda", 0)
+    W = S.workload("small")
+    p, w, F = W["parent"], W["weight"], W["F"]
+    n, d = F.shape
+    tfi = TreeIntegrator(p, w, device=0)
+    K = tfi.kernel_length
+    tab = W["kernels"][0][1](K)
+    f = torch.tensor(tab, dtype=torch.float64, device=dev)
+    Ft = torch.tensor(F, device=dev)
+    cost = tfi.autotune(f, d)
+    out = torch.empty_like(Ft)
+    ms = _timed(lambda: tfi.integrate(f, Ft, out=out), max(20, args.steps))
+    stages = _stages(tfi, lambda: tfi.integrate(f, Ft, out=out))
+    tfi.integrate(f, Ft, out=out)
+    ref = oracle.integrate(p, w, tab, F)
+    err = float(np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref))
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    log(f"small fp64: N={n} d={d} {ms:.4f} ms/integration, parity {err:.2e}")
+    return {"workload": "plain forward, random recursive tree N=2000, weights U{1..4}, "
+                        "F[N x 4] fp64 ~ N(0,1), f = exp(-0.1 d)",
+            "dtype": "f64", "N": n, "d": d, "ms": round(ms, 5),
+            "value": n * d / (ms * 1e-3), "unit": "vertex*channels/s", "fft_cost": cost,
+            "parity": {"rows": "all", "rel_err": err, "ok": err <= 1e-10},
+            "roofline": stage_roofline(dom, stages[dom], "f64")}
+
+
+def sinkhorn_sphere(args):
+    """Iterated solve: Sinkhorn scaling on the minimum spanning tree of the
+    symmetrised 8-NN graph of 50,000 points uniform on the sphere, lengths
+    quantised to 1/64, f(k) = exp(-k / 3.2) (exp(-d / 0.05)), marginals
+    ~ Dirichlet(1). 200 iterations of two FP32 products each are timed
+    (no residual checks inside the timed loop); then every product of a
+    second 200-iteration run is checked against the FP64 exp-kernel tree
+    recursion applied to the same rounded input vector."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+    from paper_2609_34025_amd.sinkhorn import sinkhorn
+
+    dev = torch.device("cuda", 0)
+    W = S.workload("sphere50k")
+    p, w = W["parent"], W["weight"]
+    n = len(p)
+    tfi = TreeIntegrator(p, w, device=0)
+    K = tfi.kernel_length
+    lam = float(np.exp(-1.0 / 3.2))
+    f = torch.tensor(lam ** np.arange(K), dtype=torch.float32, device=dev)
+    a = torch.tensor(W["a"], device=dev)
+    b = torch.tensor(W["b"], device=dev)
+    cost = tfi.autotune(f, 1)
+    iters = 200
+    sinkhorn(tfi, f, a, b, iters=5, check_every=10 ** 9)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, v, _ = sinkhorn(tfi, f, a, b, iters=iters, check_every=10 ** 9)
+    torch.cuda.synchronize()
+    ms_iter = 1e3 * (time.perf_counter() - t0) / iters
+    x = torch.rand(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    ms_prod = _timed(lambda: tfi.integrate(f, x, out=y), 200)
+    stages = _stages(tfi, lambda: tfi.integrate(f, x, out=y))
+    errs = []
+
+    def check(xin, yv):
+        ref = oracle.expdp(p, w, [1.0], [lam], xin.double().cpu().numpy())
+        errs.append(float(np.linalg.norm(yv.double().cpu().numpy() - ref) / np.linalg.norm(ref)))
+
+    _, _, res = sinkhorn(tfi, f, a, b, iters=iters, on_product=check)
+    dom = max(stages, key=lambda k: stages[k]["ms"])
+    log(f"sinkhorn: N={n} {ms_iter:.4f} ms/iteration ({ms_prod:.4f} ms/product), "
+        f"{len(errs)} products checked, max rel err {max(errs):.2e}")
+    return {"workload": "200 Sinkhorn iterations (2 fp32 products each) on the MST of the 8-NN "
+                        "graph of 50000 points on the sphere, lengths in units of 1/64, "
+                        "f(k) = exp(-k/3.2), marginals Dirichlet(1)",
+            "N": n, "d": 1, "iterations": iters, "ms_per_iteration": round(ms_iter, 5),
+            "ms_per_product": round(ms_prod, 5), "value": n / (ms_prod * 1e-3),
+            "unit": "vertex*channels/s (one product)", "fft_cost": cost,
+            "parity": {"products": len(errs), "max_rel_err": max(errs),
+                       "ok": max(errs) <= 1e-4,
+                       "oracle": "fp64 exp-kernel tree recursion on the same fp32 input"},
+            "residual_first_last": [res[0][1], res[-1][1]],
+            "roofline": stage_roofline(dom, stages[dom], "f32")}
+
+
+def large_trees(args):
+    """Large forward + adjoint: N = 2,000,000 as a caterpillar (spine of
+    N/4, three leaves per spine vertex) and as a binary random recursive
+    tree, weights U{1..8}, F[N x 32] FP32 ~ N(0, 1), f(d) = exp(-0.01 d),
+    gout ~ N(0, 1), under a 64 GB device-memory budget (kernel spectra are
+    formed again in the adjoint, nothing is kept between the passes).
+    Forward and dF are timed; parity on 512 sampled rows against the BFS
+    oracle and on all rows against the exp-kernel tree recursion."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+
+    dev = torch.device("cuda", 0)
+    budget = 64 << 30
+    out_cases = []
+    for name in ("cater2m", "binary2m"):
+        t0 = time.perf_counter()
+        W = S.workload(name)
+        p, w, F = W["parent"], W["weight"], W["F"]
+        n, d = F.shape
+        tfi = TreeIntegrator(p, w, device=0, memory_budget=budget)
+        build_s = time.perf_counter() - t0
+        K = tfi.kernel_length
+        lam = float(np.exp(-0.01))
+        tab = lam ** np.arange(K)
+        f = torch.tensor(tab, dtype=torch.float32, device=dev)
+        Ft = torch.tensor(F, device=dev)
+        G = torch.tensor(np.random.default_rng(55).standard_normal(F.shape), dtype=torch.float32,
+                         device=dev)
+        out = torch.empty_like(Ft)
+        ms_f = _timed(lambda: tfi.integrate(f, Ft, out=out), 3, warm=1)
+        dF = {}
+
+        def bwd():
+            dF["x"], _ = tfi.backward(f, Ft, G, need_df=False)
+
+        ms_b = _timed(bwd, 3, warm=1)
+        stages = _stages(tfi, lambda: tfi.integrate(f, Ft, out=out))
+        tfi.integrate(f, Ft, out=out)
+        bwd()
+        torch.cuda.synchronize()
+        y, yd = out.cpu().numpy(), dF["x"].cpu().numpy()
+        Fd, Gd = F.astype(np.float64), G.cpu().numpy().astype(np.float64)
+        rows = np.random.default_rng(5).choice(n, 512, replace=False)
+        errs = {"fwd_rows": oracle.integrate(p, w, tab, Fd, rows=rows),
+                "dF_rows": oracle.integrate(p, w, tab, Gd, rows=rows)}
+        errs = {"fwd_rows": float(np.linalg.norm(y[rows] - errs["fwd_rows"]) /
+                                  np.linalg.norm(errs["fwd_rows"])),
+                "dF_rows": float(np.linalg.norm(yd[rows] - errs["dF_rows"]) /
+                                 np.linalg.norm(errs["dF_rows"]))}
+        r = oracle.expdp(p, w, [1.0], [lam], Fd)
+        errs["fwd_all"] = float(np.linalg.norm(y - r) / np.linalg.norm(r))
+        r = oracle.expdp(p, w, [1.0], [lam], Gd)
+        errs["dF_all"] = float(np.linalg.norm(yd - r) / np.linalg.norm(r))
+        st = tfi.stats()
+        dom = max(stages, key=lambda k: stages[k]["ms"])
+        rec = {"tree": name, "N": n, "d": d, "build_s": round(build_s, 2),
+               "ms_fwd": round(ms_f, 3), "ms_bwd_dF": round(ms_b, 3),
+               "value": 2 * n * d / ((ms_f + ms_b) * 1e-3),
+               "device_GiB": round(st["device_bytes"] / 2 ** 30, 2),
+               "parity": {"rel_err": errs, "ok": max(errs.values()) <= 1e-4},
+               "roofline": stage_roofline(dom, stages[dom], "f32")}
+        out_cases.append(rec)
+        log(f"large[{name}] N={n} d={d}: fwd {ms_f:.2f} ms, bwd dF {ms_b:.2f} ms, "
+            f"{rec['device_GiB']} GiB, parity {errs}")
+        del tfi, Ft, G, out, dF
+        torch.cuda.empty_cache()
+    return {"unit": "vertex*channels/s (forward + adjoint dF)", "dtype": "f32",
+            "budget_bytes": budget, "cases": out_cases}
 
 
 # The paper's CPU timings (ms) of the scalar forward with f(d) = 1/(1+d) at

@@ -8,7 +8,9 @@
 // attention-width appendix). Beyond LDS it runs as a four-step transform in
 // three kernels over a channel-tiled buffer
 //     buf[slot][i][c],  slot = job * ntiles + tile,  c < TC channel pairs,
-// so that every access moves TC contiguous complex values:
+// so that every access moves TC contiguous complex values. When the buffer
+// of all tiles would exceed kConvGroupBytes, the three kernels run on groups
+// of tiles in turn (the buffer then holds one group):
 //   k_conv1d_hi<false>  gathers the job's cells (TC channel pairs each) at the
 //                       points i = e 2^lgL + l of one low value l and runs the
 //                       DIF stages of the high bits [lgL, lg);
@@ -52,6 +54,7 @@
 namespace tfi {
 
 constexpr int kC1MaxR = 5;      // register bits per phase (32 points per thread)
+constexpr int64_t kConvGroupBytes = (int64_t)2 << 30;  // buffer of one tile group
 constexpr int kC1Pad = 8;       // complex values of padding per LDS row
 
 // exp(-2 pi i m / 32), m < 16
@@ -135,8 +138,10 @@ __device__ __forceinline__ int lds_at(int a, int b, int c, int RB) {
     return a * ((TC << RB) + kC1Pad) + b * TC + c;
 }
 
-// High-bit passes. Grid: (2^lgL low values l, tiles, jobs of the chunk);
-// block: 2^RB x TC threads, RB = lgB/2, lgB = lg - lgL.
+// High-bit passes. Grid: (2^lgL low values l, tiles of the group, jobs of
+// the chunk); block: 2^RB x TC threads, RB = lgB/2, lgB = lg - lgL. The
+// group's tiles start at tile0 (channel pairs from tile0 TC); its slots in
+// buf are job x (tiles of the group) + tile.
 // INV = false: gather the cells' channel pairs [tile TC, tile TC + TC) from
 // src (rows of d channels) at the points of low value l, DIF stages of bits
 // [lgL, lg), store to buf.
@@ -146,7 +151,7 @@ template <typename T, int TC, bool INV, int LGB = 0>
 __global__ void __launch_bounds__(512)
 k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restrict__ map,
             int64_t mstride, int32_t d, const T* __restrict__ src, T* __restrict__ dst,
-            cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int lgtw) {
+            cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int lgtw, int32_t tile0) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int lgB = LGB ? LGB : lg - lgL, RB = lgB / 2, RA = lgB - RB;
@@ -157,7 +162,7 @@ k_conv1d_hi(int lg, int lgL, int32_t cmax, int reflect, const int32_t* __restric
     cpx<T>* sb = buf + (slot << lg) * TC;
     const int c = threadIdx.x % TC;
     const int b = threadIdx.x / TC;  // phase A: low bits; phase B: first high value
-    const int32_t ch = 2 * (blockIdx.y * TC + c);
+    const int32_t ch = 2 * ((tile0 + (int32_t)blockIdx.y) * TC + c);
     const bool has0 = ch < d, has1 = ch + 1 < d;
     // rows of even length in an aligned buffer: one access per channel pair
     const T* io = INV ? dst : src;

@@ -1247,6 +1247,23 @@ int64_t fft_job_bytes(const Bucket& b, int32_t d) {
     return pairs * b.P() * (int64_t)sizeof(tfi::cpx<T>);
 }
 
+// Work buffer a bucket needs: for the channel-tiled 1-D convolution, the
+// slots of all jobs and tiles, or of one group of tiles of about
+// kConvGroupBytes when that is less (the passes then run group by group);
+// else chunks of at most 2 GiB, or one job's slots when a job alone is
+// larger.
+template <typename T>
+size_t fft_buf_bytes(const Bucket& b, int32_t d) {
+    const int64_t one_job = fft_job_bytes<T>(b, d);
+    const int64_t all = one_job * b.njobs();
+    if (const int tc = conv1d_tc<T>(b, d)) {
+        const int64_t slot = (int64_t)tc * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+        const int64_t group = std::max<int64_t>(1, tfi::kConvGroupBytes / slot) * slot;
+        return (size_t)std::min(all, group);
+    }
+    return (size_t)std::max(one_job, std::min(all, (int64_t)2 << 30));
+}
+
 template <typename T, int TC>
 void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t d, const T* val,
                       T* g, const tfi::cpx<T>* spec, const tfi::cpx<T>* tw, tfi::cpx<T>* buf,
@@ -1255,9 +1272,13 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     (void)conv1d_tc<T>(b, d, &lgL);
     const int lg = b.lg1 + b.lg2, lgH = lg - lgL;
     const int32_t ntiles = ((d + 1) / 2 + TC - 1) / TC;
-    const int64_t job_bytes = (int64_t)ntiles * TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
-    const int64_t jpc =
-        std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)buf_bytes / job_bytes));
+    const int64_t slot_bytes = (int64_t)TC * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+    const int64_t nslots = std::max<int64_t>(1, (int64_t)buf_bytes / slot_bytes);
+    // tiles per group: all of them when the buffer holds a job's slots, else
+    // as many as it holds (one job per group then)
+    const int32_t gt = (int32_t)std::min<int64_t>(ntiles, nslots);
+    const int64_t jpc = gt == ntiles ? std::max<int64_t>(1, std::min<int64_t>(65535, nslots / ntiles))
+                                     : 1;
     // LDS block: 2^RA rows of (2^RB x TC + pad) complex; 2^RB x TC threads
     const int hRB = lgH / 2, hRA = lgH - hRB, lRB = lgL / 2, lRA = lgL - lRB;
     const unsigned lds_hi = (unsigned)(((int64_t)1 << hRA) * ((TC << hRB) + tfi::kC1Pad) *
@@ -1272,7 +1293,7 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     const unsigned thr_hi = (unsigned)(TC << hRB), thr_lo = (unsigned)(lo_cw << lRB);
     // kernel instances: the fixed split where one is compiled, else runtime
     using HiK = void (*)(int, int, int32_t, int, const int32_t*, int64_t, int32_t, const T*, T*,
-                         tfi::cpx<T>*, const tfi::cpx<T>*, int);
+                         tfi::cpx<T>*, const tfi::cpx<T>*, int, int32_t);
     using LoK = void (*)(int, int, tfi::cpx<T>*, const tfi::cpx<T>*, const tfi::cpx<T>*, int);
     HiK hi_fwd = tfi::k_conv1d_hi<T, TC, false, 0>, hi_inv = tfi::k_conv1d_hi<T, TC, true, 0>;
     LoK lo = tfi::k_conv1d_lo<T, TC, 0>;
@@ -1294,15 +1315,17 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
         const int32_t* map = bmap + j0 * b.mstride;
-        hipLaunchKernelGGL(hi_fwd, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
-                           dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, (int)b.reflect, map,
-                           b.mstride, d, val, (T*)nullptr, buf, tw, h->lgtw);
-        hipLaunchKernelGGL(lo, dim3((1u << lgH) * lo_parts, (unsigned)ntiles, (unsigned)nj),
-                           dim3(thr_lo),
-                           lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
-        hipLaunchKernelGGL(hi_inv, dim3(1u << lgL, (unsigned)ntiles, (unsigned)nj),
-                           dim3(thr_hi), lds_hi, st, lg, lgL, b.cmax, 0, map, b.mstride, d,
-                           (const T*)nullptr, g, buf, tw, h->lgtw);
+        for (int32_t t0 = 0; t0 < ntiles; t0 += gt) {
+            const unsigned nt = (unsigned)std::min(gt, ntiles - t0);
+            hipLaunchKernelGGL(hi_fwd, dim3(1u << lgL, nt, (unsigned)nj), dim3(thr_hi), lds_hi, st,
+                               lg, lgL, b.cmax, (int)b.reflect, map, b.mstride, d, val, (T*)nullptr,
+                               buf, tw, h->lgtw, t0);
+            hipLaunchKernelGGL(lo, dim3((1u << lgH) * lo_parts, nt, (unsigned)nj), dim3(thr_lo),
+                               lds_lo, st, lg, lgL, buf, spec + b.spec_off, tw, h->lgtw);
+            hipLaunchKernelGGL(hi_inv, dim3(1u << lgL, nt, (unsigned)nj), dim3(thr_hi), lds_hi, st,
+                               lg, lgL, b.cmax, 0, map, b.mstride, d, (const T*)nullptr, g, buf, tw,
+                               h->lgtw, t0);
+        }
     }
 }
 
@@ -1403,12 +1426,7 @@ WorkSizes forward_sizes(const tfi_plan* h, int32_t d, bool general = false, int 
             z.part = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     }
     z.spec = (size_t)nk * std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>);
-    for (int bi : h->global_b[ti]) {
-        const Bucket& b = h->buckets[bi];
-        const size_t one_job = (size_t)fft_job_bytes<T>(b, d);
-        const size_t all = one_job * (size_t)b.njobs();
-        z.fft = std::max(z.fft, std::max(one_job, std::min(all, (size_t)2 << 30)));
-    }
+    for (int bi : h->global_b[ti]) z.fft = std::max(z.fft, fft_buf_bytes<T>(h->buckets[bi], d));
     return z;
 }
 
