@@ -89,7 +89,13 @@ typedef struct {
     int32_t table_method;        /* 0 = per-job choice, 1 = force direct
                                     sums, 2 = force FFT for every table    */
     uint64_t memory_budget_bytes;/* cap on device bytes held by the handle
-                                    and its per-call scratch; 0 = none     */
+                                    and its per-call scratch; 0 = none.
+                                    tfi_integrate and tfi_backward (without
+                                    kept cell sums) split a call whose
+                                    scratch would not fit into tiles of
+                                    channels that do, each a full pass;
+                                    TFI_ERR_BUDGET when not even one
+                                    channel fits                           */
     int32_t no_graphs;           /* 1 = launch kernels directly instead of
                                     replaying captured hipGraphs           */
     float fft_cost;              /* per-job rule: direct sums if

@@ -952,6 +952,21 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
     if (tid < n) p[tid] = v;
 }
 
+// Channel tile [c0, c0 + w) of an [N x d] matrix into a dense [N x w] one
+// (PUT = false), or back (PUT = true).
+template <typename T, bool PUT>
+__global__ void k_cols(const T* __restrict__ src, T* __restrict__ dst, int64_t N, int32_t d,
+                       int32_t c0, int32_t w) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= N * w) return;
+    const int64_t v = tid / w;
+    const int32_t c = (int32_t)(tid - v * w);
+    if (PUT)
+        dst[v * d + c0 + c] = src[tid];
+    else
+        dst[tid] = src[v * d + c0 + c];
+}
+
 }  // namespace tfi
 
 namespace tfi {

@@ -199,6 +199,9 @@ struct tfi_plan {
     // exponential sums: per-term power table and f table, sweep scratch,
     // leaf pair histogram (FP64)
     DeviceBuf expw[2], exps[2], hleaf;
+    // channel tiles of a call over the memory budget: the tile of F (and of
+    // gout) and of the result
+    DeviceBuf tin[2], tgin[2], tout[2];
     // table jobs for the sweep evaluator: ids sorted by size, cell offsets,
     // first scratch position (-1: one backbone position), signs
     int32_t *d_ej1 = nullptr, *d_ejm = nullptr, *d_jsign = nullptr;
@@ -287,8 +290,7 @@ struct tfi_plan {
         for (void* p : mallocs) (void)hipFree(p);
         for (int t = 0; t < 2; ++t)
             for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t], &part[t],
-                                 &partg[t],
-                                 &expw[t], &exps[t]})
+                                 &partg[t], &expw[t], &exps[t], &tin[t], &tgin[t], &tout[t]})
                 if (b->p) (void)hipFree(b->p);
         if (hleaf.p) (void)hipFree(hleaf.p);
         if (mrows.p) (void)hipFree(mrows.p);
@@ -330,6 +332,36 @@ struct tfi_plan {
         if (!src.empty())
             TFI_HIP(hipMemcpy(p, src.data(), src.size() * sizeof(V), hipMemcpyHostToDevice));
         *dst = (V*)p;
+        return TFI_OK;
+    }
+
+    // Every per-call scratch buffer, and their bytes.
+    std::vector<DeviceBuf*> scratch_bufs() {
+        std::vector<DeviceBuf*> v;
+        for (int t = 0; t < 2; ++t)
+            for (DeviceBuf* b : {&val[t], &g[t], &spec[t], &fftbuf[t], &valg[t], &dfbuf[t], &part[t],
+                                 &partg[t], &expw[t], &exps[t], &tin[t], &tgin[t], &tout[t]})
+                v.push_back(b);
+        v.push_back(&hleaf);
+        v.push_back(&mrows);
+        return v;
+    }
+    size_t scratch_bytes() {
+        size_t n = 0;
+        for (DeviceBuf* b : scratch_bufs()) n += b->p ? b->bytes : 0;
+        return n;
+    }
+    // Release every scratch buffer (after the device drained).
+    int free_scratch() {
+        TFI_HIP(hipDeviceSynchronize());
+        drop_graphs();
+        for (DeviceBuf* b : scratch_bufs())
+            if (b->p) {
+                (void)hipFree(b->p);
+                dev_bytes -= b->bytes;
+                b->p = nullptr;
+                b->bytes = 0;
+            }
         return TFI_OK;
     }
 
@@ -1902,7 +1934,7 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
 template <typename T>
 void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
                       double* df, hipStream_t s0, hipStream_t s1, hipStream_t s2,
-                      const T* cells = nullptr) {
+                      const T* cells = nullptr, bool zero_df = true) {
     const Work w = handle_work<T>(h);
     if (!df) {  // dF alone is the forward applied to gout
         if (dF) enqueue_forward<T>(h, f, gout, d, dF, s0, s1, s2, w);
@@ -1913,7 +1945,7 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     T* val = (T*)w.val;
     T* valg = (T*)h->valg[ti].p;
     T* g = (T*)w.g;
-    if (df)
+    if (df && zero_df)
         hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
                            s0, df, (int64_t)p.kernel_len);
     fork3(h, s0, s1, s2);
@@ -1941,34 +1973,45 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     if (dF) enq_gather<T>(h, d, g, dF, s0);
 }
 
+// Bytes of the adjoint's scratch beyond the forward's when df is wanted:
+// the cell sums of gout (and their partial rows), and the df FFT slots.
+struct DfSizes {
+    size_t valg = 0, partg = 0, dfbuf = 0;
+};
+
 template <typename T>
-int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
-    int rc = prepare_forward<T>(h, d, need_df);
-    if (rc) return rc;
-    if (!need_df) return TFI_OK;  // dF alone runs the forward on gout
-    const int ti = sizeof(T) == 8 ? 1 : 0;
-    const size_t rowbytes = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
-    if ((rc = h->ensure(h->valg[ti], rowbytes))) return rc;
-    if (scatter_pieces(h, d) &&
-        (rc = h->ensure(h->partg[ti], (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d *
-                                          sizeof(T))))
-        return rc;
+DfSizes df_sizes(const tfi_plan* h, int32_t d) {
+    DfSizes z;
+    z.valg = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    if (scatter_pieces(h, d))
+        z.partg = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     const int32_t npairs = (d + 1) / 2;
     const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
-    size_t want = 0;
     for (const Bucket& b : h->buckets) {
         const int64_t P = b.P();
         if (df_lds_bytes<T>(h, b)) {
-            want = std::max(want, (size_t)(b.njobs() * groups * P * sizeof(tfi::cpx<T>)));
+            z.dfbuf = std::max(z.dfbuf, (size_t)(b.njobs() * groups * P * sizeof(tfi::cpx<T>)));
             continue;
         }
         const int64_t per_job = (2 * (int64_t)npairs + 1) * P * (int64_t)sizeof(tfi::cpx<T>);
         const int64_t cap = (int64_t)2 << 30;
         const int64_t jpc = std::max<int64_t>(
             1, std::min<int64_t>(cap / per_job, 65535 / std::max<int32_t>(npairs, 1)));
-        want = std::max(want, (size_t)(std::min(jpc, b.njobs()) * per_job));
+        z.dfbuf = std::max(z.dfbuf, (size_t)(std::min(jpc, b.njobs()) * per_job));
     }
-    if (want && (rc = h->ensure(h->dfbuf[ti], want))) return rc;
+    return z;
+}
+
+template <typename T>
+int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
+    int rc = prepare_forward<T>(h, d, need_df);
+    if (rc) return rc;
+    if (!need_df) return TFI_OK;  // dF alone runs the forward on gout
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const DfSizes z = df_sizes<T>(h, d);
+    if ((rc = h->ensure(h->valg[ti], z.valg))) return rc;
+    if (z.partg && (rc = h->ensure(h->partg[ti], z.partg))) return rc;
+    if (z.dfbuf && (rc = h->ensure(h->dfbuf[ti], z.dfbuf))) return rc;
     return TFI_OK;
 }
 
@@ -2134,12 +2177,13 @@ int run_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, int32_
 
 template <typename T>
 int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
-                 double* df, hipStream_t st, const T* cells = nullptr) {
+                 double* df, hipStream_t st, const T* cells = nullptr, bool zero_df = true) {
     int rc = prepare_backward<T>(h, d, df != nullptr);
     if (rc) return rc;
     GraphKey key;
     key.kind = 2;
     key.dtype = sizeof(T) == 8;
+    key.n = zero_df ? 0 : 1;
     key.d = d;
     key.p[0] = f;
     key.p[1] = F;
@@ -2148,8 +2192,118 @@ int run_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, 
     key.p[4] = df;
     key.p[5] = cells;
     return run_dag(h, key, st, [&](hipStream_t a, hipStream_t b, hipStream_t c) {
-        enqueue_backward<T>(h, f, F, gout, d, dF, df, a, b, c, cells);
+        enqueue_backward<T>(h, f, F, gout, d, dF, df, a, b, c, cells, zero_df);
     });
+}
+
+// ---- channel tiles under the memory budget ----------------------------------
+// Channels are independent, so a call whose scratch would not fit the
+// handle's budget runs on tiles of the channels, each tile a full pass
+// (kernel spectra formed again, no state kept between tiles) on a dense
+// copy of its columns; df adds up over the tiles. Returns the widest tile
+// that fits: d when the whole call fits, 0 when not even one channel does.
+template <typename T>
+int32_t budget_tile(tfi_plan* h, int32_t d, bool bwd, bool need_df) {
+    if (!h->budget) return d;
+    const size_t base = h->dev_bytes - h->scratch_bytes();
+    const size_t N = (size_t)h->plan.N;
+    auto need = [&](int32_t w, bool tiled) {
+        const WorkSizes z = forward_sizes<T>(h, w, need_df);
+        size_t n = z.val + z.g + z.spec + z.fft + z.part + 5 * 16;
+        if (need_df) {
+            const DfSizes e = df_sizes<T>(h, w);
+            n += e.valg + e.partg + e.dfbuf + 3 * 16;
+        }
+        if (tiled) n += (bwd ? 3 : 2) * N * (size_t)w * sizeof(T);  // tiles in and out
+        return base + n;
+    };
+    if (need(d, false) <= h->budget) return d;
+    int32_t lo = 0, hi = d;  // need(lo) fits (lo = 0 trivially), need(hi) does not
+    while (hi - lo > 1) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (need(mid, true) <= h->budget) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Run fn; if it stops at the budget (before launching anything) because
+// buffers of other passes are held, release every scratch buffer and run it
+// once more.
+template <typename Fn>
+int budget_retry(tfi_plan* h, Fn fn) {
+    int rc = fn();
+    if (rc != TFI_ERR_BUDGET || !h->budget) return rc;
+    if ((rc = h->free_scratch())) return rc;
+    rc = fn();
+    if (rc == TFI_OK) g_err.clear();
+    return rc;
+}
+
+// The forward (tfi_integrate) on channel tiles of width dt < d.
+template <typename T>
+int run_forward_tiled(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hipStream_t st,
+                      int32_t dt) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const size_t tb = (size_t)h->plan.N * dt * sizeof(T);
+    int rc = budget_retry(h, [&]() {
+        int r = h->ensure(h->tin[ti], tb);
+        if (!r) r = h->ensure(h->tout[ti], tb);
+        if (!r) r = prepare_forward<T>(h, dt);
+        return r;
+    });
+    if (rc) return rc;
+    T* tin = (T*)h->tin[ti].p;
+    T* tout = (T*)h->tout[ti].p;
+    const int64_t N = h->plan.N;
+    for (int32_t c0 = 0; c0 < d && !rc; c0 += dt) {
+        const int32_t w = std::min(dt, d - c0);
+        hipLaunchKernelGGL((tfi::k_cols<T, false>), dim3(blocks_for(N * w)), dim3(kThreads), 0, st,
+                           F, tin, N, d, c0, w);
+        rc = run_forward<T>(h, f, tin, w, tout, st);
+        if (!rc)
+            hipLaunchKernelGGL((tfi::k_cols<T, true>), dim3(blocks_for(N * w)), dim3(kThreads), 0,
+                               st, (const T*)tout, out, N, d, c0, w);
+    }
+    if (rc) return rc;
+    TFI_HIP(hipGetLastError());
+    return TFI_OK;
+}
+
+// The adjoint (tfi_backward) on channel tiles of width dt < d: dF tile by
+// tile, df summed over the tiles (cleared by the first).
+template <typename T>
+int run_backward_tiled(tfi_plan* h, const T* f, const T* F, const T* gout, int32_t d, T* dF,
+                       double* df, hipStream_t st, int32_t dt) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const size_t tb = (size_t)h->plan.N * dt * sizeof(T);
+    int rc = budget_retry(h, [&]() {
+        int r = h->ensure(h->tin[ti], tb);
+        if (!r) r = h->ensure(h->tgin[ti], tb);
+        if (!r) r = h->ensure(h->tout[ti], tb);
+        if (!r) r = prepare_backward<T>(h, dt, df != nullptr);
+        return r;
+    });
+    if (rc) return rc;
+    T* tin = (T*)h->tin[ti].p;
+    T* tg = (T*)h->tgin[ti].p;
+    T* tout = (T*)h->tout[ti].p;
+    const int64_t N = h->plan.N;
+    for (int32_t c0 = 0; c0 < d && !rc; c0 += dt) {
+        const int32_t w = std::min(dt, d - c0);
+        if (df)
+            hipLaunchKernelGGL((tfi::k_cols<T, false>), dim3(blocks_for(N * w)), dim3(kThreads), 0,
+                               st, F, tin, N, d, c0, w);
+        hipLaunchKernelGGL((tfi::k_cols<T, false>), dim3(blocks_for(N * w)), dim3(kThreads), 0, st,
+                           gout, tg, N, d, c0, w);
+        rc = run_backward<T>(h, f, tin, tg, w, dF ? tout : nullptr, df, st, nullptr, c0 == 0);
+        if (!rc && dF)
+            hipLaunchKernelGGL((tfi::k_cols<T, true>), dim3(blocks_for(N * w)), dim3(kThreads), 0,
+                               st, (const T*)tout, dF, N, d, c0, w);
+    }
+    if (rc) return rc;
+    TFI_HIP(hipGetLastError());
+    return TFI_OK;
 }
 
 
@@ -2559,6 +2713,20 @@ int64_t tfi_num_vertices(tfi_handle h) { return h ? h->plan.N : -1; }
 int64_t tfi_kernel_length(tfi_handle h) { return h ? h->plan.kernel_len : -1; }
 
 namespace {
+// A forward, on channel tiles when the whole call would exceed the budget
+// (not for the cell-keeping forward, whose cell sums span every channel).
+extern "C++" template <typename T>
+int forward_entry(const std::string& fs, tfi_plan* h, const T* f, const T* F, int32_t d, T* out,
+                  hipStream_t st, T* cells) {
+    if (!cells && h->budget) {
+        const int32_t dt = budget_tile<T>(h, d, false, false);
+        if (dt == 0)
+            return fail(TFI_ERR_BUDGET, fs + ": the budget does not hold one channel of the pass");
+        if (dt < d) return run_forward_tiled<T>(h, f, F, d, out, st, dt);
+    }
+    return budget_retry(h, [&]() { return run_forward<T>(h, f, F, d, out, st, cells); });
+}
+
 int integrate_impl(const char* fn, tfi_handle h, const void* f, const void* F, int64_t d,
                    tfi_dtype dtype, void* out, void* cells, void* stream) {
     g_err.clear();
@@ -2572,11 +2740,11 @@ int integrate_impl(const char* fn, tfi_handle h, const void* f, const void* F, i
         return fail(TFI_ERR_ARG, fs + ": cells must not alias F or out");
     hipStream_t st = (hipStream_t)stream;
     if (dtype == TFI_F32)
-        return run_forward<float>(h, (const float*)f, (const float*)F, (int32_t)d, (float*)out, st,
-                                  (float*)cells);
+        return forward_entry<float>(fs, h, (const float*)f, (const float*)F, (int32_t)d,
+                                    (float*)out, st, (float*)cells);
     if (dtype == TFI_F64)
-        return run_forward<double>(h, (const double*)f, (const double*)F, (int32_t)d,
-                                   (double*)out, st, (double*)cells);
+        return forward_entry<double>(fs, h, (const double*)f, (const double*)F, (int32_t)d,
+                                     (double*)out, st, (double*)cells);
     return fail(TFI_ERR_DTYPE, fs + ": unknown dtype");
 }
 }  // namespace
@@ -2623,6 +2791,20 @@ int tfi_integrate_multi(tfi_handle h, int32_t nk, const void* const* f, const vo
 }
 
 namespace {
+// The adjoint, on channel tiles when the whole call would exceed the budget
+// (not with kept cell sums, which span every channel).
+extern "C++" template <typename T>
+int backward_entry(const std::string& fs, tfi_plan* h, const T* f, const T* F, const T* gout,
+                   int32_t d, T* dF, double* df, hipStream_t st, const T* cells) {
+    if (!cells && h->budget) {
+        const int32_t dt = budget_tile<T>(h, d, true, df != nullptr);
+        if (dt == 0)
+            return fail(TFI_ERR_BUDGET, fs + ": the budget does not hold one channel of the pass");
+        if (dt < d) return run_backward_tiled<T>(h, f, F, gout, d, dF, df, st, dt);
+    }
+    return budget_retry(h, [&]() { return run_backward<T>(h, f, F, gout, d, dF, df, st, cells); });
+}
+
 int backward_impl(const char* fn, tfi_handle h, const void* f, const void* F, const void* cells,
                   const void* gout, int64_t d, tfi_dtype dtype, void* dF, double* df,
                   void* stream) {
@@ -2639,10 +2821,10 @@ int backward_impl(const char* fn, tfi_handle h, const void* f, const void* F, co
     hipStream_t st = (hipStream_t)stream;
     // f(D) is symmetric: dF = f(D) gout
     if (dtype == TFI_F32)
-        return run_backward<float>(h, (const float*)f, (const float*)F, (const float*)gout,
-                                   (int32_t)d, (float*)dF, df, st, (const float*)cells);
-    return run_backward<double>(h, (const double*)f, (const double*)F, (const double*)gout,
-                                (int32_t)d, (double*)dF, df, st, (const double*)cells);
+        return backward_entry<float>(fs, h, (const float*)f, (const float*)F, (const float*)gout,
+                                     (int32_t)d, (float*)dF, df, st, (const float*)cells);
+    return backward_entry<double>(fs, h, (const double*)f, (const double*)F, (const double*)gout,
+                                  (int32_t)d, (double*)dF, df, st, (const double*)cells);
 }
 }  // namespace
 

@@ -38,7 +38,9 @@ class TreeIntegrator:
     device  CUDA/HIP device index, or None for a host-only plan (stats and
             plan inspection only).
     table_method  'auto', 'direct' or 'fft' for every interaction table.
-    memory_budget  cap in bytes on device memory held by the handle (0 = no cap).
+    memory_budget  cap in bytes on device memory held by the handle (0 = no cap);
+            an integration or adjoint whose scratch would exceed it runs on
+            tiles of channels that fit.
     graphs  replay captured hipGraphs (True) or launch kernels directly.
     fft_cost  direct sums for a table iff cells^2 <= fft_cost * P log2 P
             (0 = default 4).
