@@ -689,43 +689,128 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
 }
 
 // ------------------------------------------------------------------- FFT --
-// In-place radix-2 transforms along one axis of a 2-D array in LDS.
+// In-place radix-2 transforms along one axis of a batch of lines in LDS.
 // Forward: decimation in frequency, natural order in, bit-reversed out.
 // Inverse: decimation in time, bit-reversed in, natural order out
 // (unnormalised). A convolution multiplies two forward spectra in the same
 // bit-reversed layout, so no reordering pass is needed.
-// Axis of length 2^lgL; `count` lines; element stride es, line stride ls.
-// tw[k] = exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), with lgtw >= lgL.
+//
+// The stages run in passes of up to three (radix-8, radix-4 or radix-2
+// groups): a thread loads the 2^R points of one group into registers, runs
+// the group's R stages there and stores them back, so a transform of 2^lgL
+// points takes ceil(lgL / 3) barriers instead of lgL. The stage of span 2^s
+// pairs points e and e + 2^s with twiddle W_{2^(s+1)}^(e mod 2^s),
+// W_n = exp(-2 pi i / n) (conjugated for the inverse). Within a pass over
+// index bits [s0, s0 + R) that twiddle factors as a compile-time 8th root of
+// unity times one table factor per stage, W_{2^(s+1)}^(e mod 2^s0).
+//
+// Twiddle table tw[k] = exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), lgtw >= lgL.
+
+// exp(-2 pi i m / 32), m < 16
+constexpr double kW32re[16] = {
+    1.0, 0.98078528040323043, 0.92387953251128674, 0.83146961230254524,
+    0.70710678118654757, 0.55557023301960229, 0.38268343236508984, 0.19509032201612833,
+    0.0, -0.19509032201612819, -0.38268343236508973, -0.55557023301960196,
+    -0.70710678118654746, -0.83146961230254535, -0.92387953251128674, -0.98078528040323043};
+constexpr double kW32im[16] = {
+    -0.0, -0.19509032201612825, -0.38268343236508978, -0.55557023301960218,
+    -0.70710678118654746, -0.83146961230254524, -0.92387953251128674, -0.98078528040323043,
+    -1.0, -0.98078528040323043, -0.92387953251128674, -0.83146961230254546,
+    -0.70710678118654757, -0.55557023301960218, -0.38268343236508989, -0.19509032201612861};
+
+// A batch of lines in LDS: line l0 + 2^lgc0 l1 (l0 < 2^lgc0, l1 < c1)
+// starts at l0 ls0 + l1 ls1; its points are es apart.
+struct LdsLines {
+    int lgc0, ls0, c1, ls1, es;
+};
+
+// One pass: R stages over index bits [s0, s0 + R) of every line. Lines that
+// are part of a longer transform (the blocked global passes) give their
+// twiddles the global index: point e of line l0 stands for index
+// (e << tsh) + tbase + l0 (tsh = 0: e itself). Ends with a barrier.
+template <typename T, bool INV, int R>
+__device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLines& L, int tsh,
+                                         int tbase, const cpx<T>* __restrict__ tw, int lgtw) {
+    const int lgr = lgL - R;
+    const int nitems = (L.c1 << L.lgc0) << lgr;
+    const bool line_fast = L.ls0 < L.es;  // neighbouring lanes on neighbouring addresses
+    const int mr = (1 << lgr) - 1, mc = (1 << L.lgc0) - 1;
+    const int step = (1 << s0) * L.es;
+    for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
+        int l0, rest;
+        if (line_fast) {
+            l0 = it & mc;
+            rest = (it >> L.lgc0) & mr;
+        } else {
+            rest = it & mr;
+            l0 = (it >> lgr) & mc;
+        }
+        const int l1 = it >> (lgr + L.lgc0);
+        const int lo = rest & ((1 << s0) - 1), hi = rest >> s0;
+        const int base = l0 * L.ls0 + l1 * L.ls1 + ((hi << (s0 + R)) | lo) * L.es;
+        cpx<T> x[1 << R];
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) x[k] = z[base + k * step];
+        const int J = (lo << tsh) + (tsh ? tbase + l0 : 0);
+        cpx<T> fs[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) fs[u] = tw[J << (lgtw - tsh - s0 - u - 1)];
+#pragma unroll
+        for (int uu = 0; uu < R; ++uu) {
+            const int u = INV ? uu : R - 1 - uu;
+            const int h = 1 << u;
+#pragma unroll
+            for (int k = 0; k < (1 << R); ++k) {
+                if (k & h) continue;
+                const int m = (k & (h - 1)) << (4 - u);  // W_{2^(u+1)}^(k mod 2^u) = W_32^m
+                const cpx<T> w = cmul(cpx<T>{(T)kW32re[m], (T)kW32im[m]}, fs[u]);
+                const cpx<T> p = x[k], q = x[k + h];
+                if (!INV) {
+                    x[k] = cadd(p, q);
+                    x[k + h] = cmul(csub(p, q), w);
+                } else {
+                    const cpx<T> qw = cmulc(q, w);
+                    x[k] = cadd(p, qw);
+                    x[k + h] = csub(p, qw);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) z[base + k * step] = x[k];
+    }
+    __syncthreads();
+}
+
+// The whole transform of 2^lgL points along every line of L: forward passes
+// from the high index bits down, inverse passes from the low bits up.
+template <typename T, bool INV>
+__device__ void fft_lines(cpx<T>* z, int lgL, const LdsLines& L, int tsh, int tbase,
+                          const cpx<T>* __restrict__ tw, int lgtw) {
+    if (INV) {
+        for (int s0 = 0; s0 < lgL;) {
+            const int R = min(3, lgL - s0);
+            if (R == 3) lds_pass<T, INV, 3>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            else if (R == 2) lds_pass<T, INV, 2>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            else lds_pass<T, INV, 1>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            s0 += R;
+        }
+    } else {
+        for (int s1 = lgL; s1 > 0;) {
+            const int R = min(3, s1);
+            if (R == 3) lds_pass<T, INV, 3>(z, lgL, s1 - 3, L, tsh, tbase, tw, lgtw);
+            else if (R == 2) lds_pass<T, INV, 2>(z, lgL, s1 - 2, L, tsh, tbase, tw, lgtw);
+            else lds_pass<T, INV, 1>(z, lgL, s1 - 1, L, tsh, tbase, tw, lgtw);
+            s1 -= R;
+        }
+    }
+}
+
+// One axis of a 2-D array: `count` (a power of two) lines of 2^lgL points,
+// element stride es, line stride ls.
 template <typename T, bool INV>
 __device__ void fft_axis_lds(cpx<T>* z, int lgL, int count, int es, int ls,
                              const cpx<T>* __restrict__ tw, int lgtw) {
-    if (lgL == 0) return;
-    const int half = 1 << (lgL - 1);
-    const int nb = count * half;
-    for (int s = 0; s < lgL; ++s) {
-        const int lh = INV ? s : (lgL - 1 - s);  // span h = 2^lh
-        const int h = 1 << lh;
-        for (int bi = threadIdx.x; bi < nb; bi += blockDim.x) {
-            const int line = bi >> (lgL - 1);
-            const int m = bi & (half - 1);
-            const int j = m & (h - 1);
-            const int blk = m >> lh;
-            const int i0 = line * ls + ((blk << (lh + 1)) + j) * es;
-            const int i1 = i0 + h * es;
-            const cpx<T> w = tw[j << (lgtw - lh - 1)];
-            const cpx<T> u = z[i0];
-            const cpx<T> v = z[i1];
-            if (!INV) {
-                z[i0] = cadd(u, v);
-                z[i1] = cmul(csub(u, v), w);
-            } else {
-                const cpx<T> vw = cmulc(v, w);
-                z[i0] = cadd(u, vw);
-                z[i1] = csub(u, vw);
-            }
-        }
-        __syncthreads();
-    }
+    fft_lines<T, INV>(z, lgL, LdsLines{31 - __clz(count), ls, 1, 0, es}, 0, 0, tw, lgtw);
 }
 
 // Bucket parameters of merged launches: bp[4 b .. 4 b + 3] = (lg1, lg2,
@@ -758,13 +843,15 @@ __global__ void k_spectrum_multi(const int32_t* __restrict__ bp, const int64_t* 
     for (int p = threadIdx.x; p < P; p += blockDim.x) out[p] = z[p];
 }
 
-// FFT convolution of LDS-resident tables: one workgroup per (job, channel
-// pair); fj[3 j .. 3 j + 2] = (first cell, end cell, bucket) of job j.
+// FFT convolution of LDS-resident tables: one workgroup per (job, group of
+// 2^lgnp channel pairs), one table per pair side by side in LDS (pair c at
+// z + c P); fj[3 j .. 3 j + 2] = (first cell, end cell, bucket) of job j.
 // Two real channels ride in the real and imaginary parts of one complex
 // table (the kernel is real, so the two results separate again in the
 // real and imaginary parts of the output). Source cell (r, x) goes to row
 // (-r mod L1): the Hankel dependence on q + r becomes a circular
-// convolution whose output row q needs no shift.
+// convolution whose output row q needs no shift. The rows of all the
+// group's tables transform as one batch of lines, then their columns.
 template <typename T>
 __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* __restrict__ bp,
                                  const int64_t* __restrict__ bo,
@@ -772,35 +859,43 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, T* __restrict__ g,
                                  const cpx<T>* __restrict__ spec_all,
-                                 const cpx<T>* __restrict__ tw, int lgtw) {
+                                 const cpx<T>* __restrict__ tw, int lgtw, int lgnp) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int32_t cb = fj[3 * blockIdx.x], ce = fj[3 * blockIdx.x + 1], bk = fj[3 * blockIdx.x + 2];
     const int lg1 = bp[4 * bk], lg2 = bp[4 * bk + 1];
     const cpx<T>* spec = spec_all + bo[bk];
-    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
-    const int32_t c0 = 2 * blockIdx.y, c1 = c0 + 1;
-    const bool has1 = c1 < d;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) z[p] = {(T)0, (T)0};
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2, lgP = lg1 + lg2;
+    const int NP = 1 << lgnp;
+    const int32_t ch0 = 2 * (int32_t)blockIdx.y * NP;  // first channel of the group
+    for (int p = threadIdx.x; p < NP * P; p += blockDim.x) z[p] = {(T)0, (T)0};
     __syncthreads();
-    for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
+    const int32_t items = (ce - cb) << lgnp;
+    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        const int c = it & (NP - 1);
+        const int32_t k = cb + (it >> lgnp), ch = ch0 + 2 * c;
+        if (ch >= d) continue;
         const int row = (L1 - jc_r[k]) & (L1 - 1);
         const int64_t vr = (int64_t)jc_val[k] * d;
-        z[(row << lg2) + jc_x[k]] = {val[vr + c0], has1 ? val[vr + c1] : (T)0};
+        z[(c << lgP) + (row << lg2) + jc_x[k]] = {val[vr + ch], ch + 1 < d ? val[vr + ch + 1] : (T)0};
     }
     __syncthreads();
-    fft_axis_lds<T, false>(z, lg2, L1, 1, L2, tw, lgtw);
-    fft_axis_lds<T, false>(z, lg1, L2, L2, 1, tw, lgtw);
-    for (int p = threadIdx.x; p < P; p += blockDim.x) z[p] = cmul(z[p], spec[p]);
+    const LdsLines rows{lg1 + lgnp, L2, 1, 0, 1}, cols{lg2, 1, NP, P, L2};
+    fft_lines<T, false>(z, lg2, rows, 0, 0, tw, lgtw);
+    fft_lines<T, false>(z, lg1, cols, 0, 0, tw, lgtw);
+    for (int p = threadIdx.x; p < NP * P; p += blockDim.x) z[p] = cmul(z[p], spec[p & (P - 1)]);
     __syncthreads();
-    fft_axis_lds<T, true>(z, lg1, L2, L2, 1, tw, lgtw);
-    fft_axis_lds<T, true>(z, lg2, L1, 1, L2, tw, lgtw);
+    fft_lines<T, true>(z, lg1, cols, 0, 0, tw, lgtw);
+    fft_lines<T, true>(z, lg2, rows, 0, 0, tw, lgtw);
     const T scale = (T)1 / (T)P;
-    for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
-        const cpx<T> y = z[(jc_r[k] << lg2) + jc_x[k]];
+    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
+        const int c = it & (NP - 1);
+        const int32_t k = cb + (it >> lgnp), ch = ch0 + 2 * c;
+        if (ch >= d) continue;
+        const cpx<T> y = z[(c << lgP) + (jc_r[k] << lg2) + jc_x[k]];
         const int64_t vr = (int64_t)jc_val[k] * d;
-        g[vr + c0] = y.x * scale;
-        if (has1) g[vr + c1] = y.y * scale;
+        g[vr + ch] = y.x * scale;
+        if (ch + 1 < d) g[vr + ch + 1] = y.y * scale;
     }
 }
 
@@ -832,8 +927,8 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
 
 // Blocked pass of the in-place transform along one axis of length 2^lgL
 // (element stride es) of every line (nlines per slot, line stride ls) of
-// every slot (2^lgP elements apart): the radix-2 stages whose butterfly
-// spans are 2^lglo .. 2^(lglo+k-1), done in LDS. A workgroup owns one
+// every slot (2^lgP elements apart): the stages whose butterfly spans are
+// 2^lglo .. 2^(lglo+k-1), done in LDS by register passes. A workgroup owns one
 // butterfly group -- the 2^k elements that differ in index bits
 // [lglo, lglo + k) -- for C = 2^lgC consecutive values of the bits below
 // lglo (consecutive addresses when es = 1). Forward (DIF) passes go from
@@ -863,32 +958,9 @@ __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t e
         z[e] = base[(i0 + (j << lglo) + lo) * es];
     }
     __syncthreads();
-    const int half = n >> 1;
-    for (int s = 0; s < k; ++s) {
-        const int m = INV ? s : (k - 1 - s);  // local span 2^m in j
-        for (int bi = threadIdx.x; bi < half; bi += blockDim.x) {
-            const int lo = bi & (int)(C - 1);
-            const int jb = bi >> lgC;  // butterfly index within the group
-            const int jj = jb & ((1 << m) - 1), blk = jb >> m;
-            const int j0 = (blk << (m + 1)) + jj;
-            const int a0 = (j0 << lgC) + lo, a1 = a0 + (1 << (m + lgC));
-            // global span h = 2^(lglo + m); exponent = index mod h
-            const int lh = lglo + m;
-            const int64_t ex = ((int64_t)jj << lglo) + (lo_chunk * C + lo);
-            const cpx<T> w = tw[ex << (lgtw - lh - 1)];
-            const cpx<T> u = z[a0];
-            const cpx<T> v = z[a1];
-            if (!INV) {
-                z[a0] = cadd(u, v);
-                z[a1] = cmul(csub(u, v), w);
-            } else {
-                const cpx<T> vw = cmulc(v, w);
-                z[a0] = cadd(u, vw);
-                z[a1] = csub(u, vw);
-            }
-        }
-        __syncthreads();
-    }
+    // the C lines (consecutive low values lo) of 2^k points j at stride C;
+    // twiddles by the global index (j << lglo) + lo_chunk C + lo
+    fft_lines<T, INV>(z, k, LdsLines{lgC, 1, 1, 0, 1 << lgC}, lglo, (int)(lo_chunk * C), tw, lgtw);
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int64_t j = e >> lgC, lo = e & (C - 1);
         base[(i0 + (j << lglo) + lo) * es] = z[e];
@@ -1383,10 +1455,9 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
             zg[(jc_r[k] << lg2) + jc_x[k]] = {valg[vr + c0], has1 ? valg[vr + c1] : (T)0};
         }
         __syncthreads();
-        fft_axis_lds<T, false>(zv, lg2, L1, 1, L2, tw, lgtw);
-        fft_axis_lds<T, false>(zv, lg1, L2, L2, 1, tw, lgtw);
-        fft_axis_lds<T, false>(zg, lg2, L1, 1, L2, tw, lgtw);
-        fft_axis_lds<T, false>(zg, lg1, L2, L2, 1, tw, lgtw);
+        // zv and zg side by side: their rows, then their columns, as one batch
+        fft_lines<T, false>(zv, lg2, LdsLines{lg1 + 1, L2, 1, 0, 1}, 0, 0, tw, lgtw);
+        fft_lines<T, false>(zv, lg1, LdsLines{lg2, 1, 2, P, L2}, 0, 0, tw, lgtw);
         for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = cadd(acc[p], cmulc(zg[p], zv[p]));
         __syncthreads();
     }

@@ -57,18 +57,6 @@ constexpr int kC1MaxR = 5;      // register bits per phase (32 points per thread
 constexpr int64_t kConvGroupBytes = (int64_t)2 << 30;  // buffer of one tile group
 constexpr int kC1Pad = 8;       // complex values of padding per LDS row
 
-// exp(-2 pi i m / 32), m < 16
-constexpr double kW32re[16] = {
-    1.0, 0.98078528040323043, 0.92387953251128674, 0.83146961230254524,
-    0.70710678118654757, 0.55557023301960229, 0.38268343236508984, 0.19509032201612833,
-    0.0, -0.19509032201612819, -0.38268343236508973, -0.55557023301960196,
-    -0.70710678118654746, -0.83146961230254535, -0.92387953251128674, -0.98078528040323043};
-constexpr double kW32im[16] = {
-    -0.0, -0.19509032201612825, -0.38268343236508978, -0.55557023301960218,
-    -0.70710678118654746, -0.83146961230254524, -0.92387953251128674, -0.98078528040323043,
-    -1.0, -0.98078528040323043, -0.92387953251128674, -0.83146961230254546,
-    -0.70710678118654757, -0.55557023301960218, -0.38268343236508989, -0.19509032201612861};
-
 // Per-stage factors fs[u] = W_{2^(shift+u+1)}^{j0} for u < R (j0 < 2^shift).
 template <typename T>
 __device__ __forceinline__ void stage_factors(cpx<T> (&fs)[kC1MaxR], int R, int shift, int64_t j0,

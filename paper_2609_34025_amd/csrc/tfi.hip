@@ -193,6 +193,9 @@ struct tfi_plan {
     int lgtw = 1;
     void* d_tw[2] = {nullptr, nullptr};  // float / double twiddles
     int64_t lds_max = 65536;        // bytes of LDS a workgroup may use
+    // channel pairs per workgroup of the LDS FFT tiers (powers of two;
+    // 0 = by table size, see fft_lgnp)
+    int fft_np[3] = {0, 0, 0};
 
     // per-dtype scratch (grow-only)
     DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2], part[2], partg[2];
@@ -1559,6 +1562,25 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nu
     }
 }
 
+// log2 of the channel pairs one workgroup of LDS tier t transforms: the
+// handle's setting, else enough tables for about 4096 points per workgroup
+// (a radix-8 pass then has a group for every thread); at most the pairs
+// there are and what fits the LDS limit.
+inline int fft_lgnp(const tfi_plan* h, int ti, int t, int32_t npairs) {
+    const Tier& T_ = h->tiers[ti][t];
+    const int64_t cs = ti ? 16 : 8;
+    const int64_t pmax = std::max<int64_t>(1, T_.lds_bytes / cs);
+    int lg = 0;
+    if (h->fft_np[t] > 0) {
+        while ((2 << lg) <= h->fft_np[t]) ++lg;
+    } else {
+        while (((int64_t)2 << lg) * pmax <= 4096) ++lg;
+    }
+    while (lg > 0 && (1 << lg) > npairs) --lg;
+    while (lg > 0 && ((int64_t)1 << lg) * T_.lds_bytes > h->lds_max) --lg;
+    return lg;
+}
+
 template <typename T>
 void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const Work& w,
              const tfi::cpx<T>* spec = nullptr) {
@@ -1570,10 +1592,13 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
     for (int t = 0; t < 3; ++t) {
         const Tier& T_ = h->tiers[ti][t];
         if (!T_.njobs) continue;
+        const int lgnp = fft_lgnp(h, ti, t, npairs);
+        const unsigned groups = (unsigned)((npairs + (1 << lgnp) - 1) >> lgnp);
         hipEvent_t ev = h->begin(st);
-        hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, npairs),
-                           dim3(kThreads), (unsigned)T_.lds_bytes, st, T_.d_fj, T_.d_bp, T_.d_bo,
-                           h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw, h->lgtw);
+        hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, groups),
+                           dim3(kThreads), (unsigned)(T_.lds_bytes << lgnp), st, T_.d_fj, T_.d_bp,
+                           T_.d_bo, h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw,
+                           h->lgtw, lgnp);
         h->end(st, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
