@@ -339,9 +339,12 @@ int64_t tfi_plan_export(tfi_handle h, const char *name, void *buf,
  * length does not change. Uses temporary device memory for three [N x d]
  * fields and one FP64 kernel-length histogram. With the chosen constant it
  * then times both strategies of the cell sums (tfi_set_scatter) and keeps
- * the faster.
- * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE (method forced at
- * build), TFI_ERR_HIP, TFI_ERR_BUDGET, TFI_ERR_OOM.
+ * the faster. A handle whose table method was forced at build keeps it (no
+ * cost constant is scanned; *best_cost is the handle's constant) and tunes
+ * the cell sums only. The FFT kernels' shapes are tuned separately
+ * (tfi_autotune_fft).
+ * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE, TFI_ERR_HIP,
+ * TFI_ERR_BUDGET, TFI_ERR_OOM.
  */
 int tfi_autotune(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
                  int with_backward, float *best_cost, void *stream);
@@ -362,6 +365,61 @@ int tfi_set_fft_cost(tfi_handle h, float cost);
  * Errors: TFI_ERR_ARG (method outside [-1, 1]), TFI_ERR_STATE, TFI_ERR_HIP.
  */
 int tfi_set_scatter(tfi_handle h, int32_t method);
+
+/*
+ * Shapes of the FFT convolution kernels (lemma "stad-2d-fft", algorithm
+ * "global-anchor-2dfft"); tfi_autotune picks them by timing. They change
+ * how the transforms are blocked, not what they compute: results agree up
+ * to rounding order.
+ *   lds_pairs[t]      channel pairs transformed together by one workgroup
+ *                     of LDS tier t (tables up to 16 KiB, up to 64 KiB,
+ *                     larger); a power of two <= 64, or 0 = enough pairs
+ *                     for about 4096 points per workgroup. Reduced to the
+ *                     pairs there are and to what fits LDS.
+ *   conv1d_min_lg     one-row and one-column tables of at least
+ *                     2^conv1d_min_lg lattice points take the channel-tiled
+ *                     1-D convolution kernels even when they fit LDS
+ *                     (default 10; tables beyond LDS always do), in [2, 31].
+ *   conv1d_pairs      channel pairs per 1-D tile: 0 = one 128-byte line
+ *                     per point (16 FP32 or 8 FP64 pairs), or a power of
+ *                     two <= 16 as a cap.
+ *   conv1d_group_mib  work buffer of one group of 1-D tiles in MiB (the
+ *                     passes run group by group); 0 = 2048.
+ *   col_lines         neighbouring columns per workgroup of the blocked
+ *                     global passes along the first table axis; a power of
+ *                     two <= 64 (default 16).
+ * tfi_set_fft_params waits for the device, drops captured launches and,
+ * when conv1d_min_lg changes, rebuilds the device job lists.
+ * Errors: TFI_ERR_ARG (a field out of range), TFI_ERR_STATE, TFI_ERR_HIP,
+ * TFI_ERR_OOM, TFI_ERR_BUDGET.
+ */
+typedef struct tfi_fft_params {
+    int32_t lds_pairs[3];
+    int32_t conv1d_min_lg;
+    int32_t conv1d_pairs;
+    int32_t conv1d_group_mib;
+    int32_t col_lines;
+} tfi_fft_params;
+
+int tfi_set_fft_params(tfi_handle h, const tfi_fft_params *p);
+
+/* The handle's current FFT kernel shapes (host struct). Errors: TFI_ERR_ARG. */
+int tfi_get_fft_params(tfi_handle h, tfi_fft_params *p);
+
+/*
+ * Search the FFT kernel shapes (tfi_fft_params) that passes of d channels
+ * of dtype run under the handle's current method rule: one parameter at a
+ * time (pairs per workgroup of each LDS tier in use, conv1d_min_lg when
+ * one-row or one-column FFT tables exist, the 1-D tile width and group
+ * buffer when 1-D kernels run, col_lines when blocked global passes run),
+ * every candidate timed as in tfi_autotune (kernel table f, fields of ones,
+ * `stream`, with_backward as there); the fastest setting stays in effect.
+ * Does nothing when the passes run no FFT kernels.
+ * Errors: TFI_ERR_ARG, TFI_ERR_DTYPE, TFI_ERR_STATE, TFI_ERR_HIP,
+ * TFI_ERR_BUDGET, TFI_ERR_OOM.
+ */
+int tfi_autotune_fft(tfi_handle h, const void *f, int64_t d, tfi_dtype dtype,
+                     int with_backward, void *stream);
 
 /*
  * Measure the channel-aware cost model of TFI_POLICY_CHANNEL on this

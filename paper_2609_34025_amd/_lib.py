@@ -40,6 +40,12 @@ class BuildOpts(C.Structure):
                 ("cost_fft", C.c_float), ("cost_call", C.c_float)]
 
 
+class FftParams(C.Structure):
+    _fields_ = [("lds_pairs", C.c_int32 * 3), ("conv1d_min_lg", C.c_int32),
+                ("conv1d_pairs", C.c_int32), ("conv1d_group_mib", C.c_int32),
+                ("col_lines", C.c_int32)]
+
+
 _lib = None
 
 EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate",
@@ -48,7 +54,8 @@ EXPORTED = ["tfi_build", "tfi_num_vertices", "tfi_kernel_length", "tfi_integrate
             "tfi_last_error", "tfi_integrate_expsum", "tfi_backward_expsum", "tfi_calibrate",
             "tfi_integrate_multi", "tfi_cell_rows", "tfi_integrate_expsum_cells",
             "tfi_backward_expsum_cells", "tfi_integrate_cells", "tfi_backward_cells",
-            "tfi_integrate_noalloc", "tfi_set_scatter"]
+            "tfi_integrate_noalloc", "tfi_set_scatter", "tfi_set_fft_params",
+            "tfi_get_fft_params", "tfi_autotune_fft"]
 
 # bytes of the fixed device scratch array of tfi_integrate_noalloc
 # (TFI_NOALLOC_SCRATCH_BYTES in include/tfi.h)
@@ -93,6 +100,12 @@ def load():
     lib.tfi_set_fft_cost.restype = C.c_int
     lib.tfi_set_scatter.argtypes = [vp, C.c_int32]
     lib.tfi_set_scatter.restype = C.c_int
+    lib.tfi_set_fft_params.argtypes = [vp, C.POINTER(FftParams)]
+    lib.tfi_set_fft_params.restype = C.c_int
+    lib.tfi_get_fft_params.argtypes = [vp, C.POINTER(FftParams)]
+    lib.tfi_get_fft_params.restype = C.c_int
+    lib.tfi_autotune_fft.argtypes = [vp, vp, i64, C.c_int, C.c_int, vp]
+    lib.tfi_autotune_fft.restype = C.c_int
     lib.tfi_calibrate.argtypes = [vp, vp, i64, C.c_int, C.POINTER(C.c_float), vp]
     lib.tfi_calibrate.restype = C.c_int
     lib.tfi_integrate_multi.argtypes = [vp, C.c_int32, C.POINTER(vp), vp, i64, C.c_int,

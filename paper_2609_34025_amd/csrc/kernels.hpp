@@ -719,15 +719,17 @@ constexpr double kW32im[16] = {
     -0.70710678118654757, -0.55557023301960218, -0.38268343236508989, -0.19509032201612861};
 
 // A batch of lines in LDS: line l0 + 2^lgc0 l1 (l0 < 2^lgc0, l1 < c1)
-// starts at l0 ls0 + l1 ls1; its points are es apart.
+// starts at l0 ls0 + l1 ls1; its points are es apart. lgtn: low bits of l0
+// that select one of several separate transforms (see lds_pass).
 struct LdsLines {
-    int lgc0, ls0, c1, ls1, es;
+    int lgc0, ls0, c1, ls1, es, lgtn = 0;
 };
 
 // One pass: R stages over index bits [s0, s0 + R) of every line. Lines that
 // are part of a longer transform (the blocked global passes) give their
 // twiddles the global index: point e of line l0 stands for index
-// (e << tsh) + tbase + l0 (tsh = 0: e itself). Ends with a barrier.
+// (e << tsh) + tbase + (l0 >> lgtn) (tsh = 0: e itself). Ends with a
+// barrier.
 template <typename T, bool INV, int R>
 __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLines& L, int tsh,
                                          int tbase, const cpx<T>* __restrict__ tw, int lgtw) {
@@ -751,7 +753,7 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
         cpx<T> x[1 << R];
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) x[k] = z[base + k * step];
-        const int J = (lo << tsh) + (tsh ? tbase + l0 : 0);
+        const int J = (lo << tsh) + (tsh ? tbase + (l0 >> L.lgtn) : 0);
         cpx<T> fs[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) fs[u] = tw[J << (lgtw - tsh - s0 - u - 1)];
@@ -928,42 +930,48 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
 // Blocked pass of the in-place transform along one axis of length 2^lgL
 // (element stride es) of every line (nlines per slot, line stride ls) of
 // every slot (2^lgP elements apart): the stages whose butterfly spans are
-// 2^lglo .. 2^(lglo+k-1), done in LDS by register passes. A workgroup owns one
-// butterfly group -- the 2^k elements that differ in index bits
+// 2^lglo .. 2^(lglo+k-1), done in LDS by register passes. A workgroup owns
+// one butterfly group -- the 2^k elements that differ in index bits
 // [lglo, lglo + k) -- for C = 2^lgC consecutive values of the bits below
-// lglo (consecutive addresses when es = 1). Forward (DIF) passes go from
-// the high bits down, inverse (DIT) passes from the low bits up, with the
-// same twiddles exp(-+2 pi i j / 2h) as the LDS transform.
+// lglo (consecutive addresses when es = 1) and N = 2^lgN neighbouring lines
+// (consecutive addresses when ls = 1: the column passes of a 2-D table).
+// Forward (DIF) passes go from the high bits down, inverse (DIT) passes from
+// the low bits up, with the same twiddles exp(-+2 pi i j / 2h) as the LDS
+// transform.
 template <typename T, bool INV>
 __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
-                           int64_t nlines, int lglo, int k, int lgC,
+                           int64_t nlines, int lglo, int k, int lgC, int lgN,
                            const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int64_t C = (int64_t)1 << lgC;
     const int64_t nlo = ((int64_t)1 << lglo) >> lgC;       // low-bit chunks
     const int64_t nhi = (int64_t)1 << (lgL - lglo - k);    // high-bit values
+    const int64_t ngrp = nlines >> lgN;                     // groups of N lines
     int64_t g = blockIdx.x;
     const int64_t lo_chunk = g % nlo;
     g /= nlo;
     const int64_t hi = g % nhi;
     g /= nhi;
-    const int64_t line = g % nlines;
-    const int64_t slot = g / nlines;
+    const int64_t line = (g % ngrp) << lgN;
+    const int64_t slot = g / ngrp;
     cpx<T>* base = buf + (slot << lgP) + line * ls;
     const int64_t i0 = (hi << (lglo + k)) + lo_chunk * C;
-    const int n = 1 << (k + lgC);
+    const int lgCN = lgC + lgN;
+    const int n = 1 << (k + lgCN);
+    // LDS e = ((j << lgC | lo) << lgN) | ln: line ln fastest
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int64_t j = e >> lgC, lo = e & (C - 1);
-        z[e] = base[(i0 + (j << lglo) + lo) * es];
+        const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
+        z[e] = base[ln * ls + (i0 + (j << lglo) + lo) * es];
     }
     __syncthreads();
-    // the C lines (consecutive low values lo) of 2^k points j at stride C;
+    // the C x N lines (l0 = lo N + ln) of 2^k points j at stride C N;
     // twiddles by the global index (j << lglo) + lo_chunk C + lo
-    fft_lines<T, INV>(z, k, LdsLines{lgC, 1, 1, 0, 1 << lgC}, lglo, (int)(lo_chunk * C), tw, lgtw);
+    fft_lines<T, INV>(z, k, LdsLines{lgCN, 1, 1, 0, 1 << lgCN, lgN}, lglo, (int)(lo_chunk * C),
+                      tw, lgtw);
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int64_t j = e >> lgC, lo = e & (C - 1);
-        base[(i0 + (j << lglo) + lo) * es] = z[e];
+        const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
+        base[ln * ls + (i0 + (j << lglo) + lo) * es] = z[e];
     }
 }
 

@@ -80,6 +80,8 @@ struct Bucket {
     bool reflect = false;
     int64_t spec_off = 0;       // element offset into the spectrum arena
     int64_t cells = 0;          // table cells over the bucket's jobs
+    int tc_cap = 0;             // FftParams::conv1d_pairs
+    int64_t group_bytes = 0;    // FftParams::conv1d_group_mib in bytes (0 = kConvGroupBytes)
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
     int64_t njobs() const { return (int64_t)jobs.size() / 2; }
 };
@@ -97,6 +99,16 @@ struct Tier {
 struct DeviceBuf {
     void* p = nullptr;
     size_t bytes = 0;
+};
+
+// Shapes of the FFT kernels, set by tfi_set_fft_params or tfi_autotune
+// (the fields of tfi_fft_params).
+struct FftParams {
+    int lds_pairs[3] = {0, 0, 0};  // channel pairs per workgroup of the LDS tiers; 0 = by size
+    int conv1d_min_lg = 10;        // one-row/one-column tables of >= 2^this points: 1-D kernels
+    int conv1d_pairs = 0;          // channel pairs per 1-D tile; 0 = one 128-byte line
+    int conv1d_group_mib = 0;      // 1-D work buffer per group of tiles; 0 = 2048
+    int col_lines = 16;            // columns per workgroup of the blocked column passes
 };
 
 // Direct-sum tables of a set of jobs: padded cell list (jobs by size),
@@ -193,9 +205,7 @@ struct tfi_plan {
     int lgtw = 1;
     void* d_tw[2] = {nullptr, nullptr};  // float / double twiddles
     int64_t lds_max = 65536;        // bytes of LDS a workgroup may use
-    // channel pairs per workgroup of the LDS FFT tiers (powers of two;
-    // 0 = by table size, see fft_lgnp)
-    int fft_np[3] = {0, 0, 0};
+    FftParams fp;                   // shapes of the FFT kernels (tfi_set_fft_params)
 
     // per-dtype scratch (grow-only)
     DeviceBuf val[2], g[2], spec[2], fftbuf[2], valg[2], dfbuf[2], part[2], partg[2];
@@ -962,6 +972,8 @@ int upload_methods(tfi_plan* h) {
                 Bucket b;
                 b.lg1 = key.first;
                 b.lg2 = key.second;
+                b.tc_cap = h->fp.conv1d_pairs;
+                b.group_bytes = (int64_t)h->fp.conv1d_group_mib << 20;
                 h->buckets.push_back(b);
             }
             Bucket& b = h->buckets[it->second];
@@ -998,7 +1010,7 @@ int upload_methods(tfi_plan* h) {
             // long 1-D tables take the channel-tiled convolution kernels even
             // when one channel pair would fit LDS (the LDS kernels read one
             // pair per workgroup: 8 bytes of every row)
-            if ((b.lg1 == 0 || b.lg2 == 0) && b.lg1 + b.lg2 >= 10) t = 3;
+            if ((b.lg1 == 0 || b.lg2 == 0) && b.lg1 + b.lg2 >= h->fp.conv1d_min_lg) t = 3;
             if (t == 3) {
                 h->global_b[ti].push_back((int)bi);
                 continue;
@@ -1192,55 +1204,69 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, T* part, int32_t d, hipSt
         launch_scatter_levels<T>(h, src, val, d, st);
 }
 
-// Pass schedule of a transform along an axis of 2^lgL points: groups of up
-// to 8 index bits with 16 consecutive low indices per workgroup, or one
-// pass when the axis fits 4096 points. Listed in DIF order (high bits
-// first); the inverse runs them in reverse.
+// Pass schedule of a transform along an axis of 2^lgL points, 2^lgN
+// neighbouring lines per workgroup: at most 4096 points per workgroup, as
+// groups of index bits with 16 consecutive low indices per workgroup (rows,
+// lgN = 0) or with the lines giving the contiguous runs (columns), or one
+// pass when the axis fits. Listed in DIF order (high bits first); the
+// inverse runs them in reverse.
 struct PassSpec {
     int lglo, k, lgC;
 };
 
-inline std::vector<PassSpec> fft_passes(int lgL) {
+inline std::vector<PassSpec> fft_passes(int lgL, int lgN) {
     std::vector<PassSpec> v;
+    const int kmax = 12 - lgN;
     int hi = lgL;
     while (hi > 0) {
-        if (hi <= 12) {
+        if (hi <= kmax) {
             v.push_back({0, hi, 0});
             break;
         }
-        v.push_back({hi - 8, 8, 4});
-        hi -= 8;
+        const int lgC = lgN ? 0 : 4, k = kmax - lgC;
+        v.push_back({hi - k, k, lgC});
+        hi -= k;
     }
     return v;
 }
 
 template <typename T, bool INV>
 void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
-                 int64_t nlines, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
-    std::vector<PassSpec> ps = fft_passes(lgL);
+                 int64_t nlines, int lgN, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
+    while (lgN > 0 && ((int64_t)1 << lgN) > nlines) --lgN;
+    std::vector<PassSpec> ps = fft_passes(lgL, lgN);
     if (INV) std::reverse(ps.begin(), ps.end());
     for (const PassSpec& q : ps) {
-        const int64_t groups = nslots * nlines * ((int64_t)1 << (lgL - q.lglo - q.k)) *
+        const int64_t groups = nslots * (nlines >> lgN) * ((int64_t)1 << (lgL - q.lglo - q.k)) *
                                (((int64_t)1 << q.lglo) >> q.lgC);
-        const unsigned lds = (unsigned)(((int64_t)1 << (q.k + q.lgC)) * sizeof(tfi::cpx<T>));
+        const unsigned lds =
+            (unsigned)(((int64_t)1 << (q.k + q.lgC + lgN)) * sizeof(tfi::cpx<T>));
         hipLaunchKernelGGL((tfi::k_fft_pass<T, INV>), dim3((unsigned)groups), dim3(kThreads), lds,
-                           st, buf, lgP, lgL, es, ls, nlines, q.lglo, q.k, q.lgC, tw, lgtw);
+                           st, buf, lgP, lgL, es, ls, nlines, q.lglo, q.k, q.lgC, lgN, tw, lgtw);
     }
 }
 
+inline int ilog2_floor(int64_t v) {
+    int lg = 0;
+    while (((int64_t)2 << lg) <= v) ++lg;
+    return lg;
+}
+
 // Forward 2-D transform (rows, then columns) or inverse (columns, then
-// rows) of nslots tables of 2^lg1 x 2^lg2 points.
+// rows) of nslots tables of 2^lg1 x 2^lg2 points; the column passes take
+// col_lines neighbouring columns per workgroup.
 template <typename T, bool INV>
 void launch_fft2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::cpx<T>* tw,
-                 int lgtw, hipStream_t st) {
+                 int lgtw, int col_lines, hipStream_t st) {
     const int lgP = lg1 + lg2;
     const int64_t L1 = (int64_t)1 << lg1, L2 = (int64_t)1 << lg2;
+    const int lgN = ilog2_floor(std::max(1, col_lines));
     if (!INV) {
-        if (lg2) launch_axis<T, false>(buf, nslots, lgP, lg2, 1, L2, L1, tw, lgtw, st);
-        if (lg1) launch_axis<T, false>(buf, nslots, lgP, lg1, L2, 1, L2, tw, lgtw, st);
+        if (lg2) launch_axis<T, false>(buf, nslots, lgP, lg2, 1, L2, L1, 0, tw, lgtw, st);
+        if (lg1) launch_axis<T, false>(buf, nslots, lgP, lg1, L2, 1, L2, lgN, tw, lgtw, st);
     } else {
-        if (lg1) launch_axis<T, true>(buf, nslots, lgP, lg1, L2, 1, L2, tw, lgtw, st);
-        if (lg2) launch_axis<T, true>(buf, nslots, lgP, lg2, 1, L2, L1, tw, lgtw, st);
+        if (lg1) launch_axis<T, true>(buf, nslots, lgP, lg1, L2, 1, L2, lgN, tw, lgtw, st);
+        if (lg2) launch_axis<T, true>(buf, nslots, lgP, lg2, 1, L2, L1, 0, tw, lgtw, st);
     }
 }
 
@@ -1260,6 +1286,7 @@ int conv1d_tc(const Bucket& b, int32_t d, int* lgL_out = nullptr) {
     const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
     const int64_t npairs = (d + 1) / 2;
     int tc = (int)(128 / cs);
+    while (b.tc_cap > 0 && tc > b.tc_cap) tc >>= 1;
     while (tc > 1 && tc / 2 >= npairs) tc >>= 1;
     for (; tc >= 1; tc >>= 1) {
         int lgH = lg - lg / 2;
@@ -1293,7 +1320,8 @@ size_t fft_buf_bytes(const Bucket& b, int32_t d) {
     const int64_t all = one_job * b.njobs();
     if (const int tc = conv1d_tc<T>(b, d)) {
         const int64_t slot = (int64_t)tc * b.P() * (int64_t)sizeof(tfi::cpx<T>);
-        const int64_t group = std::max<int64_t>(1, tfi::kConvGroupBytes / slot) * slot;
+        const int64_t gb = b.group_bytes > 0 ? b.group_bytes : tfi::kConvGroupBytes;
+        const int64_t group = std::max<int64_t>(1, gb / slot) * slot;
         return (size_t)std::min(all, group);
     }
     return (size_t)std::max(one_job, std::min(all, (int64_t)2 << 30));
@@ -1409,10 +1437,10 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
         hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, val, buf);
-        launch_fft2<T, false>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, st);
+        launch_fft2<T, false>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
                            dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
-        launch_fft2<T, true>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, st);
+        launch_fft2<T, true>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                            0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, buf, g);
@@ -1557,7 +1585,7 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nu
         tfi::cpx<T>* z = spec + b.spec_off;
         hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
-        launch_fft2<T, false>(z, 1, b.lg1, b.lg2, tw, h->lgtw, st);
+        launch_fft2<T, false>(z, 1, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         h->end(st, ev, "spectrum_global", 2.0 * sizeof(T) * (double)b.P());
     }
 }
@@ -1571,8 +1599,8 @@ inline int fft_lgnp(const tfi_plan* h, int ti, int t, int32_t npairs) {
     const int64_t cs = ti ? 16 : 8;
     const int64_t pmax = std::max<int64_t>(1, T_.lds_bytes / cs);
     int lg = 0;
-    if (h->fft_np[t] > 0) {
-        while ((2 << lg) <= h->fft_np[t]) ++lg;
+    if (h->fp.lds_pairs[t] > 0) {
+        while ((2 << lg) <= h->fp.lds_pairs[t]) ++lg;
     } else {
         while (((int64_t)2 << lg) * pmax <= 4096) ++lg;
     }
@@ -1754,11 +1782,11 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
             hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                                0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
                                h->d_jc_val, d, val, valg, bv, bg);
-            launch_fft2<T, false>(bv, 2 * nslots, b.lg1, b.lg2, tw, h->lgtw, st);
+            launch_fft2<T, false>(bv, 2 * nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
             hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
                                dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
                                (const tfi::cpx<T>*)bg, acc);
-            launch_fft2<T, true>(acc, nj, b.lg1, b.lg2, tw, h->lgtw, st);
+            launch_fft2<T, true>(acc, nj, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
             hipLaunchKernelGGL(tfi::k_fold_global<T>, dim3(blocks_for(nj * P)), dim3(kThreads), 0,
                                st, nj, b.lg1, b.lg2, p.NA, jobs, b.d_hx + 2 * j0, h->d_jc_val,
                                (const tfi::cpx<T>*)acc, df);
@@ -2664,6 +2692,114 @@ int time_pass(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, bool
     return rc;
 }
 
+
+// Apply FFT kernel shapes: tables move between the LDS tiers and the 1-D
+// kernels when conv1d_min_lg changes (the device job lists are rebuilt);
+// graphs holding the old launches are dropped.
+int apply_fft_params(tfi_plan* h, const FftParams& p) {
+    TFI_HIP(hipDeviceSynchronize());
+    h->drop_graphs();
+    const bool retier = p.conv1d_min_lg != h->fp.conv1d_min_lg;
+    h->fp = p;
+    if (retier) {
+        int rc = h->free_methods();
+        if (rc) return rc;
+        return upload_methods(h);
+    }
+    for (Bucket& b : h->buckets) {
+        b.tc_cap = p.conv1d_pairs;
+        b.group_bytes = (int64_t)p.conv1d_group_mib << 20;
+    }
+    return TFI_OK;
+}
+
+// Coordinate search over the FFT kernel shapes that this dtype and width
+// use: channel pairs per workgroup of each LDS tier, the size from which
+// one-row and one-column tables take the 1-D kernels, the 1-D tile width
+// and tile-group buffer, and the columns per workgroup of the blocked
+// column passes. Each candidate is timed like the method rule; the fastest
+// setting of each parameter is kept before the next is tried.
+template <typename T>
+int tune_fft(tfi_plan* h, const T* f, int32_t d, hipStream_t st, bool with_bwd) {
+    const int ti = sizeof(T) == 8 ? 1 : 0;
+    const int32_t npairs = (d + 1) / 2;
+    auto uses = [&](bool* lds, bool* c1, bool* g2) {
+        for (int t = 0; t < 3; ++t) lds[t] = h->tiers[ti][t].njobs > 0;
+        *c1 = *g2 = false;
+        for (int bi : h->global_b[ti]) (conv1d_tc<T>(h->buckets[bi], d) ? *c1 : *g2) = true;
+    };
+    bool lds[3], c1, g2;
+    uses(lds, &c1, &g2);
+    bool line_tables = false;  // one-row/one-column tables the 1-D threshold can move
+    for (const Bucket& b : h->buckets)
+        if ((b.lg1 == 0 || b.lg2 == 0) && b.lg1 + b.lg2 >= 6) line_tables = true;
+    if (!lds[0] && !lds[1] && !lds[2] && !c1 && !g2) return TFI_OK;
+    FftParams best = h->fp;
+    float best_ms = 1e30f;
+    int rc = time_pass<T>(h, f, d, st, 5, with_bwd, &best_ms);
+    if (rc) return rc;
+    auto trial = [&](const FftParams& cand) -> int {
+        int r = apply_fft_params(h, cand);
+        if (r) return r;
+        float ms = 1e30f;
+        r = time_pass<T>(h, f, d, st, 5, with_bwd, &ms);
+        if (r) return r;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+        return TFI_OK;
+    };
+    for (int t = 0; t < 3 && !rc; ++t) {
+        if (!lds[t]) continue;
+        // candidates by the pair count they give (after the LDS and pair limits)
+        auto eff = [&](const FftParams& c) {
+            const FftParams keep = h->fp;
+            h->fp = c;
+            const int lg = fft_lgnp(h, ti, t, npairs);
+            h->fp = keep;
+            return lg;
+        };
+        std::set<int> tried = {eff(best)};
+        for (int np : {1, 2, 4, 8, 16, 32}) {
+            FftParams c = best;
+            c.lds_pairs[t] = np;
+            if (!tried.insert(eff(c)).second) continue;
+            if ((rc = trial(c))) break;
+        }
+    }
+    if (!rc && line_tables)
+        for (int lg : {6, 8, 12, 15}) {
+            if (lg == best.conv1d_min_lg) continue;
+            FftParams c = best;
+            c.conv1d_min_lg = lg;
+            if ((rc = trial(c))) break;
+        }
+    if (!rc) rc = apply_fft_params(h, best);
+    uses(lds, &c1, &g2);
+    if (!rc && c1)
+        for (int tc : {8, 4}) {
+            if (tc * (int)sizeof(tfi::cpx<T>) >= 128) continue;
+            FftParams c = best;
+            c.conv1d_pairs = tc;
+            if ((rc = trial(c))) break;
+        }
+    if (!rc && c1)
+        for (int mib : {512, 128}) {
+            FftParams c = best;
+            c.conv1d_group_mib = mib;
+            if ((rc = trial(c))) break;
+        }
+    if (!rc && g2)
+        for (int n : {1, 4, 32}) {
+            FftParams c = best;
+            c.col_lines = n;
+            if ((rc = trial(c))) break;
+        }
+    const int rc2 = apply_fft_params(h, best);
+    return rc ? rc : rc2;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3180,12 +3316,12 @@ int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int wi
     if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_autotune: need 1 <= d <= 2^20");
     if (dtype != TFI_F32 && dtype != TFI_F64)
         return fail(TFI_ERR_DTYPE, "tfi_autotune: unknown dtype");
-    if (h->popt.table_method != 0)
-        return fail(TFI_ERR_STATE, "tfi_autotune: table method is forced for this handle");
     hipStream_t st = (hipStream_t)stream;
     const float cands[] = {0.25f, 1.0f, 2.0f, 4.0f, 8.0f, 16.0f, 32.0f, 64.0f};
     float best = (float)h->popt.fft_cost, best_ms = 1e30f;
+    // a forced table method keeps its assignment: no cost constant to scan
     for (float c : cands) {
+        if (h->popt.table_method != 0) break;
         if ((rc = reassign_methods(h, c))) return rc;
         float ms = 1e30f;
         rc = dtype == TFI_F32 ? time_pass<float>(h, (const float*)f, (int32_t)d, st, 5,
@@ -3198,7 +3334,7 @@ int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int wi
             best = c;
         }
     }
-    if ((rc = reassign_methods(h, best))) return rc;
+    if (h->popt.table_method == 0 && (rc = reassign_methods(h, best))) return rc;
     // the cell-sum strategy at this width: pieces or levels, the faster pass
     float sms[2] = {1e30f, 1e30f};
     for (int m = 0; m < 2 && !rc; ++m) {
@@ -3211,6 +3347,58 @@ int tfi_autotune(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int wi
     h->scatter_pick = sms[0] <= sms[1] ? 0 : 1;
     if (rc) return rc;
     *best_cost = best;
+    return TFI_OK;
+}
+
+int tfi_autotune_fft(tfi_handle h, const void* f, int64_t d, tfi_dtype dtype, int with_backward,
+                     void* stream) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!f) return fail(TFI_ERR_ARG, "tfi_autotune_fft: null pointer");
+    if (d < 1 || d > (1 << 20)) return fail(TFI_ERR_ARG, "tfi_autotune_fft: need 1 <= d <= 2^20");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == TFI_F32)
+        return tune_fft<float>(h, (const float*)f, (int32_t)d, st, with_backward != 0);
+    if (dtype == TFI_F64)
+        return tune_fft<double>(h, (const double*)f, (int32_t)d, st, with_backward != 0);
+    return fail(TFI_ERR_DTYPE, "tfi_autotune_fft: unknown dtype");
+}
+
+int tfi_set_fft_params(tfi_handle h, const tfi_fft_params* p) {
+    g_err.clear();
+    int rc = check_handle(h, true);
+    if (rc) return rc;
+    if (!p) return fail(TFI_ERR_ARG, "tfi_set_fft_params: null pointer");
+    auto pow2_or0 = [](int32_t v, int32_t hi) { return v == 0 || (v > 0 && v <= hi && !(v & (v - 1))); };
+    for (int t = 0; t < 3; ++t)
+        if (!pow2_or0(p->lds_pairs[t], 64))
+            return fail(TFI_ERR_ARG, "tfi_set_fft_params: lds_pairs must be 0 or a power of two <= 64");
+    if (p->conv1d_min_lg < 2 || p->conv1d_min_lg > 31)
+        return fail(TFI_ERR_ARG, "tfi_set_fft_params: conv1d_min_lg outside [2, 31]");
+    if (!pow2_or0(p->conv1d_pairs, 16))
+        return fail(TFI_ERR_ARG, "tfi_set_fft_params: conv1d_pairs must be 0 or a power of two <= 16");
+    if (p->conv1d_group_mib < 0 || p->conv1d_group_mib > (1 << 20))
+        return fail(TFI_ERR_ARG, "tfi_set_fft_params: conv1d_group_mib outside [0, 2^20]");
+    if (p->col_lines < 1 || p->col_lines > 64 || (p->col_lines & (p->col_lines - 1)))
+        return fail(TFI_ERR_ARG, "tfi_set_fft_params: col_lines must be a power of two <= 64");
+    FftParams q;
+    for (int t = 0; t < 3; ++t) q.lds_pairs[t] = p->lds_pairs[t];
+    q.conv1d_min_lg = p->conv1d_min_lg;
+    q.conv1d_pairs = p->conv1d_pairs;
+    q.conv1d_group_mib = p->conv1d_group_mib;
+    q.col_lines = p->col_lines;
+    return apply_fft_params(h, q);
+}
+
+int tfi_get_fft_params(tfi_handle h, tfi_fft_params* p) {
+    g_err.clear();
+    if (!h || !p) return fail(TFI_ERR_ARG, "tfi_get_fft_params: null argument");
+    for (int t = 0; t < 3; ++t) p->lds_pairs[t] = h->fp.lds_pairs[t];
+    p->conv1d_min_lg = h->fp.conv1d_min_lg;
+    p->conv1d_pairs = h->fp.conv1d_pairs;
+    p->conv1d_group_mib = h->fp.conv1d_group_mib;
+    p->col_lines = h->fp.col_lines;
     return TFI_OK;
 }
 

@@ -123,39 +123,79 @@ class TreeIntegrator:
         kind = self.stats()["arrays"][name]
         arr = np.empty(nbytes // np.dtype(_lib._EXPORT_TYPES[kind]).itemsize,
                        dtype=_lib._EXPORT_TYPES[kind])
+        if arr.nbytes != nbytes:
+            raise _lib.TFIError(-1, f"plan array {name}: {nbytes} bytes is not a whole number "
+                                    f"of {kind} elements")
         if nbytes:
-            _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, nbytes))
+            _lib.check(lib.tfi_plan_export(self._h, name.encode(), arr.ctypes.data, arr.nbytes))
         return arr
 
-    def autotune(self, f, d, cache=None, backward=False):
-        """Choose the per-table method rule (direct sums vs FFT) by timing
-        passes of ``d`` channels in ``f``'s dtype: forward integrations, or
-        forward + adjoint (dF and df) with ``backward=True``; the fastest
-        setting stays in effect. ``cache``: optional JSON file of tuned
-        values keyed by (plan fingerprint, d, dtype, pass), read before and
-        updated after tuning. Returns the chosen cost constant."""
+    def autotune(self, f, d, cache=None, backward=False, fft_shapes=False):
+        """Choose the per-table method rule (direct sums vs FFT) and the
+        cell-sum strategy by timing passes of ``d`` channels in ``f``'s
+        dtype: forward integrations, or forward + adjoint (dF and df) with
+        ``backward=True``; with ``fft_shapes=True`` also the FFT kernels'
+        shapes (``tfi_autotune_fft``). The fastest settings stay in effect.
+        ``cache``: optional JSON file of tuned settings keyed by (plan
+        fingerprint, d, dtype, pass), read before and updated after tuning.
+        Returns the chosen cost constant."""
         self._check(f)
         key = (f"{self.stats()['fingerprint']}:{int(d)}:{str(f.dtype)}:"
-               f"{'fwdbwd' if backward else 'fwd'}")
+               f"{'fwdbwd' if backward else 'fwd'}{':fft' if fft_shapes else ''}")
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as fp:
                 table = json.load(fp)
         lib = _lib.load()
         if key in table:
-            _lib.check(lib.tfi_set_fft_cost(self._h, float(table[key])))
-            return float(table[key])
+            ent = table[key]
+            if not isinstance(ent, dict):
+                ent = {"fft_cost": ent}
+            _lib.check(lib.tfi_set_fft_cost(self._h, float(ent["fft_cost"])))
+            if "scatter" in ent:
+                _lib.check(lib.tfi_set_scatter(self._h, int(ent["scatter"])))
+            if "fft" in ent:
+                self.set_fft_params(**ent["fft"])
+            return float(ent["fft_cost"])
         best = C.c_float()
         _lib.check(lib.tfi_autotune(self._h, f.data_ptr(), int(d), _DTYPES[f.dtype],
                                     1 if backward else 0, C.byref(best),
                                     self._stream(self.device)))
+        if fft_shapes:
+            _lib.check(lib.tfi_autotune_fft(self._h, f.data_ptr(), int(d), _DTYPES[f.dtype],
+                                            1 if backward else 0, self._stream(self.device)))
         if cache:
-            table[key] = best.value
+            table[key] = {"fft_cost": best.value, "scatter": self.stats()["scatter_pick"],
+                          "fft": self.fft_params()}
             tmp = f"{cache}.{os.getpid()}.tmp"
             with open(tmp, "w") as fp:
                 json.dump(table, fp, indent=1, sort_keys=True)
             os.replace(tmp, cache)
         return best.value
+
+    def fft_params(self):
+        """Shapes of the FFT kernels (``tfi_fft_params``) as a dict."""
+        q = _lib.FftParams()
+        _lib.check(_lib.load().tfi_get_fft_params(self._h, C.byref(q)))
+        return {"lds_pairs": list(q.lds_pairs), "conv1d_min_lg": q.conv1d_min_lg,
+                "conv1d_pairs": q.conv1d_pairs, "conv1d_group_mib": q.conv1d_group_mib,
+                "col_lines": q.col_lines}
+
+    def set_fft_params(self, **changes):
+        """Change some of the FFT kernels' shapes (keys of ``fft_params``)."""
+        cur = self.fft_params()
+        unknown = set(changes) - set(cur)
+        if unknown:
+            raise KeyError(f"unknown FFT parameters {sorted(unknown)}")
+        cur.update(changes)
+        q = _lib.FftParams()
+        for t in range(3):
+            q.lds_pairs[t] = int(cur["lds_pairs"][t])
+        q.conv1d_min_lg = int(cur["conv1d_min_lg"])
+        q.conv1d_pairs = int(cur["conv1d_pairs"])
+        q.conv1d_group_mib = int(cur["conv1d_group_mib"])
+        q.col_lines = int(cur["col_lines"])
+        _lib.check(_lib.load().tfi_set_fft_params(self._h, C.byref(q)))
 
     def calibrate(self, f, d):
         """Measure the channel-aware cost model on this plan at ``d``

@@ -36,6 +36,15 @@ def test_build_opts_layout_matches_header():
     assert C.sizeof(_lib.BuildOpts) == 56
 
 
+def test_fft_params_layout_matches_header():
+    text = header()
+    body = text[text.index("typedef struct tfi_fft_params {"):text.index("} tfi_fft_params;")]
+    fields = re.findall(r"^\s*int32_t\s+(\w+)", body, flags=re.M)
+    assert fields == [f[0] for f in _lib.FftParams._fields_]
+    assert C.sizeof(_lib.FftParams) == 28
+    assert _lib.load().tfi_get_fft_params(None, None) == -1
+
+
 def test_last_error_and_null_handle_paths():
     lib = _lib.load()
     assert lib.tfi_kernel_length(None) == -1
