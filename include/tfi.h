@@ -87,7 +87,12 @@ typedef struct {
                                     plan (no device upload; for planning
                                     statistics and host-side tests)        */
     int32_t table_method;        /* 0 = per-job choice, 1 = force direct
-                                    sums, 2 = force FFT for every table    */
+                                    sums, 2 = force FFT for every table,
+                                    3 = tables with several depths and
+                                    several backbone positions as one 1-D
+                                    FFT convolution along the backbone per
+                                    pair of depths (algorithm
+                                    "global-anchor"), the others by FFT    */
     uint64_t memory_budget_bytes;/* cap on device bytes held by the handle
                                     and its per-call scratch; 0 = none.
                                     tfi_integrate and tfi_backward (without

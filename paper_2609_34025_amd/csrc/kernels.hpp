@@ -906,12 +906,14 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
 // (job, channel pair) slot of a bucket, as blocked passes (k_fft_pass) of up
 // to 12 radix-2 stages each, every pass staged through LDS. Buffer layout:
 // slot s = job * npairs + pair holds P complex.
+// rev != 0: source cell (r, x) at row -r mod L1 (the 2-D convolution);
+// rev = 0: at row r (the per-depth rows of the 1-D path).
 template <typename T>
 __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
                               const int32_t* __restrict__ jobs,
                               const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                               const int32_t* __restrict__ jc_val, int32_t d,
-                              const T* __restrict__ val, cpx<T>* __restrict__ buf) {
+                              const T* __restrict__ val, cpx<T>* __restrict__ buf, int rev) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
     const int64_t slot = blockIdx.y;
     const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
@@ -921,7 +923,7 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
          k += gridDim.x * blockDim.x) {
-        const int64_t row = (L1 - jc_r[k]) & (L1 - 1);
+        const int64_t row = rev ? (L1 - jc_r[k]) & (L1 - 1) : jc_r[k];
         const int64_t vr = (int64_t)jc_val[k] * d;
         z[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
     }
@@ -998,18 +1000,20 @@ __global__ void k_spec_mul_global(cpx<T>* __restrict__ buf, int64_t nslots, int 
     buf[tid] = cmul(buf[tid], spec[tid & (P - 1)]);
 }
 
+// Table rows of the cells from the inverse transforms, scaled by 2^-lgS
+// (the points the inverse ran over: P for the 2-D transform, L2 for rows).
 template <typename T>
 __global__ void k_extract_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
                                  const int32_t* __restrict__ jobs,
                                  const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                                  const int32_t* __restrict__ jc_val, int32_t d,
-                                 const cpx<T>* __restrict__ buf, T* __restrict__ g) {
+                                 const cpx<T>* __restrict__ buf, T* __restrict__ g, int lgS) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
     const int64_t slot = blockIdx.y;
     const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
     const int32_t c0 = 2 * pair, c1 = c0 + 1;
     const cpx<T>* z = buf + slot * P;
-    const T scale = (T)1 / (T)P;
+    const T scale = (T)1 / (T)((int64_t)1 << lgS);
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
          k += gridDim.x * blockDim.x) {
@@ -1018,6 +1022,30 @@ __global__ void k_extract_global(int lg1, int lg2, int32_t njobs, int32_t npairs
         g[vr + c0] = y.x * scale;
         if (c1 < d) g[vr + c1] = y.y * scale;
     }
+}
+
+// Depth mixing of the per-depth path (algorithm "global-anchor"): with
+// a[r] the backbone spectrum of depth row r of a slot (rows transformed
+// along the backbone axis) and spec[s] that of kernel row s, f(s + |b|),
+//     out[q][w] = sum_{r <= hmax} spec[q + r][w] a[r][w],   q <= hmax,
+// the spectra of sum_r (f(q + r + |.|) * A_r), one 1-D convolution per
+// depth pair summed before a single inverse transform per output row.
+template <typename T>
+__global__ void k_d1_mix(int lg1, int lg2, int32_t hmax, int64_t nslots,
+                         const cpx<T>* __restrict__ a, const cpx<T>* __restrict__ spec,
+                         cpx<T>* __restrict__ out) {
+    const int64_t L2 = (int64_t)1 << lg2;
+    const int64_t rows = (int64_t)hmax + 1;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= nslots * rows * L2) return;
+    const int64_t w = tid & (L2 - 1);
+    const int64_t q = (tid >> lg2) % rows;
+    const int64_t slot = (tid >> lg2) / rows;
+    const cpx<T>* as = a + (slot << (lg1 + lg2)) + w;
+    const cpx<T>* ks = spec + (q << lg2) + w;
+    cpx<T> acc = {(T)0, (T)0};
+    for (int64_t r = 0; r < rows; ++r) acc = cadd(acc, cmul(ks[r << lg2], as[r << lg2]));
+    out[(slot << (lg1 + lg2)) + (q << lg2) + w] = acc;
 }
 
 template <typename T>

@@ -25,6 +25,7 @@
 #include <type_traits>
 #include <new>
 #include <set>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -80,6 +81,7 @@ struct Bucket {
     bool reflect = false;
     int64_t spec_off = 0;       // element offset into the spectrum arena
     int64_t cells = 0;          // table cells over the bucket's jobs
+    bool d1 = false;            // per-depth 1-D convolutions (METHOD_FFT1D jobs)
     int tc_cap = 0;             // FftParams::conv1d_pairs
     int64_t group_bytes = 0;    // FftParams::conv1d_group_mib in bytes (0 = kConvGroupBytes)
     int64_t P() const { return (int64_t)1 << (lg1 + lg2); }
@@ -958,20 +960,22 @@ int upload_methods(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
     std::vector<int64_t> djobs;  // direct-method jobs
-    std::map<std::pair<int, int>, size_t> bidx;
+    std::map<std::tuple<int, int, bool>, size_t> bidx;
     const int64_t J = (int64_t)p.job_H.size();
     for (int64_t j = 0; j < J; ++j) {
         const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
         if (p.job_method[j] == tfi::METHOD_DIRECT) {
             djobs.push_back(j);
         } else {
-            auto key = std::make_pair((int)p.job_lg1[j], (int)p.job_lg2[j]);
+            const bool d1 = p.job_method[j] == tfi::METHOD_FFT1D;
+            auto key = std::make_tuple((int)p.job_lg1[j], (int)p.job_lg2[j], d1);
             auto it = bidx.find(key);
             if (it == bidx.end()) {
                 it = bidx.emplace(key, h->buckets.size()).first;
                 Bucket b;
-                b.lg1 = key.first;
-                b.lg2 = key.second;
+                b.lg1 = std::get<0>(key);
+                b.lg2 = std::get<1>(key);
+                b.d1 = d1;
                 b.tc_cap = h->fp.conv1d_pairs;
                 b.group_bytes = (int64_t)h->fp.conv1d_group_mib << 20;
                 h->buckets.push_back(b);
@@ -1011,6 +1015,7 @@ int upload_methods(tfi_plan* h) {
             // when one channel pair would fit LDS (the LDS kernels read one
             // pair per workgroup: 8 bytes of every row)
             if ((b.lg1 == 0 || b.lg2 == 0) && b.lg1 + b.lg2 >= h->fp.conv1d_min_lg) t = 3;
+            if (b.d1) t = 3;  // the per-depth path runs through global memory
             if (t == 3) {
                 h->global_b[ti].push_back((int)bi);
                 continue;
@@ -1306,7 +1311,8 @@ int64_t fft_job_bytes(const Bucket& b, int32_t d) {
     const int64_t npairs = (d + 1) / 2;
     const int tc = conv1d_tc<T>(b, d);
     const int64_t pairs = tc ? (npairs + tc - 1) / tc * tc : npairs;
-    return pairs * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+    // the per-depth path keeps the depth-row spectra and the mixed rows
+    return (b.d1 ? 2 : 1) * pairs * b.P() * (int64_t)sizeof(tfi::cpx<T>);
 }
 
 // Work buffer a bucket needs: for the channel-tiled 1-D convolution, the
@@ -1412,6 +1418,51 @@ void launch_conv1d(tfi_plan* h, int tc, const Bucket& b, const int32_t* bmap, in
     }
 }
 
+// Transform along the second table axis only (every row of nrows rows of
+// each of nslots tables of 2^lg1 x 2^lg2 points).
+template <typename T, bool INV>
+void launch_rows(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, int64_t nrows,
+                 const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
+    if (lg2) launch_axis<T, INV>(buf, nslots, lg1 + lg2, lg2, 1, (int64_t)1 << lg2, nrows, 0, tw,
+                                 lgtw, st);
+}
+
+// Per-depth path of one bucket (algorithm "global-anchor"): the depth rows
+// of every (job, channel pair) slot are transformed along the backbone,
+// mixed with the kernel-row spectra (k_d1_mix), and the hmax + 1 output rows
+// transformed back. The work buffer holds the row spectra and the mixed
+// rows of each chunk of slots.
+template <typename T>
+void launch_d1_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T* g,
+                      const tfi::cpx<T>* spec, const tfi::cpx<T>* tw, tfi::cpx<T>* buf,
+                      size_t buf_bytes, hipStream_t st) {
+    const int32_t npairs = (d + 1) / 2;
+    const int64_t P = b.P();
+    const int64_t slots_cap =
+        std::min<int64_t>(65535, (int64_t)(buf_bytes / sizeof(tfi::cpx<T>)) / (2 * P));
+    const int64_t jobs_per_chunk = std::max<int64_t>(1, slots_cap / npairs);
+    for (int64_t j0 = 0; j0 < b.njobs(); j0 += jobs_per_chunk) {
+        const int64_t nj = std::min(jobs_per_chunk, b.njobs() - j0);
+        const int64_t nslots = nj * npairs;
+        const int32_t* jobs = b.d_jobs + 2 * j0;
+        tfi::cpx<T>* mixed = buf + nslots * P;
+        hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * P)), dim3(kThreads),
+                           0, st, buf, nslots * P);
+        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
+                           st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                           h->d_jc_val, d, val, buf, 0);
+        launch_rows<T, false>(buf, nslots, b.lg1, b.lg2, (int64_t)b.hmax + 1, tw, h->lgtw, st);
+        const int64_t n = nslots * ((int64_t)b.hmax + 1) << b.lg2;
+        hipLaunchKernelGGL(tfi::k_d1_mix<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, b.lg1,
+                           b.lg2, b.hmax, nslots, (const tfi::cpx<T>*)buf, spec + b.spec_off,
+                           mixed);
+        launch_rows<T, true>(mixed, nslots, b.lg1, b.lg2, (int64_t)b.hmax + 1, tw, h->lgtw, st);
+        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
+                           0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
+                           h->d_jc_val, d, (const tfi::cpx<T>*)mixed, g, b.lg2);
+    }
+}
+
 // Global-memory FFT passes of one bucket (tables beyond LDS): forward
 // transform of (job, channel pair) slots, product with the spectrum,
 // inverse, read-back.
@@ -1421,6 +1472,10 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
                        size_t buf_bytes, hipStream_t st) {
     if (const int tc = conv1d_tc<T>(b, d)) {
         launch_conv1d<T>(h, tc, b, b.d_map, d, val, g, spec, tw, buf, buf_bytes, st);
+        return;
+    }
+    if (b.d1) {
+        launch_d1_global<T>(h, b, d, val, g, spec, tw, buf, buf_bytes, st);
         return;
     }
     const int32_t npairs = (d + 1) / 2;
@@ -1436,14 +1491,14 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
                            dim3(kThreads), 0, st, buf, nslots * b.P());
         hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, val, buf);
+                           h->d_jc_val, d, val, buf, 1);
         launch_fft2<T, false>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
                            dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
         launch_fft2<T, true>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                            0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, buf, g);
+                           h->d_jc_val, d, buf, g, lgP);
     }
 }
 
@@ -1585,7 +1640,10 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nu
         tfi::cpx<T>* z = spec + b.spec_off;
         hipLaunchKernelGGL(tfi::k_spec_fill_global<T>, dim3(blocks_for(b.P())), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, b.hmax, b.xmax, f, z);
-        launch_fft2<T, false>(z, 1, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
+        if (b.d1)  // kernel rows f(s + |b|), s <= 2 hmax, along the backbone axis only
+            launch_rows<T, false>(z, 1, b.lg1, b.lg2, (int64_t)1 << b.lg1, tw, h->lgtw, st);
+        else
+            launch_fft2<T, false>(z, 1, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
         h->end(st, ev, "spectrum_global", 2.0 * sizeof(T) * (double)b.P());
     }
 }
@@ -1633,7 +1691,7 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
         const Bucket& b = h->buckets[bi];
         hipEvent_t ev = h->begin(st);
         launch_fft_global<T>(h, b, d, val, g, spec, tw, (tfi::cpx<T>*)w.fft, w.fft_bytes, st);
-        h->end(st, ev, conv1d_tc<T>(b, d) ? "fft_conv1d" : "fft_global",
+        h->end(st, ev, conv1d_tc<T>(b, d) ? "fft_conv1d" : (b.d1 ? "fft1d_global" : "fft_global"),
                2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
     }
 }
@@ -2818,6 +2876,8 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     if (po.leaf_max < 1 || po.leaf_max > tfi::kLeafMax)
         return fail(TFI_ERR_ARG, "tfi_build: leaf_max must be in [0, " +
                                      std::to_string(tfi::kLeafMax) + "]");
+    if (o.table_method < 0 || o.table_method > 3)
+        return fail(TFI_ERR_ARG, "tfi_build: table_method must be in [0, 3]");
     po.table_method = o.table_method;
     po.fft_cost = o.fft_cost == 0.0f ? 4.0 : (double)o.fft_cost;
     po.chan_width = o.chan_width == 0 ? 1 : o.chan_width;

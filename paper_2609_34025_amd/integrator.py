@@ -37,7 +37,11 @@ class TreeIntegrator:
     leaf_max  subtrees up to this size are integrated densely (0 = default).
     device  CUDA/HIP device index, or None for a host-only plan (stats and
             plan inspection only).
-    table_method  'auto', 'direct' or 'fft' for every interaction table.
+    table_method  'auto', 'direct' or 'fft' for every interaction table, or
+            'fft1d': tables with several depths and backbone positions as one
+            1-D FFT convolution along the backbone per pair of depths (with
+            policy 'diameter', the paper's Diameter-1D variant), the others
+            by FFT.
     memory_budget  cap in bytes on device memory held by the handle (0 = no cap);
             an integration or adjoint whose scratch would exceed it runs on
             tiles of channels that fit.
