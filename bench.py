@@ -36,6 +36,7 @@ def log(msg):
 
 
 LIB_SOURCES = ["kernels.hpp", "kernels_expsum.hpp", "kernels_conv1d.hpp", "kernels_cells.hpp",
+               "kernels_hankel.hpp",
                "tfi.hip", "plan.cpp", "plan.hpp"]
 
 

@@ -92,7 +92,12 @@ typedef struct {
                                     several backbone positions as one 1-D
                                     FFT convolution along the backbone per
                                     pair of depths (algorithm
-                                    "global-anchor"), the others by FFT    */
+                                    "global-anchor"), the others by FFT,
+                                    4 = such tables with depth H <= 127 by
+                                    the product with the Hankel matrix
+                                    f(l + r) and walks along the backbone
+                                    (attention-width appendix
+                                    "Hankel-GEMM"), the others by FFT      */
     uint64_t memory_budget_bytes;/* cap on device bytes held by the handle
                                     and its per-call scratch; 0 = none.
                                     tfi_integrate and tfi_backward (without

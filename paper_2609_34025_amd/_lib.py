@@ -18,7 +18,7 @@ TFI_F32 = 0
 TFI_F64 = 1
 
 POLICIES = {"adaptive": 0, "diameter": 1, "centroid": 2, "channel": 3}
-TABLE_METHODS = {"auto": 0, "direct": 1, "fft": 2, "fft1d": 3}
+TABLE_METHODS = {"auto": 0, "direct": 1, "fft": 2, "fft1d": 3, "hankel": 4}
 
 STATUS = {0: "ok", -1: "TFI_ERR_ARG", -2: "TFI_ERR_TREE", -3: "TFI_ERR_WEIGHT",
           -4: "TFI_ERR_DTYPE", -5: "TFI_ERR_OOM", -6: "TFI_ERR_BUDGET",

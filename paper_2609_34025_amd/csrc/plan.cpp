@@ -571,9 +571,13 @@ void assign_methods(Plan& plan, const PlanOptions& opt) {
         else if (opt.table_method == 2) m = METHOD_FFT;
         else if (opt.table_method == 3)
             m = (plan.job_H[j] > 0 && plan.job_X[j] > 0) ? METHOD_FFT1D : METHOD_FFT;
+        else if (opt.table_method == 4)
+            m = (plan.job_H[j] > 0 && plan.job_X[j] > 0 && plan.job_H[j] <= kHankelMaxDepth)
+                    ? METHOD_HANKEL
+                    : METHOD_FFT;
         else m = (direct <= fft) ? METHOD_DIRECT : METHOD_FFT;
         plan.job_method[j] = m;
-        if (m != METHOD_DIRECT) plan.sum_P += P;
+        if (m == METHOD_FFT || m == METHOD_FFT1D) plan.sum_P += P;
     }
 }
 
@@ -601,7 +605,7 @@ int build_plan(const int64_t* parent, const int32_t* weight, int64_t N,
                const PlanOptions& opt, Plan& plan, std::string& err) {
     plan = Plan();
     if (opt.policy < 0 || opt.policy > 3 || opt.table_method < 0 ||
-        opt.table_method > 3 || opt.leaf_max < 0 || !(opt.fft_cost > 0.0) ||
+        opt.table_method > 4 || opt.leaf_max < 0 || !(opt.fft_cost > 0.0) ||
         opt.chan_width < 1 || !(opt.cost_vertex >= 0.0) || !(opt.cost_direct > 0.0) ||
         !(opt.cost_fft > 0.0) || !(opt.cost_call >= 0.0)) {
         err = "tfi_build: invalid option";

@@ -29,13 +29,16 @@ namespace tfi {
 // Evaluation of a table job: direct sums, one FFT convolution on the padded
 // lattice (lemma "stad-2d-fft"), or -- tables with several depths and
 // several backbone positions only -- 1-D FFT convolutions along the
-// backbone for every pair of depths (algorithm "global-anchor").
-enum Method : int32_t { METHOD_DIRECT = 0, METHOD_FFT = 1, METHOD_FFT1D = 2 };
+// backbone for every pair of depths (algorithm "global-anchor"), or the
+// product with the Hankel matrix f(l + r) followed by walks along the
+// backbone (the attention-width appendix "Hankel-GEMM"; depth H <= 127).
+enum Method : int32_t { METHOD_DIRECT = 0, METHOD_FFT = 1, METHOD_FFT1D = 2, METHOD_HANKEL = 3 };
+constexpr int32_t kHankelMaxDepth = 127;
 
 struct PlanOptions {
     int32_t policy = 0;       // 0 adaptive, 1 diameter, 2 centroid, 3 channel-aware
     int32_t leaf_max = 32;    // dense tiles for subtrees up to this size
-    int32_t table_method = 0; // 0 choose, 1 direct, 2 fft, 3 fft1d (2-D tables)
+    int32_t table_method = 0; // 0 choose, 1 direct, 2 fft, 3 fft1d, 4 hankel (2-D tables)
     double fft_cost = 4.0;    // direct iff cells^2 <= fft_cost * P log2 P
     // channel-aware cost model (policy 3): a candidate backbone costs
     // cost_call per table job + chan_width x (cost_vertex per incidence,

@@ -34,6 +34,7 @@
 #include "kernels_expsum.hpp"
 #include "kernels_conv1d.hpp"
 #include "kernels_cells.hpp"
+#include "kernels_hankel.hpp"
 #include "plan.hpp"
 
 namespace {
@@ -124,6 +125,20 @@ struct DirectSet {
     double direct_pairs = 0;  // sum over the jobs of cells^2 (unpadded)
 };
 
+// Tables evaluated by the Hankel product and backbone walks
+// (kernels_hankel.hpp), in groups whose B rows share one buffer.
+struct HankelSet {
+    int64_t njobs = 0;
+    int64_t* d_jh = nullptr;        // per job: H, X, map offset, B row offset in its group
+    int32_t* d_map = nullptr;       // per job: (H + 1) x (X + 1) value rows, or -1
+    int32_t* d_bt = nullptr;        // product items (job, t)
+    int32_t* d_ln = nullptr;        // walk items (job, line)
+    std::vector<int64_t> grp_bt, grp_ln;  // item ranges of the groups
+    int64_t max_rows = 0;           // B rows of the largest group
+    double pairs = 0;               // Hankel-product multiply-adds per channel
+    double cells = 0;               // table cells of the jobs
+};
+
 // Pieces of the cell-sum kernel (k_cells): their segments, b-cell and
 // A-cell entries, and the cells cut between pieces (see kernels_cells.hpp).
 struct CellPlan {
@@ -171,6 +186,8 @@ struct tfi_plan {
     // direct tables: every direct job (adjoint, cell-keeping forward), and
     // those of the calls the fused call kernel leaves to the table kernels
     DirectSet dall;
+    HankelSet hk;                   // Hankel-product tables (METHOD_HANKEL)
+    DirectSet dhank;                // the same tables as direct sums, for df
     // cell sums: pieces of the cell-sum kernel
     CellPlan cells;
     // cell sums: levels of bounded segment sums (the other strategy)
@@ -397,6 +414,8 @@ struct tfi_plan {
             for (int k = 0; k < 3; ++k) tiers[t][k] = Tier();
         }
         dall = DirectSet();
+        hk = HankelSet();
+        dhank = DirectSet();
         spec_elems = 0;
         return TFI_OK;
     }
@@ -956,16 +975,69 @@ int build_direct(tfi_plan* h, std::vector<int64_t> djobs, DirectSet& ds) {
     return TFI_OK;
 }
 
+// B rows of one group of Hankel tables (a larger table is a group alone).
+constexpr int64_t kHankGroupRows = (int64_t)1 << 21;
+
+int build_hankel(tfi_plan* h, const std::vector<int64_t>& hjobs) {
+    const tfi::Plan& p = h->plan;
+    HankelSet& k = h->hk;
+    k = HankelSet();
+    if (hjobs.empty()) return TFI_OK;
+    std::vector<int64_t> jh;
+    std::vector<int32_t> map, bt, ln;
+    int64_t rows_in = 0;
+    k.grp_bt.push_back(0);
+    k.grp_ln.push_back(0);
+    auto close = [&]() {
+        k.grp_bt.push_back((int64_t)bt.size() / 2);
+        k.grp_ln.push_back((int64_t)ln.size() / 2);
+        k.max_rows = std::max(k.max_rows, rows_in);
+        rows_in = 0;
+    };
+    for (int64_t j : hjobs) {
+        const int32_t H = p.job_H[j], X = p.job_X[j];
+        const int64_t rows = (int64_t)(H + X + 1) * (X + 1);
+        if (H > tfi::kHankHmax || H < 0 || X < 0)
+            return fail(TFI_ERR_STATE, "Hankel table outside the kernel's limits");
+        if (rows_in > 0 && rows_in + rows > kHankGroupRows) close();
+        const int64_t mapoff = (int64_t)map.size();
+        map.resize((size_t)(mapoff + (int64_t)(H + 1) * (X + 1)), -1);
+        for (int64_t c = p.job_cell_off[j]; c < p.job_cell_off[j + 1]; ++c) {
+            if (p.jc_r[c] < 0 || p.jc_r[c] > H || p.jc_x[c] < 0 || p.jc_x[c] > X)
+                return fail(TFI_ERR_STATE, "Hankel table cell outside its job's range");
+            map[(size_t)(mapoff + (int64_t)p.jc_r[c] * (X + 1) + p.jc_x[c])] = p.jc_val[c];
+        }
+        const int32_t jid = (int32_t)(jh.size() / 4);
+        jh.insert(jh.end(), {(int64_t)H, (int64_t)X, mapoff, rows_in});
+        for (int32_t t = 0; t <= X; ++t) bt.insert(bt.end(), {jid, t});
+        for (int32_t l = 0; l <= H + X; ++l) ln.insert(ln.end(), {jid, l});
+        rows_in += rows;
+        k.pairs += (double)(H + X + 1) * (H + 1) * (X + 1);
+        k.cells += (double)(p.job_cell_off[j + 1] - p.job_cell_off[j]);
+    }
+    close();
+    k.njobs = (int64_t)hjobs.size();
+    int rc;
+    if ((rc = h->upload_m(&k.d_jh, jh))) return rc;
+    if ((rc = h->upload_m(&k.d_map, map))) return rc;
+    if ((rc = h->upload_m(&k.d_bt, bt))) return rc;
+    if ((rc = h->upload_m(&k.d_ln, ln))) return rc;
+    return TFI_OK;
+}
+
 int upload_methods(tfi_plan* h) {
     const tfi::Plan& p = h->plan;
     int rc;
     std::vector<int64_t> djobs;  // direct-method jobs
+    std::vector<int64_t> hjobs;  // Hankel-product jobs
     std::map<std::tuple<int, int, bool>, size_t> bidx;
     const int64_t J = (int64_t)p.job_H.size();
     for (int64_t j = 0; j < J; ++j) {
         const int32_t cb = (int32_t)p.job_cell_off[j], ce = (int32_t)p.job_cell_off[j + 1];
         if (p.job_method[j] == tfi::METHOD_DIRECT) {
             djobs.push_back(j);
+        } else if (p.job_method[j] == tfi::METHOD_HANKEL) {
+            hjobs.push_back(j);
         } else {
             const bool d1 = p.job_method[j] == tfi::METHOD_FFT1D;
             auto key = std::make_tuple((int)p.job_lg1[j], (int)p.job_lg2[j], d1);
@@ -991,6 +1063,8 @@ int upload_methods(tfi_plan* h) {
         }
     }
     if ((rc = build_direct(h, djobs, h->dall))) return rc;
+    if ((rc = build_hankel(h, hjobs))) return rc;
+    if ((rc = build_direct(h, hjobs, h->dhank))) return rc;
 
     h->spec_elems = 0;
     for (Bucket& b : h->buckets) {
@@ -1545,6 +1619,10 @@ WorkSizes forward_sizes(const tfi_plan* h, int32_t d, bool general = false, int 
     }
     z.spec = (size_t)nk * std::max<int64_t>(h->spec_elems, 1) * sizeof(tfi::cpx<T>);
     for (int bi : h->global_b[ti]) z.fft = std::max(z.fft, fft_buf_bytes<T>(h->buckets[bi], d));
+    // the Hankel tables' B rows share the buffer (same stream, after the FFTs)
+    if (h->hk.njobs)
+        z.fft = std::max(z.fft, (size_t)h->hk.max_rows * std::min<int32_t>(d, tfi::kHankCh) *
+                                    sizeof(T));
     return z;
 }
 
@@ -1694,6 +1772,34 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
         h->end(st, ev, conv1d_tc<T>(b, d) ? "fft_conv1d" : (b.d1 ? "fft1d_global" : "fft_global"),
                2.0 * sz * d * (double)b.cells + 12.0 * b.cells + 2.0 * sz * b.P());
     }
+}
+
+// Hankel-product tables (kernels_hankel.hpp): per chunk of at most 64
+// channels and group of tables, the product B (one workgroup per backbone
+// column) and the two walks; B lives in the FFT work buffer.
+template <typename T>
+void enq_hankel(tfi_plan* h, const T* f, int32_t d, const T* val, T* g, hipStream_t st,
+                const Work& w) {
+    const HankelSet& k = h->hk;
+    if (!k.njobs) return;
+    hipEvent_t ev = h->begin(st);
+    T* B = (T*)w.fft;
+    for (int32_t c0 = 0; c0 < d; c0 += tfi::kHankCh) {
+        const int32_t cw = std::min<int32_t>(tfi::kHankCh, d - c0);
+        for (size_t gi = 0; gi + 1 < k.grp_bt.size(); ++gi) {
+            const int64_t b0 = k.grp_bt[gi], nb = k.grp_bt[gi + 1] - b0;
+            const int64_t l0 = k.grp_ln[gi], nl = k.grp_ln[gi + 1] - l0;
+            const unsigned wb = (unsigned)((nl + 3) / 4);  // 4 items of 64 lanes per block
+            hipLaunchKernelGGL(tfi::k_hankel_b<T>, dim3((unsigned)nb), dim3(256), 0, st,
+                               k.d_bt + 2 * b0, k.d_jh, k.d_map, f, val, d, c0, cw, B);
+            hipLaunchKernelGGL((tfi::k_hankel_walk<T, true>), dim3(wb), dim3(256), 0, st, nl,
+                               k.d_ln + 2 * l0, k.d_jh, k.d_map, (const T*)B, d, c0, cw, g);
+            hipLaunchKernelGGL((tfi::k_hankel_walk<T, false>), dim3(wb), dim3(256), 0, st, nl,
+                               k.d_ln + 2 * l0, k.d_jh, k.d_map, (const T*)B, d, c0, cw, g);
+        }
+    }
+    const double sz = (double)sizeof(T);
+    h->end(st, ev, "hankel", 2.0 * sz * d * k.cells + 8.0 * k.cells, 2.0 * d * k.pairs);
 }
 
 // Direct tables of one kernel (f into g), or of two (also f1 into g1): on
@@ -1854,9 +1960,9 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
 }
 
 template <typename T>
-void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* df,
-                   hipStream_t st) {
-    if (h->dall.ndblk == 0) return;
+void enq_df_direct(tfi_plan* h, const DirectSet& ds, int32_t d, const T* val, const T* valg,
+                   double* df, hipStream_t st) {
+    if (ds.ndblk == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
     const bool mfma = sizeof(T) == 4 && (h->direct_kernel == 2 || (h->direct_kernel == 0 && d >= 8));
@@ -1866,9 +1972,9 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
         // histogram copies: as many as fit (up to 16) in 80 KiB of LDS, so
         // that two blocks share a CU; none when one copy does not fit
         auto launch = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3((unsigned)h->dall.ndblk), dim3(tfi::kDirThreads), 0, st, d,
-                               p.NA, h->dall.d_dblk, h->dall.d_dl_r, h->dall.d_dl_x, h->dall.d_dl_row, h->dall.d_qjb,
-                               h->dall.d_qje, (const float*)val, (const float*)valg, h->dall.d_dbin, df);
+            hipLaunchKernelGGL(kern, dim3((unsigned)ds.ndblk), dim3(tfi::kDirThreads), 0, st, d,
+                               p.NA, ds.d_dblk, ds.d_dl_r, ds.d_dl_x, ds.d_dl_row, ds.d_qjb,
+                               ds.d_qje, (const float*)val, (const float*)valg, ds.d_dbin, df);
         };
         switch (cpl) {
             case 16: launch(tfi::k_df_direct_mfma<16>); break;
@@ -1878,13 +1984,13 @@ void enq_df_direct(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
             default: launch(tfi::k_df_direct_mfma<1>); break;
         }
     } else {
-        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)h->dall.ndblk), dim3(tfi::kDfThreads), 0,
-                           st, d, p.NA, h->dall.d_dblk, h->dall.d_dl_r, h->dall.d_dl_x, h->dall.d_dl_row, h->dall.d_qjb,
-                           h->dall.d_qje, val, valg, h->dall.d_dbin, df);
+        hipLaunchKernelGGL(tfi::k_df_direct<T>, dim3((unsigned)ds.ndblk), dim3(tfi::kDfThreads), 0,
+                           st, d, p.NA, ds.d_dblk, ds.d_dl_r, ds.d_dl_x, ds.d_dl_row, ds.d_qjb,
+                           ds.d_qje, val, valg, ds.d_dbin, df);
     }
     h->end(st, ev, mfma ? "df_direct_mfma" : "df_direct",
-           2.0 * sizeof(T) * d * (double)h->dall.ndirect + 20.0 * h->dall.ndirect,
-           2.0 * d * h->dall.direct_pairs);
+           2.0 * sizeof(T) * d * (double)ds.ndirect + 20.0 * ds.ndirect,
+           2.0 * d * ds.direct_pairs);
 }
 
 template <typename T>
@@ -1915,7 +2021,7 @@ bool fft_work(const tfi_plan* h) {
     const int ti = sizeof(T) == 8 ? 1 : 0;
     for (int t = 0; t < 3; ++t)
         if (h->tiers[ti][t].nbuckets || h->tiers[ti][t].njobs) return true;
-    return !h->global_b[ti].empty();
+    return !h->global_b[ti].empty() || h->hk.njobs > 0;
 }
 
 // Fork the side streams that have work from s0.
@@ -1971,6 +2077,7 @@ void enqueue_forward(tfi_plan* h, const T* f, const T* F, int32_t d, T* out, hip
         (void)hipEventRecord(h->ev_a, s0);
         (void)hipStreamWaitEvent(s1, h->ev_a, 0);
         enq_fft<T>(h, d, val, g, s1, w);        // side1: FFT tables
+        enq_hankel<T>(h, f, d, val, g, s1, w);  // side1: Hankel-product tables
         (void)hipEventRecord(h->ev_b, s1);
     }
     enq_direct<T>(h, h->dall, f, d, val, g, s0);  // main: direct tables
@@ -2019,8 +2126,10 @@ void enqueue_forward_multi(tfi_plan* h, int nk, const T* const* f, const T* F, i
     if (use1) {
         (void)hipEventRecord(h->ev_a, s0);
         (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-        for (int i = 0; i < nk; ++i)
+        for (int i = 0; i < nk; ++i) {
             enq_fft<T>(h, d, val, g0 + i * gstride, s1, w, spec0 + i * sstride);
+            enq_hankel<T>(h, f[i], d, val, g0 + i * gstride, s1, w);
+        }
         (void)hipEventRecord(h->ev_b, s1);
     }
     // kernels in pairs: one launch per pair for the direct tables and the
@@ -2071,13 +2180,17 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     launch_scatter<T>(h, gout, valg, (T*)h->partg[ti].p, d, s0);
     (void)hipEventRecord(h->ev_a, s0);
     (void)hipStreamWaitEvent(s1, h->ev_a, 0);
-    if (dF) enq_fft<T>(h, d, valg, g, s1, w);
+    if (dF) {
+        enq_fft<T>(h, d, valg, g, s1, w);
+        enq_hankel<T>(h, f, d, valg, g, s1, w);
+    }
     if (df) enq_df_tables<T>(h, d, valF, valg, df, s1);
     (void)hipEventRecord(h->ev_b, s1);
     if (dF) enq_direct<T>(h, h->dall, f, d, valg, g, s0);
     if (df) {
         (void)hipStreamWaitEvent(s0, h->ev_d, 0);
-        enq_df_direct<T>(h, d, valF, valg, df, s0);
+        enq_df_direct<T>(h, h->dall, d, valF, valg, df, s0);
+        enq_df_direct<T>(h, h->dhank, d, valF, valg, df, s0);
     }
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
@@ -2876,8 +2989,8 @@ int tfi_build(const int64_t* parent, const int32_t* weight, int64_t N,
     if (po.leaf_max < 1 || po.leaf_max > tfi::kLeafMax)
         return fail(TFI_ERR_ARG, "tfi_build: leaf_max must be in [0, " +
                                      std::to_string(tfi::kLeafMax) + "]");
-    if (o.table_method < 0 || o.table_method > 3)
-        return fail(TFI_ERR_ARG, "tfi_build: table_method must be in [0, 3]");
+    if (o.table_method < 0 || o.table_method > 4)
+        return fail(TFI_ERR_ARG, "tfi_build: table_method must be in [0, 4]");
     po.table_method = o.table_method;
     po.fft_cost = o.fft_cost == 0.0f ? 4.0 : (double)o.fft_cost;
     po.chan_width = o.chan_width == 0 ? 1 : o.chan_width;
@@ -3177,7 +3290,8 @@ int64_t tfi_plan_stats(tfi_handle h, char* json, size_t cap) {
          std::to_string(h->popt.fft_cost);
     s += ",\"scatter_pick\":" + std::to_string(h->scatter_pick) +
          ",\"cell_pieces\":" + std::to_string(h->cells.npieces) +
-         ",\"cell_cuts\":" + std::to_string(h->cells.ncomb);
+         ",\"cell_cuts\":" + std::to_string(h->cells.ncomb) +
+         ",\"hankel_jobs\":" + std::to_string(h->hk.njobs);
     s += ",\"device\":" + std::to_string(h->device) +
          ",\"device_bytes\":" + std::to_string(h->dev_bytes) +
          ",\"arrays\":{\"job_H\":\"i32\",\"job_X\":\"i32\",\"job_sign\":\"i32\","

@@ -41,7 +41,9 @@ class TreeIntegrator:
             'fft1d': tables with several depths and backbone positions as one
             1-D FFT convolution along the backbone per pair of depths (with
             policy 'diameter', the paper's Diameter-1D variant), the others
-            by FFT.
+            by FFT; or 'hankel': such tables of depth <= 127 by the product
+            with the Hankel matrix f(l + r) and walks along the backbone, the
+            others by FFT.
     memory_budget  cap in bytes on device memory held by the handle (0 = no cap);
             an integration or adjoint whose scratch would exceed it runs on
             tiles of channels that fit.

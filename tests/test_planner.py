@@ -321,12 +321,15 @@ def test_channel_policy_rejects_bad_cost_model():
 def test_fft1d_method_assignment():
     """table_method 'fft1d' gives the per-depth-pair method (2) to exactly the
     tables with several depths and several backbone positions, FFT (1) to
-    the others; a method outside [0, 3] is refused."""
+    the others; with 'hankel' (4) the tables of depth <= 127 among them get
+    the Hankel product (3); a method outside [0, 4] is refused."""
     p, w = S.caterpillar_hanging_paths(20)
     t = TreeIntegrator(p, w, device=None, policy="diameter", table_method="fft1d")
     H, X, m = t.export("job_H"), t.export("job_X"), t.export("job_method")
     two_d = (H > 0) & (X > 0)
     assert two_d.any() and (~two_d).any()
     assert np.array_equal(m, np.where(two_d, 2, 1))
+    t = TreeIntegrator(p, w, device=None, policy="diameter", table_method="hankel")
+    assert np.array_equal(t.export("job_method"), np.where(two_d & (H <= 127), 3, 1))
     with pytest.raises(TFIError, match="table_method"):
-        TreeIntegrator(p, w, device=None, table_method=4)
+        TreeIntegrator(p, w, device=None, table_method=5)
