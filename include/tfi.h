@@ -111,7 +111,11 @@ typedef struct {
     float fft_cost;              /* per-job rule: direct sums if
                                     cells^2 <= fft_cost * P log2 P, FFT
                                     otherwise (P = padded table cells);
-                                    0 = default (4)                        */
+                                    0 = default (4). A table with depths
+                                    0 < H <= 127 and backbone positions
+                                    X > 0 takes the Hankel product
+                                    (table_method 4) when (H + X + 1)
+                                    (X + 1)(H + 3) is below both           */
     int32_t direct_kernel;       /* direct sums: 0 = matrix cores for FP32
                                     with d >= 8, vector ALU otherwise;
                                     1 = vector ALU; 2 = matrix cores when

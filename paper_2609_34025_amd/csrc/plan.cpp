@@ -575,7 +575,17 @@ void assign_methods(Plan& plan, const PlanOptions& opt) {
             m = (plan.job_H[j] > 0 && plan.job_X[j] > 0 && plan.job_H[j] <= kHankelMaxDepth)
                     ? METHOD_HANKEL
                     : METHOD_FFT;
-        else m = (direct <= fft) ? METHOD_DIRECT : METHOD_FFT;
+        else {
+            m = (direct <= fft) ? METHOD_DIRECT : METHOD_FFT;
+            // tables with several depths and backbone positions: the Hankel
+            // product and walks when their multiply-adds, (H + X + 1)(H + 1)
+            // (X + 1) plus two walks over B, undercut both
+            const int64_t H = plan.job_H[j], X = plan.job_X[j];
+            if (H > 0 && X > 0 && H <= kHankelMaxDepth) {
+                const double hank = (double)(H + X + 1) * (double)(X + 1) * (double)(H + 3);
+                if (hank < std::min(direct, fft)) m = METHOD_HANKEL;
+            }
+        }
         plan.job_method[j] = m;
         if (m == METHOD_FFT || m == METHOD_FFT1D) plan.sum_P += P;
     }

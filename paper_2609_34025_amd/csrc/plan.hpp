@@ -39,7 +39,9 @@ struct PlanOptions {
     int32_t policy = 0;       // 0 adaptive, 1 diameter, 2 centroid, 3 channel-aware
     int32_t leaf_max = 32;    // dense tiles for subtrees up to this size
     int32_t table_method = 0; // 0 choose, 1 direct, 2 fft, 3 fft1d, 4 hankel (2-D tables)
-    double fft_cost = 4.0;    // direct iff cells^2 <= fft_cost * P log2 P
+    double fft_cost = 4.0;    // direct iff cells^2 <= fft_cost * P log2 P; a table with
+                              // 0 < H <= 127 and X > 0 takes the Hankel product when
+                              // (H + X + 1)(X + 1)(H + 3) is below both
     // channel-aware cost model (policy 3): a candidate backbone costs
     // cost_call per table job + chan_width x (cost_vertex per incidence,
     // cost_direct per direct cell pair, cost_fft per P log2 P of an FFT)
