@@ -29,6 +29,9 @@ METRIC = ("vertex·channels integrated/s, fwd+bwd batched vs plain fwd, "
 
 # published dense peaks of one MI355X (FP32 vector includes packed issue)
 PEAK_TFLOPS = {"mfma": {"f32": 157.3, "f64": 78.6}, "alu": {"f32": 157.3, "f64": 78.6}}
+# the vector roof without packed FP32 issue, which the library's build turns
+# off: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+ALU_UNPACKED_TFLOPS = {"f32": 78.6, "f64": 78.6}
 
 
 def log(msg):
@@ -78,6 +81,9 @@ def stage_roofline(name, sd, dtype, workload=None, plan="-"):
         tfs = flops / sec / 1e12
         r = {"bound": unit, "achieved": round(tfs, 3), "peak": peak_tf, "unit": "TFLOP/s",
              "frac": round(tfs / peak_tf, 4), "hbm_gbs": round(gbs, 2)}
+        if unit == "alu":
+            up = ALU_UNPACKED_TFLOPS[dtype]
+            r.update({"peak_unpacked": up, "frac_unpacked": round(tfs / up, 4)})
     else:
         r = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
              "frac": round(gbs / HBM_PEAK_GBS, 4)}
@@ -129,6 +135,12 @@ def main():
                     help="skip the FP64 2000-vertex, Sinkhorn and 2M-vertex configurations")
     ap.add_argument("--configs-only", action="store_true",
                     help="run only those three configurations")
+    ap.add_argument("--ablation", action="store_true",
+                    help="also run the decomposition/evaluator ablation on six families, in "
+                         "a child process (off by default: its one run ended in a host "
+                         "heap-corruption abort, no cause shown yet)")
+    ap.add_argument("--ablation-only", action="store_true",
+                    help="run only that ablation")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM counters)")
     args = ap.parse_args()
@@ -149,6 +161,9 @@ def main():
         return
     if args.families_only:
         print(json.dumps({"family_sweep": family_sweep(args)}), flush=True)
+        return
+    if args.ablation_only:
+        print(json.dumps({"policy_ablation": policy_ablation(args)}), flush=True)
         return
     if args.configs_only:
         print(json.dumps({"small_fp64": small_fp64(args), "sinkhorn": sinkhorn_sphere(args),
@@ -309,6 +324,7 @@ def main():
     if not args.no_configs:
         small, sink, large = small_fp64(args), sinkhorn_sphere(args), large_trees(args)
     families = family_sweep(args) if (args.families and not args.no_families) else None
+    ablation = child_section("--ablation-only", "policy_ablation") if args.ablation else None
 
     rec = {
         "metric": METRIC, "value": value, "unit": "vertex*channels/s", "n_gpus": 1,
@@ -338,6 +354,7 @@ def main():
         "sinkhorn": sink,
         "large": large,
         "family_sweep": families,
+        "policy_ablation": ablation,
         "stages": stages,
     }
     print(json.dumps(rec), flush=True)
@@ -777,6 +794,109 @@ PAPER_FAMILY_MS = {
     "long_arm_spider": (259.52, 382.98, 20.33), "star": (25.25, 23.52, 25.02),
     "random_recursive": (43.73, 18.29, 38.83), "random_mst_topology": (46.37, 17.09, 41.79),
     "preferential_attachment": (38.42, 21.14, 33.22)}
+
+
+def child_section(flag, key, timeout=900):
+    """Run one section of this script in a child process (its own HIP
+    context) and return its record; a child that fails leaves an error
+    record instead of ending the whole run."""
+    import subprocess
+    t0 = time.perf_counter()
+    r = subprocess.run([sys.executable, "-u", os.path.abspath(__file__), flag],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True,
+                       timeout=timeout)
+    for line in r.stderr.splitlines():
+        if line.startswith("bench") or line.startswith("ablation"):
+            log(line)
+    lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return {"error": f"child exited with status {r.returncode}",
+                "stderr_tail": r.stderr[-2000:], "s": round(time.perf_counter() - t0, 1)}
+    return json.loads(lines[-1])[key]
+
+
+# Diameter-1D times of table "synthetic-largest" (CPU, Python; context only)
+PAPER_D1_MS = {"balanced_binary": 49.46, "complete_3ary": 63.56,
+               "caterpillar_hanging_paths": 62.78, "uniform_spider": 32.04,
+               "long_arm_spider": 70288.89, "random_recursive": 37.48}
+
+ABLATION_VARIANTS = [  # (label, policy, table method)
+    ("centroid_fft", "centroid", "fft"),   # centroid-only decomposition (FTFI-style)
+    ("D1", "diameter", "fft1d"),           # Diameter + per-depth-pair 1-D FFTs
+    ("D2", "diameter", "fft"),             # Diameter + 2-D FFT
+    ("A2", "adaptive", "fft"),             # Adaptive + 2-D FFT
+    ("diameter_hankel", "diameter", "hankel"),  # Diameter + Hankel product
+    ("adaptive_auto", "adaptive", "auto"),  # the library's default rule
+]
+
+
+def policy_ablation(args):
+    """Decomposition and evaluator variants of the paper's ablation (table
+    "synthetic-largest": FTFI, D1, D2, A2) plus the Hankel product and the
+    library's default, on six of the fifteen families at their largest
+    sizes: ms per integration (graph replay) of a scalar FP64 field with
+    f(d) = 1/(1+d), the paper's setting, and of an FP32 field of 64
+    channels; parity against the FP64 oracle on every row (scalar) or 16
+    sampled rows (64 channels). One handle per (family, variant)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2609_34025_amd import TreeIntegrator, synth as S
+
+    dev = torch.device("cuda", 0)
+    fams = {name: (p, w) for name, p, w in S.paper_families()}
+    out = []
+    worst = 0.0
+    for name in PAPER_D1_MS:
+        p, w = fams[name]
+        n = len(p)
+        rng = np.random.default_rng(321)
+        F1 = rng.standard_normal(n)
+        F64 = rng.standard_normal((n, 64)).astype(np.float32)
+        rows = np.sort(rng.choice(n, 16, replace=False))
+        rec = {"family": name, "N": n, "ms_scalar_fp64": {}, "ms_d64_fp32": {},
+               "root": {}, "methods": {},
+               "paper_cpu_ms": {"FTFI": PAPER_FAMILY_MS[name][0], "D1": PAPER_D1_MS[name],
+                                "D2": PAPER_FAMILY_MS[name][1], "A2": PAPER_FAMILY_MS[name][2]}}
+        for label, pol, meth in ABLATION_VARIANTS:
+            tfi = TreeIntegrator(p, w, device=0, policy=pol, table_method=meth)
+            K = tfi.kernel_length
+            tab = 1.0 / (1.0 + np.arange(K, dtype=np.float64))
+            st = tfi.stats()
+            rec["root"][label] = [st["root"]["m"], st["root"]["H"]]
+            m = tfi.export("job_method")
+            rec["methods"][label] = {k: int((m == v).sum()) for k, v in
+                                     (("direct", 0), ("fft", 1), ("fft1d", 2), ("hankel", 3))}
+            for key, dt, Fh, bar in (("ms_scalar_fp64", torch.float64, F1, 1e-10),
+                                     ("ms_d64_fp32", torch.float32, F64, 1e-4)):
+                f = torch.tensor(tab, dtype=dt, device=dev)
+                Fd = torch.tensor(Fh, device=dev)
+                for _ in range(3):
+                    y = tfi.integrate(f, Fd)
+                torch.cuda.synchronize()
+                reps = 20
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    y = tfi.integrate(f, Fd)
+                torch.cuda.synchronize()
+                rec[key][label] = round(1e3 * (time.perf_counter() - t0) / reps, 4)
+                if Fh.ndim == 1:
+                    ref = oracle.integrate(p, w, tab, Fh)
+                    got = y.cpu().numpy()
+                else:
+                    ref = oracle.integrate(p, w, tab, Fh.astype(np.float64), rows=rows)
+                    got = y[rows].double().cpu().numpy()
+                err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+                worst = max(worst, err / bar)
+            tfi.close()
+        out.append(rec)
+        log(f"ablation[{name} N={n}] scalar fp64 ms {rec['ms_scalar_fp64']}")
+    return {"unit": "ms per integration (graph replay)", "kernel": "f(d) = 1/(1+d)",
+            "variants": {l: f"policy {p}, table method {m}" for l, p, m in ABLATION_VARIANTS},
+            "parity_ok": worst <= 1.0, "worst_err_over_bar": worst,
+            "paper_cpu_ms": "table synthetic-largest, CPU Python, context only",
+            "families": out}
 
 
 def family_sweep(args):

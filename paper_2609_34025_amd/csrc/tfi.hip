@@ -2858,7 +2858,10 @@ int time_pass(tfi_plan* h, const T* f, int32_t d, hipStream_t st, int reps, bool
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->drop_graphs();  // they captured the temporary buffers
+    // graphs are dropped after the whole device has drained, as everywhere
+    // else (they captured the temporary buffers)
+    (void)hipDeviceSynchronize();
+    h->drop_graphs();
     release();
     return rc;
 }
