@@ -12,8 +12,9 @@
 //   gather   : out[v] = sum over the calls holding v of G - E
 //              (lemma "stad-cross");
 //   leaves   : dense f(D) F on small subtrees.
-// No floating-point atomics: every sum has a fixed order, so results are
-// bitwise reproducible run to run.
+// No floating-point atomics: every sum has a fixed order, or (the histograms
+// of the kernel-table gradient) is an integer sum, so results are bitwise
+// reproducible run to run.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -1085,27 +1086,64 @@ namespace tfi {
 // sign * sum_{i, j} [r_i + r_j + |x_i - x_j| = k] <gbar_i, val_j>, where
 // gbar and val are the same cell sums applied to gout and F (call jobs
 // sign +1 on A-cell rows < NA, corrections sign -1 on b-cell rows), and
-// every leaf tile adds its own dense pair histogram. Histograms accumulate
-// in FP64 (LDS bins flushed with FP64 atomics): df is reproducible to FP64
-// rounding, not bitwise.
+// every leaf tile adds its own dense pair histogram.
+//
+// The histograms accumulate in fixed point, so that no sum depends on the
+// order of its additions and df is bitwise reproducible: a contribution v
+// splits into hi = floor(v 2^14) and lo = round(frac(v 2^14) 2^33), two
+// 64-bit integers summed with integer atomics (in LDS bins per workgroup,
+// normalised and added to the global accumulator), and df = hi 2^-14 +
+// lo 2^-47 at the end (k_df_finish). Resolution 2^-47 (7e-15) per
+// contribution; |df| below 2^49 (5.6e14).
 constexpr int kDfTile = 64, kDfThreads = 256;
-// LDS histogram bins: 16 KiB in the working precision
-template <typename T>
-constexpr int df_hist_bins() { return 16384 / (int)sizeof(T); }
+constexpr int kDfHiExp = 14, kDfLoBits = 33;
+using u64 = unsigned long long;
+// LDS histogram bins of 16 bytes: 16 KiB, 32 KiB for the matrix-core kernel
+constexpr int kDfBins = 1024, kDfBinsMfma = 2048;
 
-// Histogram bin add: LDS bins in the working precision when the kernel
-// table fits, else straight FP64 atomics in global memory.
-template <typename T>
-__device__ __forceinline__ void hist_add(T* lh, double* gh, int32_t k, T v) {
-    if (lh) atomicAdd(lh + k, v);
-    else atomicAdd(gh + k, (double)v);
+__device__ __forceinline__ void df_atomic(u64* acc, int32_t k, double v) {
+    const double s = v * (double)(1 << kDfHiExp);  // exact
+    const double fl = floor(s);
+    const u64 hi = (u64)(long long)fl;
+    const u64 lo = (u64)__double2ll_rn((s - fl) * (double)(1ull << kDfLoBits));
+    if (hi) atomicAdd(acc + 2 * k, hi);
+    if (lo) atomicAdd(acc + 2 * k + 1, lo);
 }
 
+// Histogram bin add: LDS bins when the block's bins fit, else the global
+// accumulator.
 template <typename T>
-__device__ __forceinline__ void hist_flush(const T* lh, double* gh, int32_t K) {
+__device__ __forceinline__ void hist_add(u64* lh, u64* gh, int32_t k, T v) {
+    df_atomic(lh ? lh : gh, k, (double)v);
+}
+
+__device__ __forceinline__ void hist_clear(u64* lh, int32_t K) {
+    for (int32_t k = threadIdx.x; k < 2 * K; k += blockDim.x) lh[k] = 0;
+}
+
+// LDS bins into the global accumulator, each normalised (lo < 2^33) first.
+__device__ __forceinline__ void hist_flush(const u64* lh, u64* gh, int32_t K) {
     __syncthreads();
-    for (int32_t k = threadIdx.x; k < K; k += blockDim.x)
-        if (lh[k] != (T)0) atomicAdd(gh + k, (double)lh[k]);
+    for (int32_t k = threadIdx.x; k < K; k += blockDim.x) {
+        u64 hi = lh[2 * k], lo = lh[2 * k + 1];
+        hi += lo >> kDfLoBits;
+        lo &= (1ull << kDfLoBits) - 1;
+        if (hi) atomicAdd(gh + 2 * k, hi);
+        if (lo) atomicAdd(gh + 2 * k + 1, lo);
+    }
+}
+
+// df[k] (or df[k] + the new value when accumulate) from the accumulator.
+__global__ void k_df_finish(const u64* __restrict__ acc, int64_t K, double* __restrict__ df,
+                            int accumulate) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    u64 hi = acc[2 * k], lo = acc[2 * k + 1];
+    hi += lo >> kDfLoBits;
+    lo &= (1ull << kDfLoBits) - 1;
+    const double v = (double)(long long)hi * (1.0 / (double)(1 << kDfHiExp)) +
+                     (double)lo * (1.0 / (double)(1ull << (kDfHiExp + kDfLoBits)));
+    df[k] = accumulate ? df[k] + v : v;
 }
 
 // Direct jobs: same blocks as k_direct, output cells taken 64 at a time.
@@ -1118,15 +1156,14 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
             const int32_t* __restrict__ qje, const T* __restrict__ val,
             const T* __restrict__ valg, const int32_t* __restrict__ dbin,
-            double* __restrict__ df) {
+            u64* __restrict__ df) {
     __shared__ T sG[kDfTile * (kDirCh + 1)], sV[kDfTile * (kDirCh + 1)];
     __shared__ int32_t sr[kDfTile], sx[kDfTile];
-    __shared__ T lh[df_hist_bins<T>()];
+    __shared__ u64 lh[2 * kDfBins];
     const int32_t Kb = dbin[blockIdx.x];  // bins this block can reach
-    const bool use_lds = Kb <= df_hist_bins<T>();
-    T* lhp = use_lds ? lh : nullptr;
-    if (use_lds)
-        for (int32_t k = threadIdx.x; k < Kb; k += blockDim.x) lh[k] = 0;
+    const bool use_lds = Kb <= kDfBins;
+    u64* lhp = use_lds ? lh : nullptr;
+    if (use_lds) hist_clear(lh, Kb);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int32_t ii = threadIdx.x & (kDfTile - 1), jj0 = threadIdx.x >> 6;
     for (int32_t oc = os; oc < oe; oc += kDfTile) {
@@ -1196,7 +1233,7 @@ k_df_direct(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             }
         }
     }
-    if (use_lds) hist_flush<T>(lh, df, Kb);
+    if (use_lds) hist_flush(lh, df, Kb);
 }
 
 // Direct jobs on the matrix cores (FP32). The pair terms <gbar_i, val_j>
@@ -1247,13 +1284,12 @@ k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
                  const int32_t* __restrict__ dl_row, const int32_t* __restrict__ qjb,
                  const int32_t* __restrict__ qje, const float* __restrict__ val,
                  const float* __restrict__ valg, const int32_t* __restrict__ dbin,
-                 double* __restrict__ df) {
-    __shared__ float lh[df_hist_bins<float>()];
+                 u64* __restrict__ df) {
+    __shared__ u64 lh[2 * kDfBinsMfma];
     const int32_t Kb = dbin[blockIdx.x];  // bins this block can reach
-    const bool use_lds = Kb <= df_hist_bins<float>();
-    float* lhp = use_lds ? lh : nullptr;
-    if (use_lds)
-        for (int32_t k = threadIdx.x; k < Kb; k += blockDim.x) lh[k] = 0.f;
+    const bool use_lds = Kb <= kDfBinsMfma;
+    u64* lhp = use_lds ? lh : nullptr;
+    if (use_lds) hist_clear(lh, Kb);
     __syncthreads();
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1327,7 +1363,7 @@ k_df_direct_mfma(int32_t d, int64_t NA, const int32_t* __restrict__ blk,
             }
         }
     }
-    if (use_lds) hist_flush<float>(lh, df, Kb);
+    if (use_lds) hist_flush(lh, df, Kb);
 }
 
 // Leaf tiles: pairs inside each tile, distance from D. The group's gout
@@ -1343,19 +1379,18 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
           const int32_t* __restrict__ lq, const int32_t* __restrict__ leaf_v,
           const int32_t* __restrict__ leaf_D, const T* __restrict__ F,
           const T* __restrict__ gout, const int32_t* __restrict__ lbin,
-          double* __restrict__ df) {
+          u64* __restrict__ df) {
     // rows of kDirCh channels at a 16-byte aligned stride, read 4 channels
     // at a time
     constexpr int kStride = kDirCh + 4;
     __shared__ __attribute__((aligned(16))) T sG[kLeafSlots * kStride];
     __shared__ __attribute__((aligned(16))) T sF[kLeafSlots * kStride];
     __shared__ int32_t svtx[kLeafSlots], srow0[kLeafQuads + 1];
-    __shared__ T lh[df_hist_bins<T>()];
+    __shared__ u64 lh[2 * kDfBins];
     const int32_t K = lbin[blockIdx.x];  // bins this group's pairs can reach
-    const bool use_lds = K <= df_hist_bins<T>();
-    T* lhp = use_lds ? lh : nullptr;
-    if (use_lds)
-        for (int32_t k = threadIdx.x; k < K; k += blockDim.x) lh[k] = 0;
+    const bool use_lds = K <= kDfBins;
+    u64* lhp = use_lds ? lh : nullptr;
+    if (use_lds) hist_clear(lh, K);
     const int32_t q0 = grp[blockIdx.x], q1 = grp[blockIdx.x + 1], nq_ = q1 - q0;
     const int64_t kb = gk[2 * blockIdx.x];
     const int32_t vb = lq[4 * q0 + 1];
@@ -1450,7 +1485,7 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
         for (int c = 0; c < rows; ++c)
             if (m[r][c] != (T)0) hist_add<T>(lhp, df, leaf_D[kb + krow + c * n + rj[r]], m[r][c]);
     }
-    if (use_lds) hist_flush<T>(lh, df, K);
+    if (use_lds) hist_flush(lh, df, K);
 }
 
 // FFT jobs, pass 1: one workgroup per (job, group of kDfPairs channel
@@ -1503,20 +1538,20 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
 
 // FFT jobs, pass 2: one workgroup per job sums the group spectra (fixed
 // order), applies one inverse transform and folds Re Z[a][b] (a = q + r,
-// b = s - x mod L2) into df[a + |b|], binned in LDS.
+// b = s - x mod L2) into df[a + |b|], binned in LDS in fixed point.
 template <typename T>
 __global__ void k_df_fft_fold(int lg1, int lg2, const int32_t* __restrict__ jobs,
                               const int32_t* __restrict__ job_hx, int32_t groups, int64_t NA,
                               const int32_t* __restrict__ jc_val, const cpx<T>* __restrict__ part,
-                              const cpx<T>* __restrict__ tw, int lgtw, double* __restrict__ df) {
+                              const cpx<T>* __restrict__ tw, int lgtw, u64* __restrict__ df) {
     extern __shared__ unsigned char smem_raw[];
     const int32_t cb = jobs[2 * blockIdx.x];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
     const int32_t H = job_hx[2 * blockIdx.x], X = job_hx[2 * blockIdx.x + 1];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
-    T* lh = reinterpret_cast<T*>(z + P);
+    u64* lh = reinterpret_cast<u64*>(z + P);
     const int32_t nk = 2 * H + X + 1;  // bins this job can reach
-    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x) lh[k] = 0;
+    hist_clear(lh, nk);
     const cpx<T>* src = part + (int64_t)blockIdx.x * groups * P;
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         cpx<T> s = {(T)0, (T)0};
@@ -1530,11 +1565,9 @@ __global__ void k_df_fft_fold(int lg1, int lg2, const int32_t* __restrict__ jobs
     for (int p = threadIdx.x; p < P; p += blockDim.x) {
         const int a = p >> lg2, b = p & (L2 - 1);
         const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
-        if (a <= 2 * H && bs <= X) atomicAdd(lh + a + bs, z[p].x * scale);
+        if (a <= 2 * H && bs <= X) df_atomic(lh, a + bs, (double)(z[p].x * scale));
     }
-    __syncthreads();
-    for (int32_t k = threadIdx.x; k < nk; k += blockDim.x)
-        if (lh[k] != (T)0) atomicAdd(df + k, (double)lh[k]);
+    hist_flush(lh, df, nk);
 }
 
 // Global-memory variant for tables beyond LDS: fills of the two tables per
@@ -1582,7 +1615,7 @@ template <typename T>
 __global__ void k_fold_global(int64_t njobs, int lg1, int lg2, int64_t NA,
                               const int32_t* __restrict__ jobs, const int32_t* __restrict__ job_hx,
                               const int32_t* __restrict__ jc_val, const cpx<T>* __restrict__ acc,
-                              double* __restrict__ df) {
+                              u64* __restrict__ df) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= njobs * P) return;
@@ -1594,7 +1627,7 @@ __global__ void k_fold_global(int64_t njobs, int lg1, int lg2, int64_t NA,
     if (a <= 2 * (int64_t)H && bs <= X) {
         const double sign = jc_val[jobs[2 * job]] < NA ? 1.0 : -1.0;
         const double v = sign * (double)acc[tid].x / (double)P;
-        if (v != 0.0) atomicAdd(df + a + bs, v);
+        if (v != 0.0) df_atomic(df, (int32_t)(a + bs), v);
     }
 }
 

@@ -231,6 +231,7 @@ struct tfi_plan {
     // exponential sums: per-term power table and f table, sweep scratch,
     // leaf pair histogram (FP64)
     DeviceBuf expw[2], exps[2], hleaf;
+    DeviceBuf dfacc;                // fixed-point df accumulator, [2 x kernel length] u64
     // channel tiles of a call over the memory budget: the tile of F (and of
     // gout) and of the result
     DeviceBuf tin[2], tgin[2], tout[2];
@@ -325,6 +326,7 @@ struct tfi_plan {
                                  &partg[t], &expw[t], &exps[t], &tin[t], &tgin[t], &tout[t]})
                 if (b->p) (void)hipFree(b->p);
         if (hleaf.p) (void)hipFree(hleaf.p);
+        if (dfacc.p) (void)hipFree(dfacc.p);
         if (mrows.p) (void)hipFree(mrows.p);
         (void)hipSetDevice(prev);
     }
@@ -375,6 +377,7 @@ struct tfi_plan {
                                  &partg[t], &expw[t], &exps[t], &tin[t], &tgin[t], &tout[t]})
                 v.push_back(b);
         v.push_back(&hleaf);
+        v.push_back(&dfacc);
         v.push_back(&mrows);
         return v;
     }
@@ -1902,7 +1905,7 @@ int64_t df_lds_bytes(const tfi_plan* h, const Bucket& b) {
 }
 
 template <typename T>
-void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* df,
+void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64* df,
                    hipStream_t st) {
     const tfi::Plan& p = h->plan;
     const int ti = sizeof(T) == 8 ? 1 : 0;
@@ -1921,7 +1924,7 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
                                dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
                                h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part);
             const unsigned fold_lds =
-                (unsigned)(P * sizeof(tfi::cpx<T>) + (2 * b.hmax + b.xmax + 1) * sizeof(T));
+                (unsigned)(P * sizeof(tfi::cpx<T>) + (2 * b.hmax + b.xmax + 1) * 2 * sizeof(tfi::u64));
             hipLaunchKernelGGL(tfi::k_df_fft_fold<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
                                fold_lds, st, b.lg1, b.lg2, b.d_jobs, b.d_hx, groups, p.NA,
                                h->d_jc_val, (const tfi::cpx<T>*)part, tw, h->lgtw, df);
@@ -1961,7 +1964,7 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, double* 
 
 template <typename T>
 void enq_df_direct(tfi_plan* h, const DirectSet& ds, int32_t d, const T* val, const T* valg,
-                   double* df, hipStream_t st) {
+                   tfi::u64* df, hipStream_t st) {
     if (ds.ndblk == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
@@ -1994,7 +1997,7 @@ void enq_df_direct(tfi_plan* h, const DirectSet& ds, int32_t d, const T* val, co
 }
 
 template <typename T>
-void enq_df_leaf(tfi_plan* h, int32_t d, const T* F, const T* gout, double* df, hipStream_t st) {
+void enq_df_leaf(tfi_plan* h, int32_t d, const T* F, const T* gout, tfi::u64* df, hipStream_t st) {
     if (h->nlgrp == 0) return;
     const tfi::Plan& p = h->plan;
     hipEvent_t ev = h->begin(st);
@@ -2165,12 +2168,12 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
     T* val = (T*)w.val;
     T* valg = (T*)h->valg[ti].p;
     T* g = (T*)w.g;
-    if (df && zero_df)
-        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
-                           s0, df, (int64_t)p.kernel_len);
+    tfi::u64* acc = (tfi::u64*)h->dfacc.p;
+    hipLaunchKernelGGL(tfi::k_zero<tfi::u64>, dim3(blocks_for(2 * p.kernel_len)), dim3(kThreads), 0,
+                       s0, acc, 2 * (int64_t)p.kernel_len);
     fork3(h, s0, s1, s2);
     if (dF) enq_leaf<T>(h, f, gout, d, dF, s2);
-    if (df) enq_df_leaf<T>(h, d, F, gout, df, s2);
+    enq_df_leaf<T>(h, d, F, gout, acc, s2);
     (void)hipEventRecord(h->ev_c, s2);
     // the cell sums of F: kept from the forward, or formed here
     const T* valF = cells ? cells : val;
@@ -2184,29 +2187,31 @@ void enqueue_backward(tfi_plan* h, const T* f, const T* F, const T* gout, int32_
         enq_fft<T>(h, d, valg, g, s1, w);
         enq_hankel<T>(h, f, d, valg, g, s1, w);
     }
-    if (df) enq_df_tables<T>(h, d, valF, valg, df, s1);
+    enq_df_tables<T>(h, d, valF, valg, acc, s1);
     (void)hipEventRecord(h->ev_b, s1);
     if (dF) enq_direct<T>(h, h->dall, f, d, valg, g, s0);
-    if (df) {
-        (void)hipStreamWaitEvent(s0, h->ev_d, 0);
-        enq_df_direct<T>(h, h->dall, d, valF, valg, df, s0);
-        enq_df_direct<T>(h, h->dhank, d, valF, valg, df, s0);
-    }
+    (void)hipStreamWaitEvent(s0, h->ev_d, 0);
+    enq_df_direct<T>(h, h->dall, d, valF, valg, acc, s0);
+    enq_df_direct<T>(h, h->dhank, d, valF, valg, acc, s0);
     (void)hipStreamWaitEvent(s0, h->ev_b, 0);
     (void)hipStreamWaitEvent(s0, h->ev_c, 0);
     if (dF) enq_gather<T>(h, d, g, dF, s0);
+    // df from the integer sums (added to df after the first channel tile)
+    hipLaunchKernelGGL(tfi::k_df_finish, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0, s0,
+                       (const tfi::u64*)acc, (int64_t)p.kernel_len, df, zero_df ? 0 : 1);
 }
 
 // Bytes of the adjoint's scratch beyond the forward's when df is wanted:
 // the cell sums of gout (and their partial rows), and the df FFT slots.
 struct DfSizes {
-    size_t valg = 0, partg = 0, dfbuf = 0;
+    size_t valg = 0, partg = 0, dfbuf = 0, dfacc = 0;
 };
 
 template <typename T>
 DfSizes df_sizes(const tfi_plan* h, int32_t d) {
     DfSizes z;
     z.valg = (size_t)std::max<int64_t>(h->val_rows, 1) * d * sizeof(T);
+    z.dfacc = (size_t)h->plan.kernel_len * 2 * sizeof(tfi::u64);
     if (scatter_pieces(h, d))
         z.partg = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     const int32_t npairs = (d + 1) / 2;
@@ -2236,6 +2241,7 @@ int prepare_backward(tfi_plan* h, int32_t d, bool need_df) {
     if ((rc = h->ensure(h->valg[ti], z.valg))) return rc;
     if (z.partg && (rc = h->ensure(h->partg[ti], z.partg))) return rc;
     if (z.dfbuf && (rc = h->ensure(h->dfbuf[ti], z.dfbuf))) return rc;
+    if ((rc = h->ensure(h->dfacc, z.dfacc))) return rc;
     return TFI_OK;
 }
 
@@ -2436,7 +2442,7 @@ int32_t budget_tile(tfi_plan* h, int32_t d, bool bwd, bool need_df) {
         size_t n = z.val + z.g + z.spec + z.fft + z.part + 5 * 16;
         if (need_df) {
             const DfSizes e = df_sizes<T>(h, w);
-            n += e.valg + e.partg + e.dfbuf + 3 * 16;
+            n += e.valg + e.partg + e.dfbuf + e.dfacc + 4 * 16;
         }
         if (tiled) n += (bwd ? 3 : 2) * N * (size_t)w * sizeof(T);  // tiles in and out
         return base + n;
@@ -2567,6 +2573,8 @@ int prepare_expsum(tfi_plan* h, int32_t nterm, int32_t d, bool bwd, bool grad) {
     if (bwd && (rc = h->ensure(h->valg[ti], rowbytes))) return rc;
     if (bwd && pieces && (rc = h->ensure(h->partg[ti], partbytes))) return rc;
     if (grad && (rc = h->ensure(h->hleaf, (size_t)p.kernel_len * sizeof(double)))) return rc;
+    if (grad && (rc = h->ensure(h->dfacc, (size_t)p.kernel_len * 2 * sizeof(tfi::u64))))
+        return rc;
     if (grad && (rc = h->ensure(h->mrows, (size_t)expsum_moment_rows(h, d, nterm) * 2 * nterm *
                                               sizeof(double))))
         return rc;
@@ -2713,13 +2721,16 @@ void enqueue_backward_expsum(tfi_plan* h, int32_t nterm, const T* c, const T* la
     const bool grad = m0 != nullptr;
     const int64_t rows = grad ? expsum_moment_rows(h, d, nterm) : 0;
     enq_expsum_prep<T>(h, nterm, c, lam, s0);
+    tfi::u64* acc = (tfi::u64*)h->dfacc.p;
     if (grad)
-        hipLaunchKernelGGL(tfi::k_zero<double>, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
-                           s0, hl, (int64_t)p.kernel_len);
+        hipLaunchKernelGGL(tfi::k_zero<tfi::u64>, dim3(blocks_for(2 * p.kernel_len)),
+                           dim3(kThreads), 0, s0, acc, 2 * (int64_t)p.kernel_len);
     fork3(h, s0, s1, s2);
     if (dF) enq_leaf<T>(h, ftab, gout, d, dF, s2);
     if (grad) {
-        enq_df_leaf<T>(h, d, F, gout, hl, s2);  // leaf pair histogram -> the last rows
+        enq_df_leaf<T>(h, d, F, gout, acc, s2);  // leaf pair histogram -> the last rows
+        hipLaunchKernelGGL(tfi::k_df_finish, dim3(blocks_for(p.kernel_len)), dim3(kThreads), 0,
+                           s2, (const tfi::u64*)acc, (int64_t)p.kernel_len, hl, 0);
         hipLaunchKernelGGL(tfi::k_expsum_leaf_moments<T>, dim3((unsigned)nterm),
                            dim3(tfi::kExpThreads), 0, s2, nterm, (int32_t)p.kernel_len, pw, hl,
                            mrow, rows - nterm);

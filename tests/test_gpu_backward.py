@@ -217,3 +217,40 @@ def test_kept_cells_table_path(case):
     assert relerr(df1.cpu().numpy(), h) <= tol
     with pytest.raises(ValueError):
         t.backward(f, F, G, cells=cells[:-1])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_df_bitwise_reproducible_every_path(dtype):
+    """df accumulates as integer sums in every kernel that bins pairs (direct
+    tables on the vector ALU and on the matrix cores, leaf tiles, FFT tables
+    in LDS and through global memory, Hankel-product tables): repeated
+    adjoints, with and without graphs, give the same bits, and match the
+    oracle's pair histogram."""
+    rng = np.random.default_rng(61)
+    p, _ = S.random_recursive(3000, rng)
+    w = S.uniform_weights(p, 1, 6, rng)
+    F = rng.standard_normal((len(p), 9))
+    G = rng.standard_normal((len(p), 9))
+    for opts in ({"table_method": "direct", "direct_kernel": "vector"},
+                 {"table_method": "direct", "direct_kernel": "mfma"},
+                 {"table_method": "fft"}, {"policy": "diameter", "table_method": "fft"},
+                 {"policy": "diameter", "table_method": "hankel"}):
+        if dtype == torch.float64 and opts.get("direct_kernel") == "mfma":
+            continue
+        outs = []
+        for graphs in (True, False):
+            t = TreeIntegrator(p, w, device=0, graphs=graphs, **opts)
+            K = t.kernel_length
+            f = torch.tensor(np.exp(-0.04 * np.arange(K)), dtype=dtype, device=DEV)
+            Ft = torch.tensor(F, dtype=dtype, device=DEV)
+            Gt = torch.tensor(G, dtype=dtype, device=DEV)
+            for _ in range(3):
+                _, df = t.backward(f, Ft, Gt)
+                outs.append(df.clone())
+        torch.cuda.synchronize()
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0]), opts
+        ref = oracle.pair_hist(p, w, G, F, K)
+        e = float(np.linalg.norm(outs[0].cpu().numpy() - ref) / np.linalg.norm(ref))
+        print(f"{opts} {dtype}: df vs oracle {e:.2e}", flush=True)
+        assert e <= (1e-10 if dtype == torch.float64 else 1e-4), opts
