@@ -1098,8 +1098,8 @@ namespace tfi {
 constexpr int kDfTile = 64, kDfThreads = 256;
 constexpr int kDfHiExp = 14, kDfLoBits = 33;
 using u64 = unsigned long long;
-// LDS histogram bins of 16 bytes: 16 KiB, 32 KiB for the matrix-core kernel
-constexpr int kDfBins = 1024, kDfBinsMfma = 2048;
+// LDS histogram bins of 16 bytes: 16 KiB, 64 KiB for the matrix-core kernel
+constexpr int kDfBins = 1024, kDfBinsMfma = 4096;
 
 __device__ __forceinline__ void df_atomic(u64* acc, int32_t k, double v) {
     const double s = v * (double)(1 << kDfHiExp);  // exact
