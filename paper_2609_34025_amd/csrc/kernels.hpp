@@ -938,28 +938,41 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
 // [lglo, lglo + k) -- for C = 2^lgC consecutive values of the bits below
 // lglo (consecutive addresses when es = 1) and N = 2^lgN neighbouring lines
 // (consecutive addresses when ls = 1: the column passes of a 2-D table).
+// The last pass (lglo = 0) takes 2^lgG consecutive groups instead, so that
+// a workgroup still holds up to 4096 points when few bits are left (with
+// es = 1 the groups are one contiguous run; lines that follow one another
+// in memory are passed as one longer axis whose top bits no stage touches).
 // Forward (DIF) passes go from the high bits down, inverse (DIT) passes from
 // the low bits up, with the same twiddles exp(-+2 pi i j / 2h) as the LDS
 // transform.
 template <typename T, bool INV>
 __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
-                           int64_t nlines, int lglo, int k, int lgC, int lgN,
+                           int64_t nlines, int lglo, int k, int lgC, int lgN, int lgG,
                            const cpx<T>* __restrict__ tw, int lgtw) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int64_t C = (int64_t)1 << lgC;
-    const int64_t nlo = ((int64_t)1 << lglo) >> lgC;       // low-bit chunks
-    const int64_t nhi = (int64_t)1 << (lgL - lglo - k);    // high-bit values
-    const int64_t ngrp = nlines >> lgN;                     // groups of N lines
+    const int64_t nlo = ((int64_t)1 << lglo) >> lgC;               // low-bit chunks
+    const int64_t nhi = ((int64_t)1 << (lgL - lglo - k)) >> lgG;   // high-bit values (groups)
+    const int64_t ngrp = nlines >> lgN;                             // groups of N lines
     int64_t g = blockIdx.x;
     const int64_t lo_chunk = g % nlo;
     g /= nlo;
-    const int64_t hi = g % nhi;
+    const int64_t hi = (g % nhi) << lgG;
     g /= nhi;
     const int64_t line = (g % ngrp) << lgN;
     const int64_t slot = g / ngrp;
     cpx<T>* base = buf + (slot << lgP) + line * ls;
     const int64_t i0 = (hi << (lglo + k)) + lo_chunk * C;
+    if (lgG > 0) {
+        // lglo = lgC = lgN = 0: 2^lgG groups of 2^k points, point e at i0 + e
+        const int n = 1 << (k + lgG);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) z[e] = base[(i0 + e) * es];
+        __syncthreads();
+        fft_lines<T, INV>(z, k, LdsLines{lgG, 1 << k, 1, 0, 1}, 0, 0, tw, lgtw);
+        for (int e = threadIdx.x; e < n; e += blockDim.x) base[(i0 + e) * es] = z[e];
+        return;
+    }
     const int lgCN = lgC + lgN;
     const int n = 1 << (k + lgCN);
     // LDS e = ((j << lgC | lo) << lgN) | ln: line ln fastest

@@ -1293,20 +1293,25 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, T* part, int32_t d, hipSt
 // pass when the axis fits. Listed in DIF order (high bits first); the
 // inverse runs them in reverse.
 struct PassSpec {
-    int lglo, k, lgC;
+    int lglo, k, lgC, lgG;
 };
 
-inline std::vector<PassSpec> fft_passes(int lgL, int lgN) {
+// lgT: index bits of the (possibly merged) axis above which no stage runs
+// but which the last pass may batch into one workgroup (lgT >= lgL).
+inline std::vector<PassSpec> fft_passes(int lgL, int lgN, int lgT) {
     std::vector<PassSpec> v;
     const int kmax = 12 - lgN;
     int hi = lgL;
     while (hi > 0) {
         if (hi <= kmax) {
-            v.push_back({0, hi, 0});
+            // the last pass: consecutive groups fill the workgroup (not with
+            // line groups, whose lines are not consecutive)
+            const int lgG = lgN ? 0 : std::min(kmax - hi, lgT - hi);
+            v.push_back({0, hi, 0, std::max(lgG, 0)});
             break;
         }
         const int lgC = lgN ? 0 : 4, k = kmax - lgC;
-        v.push_back({hi - k, k, lgC});
+        v.push_back({hi - k, k, lgC, 0});
         hi -= k;
     }
     return v;
@@ -1316,15 +1321,24 @@ template <typename T, bool INV>
 void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
                  int64_t nlines, int lgN, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
     while (lgN > 0 && ((int64_t)1 << lgN) > nlines) --lgN;
-    std::vector<PassSpec> ps = fft_passes(lgL, lgN);
+    // lines that follow one another in memory form one longer axis: its top
+    // bits (the line) are never transformed, only batched by the last pass
+    int lgA = lgL;
+    if (es == 1 && ls == ((int64_t)1 << lgL) && lgN == 0 && (nlines & (nlines - 1)) == 0) {
+        while (((int64_t)1 << (lgA - lgL)) < nlines) ++lgA;
+        nlines = 1;
+    }
+    std::vector<PassSpec> ps = fft_passes(lgL, lgN, lgA);
     if (INV) std::reverse(ps.begin(), ps.end());
     for (const PassSpec& q : ps) {
-        const int64_t groups = nslots * (nlines >> lgN) * ((int64_t)1 << (lgL - q.lglo - q.k)) *
+        const int64_t groups = nslots * (nlines >> lgN) *
+                               (((int64_t)1 << (lgA - q.lglo - q.k)) >> q.lgG) *
                                (((int64_t)1 << q.lglo) >> q.lgC);
         const unsigned lds =
-            (unsigned)(((int64_t)1 << (q.k + q.lgC + lgN)) * sizeof(tfi::cpx<T>));
+            (unsigned)(((int64_t)1 << (q.k + q.lgC + lgN + q.lgG)) * sizeof(tfi::cpx<T>));
         hipLaunchKernelGGL((tfi::k_fft_pass<T, INV>), dim3((unsigned)groups), dim3(kThreads), lds,
-                           st, buf, lgP, lgL, es, ls, nlines, q.lglo, q.k, q.lgC, lgN, tw, lgtw);
+                           st, buf, lgP, lgA, es, ls, nlines, q.lglo, q.k, q.lgC, lgN, q.lgG, tw,
+                           lgtw);
     }
 }
 
