@@ -944,11 +944,15 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
 // in memory are passed as one longer axis whose top bits no stage touches).
 // Forward (DIF) passes go from the high bits down, inverse (DIT) passes from
 // the low bits up, with the same twiddles exp(-+2 pi i j / 2h) as the LDS
-// transform.
-template <typename T, bool INV>
+// transform. MUL: the last forward pass of a convolution also multiplies by
+// the kernel spectrum (spec, indexed by the point's offset in its table) and
+// runs the first inverse pass, so the buffer is read and written once for
+// the three.
+template <typename T, bool INV, bool MUL = false>
 __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
                            int64_t nlines, int lglo, int k, int lgC, int lgN, int lgG,
-                           const cpx<T>* __restrict__ tw, int lgtw) {
+                           const cpx<T>* __restrict__ tw, int lgtw,
+                           const cpx<T>* __restrict__ spec = nullptr) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int64_t C = (int64_t)1 << lgC;
@@ -969,7 +973,14 @@ __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t e
         const int n = 1 << (k + lgG);
         for (int e = threadIdx.x; e < n; e += blockDim.x) z[e] = base[(i0 + e) * es];
         __syncthreads();
-        fft_lines<T, INV>(z, k, LdsLines{lgG, 1 << k, 1, 0, 1}, 0, 0, tw, lgtw);
+        const LdsLines L{lgG, 1 << k, 1, 0, 1};
+        fft_lines<T, INV>(z, k, L, 0, 0, tw, lgtw);
+        if (MUL) {
+            for (int e = threadIdx.x; e < n; e += blockDim.x)
+                z[e] = cmul(z[e], spec[line * ls + (i0 + e) * es]);
+            __syncthreads();
+            fft_lines<T, true>(z, k, L, 0, 0, tw, lgtw);
+        }
         for (int e = threadIdx.x; e < n; e += blockDim.x) base[(i0 + e) * es] = z[e];
         return;
     }
@@ -983,8 +994,16 @@ __global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t e
     __syncthreads();
     // the C x N lines (l0 = lo N + ln) of 2^k points j at stride C N;
     // twiddles by the global index (j << lglo) + lo_chunk C + lo
-    fft_lines<T, INV>(z, k, LdsLines{lgCN, 1, 1, 0, 1 << lgCN, lgN}, lglo, (int)(lo_chunk * C),
-                      tw, lgtw);
+    const LdsLines L{lgCN, 1, 1, 0, 1 << lgCN, lgN};
+    fft_lines<T, INV>(z, k, L, lglo, (int)(lo_chunk * C), tw, lgtw);
+    if (MUL) {  // lglo = 0 here: the last forward pass
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
+            z[e] = cmul(z[e], spec[(line + ln) * ls + (i0 + (j << lglo) + lo) * es]);
+        }
+        __syncthreads();
+        fft_lines<T, true>(z, k, L, lglo, (int)(lo_chunk * C), tw, lgtw);
+    }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
         base[ln * ls + (i0 + (j << lglo) + lo) * es] = z[e];
@@ -1003,15 +1022,6 @@ __global__ void k_spec_fill_global(int lg1, int lg2, int32_t hmax, int32_t xmax,
     T v = 0;
     if (a <= 2 * (int64_t)hmax && bs <= xmax) v = f[a + bs];
     z[p] = {v, (T)0};
-}
-
-template <typename T>
-__global__ void k_spec_mul_global(cpx<T>* __restrict__ buf, int64_t nslots, int lgP,
-                                  const cpx<T>* __restrict__ spec) {
-    const int64_t P = (int64_t)1 << lgP;
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid >= nslots * P) return;
-    buf[tid] = cmul(buf[tid], spec[tid & (P - 1)]);
 }
 
 // Table rows of the cells from the inverse transforms, scaled by 2^-lgS

@@ -1317,9 +1317,16 @@ inline std::vector<PassSpec> fft_passes(int lgL, int lgN, int lgT) {
     return v;
 }
 
-template <typename T, bool INV>
-void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
-                 int64_t nlines, int lgN, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
+// One axis of a batch of tables: its (possibly merged) index bits, line
+// groups and pass schedule.
+struct AxisPlan {
+    int lgL = 0, lgA = 0, lgN = 0;
+    int64_t es = 1, ls = 1, nlines = 1;
+    std::vector<PassSpec> ps;  // DIF order
+};
+
+inline AxisPlan plan_axis(int lgL, int64_t es, int64_t ls, int64_t nlines, int lgN) {
+    AxisPlan a;
     while (lgN > 0 && ((int64_t)1 << lgN) > nlines) --lgN;
     // lines that follow one another in memory form one longer axis: its top
     // bits (the line) are never transformed, only batched by the last pass
@@ -1328,18 +1335,51 @@ void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es,
         while (((int64_t)1 << (lgA - lgL)) < nlines) ++lgA;
         nlines = 1;
     }
-    std::vector<PassSpec> ps = fft_passes(lgL, lgN, lgA);
+    a.lgL = lgL;
+    a.lgA = lgA;
+    a.lgN = lgN;
+    a.es = es;
+    a.ls = ls;
+    a.nlines = nlines;
+    a.ps = fft_passes(lgL, lgN, lgA);
+    return a;
+}
+
+template <typename T, bool INV, bool MUL = false>
+void launch_pass(tfi::cpx<T>* buf, int64_t nslots, int lgP, const AxisPlan& a, const PassSpec& q,
+                 const tfi::cpx<T>* tw, int lgtw, hipStream_t st,
+                 const tfi::cpx<T>* spec = nullptr) {
+    const int64_t groups = nslots * (a.nlines >> a.lgN) *
+                           (((int64_t)1 << (a.lgA - q.lglo - q.k)) >> q.lgG) *
+                           (((int64_t)1 << q.lglo) >> q.lgC);
+    const unsigned lds =
+        (unsigned)(((int64_t)1 << (q.k + q.lgC + a.lgN + q.lgG)) * sizeof(tfi::cpx<T>));
+    hipLaunchKernelGGL((tfi::k_fft_pass<T, INV, MUL>), dim3((unsigned)groups), dim3(kThreads), lds,
+                       st, buf, lgP, a.lgA, a.es, a.ls, a.nlines, q.lglo, q.k, q.lgC, a.lgN, q.lgG,
+                       tw, lgtw, spec);
+}
+
+template <typename T, bool INV>
+void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
+                 int64_t nlines, int lgN, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
+    AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN);
+    std::vector<PassSpec> ps = a.ps;
     if (INV) std::reverse(ps.begin(), ps.end());
-    for (const PassSpec& q : ps) {
-        const int64_t groups = nslots * (nlines >> lgN) *
-                               (((int64_t)1 << (lgA - q.lglo - q.k)) >> q.lgG) *
-                               (((int64_t)1 << q.lglo) >> q.lgC);
-        const unsigned lds =
-            (unsigned)(((int64_t)1 << (q.k + q.lgC + lgN + q.lgG)) * sizeof(tfi::cpx<T>));
-        hipLaunchKernelGGL((tfi::k_fft_pass<T, INV>), dim3((unsigned)groups), dim3(kThreads), lds,
-                           st, buf, lgP, lgA, es, ls, nlines, q.lglo, q.k, q.lgC, lgN, q.lgG, tw,
-                           lgtw);
-    }
+    for (const PassSpec& q : ps) launch_pass<T, INV>(buf, nslots, lgP, a, q, tw, lgtw, st);
+}
+
+// The forward DIF passes of the axis, the spectrum product, and its inverse
+// DIT passes, with the last forward pass, the product and the first inverse
+// pass in one launch.
+template <typename T>
+void launch_axis_conv(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
+                      int64_t nlines, int lgN, const tfi::cpx<T>* spec, const tfi::cpx<T>* tw,
+                      int lgtw, hipStream_t st) {
+    const AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN);
+    const size_t np = a.ps.size();
+    for (size_t i = 0; i + 1 < np; ++i) launch_pass<T, false>(buf, nslots, lgP, a, a.ps[i], tw, lgtw, st);
+    launch_pass<T, false, true>(buf, nslots, lgP, a, a.ps[np - 1], tw, lgtw, st, spec);
+    for (size_t i = np - 1; i-- > 0;) launch_pass<T, true>(buf, nslots, lgP, a, a.ps[i], tw, lgtw, st);
 }
 
 inline int ilog2_floor(int64_t v) {
@@ -1364,6 +1404,24 @@ void launch_fft2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::
         if (lg1) launch_axis<T, true>(buf, nslots, lgP, lg1, L2, 1, L2, lgN, tw, lgtw, st);
         if (lg2) launch_axis<T, true>(buf, nslots, lgP, lg2, 1, L2, L1, 0, tw, lgtw, st);
     }
+}
+
+// Convolution of nslots tables with one spectrum: forward 2-D transform
+// (rows, then columns), product, inverse (columns, then rows), the last axis
+// fused around the product (launch_axis_conv).
+template <typename T>
+void launch_conv2(tfi::cpx<T>* buf, int64_t nslots, int lg1, int lg2, const tfi::cpx<T>* spec,
+                  const tfi::cpx<T>* tw, int lgtw, int col_lines, hipStream_t st) {
+    const int lgP = lg1 + lg2;
+    const int64_t L1 = (int64_t)1 << lg1, L2 = (int64_t)1 << lg2;
+    const int lgN = ilog2_floor(std::max(1, col_lines));
+    if (lg1 == 0) {  // one row: the row axis carries the product
+        launch_axis_conv<T>(buf, nslots, lgP, lg2, 1, L2, L1, 0, spec, tw, lgtw, st);
+        return;
+    }
+    if (lg2) launch_axis<T, false>(buf, nslots, lgP, lg2, 1, L2, L1, 0, tw, lgtw, st);
+    launch_axis_conv<T>(buf, nslots, lgP, lg1, L2, 1, L2, lgN, spec, tw, lgtw, st);
+    if (lg2) launch_axis<T, true>(buf, nslots, lgP, lg2, 1, L2, L1, 0, tw, lgtw, st);
 }
 
 // Shape of the 1-D convolution kernels for a bucket: TC channel pairs per
@@ -1583,10 +1641,8 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
         hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
                            st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, val, buf, 1);
-        launch_fft2<T, false>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
-        hipLaunchKernelGGL(tfi::k_spec_mul_global<T>, dim3(blocks_for(nslots * b.P())),
-                           dim3(kThreads), 0, st, buf, nslots, lgP, spec + b.spec_off);
-        launch_fft2<T, true>(buf, nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
+        launch_conv2<T>(buf, nslots, b.lg1, b.lg2, spec + b.spec_off, tw, h->lgtw,
+                        h->fp.col_lines, st);
         hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
                            0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
                            h->d_jc_val, d, buf, g, lgP);
