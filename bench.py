@@ -658,10 +658,13 @@ def sinkhorn_sphere(args):
     """Iterated solve: Sinkhorn scaling on the minimum spanning tree of the
     symmetrised 8-NN graph of 50,000 points uniform on the sphere, lengths
     quantised to 1/64, f(k) = exp(-k / 3.2) (exp(-d / 0.05)), marginals
-    ~ Dirichlet(1). 200 iterations of two FP32 products each are timed
-    (no residual checks inside the timed loop); then every product of a
-    second 200-iteration run is checked against the FP64 exp-kernel tree
-    recursion applied to the same rounded input vector."""
+    ~ Dirichlet(1). The products run through the kernel table (per-table
+    rule autotuned) and, since f is one exponential, through the backbone
+    sweeps; for each, 200 iterations of two FP32 products are timed (no
+    residual checks inside the timed loop), then every product of a second
+    200-iteration run is checked against the FP64 exp-kernel tree recursion
+    applied to the same rounded input vector. The faster evaluator is the
+    record's value."""
     import numpy as np
     import torch
 
@@ -676,42 +679,55 @@ def sinkhorn_sphere(args):
     tfi = TreeIntegrator(p, w, device=0)
     K = tfi.kernel_length
     lam = float(np.exp(-1.0 / 3.2))
-    f = torch.tensor(lam ** np.arange(K), dtype=torch.float32, device=dev)
+    table = torch.tensor(lam ** np.arange(K), dtype=torch.float32, device=dev)
+    sweep = (torch.ones(1, dtype=torch.float32, device=dev),
+             torch.full((1,), lam, dtype=torch.float32, device=dev))
     a = torch.tensor(W["a"], device=dev)
     b = torch.tensor(W["b"], device=dev)
-    cost = tfi.autotune(f, 1)
+    cost = tfi.autotune(table, 1)
     iters = 200
-    sinkhorn(tfi, f, a, b, iters=5, check_every=10 ** 9)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    u, v, _ = sinkhorn(tfi, f, a, b, iters=iters, check_every=10 ** 9)
-    torch.cuda.synchronize()
-    ms_iter = 1e3 * (time.perf_counter() - t0) / iters
     x = torch.rand(n, dtype=torch.float32, device=dev)
     y = torch.empty_like(x)
-    ms_prod = _timed(lambda: tfi.integrate(f, x, out=y), 200)
-    stages = _stages(tfi, lambda: tfi.integrate(f, x, out=y))
-    errs = []
+    runs = {}
+    for name, f, prod in (("table", table, lambda: tfi.integrate(table, x, out=y)),
+                          ("sweep", sweep, lambda: tfi.integrate_expsum(sweep[0], sweep[1], x))):
+        sinkhorn(tfi, f, a, b, iters=5, check_every=10 ** 9)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sinkhorn(tfi, f, a, b, iters=iters, check_every=10 ** 9)
+        torch.cuda.synchronize()
+        ms_iter = 1e3 * (time.perf_counter() - t0) / iters
+        ms_prod = _timed(prod, 200)
+        stages = _stages(tfi, prod)
+        errs = []
 
-    def check(xin, yv):
-        ref = oracle.expdp(p, w, [1.0], [lam], xin.double().cpu().numpy())
-        errs.append(float(np.linalg.norm(yv.double().cpu().numpy() - ref) / np.linalg.norm(ref)))
+        def check(xin, yv):
+            ref = oracle.expdp(p, w, [1.0], [lam], xin.double().cpu().numpy())
+            errs.append(float(np.linalg.norm(yv.double().cpu().numpy() - ref) /
+                              np.linalg.norm(ref)))
 
-    _, _, res = sinkhorn(tfi, f, a, b, iters=iters, on_product=check)
-    dom = max(stages, key=lambda k: stages[k]["ms"])
-    log(f"sinkhorn: N={n} {ms_iter:.4f} ms/iteration ({ms_prod:.4f} ms/product), "
-        f"{len(errs)} products checked, max rel err {max(errs):.2e}")
+        _, _, res = sinkhorn(tfi, f, a, b, iters=iters, on_product=check)
+        dom = max(stages, key=lambda k: stages[k]["ms"])
+        log(f"sinkhorn[{name}]: N={n} {ms_iter:.4f} ms/iteration ({ms_prod:.4f} ms/product), "
+            f"{len(errs)} products checked, max rel err {max(errs):.2e}")
+        runs[name] = {"ms_per_iteration": round(ms_iter, 5), "ms_per_product": round(ms_prod, 5),
+                      "parity": {"products": len(errs), "max_rel_err": max(errs),
+                                 "ok": max(errs) <= 1e-4},
+                      "residual_first_last": [res[0][1], res[-1][1]],
+                      "roofline": stage_roofline(dom, stages[dom], "f32")}
+    best = min(runs, key=lambda k: runs[k]["ms_per_iteration"])
+    r = runs[best]
     return {"workload": "200 Sinkhorn iterations (2 fp32 products each) on the MST of the 8-NN "
                         "graph of 50000 points on the sphere, lengths in units of 1/64, "
                         "f(k) = exp(-k/3.2), marginals Dirichlet(1)",
-            "N": n, "d": 1, "iterations": iters, "ms_per_iteration": round(ms_iter, 5),
-            "ms_per_product": round(ms_prod, 5), "value": n / (ms_prod * 1e-3),
+            "N": n, "d": 1, "iterations": iters, "evaluator": best,
+            "ms_per_iteration": r["ms_per_iteration"], "ms_per_product": r["ms_per_product"],
+            "value": n / (r["ms_per_product"] * 1e-3),
             "unit": "vertex*channels/s (one product)", "fft_cost": cost,
-            "parity": {"products": len(errs), "max_rel_err": max(errs),
-                       "ok": max(errs) <= 1e-4,
-                       "oracle": "fp64 exp-kernel tree recursion on the same fp32 input"},
-            "residual_first_last": [res[0][1], res[-1][1]],
-            "roofline": stage_roofline(dom, stages[dom], "f32")}
+            "parity": dict(r["parity"], oracle="fp64 exp-kernel tree recursion on the same "
+                                               "fp32 input"),
+            "residual_first_last": r["residual_first_last"], "roofline": r["roofline"],
+            "evaluators": runs}
 
 
 def large_trees(args):

@@ -20,7 +20,10 @@ def sinkhorn(integrator, f, a, b, iters=200, delta=1e-30, tol=None, check_every=
     """Run ``iters`` Sinkhorn iterations (or stop at the first residual
     check below ``tol``).
 
-    integrator  TreeIntegrator of the tree; f its kernel table (device)
+    integrator  TreeIntegrator of the tree; f its kernel table (device), or
+                a pair (c, lam) of device tensors for f(k) = sum_l c_l lam_l^k,
+                whose products then run through the backbone sweeps
+                (``integrate_expsum``)
     a, b        marginals, device tensors [N] (any float dtype; kept FP64)
     on_product  optional callback(x_in, Kx) after every product (for checks)
     Returns (u, v, residuals) with residuals a list of (t, R_t).
@@ -30,9 +33,12 @@ def sinkhorn(integrator, f, a, b, iters=200, delta=1e-30, tol=None, check_every=
     u = torch.ones_like(a)
     v = torch.ones_like(b)
 
+    sweeps = isinstance(f, tuple)
+    dtype = f[0].dtype if sweeps else f.dtype
+
     def K(x):
-        xin = x.to(f.dtype).contiguous()
-        y = integrator.integrate(f, xin)
+        xin = x.to(dtype).contiguous()
+        y = integrator.integrate_expsum(f[0], f[1], xin) if sweeps else integrator.integrate(f, xin)
         if on_product is not None:
             on_product(xin, y)
         return y.to(torch.float64)
