@@ -67,3 +67,33 @@ def test_sinkhorn_fp64_products_follow_cpu_trajectory():
     assert np.linalg.norm(v.cpu().numpy() - vc) / np.linalg.norm(vc) < 1e-5
     np.testing.assert_allclose([r for _, r in res], rc, rtol=1e-5)
     assert res[-1][1] < res[0][1]
+
+
+def test_sinkhorn_through_backbone_sweeps():
+    """f = exp(-k / 3.2) is one exponential: the products may run through
+    the backbone sweeps (f given as (c, lam)). Every FP32 product against the
+    FP64 recursion, and the FP64 sweep trajectory equals the FP64 table
+    trajectory to the iteration's amplification of rounding."""
+    W = S.workload("sphere50k")
+    p, w = W["parent"], W["weight"]
+    t = TreeIntegrator(p, w, device=0)
+    lam = np.exp(-1.0 / 3.2)
+    a = torch.tensor(W["a"], device=DEV)
+    b = torch.tensor(W["b"], device=DEV)
+    errs = []
+
+    def check(xin, y):
+        ref = oracle.expdp(p, w, [1.0], [lam], xin.double().cpu().numpy())
+        errs.append(np.linalg.norm(y.double().cpu().numpy() - ref) / np.linalg.norm(ref))
+
+    cl32 = (torch.ones(1, device=DEV), torch.full((1,), lam, dtype=torch.float32, device=DEV))
+    sinkhorn(t, cl32, a, b, iters=60, on_product=check)
+    print(f"sinkhorn sweeps fp32: {len(errs)} products, max rel err {max(errs):.2e}")
+    assert max(errs) <= 1e-4
+    cl64 = (torch.ones(1, dtype=torch.float64, device=DEV),
+            torch.full((1,), lam, dtype=torch.float64, device=DEV))
+    f64 = torch.tensor(lam ** np.arange(t.kernel_length), dtype=torch.float64, device=DEV)
+    u1, v1, r1 = sinkhorn(t, cl64, a, b, iters=41)
+    u2, v2, r2 = sinkhorn(t, f64, a, b, iters=41)
+    assert np.linalg.norm((u1 - u2).cpu().numpy()) / np.linalg.norm(u2.cpu().numpy()) < 1e-5
+    np.testing.assert_allclose([r for _, r in r1], [r for _, r in r2], rtol=1e-5)
