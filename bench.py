@@ -135,6 +135,10 @@ def main():
                     help="run only the backbone-policy family sweep")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the FP64 2000-vertex, Sinkhorn and 2M-vertex configurations")
+    ap.add_argument("--large-only", action="store_true",
+                    help="run only the 2M-vertex forward + dF measurement")
+    ap.add_argument("--large-trees", default="cater2m,binary2m",
+                    help="comma-separated trees of that measurement")
     ap.add_argument("--configs-only", action="store_true",
                     help="run only those three configurations")
     ap.add_argument("--ablation", action="store_true",
@@ -175,6 +179,9 @@ def main():
         return
     if args.ablation_only:
         print(json.dumps({"policy_ablation": policy_ablation(args)}), flush=True)
+        return
+    if args.large_only:
+        print(json.dumps({"large": large_trees(args)}), flush=True)
         return
     if args.configs_only:
         print(json.dumps({"small_fp64": small_fp64(args), "sinkhorn": sinkhorn_sphere(args),
@@ -747,7 +754,7 @@ def large_trees(args):
     dev = torch.device("cuda", 0)
     budget = 64 << 30
     out_cases = []
-    for name in ("cater2m", "binary2m"):
+    for name in args.large_trees.split(","):
         t0 = time.perf_counter()
         W = S.workload(name)
         p, w, F = W["parent"], W["weight"], W["F"]
@@ -793,7 +800,11 @@ def large_trees(args):
                "value": 2 * n * d / ((ms_f + ms_b) * 1e-3),
                "device_GiB": round(st["device_bytes"] / 2 ** 30, 2),
                "parity": {"rel_err": errs, "ok": max(errs.values()) <= 1e-4},
-               "roofline": stage_roofline(dom, stages[dom], "f32")}
+               "roofline": stage_roofline(dom, stages[dom], "f32", name),
+               "stages": stages}
+        # the FFT cross-interaction stages of this tree (K3)
+        rec["k3_roofline"] = {k: stage_roofline(k, sd, "f32", name)
+                              for k, sd in stages.items() if k.startswith("fft") and sd["ms"] > 0}
         out_cases.append(rec)
         log(f"large[{name}] N={n} d={d}: fwd {ms_f:.2f} ms, bwd dF {ms_b:.2f} ms, "
             f"{rec['device_GiB']} GiB, parity {errs}")

@@ -726,12 +726,21 @@ struct LdsLines {
     int lgc0, ls0, c1, ls1, es, lgtn = 0;
 };
 
+// LDS position of point i of a block stored with one spare element after
+// every 2^PAD (PAD = 0: none). A pass whose lanes read points 2^R apart
+// (the groups of a line, lines one after another) then spreads them over
+// the banks instead of hitting a few.
+template <int PAD>
+__device__ __forceinline__ int lds_at(int i) {
+    return PAD ? i + (i >> PAD) : i;
+}
+
 // One pass: R stages over index bits [s0, s0 + R) of every line. Lines that
 // are part of a longer transform (the blocked global passes) give their
 // twiddles the global index: point e of line l0 stands for index
 // (e << tsh) + tbase + (l0 >> lgtn) (tsh = 0: e itself). Ends with a
 // barrier.
-template <typename T, bool INV, int R>
+template <typename T, bool INV, int R, int PAD = 0>
 __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLines& L, int tsh,
                                          int tbase, const cpx<T>* __restrict__ tw, int lgtw) {
     const int lgr = lgL - R;
@@ -739,8 +748,10 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
     const bool line_fast = L.ls0 < L.es;  // neighbouring lanes on neighbouring addresses
     const int mr = (1 << lgr) - 1, mc = (1 << L.lgc0) - 1;
     const int step = (1 << s0) * L.es;
-    for (int it = threadIdx.x; it < nitems; it += blockDim.x) {
-        int l0, rest;
+    // item it: line (l0, l1) and the butterfly group (hi, lo) of index bits
+    // below and above the pass's R bits
+    auto split = [&](int it, int& l0, int& l1, int& lo, int& hi) {
+        int rest;
         if (line_fast) {
             l0 = it & mc;
             rest = (it >> L.lgc0) & mr;
@@ -748,16 +759,48 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
             rest = it & mr;
             l0 = (it >> lgr) & mc;
         }
-        const int l1 = it >> (lgr + L.lgc0);
-        const int lo = rest & ((1 << s0) - 1), hi = rest >> s0;
+        l1 = it >> (lgr + L.lgc0);
+        lo = rest & ((1 << s0) - 1);
+        hi = rest >> s0;
+    };
+    // table factors of an item's R stages (see the twiddle note above)
+    auto factors = [&](int l0, int lo, cpx<T> (&fs)[R]) {
+        const int J = (lo << tsh) + (tsh ? tbase + (l0 >> L.lgtn) : 0);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int t = J << (lgtw - tsh - s0 - u - 1);
+            if (tsh) {
+                // A pass over the high bits of a long axis would touch the
+                // whole table (megabytes, missing in L2 on every slot): split
+                // t = th 2^lgb + tl, W^t = W^(th 2^lgb) W^tl, two factors
+                // from 2^(lgtw-1-lgb) strided and 2^lgb leading entries.
+                const int lgb = (lgtw + 1) >> 1;
+                fs[u] = cmul(tw[(t >> lgb) << lgb], tw[t & ((1 << lgb) - 1)]);
+            } else {
+                fs[u] = tw[t];
+            }
+        }
+    };
+    const int nb = blockDim.x;
+    cpx<T> fs[R];
+    int l0, l1, lo, hi;
+    if ((int)threadIdx.x < nitems) {
+        split(threadIdx.x, l0, l1, lo, hi);
+        factors(l0, lo, fs);
+    }
+    for (int it = threadIdx.x; it < nitems; it += nb) {
+        split(it, l0, l1, lo, hi);
+        // the next item's factors are requested before this item's work
+        cpx<T> fn[R];
+        if (it + nb < nitems) {
+            int m0, m1, mlo, mhi;
+            split(it + nb, m0, m1, mlo, mhi);
+            factors(m0, mlo, fn);
+        }
         const int base = l0 * L.ls0 + l1 * L.ls1 + ((hi << (s0 + R)) | lo) * L.es;
         cpx<T> x[1 << R];
 #pragma unroll
-        for (int k = 0; k < (1 << R); ++k) x[k] = z[base + k * step];
-        const int J = (lo << tsh) + (tsh ? tbase + (l0 >> L.lgtn) : 0);
-        cpx<T> fs[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) fs[u] = tw[J << (lgtw - tsh - s0 - u - 1)];
+        for (int k = 0; k < (1 << R); ++k) x[k] = z[lds_at<PAD>(base + k * step)];
 #pragma unroll
         for (int uu = 0; uu < R; ++uu) {
             const int u = INV ? uu : R - 1 - uu;
@@ -779,30 +822,32 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
             }
         }
 #pragma unroll
-        for (int k = 0; k < (1 << R); ++k) z[base + k * step] = x[k];
+        for (int k = 0; k < (1 << R); ++k) z[lds_at<PAD>(base + k * step)] = x[k];
+#pragma unroll
+        for (int u = 0; u < R; ++u) fs[u] = fn[u];
     }
     __syncthreads();
 }
 
 // The whole transform of 2^lgL points along every line of L: forward passes
 // from the high index bits down, inverse passes from the low bits up.
-template <typename T, bool INV>
+template <typename T, bool INV, int PAD = 0>
 __device__ void fft_lines(cpx<T>* z, int lgL, const LdsLines& L, int tsh, int tbase,
                           const cpx<T>* __restrict__ tw, int lgtw) {
     if (INV) {
         for (int s0 = 0; s0 < lgL;) {
             const int R = min(3, lgL - s0);
-            if (R == 3) lds_pass<T, INV, 3>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
-            else if (R == 2) lds_pass<T, INV, 2>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
-            else lds_pass<T, INV, 1>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            if (R == 3) lds_pass<T, INV, 3, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            else if (R == 2) lds_pass<T, INV, 2, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            else lds_pass<T, INV, 1, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
             s0 += R;
         }
     } else {
         for (int s1 = lgL; s1 > 0;) {
             const int R = min(3, s1);
-            if (R == 3) lds_pass<T, INV, 3>(z, lgL, s1 - 3, L, tsh, tbase, tw, lgtw);
-            else if (R == 2) lds_pass<T, INV, 2>(z, lgL, s1 - 2, L, tsh, tbase, tw, lgtw);
-            else lds_pass<T, INV, 1>(z, lgL, s1 - 1, L, tsh, tbase, tw, lgtw);
+            if (R == 3) lds_pass<T, INV, 3, PAD>(z, lgL, s1 - 3, L, tsh, tbase, tw, lgtw);
+            else if (R == 2) lds_pass<T, INV, 2, PAD>(z, lgL, s1 - 2, L, tsh, tbase, tw, lgtw);
+            else lds_pass<T, INV, 1, PAD>(z, lgL, s1 - 1, L, tsh, tbase, tw, lgtw);
             s1 -= R;
         }
     }
@@ -909,24 +954,28 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
 // slot s = job * npairs + pair holds P complex.
 // rev != 0: source cell (r, x) at row -r mod L1 (the 2-D convolution);
 // rev = 0: at row r (the per-depth rows of the 1-D path).
+// Job blockIdx.y: a thread takes one cell and every channel pair of it, so
+// that its value row is fetched once and each pair's stores are contiguous
+// across the wave.
 template <typename T>
-__global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
-                              const int32_t* __restrict__ jobs,
+__global__ void k_fill_global(int lg1, int lg2, int32_t npairs, const int32_t* __restrict__ jobs,
                               const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                               const int32_t* __restrict__ jc_val, int32_t d,
                               const T* __restrict__ val, cpx<T>* __restrict__ buf, int rev) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
-    const int64_t slot = blockIdx.y;
-    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
-    const int32_t c0 = 2 * pair, c1 = c0 + 1;
+    const int32_t job = blockIdx.y;
     const int64_t L1 = (int64_t)1 << lg1;
-    cpx<T>* z = buf + slot * P;
+    cpx<T>* z = buf + (int64_t)job * npairs * P;
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
          k += gridDim.x * blockDim.x) {
         const int64_t row = rev ? (L1 - jc_r[k]) & (L1 - 1) : jc_r[k];
-        const int64_t vr = (int64_t)jc_val[k] * d;
-        z[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
+        const int64_t at = (row << lg2) + jc_x[k];
+        const T* v = val + (int64_t)jc_val[k] * d;
+        for (int32_t pair = 0; pair < npairs; ++pair) {
+            const int32_t c0 = 2 * pair;
+            z[pair * P + at] = {v[c0], c0 + 1 < d ? v[c0 + 1] : (T)0};
+        }
     }
 }
 
@@ -948,65 +997,97 @@ __global__ void k_fill_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
 // the kernel spectrum (spec, indexed by the point's offset in its table) and
 // runs the first inverse pass, so the buffer is read and written once for
 // the three.
+constexpr int kPassThreads = 256;  // k_fft_pass block size
+constexpr int kPassPer = 16;       // points per thread (at most 2^12 per workgroup)
+constexpr int kPassPad = 4;        // one spare LDS element per 16 (lds_at)
+
+// LDS elements of a k_fft_pass block of n points.
+constexpr int64_t pass_lds_elems(int64_t n) { return n + (n >> kPassPad); }
+
 template <typename T, bool INV, bool MUL = false>
-__global__ void k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
-                           int64_t nlines, int lglo, int k, int lgC, int lgN, int lgG,
-                           const cpx<T>* __restrict__ tw, int lgtw,
-                           const cpx<T>* __restrict__ spec = nullptr) {
+__global__ void __launch_bounds__(kPassThreads)
+k_fft_pass(cpx<T>* __restrict__ buf, int lgP, int lgL, int64_t es, int64_t ls,
+           int64_t nlines, int lglo, int k, int lgC, int lgN, int lgG,
+           const cpx<T>* __restrict__ tw, int lgtw,
+           const cpx<T>* __restrict__ spec = nullptr) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int64_t C = (int64_t)1 << lgC;
     const int64_t nlo = ((int64_t)1 << lglo) >> lgC;               // low-bit chunks
     const int64_t nhi = ((int64_t)1 << (lgL - lglo - k)) >> lgG;   // high-bit values (groups)
     const int64_t ngrp = nlines >> lgN;                             // groups of N lines
-    int64_t g = blockIdx.x;
+    int64_t g = blockIdx.x, slot = 0;
+    const bool slots_fast = MUL && (gridDim.x & 7) == 0;
+    if (slots_fast) {
+        // Every slot multiplies by the same spectrum chunk. Workgroups are
+        // dealt to the 8 XCDs in turn: renumber them so that each XCD runs a
+        // contiguous range, slots fastest, and the slots of one chunk follow
+        // one another on one XCD, reading the chunk from its L2.
+        g = (g & 7) * (gridDim.x >> 3) + (g >> 3);
+        const int64_t nslots = (int64_t)gridDim.x / (nlo * nhi * ngrp);
+        slot = g % nslots;
+        g /= nslots;
+    }
     const int64_t lo_chunk = g % nlo;
     g /= nlo;
     const int64_t hi = (g % nhi) << lgG;
     g /= nhi;
     const int64_t line = (g % ngrp) << lgN;
-    const int64_t slot = g / ngrp;
+    if (!slots_fast) slot = g / ngrp;
     cpx<T>* base = buf + (slot << lgP) + line * ls;
     const int64_t i0 = (hi << (lglo + k)) + lo_chunk * C;
-    if (lgG > 0) {
-        // lglo = lgC = lgN = 0: 2^lgG groups of 2^k points, point e at i0 + e
-        const int n = 1 << (k + lgG);
-        for (int e = threadIdx.x; e < n; e += blockDim.x) z[e] = base[(i0 + e) * es];
-        __syncthreads();
-        const LdsLines L{lgG, 1 << k, 1, 0, 1};
-        fft_lines<T, INV>(z, k, L, 0, 0, tw, lgtw);
-        if (MUL) {
-            for (int e = threadIdx.x; e < n; e += blockDim.x)
-                z[e] = cmul(z[e], spec[line * ls + (i0 + e) * es]);
-            __syncthreads();
-            fft_lines<T, true>(z, k, L, 0, 0, tw, lgtw);
-        }
-        for (int e = threadIdx.x; e < n; e += blockDim.x) base[(i0 + e) * es] = z[e];
-        return;
-    }
+    // Point e of the workgroup (e = threadIdx.x + u kPassThreads) sits at
+    // off(e) from base. The lgG > 0 pass (lglo = lgC = lgN = 0) holds 2^lgG
+    // groups of 2^k points, point e at i0 + e; the others hold C x N lines
+    // of 2^k points, LDS e = ((j << lgC | lo) << lgN) | ln (line ln fastest)
+    // at ln ls + (i0 + (j << lglo) + lo) es. Every load of the thread is
+    // issued before the first is used.
     const int lgCN = lgC + lgN;
-    const int n = 1 << (k + lgCN);
-    // LDS e = ((j << lgC | lo) << lgN) | ln: line ln fastest
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int n = 1 << (k + (lgG > 0 ? lgG : lgCN));
+    auto off = [&](int e) -> int64_t {
+        if (lgG > 0) return (i0 + e) * es;
         const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
-        z[e] = base[ln * ls + (i0 + (j << lglo) + lo) * es];
+        return ln * ls + (i0 + (j << lglo) + lo) * es;
+    };
+    cpx<T> r[kPassPer], sv[kPassPer];
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+        const int e = threadIdx.x + u * kPassThreads;
+        if (e < n) r[u] = base[off(e)];
+    }
+    if (MUL) {  // the last forward pass (lglo = 0): the spectrum at each point
+#pragma unroll
+        for (int u = 0; u < kPassPer; ++u) {
+            const int e = threadIdx.x + u * kPassThreads;
+            if (e < n) sv[u] = spec[line * ls + off(e)];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+        const int e = threadIdx.x + u * kPassThreads;
+        if (e < n) z[lds_at<kPassPad>(e)] = r[u];
     }
     __syncthreads();
-    // the C x N lines (l0 = lo N + ln) of 2^k points j at stride C N;
-    // twiddles by the global index (j << lglo) + lo_chunk C + lo
-    const LdsLines L{lgCN, 1, 1, 0, 1 << lgCN, lgN};
-    fft_lines<T, INV>(z, k, L, lglo, (int)(lo_chunk * C), tw, lgtw);
-    if (MUL) {  // lglo = 0 here: the last forward pass
-        for (int e = threadIdx.x; e < n; e += blockDim.x) {
-            const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
-            z[e] = cmul(z[e], spec[(line + ln) * ls + (i0 + (j << lglo) + lo) * es]);
+    // lgG > 0: 2^lgG lines of 2^k points; else the C x N lines (l0 = lo N + ln)
+    // of 2^k points j at stride C N, twiddles by the global index
+    // (j << lglo) + lo_chunk C + lo
+    const LdsLines L = lgG > 0 ? LdsLines{lgG, 1 << k, 1, 0, 1}
+                               : LdsLines{lgCN, 1, 1, 0, 1 << lgCN, lgN};
+    const int tsh = lgG > 0 ? 0 : lglo, tb = lgG > 0 ? 0 : (int)(lo_chunk * C);
+    fft_lines<T, INV, kPassPad>(z, k, L, tsh, tb, tw, lgtw);
+    if (MUL) {
+#pragma unroll
+        for (int u = 0; u < kPassPer; ++u) {
+            const int e = threadIdx.x + u * kPassThreads;
+            if (e < n) z[lds_at<kPassPad>(e)] = cmul(z[lds_at<kPassPad>(e)], sv[u]);
         }
         __syncthreads();
-        fft_lines<T, true>(z, k, L, lglo, (int)(lo_chunk * C), tw, lgtw);
+        fft_lines<T, true, kPassPad>(z, k, L, tsh, tb, tw, lgtw);
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int64_t ln = e & ((1 << lgN) - 1), lo = (e >> lgN) & (C - 1), j = e >> lgCN;
-        base[ln * ls + (i0 + (j << lglo) + lo) * es] = z[e];
+#pragma unroll
+    for (int u = 0; u < kPassPer; ++u) {
+        const int e = threadIdx.x + u * kPassThreads;
+        if (e < n) base[off(e)] = z[lds_at<kPassPad>(e)];
     }
 }
 
@@ -1026,25 +1107,28 @@ __global__ void k_spec_fill_global(int lg1, int lg2, int32_t hmax, int32_t xmax,
 
 // Table rows of the cells from the inverse transforms, scaled by 2^-lgS
 // (the points the inverse ran over: P for the 2-D transform, L2 for rows).
+// Job blockIdx.y: a thread writes the whole row of one cell, pair by pair.
 template <typename T>
-__global__ void k_extract_global(int lg1, int lg2, int32_t njobs, int32_t npairs,
+__global__ void k_extract_global(int lg1, int lg2, int32_t npairs,
                                  const int32_t* __restrict__ jobs,
                                  const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const cpx<T>* __restrict__ buf, T* __restrict__ g, int lgS) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
-    const int64_t slot = blockIdx.y;
-    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
-    const int32_t c0 = 2 * pair, c1 = c0 + 1;
-    const cpx<T>* z = buf + slot * P;
+    const int32_t job = blockIdx.y;
+    const cpx<T>* z = buf + (int64_t)job * npairs * P;
     const T scale = (T)1 / (T)((int64_t)1 << lgS);
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
          k += gridDim.x * blockDim.x) {
-        const cpx<T> y = z[((int64_t)jc_r[k] << lg2) + jc_x[k]];
-        const int64_t vr = (int64_t)jc_val[k] * d;
-        g[vr + c0] = y.x * scale;
-        if (c1 < d) g[vr + c1] = y.y * scale;
+        const int64_t at = ((int64_t)jc_r[k] << lg2) + jc_x[k];
+        T* out = g + (int64_t)jc_val[k] * d;
+        for (int32_t pair = 0; pair < npairs; ++pair) {
+            const cpx<T> y = z[pair * P + at];
+            const int32_t c0 = 2 * pair;
+            out[c0] = y.x * scale;
+            if (c0 + 1 < d) out[c0 + 1] = y.y * scale;
+        }
     }
 }
 
@@ -1602,19 +1686,22 @@ __global__ void k_fill2_global(int lg1, int lg2, int32_t npairs, const int32_t* 
                                const T* __restrict__ val, const T* __restrict__ valg,
                                cpx<T>* __restrict__ bv, cpx<T>* __restrict__ bg) {
     const int64_t P = (int64_t)1 << (lg1 + lg2);
-    const int64_t slot = blockIdx.y;
-    const int32_t job = (int32_t)(slot / npairs), pair = (int32_t)(slot % npairs);
-    const int32_t c0 = 2 * pair, c1 = c0 + 1;
+    const int32_t job = blockIdx.y;
     const int64_t L1 = (int64_t)1 << lg1;
-    cpx<T>* zv = bv + slot * P;
-    cpx<T>* zg = bg + slot * P;
+    cpx<T>* zv = bv + (int64_t)job * npairs * P;
+    cpx<T>* zg = bg + (int64_t)job * npairs * P;
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
          k += gridDim.x * blockDim.x) {
         const int64_t vr = (int64_t)jc_val[k] * d;
-        const int64_t row = (L1 - jc_r[k]) & (L1 - 1);
-        zv[(row << lg2) + jc_x[k]] = {val[vr + c0], c1 < d ? val[vr + c1] : (T)0};
-        zg[((int64_t)jc_r[k] << lg2) + jc_x[k]] = {valg[vr + c0], c1 < d ? valg[vr + c1] : (T)0};
+        const int64_t av = (((L1 - jc_r[k]) & (L1 - 1)) << lg2) + jc_x[k];
+        const int64_t ag = ((int64_t)jc_r[k] << lg2) + jc_x[k];
+        for (int32_t pair = 0; pair < npairs; ++pair) {
+            const int32_t c0 = 2 * pair;
+            const bool two = c0 + 1 < d;
+            zv[pair * P + av] = {val[vr + c0], two ? val[vr + c0 + 1] : (T)0};
+            zg[pair * P + ag] = {valg[vr + c0], two ? valg[vr + c0 + 1] : (T)0};
+        }
     }
 }
 

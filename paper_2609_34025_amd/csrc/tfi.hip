@@ -57,6 +57,12 @@ int fail(int code, const std::string& msg) {
 constexpr int kThreads = 256;
 constexpr int kGraphCache = 16;
 
+// Workgroups per job of the per-cell fill and extract kernels (grid-stride
+// over the job's cells): about 4096 in all.
+inline unsigned cell_blocks(int64_t njobs) {
+    return (unsigned)std::max<int64_t>(4, std::min<int64_t>(1024, 4096 / std::max<int64_t>(1, njobs)));
+}
+
 inline unsigned blocks_for(int64_t n, int threads = kThreads) {
     return (unsigned)((n + threads - 1) / threads);
 }
@@ -851,9 +857,9 @@ int conv1d_lds_optin_lg(int lds) {
 }
 
 // Block splits compiled with fixed sizes (straight-line register stages):
-// FP32 with full-line tiles, blocks of 2^7 .. 2^10 points. FP64 at these
+// FP32 with full-line tiles, blocks of 2^5 .. 2^10 points. FP64 at these
 // sizes runs out of registers unrolled and keeps the runtime split.
-constexpr int kC1FixedMin = 7, kC1FixedMax = 10;
+constexpr int kC1FixedMin = 5, kC1FixedMax = 10;
 template <typename T, int TC>
 constexpr bool conv1d_fixed() {
     return std::is_same<T, float>::value && TC == 16;
@@ -863,6 +869,8 @@ template <typename T, int TC>
 int conv1d_lds_optin_tc(int lds) {
     int rc = conv1d_lds_optin_lg<T, TC, 0>(lds);
     if constexpr (conv1d_fixed<T, TC>()) {
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 5>(lds);
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 6>(lds);
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 7>(lds);
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 8>(lds);
         if (!rc) rc = conv1d_lds_optin_lg<T, TC, 9>(lds);
@@ -1287,7 +1295,7 @@ void launch_scatter(tfi_plan* h, const T* src, T* val, T* part, int32_t d, hipSt
 }
 
 // Pass schedule of a transform along an axis of 2^lgL points, 2^lgN
-// neighbouring lines per workgroup: at most 4096 points per workgroup, as
+// neighbouring lines per workgroup: at most 2^lgW points per workgroup, as
 // groups of index bits with 16 consecutive low indices per workgroup (rows,
 // lgN = 0) or with the lines giving the contiguous runs (columns), or one
 // pass when the axis fits. Listed in DIF order (high bits first); the
@@ -1296,11 +1304,19 @@ struct PassSpec {
     int lglo, k, lgC, lgG;
 };
 
+// log2 of the points of a k_fft_pass workgroup: 2^12 in FP32; 2^11 in FP64,
+// whose padded block of 2^12 would pass the 64 KiB LDS a launch may take
+// without opting in.
+template <typename T>
+constexpr int pass_lgw() {
+    return sizeof(T) == 8 ? 11 : 12;
+}
+
 // lgT: index bits of the (possibly merged) axis above which no stage runs
 // but which the last pass may batch into one workgroup (lgT >= lgL).
-inline std::vector<PassSpec> fft_passes(int lgL, int lgN, int lgT) {
+inline std::vector<PassSpec> fft_passes(int lgL, int lgN, int lgT, int lgW) {
     std::vector<PassSpec> v;
-    const int kmax = 12 - lgN;
+    const int kmax = lgW - lgN;
     int hi = lgL;
     while (hi > 0) {
         if (hi <= kmax) {
@@ -1325,7 +1341,7 @@ struct AxisPlan {
     std::vector<PassSpec> ps;  // DIF order
 };
 
-inline AxisPlan plan_axis(int lgL, int64_t es, int64_t ls, int64_t nlines, int lgN) {
+inline AxisPlan plan_axis(int lgL, int64_t es, int64_t ls, int64_t nlines, int lgN, int lgW) {
     AxisPlan a;
     while (lgN > 0 && ((int64_t)1 << lgN) > nlines) --lgN;
     // lines that follow one another in memory form one longer axis: its top
@@ -1341,7 +1357,7 @@ inline AxisPlan plan_axis(int lgL, int64_t es, int64_t ls, int64_t nlines, int l
     a.es = es;
     a.ls = ls;
     a.nlines = nlines;
-    a.ps = fft_passes(lgL, lgN, lgA);
+    a.ps = fft_passes(lgL, lgN, lgA, lgW);
     return a;
 }
 
@@ -1352,9 +1368,9 @@ void launch_pass(tfi::cpx<T>* buf, int64_t nslots, int lgP, const AxisPlan& a, c
     const int64_t groups = nslots * (a.nlines >> a.lgN) *
                            (((int64_t)1 << (a.lgA - q.lglo - q.k)) >> q.lgG) *
                            (((int64_t)1 << q.lglo) >> q.lgC);
-    const unsigned lds =
-        (unsigned)(((int64_t)1 << (q.k + q.lgC + a.lgN + q.lgG)) * sizeof(tfi::cpx<T>));
-    hipLaunchKernelGGL((tfi::k_fft_pass<T, INV, MUL>), dim3((unsigned)groups), dim3(kThreads), lds,
+    const unsigned lds = (unsigned)(tfi::pass_lds_elems((int64_t)1 << (q.k + q.lgC + a.lgN + q.lgG)) *
+                                    sizeof(tfi::cpx<T>));
+    hipLaunchKernelGGL((tfi::k_fft_pass<T, INV, MUL>), dim3((unsigned)groups), dim3(tfi::kPassThreads), lds,
                        st, buf, lgP, a.lgA, a.es, a.ls, a.nlines, q.lglo, q.k, q.lgC, a.lgN, q.lgG,
                        tw, lgtw, spec);
 }
@@ -1362,7 +1378,7 @@ void launch_pass(tfi::cpx<T>* buf, int64_t nslots, int lgP, const AxisPlan& a, c
 template <typename T, bool INV>
 void launch_axis(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
                  int64_t nlines, int lgN, const tfi::cpx<T>* tw, int lgtw, hipStream_t st) {
-    AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN);
+    AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN, pass_lgw<T>());
     std::vector<PassSpec> ps = a.ps;
     if (INV) std::reverse(ps.begin(), ps.end());
     for (const PassSpec& q : ps) launch_pass<T, INV>(buf, nslots, lgP, a, q, tw, lgtw, st);
@@ -1375,7 +1391,7 @@ template <typename T>
 void launch_axis_conv(tfi::cpx<T>* buf, int64_t nslots, int lgP, int lgL, int64_t es, int64_t ls,
                       int64_t nlines, int lgN, const tfi::cpx<T>* spec, const tfi::cpx<T>* tw,
                       int lgtw, hipStream_t st) {
-    const AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN);
+    const AxisPlan a = plan_axis(lgL, es, ls, nlines, lgN, pass_lgw<T>());
     const size_t np = a.ps.size();
     for (size_t i = 0; i + 1 < np; ++i) launch_pass<T, false>(buf, nslots, lgP, a, a.ps[i], tw, lgtw, st);
     launch_pass<T, false, true>(buf, nslots, lgP, a, a.ps[np - 1], tw, lgtw, st, spec);
@@ -1522,13 +1538,15 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
         hi_inv = tfi::k_conv1d_hi<T, TC, true, LG>;              \
     }                                                            \
     if (lgL == LG) lo = tfi::k_conv1d_lo<T, TC, LG>;
+        TFI_C1_FIXED(5)
+        TFI_C1_FIXED(6)
         TFI_C1_FIXED(7)
         TFI_C1_FIXED(8)
         TFI_C1_FIXED(9)
         TFI_C1_FIXED(10)
 #undef TFI_C1_FIXED
         if (lo_parts == 2) lo = tfi::k_conv1d_lo<T, TC, 10, TC / 2>;
-        static_assert(kC1FixedMin == 7 && kC1FixedMax == 10, "fixed splits listed above");
+        static_assert(kC1FixedMin == 5 && kC1FixedMax == 10, "fixed splits listed above");
     }
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
@@ -1597,18 +1615,18 @@ void launch_d1_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T* 
         tfi::cpx<T>* mixed = buf + nslots * P;
         hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * P)), dim3(kThreads),
                            0, st, buf, nslots * P);
-        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
-                           st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, val, buf, 0);
+        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(cell_blocks(nj), (unsigned)nj),
+                           dim3(kThreads), 0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r,
+                           h->d_jc_x, h->d_jc_val, d, val, buf, 0);
         launch_rows<T, false>(buf, nslots, b.lg1, b.lg2, (int64_t)b.hmax + 1, tw, h->lgtw, st);
         const int64_t n = nslots * ((int64_t)b.hmax + 1) << b.lg2;
         hipLaunchKernelGGL(tfi::k_d1_mix<T>, dim3(blocks_for(n)), dim3(kThreads), 0, st, b.lg1,
                            b.lg2, b.hmax, nslots, (const tfi::cpx<T>*)buf, spec + b.spec_off,
                            mixed);
         launch_rows<T, true>(mixed, nslots, b.lg1, b.lg2, (int64_t)b.hmax + 1, tw, h->lgtw, st);
-        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                           0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, (const tfi::cpx<T>*)mixed, g, b.lg2);
+        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(cell_blocks(nj), (unsigned)nj),
+                           dim3(kThreads), 0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r,
+                           h->d_jc_x, h->d_jc_val, d, (const tfi::cpx<T>*)mixed, g, b.lg2);
     }
 }
 
@@ -1638,14 +1656,14 @@ void launch_fft_global(tfi_plan* h, const Bucket& b, int32_t d, const T* val, T*
         const int32_t* jobs = b.d_jobs + 2 * j0;
         hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(nslots * b.P())),
                            dim3(kThreads), 0, st, buf, nslots * b.P());
-        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads), 0,
-                           st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, val, buf, 1);
+        hipLaunchKernelGGL(tfi::k_fill_global<T>, dim3(cell_blocks(nj), (unsigned)nj),
+                           dim3(kThreads), 0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r,
+                           h->d_jc_x, h->d_jc_val, d, val, buf, 1);
         launch_conv2<T>(buf, nslots, b.lg1, b.lg2, spec + b.spec_off, tw, h->lgtw,
                         h->fp.col_lines, st);
-        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                           0, st, b.lg1, b.lg2, (int32_t)nj, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                           h->d_jc_val, d, buf, g, lgP);
+        hipLaunchKernelGGL(tfi::k_extract_global<T>, dim3(cell_blocks(nj), (unsigned)nj),
+                           dim3(kThreads), 0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r,
+                           h->d_jc_x, h->d_jc_val, d, buf, g, lgP);
     }
 }
 
@@ -2016,9 +2034,9 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
             const int32_t* jobs = b.d_jobs + 2 * j0;
             hipLaunchKernelGGL(tfi::k_zero<tfi::cpx<T>>, dim3(blocks_for(2 * nslots * P)),
                                dim3(kThreads), 0, st, bv, 2 * nslots * P);
-            hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(64, (unsigned)nslots), dim3(kThreads),
-                               0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r, h->d_jc_x,
-                               h->d_jc_val, d, val, valg, bv, bg);
+            hipLaunchKernelGGL(tfi::k_fill2_global<T>, dim3(cell_blocks(nj), (unsigned)nj),
+                               dim3(kThreads), 0, st, b.lg1, b.lg2, npairs, jobs, h->d_jc_r,
+                               h->d_jc_x, h->d_jc_val, d, val, valg, bv, bg);
             launch_fft2<T, false>(bv, 2 * nslots, b.lg1, b.lg2, tw, h->lgtw, h->fp.col_lines, st);
             hipLaunchKernelGGL(tfi::k_corr_accum_global<T>, dim3(blocks_for(nj * P)),
                                dim3(kThreads), 0, st, nj, npairs, lgP, (const tfi::cpx<T>*)bv,
