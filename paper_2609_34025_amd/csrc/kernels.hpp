@@ -855,10 +855,10 @@ __device__ void fft_lines(cpx<T>* z, int lgL, const LdsLines& L, int tsh, int tb
 
 // One axis of a 2-D array: `count` (a power of two) lines of 2^lgL points,
 // element stride es, line stride ls.
-template <typename T, bool INV>
+template <typename T, bool INV, int PAD = 0>
 __device__ void fft_axis_lds(cpx<T>* z, int lgL, int count, int es, int ls,
                              const cpx<T>* __restrict__ tw, int lgtw) {
-    fft_lines<T, INV>(z, lgL, LdsLines{31 - __clz(count), ls, 1, 0, es}, 0, 0, tw, lgtw);
+    fft_lines<T, INV, PAD>(z, lgL, LdsLines{31 - __clz(count), ls, 1, 0, es}, 0, 0, tw, lgtw);
 }
 
 // Bucket parameters of merged launches: bp[4 b .. 4 b + 3] = (lg1, lg2,
@@ -900,7 +900,13 @@ __global__ void k_spectrum_multi(const int32_t* __restrict__ bp, const int64_t* 
 // (-r mod L1): the Hankel dependence on q + r becomes a circular
 // convolution whose output row q needs no shift. The rows of all the
 // group's tables transform as one batch of lines, then their columns.
-template <typename T>
+// PAD: the block is stored with lds_at<PAD> (one spare element per 2^PAD),
+// so that the row passes, whose lanes read points of one row 8 apart, do not
+// share banks. Each thread issues the global loads of kConvBatch items
+// before it uses the first.
+constexpr int kConvBatch = 8;
+
+template <typename T, int PAD = 0>
 __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* __restrict__ bp,
                                  const int64_t* __restrict__ bo,
                                  const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
@@ -915,35 +921,83 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
     const cpx<T>* spec = spec_all + bo[bk];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2, lgP = lg1 + lg2;
     const int NP = 1 << lgnp;
+    const int nb = blockDim.x;
     const int32_t ch0 = 2 * (int32_t)blockIdx.y * NP;  // first channel of the group
-    for (int p = threadIdx.x; p < NP * P; p += blockDim.x) z[p] = {(T)0, (T)0};
+    for (int p = threadIdx.x; p < NP * P; p += nb) z[lds_at<PAD>(p)] = {(T)0, (T)0};
     __syncthreads();
+    // item it: cell cb + (it >> lgnp), pair it mod NP of the group
     const int32_t items = (ce - cb) << lgnp;
-    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
-        const int c = it & (NP - 1);
-        const int32_t k = cb + (it >> lgnp), ch = ch0 + 2 * c;
-        if (ch >= d) continue;
-        const int row = (L1 - jc_r[k]) & (L1 - 1);
-        const int64_t vr = (int64_t)jc_val[k] * d;
-        z[(c << lgP) + (row << lg2) + jc_x[k]] = {val[vr + ch], ch + 1 < d ? val[vr + ch + 1] : (T)0};
+    for (int32_t i0 = threadIdx.x; i0 < items; i0 += kConvBatch * nb) {
+        int at[kConvBatch];
+        int64_t vr[kConvBatch];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) {
+            const int32_t it = i0 + u * nb;
+            at[u] = -1;
+            if (it < items) {
+                const int c = it & (NP - 1);
+                const int32_t k = cb + (it >> lgnp);
+                const int row = (L1 - jc_r[k]) & (L1 - 1);
+                at[u] = (c << lgP) + (row << lg2) + jc_x[k];
+                vr[u] = (int64_t)jc_val[k] * d + ch0 + 2 * c;
+                if (ch0 + 2 * c >= d) at[u] = -1;
+            }
+        }
+        cpx<T> v[kConvBatch];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) {
+            const int32_t it = i0 + u * nb;
+            if (at[u] >= 0) {
+                const int ch = ch0 + 2 * (it & (NP - 1));
+                v[u] = {val[vr[u]], ch + 1 < d ? val[vr[u] + 1] : (T)0};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u)
+            if (at[u] >= 0) z[lds_at<PAD>(at[u])] = v[u];
     }
     __syncthreads();
     const LdsLines rows{lg1 + lgnp, L2, 1, 0, 1}, cols{lg2, 1, NP, P, L2};
-    fft_lines<T, false>(z, lg2, rows, 0, 0, tw, lgtw);
-    fft_lines<T, false>(z, lg1, cols, 0, 0, tw, lgtw);
-    for (int p = threadIdx.x; p < NP * P; p += blockDim.x) z[p] = cmul(z[p], spec[p & (P - 1)]);
+    fft_lines<T, false, PAD>(z, lg2, rows, 0, 0, tw, lgtw);
+    fft_lines<T, false, PAD>(z, lg1, cols, 0, 0, tw, lgtw);
+    for (int p0 = threadIdx.x; p0 < NP * P; p0 += kConvBatch * nb) {
+        cpx<T> sv[kConvBatch];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u)
+            if (p0 + u * nb < NP * P) sv[u] = spec[(p0 + u * nb) & (P - 1)];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) {
+            const int p = p0 + u * nb;
+            if (p < NP * P) z[lds_at<PAD>(p)] = cmul(z[lds_at<PAD>(p)], sv[u]);
+        }
+    }
     __syncthreads();
-    fft_lines<T, true>(z, lg1, cols, 0, 0, tw, lgtw);
-    fft_lines<T, true>(z, lg2, rows, 0, 0, tw, lgtw);
+    fft_lines<T, true, PAD>(z, lg1, cols, 0, 0, tw, lgtw);
+    fft_lines<T, true, PAD>(z, lg2, rows, 0, 0, tw, lgtw);
     const T scale = (T)1 / (T)P;
-    for (int32_t it = threadIdx.x; it < items; it += blockDim.x) {
-        const int c = it & (NP - 1);
-        const int32_t k = cb + (it >> lgnp), ch = ch0 + 2 * c;
-        if (ch >= d) continue;
-        const cpx<T> y = z[(c << lgP) + (jc_r[k] << lg2) + jc_x[k]];
-        const int64_t vr = (int64_t)jc_val[k] * d;
-        g[vr + ch] = y.x * scale;
-        if (ch + 1 < d) g[vr + ch + 1] = y.y * scale;
+    for (int32_t i0 = threadIdx.x; i0 < items; i0 += kConvBatch * nb) {
+        int at[kConvBatch];
+        int64_t vr[kConvBatch];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) {
+            const int32_t it = i0 + u * nb;
+            at[u] = -1;
+            if (it < items) {
+                const int c = it & (NP - 1);
+                const int32_t k = cb + (it >> lgnp);
+                at[u] = (c << lgP) + (jc_r[k] << lg2) + jc_x[k];
+                vr[u] = (int64_t)jc_val[k] * d + ch0 + 2 * c;
+                if (ch0 + 2 * c >= d) at[u] = -1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) {
+            if (at[u] < 0) continue;
+            const cpx<T> y = z[lds_at<PAD>(at[u])];
+            const int ch = ch0 + 2 * ((i0 + u * nb) & (NP - 1));
+            g[vr[u]] = y.x * scale;
+            if (ch + 1 < d) g[vr[u] + 1] = y.y * scale;
+        }
     }
 }
 
@@ -1602,7 +1656,14 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
 // written to global memory (slot = job * groups + group).
 constexpr int kDfPairs = 4;
 
-template <typename T>
+// PAD: the two transformed tables are one block stored with lds_at<PAD>
+// (zv point p at p, zg point p at P + p); the accumulator follows it. The
+// cells' loads go out kDfBatch at a time (two tables per cell: a smaller
+// batch than the forward kernel's keeps the registers of small tables'
+// workgroups within occupancy).
+constexpr int kDfBatch = 4;
+
+template <typename T, int PAD = 0>
 __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ jobs,
                                  const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                                  const int32_t* __restrict__ jc_val, int32_t d,
@@ -1612,41 +1673,61 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
     extern __shared__ unsigned char smem_raw[];
     const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    const int nb = blockDim.x;
     cpx<T>* zv = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* zg = zv + P;
-    cpx<T>* acc = zg + P;
+    cpx<T>* acc = zv + 2 * P + (PAD ? (2 * P) >> PAD : 0);
     const int32_t npairs = (d + 1) / 2;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = {(T)0, (T)0};
+    for (int p = threadIdx.x; p < P; p += nb) acc[p] = {(T)0, (T)0};
     const int32_t pe = min(npairs, (int32_t)(blockIdx.y + 1) * kDfPairs);
     for (int32_t pr = blockIdx.y * kDfPairs; pr < pe; ++pr) {
         const int32_t c0 = 2 * pr, c1 = c0 + 1;
         const bool has1 = c1 < d;
-        for (int p = threadIdx.x; p < P; p += blockDim.x) {
-            zv[p] = {(T)0, (T)0};
-            zg[p] = {(T)0, (T)0};
-        }
+        for (int p = threadIdx.x; p < 2 * P; p += nb) zv[lds_at<PAD>(p)] = {(T)0, (T)0};
         __syncthreads();
-        for (int32_t k = cb + threadIdx.x; k < ce; k += blockDim.x) {
-            const int64_t vr = (int64_t)jc_val[k] * d;
-            const int row = (L1 - jc_r[k]) & (L1 - 1);
-            zv[(row << lg2) + jc_x[k]] = {val[vr + c0], has1 ? val[vr + c1] : (T)0};
-            zg[(jc_r[k] << lg2) + jc_x[k]] = {valg[vr + c0], has1 ? valg[vr + c1] : (T)0};
+        for (int32_t k0 = cb + threadIdx.x; k0 < ce; k0 += kDfBatch * nb) {
+            int av[kDfBatch], ag[kDfBatch];
+            int64_t vr[kDfBatch];
+#pragma unroll
+            for (int u = 0; u < kDfBatch; ++u) {
+                const int32_t k = k0 + u * nb;
+                av[u] = -1;
+                if (k < ce) {
+                    vr[u] = (int64_t)jc_val[k] * d + c0;
+                    const int r = jc_r[k], x = jc_x[k];
+                    av[u] = (((L1 - r) & (L1 - 1)) << lg2) + x;
+                    ag[u] = P + (r << lg2) + x;
+                }
+            }
+            cpx<T> v[kDfBatch], w[kDfBatch];
+#pragma unroll
+            for (int u = 0; u < kDfBatch; ++u) {
+                if (av[u] < 0) continue;
+                v[u] = {val[vr[u]], has1 ? val[vr[u] + 1] : (T)0};
+                w[u] = {valg[vr[u]], has1 ? valg[vr[u] + 1] : (T)0};
+            }
+#pragma unroll
+            for (int u = 0; u < kDfBatch; ++u) {
+                if (av[u] < 0) continue;
+                zv[lds_at<PAD>(av[u])] = v[u];
+                zv[lds_at<PAD>(ag[u])] = w[u];
+            }
         }
         __syncthreads();
         // zv and zg side by side: their rows, then their columns, as one batch
-        fft_lines<T, false>(zv, lg2, LdsLines{lg1 + 1, L2, 1, 0, 1}, 0, 0, tw, lgtw);
-        fft_lines<T, false>(zv, lg1, LdsLines{lg2, 1, 2, P, L2}, 0, 0, tw, lgtw);
-        for (int p = threadIdx.x; p < P; p += blockDim.x) acc[p] = cadd(acc[p], cmulc(zg[p], zv[p]));
+        fft_lines<T, false, PAD>(zv, lg2, LdsLines{lg1 + 1, L2, 1, 0, 1}, 0, 0, tw, lgtw);
+        fft_lines<T, false, PAD>(zv, lg1, LdsLines{lg2, 1, 2, P, L2}, 0, 0, tw, lgtw);
+        for (int p = threadIdx.x; p < P; p += nb)
+            acc[p] = cadd(acc[p], cmulc(zv[lds_at<PAD>(P + p)], zv[lds_at<PAD>(p)]));
         __syncthreads();
     }
     cpx<T>* out = part + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * P;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) out[p] = acc[p];
+    for (int p = threadIdx.x; p < P; p += nb) out[p] = acc[p];
 }
 
 // FFT jobs, pass 2: one workgroup per job sums the group spectra (fixed
 // order), applies one inverse transform and folds Re Z[a][b] (a = q + r,
 // b = s - x mod L2) into df[a + |b|], binned in LDS in fixed point.
-template <typename T>
+template <typename T, int PAD = 0>
 __global__ void k_df_fft_fold(int lg1, int lg2, const int32_t* __restrict__ jobs,
                               const int32_t* __restrict__ job_hx, int32_t groups, int64_t NA,
                               const int32_t* __restrict__ jc_val, const cpx<T>* __restrict__ part,
@@ -1654,25 +1735,40 @@ __global__ void k_df_fft_fold(int lg1, int lg2, const int32_t* __restrict__ jobs
     extern __shared__ unsigned char smem_raw[];
     const int32_t cb = jobs[2 * blockIdx.x];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    const int nb = blockDim.x;
     const int32_t H = job_hx[2 * blockIdx.x], X = job_hx[2 * blockIdx.x + 1];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
-    u64* lh = reinterpret_cast<u64*>(z + P);
+    u64* lh = reinterpret_cast<u64*>(z + P + (PAD ? P >> PAD : 0));
     const int32_t nk = 2 * H + X + 1;  // bins this job can reach
     hist_clear(lh, nk);
     const cpx<T>* src = part + (int64_t)blockIdx.x * groups * P;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
-        cpx<T> s = {(T)0, (T)0};
-        for (int32_t gq = 0; gq < groups; ++gq) s = cadd(s, src[(int64_t)gq * P + p]);
-        z[p] = s;
+    // group spectra summed in group order; the loads of kConvBatch points
+    // are issued together
+    for (int p0 = threadIdx.x; p0 < P; p0 += kConvBatch * nb) {
+        cpx<T> acc[kConvBatch];
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u) acc[u] = {(T)0, (T)0};
+        for (int32_t gq = 0; gq < groups; ++gq) {
+            cpx<T> v[kConvBatch];
+#pragma unroll
+            for (int u = 0; u < kConvBatch; ++u)
+                if (p0 + u * nb < P) v[u] = src[(int64_t)gq * P + p0 + u * nb];
+#pragma unroll
+            for (int u = 0; u < kConvBatch; ++u)
+                if (p0 + u * nb < P) acc[u] = cadd(acc[u], v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kConvBatch; ++u)
+            if (p0 + u * nb < P) z[lds_at<PAD>(p0 + u * nb)] = acc[u];
     }
     __syncthreads();
-    fft_axis_lds<T, true>(z, lg1, L2, L2, 1, tw, lgtw);
-    fft_axis_lds<T, true>(z, lg2, L1, 1, L2, tw, lgtw);
+    fft_axis_lds<T, true, PAD>(z, lg1, L2, L2, 1, tw, lgtw);
+    fft_axis_lds<T, true, PAD>(z, lg2, L1, 1, L2, tw, lgtw);
     const T scale = (jc_val[cb] < NA ? (T)1 : (T)-1) / (T)P;
-    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    for (int p = threadIdx.x; p < P; p += nb) {
         const int a = p >> lg2, b = p & (L2 - 1);
         const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
-        if (a <= 2 * H && bs <= X) df_atomic(lh, a + bs, (double)(z[p].x * scale));
+        if (a <= 2 * H && bs <= X) df_atomic(lh, a + bs, (double)(z[lds_at<PAD>(p)].x * scale));
     }
     hist_flush(lh, df, nk);
 }

@@ -477,6 +477,10 @@ int lds_optin_once(int device, int lds) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<double>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<float, tfi::kPassPad>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_fft_conv_multi<double, tfi::kPassPad>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<float>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_spectrum_multi<double>,
@@ -488,6 +492,14 @@ int lds_optin_once(int device, int lds) {
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<float>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float, tfi::kPassPad>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double, tfi::kPassPad>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<float, tfi::kPassPad>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double, tfi::kPassPad>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int rc1 = conv1d_lds_optin<float>(lds);
     if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
@@ -1849,11 +1861,22 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
         if (!T_.njobs) continue;
         const int lgnp = fft_lgnp(h, ti, t, npairs);
         const unsigned groups = (unsigned)((npairs + (1 << lgnp) - 1) >> lgnp);
+        // the padded block where it fits the LDS limit
+        const int64_t lds = T_.lds_bytes << lgnp;
+        const int64_t lds_pad = tfi::pass_lds_elems(lds / (int64_t)sizeof(tfi::cpx<T>)) *
+                                (int64_t)sizeof(tfi::cpx<T>);
+        const bool pad = lds_pad <= h->lds_max;
         hipEvent_t ev = h->begin(st);
-        hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, groups),
-                           dim3(kThreads), (unsigned)(T_.lds_bytes << lgnp), st, T_.d_fj, T_.d_bp,
-                           T_.d_bo, h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw,
-                           h->lgtw, lgnp);
+        if (pad)
+            hipLaunchKernelGGL((tfi::k_fft_conv_multi<T, tfi::kPassPad>),
+                               dim3((unsigned)T_.njobs, groups), dim3(kThreads), (unsigned)lds_pad,
+                               st, T_.d_fj, T_.d_bp, T_.d_bo, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
+                               val, g, spec, tw, h->lgtw, lgnp);
+        else
+            hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, groups),
+                               dim3(kThreads), (unsigned)lds, st, T_.d_fj, T_.d_bp, T_.d_bo,
+                               h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw, h->lgtw,
+                               lgnp);
         h->end(st, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
@@ -2008,14 +2031,31 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
         if (lds) {
             hipEvent_t ev = h->begin(st);
             tfi::cpx<T>* part = (tfi::cpx<T>*)h->dfbuf[ti].p;
-            hipLaunchKernelGGL(tfi::k_df_fft_partial<T>, dim3((unsigned)b.njobs(), groups),
-                               dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
-                               h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part);
-            const unsigned fold_lds =
-                (unsigned)(P * sizeof(tfi::cpx<T>) + (2 * b.hmax + b.xmax + 1) * 2 * sizeof(tfi::u64));
-            hipLaunchKernelGGL(tfi::k_df_fft_fold<T>, dim3((unsigned)b.njobs()), dim3(kThreads),
-                               fold_lds, st, b.lg1, b.lg2, b.d_jobs, b.d_hx, groups, p.NA,
-                               h->d_jc_val, (const tfi::cpx<T>*)part, tw, h->lgtw, df);
+            // padded LDS blocks (lds_at) where they fit the limit
+            const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
+            const int64_t lds_pad = (tfi::pass_lds_elems(2 * P) + P) * cs;
+            if (lds_pad <= h->lds_max)
+                hipLaunchKernelGGL((tfi::k_df_fft_partial<T, tfi::kPassPad>),
+                                   dim3((unsigned)b.njobs(), groups), dim3(kThreads),
+                                   (unsigned)lds_pad, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
+                                   h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part);
+            else
+                hipLaunchKernelGGL(tfi::k_df_fft_partial<T>, dim3((unsigned)b.njobs(), groups),
+                                   dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
+                                   h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
+                                   part);
+            const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
+            const int64_t fold_lds = P * cs + hist, fold_pad = tfi::pass_lds_elems(P) * cs + hist;
+            if (fold_pad <= h->lds_max)
+                hipLaunchKernelGGL((tfi::k_df_fft_fold<T, tfi::kPassPad>),
+                                   dim3((unsigned)b.njobs()), dim3(kThreads), (unsigned)fold_pad,
+                                   st, b.lg1, b.lg2, b.d_jobs, b.d_hx, groups, p.NA, h->d_jc_val,
+                                   (const tfi::cpx<T>*)part, tw, h->lgtw, df);
+            else
+                hipLaunchKernelGGL(tfi::k_df_fft_fold<T>, dim3((unsigned)b.njobs()),
+                                   dim3(kThreads), (unsigned)fold_lds, st, b.lg1, b.lg2, b.d_jobs,
+                                   b.d_hx, groups, p.NA, h->d_jc_val, (const tfi::cpx<T>*)part,
+                                   tw, h->lgtw, df);
             h->end(st, ev, "df_fft_lds", bytes);
             continue;
         }
