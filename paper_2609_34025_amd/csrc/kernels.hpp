@@ -1001,6 +1001,27 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
     }
 }
 
+// One channel pair of a row as a single 8- or 16-byte access (the pair
+// starts at an even channel of a row of even length, in a buffer aligned to
+// two elements).
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_pair(const T* p) {
+    if constexpr (sizeof(T) == 4) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        return {v.x, v.y};
+    } else {
+        const double2 v = *reinterpret_cast<const double2*>(p);
+        return {v.x, v.y};
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(T* p, cpx<T> v) {
+    if constexpr (sizeof(T) == 4)
+        *reinterpret_cast<float2*>(p) = make_float2(v.x, v.y);
+    else
+        *reinterpret_cast<double2*>(p) = make_double2(v.x, v.y);
+}
+
 // ---------------------------------------------- FFT through global memory --
 // Tables too large for LDS: the same in-place DIF/DIT transforms over every
 // (job, channel pair) slot of a bucket, as blocked passes (k_fft_pass) of up
@@ -1008,27 +1029,67 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
 // slot s = job * npairs + pair holds P complex.
 // rev != 0: source cell (r, x) at row -r mod L1 (the 2-D convolution);
 // rev = 0: at row r (the per-depth rows of the 1-D path).
-// Job blockIdx.y: a thread takes one cell and every channel pair of it, so
-// that its value row is fetched once and each pair's stores are contiguous
-// across the wave.
+// Job blockIdx.y; a workgroup takes kXCells cells at a time and moves them
+// through LDS in chunks of kXPairs channel pairs: the value rows are read
+// whole (4 threads per cell, 4 pairs each) and every pair's points are
+// written by consecutive lanes, one cell per lane.
+constexpr int kXCells = 64, kXPairs = 16, kXStride = kXPairs + 1;
+
+// The cell's table point (-1 past the job's end) and value row.
+__device__ __forceinline__ void cell_point(int32_t k, int32_t ce, const int32_t* __restrict__ jc_r,
+                                           const int32_t* __restrict__ jc_x,
+                                           const int32_t* __restrict__ jc_val, int64_t L1, int lg2,
+                                           int rev, int64_t& at, int64_t& vrow) {
+    at = -1;
+    vrow = 0;
+    if (k < ce) {
+        const int64_t row = rev ? (L1 - jc_r[k]) & (L1 - 1) : jc_r[k];
+        at = (row << lg2) + jc_x[k];
+        vrow = jc_val[k];
+    }
+}
+
 template <typename T>
-__global__ void k_fill_global(int lg1, int lg2, int32_t npairs, const int32_t* __restrict__ jobs,
-                              const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
-                              const int32_t* __restrict__ jc_val, int32_t d,
-                              const T* __restrict__ val, cpx<T>* __restrict__ buf, int rev) {
+__global__ void __launch_bounds__(256)
+k_fill_global(int lg1, int lg2, int32_t npairs, const int32_t* __restrict__ jobs,
+              const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+              const int32_t* __restrict__ jc_val, int32_t d, const T* __restrict__ val,
+              cpx<T>* __restrict__ buf, int rev) {
+    __shared__ cpx<T> sc[kXCells * kXStride];
     const int64_t P = (int64_t)1 << (lg1 + lg2);
     const int32_t job = blockIdx.y;
     const int64_t L1 = (int64_t)1 << lg1;
     cpx<T>* z = buf + (int64_t)job * npairs * P;
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
-    for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
-         k += gridDim.x * blockDim.x) {
-        const int64_t row = rev ? (L1 - jc_r[k]) & (L1 - 1) : jc_r[k];
-        const int64_t at = (row << lg2) + jc_x[k];
-        const T* v = val + (int64_t)jc_val[k] * d;
-        for (int32_t pair = 0; pair < npairs; ++pair) {
-            const int32_t c0 = 2 * pair;
-            z[pair * P + at] = {v[c0], c0 + 1 < d ? v[c0 + 1] : (T)0};
+    const bool pairs = (d & 1) == 0 && ((uintptr_t)val & (2 * sizeof(T) - 1)) == 0;
+    const int t = threadIdx.x;
+    for (int32_t k0 = cb + blockIdx.x * kXCells; k0 < ce; k0 += gridDim.x * kXCells) {
+        // lane view: cell t % 64 (points); row view: cell t / 4, pairs 4 (t % 4) ..
+        int64_t at, vrow, at_r, vrow_r;
+        cell_point(k0 + (t & 63), ce, jc_r, jc_x, jc_val, L1, lg2, rev, at, vrow);
+        cell_point(k0 + (t >> 2), ce, jc_r, jc_x, jc_val, L1, lg2, rev, at_r, vrow_r);
+        for (int32_t p0 = 0; p0 < npairs; p0 += kXPairs) {
+            __syncthreads();
+            if (at_r >= 0) {
+                const T* v = val + vrow_r * d;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t pl = 4 * (t & 3) + q, c0 = 2 * (p0 + pl);
+                    if (p0 + pl >= npairs) continue;
+                    cpx<T> y;
+                    if (pairs) y = ld_pair(v + c0);
+                    else y = {v[c0], c0 + 1 < d ? v[c0 + 1] : (T)0};
+                    sc[(t >> 2) * kXStride + pl] = y;
+                }
+            }
+            __syncthreads();
+            if (at >= 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t pl = (t >> 6) + 4 * q;
+                    if (p0 + pl < npairs) z[(p0 + pl) * P + at] = sc[(t & 63) * kXStride + pl];
+                }
+            }
         }
     }
 }
@@ -1161,27 +1222,57 @@ __global__ void k_spec_fill_global(int lg1, int lg2, int32_t hmax, int32_t xmax,
 
 // Table rows of the cells from the inverse transforms, scaled by 2^-lgS
 // (the points the inverse ran over: P for the 2-D transform, L2 for rows).
-// Job blockIdx.y: a thread writes the whole row of one cell, pair by pair.
+// Job blockIdx.y; the transpose of k_fill_global: every pair's points read
+// by consecutive lanes, the rows written whole.
 template <typename T>
-__global__ void k_extract_global(int lg1, int lg2, int32_t npairs,
-                                 const int32_t* __restrict__ jobs,
-                                 const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
-                                 const int32_t* __restrict__ jc_val, int32_t d,
-                                 const cpx<T>* __restrict__ buf, T* __restrict__ g, int lgS) {
+__global__ void __launch_bounds__(256)
+k_extract_global(int lg1, int lg2, int32_t npairs, const int32_t* __restrict__ jobs,
+                 const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
+                 const int32_t* __restrict__ jc_val, int32_t d, const cpx<T>* __restrict__ buf,
+                 T* __restrict__ g, int lgS) {
+    __shared__ cpx<T> sc[kXCells * kXStride];
     const int64_t P = (int64_t)1 << (lg1 + lg2);
     const int32_t job = blockIdx.y;
     const cpx<T>* z = buf + (int64_t)job * npairs * P;
     const T scale = (T)1 / (T)((int64_t)1 << lgS);
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
-    for (int32_t k = cb + blockIdx.x * blockDim.x + threadIdx.x; k < ce;
-         k += gridDim.x * blockDim.x) {
-        const int64_t at = ((int64_t)jc_r[k] << lg2) + jc_x[k];
-        T* out = g + (int64_t)jc_val[k] * d;
-        for (int32_t pair = 0; pair < npairs; ++pair) {
-            const cpx<T> y = z[pair * P + at];
-            const int32_t c0 = 2 * pair;
-            out[c0] = y.x * scale;
-            if (c0 + 1 < d) out[c0 + 1] = y.y * scale;
+    const bool pairs = (d & 1) == 0 && ((uintptr_t)g & (2 * sizeof(T) - 1)) == 0;
+    const int t = threadIdx.x;
+    for (int32_t k0 = cb + blockIdx.x * kXCells; k0 < ce; k0 += gridDim.x * kXCells) {
+        int64_t at, vrow, at_r, vrow_r;
+        cell_point(k0 + (t & 63), ce, jc_r, jc_x, jc_val, 0, lg2, 0, at, vrow);
+        cell_point(k0 + (t >> 2), ce, jc_r, jc_x, jc_val, 0, lg2, 0, at_r, vrow_r);
+        for (int32_t p0 = 0; p0 < npairs; p0 += kXPairs) {
+            __syncthreads();
+            if (at >= 0) {
+                cpx<T> y[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t pl = (t >> 6) + 4 * q;
+                    if (p0 + pl < npairs) y[q] = z[(p0 + pl) * P + at];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t pl = (t >> 6) + 4 * q;
+                    if (p0 + pl < npairs) sc[(t & 63) * kXStride + pl] = y[q];
+                }
+            }
+            __syncthreads();
+            if (at_r >= 0) {
+                T* out = g + vrow_r * d;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t pl = 4 * (t & 3) + q, c0 = 2 * (p0 + pl);
+                    if (p0 + pl >= npairs) continue;
+                    const cpx<T> y = sc[(t >> 2) * kXStride + pl];
+                    if (pairs) {
+                        st_pair(out + c0, cpx<T>{y.x * scale, y.y * scale});
+                    } else {
+                        out[c0] = y.x * scale;
+                        if (c0 + 1 < d) out[c0 + 1] = y.y * scale;
+                    }
+                }
+            }
         }
     }
 }

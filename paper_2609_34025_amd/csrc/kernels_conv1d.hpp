@@ -97,27 +97,6 @@ __device__ __forceinline__ void reg_fft(cpx<T> (&x)[1 << kC1MaxR], int R,
     }
 }
 
-// One channel pair of a row as a single 8- or 16-byte access (the pair
-// starts at an even channel of a row of even length, in a buffer aligned to
-// two elements).
-template <typename T>
-__device__ __forceinline__ cpx<T> ld_pair(const T* p) {
-    if constexpr (sizeof(T) == 4) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
-        return {v.x, v.y};
-    } else {
-        const double2 v = *reinterpret_cast<const double2*>(p);
-        return {v.x, v.y};
-    }
-}
-template <typename T>
-__device__ __forceinline__ void st_pair(T* p, cpx<T> v) {
-    if constexpr (sizeof(T) == 4)
-        *reinterpret_cast<float2*>(p) = make_float2(v.x, v.y);
-    else
-        *reinterpret_cast<double2*>(p) = make_double2(v.x, v.y);
-}
-
 // LDS block layout: row a (2^RA rows) holds the 2^RB points b x TC pairs,
 // padded by kC1Pad complex values so that phase B's lanes (different a, same
 // b) spread over the banks.
