@@ -869,12 +869,18 @@ int conv1d_lds_optin_lg(int lds) {
 }
 
 // Block splits compiled with fixed sizes (straight-line register stages):
-// FP32 with full-line tiles, blocks of 2^5 .. 2^10 points. FP64 at these
-// sizes runs out of registers unrolled and keeps the runtime split.
+// FP32 with full-line tiles, blocks of 2^5 .. 2^10 points, and FP32 with
+// half-line tiles at the 2^10 x 2^10 split of 2^20-point tables (whose
+// full-line blocks would pass 64 KiB of LDS). FP64 at these sizes runs out
+// of registers unrolled and keeps the runtime split.
 constexpr int kC1FixedMin = 5, kC1FixedMax = 10;
 template <typename T, int TC>
 constexpr bool conv1d_fixed() {
     return std::is_same<T, float>::value && TC == 16;
+}
+template <typename T, int TC>
+constexpr bool conv1d_fixed_half() {
+    return std::is_same<T, float>::value && TC == 8;
 }
 
 template <typename T, int TC>
@@ -890,6 +896,9 @@ int conv1d_lds_optin_tc(int lds) {
         if (!rc)
             TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_conv1d_lo<T, TC, 10, TC / 2>,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    }
+    if constexpr (conv1d_fixed_half<T, TC>()) {
+        if (!rc) rc = conv1d_lds_optin_lg<T, TC, 10>(lds);
     }
     return rc;
 }
@@ -1559,6 +1568,13 @@ void launch_conv1d_tc(tfi_plan* h, const Bucket& b, const int32_t* bmap, int32_t
 #undef TFI_C1_FIXED
         if (lo_parts == 2) lo = tfi::k_conv1d_lo<T, TC, 10, TC / 2>;
         static_assert(kC1FixedMin == 5 && kC1FixedMax == 10, "fixed splits listed above");
+    }
+    if constexpr (conv1d_fixed_half<T, TC>()) {
+        if (lgH == 10) {
+            hi_fwd = tfi::k_conv1d_hi<T, TC, false, 10>;
+            hi_inv = tfi::k_conv1d_hi<T, TC, true, 10>;
+        }
+        if (lgL == 10) lo = tfi::k_conv1d_lo<T, TC, 10>;
     }
     for (int64_t j0 = 0; j0 < b.njobs(); j0 += jpc) {
         const int64_t nj = std::min(jpc, b.njobs() - j0);
