@@ -211,7 +211,11 @@ __device__ __forceinline__ void stage_cells(const int32_t* __restrict__ dl_r,
     }
 }
 
-template <typename T>
+// FL: the kernel table is staged in LDS (flds = its length > 0). Kept a
+// template argument so that every lookup is an LDS read: a pointer that may
+// be either LDS or global compiles to flat loads, which wait on both
+// counters and serialize the lookups.
+template <typename T, bool FL>
 __global__ void __launch_bounds__(kDirThreads)
 k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
          const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
@@ -224,11 +228,9 @@ k_direct(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__
     T* sf = reinterpret_cast<T*>(dyn_raw);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
     const int32_t ss = blk[4 * blockIdx.x + 2], se = blk[4 * blockIdx.x + 3];
-    const T* fp = f;
-    if (flds > 0) {
+    if (FL)
         for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) sf[k] = f[k];
-        fp = sf;
-    }
+    const T* fp = FL ? sf : f;
     // channel chunks: this workgroup takes every gridDim.y-th one
     for (int32_t c0 = blockIdx.y * kDirCh; c0 < d; c0 += gridDim.y * kDirCh) {
         const int32_t nch = min(kDirCh, d - c0);
@@ -307,7 +309,10 @@ struct MfTile {
     static constexpr int stride = NCH == 1 ? 16 : NCH <= 3 ? 48 : 80;
 };
 
-template <int NCH, int NK>
+// FL as in k_direct: the kernel tables in LDS; the four row tiles' entries
+// of a source step are then read (clamped into the table, zeroed outside
+// the lane's job) before any of the step's products.
+template <int NCH, int NK, bool FL>
 __global__ void __launch_bounds__(kDirThreads)
 k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restrict__ dl_r,
               const int32_t* __restrict__ dl_x, const int32_t* __restrict__ dl_row,
@@ -325,7 +330,7 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
     const float* fp[NK];
     fp[0] = f;
     if (NK > 1) fp[NK - 1] = f1;
-    if (flds > 0) {
+    if (FL) {
         for (int32_t k = threadIdx.x; k < flds; k += blockDim.x) {
             sf[k] = f[k];
             if (NK > 1) sf[flds + k] = f1[k];
@@ -423,6 +428,33 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
                 float b[NCH];
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) b[ch] = sv[kl * SV + 16 * ch + lr];
+                if (FL) {
+                    // every tile's entries first (LDS reads in flight
+                    // together), then the products
+                    float a[4][NK];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int32_t dx = xi[q] - xk;
+                        const int32_t e = min(max(ri[q] + rk + (dx < 0 ? -dx : dx), 0), flds - 1);
+                        const bool own = k >= jb[q] && k < je[q];  // the lane's own job only
+#pragma unroll
+                        for (int u = 0; u < NK; ++u) {
+                            const float v = fp[u][e];
+                            a[q][u] = own ? v : 0.f;
+                        }
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        if (k4 < kb[q] || k4 >= ke[q]) continue;  // uniform per wave
+#pragma unroll
+                        for (int u = 0; u < NK; ++u)
+#pragma unroll
+                            for (int ch = 0; ch < NCH; ++ch)
+                                acc[u][ch][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                    a[q][u], b[ch], acc[u][ch][q], 0, 0, 0);
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (k4 < kb[q] || k4 >= ke[q]) continue;  // uniform per wave

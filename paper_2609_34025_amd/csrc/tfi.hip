@@ -1961,24 +1961,30 @@ void enq_direct(tfi_plan* h, const DirectSet& ds, const T* f, int32_t d, const T
                                ds.d_qje, (const float*)f, (const float*)f1, flds,
                                (const float*)val, (float*)g, (float*)g1);
         };
-        if (nk == 2) {
-            switch (nch) {
-                case 4: launch(tfi::k_direct_mfma<4, 2>); break;
-                case 3: launch(tfi::k_direct_mfma<3, 2>); break;
-                case 2: launch(tfi::k_direct_mfma<2, 2>); break;
-                default: launch(tfi::k_direct_mfma<1, 2>); break;
+        // instances: kernel tables staged in LDS (flds > 0) or read from HBM
+        auto launch_nk = [&](auto fl) {
+            constexpr bool FL = decltype(fl)::value;
+            if (nk == 2) {
+                switch (nch) {
+                    case 4: launch(tfi::k_direct_mfma<4, 2, FL>); break;
+                    case 3: launch(tfi::k_direct_mfma<3, 2, FL>); break;
+                    case 2: launch(tfi::k_direct_mfma<2, 2, FL>); break;
+                    default: launch(tfi::k_direct_mfma<1, 2, FL>); break;
+                }
+            } else {
+                switch (nch) {
+                    case 4: launch(tfi::k_direct_mfma<4, 1, FL>); break;
+                    case 3: launch(tfi::k_direct_mfma<3, 1, FL>); break;
+                    case 2: launch(tfi::k_direct_mfma<2, 1, FL>); break;
+                    default: launch(tfi::k_direct_mfma<1, 1, FL>); break;
+                }
             }
-        } else {
-            switch (nch) {
-                case 4: launch(tfi::k_direct_mfma<4, 1>); break;
-                case 3: launch(tfi::k_direct_mfma<3, 1>); break;
-                case 2: launch(tfi::k_direct_mfma<2, 1>); break;
-                default: launch(tfi::k_direct_mfma<1, 1>); break;
-            }
-        }
+        };
+        if (flds > 0) launch_nk(std::true_type{});
+        else launch_nk(std::false_type{});
     } else {
-        hipLaunchKernelGGL(tfi::k_direct<T>,
-                           dim3((unsigned)ds.ndblk, chan_split(ds.ndblk, d, tfi::kDirCh)),
+        auto kern = flds > 0 ? tfi::k_direct<T, true> : tfi::k_direct<T, false>;
+        hipLaunchKernelGGL(kern, dim3((unsigned)ds.ndblk, chan_split(ds.ndblk, d, tfi::kDirCh)),
                            dim3(tfi::kDirThreads), (unsigned)(flds * sizeof(T)), st, d, ds.d_dblk,
                            ds.d_dl_r, ds.d_dl_x, ds.d_dl_row, ds.d_qjb, ds.d_qje, f, flds, val,
                            g);
