@@ -323,6 +323,10 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
     constexpr int PER = ROWS / 16;  // staged rows per thread
     __shared__ __attribute__((aligned(16))) float sv[ROWS * SV];
     __shared__ int32_t sr[ROWS], sx[ROWS];
+    // output rows of the block's cells, kept while their source tiles are
+    // staged (every output cell is also a source cell of its block), so the
+    // results need no further round trip for them
+    __shared__ int32_t so[kDirOut];
     extern __shared__ unsigned char dyn_raw[];
     float* sf = reinterpret_cast<float*>(dyn_raw);
     const int32_t os = blk[4 * blockIdx.x], oe = blk[4 * blockIdx.x + 1];
@@ -407,6 +411,13 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
                     sr[threadIdx.x] = dl_r[ts + threadIdx.x];
                     sx[threadIdx.x] = dl_x[ts + threadIdx.x];
                 }
+                if (cc == 0) {
+#pragma unroll
+                    for (int i = 0; i < PER; ++i) {
+                        const int32_t src = ts + k0 + 16 * i;
+                        if (k0 + 16 * i < tn && src >= os && src < oe) so[src - os] = rows[i];
+                    }
+                }
             }
             __syncthreads();
             int32_t kb[4], ke[4];
@@ -485,7 +496,7 @@ k_direct_mfma(int32_t d, const int32_t* __restrict__ blk, const int32_t* __restr
             for (int r = 0; r < 4; ++r) {
                 const int32_t i = os + 16 * t + 4 * lk + r;
                 if (i >= oe) continue;
-                const int32_t row = dl_row[i];
+                const int32_t row = so[i - os];
                 if (row < 0) continue;
 #pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
