@@ -480,13 +480,16 @@ def batched_fwd_bwd(args, plain_value):
                 "db": rel(b.grad.double().cpu().numpy(), db_ref)}
         ok = all(e <= 1e-4 for e in errs.values())
         log(f"batched[{name}]: parity {errs} ok={ok}")
+        plan = "-" if name == "sweep" else f"fft{tfi.stats()['fft_jobs']}"
+        wl = "grid512_sweep" if name == "sweep" else "grid512"
         results[name] = {"value": value, "steps": steps, "ms_per_step": 1e3 * el / steps,
                          "parity": {"rows": 512, "rel_err": errs, "ok": ok},
-                         "roofline": stage_roofline(dom, stages[dom], "f32",
-                                                    "grid512_sweep" if name == "sweep"
-                                                    else "grid512",
-                                                    plan="-" if name == "sweep"
-                                                    else f"fft{tfi.stats()['fft_jobs']}"),
+                         "roofline": stage_roofline(dom, stages[dom], "f32", wl, plan=plan),
+                         # the FFT cross-interaction stages of the step
+                         "k3_roofline": {k: stage_roofline(k, sd, "f32", wl, plan=plan)
+                                         for k, sd in stages.items()
+                                         if (k.startswith("fft") or k.startswith("df_fft"))
+                                         and sd["ms"] > 0},
                          "stages": stages}
     best = results["sweep"]
     return {"value": best["value"], "unit": "vertex*channels/s", "steps": best["steps"],
@@ -506,6 +509,7 @@ def batched_fwd_bwd(args, plain_value):
                            "fft_cost": cost, "plan_key": f"fft{tfi.stats()['fft_jobs']}",
                            "parity": results["table"]["parity"],
                            "roofline": results["table"]["roofline"],
+                           "k3_roofline": results["table"]["k3_roofline"],
                            "stages": results["table"]["stages"]}}
 
 
