@@ -1783,11 +1783,13 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
     if (use_lds) hist_flush(lh, df, K);
 }
 
-// FFT jobs, pass 1: one workgroup per (job, group of kDfPairs channel
-// pairs) forms, per pair, the forward transforms of the gout table (at
-// output positions) and of the field table (at source positions), and
-// sums Zg * conj(Zv) over the group's pairs into a partial spectrum
-// written to global memory (slot = job * groups + group).
+// FFT jobs, pass 1: one workgroup per (job, group of ppg channel pairs)
+// forms, per pair, the forward transforms of the gout table (at output
+// positions) and of the field table (at source positions), and sums
+// Zg * conj(Zv) over the group's pairs into a partial spectrum written to
+// global memory (slot = job * groups + group). ppg is kDfPairs, or more
+// when the bucket has jobs enough to fill the device with fewer groups
+// (fewer partial spectra to write and sum).
 constexpr int kDfPairs = 4;
 
 // PAD: the two transformed tables are one block stored with lds_at<PAD>
@@ -1803,7 +1805,7 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, const T* __restrict__ valg,
                                  const cpx<T>* __restrict__ tw, int lgtw,
-                                 cpx<T>* __restrict__ part) {
+                                 cpx<T>* __restrict__ part, int32_t ppg) {
     extern __shared__ unsigned char smem_raw[];
     const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
@@ -1812,8 +1814,8 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
     cpx<T>* acc = zv + 2 * P + (PAD ? (2 * P) >> PAD : 0);
     const int32_t npairs = (d + 1) / 2;
     for (int p = threadIdx.x; p < P; p += nb) acc[p] = {(T)0, (T)0};
-    const int32_t pe = min(npairs, (int32_t)(blockIdx.y + 1) * kDfPairs);
-    for (int32_t pr = blockIdx.y * kDfPairs; pr < pe; ++pr) {
+    const int32_t pe = min(npairs, (int32_t)(blockIdx.y + 1) * ppg);
+    for (int32_t pr = (int32_t)blockIdx.y * ppg; pr < pe; ++pr) {
         const int32_t c0 = 2 * pr, c1 = c0 + 1;
         const bool has1 = c1 < d;
         for (int p = threadIdx.x; p < 2 * P; p += nb) zv[lds_at<PAD>(p)] = {(T)0, (T)0};

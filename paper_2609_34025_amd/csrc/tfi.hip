@@ -2037,6 +2037,14 @@ int64_t df_lds_bytes(const tfi_plan* h, const Bucket& b) {
     return need <= h->lds_max ? need : 0;
 }
 
+// Channel pairs per workgroup of the LDS df pass for a bucket: kDfPairs,
+// doubled while the bucket still has at least 4096 (job, group) workgroups.
+inline int32_t df_pairs_per_group(int64_t njobs, int32_t npairs) {
+    int32_t ppg = tfi::kDfPairs;
+    while (ppg < npairs && njobs * ((npairs + 2 * ppg - 1) / (2 * ppg)) >= 4096) ppg *= 2;
+    return ppg;
+}
+
 template <typename T>
 void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64* df,
                    hipStream_t st) {
@@ -2044,10 +2052,11 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
     const int ti = sizeof(T) == 8 ? 1 : 0;
     const tfi::cpx<T>* tw = (const tfi::cpx<T>*)h->d_tw[ti];
     const int32_t npairs = (d + 1) / 2;
-    const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
     const double sz = (double)sizeof(T);
     for (const Bucket& b : h->buckets) {
         const int64_t P = b.P();
+        const int32_t ppg = df_pairs_per_group(b.njobs(), npairs);
+        const int32_t groups = (npairs + ppg - 1) / ppg;
         const double bytes = 2.0 * sz * d * (double)b.cells + 12.0 * b.cells;
         const int64_t lds = df_lds_bytes<T>(h, b);
         if (lds) {
@@ -2060,12 +2069,12 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
                 hipLaunchKernelGGL((tfi::k_df_fft_partial<T, tfi::kPassPad>),
                                    dim3((unsigned)b.njobs(), groups), dim3(kThreads),
                                    (unsigned)lds_pad, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
-                                   h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part);
+                                   h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part, ppg);
             else
                 hipLaunchKernelGGL(tfi::k_df_fft_partial<T>, dim3((unsigned)b.njobs(), groups),
                                    dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
                                    h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
-                                   part);
+                                   part, ppg);
             const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
             const int64_t fold_lds = P * cs + hist, fold_pad = tfi::pass_lds_elems(P) * cs + hist;
             if (fold_pad <= h->lds_max)
@@ -2365,10 +2374,11 @@ DfSizes df_sizes(const tfi_plan* h, int32_t d) {
     if (scatter_pieces(h, d))
         z.partg = (size_t)std::max<int64_t>(h->cells.part_rows, 1) * d * sizeof(T);
     const int32_t npairs = (d + 1) / 2;
-    const int32_t groups = (npairs + tfi::kDfPairs - 1) / tfi::kDfPairs;
     for (const Bucket& b : h->buckets) {
         const int64_t P = b.P();
         if (df_lds_bytes<T>(h, b)) {
+            const int32_t ppg = df_pairs_per_group(b.njobs(), npairs);
+            const int32_t groups = (npairs + ppg - 1) / ppg;
             z.dfbuf = std::max(z.dfbuf, (size_t)(b.njobs() * groups * P * sizeof(tfi::cpx<T>)));
             continue;
         }
