@@ -254,3 +254,26 @@ def test_df_bitwise_reproducible_every_path(dtype):
         e = float(np.linalg.norm(outs[0].cpu().numpy() - ref) / np.linalg.norm(ref))
         print(f"{opts} {dtype}: df vs oracle {e:.2e}", flush=True)
         assert e <= (1e-10 if dtype == torch.float64 else 1e-4), opts
+
+
+def test_df_fft_tables_in_wide_pair_groups():
+    """Buckets of more than a thousand FFT tables at 64 channels take 8
+    channel pairs per df workgroup instead of 4 (fewer partial spectra).
+    FP64: the forced-FFT df must match the direct tables' df, computed by
+    independent kernels, and dF the oracle's rows."""
+    rng = np.random.default_rng(31)
+    trees_ = [S.grid_mst(int(s), 16, rng) for s in rng.integers(10, 15, size=160)]
+    p, w, _ = S.forest(trees_)
+    host = TreeIntegrator(p, w, device=None, table_method="fft")
+    assert max(b[2] for b in host.stats()["fft_buckets"]) >= 1024
+    F = rng.standard_normal((len(p), 64))
+    G = rng.standard_normal((len(p), 64))
+    ftab = lambda K: np.exp(-0.02 * np.arange(K)) + 0.5 / (1.0 + np.arange(K))
+    t1, tab, dF1, df1 = run_backward(p, w, ftab, F, G, torch.float64, table_method="fft")
+    t2, _, dF2, df2 = run_backward(p, w, ftab, F, G, torch.float64, table_method="direct")
+    rows = np.sort(rng.choice(len(p), 24, replace=False))
+    ref = oracle.integrate(p, w, tab, G, rows=rows)
+    e = [relerr(df1, df2), relerr(dF1, dF2), relerr(dF1[rows], ref)]
+    print(f"forest N={len(p)} d=64 fp64: df fft vs direct {e[0]:.2e}, dF {e[1]:.2e}, "
+          f"dF rows vs oracle {e[2]:.2e}", flush=True)
+    assert max(e) <= 1e-10, e
