@@ -746,7 +746,9 @@ k_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict__ g
 // pairs points e and e + 2^s with twiddle W_{2^(s+1)}^(e mod 2^s),
 // W_n = exp(-2 pi i / n) (conjugated for the inverse). Within a pass over
 // index bits [s0, s0 + R) that twiddle factors as a compile-time 8th root of
-// unity times one table factor per stage, W_{2^(s+1)}^(e mod 2^s0).
+// unity times one table factor per stage, W_{2^(s+1)}^(e mod 2^s0). The
+// stage factors of a pass are successive squares of the last one, so a
+// group reads one table entry: f = W_{2^(s0+R)}^(e mod 2^s0), f^2, f^4.
 //
 // Twiddle table tw[k] = exp(-2 pi i k / 2^lgtw), k < 2^(lgtw-1), lgtw >= lgL.
 
@@ -761,6 +763,38 @@ constexpr double kW32im[16] = {
     -0.70710678118654746, -0.83146961230254524, -0.92387953251128674, -0.98078528040323043,
     -1.0, -0.98078528040323043, -0.92387953251128674, -0.83146961230254546,
     -0.70710678118654757, -0.55557023301960218, -0.38268343236508989, -0.19509032201612861};
+
+// z W_32^m and z conj(W_32^m) for m < 16 known at compile time once the
+// butterfly loops are unrolled. The powers 1, W_8, -i and W_8^3 (m = 0, 4,
+// 8, 12) take sign flips, adds and one scale by sqrt(1/2) rather than a
+// full complex product with rounded constants.
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_w32(cpx<T> z, int m) {
+    const T h = (T)0.70710678118654752440;
+    switch (m) {
+        case 0: return z;
+        case 4: return {(z.x + z.y) * h, (z.y - z.x) * h};
+        case 8: return {z.y, -z.x};
+        case 12: return {(z.y - z.x) * h, -(z.x + z.y) * h};
+        default: return cmul(z, cpx<T>{(T)kW32re[m], (T)kW32im[m]});
+    }
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> mul_w32c(cpx<T> z, int m) {
+    const T h = (T)0.70710678118654752440;
+    switch (m) {
+        case 0: return z;
+        case 4: return {(z.x - z.y) * h, (z.x + z.y) * h};
+        case 8: return {-z.y, z.x};
+        case 12: return {-(z.x + z.y) * h, (z.x - z.y) * h};
+        default: return cmulc(z, cpx<T>{(T)kW32re[m], (T)kW32im[m]});
+    }
+}
+// z^2, with the real part as (x - y)(x + y)
+template <typename T>
+__device__ __forceinline__ cpx<T> csq(cpx<T> z) {
+    return {(z.x - z.y) * (z.x + z.y), (T)2 * z.x * z.y};
+}
 
 // A batch of lines in LDS: line l0 + 2^lgc0 l1 (l0 < 2^lgc0, l1 < c1)
 // starts at l0 ls0 + l1 ls1; its points are es apart. lgtn: low bits of l0
@@ -806,40 +840,40 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
         lo = rest & ((1 << s0) - 1);
         hi = rest >> s0;
     };
-    // table factors of an item's R stages (see the twiddle note above)
-    auto factors = [&](int l0, int lo, cpx<T> (&fs)[R]) {
+    // table factor of an item's last stage (see the twiddle note above)
+    auto factor = [&](int l0, int lo) -> cpx<T> {
         const int J = (lo << tsh) + (tsh ? tbase + (l0 >> L.lgtn) : 0);
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const int t = J << (lgtw - tsh - s0 - u - 1);
-            if (tsh) {
-                // A pass over the high bits of a long axis would touch the
-                // whole table (megabytes, missing in L2 on every slot): split
-                // t = th 2^lgb + tl, W^t = W^(th 2^lgb) W^tl, two factors
-                // from 2^(lgtw-1-lgb) strided and 2^lgb leading entries.
-                const int lgb = (lgtw + 1) >> 1;
-                fs[u] = cmul(tw[(t >> lgb) << lgb], tw[t & ((1 << lgb) - 1)]);
-            } else {
-                fs[u] = tw[t];
-            }
+        const int t = J << (lgtw - tsh - s0 - R);
+        if (tsh) {
+            // A pass over the high bits of a long axis would touch the
+            // whole table (megabytes, missing in L2 on every slot): split
+            // t = th 2^lgb + tl, W^t = W^(th 2^lgb) W^tl, two factors
+            // from 2^(lgtw-1-lgb) strided and 2^lgb leading entries.
+            const int lgb = (lgtw + 1) >> 1;
+            return cmul(tw[(t >> lgb) << lgb], tw[t & ((1 << lgb) - 1)]);
         }
+        return tw[t];
     };
     const int nb = blockDim.x;
-    cpx<T> fs[R];
+    cpx<T> f;
     int l0, l1, lo, hi;
     if ((int)threadIdx.x < nitems) {
         split(threadIdx.x, l0, l1, lo, hi);
-        factors(l0, lo, fs);
+        f = factor(l0, lo);
     }
     for (int it = threadIdx.x; it < nitems; it += nb) {
         split(it, l0, l1, lo, hi);
-        // the next item's factors are requested before this item's work
-        cpx<T> fn[R];
+        // the next item's factor is requested before this item's work
+        cpx<T> fn;
         if (it + nb < nitems) {
             int m0, m1, mlo, mhi;
             split(it + nb, m0, m1, mlo, mhi);
-            factors(m0, mlo, fn);
+            fn = factor(m0, mlo);
         }
+        cpx<T> fs[R];
+        fs[R - 1] = f;
+#pragma unroll
+        for (int u = R - 2; u >= 0; --u) fs[u] = csq(fs[u + 1]);
         const int base = l0 * L.ls0 + l1 * L.ls1 + ((hi << (s0 + R)) | lo) * L.es;
         cpx<T> x[1 << R];
 #pragma unroll
@@ -852,13 +886,12 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
             for (int k = 0; k < (1 << R); ++k) {
                 if (k & h) continue;
                 const int m = (k & (h - 1)) << (4 - u);  // W_{2^(u+1)}^(k mod 2^u) = W_32^m
-                const cpx<T> w = cmul(cpx<T>{(T)kW32re[m], (T)kW32im[m]}, fs[u]);
                 const cpx<T> p = x[k], q = x[k + h];
                 if (!INV) {
                     x[k] = cadd(p, q);
-                    x[k + h] = cmul(csub(p, q), w);
+                    x[k + h] = cmul(csub(p, q), mul_w32(fs[u], m));
                 } else {
-                    const cpx<T> qw = cmulc(q, w);
+                    const cpx<T> qw = cmulc(q, mul_w32(fs[u], m));
                     x[k] = cadd(p, qw);
                     x[k + h] = csub(p, qw);
                 }
@@ -866,8 +899,7 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
         }
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) z[lds_at<PAD>(base + k * step)] = x[k];
-#pragma unroll
-        for (int u = 0; u < R; ++u) fs[u] = fn[u];
+        f = fn;
     }
     __syncthreads();
 }
@@ -877,20 +909,21 @@ __device__ __forceinline__ void lds_pass(cpx<T>* z, int lgL, int s0, const LdsLi
 template <typename T, bool INV, int PAD = 0>
 __device__ void fft_lines(cpx<T>* z, int lgL, const LdsLines& L, int tsh, int tbase,
                           const cpx<T>* __restrict__ tw, int lgtw) {
+    auto pass = [&](int s0, int R) {
+        if (R == 3) lds_pass<T, INV, 3, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+        else if (R == 2) lds_pass<T, INV, 2, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+        else lds_pass<T, INV, 1, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+    };
     if (INV) {
         for (int s0 = 0; s0 < lgL;) {
             const int R = min(3, lgL - s0);
-            if (R == 3) lds_pass<T, INV, 3, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
-            else if (R == 2) lds_pass<T, INV, 2, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
-            else lds_pass<T, INV, 1, PAD>(z, lgL, s0, L, tsh, tbase, tw, lgtw);
+            pass(s0, R);
             s0 += R;
         }
     } else {
         for (int s1 = lgL; s1 > 0;) {
             const int R = min(3, s1);
-            if (R == 3) lds_pass<T, INV, 3, PAD>(z, lgL, s1 - 3, L, tsh, tbase, tw, lgtw);
-            else if (R == 2) lds_pass<T, INV, 2, PAD>(z, lgL, s1 - 2, L, tsh, tbase, tw, lgtw);
-            else lds_pass<T, INV, 1, PAD>(z, lgL, s1 - 1, L, tsh, tbase, tw, lgtw);
+            pass(s1 - R, R);
             s1 -= R;
         }
     }

@@ -82,14 +82,12 @@ __device__ __forceinline__ void reg_fft(cpx<T> (&x)[1 << kC1MaxR], int R,
         for (int k = 0; k < (1 << kC1MaxR); ++k) {
             if ((k & h) || k >= (1 << R)) continue;
             const int m = (k & (h - 1)) << (4 - u);  // W_{2^(u+1)}^{k mod 2^u} = W_32^m
-            cpx<T> w = {(T)kW32re[m], (T)kW32im[m]};
-            if (FS) w = cmul(w, fs[u]);
             const cpx<T> p = x[k], q = x[k + h];
             if (!INV) {
                 x[k] = cadd(p, q);
-                x[k + h] = cmul(csub(p, q), w);
+                x[k + h] = FS ? cmul(csub(p, q), mul_w32(fs[u], m)) : mul_w32(csub(p, q), m);
             } else {
-                const cpx<T> qw = cmulc(q, w);
+                const cpx<T> qw = FS ? cmulc(q, mul_w32(fs[u], m)) : mul_w32c(q, m);
                 x[k] = cadd(p, qw);
                 x[k + h] = csub(p, qw);
             }
