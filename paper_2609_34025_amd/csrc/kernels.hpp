@@ -1832,23 +1832,47 @@ constexpr int kDfPairs = 4;
 // workgroups within occupancy).
 constexpr int kDfBatch = 4;
 
-template <typename T, int PAD = 0>
+//
+// FOLD: the workgroup also applies the inverse transform to its own group
+// sum and folds it into df as k_df_fft_fold does (the transform is linear
+// and the fixed-point bins add in any order, so the per-group folds sum to
+// the same df up to the rounding of each group's transform), with no
+// partial spectrum in global memory. The bins (2 H + X + 1 of 16 bytes)
+// reuse the LDS from the second table on, which holds at least 2 P complex
+// values; the host checks that they fit.
+template <typename T, int PAD = 0, bool FOLD = false>
 __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ jobs,
                                  const int32_t* __restrict__ jc_r, const int32_t* __restrict__ jc_x,
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, const T* __restrict__ valg,
                                  const cpx<T>* __restrict__ tw, int lgtw,
-                                 cpx<T>* __restrict__ part, int32_t ppg) {
+                                 cpx<T>* __restrict__ part, int32_t ppg,
+                                 const int32_t* __restrict__ job_hx = nullptr, int64_t NA = 0,
+                                 u64* __restrict__ df = nullptr) {
     extern __shared__ unsigned char smem_raw[];
-    const int32_t cb = jobs[2 * blockIdx.x], ce = jobs[2 * blockIdx.x + 1];
+    // (job, group) of this workgroup. Workgroups are dealt to the 8 XCDs in
+    // turn; when their count allows, the groups of one job, which read the
+    // same cell rows (2 ppg channels of each), take consecutive slots of one
+    // XCD, so they run together and the rows come from that XCD's L2.
+    int32_t job = blockIdx.x, grp = blockIdx.y;
+    {
+        const int64_t W = (int64_t)gridDim.x * gridDim.y;
+        if (gridDim.y > 1 && (W & 7) == 0) {
+            const int64_t w = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+            const int64_t lw = (w & 7) * (W >> 3) + (w >> 3);
+            job = (int32_t)(lw / gridDim.y);
+            grp = (int32_t)(lw % gridDim.y);
+        }
+    }
+    const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
     const int nb = blockDim.x;
     cpx<T>* zv = reinterpret_cast<cpx<T>*>(smem_raw);
     cpx<T>* acc = zv + 2 * P + (PAD ? (2 * P) >> PAD : 0);
     const int32_t npairs = (d + 1) / 2;
     for (int p = threadIdx.x; p < P; p += nb) acc[p] = {(T)0, (T)0};
-    const int32_t pe = min(npairs, (int32_t)(blockIdx.y + 1) * ppg);
-    for (int32_t pr = (int32_t)blockIdx.y * ppg; pr < pe; ++pr) {
+    const int32_t pe = min(npairs, (grp + 1) * ppg);
+    for (int32_t pr = grp * ppg; pr < pe; ++pr) {
         const int32_t c0 = 2 * pr, c1 = c0 + 1;
         const bool has1 = c1 < d;
         for (int p = threadIdx.x; p < 2 * P; p += nb) zv[lds_at<PAD>(p)] = {(T)0, (T)0};
@@ -1889,8 +1913,27 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
             acc[p] = cadd(acc[p], cmulc(zv[lds_at<PAD>(P + p)], zv[lds_at<PAD>(p)]));
         __syncthreads();
     }
-    cpx<T>* out = part + ((int64_t)blockIdx.x * gridDim.y + blockIdx.y) * P;
-    for (int p = threadIdx.x; p < P; p += nb) out[p] = acc[p];
+    if (!FOLD) {
+        cpx<T>* out = part + ((int64_t)job * gridDim.y + grp) * P;
+        for (int p = threadIdx.x; p < P; p += nb) out[p] = acc[p];
+        return;
+    }
+    for (int p = threadIdx.x; p < P; p += nb) zv[lds_at<PAD>(p)] = acc[p];
+    __syncthreads();
+    fft_axis_lds<T, true, PAD>(zv, lg1, L2, L2, 1, tw, lgtw);
+    fft_axis_lds<T, true, PAD>(zv, lg2, L1, 1, L2, tw, lgtw);
+    const int32_t H = job_hx[2 * job], X = job_hx[2 * job + 1];
+    const int32_t nk = 2 * H + X + 1;
+    u64* lh = reinterpret_cast<u64*>(zv + lds_at<PAD>(P));
+    hist_clear(lh, nk);
+    __syncthreads();
+    const T scale = (jc_val[cb] < NA ? (T)1 : (T)-1) / (T)P;
+    for (int p = threadIdx.x; p < P; p += nb) {
+        const int a = p >> lg2, b = p & (L2 - 1);
+        const int bs = (b <= (L2 >> 1)) ? b : L2 - b;
+        if (a <= 2 * H && bs <= X) df_atomic(lh, a + bs, (double)(zv[lds_at<PAD>(p)].x * scale));
+    }
+    hist_flush(lh, df, nk);
 }
 
 // FFT jobs, pass 2: one workgroup per job sums the group spectra (fixed

@@ -501,6 +501,14 @@ int lds_optin_once(int device, int lds) {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_fold<double, tfi::kPassPad>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float, 0, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double, 0, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<float, tfi::kPassPad, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    TFI_HIP(hipFuncSetAttribute((const void*)tfi::k_df_fft_partial<double, tfi::kPassPad, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int rc1 = conv1d_lds_optin<float>(lds);
     if (!rc1) rc1 = conv1d_lds_optin<double>(lds);
     if (rc1) return rc1;
@@ -2037,6 +2045,18 @@ int64_t df_lds_bytes(const tfi_plan* h, const Bucket& b) {
     return need <= h->lds_max ? need : 0;
 }
 
+// Whether the LDS df pass of a bucket folds each group's spectrum in the
+// same workgroup (no partial spectra in global memory): when a job has at
+// most two groups (beyond that, the extra inverse transforms and bin
+// flushes per group cost more than the partial spectra's round trip) and
+// the bins of its largest job fit the LDS from the second table on (2 P
+// complex values).
+template <typename T>
+bool df_group_folds(const Bucket& b, int32_t groups) {
+    const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
+    return groups <= 2 && hist <= 2 * b.P() * (int64_t)sizeof(tfi::cpx<T>);
+}
+
 // Channel pairs per workgroup of the LDS df pass for a bucket: kDfPairs,
 // doubled while the bucket still has at least 4096 (job, group) workgroups.
 inline int32_t df_pairs_per_group(int64_t njobs, int32_t npairs) {
@@ -2065,6 +2085,23 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
             // padded LDS blocks (lds_at) where they fit the limit
             const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
             const int64_t lds_pad = (tfi::pass_lds_elems(2 * P) + P) * cs;
+            const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
+            if (df_group_folds<T>(b, groups)) {
+                if (lds_pad <= h->lds_max)
+                    hipLaunchKernelGGL((tfi::k_df_fft_partial<T, tfi::kPassPad, true>),
+                                       dim3((unsigned)b.njobs(), groups), dim3(kThreads),
+                                       (unsigned)lds_pad, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
+                                       h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
+                                       (tfi::cpx<T>*)nullptr, ppg, b.d_hx, p.NA, df);
+                else
+                    hipLaunchKernelGGL((tfi::k_df_fft_partial<T, 0, true>),
+                                       dim3((unsigned)b.njobs(), groups), dim3(kThreads),
+                                       (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
+                                       h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
+                                       (tfi::cpx<T>*)nullptr, ppg, b.d_hx, p.NA, df);
+                h->end(st, ev, "df_fft_lds", bytes);
+                continue;
+            }
             if (lds_pad <= h->lds_max)
                 hipLaunchKernelGGL((tfi::k_df_fft_partial<T, tfi::kPassPad>),
                                    dim3((unsigned)b.njobs(), groups), dim3(kThreads),
@@ -2075,7 +2112,6 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
                                    dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
                                    h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
                                    part, ppg);
-            const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
             const int64_t fold_lds = P * cs + hist, fold_pad = tfi::pass_lds_elems(P) * cs + hist;
             if (fold_pad <= h->lds_max)
                 hipLaunchKernelGGL((tfi::k_df_fft_fold<T, tfi::kPassPad>),
@@ -2379,6 +2415,7 @@ DfSizes df_sizes(const tfi_plan* h, int32_t d) {
         if (df_lds_bytes<T>(h, b)) {
             const int32_t ppg = df_pairs_per_group(b.njobs(), npairs);
             const int32_t groups = (npairs + ppg - 1) / ppg;
+            if (df_group_folds<T>(b, groups)) continue;
             z.dfbuf = std::max(z.dfbuf, (size_t)(b.njobs() * groups * P * sizeof(tfi::cpx<T>)));
             continue;
         }
