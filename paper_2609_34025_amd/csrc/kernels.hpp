@@ -989,16 +989,22 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, T* __restrict__ g,
                                  const cpx<T>* __restrict__ spec_all,
-                                 const cpx<T>* __restrict__ tw, int lgtw, int lgnp) {
+                                 const cpx<T>* __restrict__ tw, int lgtw, int lgw, int lgcap) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
     const int32_t cb = fj[3 * blockIdx.x], ce = fj[3 * blockIdx.x + 1], bk = fj[3 * blockIdx.x + 2];
     const int lg1 = bp[4 * bk], lg2 = bp[4 * bk + 1];
     const cpx<T>* spec = spec_all + bo[bk];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2, lgP = lg1 + lg2;
+    // channel pairs of this table's workgroups: as many as fill the block
+    // of 2^lgw points (the launch's pairs for its largest table, more for
+    // smaller ones), at most 2^lgcap; a job then needs fewer of the
+    // launch's groups, and the others leave at once
+    const int lgnp = max(0, min(lgw - lgP, lgcap));
     const int NP = 1 << lgnp;
     const int nb = blockDim.x;
     const int32_t ch0 = 2 * (int32_t)blockIdx.y * NP;  // first channel of the group
+    if (ch0 >= d) return;
     for (int p = threadIdx.x; p < NP * P; p += nb) z[lds_at<PAD>(p)] = {(T)0, (T)0};
     __syncthreads();
     // item it: cell cb + (it >> lgnp), pair it mod NP of the group

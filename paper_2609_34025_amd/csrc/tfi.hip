@@ -1890,17 +1890,22 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
         const int64_t lds_pad = tfi::pass_lds_elems(lds / (int64_t)sizeof(tfi::cpx<T>)) *
                                 (int64_t)sizeof(tfi::cpx<T>);
         const bool pad = lds_pad <= h->lds_max;
+        // points per workgroup (lgnp pairs of the tier's largest table),
+        // which smaller tables fill with more pairs, up to npairs
+        int lgw = lgnp, lgcap = 0;
+        while (((int64_t)sizeof(tfi::cpx<T>) << lgw) < lds) ++lgw;
+        while ((2 << lgcap) <= npairs) ++lgcap;
         hipEvent_t ev = h->begin(st);
         if (pad)
             hipLaunchKernelGGL((tfi::k_fft_conv_multi<T, tfi::kPassPad>),
                                dim3((unsigned)T_.njobs, groups), dim3(kThreads), (unsigned)lds_pad,
                                st, T_.d_fj, T_.d_bp, T_.d_bo, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
-                               val, g, spec, tw, h->lgtw, lgnp);
+                               val, g, spec, tw, h->lgtw, lgw, lgcap);
         else
             hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, groups),
                                dim3(kThreads), (unsigned)lds, st, T_.d_fj, T_.d_bp, T_.d_bo,
                                h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw, h->lgtw,
-                               lgnp);
+                               lgw, lgcap);
         h->end(st, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
