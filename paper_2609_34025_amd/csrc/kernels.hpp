@@ -1831,8 +1831,9 @@ k_df_leaf(int32_t d, const int32_t* __restrict__ grp, const int64_t* __restrict_
 // (fewer partial spectra to write and sum).
 constexpr int kDfPairs = 4;
 
-// PAD: the two transformed tables are one block stored with lds_at<PAD>
-// (zv point p at p, zg point p at P + p); the accumulator follows it. The
+// PAD: the transformed tables are one block stored with lds_at<PAD> (for
+// pair b of a batch of 2^lgnb, zv point p at 2 b P + p, zg point p at
+// (2 b + 1) P + p); the accumulator follows it. The
 // cells' loads go out kDfBatch at a time (two tables per cell: a smaller
 // batch than the forward kernel's keeps the registers of small tables'
 // workgroups within occupancy).
@@ -1852,7 +1853,7 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, const T* __restrict__ valg,
                                  const cpx<T>* __restrict__ tw, int lgtw,
-                                 cpx<T>* __restrict__ part, int32_t ppg,
+                                 cpx<T>* __restrict__ part, int32_t ppg, int lgnb,
                                  const int32_t* __restrict__ job_hx = nullptr, int64_t NA = 0,
                                  u64* __restrict__ df = nullptr) {
     extern __shared__ unsigned char smem_raw[];
@@ -1871,38 +1872,49 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
         }
     }
     const int32_t cb = jobs[2 * job], ce = jobs[2 * job + 1];
-    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2;
+    const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2, lgP = lg1 + lg2;
     const int nb = blockDim.x;
+    // the tables of NB = 2^lgnb pairs at a time: pair b's field table at
+    // 2 b P, its gout table at (2 b + 1) P
+    const int NB = 1 << lgnb;
     cpx<T>* zv = reinterpret_cast<cpx<T>*>(smem_raw);
-    cpx<T>* acc = zv + 2 * P + (PAD ? (2 * P) >> PAD : 0);
+    cpx<T>* acc = zv + (2 * P << lgnb) + (PAD ? (2 * P << lgnb) >> PAD : 0);
     const int32_t npairs = (d + 1) / 2;
     for (int p = threadIdx.x; p < P; p += nb) acc[p] = {(T)0, (T)0};
     const int32_t pe = min(npairs, (grp + 1) * ppg);
-    for (int32_t pr = grp * ppg; pr < pe; ++pr) {
-        const int32_t c0 = 2 * pr, c1 = c0 + 1;
-        const bool has1 = c1 < d;
-        for (int p = threadIdx.x; p < 2 * P; p += nb) zv[lds_at<PAD>(p)] = {(T)0, (T)0};
+    const int32_t ncell = ce - cb;
+    for (int32_t pb = grp * ppg; pb < pe; pb += NB) {
+        const int32_t nbp = min(NB, pe - pb);
+        for (int p = threadIdx.x; p < (2 * P << lgnb); p += nb) zv[lds_at<PAD>(p)] = {(T)0, (T)0};
         __syncthreads();
-        for (int32_t k0 = cb + threadIdx.x; k0 < ce; k0 += kDfBatch * nb) {
+        // item it: cell cb + (it >> lgnb), pair pb + (it mod NB) (the pairs
+        // of one cell row on neighbouring lanes)
+        const int32_t items = ncell << lgnb;
+        for (int32_t i0 = threadIdx.x; i0 < items; i0 += kDfBatch * nb) {
             int av[kDfBatch], ag[kDfBatch];
             int64_t vr[kDfBatch];
+            bool h1[kDfBatch];
 #pragma unroll
             for (int u = 0; u < kDfBatch; ++u) {
-                const int32_t k = k0 + u * nb;
+                const int32_t it = i0 + u * nb;
+                const int b = it & (NB - 1);
                 av[u] = -1;
-                if (k < ce) {
+                if (it < items && b < nbp) {
+                    const int32_t k = cb + (it >> lgnb);
+                    const int32_t c0 = 2 * (pb + b);
                     vr[u] = (int64_t)jc_val[k] * d + c0;
+                    h1[u] = c0 + 1 < d;
                     const int r = jc_r[k], x = jc_x[k];
-                    av[u] = (((L1 - r) & (L1 - 1)) << lg2) + x;
-                    ag[u] = P + (r << lg2) + x;
+                    av[u] = (2 * b << lgP) + ((((L1 - r) & (L1 - 1)) << lg2) + x);
+                    ag[u] = ((2 * b + 1) << lgP) + (r << lg2) + x;
                 }
             }
             cpx<T> v[kDfBatch], w[kDfBatch];
 #pragma unroll
             for (int u = 0; u < kDfBatch; ++u) {
                 if (av[u] < 0) continue;
-                v[u] = {val[vr[u]], has1 ? val[vr[u] + 1] : (T)0};
-                w[u] = {valg[vr[u]], has1 ? valg[vr[u] + 1] : (T)0};
+                v[u] = {val[vr[u]], h1[u] ? val[vr[u] + 1] : (T)0};
+                w[u] = {valg[vr[u]], h1[u] ? valg[vr[u] + 1] : (T)0};
             }
 #pragma unroll
             for (int u = 0; u < kDfBatch; ++u) {
@@ -1912,11 +1924,17 @@ __global__ void k_df_fft_partial(int lg1, int lg2, const int32_t* __restrict__ j
             }
         }
         __syncthreads();
-        // zv and zg side by side: their rows, then their columns, as one batch
-        fft_lines<T, false, PAD>(zv, lg2, LdsLines{lg1 + 1, L2, 1, 0, 1}, 0, 0, tw, lgtw);
-        fft_lines<T, false, PAD>(zv, lg1, LdsLines{lg2, 1, 2, P, L2}, 0, 0, tw, lgtw);
-        for (int p = threadIdx.x; p < P; p += nb)
-            acc[p] = cadd(acc[p], cmulc(zv[lds_at<PAD>(P + p)], zv[lds_at<PAD>(p)]));
+        // every table of the batch: their rows, then their columns
+        fft_lines<T, false, PAD>(zv, lg2, LdsLines{lg1 + 1 + lgnb, L2, 1, 0, 1}, 0, 0, tw, lgtw);
+        fft_lines<T, false, PAD>(zv, lg1, LdsLines{lg2, 1, 2 * NB, P, L2}, 0, 0, tw, lgtw);
+        // pairs summed in pair order
+        for (int p = threadIdx.x; p < P; p += nb) {
+            cpx<T> a = acc[p];
+            for (int b = 0; b < nbp; ++b)
+                a = cadd(a, cmulc(zv[lds_at<PAD>(((2 * b + 1) << lgP) + p)],
+                                  zv[lds_at<PAD>((2 * b << lgP) + p)]));
+            acc[p] = a;
+        }
         __syncthreads();
     }
     if (!FOLD) {

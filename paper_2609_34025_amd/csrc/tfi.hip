@@ -2087,9 +2087,16 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
         if (lds) {
             hipEvent_t ev = h->begin(st);
             tfi::cpx<T>* part = (tfi::cpx<T>*)h->dfbuf[ti].p;
-            // padded LDS blocks (lds_at) where they fit the limit
             const int64_t cs = (int64_t)sizeof(tfi::cpx<T>);
-            const int64_t lds_pad = (tfi::pass_lds_elems(2 * P) + P) * cs;
+            // pairs transformed together: 2^lgnb of the group's, while their
+            // tables hold at most one radix-8 group per thread (more would
+            // only cost occupancy) and the padded block fits the limit
+            int lgnb = 0;
+            while ((2 << lgnb) <= ppg && (4 * P << lgnb) <= 8 * kThreads &&
+                   (tfi::pass_lds_elems(4 * P << lgnb) + P) * cs <= h->lds_max)
+                ++lgnb;
+            // padded LDS blocks (lds_at) where they fit the limit
+            const int64_t lds_pad = (tfi::pass_lds_elems(2 * P << lgnb) + P) * cs;
             const int64_t hist = (2 * (int64_t)b.hmax + b.xmax + 1) * 2 * (int64_t)sizeof(tfi::u64);
             if (df_group_folds<T>(b, groups)) {
                 if (lds_pad <= h->lds_max)
@@ -2097,13 +2104,13 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
                                        dim3((unsigned)b.njobs(), groups), dim3(kThreads),
                                        (unsigned)lds_pad, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
                                        h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
-                                       (tfi::cpx<T>*)nullptr, ppg, b.d_hx, p.NA, df);
+                                       (tfi::cpx<T>*)nullptr, ppg, lgnb, b.d_hx, p.NA, df);
                 else
                     hipLaunchKernelGGL((tfi::k_df_fft_partial<T, 0, true>),
                                        dim3((unsigned)b.njobs(), groups), dim3(kThreads),
                                        (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
                                        h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
-                                       (tfi::cpx<T>*)nullptr, ppg, b.d_hx, p.NA, df);
+                                       (tfi::cpx<T>*)nullptr, ppg, lgnb, b.d_hx, p.NA, df);
                 h->end(st, ev, "df_fft_lds", bytes);
                 continue;
             }
@@ -2111,12 +2118,13 @@ void enq_df_tables(tfi_plan* h, int32_t d, const T* val, const T* valg, tfi::u64
                 hipLaunchKernelGGL((tfi::k_df_fft_partial<T, tfi::kPassPad>),
                                    dim3((unsigned)b.njobs(), groups), dim3(kThreads),
                                    (unsigned)lds_pad, st, b.lg1, b.lg2, b.d_jobs, h->d_jc_r,
-                                   h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part, ppg);
+                                   h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw, part, ppg,
+                                   lgnb);
             else
                 hipLaunchKernelGGL(tfi::k_df_fft_partial<T>, dim3((unsigned)b.njobs(), groups),
                                    dim3(kThreads), (unsigned)lds, st, b.lg1, b.lg2, b.d_jobs,
                                    h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, valg, tw, h->lgtw,
-                                   part, ppg);
+                                   part, ppg, lgnb);
             const int64_t fold_lds = P * cs + hist, fold_pad = tfi::pass_lds_elems(P) * cs + hist;
             if (fold_pad <= h->lds_max)
                 hipLaunchKernelGGL((tfi::k_df_fft_fold<T, tfi::kPassPad>),
