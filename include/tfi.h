@@ -387,9 +387,12 @@ int tfi_set_scatter(tfi_handle h, int32_t method);
  * to rounding order.
  *   lds_pairs[t]      channel pairs transformed together by one workgroup
  *                     of LDS tier t (tables up to 16 KiB, up to 64 KiB,
- *                     larger); a power of two <= 64, or 0 = enough pairs
- *                     for about 4096 points per workgroup. Reduced to the
- *                     pairs there are and to what fits LDS.
+ *                     larger) for the tier's largest table; smaller tables
+ *                     take proportionally more (the same points per
+ *                     workgroup). A power of two <= 64, or 0 = enough pairs
+ *                     for about 2048 points per workgroup (4096 when d
+ *                     exceeds 64 channels). Reduced to the pairs there are
+ *                     and to what fits LDS.
  *   conv1d_min_lg     one-row and one-column tables of at least
  *                     2^conv1d_min_lg lattice points take the channel-tiled
  *                     1-D convolution kernels even when they fit LDS

@@ -982,6 +982,8 @@ __global__ void k_spectrum_multi(const int32_t* __restrict__ bp, const int64_t* 
 // before it uses the first.
 constexpr int kConvBatch = 8;
 
+constexpr unsigned kConvXcdGroups = 16;
+
 template <typename T, int PAD = 0>
 __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* __restrict__ bp,
                                  const int64_t* __restrict__ bo,
@@ -989,10 +991,27 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
                                  const int32_t* __restrict__ jc_val, int32_t d,
                                  const T* __restrict__ val, T* __restrict__ g,
                                  const cpx<T>* __restrict__ spec_all,
-                                 const cpx<T>* __restrict__ tw, int lgtw, int lgw, int lgcap) {
+                                 const cpx<T>* __restrict__ tw, int lgtw, int lgw, int lgcap,
+                                 int32_t njobs) {
     extern __shared__ unsigned char smem_raw[];
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_raw);
-    const int32_t cb = fj[3 * blockIdx.x], ce = fj[3 * blockIdx.x + 1], bk = fj[3 * blockIdx.x + 2];
+    // (job, group) of this workgroup. The groups of one job read the same
+    // cell rows, a few pairs each. Workgroups are dealt to the 8 XCDs in
+    // turn; with kConvXcdGroups groups or more (wide rows; the grid then
+    // has a multiple of 8 job columns) job j goes to XCD j mod 8 and its
+    // groups to consecutive slots there, so they run together and read the
+    // rows from that XCD's L2, while neighbouring jobs (tables of similar
+    // size) spread over the XCDs. With fewer groups, most of a small
+    // table's groups exit at once and grid order measured faster.
+    int32_t job = blockIdx.x, grp = blockIdx.y;
+    if (gridDim.y >= kConvXcdGroups) {
+        const int64_t w = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+        const int64_t k = w >> 3;
+        job = (int32_t)((w & 7) + 8 * (k / gridDim.y));
+        grp = (int32_t)(k % gridDim.y);
+    }
+    if (job >= njobs) return;
+    const int32_t cb = fj[3 * job], ce = fj[3 * job + 1], bk = fj[3 * job + 2];
     const int lg1 = bp[4 * bk], lg2 = bp[4 * bk + 1];
     const cpx<T>* spec = spec_all + bo[bk];
     const int L1 = 1 << lg1, L2 = 1 << lg2, P = L1 * L2, lgP = lg1 + lg2;
@@ -1003,7 +1022,7 @@ __global__ void k_fft_conv_multi(const int32_t* __restrict__ fj, const int32_t* 
     const int lgnp = max(0, min(lgw - lgP, lgcap));
     const int NP = 1 << lgnp;
     const int nb = blockDim.x;
-    const int32_t ch0 = 2 * (int32_t)blockIdx.y * NP;  // first channel of the group
+    const int32_t ch0 = 2 * grp * NP;  // first channel of the group
     if (ch0 >= d) return;
     for (int p = threadIdx.x; p < NP * P; p += nb) z[lds_at<PAD>(p)] = {(T)0, (T)0};
     __syncthreads();

@@ -1853,10 +1853,13 @@ void enq_spectra(tfi_plan* h, const T* f, hipStream_t st, tfi::cpx<T>* spec = nu
     }
 }
 
-// log2 of the channel pairs one workgroup of LDS tier t transforms: the
-// handle's setting, else enough tables for about 4096 points per workgroup
-// (a radix-8 pass then has a group for every thread); at most the pairs
-// there are and what fits the LDS limit.
+// log2 of the channel pairs one workgroup of LDS tier t transforms for the
+// tier's largest table (smaller tables take proportionally more, see
+// k_fft_conv_multi): the handle's setting, else enough for about 2048
+// points per workgroup (a radix-8 pass then has one group per thread), or
+// 4096 for rows of more than 32 pairs (a job's many groups then read
+// longer slices of each row); at most the pairs there are and what fits
+// the LDS limit.
 inline int fft_lgnp(const tfi_plan* h, int ti, int t, int32_t npairs) {
     const Tier& T_ = h->tiers[ti][t];
     const int64_t cs = ti ? 16 : 8;
@@ -1865,7 +1868,8 @@ inline int fft_lgnp(const tfi_plan* h, int ti, int t, int32_t npairs) {
     if (h->fp.lds_pairs[t] > 0) {
         while ((2 << lg) <= h->fp.lds_pairs[t]) ++lg;
     } else {
-        while (((int64_t)2 << lg) * pmax <= 4096) ++lg;
+        const int64_t points = (npairs > 32 ? 16 : 8) * kThreads;
+        while (((int64_t)2 << lg) * pmax <= points) ++lg;
     }
     while (lg > 0 && (1 << lg) > npairs) --lg;
     while (lg > 0 && ((int64_t)1 << lg) * T_.lds_bytes > h->lds_max) --lg;
@@ -1895,17 +1899,21 @@ void enq_fft(tfi_plan* h, int32_t d, const T* val, T* g, hipStream_t st, const W
         int lgw = lgnp, lgcap = 0;
         while (((int64_t)sizeof(tfi::cpx<T>) << lgw) < lds) ++lgw;
         while ((2 << lgcap) <= npairs) ++lgcap;
+        // with 16 groups or more the job columns are padded to a multiple
+        // of 8 (the kernel's XCD order; the extra workgroups exit at once)
+        const int64_t nj = T_.njobs;
+        const unsigned gx = (unsigned)(groups >= tfi::kConvXcdGroups ? (nj + 7) / 8 * 8 : nj);
         hipEvent_t ev = h->begin(st);
         if (pad)
-            hipLaunchKernelGGL((tfi::k_fft_conv_multi<T, tfi::kPassPad>),
-                               dim3((unsigned)T_.njobs, groups), dim3(kThreads), (unsigned)lds_pad,
-                               st, T_.d_fj, T_.d_bp, T_.d_bo, h->d_jc_r, h->d_jc_x, h->d_jc_val, d,
-                               val, g, spec, tw, h->lgtw, lgw, lgcap);
-        else
-            hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3((unsigned)T_.njobs, groups),
-                               dim3(kThreads), (unsigned)lds, st, T_.d_fj, T_.d_bp, T_.d_bo,
+            hipLaunchKernelGGL((tfi::k_fft_conv_multi<T, tfi::kPassPad>), dim3(gx, groups),
+                               dim3(kThreads), (unsigned)lds_pad, st, T_.d_fj, T_.d_bp, T_.d_bo,
                                h->d_jc_r, h->d_jc_x, h->d_jc_val, d, val, g, spec, tw, h->lgtw,
-                               lgw, lgcap);
+                               lgw, lgcap, (int32_t)nj);
+        else
+            hipLaunchKernelGGL(tfi::k_fft_conv_multi<T>, dim3(gx, groups), dim3(kThreads),
+                               (unsigned)lds, st, T_.d_fj, T_.d_bp, T_.d_bo, h->d_jc_r, h->d_jc_x,
+                               h->d_jc_val, d, val, g, spec, tw, h->lgtw, lgw, lgcap,
+                               (int32_t)nj);
         h->end(st, ev, "fft_lds", sz * d * T_.bytes_per_d + T_.bytes_fixed + sz * T_.spec_bytes);
     }
     for (int bi : h->global_b[ti]) {
