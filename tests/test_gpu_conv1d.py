@@ -226,3 +226,49 @@ def test_serpentine_full_size_c4160(side):
     assert e <= TOL[torch.float32], e
     del t, F, y
     torch.cuda.empty_cache()
+
+
+def test_comb_c4160_lds_tables_in_xcd_order():
+    """The masked-attention payload at full width on the 256 x 256 comb at
+    the direct/FFT rule the benchmark's tuner picks (8): its FFT tables fit
+    LDS, and with 2080 channel pairs every job has far more than 16 pair
+    groups, so k_fft_conv_multi runs its 4096-point workgroups in the XCD
+    order (job j on XCD j mod 8, the job columns padded to a multiple of 8)
+    and its smaller tables take more pairs per workgroup. 32 sampled rows x
+    64 sampled channels against the FP64 oracle, and a graph replay equal
+    to the profiled run bit for bit."""
+    W = S.workload("attn", tree="comb", side=256)
+    p, w = W["parent"], W["weight"]
+    n, C = len(p), W["d"]
+    print(f"comb side=256 N={n} C={C} fp32 fft_cost 8", flush=True)
+    t = TreeIntegrator(p, w, device=0)
+    t.set_fft_cost(8.0)
+    K = t.kernel_length
+    tab = W["kernels"][0][1](K)
+    f = torch.tensor(tab, dtype=torch.float32, device=DEV)
+    phi = torch.from_numpy(W["phi"]).to(DEV)
+    v = torch.from_numpy(W["v"]).to(DEV)
+    F = torch.cat([(phi[:, :, None] * v[:, None, :]).reshape(n, -1), phi], 1).contiguous()
+    del phi, v
+    t.profile(True)
+    y = t.integrate(f, F)
+    torch.cuda.synchronize()
+    st = t.profile_report()
+    t.profile(False)
+    assert "fft_lds" in st, st
+    again = t.integrate(f, F)
+    torch.cuda.synchronize()
+    assert torch.equal(again, y)
+    del again
+    rng = np.random.default_rng(256)
+    rows = np.sort(rng.choice(n, 32, replace=False))
+    chans = np.sort(rng.choice(C, 64, replace=False))
+    Fs = F[:, torch.from_numpy(chans).to(DEV)].double().cpu().numpy()
+    got = y[torch.from_numpy(rows).to(DEV)][:, torch.from_numpy(chans).to(DEV)]
+    got = got.double().cpu().numpy()
+    ref = oracle.integrate(p, w, tab, Fs, rows=rows)
+    e = relerr(got, ref)
+    print(f"  err {e:.2e}", flush=True)
+    assert e <= TOL[torch.float32], e
+    del t, F, y
+    torch.cuda.empty_cache()
